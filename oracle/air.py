@@ -1,0 +1,284 @@
+"""lAIR algebraic multigrid (oracle).
+
+Passages followed: two-grid correction ``x <- x + P (R A P)^-1 R r`` and the
+C/F block form, ideal restriction ``R_ideal = [-A_cf A_ff^-1, I]`` with any
+``P = [W; I]`` (Section 3); the solver settings of Section 4: distance-one
+restriction neighbourhoods from a strength tolerance, one-point
+interpolation, no pre-relaxation, post-relaxation on F points then all
+points, AIR applied to the matrix scaled by the inverse facet blocks.
+
+Readings where the paper is silent or where this build deviates (listed in
+the design notes):
+  * strength: ``j in S_i`` iff ``j != i`` and
+    ``|a_ij| >= theta max_{k != i} |a_ik| (1 - 1e-12)``; a row whose
+    off-diagonal entries are all zero has no strong connections;
+  * coarsening: PMIS on the symmetrised strength graph, point weights compared
+    as the integer key ``influence_count * 2^44 + hash44(i, level)`` (a
+    bijective 44-bit mix, so keys never tie); points nothing depends on
+    strongly start as F; coarse index = rank of the C point;
+  * lAIR restriction row of C point i: ``N_i`` = strong F neighbours (sorted),
+    ``A[N_i,N_i]^T z = -A[i,N_i]^T`` by LU with partial pivoting,
+    ``R[i,i] = 1``, ``R[i,N_i] = z``; injection when ``N_i`` is empty or a pivot
+    satisfies ``|pivot| <= 1e-14 max |A[N_i,N_i]|``;
+  * one-point interpolation: an F point takes weight 1 at its strongest
+    strong C neighbour (ties within relative 1e-12 -> smallest index), or
+    a zero row when it has none;
+  * relaxation: Jacobi (omega = 1) sweeps on F, F, C ("FFC") or one F sweep
+    ("F") instead of Gauss-Seidel; no filtering of R, P or R A P;
+  * hierarchy stops when the coarse grid has at most ``max_coarse`` points,
+    when ``max_levels`` is reached, or when coarsening stalls
+    (``n_c == 0`` or ``n_c > 0.9 n``); coarsest level: dense LU.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.linalg as sla
+
+MASK44 = (1 << 44) - 1
+
+
+def hash44(i, level):
+    """Bijective 44-bit mix of the point index (per level)."""
+    m = np.uint64(MASK44)
+    with np.errstate(over="ignore"):          # products are taken mod 2^64, then mod 2^44
+        x = (np.asarray(i, dtype=np.uint64) + np.uint64((level + 1) * 0x9E3779B97F4A7C15 & MASK44)) & m
+        x = x ^ (x >> np.uint64(21))
+        x = (x * np.uint64(0xBF58476D1CE4E5B9 & MASK44)) & m
+        x = x ^ (x >> np.uint64(19))
+        x = (x * np.uint64(0x94D049BB133111EB & MASK44)) & m
+        x = x ^ (x >> np.uint64(22))
+    return x
+
+
+def _rows(A):
+    return np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+
+
+def strength(A, theta):
+    """Boolean mask over the stored entries of CSR ``A``: strong connections."""
+    n = A.shape[0]
+    r = _rows(A)
+    absv = np.abs(A.data)
+    off = A.indices != r
+    offabs = np.where(off, absv, 0.0)
+    rmax = np.zeros(n)
+    np.maximum.at(rmax, r, offabs)
+    return off & (rmax[r] > 0) & (absv >= theta * rmax[r] * (1.0 - 1e-12))
+
+
+def pmis(A, strong, level):
+    """PMIS C/F splitting: returns ``cf`` with 1 = C, 0 = F."""
+    n = A.shape[0]
+    r = _rows(A)
+    si, sj = r[strong], A.indices[strong]           # i depends strongly on j
+    lam = np.bincount(sj, minlength=n)              # how many points depend on j
+    key = (lam.astype(np.uint64) << np.uint64(44)) | hash44(np.arange(n), level)
+    state = np.zeros(n, dtype=np.int8)               # 0 undecided, 1 C, -1 F
+    state[lam == 0] = -1
+    # symmetrised graph edges (both directions)
+    gi = np.concatenate([si, sj])
+    gj = np.concatenate([sj, si])
+    while np.any(state == 0):
+        und = state == 0
+        e = und[gi] & und[gj]
+        nbmax = np.zeros(n, dtype=np.uint64)
+        np.maximum.at(nbmax, gi[e], key[gj[e]])
+        newc = und & (key > nbmax)
+        state[newc] = 1
+        isc = state == 1
+        dep = np.zeros(n, dtype=bool)
+        hit = isc[sj] & (state[si] == 0)
+        dep[si[hit]] = True
+        state[dep & (state == 0)] = -1
+    return (state == 1).astype(np.int8)
+
+
+def one_point_P(A, strong, cf, cidx):
+    n = A.shape[0]
+    nc = int(cf.sum())
+    r = _rows(A)
+    absv = np.abs(A.data)
+    elig = strong & (cf[A.indices] == 1) & (cf[r] == 0)
+    rmax = np.zeros(n)
+    np.maximum.at(rmax, r[elig], absv[elig])
+    cand = elig & (absv >= rmax[r] * (1.0 - 1e-12))
+    pos = np.nonzero(cand)[0]
+    first = {}
+    for k in pos:                       # CSR order: smallest column first within a row
+        i = r[k]
+        if i not in first:
+            first[i] = A.indices[k]
+    rows = list(np.nonzero(cf == 1)[0])
+    cols = [cidx[i] for i in rows]
+    for i, j in first.items():
+        rows.append(i)
+        cols.append(cidx[j])
+    P = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+def batched_lu_solve(M, rhs):
+    """Gaussian elimination with partial pivoting on a batch ``M[k][m][m]``,
+    ``rhs[k][m]``.  Returns solutions and a flag for systems with a pivot
+    ``|pivot| <= 1e-14 max |M|``."""
+    M = M.copy()
+    x = rhs.copy()
+    k, m, _ = M.shape
+    scale = np.abs(M).reshape(k, -1).max(axis=1) if m else np.zeros(k)
+    bad = np.zeros(k, dtype=bool)
+    ar = np.arange(k)
+    for c in range(m):
+        piv = c + np.argmax(np.abs(M[:, c:, c]), axis=1)
+        # swap rows c and piv
+        rowc = M[ar, c].copy(); M[ar, c] = M[ar, piv]; M[ar, piv] = rowc
+        xc = x[ar, c].copy(); x[ar, c] = x[ar, piv]; x[ar, piv] = xc
+        pv = M[:, c, c]
+        bad |= np.abs(pv) <= 1e-14 * scale
+        pv_safe = np.where(bad, 1.0, pv)
+        f = M[:, c + 1:, c] / pv_safe[:, None]
+        M[:, c + 1:, :] -= f[:, :, None] * M[:, None, c, :]
+        x[:, c + 1:] -= f * x[:, c:c + 1]
+    for c in range(m - 1, -1, -1):
+        pv = np.where(bad, 1.0, M[:, c, c])
+        x[:, c] = (x[:, c] - np.einsum("kj,kj->k", M[:, c, c + 1:], x[:, c + 1:])) / pv
+    return x, bad
+
+
+def lair_R(A, strong, cf, cidx):
+    """Distance-one lAIR restriction: ``(R A)[i, j] = 0`` for ``j in N_i``."""
+    n = A.shape[0]
+    nc = int(cf.sum())
+    Cpts = np.nonzero(cf == 1)[0]
+    r = _rows(A)
+    sF = strong & (cf[A.indices] == 0)
+    Ni = {}
+    cnt = np.zeros(n, dtype=np.int64)
+    np.add.at(cnt, r[sF], 1)
+    rows, cols, vals = [], [], []
+    nfall = 0
+    for m in np.unique(cnt[Cpts]):
+        pts = Cpts[cnt[Cpts] == m]
+        if m == 0:
+            rows.append(cidx[pts]); cols.append(pts); vals.append(np.ones(len(pts)))
+            nfall += len(pts)
+            continue
+        N = np.zeros((len(pts), m), dtype=np.int64)
+        for t, i in enumerate(pts):
+            lo, hi = A.indptr[i], A.indptr[i + 1]
+            N[t] = A.indices[lo:hi][sF[lo:hi]]
+        rr = np.repeat(N, m, axis=1).ravel()
+        cc = np.tile(N, (1, m)).ravel()
+        Mloc = np.asarray(A[rr, cc]).reshape(len(pts), m, m)
+        ai = np.asarray(A[np.repeat(pts, m), N.ravel()]).reshape(len(pts), m)
+        z, bad = batched_lu_solve(np.transpose(Mloc, (0, 2, 1)), -ai)
+        good = ~bad
+        nfall += int(bad.sum())
+        rows.append(cidx[pts]); cols.append(pts); vals.append(np.ones(len(pts)))
+        rows.append(np.repeat(cidx[pts[good]], m)); cols.append(N[good].ravel())
+        vals.append(z[good].ravel())
+    R = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nc, n))
+    R.sort_indices()
+    return R, nfall
+
+
+class Level:
+    pass
+
+
+class Hierarchy:
+    pass
+
+
+def setup(A0, theta=0.25, max_coarse=500, max_levels=25, relax="FFC", omega=1.0,
+          stall=0.9, max_dense=8192):
+    """Build the lAIR hierarchy on the scaled matrix (treated as scalar)."""
+    H = Hierarchy()
+    H.levels = []
+    H.relax, H.omega = relax, omega
+    H.n_fallback = 0
+    A = sp.csr_matrix(A0)
+    A.sort_indices()
+    l = 0
+    while True:
+        n = A.shape[0]
+        lev = Level()
+        lev.A = A
+        lev.diag = A.diagonal()
+        H.levels.append(lev)
+        if n <= max_coarse or l == max_levels - 1:
+            break
+        strong = strength(A, theta)
+        cf = pmis(A, strong, l)
+        nc = int(cf.sum())
+        if nc == 0 or nc > stall * n:
+            break
+        cidx = np.cumsum(cf) - 1
+        lev.cf = cf
+        lev.strong = strong
+        lev.P = one_point_P(A, strong, cf, cidx)
+        lev.R, nf = lair_R(A, strong, cf, cidx)
+        H.n_fallback += nf
+        Ac = (lev.R @ A @ lev.P).tocsr()
+        Ac.sort_indices()
+        A = Ac
+        l += 1
+    last = H.levels[-1]
+    if last.A.shape[0] > max_dense:
+        raise RuntimeError("coarsest level too large for a dense solve")
+    last.lu = sla.lu_factor(last.A.toarray()) if last.A.shape[0] else None
+    H.nlev = len(H.levels)
+    return H
+
+
+def _sweep_sets(H, lev, transpose):
+    F = np.nonzero(lev.cf == 0)[0]
+    C = np.nonzero(lev.cf == 1)[0]
+    sets = [F, F, C] if H.relax == "FFC" else [F]
+    return sets[::-1] if transpose else sets
+
+
+def _coarse_solve(last, b, trans=0):
+    if last.lu is None:
+        return np.zeros(0)
+    return sla.lu_solve(last.lu, b, trans=trans)
+
+
+def vcycle(H, b, l=0):
+    """One V-cycle with zero initial guess (Section 3 coarse-grid correction,
+    post-relaxation only)."""
+    lev = H.levels[l]
+    if l == H.nlev - 1:
+        return _coarse_solve(lev, b)
+    ec = vcycle(H, lev.R @ b, l + 1)
+    x = lev.P @ ec
+    d = lev.diag
+    for X in _sweep_sets(H, lev, False):
+        X = X[np.abs(d[X]) >= 1e-30]
+        r = b - lev.A @ x
+        x[X] += H.omega * r[X] / d[X]
+    return x
+
+
+def vcycle_T(H, g, l=0):
+    """Transpose of :func:`vcycle`: sweeps C, F, F with ``A^T``, then restriction
+    by ``P^T`` and interpolation by ``R^T``; coarsest ``LU^T`` solve."""
+    lev = H.levels[l]
+    if l == H.nlev - 1:
+        return _coarse_solve(lev, g, trans=1)
+    y = np.zeros_like(g)
+    d = lev.diag
+    AT = lev.A.T.tocsr()
+    for X in _sweep_sets(H, lev, True):
+        X = X[np.abs(d[X]) >= 1e-30]
+        r = g - AT @ y
+        y[X] += H.omega * r[X] / d[X]
+    y = y + lev.R.T @ vcycle_T(H, lev.P.T @ (g - AT @ y), l + 1)
+    return y
+
+
+def stats(H):
+    """Level sizes, nonzeros and operator complexity."""
+    ns = [lev.A.shape[0] for lev in H.levels]
+    nnz = [lev.A.nnz for lev in H.levels]
+    return {"n": ns, "nnz": nnz, "op_complexity": sum(nnz) / nnz[0]}

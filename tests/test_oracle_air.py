@@ -1,0 +1,221 @@
+"""Pins of the oracle's AIR setup, cycles and Krylov solver (no GPU)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import air, krylov
+from oracle.drivers import setup_problem, direct_solve, air_fgmres_solve
+from workloads import square_tri_mesh, slab_prism_tet_mesh, kuhn_cube_mesh
+from workloads.problems import C1Advection1D, slab_hill, SmoothPlusFront
+
+
+@pytest.fixture(scope="module")
+def c1_sys():
+    v, c = square_tri_mesh(16)
+    return setup_problem(v, c, C1Advection1D(1e-4), 1)
+
+
+@pytest.fixture(scope="module")
+def slab_sys():
+    v, c = slab_prism_tet_mesh(6, 1 / 6)
+    return setup_problem(v, c, slab_hill(1e-3), 2)
+
+
+def _dense_strength(Ad, theta):
+    n = Ad.shape[0]
+    S = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        off = [abs(Ad[i, k]) for k in range(n) if k != i]
+        m = max(off) if off else 0.0
+        for j in range(n):
+            if j != i and m > 0 and abs(Ad[i, j]) >= theta * m * (1 - 1e-12) and Ad[i, j] != 0:
+                S[i, j] = True
+    return S
+
+
+def test_strength_brute_force(c1_sys):
+    A = c1_sys.Shat[:200, :200].tocsr()
+    A.sort_indices()
+    st = air.strength(A, 0.25)
+    Sd = np.zeros(A.shape, dtype=bool)
+    r = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    Sd[r[st], A.indices[st]] = True
+    assert np.array_equal(Sd, _dense_strength(A.toarray(), 0.25))
+
+
+def test_hash44_is_injective():
+    h = air.hash44(np.arange(200000), 3)
+    assert np.unique(h).size == 200000
+    assert int(h.max()) < (1 << 44)
+
+
+def _pmis_loops(n, S_rows, level):
+    """PMIS written with plain loops over points (tiny inputs only)."""
+    infl = [0] * n
+    for i in range(n):
+        for j in S_rows[i]:
+            infl[j] += 1
+    key = [infl[i] * (1 << 44) + int(air.hash44(i, level)) for i in range(n)]
+    nbrs = [set() for _ in range(n)]
+    for i in range(n):
+        for j in S_rows[i]:
+            nbrs[i].add(j)
+            nbrs[j].add(i)
+    state = ["F" if infl[i] == 0 else "U" for i in range(n)]
+    while "U" in state:
+        newc = [i for i in range(n) if state[i] == "U"
+                and all(key[i] > key[j] for j in nbrs[i] if state[j] == "U")]
+        for i in newc:
+            state[i] = "C"
+        for j in range(n):
+            if state[j] == "U" and any(state[i] == "C" for i in S_rows[j]):
+                state[j] = "F"
+    return np.array([1 if s == "C" else 0 for s in state])
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_pmis_matches_loop_definition_and_invariants(which, c1_sys, slab_sys):
+    s = c1_sys if which == "c1" else slab_sys
+    A = s.Shat[:600, :600].tocsr() if which == "slab" else s.Shat
+    A.sort_indices()
+    st = air.strength(A, 0.25)
+    cf = air.pmis(A, st, 2)
+    r = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    si, sj = r[st], A.indices[st]
+    S_rows = [[] for _ in range(A.shape[0])]
+    for i, j in zip(si, sj):
+        S_rows[i].append(j)
+    assert np.array_equal(cf, _pmis_loops(A.shape[0], S_rows, 2))
+    # every F point that something depends on has a strong C dependency
+    infl = np.bincount(sj, minlength=A.shape[0])
+    hasC = np.zeros(A.shape[0], dtype=bool)
+    hasC[si[cf[sj] == 1]] = True
+    assert np.all(hasC[(cf == 0) & (infl > 0)])
+    # no point that depends on nothing strongly and influences nothing is C
+    assert np.all(cf[infl == 0] == 0)
+
+
+def test_one_point_interpolation_preserves_constants(slab_sys):
+    A = slab_sys.Shat
+    st = air.strength(A, 0.25)
+    cf = air.pmis(A, st, 0)
+    cidx = np.cumsum(cf) - 1
+    P = air.one_point_P(A, st, cf, cidx)
+    rs = np.asarray(P.sum(1)).ravel()
+    r = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    hasC = np.zeros(A.shape[0], dtype=bool)
+    hasC[r[st & (cf[A.indices] == 1)]] = True
+    assert np.all(rs[(cf == 1) | hasC] == 1.0)
+    assert np.all(rs[(cf == 0) & ~hasC] == 0.0)
+    # the chosen C neighbour is a strongest one
+    Ad = A.tocsr()
+    for i in np.nonzero((cf == 0) & hasC)[0][:200]:
+        j = np.nonzero(cf == 1)[0][P[i].indices[0]]
+        lo, hi = Ad.indptr[i], Ad.indptr[i + 1]
+        cand = [abs(Ad.data[k]) for k in range(lo, hi) if st[k] and cf[Ad.indices[k]] == 1]
+        assert abs(Ad[i, j]) >= max(cand) * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_lair_rows_annihilate_f_neighbourhood(which, c1_sys, slab_sys):
+    s = c1_sys if which == "c1" else slab_sys
+    A = s.Shat
+    st = air.strength(A, 0.25)
+    cf = air.pmis(A, st, 0)
+    cidx = np.cumsum(cf) - 1
+    R, nfall = air.lair_R(A, st, cf, cidx)
+    RA = (R @ A).tocsr()
+    Cpts = np.nonzero(cf == 1)[0]
+    Ad = A.tocsr()
+    checked = 0
+    for ci, i in enumerate(Cpts):
+        assert R[ci, i] == 1.0
+        lo, hi = Ad.indptr[i], Ad.indptr[i + 1]
+        Ni = [Ad.indices[k] for k in range(lo, hi) if st[k] and cf[Ad.indices[k]] == 0]
+        if not Ni or R[ci].nnz == 1:
+            continue
+        rownorm = np.abs(Ad[i].data).max()
+        for j in Ni:
+            assert abs(RA[ci, j]) <= 1e-12 * max(rownorm, 1.0)
+        checked += 1
+    assert checked > 0
+
+
+def test_batched_lu_matches_library_solve():
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((50, 7, 7))
+    rhs = rng.standard_normal((50, 7))
+    x, bad = air.batched_lu_solve(M, rhs)
+    assert not bad.any()
+    assert np.allclose(x, np.linalg.solve(M, rhs[..., None])[..., 0], atol=1e-12)
+    M[0] = 0.0
+    _, bad = air.batched_lu_solve(M, rhs)
+    assert bad[0] and not bad[1:].any()
+
+
+def test_ideal_restriction_two_grid_exact():
+    # Section 3: with R_ideal = [-A_cf A_ff^-1, I] and any P = [W; I],
+    # R A P = A_cc - A_cf A_ff^-1 A_fc and coarse correction followed by an exact
+    # F solve removes all error.
+    rng = np.random.default_rng(7)
+    n, nc = 12, 5
+    A = rng.standard_normal((n, n)) + 6 * np.eye(n)
+    f = np.arange(n - nc); c = np.arange(n - nc, n)
+    Aff, Afc, Acf, Acc = A[np.ix_(f, f)], A[np.ix_(f, c)], A[np.ix_(c, f)], A[np.ix_(c, c)]
+    R = np.hstack([-Acf @ np.linalg.inv(Aff), np.eye(nc)])
+    W = rng.standard_normal((n - nc, nc))
+    P = np.vstack([W, np.eye(nc)])
+    schur = Acc - Acf @ np.linalg.solve(Aff, Afc)
+    assert np.allclose(R @ A @ P, schur, atol=1e-12)
+    b = rng.standard_normal(n)
+    x = P @ np.linalg.solve(R @ A @ P, R @ b)
+    r = b - A @ x
+    x[f] += np.linalg.solve(Aff, r[f])
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-11)
+
+
+def test_vcycle_linear_and_transpose_identity(slab_sys):
+    H = air.setup(slab_sys.Shat, max_coarse=50)
+    assert H.nlev >= 3
+    rng = np.random.default_rng(11)
+    n = slab_sys.n
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    Bx, By = air.vcycle(H, x), air.vcycle(H, y)
+    assert np.allclose(air.vcycle(H, 2 * x - 3 * y), 2 * Bx - 3 * By, atol=1e-10 * np.abs(Bx).max())
+    lhs = Bx @ y
+    rhs = x @ air.vcycle_T(H, y)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * np.linalg.norm(Bx) / np.linalg.norm(x) * 10
+
+
+def test_fgmres_exact_preconditioner_one_iteration(c1_sys):
+    A = c1_sys.Shat
+    Ad = A.toarray()
+    lu = np.linalg.inv(Ad)
+    x, info = krylov.fgmres(A, c1_sys.Hhat, lambda r: lu @ r, tol=1e-12)
+    assert info["iters"] == 1
+    assert np.allclose(x, np.linalg.solve(Ad, c1_sys.Hhat), atol=1e-10)
+
+
+def test_fgmres_restart_path_reaches_solution(c1_sys):
+    A = c1_sys.Shat
+    x, info = krylov.fgmres(A, c1_sys.Hhat, lambda r: r, tol=1e-10, restart=5, maxit=5000)
+    assert info["converged"]
+    ref = direct_solve(c1_sys)
+    assert np.abs(x - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_air_fgmres_matches_direct(which, c1_sys, slab_sys):
+    s = c1_sys if which == "c1" else slab_sys
+    x, info = air_fgmres_solve(s, tol=1e-12)
+    assert info["converged"] and info["iters"] < 30
+    ref = direct_solve(s)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_pure_advection_air_converges():
+    prob = SmoothPlusFront(0.0)
+    v, c = kuhn_cube_mesh(6)
+    s = setup_problem(v, c, prob, 1)
+    x, info = air_fgmres_solve(s, tol=1e-10)
+    assert info["converged"] and info["iters"] <= 15
