@@ -1,0 +1,264 @@
+/*
+ * airhdg: space-time HDG facet systems solved by FGMRES preconditioned with
+ * lAIR algebraic multigrid, on one AMD MI355X (gfx950).
+ *
+ * Method: Sivas, Southworth, Rhebergen, "AIR algebraic multigrid for a
+ * space-time hybridizable discontinuous Galerkin discretization of
+ * advection(-diffusion)", arXiv 2010.11130.
+ *
+ * Conventions shared by every call
+ *   - Space-time coordinates: column 0 is t, columns 1..d are space;
+ *     D = d + 1 is the space-time dimension (2 or 3), p in {1, 2, 3}.
+ *   - Pointers marked "host" are host memory, "dev" are device memory
+ *     (hipMalloc'd or torch tensors); the caller owns every pointer argument.
+ *   - stream: a hipStream_t passed as void* (NULL = default stream).  Device
+ *     work is enqueued on it.  Calls that return an info struct or sizes
+ *     synchronize the stream before returning.
+ *   - Library objects (ah_mesh, ah_system, ah_hier) own their device memory,
+ *     allocated stream-ordered on the stream of the call that creates them and
+ *     released by the matching destroy call.
+ *   - Return values: AH_OK (0) on success, a positive warning (AH_ENOCONV) or
+ *     a negative error.  On error nothing is written to outputs except where
+ *     stated, and ah_last_error() (per thread) describes the failure.
+ *   - Facets are numbered by the lexicographic order of their sorted
+ *     vertex-id tuples.  Facet unknowns: Lagrange nodes of degree p at the
+ *     equispaced lattice of the facet simplex whose vertices are the facet's
+ *     vertex ids in increasing order (lattice index i_1 fastest).  "Free"
+ *     DOFs are those of non-Dirichlet facets, numbered facet-rank * b + node.
+ *   - Element unknowns returned by hdg_reconstruct are the values of u_h at
+ *     the equispaced degree-p lattice of each element's reference simplex
+ *     (vertex order of the cell, i_1 fastest).
+ *   - Quadrature: conical-product Gauss-Jacobi rules with p+2 points per
+ *     direction on elements and facets (collapsed coordinates, s_1 fastest).
+ */
+#ifndef AIRHDG_H
+#define AIRHDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AH_OK = 0,
+  AH_ENOCONV = 1,        /* iteration limit reached; best iterate written */
+  AH_EINVAL = -1,        /* bad argument, size, or non-finite input */
+  AH_ESINGULAR = -2,     /* degenerate element or singular facet block */
+  AH_EBREAKDOWN = -3,    /* NaN/Inf during the Krylov iteration */
+  AH_EHIP = -4,          /* HIP runtime error */
+  AH_ENOMEM = -5,        /* device allocation failed */
+  AH_EUNSUPPORTED = -6   /* size or parameter outside what is implemented */
+} ah_status;
+
+typedef struct ah_mesh ah_mesh;
+typedef struct ah_system ah_system;
+typedef struct ah_hier ah_hier;
+
+/* Last error message of the calling thread (never NULL). */
+const char* ah_last_error(void);
+
+/* ---------------------------------------------------------------- mesh ---
+ * Space-time simplex mesh (Section 2.2: slab-by-slab slabs or one
+ * all-at-once triangulation).  vert: host [nv][dim_st]; cell: host
+ * [ne][dim_st+1] vertex ids.  Inputs are copied.  Builds the facets (sorted
+ * vertex tuples), element-facet maps and the facet adjacency pattern on the
+ * host.  AH_EINVAL for ids out of range or a facet shared by more than two
+ * cells; AH_ESINGULAR for a degenerate cell. */
+ah_status ah_mesh_create(int dim_st, int64_t nv, const double* vert, int64_t ne,
+                         const int32_t* cell, ah_mesh** out);
+void ah_mesh_destroy(ah_mesh* m);
+/* Sizes: number of facets, of boundary facets (one adjacent cell). */
+ah_status ah_mesh_sizes(const ah_mesh* m, int64_t* nf, int64_t* nbf);
+/* facet_vert: host [nf][dim_st] sorted vertex ids; facet_elem: host [nf][2]
+ * adjacent cells (-1 when absent).  Either may be NULL. */
+ah_status ah_mesh_facets(const ah_mesh* m, int32_t* facet_vert, int32_t* facet_elem);
+/* Boundary facet ids in increasing order: host [nbf].  Boundary data arrays
+ * (g_q) are indexed in this order. */
+ah_status ah_mesh_boundary_facets(const ah_mesh* m, int32_t* ids);
+/* Boundary kinds, host [nf]: 0 interior, 1 Dirichlet (u = g_D, facet
+ * unknowns eliminated), 2 Neumann (total-flux condition of Section 2.1; the
+ * initial plane is an inflow Neumann facet).  Must be called before
+ * hdg_assemble.  AH_EINVAL if an interior facet is tagged or a boundary
+ * facet is left 0. */
+ah_status ah_mesh_set_bc(ah_mesh* m, const int8_t* kind);
+
+/* Quadrature sizes for (dim_st, p): element and facet points, element and
+ * facet basis sizes (nu = dim P_p(K), b = dim P_p(F)). */
+ah_status ah_sizes(int dim_st, int p, int* nq, int* nqf, int* nu, int* b);
+/* The conical-product rule on the reference simplex of dimension dim (0..3)
+ * with n points per direction: xi host [n^dim][dim], w host [n^dim]
+ * (weights sum to 1/dim!). */
+ah_status ah_quad_rule(int dim, int n, double* xi, double* w);
+/* Physical quadrature points where the caller evaluates f and g: xq_elem dev
+ * [ne][nq][dim_st], xq_bfacet dev [nbf][nqf][dim_st] (either may be NULL). */
+ah_status ah_quad_points(const ah_mesh* m, int p, double* xq_elem, double* xq_bfacet,
+                         void* stream);
+
+/* ------------------------------------------------------- hdg_assemble ---
+ * Space-time HDG discretization (Section 2.3, bilinear form with upwind
+ * flux sigma_a and interior-penalty flux sigma_d, tau = nu alpha / h_K with
+ * h_K = |det J_K|^(1/D)), static condensation S = D - C A^-1 B,
+ * H = G - C A^-1 F (Section 2.5), Dirichlet elimination (facet L2
+ * projection of g_D), and left scaling by the inverse facet diagonal blocks
+ * (Section 4): builds S_hat = D_b^-1 S and H_hat = D_b^-1 H on the free
+ * facets.
+ *   alpha <= 0 selects 10 p^2 (Section 4).
+ *   a_vert: dev [nv][d] velocity at the vertices, interpolated linearly in
+ *           each cell (exact for affine velocity fields).
+ *   f_q:    dev [ne][nq] source at ah_quad_points' element points, or NULL (0).
+ *   g_q:    dev [nbf][nqf] boundary data at the boundary-facet points:
+ *           g_D on Dirichlet facets, g_N on Neumann facets; NULL = 0.
+ * Returns AH_ESINGULAR if a facet diagonal block or an element block is
+ * singular (e.g. a characteristic facet at nu = 0), AH_EINVAL for nu < 0 or
+ * p outside 1..3.  Synchronizes the stream. */
+typedef struct {
+  int p;
+  double alpha;
+  int keep_element_data;   /* nonzero: keep blocks for reconstruct/adjoint */
+} ah_hdg_params;
+
+ah_status hdg_assemble(const ah_mesh* m, const ah_hdg_params* prm, double nu,
+                       const double* a_vert, const double* f_q, const double* g_q,
+                       void* stream, ah_system** out);
+void ah_system_destroy(ah_system* s);
+/* n_free = number of free facet DOFs; b = facet block size; nnz = stored
+ * entries of the scaled level-0 matrix (exact zeros off the diagonal are not
+ * stored). */
+ah_status ah_system_sizes(const ah_system* s, int64_t* n_free, int* b, int64_t* nnz);
+/* Copies of the scaled CSR matrix S_hat (row_ptr dev [n+1] int64, col dev
+ * [nnz] int32, val dev [nnz] double), H_hat dev [n], the inverse facet blocks
+ * D_b^-1 dev [n/b][b][b] and the Dirichlet traces of all facets dev
+ * [nf][b] (zero on non-Dirichlet facets).  Any pointer may be NULL. */
+ah_status ah_system_export(const ah_system* s, int64_t* row_ptr, int32_t* col, double* val,
+                           double* h_hat, double* dinv, double* lam_dir, void* stream);
+/* u_h at the element lattice nodes: U_K = A_K^-1 (F_K - B_K Lambda_K)
+ * (Section 2.5).  lam dev [n_free] (unscaled solution); U dev [ne][nu].
+ * Requires keep_element_data. */
+ah_status hdg_reconstruct(const ah_system* s, const double* lam, double* U, void* stream);
+/* Slab coupling (Section 2.4): the next slab's inflow data on its initial
+ * plane is the previous slab's trace on its final plane.  For every
+ * boundary facet of next's mesh lying on its initial plane whose spatial
+ * vertices coincide with a final-plane facet of prev's mesh, writes that
+ * trace (free DOFs lam_prev dev [n_free(prev)]) evaluated at next's facet
+ * quadrature points into g_q_next dev [nbf(next)][nqf]; other rows are left
+ * untouched.  The meshes may be the same object. */
+ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev,
+                                const ah_system* next, double* g_q_next, void* stream);
+
+/* ---------------------------------------------------------- air_setup ---
+ * lAIR hierarchy on S_hat treated as a scalar matrix (Section 3; Section 4
+ * settings): strength |a_ij| >= theta max_{k!=i}|a_ik| (1-1e-12); PMIS
+ * coarsening with integer keys (influence count, 44-bit index hash);
+ * one-point interpolation; distance-one lAIR restriction from local
+ * solves A[N_i,N_i]^T z = -A[i,N_i]^T; A_c = R A P; coarsest level inverted
+ * densely.  Stops at n <= max_coarse, at max_levels, or when the coarse grid
+ * is empty or larger than stall * n.  fp32_cycle: also keep FP32 copies of the
+ * cycle operators; adjoint: also build the transposed operators. */
+typedef struct {
+  double theta;        /* strength threshold, default 0.25 */
+  int max_coarse;      /* default 500 */
+  int max_levels;      /* default 25 */
+  int relax;           /* 0: F,F,C Jacobi sweeps; 1: one F sweep */
+  double omega;        /* Jacobi weight, default 1 */
+  double stall;        /* default 0.9 */
+  int fp32_cycle;
+  int adjoint;
+} ah_air_params;
+
+typedef struct {
+  int levels;
+  int64_t n[32];
+  int64_t nnz[32];
+  int64_t n_fallback;  /* lAIR rows that fell back to injection */
+  double op_complexity;
+  double t_setup_ms;
+} ah_setup_info;
+
+/* Defaults for ah_air_params / ah_solve_params. */
+void ah_air_defaults(ah_air_params* p);
+
+ah_status air_setup(const ah_system* s, const ah_air_params* prm, void* stream,
+                    ah_hier** out, ah_setup_info* info);
+void ah_hier_destroy(ah_hier* h);
+/* Level data for inspection (device copies): n, nnz of A_l and of R_l. */
+ah_status ah_hier_level_sizes(const ah_hier* h, int l, int64_t* n, int64_t* nnz,
+                              int64_t* nnz_r);
+/* A_l (CSR), C/F marks (1 = C, int8), one-point P (coarse column or -1 per
+ * fine point), R_l (CSR).  Any pointer may be NULL; sizes from
+ * ah_hier_level_sizes.  The coarsest level has no cf/pcol/R. */
+ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_t* col,
+                               double* val, int8_t* cf, int32_t* pcol, int64_t* r_row_ptr,
+                               int32_t* r_col, double* r_val, void* stream);
+
+/* ---------------------------------------------------------- air_solve ---
+ * FGMRES(restart) with right preconditioning by one V-cycle (no
+ * pre-relaxation, post-relaxation F,F,C; Section 4) on S_hat x = D_b^-1 rhs.
+ * rhs dev [n_free] unscaled, or NULL for the assembled H; x dev [n_free]
+ * (initial guess if x0_given, else zero; overwritten by the solution).
+ * Convergence: ||r_hat|| <= tol ||D_b^-1 rhs|| estimated by the Arnoldi
+ * recurrence and confirmed by a true residual in FP64 (restart otherwise).
+ * precision 1: the V-cycle runs in FP32 (FP32 operators, FP32 accumulation)
+ * inside the FP64 FGMRES; the coarsest solve stays FP64.  Returns AH_ENOCONV
+ * if maxit is reached (x holds the best iterate), AH_EBREAKDOWN on NaN. */
+typedef struct {
+  double tol;       /* default 1e-8 */
+  int restart;      /* default 100 */
+  int maxit;        /* default 1000 */
+  int precision;    /* 0 FP64 cycle, 1 FP32 cycle */
+  int x0_given;
+} ah_solve_params;
+
+typedef struct {
+  int iters;
+  int converged;
+  double relres;        /* estimated scaled relative residual at exit */
+  double true_relres;   /* recomputed ||H_hat - S_hat x|| / ||H_hat|| */
+  double t_solve_ms;
+} ah_solve_info;
+
+void ah_solve_defaults(ah_solve_params* p);
+
+ah_status air_solve(const ah_hier* h, const double* rhs, double* x, const ah_solve_params* prm,
+                    void* stream, ah_solve_info* info);
+
+/* Adjoint solve S^T lam = g: FGMRES on S_hat^T mu = g with the transposed
+ * V-cycle (sweeps C,F,F with A_l^T, restriction by P_l^T, interpolation by
+ * R_l^T, transposed coarsest solve), then lam = D_b^-T mu.  g dev [n_free],
+ * lam dev [n_free].  Requires air_setup with adjoint = 1. */
+ah_status air_solve_adjoint(const ah_hier* h, const double* g, double* lam,
+                            const ah_solve_params* prm, void* stream, ah_solve_info* info);
+
+/* One application of the preconditioner z = B r (transpose = 1: B^T r) on
+ * the scaled level-0 system, for inspection: r, z dev [n_free]. */
+ah_status ah_vcycle_apply(const ah_hier* h, const double* r, double* z, int precision,
+                          int transpose, void* stream);
+
+/* -------------------------------------------------- adjoint gradients ---
+ * For J(Lambda) with dJ/dLambda = g and the adjoint lam = S^-T g of a
+ * solved system with solution Lambda (both dev [n_free]):
+ *   dJdf_q dev [ne][nq]: derivative of J with respect to the source values at
+ *          the element quadrature points (through F_K = int f v);
+ *   dJdnu  host scalar: derivative with respect to nu (the blocks are affine
+ *          in nu), sum over elements of
+ *          -w_K.(A1 U + B1 Lambda) - lam_K.(C1 U + D1 Lambda),
+ *          w_K = -A_K^-T C_K^T lam_K.
+ * Requires keep_element_data.  Synchronizes the stream. */
+ah_status hdg_assemble_grad(const ah_system* s, const double* a_vert, const double* lam_fwd,
+                            const double* lam_adj, double* dJdf_q, double* dJdnu, void* stream);
+
+/* Gaussian sources phi_k(X) = exp(-|X - X_k|^2 / (2 w^2)) at points X dev
+ * [npts][dim_st]; centers dev [K][dim_st].
+ *   forward:   f dev [npts] = sum_k c_k phi_k(X)          (c dev [K])
+ *   transpose: dc dev [K] = sum_pts y(X) phi_k(X)         (y dev [npts]) */
+ah_status ah_source_gauss(int dim_st, int64_t npts, const double* X, int K, const double* centers,
+                          double width, const double* c, double* f, void* stream);
+ah_status ah_source_gauss_T(int dim_st, int64_t npts, const double* X, int K,
+                            const double* centers, double width, const double* y, double* dc,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIRHDG_H */

@@ -1,0 +1,12 @@
+"""airhdg: space-time HDG + lAIR-preconditioned FGMRES on one MI355X.
+
+The compute path is the HIP library ``libairhdg.so`` (C-ABI in
+``include/airhdg.h``); this package only marshals arguments.
+"""
+from .api import (Mesh, System, Hierarchy, AIRSolve, HDGSolve, sizes, quad_rule,
+                  source_gauss, source_gauss_T, air_params, solve_params)
+from ._lib import lib, AirHdgError, LIB_PATH
+
+__all__ = ["Mesh", "System", "Hierarchy", "AIRSolve", "HDGSolve", "sizes", "quad_rule",
+           "source_gauss", "source_gauss_T", "air_params", "solve_params", "lib",
+           "AirHdgError", "LIB_PATH"]

@@ -1,0 +1,311 @@
+"""Python binding of the airhdg C-ABI: argument marshalling only.
+
+torch tensors provide device memory and the current HIP stream; every step
+of the method runs in the library's HIP kernels.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import (lib, check, HdgParams, AirParams, SetupInfo, SolveParams, SolveInfo,
+                   AH_OK, AH_ENOCONV)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype=torch.float64):
+    if x is None:
+        return None
+    t = torch.as_tensor(x, dtype=dtype)
+    if t.device.type != "cuda":
+        t = t.cuda()
+    return t.contiguous()
+
+
+def sizes(dim_st, p):
+    """(nq, nqf, nu, b) for space-time dimension ``dim_st`` and degree ``p``."""
+    a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    check(lib().ah_sizes(dim_st, p, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "ah_sizes")
+    return a.value, b.value, c.value, d.value
+
+
+def quad_rule(dim, n):
+    """Conical-product rule on the reference simplex (host arrays)."""
+    nq = n ** dim
+    xi = np.zeros((nq, max(dim, 1)))
+    w = np.zeros(nq)
+    check(lib().ah_quad_rule(dim, n, xi.ctypes.data, w.ctypes.data), "ah_quad_rule")
+    return xi[:, :dim], w
+
+
+class Mesh:
+    """Space-time simplex mesh; topology built on the host by the library."""
+
+    def __init__(self, vert, cell):
+        vert = np.ascontiguousarray(vert, dtype=np.float64)
+        cell = np.ascontiguousarray(cell, dtype=np.int32)
+        self.D = vert.shape[1]
+        self.nv, self.ne = vert.shape[0], cell.shape[0]
+        h = C.c_void_p()
+        check(lib().ah_mesh_create(self.D, self.nv, vert.ctypes.data, self.ne, cell.ctypes.data,
+                                   C.byref(h)), "ah_mesh_create")
+        self.h = h
+        nf, nbf = C.c_int64(), C.c_int64()
+        check(lib().ah_mesh_sizes(h, C.byref(nf), C.byref(nbf)), "ah_mesh_sizes")
+        self.nf, self.nbf = nf.value, nbf.value
+        self.vert = vert
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().ah_mesh_destroy(self.h)
+            self.h = None
+
+    def facets(self):
+        fv = np.zeros((self.nf, self.D), dtype=np.int32)
+        fe = np.zeros((self.nf, 2), dtype=np.int32)
+        check(lib().ah_mesh_facets(self.h, fv.ctypes.data, fe.ctypes.data), "ah_mesh_facets")
+        return fv, fe
+
+    def boundary_facets(self):
+        ids = np.zeros(self.nbf, dtype=np.int32)
+        if self.nbf:
+            check(lib().ah_mesh_boundary_facets(self.h, ids.ctypes.data), "ah_mesh_boundary_facets")
+        return ids
+
+    def set_bc(self, kind):
+        kind = np.ascontiguousarray(kind, dtype=np.int8)
+        check(lib().ah_mesh_set_bc(self.h, kind.ctypes.data), "ah_mesh_set_bc")
+        self.kind = kind
+
+    def quad_points(self, p):
+        """Element and boundary-facet quadrature points (device tensors)."""
+        nq, nqf, _, _ = sizes(self.D, p)
+        xe = torch.empty((self.ne, nq, self.D), dtype=torch.float64, device="cuda")
+        xb = torch.empty((max(self.nbf, 1), nqf, self.D), dtype=torch.float64, device="cuda")
+        check(lib().ah_quad_points(self.h, p, _p(xe), _p(xb), _stream()), "ah_quad_points")
+        return xe, xb[:self.nbf]
+
+
+class System:
+    """Assembled, condensed and scaled facet system (``hdg_assemble``)."""
+
+    def __init__(self, mesh, p, nu, a_vert, f_q=None, g_q=None, alpha=0.0, keep=True):
+        self.mesh = mesh
+        self.p = p
+        self.nu = float(nu)
+        self._a = _dev(a_vert)
+        self._f = _dev(f_q)
+        self._g = _dev(g_q)
+        prm = HdgParams(p, float(alpha), 1 if keep else 0)
+        h = C.c_void_p()
+        check(lib().hdg_assemble(mesh.h, C.byref(prm), float(nu), _p(self._a), _p(self._f), _p(self._g),
+                                 _stream(), C.byref(h)), "hdg_assemble")
+        self.h = h
+        n, b, nnz = C.c_int64(), C.c_int(), C.c_int64()
+        check(lib().ah_system_sizes(h, C.byref(n), C.byref(b), C.byref(nnz)), "ah_system_sizes")
+        self.n, self.b, self.nnz = n.value, b.value, nnz.value
+        self.nq, self.nqf, self.nu_dofs, _ = sizes(mesh.D, p)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().ah_system_destroy(self.h)
+            self.h = None
+
+    def export(self):
+        """Scaled CSR matrix, H_hat, D_b^-1 and the Dirichlet traces (device)."""
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device="cuda")
+        va = torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
+        hh = torch.empty(max(self.n, 1), dtype=torch.float64, device="cuda")
+        dinv = torch.empty((max(self.n // self.b, 1), self.b, self.b), dtype=torch.float64, device="cuda")
+        lamd = torch.empty((self.mesh.nf, self.b), dtype=torch.float64, device="cuda")
+        check(lib().ah_system_export(self.h, _p(rp), _p(ci), _p(va), _p(hh), _p(dinv), _p(lamd), _stream()),
+              "ah_system_export")
+        torch.cuda.synchronize()
+        return {"rowptr": rp, "col": ci[:self.nnz], "val": va[:self.nnz], "hhat": hh[:self.n],
+                "dinv": dinv[:self.n // self.b], "lam_dir": lamd}
+
+    def reconstruct(self, lam):
+        U = torch.empty((self.mesh.ne, self.nu_dofs), dtype=torch.float64, device="cuda")
+        check(lib().hdg_reconstruct(self.h, _p(lam.contiguous()), _p(U), _stream()), "hdg_reconstruct")
+        return U
+
+    def inflow_from(self, prev, lam_prev, g_q):
+        """Write ``prev``'s final-plane trace into this system's inflow rows of ``g_q``."""
+        check(lib().hdg_inflow_from_trace(prev.h, _p(lam_prev.contiguous()), self.h, _p(g_q), _stream()),
+              "hdg_inflow_from_trace")
+        return g_q
+
+    def grad(self, lam_fwd, lam_adj, a_vert=None, want_f=True):
+        """dJ/df at the element quadrature points and dJ/dnu (``hdg_assemble_grad``)."""
+        dq = torch.empty((self.mesh.ne, self.nq), dtype=torch.float64, device="cuda") if want_f else None
+        dnu = C.c_double()
+        a = self._a if a_vert is None else _dev(a_vert)
+        check(lib().hdg_assemble_grad(self.h, _p(a), _p(lam_fwd.contiguous()), _p(lam_adj.contiguous()),
+                                      _p(dq), C.byref(dnu), _stream()), "hdg_assemble_grad")
+        return dq, dnu.value
+
+
+def air_params(**kw):
+    p = AirParams()
+    lib().ah_air_defaults(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def solve_params(**kw):
+    p = SolveParams()
+    lib().ah_solve_defaults(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Hierarchy:
+    """lAIR hierarchy of a system (``air_setup``)."""
+
+    def __init__(self, system, **kw):
+        self.system = system
+        self.prm = air_params(**kw)
+        info = SetupInfo()
+        h = C.c_void_p()
+        check(lib().air_setup(system.h, C.byref(self.prm), _stream(), C.byref(h), C.byref(info)), "air_setup")
+        self.h = h
+        self.info = {"levels": info.levels, "n": list(info.n[:info.levels]),
+                     "nnz": list(info.nnz[:info.levels]), "n_fallback": info.n_fallback,
+                     "op_complexity": info.op_complexity, "t_setup_ms": info.t_setup_ms}
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().ah_hier_destroy(self.h)
+            self.h = None
+
+    def solve(self, rhs=None, x0=None, out=None, **kw):
+        """FGMRES + V-cycle: ``S Lambda = rhs`` (unscaled; ``None`` = assembled H)."""
+        prm = solve_params(**kw)
+        n = self.system.n
+        x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+        if x0 is not None:
+            x.copy_(x0)
+            prm.x0_given = 1
+        info = SolveInfo()
+        st = check(lib().air_solve(self.h, _p(rhs), _p(x), C.byref(prm), _stream(), C.byref(info)),
+                   "air_solve", allow=(AH_OK, AH_ENOCONV))
+        return x, _info(info, st)
+
+    def solve_adjoint(self, g, out=None, **kw):
+        """``S^T lam = g`` with the transposed cycle."""
+        prm = solve_params(**kw)
+        lam = out if out is not None else torch.empty(self.system.n, dtype=torch.float64, device="cuda")
+        info = SolveInfo()
+        st = check(lib().air_solve_adjoint(self.h, _p(g.contiguous()), _p(lam), C.byref(prm), _stream(),
+                                           C.byref(info)), "air_solve_adjoint", allow=(AH_OK, AH_ENOCONV))
+        return lam, _info(info, st)
+
+    def vcycle(self, r, precision=0, transpose=False):
+        z = torch.empty_like(r)
+        check(lib().ah_vcycle_apply(self.h, _p(r.contiguous()), _p(z), int(precision), int(bool(transpose)),
+                                    _stream()), "ah_vcycle_apply")
+        return z
+
+    def level(self, l):
+        n, nnz, nnzr = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().ah_hier_level_sizes(self.h, l, C.byref(n), C.byref(nnz), C.byref(nnzr)), "level_sizes")
+        n, nnz, nnzr = n.value, nnz.value, nnzr.value
+        coarse = l + 1 < self.info["levels"]
+        e = lambda k, dt: torch.empty(max(k, 1), dtype=dt, device="cuda")
+        out = {"rowptr": e(n + 1, torch.int64), "col": e(nnz, torch.int32), "val": e(nnz, torch.float64)}
+        if coarse:
+            nc = self.info["n"][l + 1]
+            out.update({"cf": e(n, torch.int8), "pcol": e(n, torch.int32), "Rptr": e(nc + 1, torch.int64),
+                        "Rcol": e(nnzr, torch.int32), "Rval": e(nnzr, torch.float64)})
+        g = out.get
+        check(lib().ah_hier_level_export(self.h, l, _p(g("rowptr")), _p(g("col")), _p(g("val")), _p(g("cf")),
+                                         _p(g("pcol")), _p(g("Rptr")), _p(g("Rcol")), _p(g("Rval")), _stream()),
+              "level_export")
+        torch.cuda.synchronize()
+        out["col"], out["val"] = out["col"][:nnz], out["val"][:nnz]
+        if coarse:
+            out["cf"], out["pcol"] = out["cf"][:n], out["pcol"][:n]
+            out["Rcol"], out["Rval"] = out["Rcol"][:nnzr], out["Rval"][:nnzr]
+        out["n"], out["nnz"] = n, nnz
+        return out
+
+
+def _info(info, st):
+    return {"iters": info.iters, "converged": bool(info.converged), "relres": info.relres,
+            "true_relres": info.true_relres, "t_solve_ms": info.t_solve_ms, "status": st}
+
+
+def source_gauss(X, centers, width, c):
+    """``f(X) = sum_k c_k exp(-|X - X_k|^2 / (2 width^2))`` (device)."""
+    X = X.contiguous()
+    D = X.shape[-1]
+    npts = X.numel() // D
+    f = torch.empty(X.shape[:-1], dtype=torch.float64, device="cuda")
+    cen = _dev(centers)
+    cc = _dev(c)
+    check(lib().ah_source_gauss(D, npts, _p(X), cen.shape[0], _p(cen), float(width), _p(cc), _p(f), _stream()),
+          "ah_source_gauss")
+    return f
+
+
+def source_gauss_T(X, centers, width, y):
+    """``dc_k = sum_points y(X) phi_k(X)`` (device)."""
+    X = X.contiguous()
+    D = X.shape[-1]
+    npts = X.numel() // D
+    cen = _dev(centers)
+    dc = torch.empty(cen.shape[0], dtype=torch.float64, device="cuda")
+    check(lib().ah_source_gauss_T(D, npts, _p(X), cen.shape[0], _p(cen), float(width), _p(y.contiguous()),
+                                  _p(dc), _stream()), "ah_source_gauss_T")
+    return dc
+
+
+class AIRSolve(torch.autograd.Function):
+    """``Lambda = S^-1 rhs``; the backward pass solves ``S^T lam = dL/dLambda``
+    with the transposed hierarchy (P^T restriction, R^T interpolation)."""
+
+    @staticmethod
+    def forward(ctx, rhs, hier, tol=1e-8, precision=0):
+        x, info = hier.solve(rhs.detach(), tol=tol, precision=precision)
+        ctx.hier, ctx.tol, ctx.precision = hier, tol, precision
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        lam, _ = ctx.hier.solve_adjoint(g.contiguous(), tol=ctx.tol, precision=ctx.precision)
+        return lam, None, None, None
+
+
+class HDGSolve(torch.autograd.Function):
+    """``Lambda(f_q, nu)``: assembly, AIR setup and solve in the forward pass;
+    the backward pass returns ``dJ/df_q`` (at the element quadrature points)
+    and ``dJ/dnu`` from one adjoint solve and the element adjoint."""
+
+    @staticmethod
+    def forward(ctx, f_q, nu, mesh, p, a_vert, g_q, tol=1e-12, precision=0, air_kw=None):
+        sysm = System(mesh, p, float(nu), a_vert, f_q.detach(), g_q)
+        hier = Hierarchy(sysm, adjoint=1, fp32_cycle=1 if precision else 0, **(air_kw or {}))
+        lam, info = hier.solve(tol=tol, precision=precision)
+        ctx.sysm, ctx.hier, ctx.tol, ctx.precision = sysm, hier, tol, precision
+        ctx.save_for_backward(lam)
+        ctx.nu_is_tensor = torch.is_tensor(nu)
+        return lam
+
+    @staticmethod
+    def backward(ctx, g):
+        (lam,) = ctx.saved_tensors
+        adj, _ = ctx.hier.solve_adjoint(g.contiguous(), tol=ctx.tol, precision=ctx.precision)
+        dq, dnu = ctx.sysm.grad(lam, adj)
+        gnu = torch.tensor(dnu, dtype=torch.float64) if ctx.nu_is_tensor else None
+        return dq, gnu, None, None, None, None, None, None, None

@@ -1,0 +1,931 @@
+// hdg_assemble: element blocks of the space-time HDG bilinear form
+// (Section 2.3), static condensation (Section 2.5), deterministic scatter
+// into the free-facet block pattern, Dirichlet elimination, and the left
+// facet-block-diagonal scaling of Section 4 fused into the conversion to the
+// scalar CSR matrix used by AIR.  Also reconstruction, slab coupling and
+// the adjoint gradient kernel.
+//
+// One workgroup (one wave) per element.  The element basis is the monomial
+// basis xi^alpha on the reference simplex of the cell; facet unknowns use the
+// nodal Lagrange basis on the sorted-vertex facet simplex.  Rows = test
+// functions, columns = trial functions:
+//   A(u,v) = int_K (-u a_hat.grad_hat v + nu grad u.grad v)
+//            + sum_F int_F [(a+ + tau) u v - nu (grad u.n) v - nu u (grad v.n)]
+//   B(l,v) = sum_F int_F [(a- - tau) l v + nu l (grad v.n)]
+//   C(u,m) = sum_F int_F [-(a+ + tau) u m + nu (grad u.n) m]
+//   D(l,m) = sum_F int_F [-(a- - tau) l m] + [F Neumann] int_F a+ l m
+//   F(v) = int_K f v,  G(m) = [F Neumann] int_F g m
+// with a_n = n_t + a.n, a+ = (a_n+|a_n|)/2, a- = (a_n-|a_n|)/2,
+// tau = nu alpha / h_K, h_K = |det J|^(1/D); grad = spatial gradient.
+#include <cmath>
+
+#include "system.h"
+
+namespace ah {
+
+template <int D, int P>
+struct Sz {
+  static constexpr int NU = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+  static constexpr int B = D == 2 ? (P + 1) : (P + 1) * (P + 2) / 2;
+  static constexpr int NFc = D + 1;
+  static constexpr int NL = NFc * B;
+  static constexpr int N1 = P + 2;
+  static constexpr int NQ = D == 2 ? N1 * N1 : N1 * N1 * N1;
+  static constexpr int NQF = D == 2 ? N1 : N1 * N1;
+  static constexpr int QC = NQ < 32 ? NQ : 32;
+  static constexpr int NR = NL + 1 + NU;   // right-hand sides of the element solve
+};
+
+struct ElemArgs {
+  int64_t ne;
+  const double* vert;
+  const int32_t* cell;
+  const int32_t* elem_facet;
+  const uint8_t* facet_loc;
+  const int8_t* kind;
+  const int32_t* bf_index;
+  const int32_t* free_rank;
+  const int32_t* elem_slot;
+  const double* a_vert;
+  const double* f_q;
+  const double* g_q;
+  const double* vol_w;
+  const double* vol_lam;
+  const double* vol_phi;
+  const double* vol_dphi;
+  const double* fac_w;
+  const double* fac_mu;
+  const double* fac_psi;
+  const double* fac_proj;
+  double nu, alpha;
+  double* bval;
+  double* H;
+  double* lamD;
+  double* Ainv;
+  double* Bm;
+  double* Cm;
+  double* Fv;
+  int* err;
+  // gradient mode
+  const double* lam_fwd;   // [n_free] forward solution (Dirichlet traces from lamD)
+  const double* lam_adj;   // [n_free] adjoint solution (zero on Dirichlet facets)
+  double* dJdf_q;          // [ne][nq]
+  double* dnu_elem;        // [ne]
+  int8_t mono[20][3];
+};
+
+template <int D, int P>
+struct ElemSmem {
+  using S = Sz<D, P>;
+  double X[(D + 1) * D];
+  double av[(D + 1) * (D - 1)];
+  double Jinv[D * D];
+  double absdet, tau;
+  double nrm[(D + 1) * D];
+  double area[D + 1];
+  double eta[(D + 1) * D];
+  int fid[D + 1], kindf[D + 1], bidx[D + 1], loc[(D + 1) * D];
+  double A[S::NU * S::NU];
+  double Bm[S::NU * S::NL];
+  double Cm[S::NL * S::NU];
+  double Dd[(D + 1) * S::B * S::B];
+  double F[S::NU];
+  double G[S::NL];
+  double LD[S::NL];
+  double q_phi[S::QC * S::NU];
+  double q_adv[S::QC * S::NU];
+  double q_gx[S::QC * S::NU * (D - 1)];
+  double q_W[S::QC];
+  double q_f[S::QC];
+  double f_phi[S::NQF * S::NU];
+  double f_dn[S::NQF * S::NU];
+  double f_cA[S::NQF], f_cB[S::NQF], f_cD[S::NQF], f_W[S::NQF], f_g[S::NQF];
+  double Xs[S::NU * S::NR];
+  double Sk[S::NL * S::NL];
+  double Hk[S::NL];
+  int piv[S::NU];
+};
+
+// Element geometry: inverse Jacobian, penalty, facet normals/areas.
+template <int D, int P>
+__device__ void elem_geometry(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e, double nu_eff, double alpha) {
+  const int t = threadIdx.x;
+  if (t < (D + 1) * D) {
+    int k = t / D, c = t % D;
+    sm.X[t] = a.vert[(int64_t)a.cell[e * (D + 1) + k] * D + c];
+    sm.loc[t] = a.facet_loc[e * (D + 1) * D + t];
+  }
+  if (t < (D + 1) * (D - 1)) {
+    int k = t / (D - 1), c = t % (D - 1);
+    sm.av[t] = a.a_vert ? a.a_vert[(int64_t)a.cell[e * (D + 1) + k] * (D - 1) + c] : 0.0;
+  }
+  if (t < D + 1) {
+    int f = a.elem_facet[e * (D + 1) + t];
+    sm.fid[t] = f;
+    sm.kindf[t] = a.kind[f];
+    sm.bidx[t] = a.bf_index[f];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double J[D * D];   // J[r][c] = X[c+1][r] - X[0][r]
+    for (int r = 0; r < D; ++r)
+      for (int c = 0; c < D; ++c) J[r * D + c] = sm.X[(c + 1) * D + r] - sm.X[r];
+    double det;
+    double Ji[D * D];
+    if (D == 2) {
+      det = J[0] * J[3] - J[1] * J[2];
+      Ji[0] = J[3] / det; Ji[1] = -J[1] / det; Ji[2] = -J[2] / det; Ji[3] = J[0] / det;
+    } else {
+      double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+      det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+      Ji[0] = c00 / det; Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det; Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+      Ji[3] = c01 / det; Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det; Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+      Ji[6] = c02 / det; Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det; Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+    }
+    for (int k = 0; k < D * D; ++k) sm.Jinv[k] = Ji[k];
+    double ad = fabs(det);
+    sm.absdet = ad;
+    double h = pow(ad, 1.0 / D);
+    sm.tau = nu_eff * alpha / h;
+    double fact = D == 2 ? 2.0 : 6.0;
+    for (int lf = 0; lf <= D; ++lf) {
+      double g[D];
+      for (int c = 0; c < D; ++c) {
+        double v = 0.0;
+        if (lf == 0)
+          for (int r = 0; r < D; ++r) v -= Ji[r * D + c];
+        else
+          v = Ji[(lf - 1) * D + c];
+        g[c] = v;
+      }
+      double gn = 0.0;
+      for (int c = 0; c < D; ++c) gn += g[c] * g[c];
+      gn = sqrt(gn);
+      for (int c = 0; c < D; ++c) sm.nrm[lf * D + c] = -g[c] / gn;
+      sm.area[lf] = D * (ad / fact) * gn;
+      for (int r = 0; r < D; ++r) {
+        double v = 0.0;
+        for (int c = 1; c < D; ++c) v += Ji[r * D + c] * sm.nrm[lf * D + c];
+        sm.eta[lf * D + r] = v;
+      }
+    }
+    if (!(ad > 0.0) || !isfinite(ad)) atomicOr(a.err, 2);
+  }
+  __syncthreads();
+}
+
+// Monomial xi^alpha and its reference gradient.
+template <int D>
+__device__ inline double mono_eval(const int8_t* ex, const double* xi, double* dv) {
+  double pw[D][4];
+  for (int c = 0; c < D; ++c) {
+    pw[c][0] = 1.0;
+    for (int k = 1; k < 4; ++k) pw[c][k] = pw[c][k - 1] * xi[c];
+  }
+  double v = 1.0;
+  for (int c = 0; c < D; ++c) v *= pw[c][ex[c]];
+  for (int c = 0; c < D; ++c) {
+    if (ex[c] == 0) { dv[c] = 0.0; continue; }
+    double d = (double)ex[c] * pw[c][ex[c] - 1];
+    for (int o = 0; o < D; ++o)
+      if (o != c) d *= pw[o][ex[o]];
+    dv[c] = d;
+  }
+  return v;
+}
+
+// Integrate A, B, C, D (diagonal facet blocks), F, G and the Dirichlet traces.
+// advect = false and nu_eff = 1 gives the nu-derivative of the blocks.
+template <int D, int P>
+__device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e, double nu_eff, bool advect,
+                               bool data) {
+  using S = Sz<D, P>;
+  constexpr int NU = S::NU, NL = S::NL, B = S::B, NQ = S::NQ, NQF = S::NQF, QC = S::QC;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  for (int k = t; k < NU * NU; k += NT) sm.A[k] = 0.0;
+  for (int k = t; k < NU; k += NT) sm.F[k] = 0.0;
+  for (int k = t; k < NL; k += NT) { sm.G[k] = 0.0; sm.LD[k] = 0.0; }
+  __syncthreads();
+  // ---- volume terms
+  for (int q0 = 0; q0 < NQ; q0 += QC) {
+    const int nqc = (NQ - q0) < QC ? (NQ - q0) : QC;
+    for (int idx = t; idx < nqc * NU; idx += NT) {
+      int q = idx / NU, i = idx % NU, qq = q0 + q;
+      double dphi[D];
+      for (int c = 0; c < D; ++c) dphi[c] = a.vol_dphi[((int64_t)qq * NU + i) * D + c];
+      double adv = 0.0;
+      if (advect) {
+        double ah[D];
+        ah[0] = 1.0;
+        for (int c = 1; c < D; ++c) {
+          double v = 0.0;
+          for (int k = 0; k <= D; ++k) v += a.vol_lam[qq * (D + 1) + k] * sm.av[k * (D - 1) + c - 1];
+          ah[c] = v;
+        }
+        for (int r = 0; r < D; ++r) {
+          double beta = 0.0;
+          for (int c = 0; c < D; ++c) beta += sm.Jinv[r * D + c] * ah[c];
+          adv += beta * dphi[r];
+        }
+      }
+      sm.q_phi[q * NU + i] = a.vol_phi[qq * NU + i];
+      sm.q_adv[q * NU + i] = adv;
+      for (int c = 1; c < D; ++c) {
+        double g = 0.0;
+        for (int r = 0; r < D; ++r) g += sm.Jinv[r * D + c] * dphi[r];
+        sm.q_gx[(q * NU + i) * (D - 1) + c - 1] = g;
+      }
+    }
+    for (int q = t; q < nqc; q += NT) {
+      sm.q_W[q] = a.vol_w[q0 + q] * sm.absdet;
+      sm.q_f[q] = (data && a.f_q) ? a.f_q[e * NQ + q0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NU * NU; idx += NT) {
+      int i = idx / NU, j = idx % NU;
+      double acc = 0.0;
+      for (int q = 0; q < nqc; ++q) {
+        double dif = 0.0;
+        for (int c = 0; c < D - 1; ++c) dif += sm.q_gx[(q * NU + j) * (D - 1) + c] * sm.q_gx[(q * NU + i) * (D - 1) + c];
+        acc += sm.q_W[q] * (-sm.q_phi[q * NU + j] * sm.q_adv[q * NU + i] + nu_eff * dif);
+      }
+      sm.A[idx] += acc;
+    }
+    for (int i = t; i < NU; i += NT) {
+      double acc = 0.0;
+      for (int q = 0; q < nqc; ++q) acc += sm.q_W[q] * sm.q_f[q] * sm.q_phi[q * NU + i];
+      sm.F[i] += acc;
+    }
+    __syncthreads();
+  }
+  // ---- facet terms
+  for (int lf = 0; lf <= D; ++lf) {
+    const bool isN = sm.kindf[lf] == 2;
+    const bool isD = sm.kindf[lf] == 1;
+    for (int idx = t; idx < NQF * NU; idx += NT) {
+      int q = idx / NU, i = idx % NU;
+      double lam[D + 1];
+      for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+      for (int s = 0; s < D; ++s) lam[sm.loc[lf * D + s]] = a.fac_mu[q * D + s];
+      double xi[D], dv[D];
+      for (int c = 0; c < D; ++c) xi[c] = lam[c + 1];
+      double v = mono_eval<D>(a.mono[i], xi, dv);
+      double dn = 0.0;
+      for (int c = 0; c < D; ++c) dn += dv[c] * sm.eta[lf * D + c];
+      sm.f_phi[q * NU + i] = v;
+      sm.f_dn[q * NU + i] = dn;
+    }
+    for (int q = t; q < NQF; q += NT) {
+      double lam[D + 1];
+      for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+      for (int s = 0; s < D; ++s) lam[sm.loc[lf * D + s]] = a.fac_mu[q * D + s];
+      double an = 0.0;
+      if (advect) {
+        an = sm.nrm[lf * D];
+        for (int c = 1; c < D; ++c) {
+          double v = 0.0;
+          for (int k = 0; k <= D; ++k) v += lam[k] * sm.av[k * (D - 1) + c - 1];
+          an += v * sm.nrm[lf * D + c];
+        }
+      }
+      double ap = 0.5 * (an + fabs(an)), am = 0.5 * (an - fabs(an));
+      double W = a.fac_w[q] * sm.area[lf];
+      sm.f_W[q] = W;
+      sm.f_cA[q] = W * (ap + sm.tau);
+      sm.f_cB[q] = W * (am - sm.tau);
+      sm.f_cD[q] = -W * (am - sm.tau) + ((isN && advect) ? W * ap : 0.0);
+      sm.f_g[q] = (data && a.g_q && sm.bidx[lf] >= 0) ? a.g_q[(int64_t)sm.bidx[lf] * NQF + q] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NU * NU; idx += NT) {
+      int i = idx / NU, j = idx % NU;
+      double acc = 0.0;
+      for (int q = 0; q < NQF; ++q) {
+        double pi = sm.f_phi[q * NU + i], pj = sm.f_phi[q * NU + j];
+        acc += sm.f_cA[q] * pj * pi - nu_eff * sm.f_W[q] * (sm.f_dn[q * NU + j] * pi + pj * sm.f_dn[q * NU + i]);
+      }
+      sm.A[idx] += acc;
+    }
+    for (int idx = t; idx < NU * B; idx += NT) {
+      int i = idx / B, m = idx % B;
+      double acc = 0.0;
+      for (int q = 0; q < NQF; ++q) {
+        double psi = a.fac_psi[q * B + m];
+        acc += sm.f_cB[q] * psi * sm.f_phi[q * NU + i] + nu_eff * sm.f_W[q] * psi * sm.f_dn[q * NU + i];
+      }
+      sm.Bm[i * NL + lf * B + m] = acc;
+    }
+    for (int idx = t; idx < B * NU; idx += NT) {
+      int m = idx / NU, j = idx % NU;
+      double acc = 0.0;
+      for (int q = 0; q < NQF; ++q) {
+        double psi = a.fac_psi[q * B + m];
+        acc += -sm.f_cA[q] * sm.f_phi[q * NU + j] * psi + nu_eff * sm.f_W[q] * sm.f_dn[q * NU + j] * psi;
+      }
+      sm.Cm[(lf * B + m) * NU + j] = acc;
+    }
+    for (int idx = t; idx < B * B; idx += NT) {
+      int m = idx / B, n = idx % B;
+      double acc = 0.0;
+      for (int q = 0; q < NQF; ++q) acc += sm.f_cD[q] * a.fac_psi[q * B + m] * a.fac_psi[q * B + n];
+      sm.Dd[lf * B * B + idx] = acc;
+    }
+    if (data) {
+      for (int m = t; m < B; m += NT) {
+        if (isN) {
+          double acc = 0.0;
+          for (int q = 0; q < NQF; ++q) acc += sm.f_W[q] * sm.f_g[q] * a.fac_psi[q * B + m];
+          sm.G[lf * B + m] = acc;
+        }
+        if (isD) {
+          double acc = 0.0;
+          for (int q = 0; q < NQF; ++q) acc += a.fac_proj[m * NQF + q] * sm.f_g[q];
+          sm.LD[lf * B + m] = acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// LU with partial pivoting of sm.A (in place, pivots in sm.piv) and the
+// solve of A X = [B | F | I] into sm.Xs.
+template <int D, int P>
+__device__ void elem_factor_solve(const ElemArgs& a, ElemSmem<D, P>& sm) {
+  using S = Sz<D, P>;
+  constexpr int NU = S::NU, NL = S::NL, NR = S::NR;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  for (int k = 0; k < NU; ++k) {
+    if (t == 0) {
+      int p = k;
+      double best = fabs(sm.A[k * NU + k]);
+      for (int r = k + 1; r < NU; ++r) {
+        double v = fabs(sm.A[r * NU + k]);
+        if (v > best) { best = v; p = r; }
+      }
+      sm.piv[k] = p;
+      if (!(best > 0.0) || !isfinite(best)) atomicOr(a.err, 1);
+    }
+    __syncthreads();
+    int p = sm.piv[k];
+    if (p != k)
+      for (int c = t; c < NU; c += NT) {
+        double x = sm.A[k * NU + c];
+        sm.A[k * NU + c] = sm.A[p * NU + c];
+        sm.A[p * NU + c] = x;
+      }
+    __syncthreads();
+    double d = sm.A[k * NU + k];
+    for (int r = k + 1 + t; r < NU; r += NT) sm.A[r * NU + k] /= d;
+    __syncthreads();
+    const int m = NU - k - 1;
+    for (int idx = t; idx < m * m; idx += NT) {
+      int r = k + 1 + idx / m, c = k + 1 + idx % m;
+      sm.A[r * NU + c] -= sm.A[r * NU + k] * sm.A[k * NU + c];
+    }
+    __syncthreads();
+  }
+  for (int c = t; c < NR; c += NT) {
+    double x[NU];
+    for (int r = 0; r < NU; ++r)
+      x[r] = c < NL ? sm.Bm[r * NL + c] : (c == NL ? sm.F[r] : (r == c - NL - 1 ? 1.0 : 0.0));
+    for (int k = 0; k < NU; ++k) {
+      int p = sm.piv[k];
+      double tmp = x[k]; x[k] = x[p]; x[p] = tmp;
+    }
+    for (int r = 1; r < NU; ++r)
+      for (int k = 0; k < r; ++k) x[r] -= sm.A[r * NU + k] * x[k];
+    for (int r = NU - 1; r >= 0; --r) {
+      double v = x[r];
+      for (int k = r + 1; k < NU; ++k) v -= sm.A[r * NU + k] * x[k];
+      x[r] = v / sm.A[r * NU + r];
+    }
+    for (int r = 0; r < NU; ++r) sm.Xs[r * NR + c] = x[r];
+  }
+  __syncthreads();
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(64) void k_element(ElemArgs a) {
+  using S = Sz<D, P>;
+  constexpr int NU = S::NU, NL = S::NL, B = S::B, NR = S::NR;
+  __shared__ ElemSmem<D, P> sm;
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  elem_geometry<D, P>(a, sm, e, a.nu, a.alpha);
+  elem_integrate<D, P>(a, sm, e, a.nu, true, true);
+  // keep the unfactored blocks
+  if (a.Bm) {
+    for (int k = t; k < NU * NL; k += NT) a.Bm[e * NU * NL + k] = sm.Bm[k];
+    for (int k = t; k < NL * NU; k += NT) a.Cm[e * NL * NU + k] = sm.Cm[k];
+    for (int k = t; k < NU; k += NT) a.Fv[e * NU + k] = sm.F[k];
+  }
+  elem_factor_solve<D, P>(a, sm);
+  // S_K = D_K - C_K A_K^-1 B_K, H_K = G_K - C_K A_K^-1 F_K
+  for (int idx = t; idx < NL * NL; idx += NT) {
+    int r = idx / NL, c = idx % NL;
+    double v = (r / B == c / B) ? sm.Dd[(r / B) * B * B + (r % B) * B + (c % B)] : 0.0;
+    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.Xs[k * NR + c];
+    sm.Sk[idx] = v;
+  }
+  for (int r = t; r < NL; r += NT) {
+    double v = sm.G[r];
+    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.Xs[k * NR + NL];
+    sm.Hk[r] = v;
+  }
+  __syncthreads();
+  // Dirichlet elimination: H_K -= S_K[:, Dirichlet] lambda_D
+  for (int r = t; r < NL; r += NT) {
+    double v = sm.Hk[r];
+    for (int lf = 0; lf <= D; ++lf) {
+      if (sm.kindf[lf] != 1) continue;
+      for (int m = 0; m < B; ++m) v -= sm.Sk[r * NL + lf * B + m] * sm.LD[lf * B + m];
+    }
+    sm.Hk[r] = v;
+  }
+  __syncthreads();
+  // scatter: <= 2 contributions per entry, so the atomic sums are order-independent
+  const int32_t* slot = a.elem_slot + e * (D + 1) * (D + 1);
+  for (int idx = t; idx < NL * NL; idx += NT) {
+    int r = idx / NL, c = idx % NL;
+    int s = slot[(r / B) * (D + 1) + c / B];
+    if (s >= 0) unsafeAtomicAdd(&a.bval[(int64_t)s * B * B + (r % B) * B + (c % B)], sm.Sk[idx]);
+  }
+  for (int r = t; r < NL; r += NT) {
+    int lf = r / B, f = sm.fid[lf];
+    int fr = a.free_rank[f];
+    if (fr >= 0) unsafeAtomicAdd(&a.H[(int64_t)fr * B + r % B], sm.Hk[r]);
+    if (sm.kindf[lf] == 1) a.lamD[(int64_t)f * B + r % B] = sm.LD[r];
+  }
+  if (a.Ainv)
+    for (int k = t; k < NU * NU; k += NT) {
+      int r = k / NU, c = k % NU;
+      a.Ainv[e * NU * NU + k] = sm.Xs[r * NR + NL + 1 + c];
+    }
+}
+
+// Inverse of each free facet's diagonal block (Gauss-Jordan, partial pivoting).
+template <int B>
+__global__ void k_diag_inv(int64_t nfree, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+                           const double* __restrict__ bval, double* __restrict__ dinv, int* err) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nfree) return;
+  int64_t s = -1;
+  for (int64_t k = bptr[r]; k < bptr[r + 1]; ++k)
+    if (bcol[k] == r) { s = k; break; }
+  double M[B * B], I[B * B];
+  for (int k = 0; k < B * B; ++k) { M[k] = s >= 0 ? bval[s * B * B + k] : 0.0; I[k] = (k / B == k % B) ? 1.0 : 0.0; }
+  double scale = 0.0;
+  for (int k = 0; k < B * B; ++k) scale = fmax(scale, fabs(M[k]));
+  bool bad = !(scale > 0.0) || !isfinite(scale);
+  for (int c = 0; c < B; ++c) {
+    int p = c;
+    for (int q = c + 1; q < B; ++q)
+      if (fabs(M[q * B + c]) > fabs(M[p * B + c])) p = q;
+    if (!(fabs(M[p * B + c]) > 1e-14 * scale)) bad = true;
+    for (int j = 0; j < B; ++j) {
+      double x = M[c * B + j]; M[c * B + j] = M[p * B + j]; M[p * B + j] = x;
+      x = I[c * B + j]; I[c * B + j] = I[p * B + j]; I[p * B + j] = x;
+    }
+    double d = M[c * B + c];
+    if (d == 0.0) d = 1.0;
+    for (int j = 0; j < B; ++j) { M[c * B + j] /= d; I[c * B + j] /= d; }
+    for (int q = 0; q < B; ++q) {
+      if (q == c) continue;
+      double f = M[q * B + c];
+      for (int j = 0; j < B; ++j) { M[q * B + j] -= f * M[c * B + j]; I[q * B + j] -= f * I[c * B + j]; }
+    }
+  }
+  if (bad) atomicOr(err, 4);
+  for (int k = 0; k < B * B; ++k) dinv[r * B * B + k] = I[k];
+}
+
+// Scaled scalar rows: row R*B+m of D_b^-1 S over the block row R; the
+// diagonal block becomes the identity; exact zeros off the diagonal are
+// dropped.  count pass (vals == nullptr) and fill pass.
+template <int B>
+__global__ void k_csr_scaled(int64_t nfree, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+                             const double* __restrict__ bval, const double* __restrict__ dinv,
+                             int32_t* __restrict__ cnt, const int64_t* __restrict__ rowptr,
+                             int32_t* __restrict__ col, double* __restrict__ val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfree * B) return;
+  int64_t R = i / B;
+  int m = (int)(i % B);
+  double di[B];
+  for (int k = 0; k < B; ++k) di[k] = dinv[R * B * B + m * B + k];
+  int32_t c = 0;
+  int64_t out = rowptr ? rowptr[i] : 0;
+  for (int64_t s = bptr[R]; s < bptr[R + 1]; ++s) {
+    int32_t C = bcol[s];
+    for (int n = 0; n < B; ++n) {
+      double v;
+      if (C == R) {
+        v = (n == m) ? 1.0 : 0.0;
+      } else {
+        v = 0.0;
+        for (int k = 0; k < B; ++k) v += di[k] * bval[s * B * B + k * B + n];
+      }
+      bool keep = (C == R && n == m) || v != 0.0;
+      if (!keep) continue;
+      if (val) {
+        col[out + c] = (int32_t)(C * B + n);
+        val[out + c] = v;
+      }
+      ++c;
+    }
+  }
+  if (!val) cnt[i] = c;
+}
+
+template <int B>
+__global__ void k_hhat(int64_t nfree, const double* __restrict__ dinv, const double* __restrict__ H,
+                       double* __restrict__ hhat) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfree * B) return;
+  int64_t R = i / B;
+  int m = (int)(i % B);
+  double v = 0.0;
+  for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * H[R * B + k];
+  hhat[i] = v;
+}
+
+// Physical quadrature points (element rule and boundary-facet rule).
+__global__ void k_quad_points_elem(int64_t ne, int D, int nq, const double* __restrict__ vert,
+                                   const int32_t* __restrict__ cell, const double* __restrict__ lam,
+                                   double* __restrict__ xq) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne * nq) return;
+  int64_t e = idx / nq;
+  int q = (int)(idx % nq);
+  for (int c = 0; c < D; ++c) {
+    double v = 0.0;
+    for (int k = 0; k <= D; ++k) v += lam[q * (D + 1) + k] * vert[(int64_t)cell[e * (D + 1) + k] * D + c];
+    xq[idx * D + c] = v;
+  }
+}
+
+__global__ void k_quad_points_bfacet(int64_t nbf, int D, int nqf, const double* __restrict__ vert,
+                                     const int32_t* __restrict__ bfacets, const int32_t* __restrict__ fvert,
+                                     const double* __restrict__ mu, double* __restrict__ xq) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nqf) return;
+  int64_t k = idx / nqf;
+  int q = (int)(idx % nqf);
+  int64_t f = bfacets[k];
+  for (int c = 0; c < D; ++c) {
+    double v = 0.0;
+    for (int s = 0; s < D; ++s) v += mu[q * D + s] * vert[(int64_t)fvert[f * D + s] * D + c];
+    xq[idx * D + c] = v;
+  }
+}
+
+// Adjoint gradient per element: with U = A^-1 (F - B Lambda) and
+// w = -A^-T C^T lam, the derivative of J through F_K at the volume
+// quadrature points, W_q w . phi(x_q), and the nu-derivative
+// -w.(A1 U + B1 Lambda) - lam.(C1 U + D1 Lambda) with X1 = dX/dnu.
+template <int D, int P>
+__global__ __launch_bounds__(64) void k_grad(ElemArgs a) {
+  using S = Sz<D, P>;
+  constexpr int NU = S::NU, NL = S::NL, B = S::B, NQ = S::NQ;
+  __shared__ ElemSmem<D, P> sm;
+  __shared__ double sL[NL], sLa[NL], sR[NU], sU[NU], sT[NU], sW[NU], sred[64];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  elem_geometry<D, P>(a, sm, e, 1.0, a.alpha);
+  elem_integrate<D, P>(a, sm, e, 1.0, false, false);
+  const double* Ai = a.Ainv + e * NU * NU;
+  const double* Bo = a.Bm + e * NU * NL;
+  const double* Co = a.Cm + e * NL * NU;
+  const double* Fo = a.Fv + e * NU;
+  for (int r = t; r < NL; r += NT) {
+    int lf = r / B, m = r % B, f = sm.fid[lf];
+    int fr = a.free_rank[f];
+    sL[r] = fr >= 0 ? a.lam_fwd[(int64_t)fr * B + m] : a.lamD[(int64_t)f * B + m];
+    sLa[r] = fr >= 0 ? a.lam_adj[(int64_t)fr * B + m] : 0.0;
+  }
+  __syncthreads();
+  for (int i = t; i < NU; i += NT) {
+    double r = Fo[i];
+    for (int c = 0; c < NL; ++c) r -= Bo[i * NL + c] * sL[c];
+    sR[i] = r;
+    double tt = 0.0;
+    for (int c = 0; c < NL; ++c) tt += Co[c * NU + i] * sLa[c];
+    sT[i] = tt;
+  }
+  __syncthreads();
+  for (int i = t; i < NU; i += NT) {
+    double u = 0.0, w = 0.0;
+    for (int k = 0; k < NU; ++k) {
+      u += Ai[i * NU + k] * sR[k];
+      w -= Ai[k * NU + i] * sT[k];
+    }
+    sU[i] = u;
+    sW[i] = w;
+  }
+  __syncthreads();
+  if (a.dJdf_q)
+    for (int q = t; q < NQ; q += NT) {
+      double v = 0.0;
+      for (int i = 0; i < NU; ++i) v += sW[i] * a.vol_phi[q * NU + i];
+      a.dJdf_q[e * NQ + q] = a.vol_w[q] * sm.absdet * v;
+    }
+  double acc = 0.0;
+  for (int i = t; i < NU; i += NT) {
+    double v = 0.0;
+    for (int j = 0; j < NU; ++j) v += sm.A[i * NU + j] * sU[j];
+    for (int c = 0; c < NL; ++c) v += sm.Bm[i * NL + c] * sL[c];
+    acc -= sW[i] * v;
+  }
+  for (int r = t; r < NL; r += NT) {
+    double v = 0.0;
+    for (int j = 0; j < NU; ++j) v += sm.Cm[r * NU + j] * sU[j];
+    int lf = r / B, m = r % B;
+    for (int n = 0; n < B; ++n) v += sm.Dd[lf * B * B + m * B + n] * sL[lf * B + n];
+    acc -= sLa[r] * v;
+  }
+  sred[t] = acc;
+  __syncthreads();
+  if (t == 0) {
+    double s2 = 0.0;
+    for (int k = 0; k < NT; ++k) s2 += sred[k];
+    a.dnu_elem[e] = s2;
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+template <int D, int P>
+static ah_status launch_element(const ElemArgs& a, hipStream_t st) {
+  if (a.ne == 0) return AH_OK;
+  hipLaunchKernelGGL((k_element<D, P>), dim3(a.ne), dim3(64), 0, st, a);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+static ah_status element_dispatch(int D, int p, const ElemArgs& a, hipStream_t st) {
+  if (D == 2 && p == 1) return launch_element<2, 1>(a, st);
+  if (D == 2 && p == 2) return launch_element<2, 2>(a, st);
+  if (D == 2 && p == 3) return launch_element<2, 3>(a, st);
+  if (D == 3 && p == 1) return launch_element<3, 1>(a, st);
+  if (D == 3 && p == 2) return launch_element<3, 2>(a, st);
+  if (D == 3 && p == 3) return launch_element<3, 3>(a, st);
+  set_error("unsupported dim_st/p");
+  return AH_EUNSUPPORTED;
+}
+
+template <int B>
+static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, int* d_err) {
+  const int64_t nfree = s->nfree;
+  const int64_t n = nfree * B;
+  Arena& ar = s->arena;
+  int threads = 128;
+  hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), threads)), dim3(threads), 0, st, nfree,
+                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
+  AH_LAUNCHED();
+  int32_t* cnt = nullptr;
+  Arena tmp;
+  tmp.stream = st;
+  AH_TRY(tmp.get(&cnt, n + 1));
+  AH_TRY(ar.get(&s->d_rowptr, n + 1));
+  hipLaunchKernelGGL(k_csr_scaled<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree,
+                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, cnt, (const int64_t*)nullptr,
+                     (int32_t*)nullptr, (double*)nullptr);
+  AH_LAUNCHED();
+  AH_TRY(scan_i32_to_i64(cnt, s->d_rowptr, n, st, tmp));
+  AH_TRY(read_i64(s->d_rowptr + n, &s->nnz, st));
+  if (s->nnz >= ((int64_t)1 << 31)) {
+    tmp.release();
+    set_error("level-0 matrix has %lld entries (limit 2^31)", (long long)s->nnz);
+    return AH_EUNSUPPORTED;
+  }
+  AH_TRY(ar.get(&s->d_col, s->nnz));
+  AH_TRY(ar.get(&s->d_val, s->nnz));
+  hipLaunchKernelGGL(k_csr_scaled<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree,
+                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, cnt, s->d_rowptr, s->d_col, s->d_val);
+  AH_LAUNCHED();
+  hipLaunchKernelGGL(k_hhat<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree, s->d_Dinv,
+                     s->d_H, s->d_Hhat);
+  AH_LAUNCHED();
+  tmp.release();
+  return AH_OK;
+}
+
+static ah_status scale_dispatch(int b, ah_system* s, const ah_mesh* m, hipStream_t st, int* d_err) {
+  switch (b) {
+    case 2: return scale_to_csr<2>(s, m, st, d_err);
+    case 3: return scale_to_csr<3>(s, m, st, d_err);
+    case 4: return scale_to_csr<4>(s, m, st, d_err);
+    case 6: return scale_to_csr<6>(s, m, st, d_err);
+    case 10: return scale_to_csr<10>(s, m, st, d_err);
+  }
+  set_error("unsupported facet block size %d", b);
+  return AH_EUNSUPPORTED;
+}
+
+static void fill_common(ElemArgs& a, const ah_mesh* m, const RefTables& t) {
+  a.ne = m->ne;
+  a.vert = m->d_vert;
+  a.cell = m->d_cell;
+  a.elem_facet = m->d_elem_facet;
+  a.facet_loc = m->d_facet_loc;
+  a.kind = m->d_kind;
+  a.bf_index = m->d_bf_index;
+  a.free_rank = m->d_free_rank;
+  a.elem_slot = m->d_elem_slot;
+  a.vol_w = t.d_vol_w;
+  a.vol_lam = t.d_vol_lam;
+  a.vol_phi = t.d_vol_phi;
+  a.vol_dphi = t.d_vol_dphi;
+  a.fac_w = t.d_fac_w;
+  a.fac_mu = t.d_fac_mu;
+  a.fac_psi = t.d_fac_psi;
+  a.fac_proj = t.d_fac_proj;
+  for (int i = 0; i < 20; ++i)
+    for (int c = 0; c < 3; ++c) a.mono[i][c] = (i < t.nu && c < t.D) ? (int8_t)t.mono[i * t.D + c] : 0;
+}
+
+template <int D, int P>
+static ah_status launch_grad(const ElemArgs& a, hipStream_t st) {
+  if (a.ne == 0) return AH_OK;
+  hipLaunchKernelGGL((k_grad<D, P>), dim3(a.ne), dim3(64), 0, st, a);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+ah_status grad_dispatch(const ah_system* s, const double* a_vert, const double* lam_fwd, const double* lam_adj,
+                        double* dJdf_q, double* dnu_elem, hipStream_t st) {
+  ElemArgs a{};
+  fill_common(a, s->mesh, s->tab);
+  a.a_vert = a_vert;
+  a.nu = 1.0;
+  a.alpha = s->alpha;
+  a.lamD = s->d_lamD;
+  a.Ainv = s->d_Ainv;
+  a.Bm = s->d_Bm;
+  a.Cm = s->d_Cm;
+  a.Fv = s->d_Fv;
+  a.lam_fwd = lam_fwd;
+  a.lam_adj = lam_adj;
+  a.dJdf_q = dJdf_q;
+  a.dnu_elem = dnu_elem;
+  int* err = nullptr;
+  Arena tmp;
+  tmp.stream = st;
+  AH_TRY(tmp.get(&err, 1));
+  a.err = err;
+  ah_status rc;
+  const int D = s->D, p = s->p;
+  if (D == 2 && p == 1) rc = launch_grad<2, 1>(a, st);
+  else if (D == 2 && p == 2) rc = launch_grad<2, 2>(a, st);
+  else if (D == 2 && p == 3) rc = launch_grad<2, 3>(a, st);
+  else if (D == 3 && p == 1) rc = launch_grad<3, 1>(a, st);
+  else if (D == 3 && p == 2) rc = launch_grad<3, 2>(a, st);
+  else if (D == 3 && p == 3) rc = launch_grad<3, 3>(a, st);
+  else { set_error("unsupported dim_st/p"); rc = AH_EUNSUPPORTED; }
+  tmp.release();
+  return rc;
+}
+
+}  // namespace ah
+
+using namespace ah;
+
+extern "C" ah_status ah_quad_points(const ah_mesh* mc, int p, double* xq_elem, double* xq_bfacet, void* stream) {
+  if (!mc) { set_error("null mesh"); return AH_EINVAL; }
+  ah_mesh* m = const_cast<ah_mesh*>(mc);
+  hipStream_t st = as_stream(stream);
+  RefTables t;
+  AH_TRY(build_ref_tables(m->D, p, t));
+  Arena tmp;
+  tmp.stream = st;
+  AH_TRY(upload_ref_tables(t, tmp));
+  double* d_vert = nullptr;
+  int32_t *d_cell = nullptr, *d_bf = nullptr, *d_fv = nullptr;
+  AH_TRY(tmp.get(&d_vert, m->vert.size()));
+  AH_TRY(tmp.get(&d_cell, m->cell.size()));
+  AH_TRY(tmp.get(&d_bf, m->bfacets.size()));
+  AH_TRY(tmp.get(&d_fv, m->facet_vert.size()));
+  AH_HIP(hipMemcpyAsync(d_vert, m->vert.data(), m->vert.size() * 8, hipMemcpyHostToDevice, st));
+  AH_HIP(hipMemcpyAsync(d_cell, m->cell.data(), m->cell.size() * 4, hipMemcpyHostToDevice, st));
+  AH_HIP(hipMemcpyAsync(d_bf, m->bfacets.data(), m->bfacets.size() * 4, hipMemcpyHostToDevice, st));
+  AH_HIP(hipMemcpyAsync(d_fv, m->facet_vert.data(), m->facet_vert.size() * 4, hipMemcpyHostToDevice, st));
+  if (xq_elem && m->ne) {
+    hipLaunchKernelGGL(k_quad_points_elem, dim3(cdiv(m->ne * t.nq, 256)), dim3(256), 0, st, m->ne, m->D, t.nq, d_vert,
+                       d_cell, t.d_vol_lam, xq_elem);
+    AH_LAUNCHED();
+  }
+  if (xq_bfacet && m->nbf) {
+    hipLaunchKernelGGL(k_quad_points_bfacet, dim3(cdiv(m->nbf * t.nqf, 256)), dim3(256), 0, st, m->nbf, m->D, t.nqf,
+                       d_vert, d_bf, d_fv, t.d_fac_mu, xq_bfacet);
+    AH_LAUNCHED();
+  }
+  AH_HIP(hipStreamSynchronize(st));
+  tmp.release();
+  return AH_OK;
+}
+
+extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, double nu, const double* a_vert,
+                                  const double* f_q, const double* g_q, void* stream, ah_system** out) {
+  if (!mc || !prm || !out || !a_vert) { set_error("hdg_assemble: null argument"); return AH_EINVAL; }
+  if (!(nu >= 0.0) || !std::isfinite(nu)) { set_error("hdg_assemble: nu must be finite and >= 0"); return AH_EINVAL; }
+  if (!mc->bc_set) { set_error("hdg_assemble: boundary kinds not set"); return AH_EINVAL; }
+  *out = nullptr;
+  ah_mesh* m = const_cast<ah_mesh*>(mc);
+  hipStream_t st = as_stream(stream);
+  AH_TRY(mesh_upload(m, st));
+  ah_system* s = new ah_system();
+  s->arena.stream = st;
+  s->mesh = m;
+  s->D = m->D;
+  s->p = prm->p;
+  s->visc = nu;
+  s->alpha = prm->alpha > 0.0 ? prm->alpha : 10.0 * prm->p * prm->p;
+  s->keep = prm->keep_element_data != 0;
+  auto fail = [&](ah_status code) { delete s; return code; };
+  ah_status rc = build_ref_tables(m->D, prm->p, s->tab);
+  if (rc) return fail(rc);
+  if ((rc = upload_ref_tables(s->tab, s->arena))) return fail(rc);
+  const RefTables& t = s->tab;
+  s->nu = t.nu; s->b = t.b; s->nl = (m->D + 1) * t.b; s->nq = t.nq; s->nqf = t.nqf;
+  s->nfree = m->nfree;
+  s->n = m->nfree * t.b;
+  s->nnzb = (int64_t)m->bsr_col.size();
+  Arena& ar = s->arena;
+  if ((rc = ar.get(&s->d_bval, s->nnzb * t.b * t.b))) return fail(rc);
+  if ((rc = ar.get(&s->d_H, s->n))) return fail(rc);
+  if ((rc = ar.get(&s->d_Hhat, s->n))) return fail(rc);
+  if ((rc = ar.get(&s->d_Dinv, s->nfree * t.b * t.b))) return fail(rc);
+  if ((rc = ar.get(&s->d_lamD, m->nf * t.b))) return fail(rc);
+  if (s->keep) {
+    if ((rc = ar.get(&s->d_Ainv, m->ne * t.nu * t.nu))) return fail(rc);
+    if ((rc = ar.get(&s->d_Bm, m->ne * t.nu * s->nl))) return fail(rc);
+    if ((rc = ar.get(&s->d_Cm, m->ne * s->nl * t.nu))) return fail(rc);
+    if ((rc = ar.get(&s->d_Fv, m->ne * t.nu))) return fail(rc);
+  }
+  int* d_err = nullptr;
+  if ((rc = ar.get(&d_err, 1))) return fail(rc);
+  if (hipMemsetAsync(d_err, 0, sizeof(int), st) != hipSuccess ||
+      hipMemsetAsync(s->d_bval, 0, s->nnzb * t.b * t.b * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(s->d_H, 0, s->n * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(s->d_lamD, 0, m->nf * t.b * sizeof(double), st) != hipSuccess) {
+    set_error("hdg_assemble: memset failed");
+    return fail(AH_EHIP);
+  }
+  ElemArgs a{};
+  fill_common(a, m, t);
+  a.a_vert = a_vert;
+  a.f_q = f_q;
+  a.g_q = g_q;
+  a.nu = nu;
+  a.alpha = s->alpha;
+  a.bval = s->d_bval;
+  a.H = s->d_H;
+  a.lamD = s->d_lamD;
+  a.Ainv = s->d_Ainv;
+  a.Bm = s->d_Bm;
+  a.Cm = s->d_Cm;
+  a.Fv = s->d_Fv;
+  a.err = d_err;
+  if ((rc = element_dispatch(m->D, prm->p, a, st))) return fail(rc);
+  if ((rc = scale_dispatch(t.b, s, m, st, d_err))) return fail(rc);
+  int herr = 0;
+  if (hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_error("hdg_assemble: %s", hipGetErrorString(hipGetLastError()));
+    return fail(AH_EHIP);
+  }
+  if (herr) {
+    set_error("hdg_assemble: singular %s", (herr & 4) ? "facet diagonal block (characteristic facet at nu = 0?)"
+                                                      : (herr & 2) ? "element (degenerate cell)" : "element block A_K");
+    return fail(AH_ESINGULAR);
+  }
+  *out = s;
+  return AH_OK;
+}
+
+extern "C" void ah_system_destroy(ah_system* s) { delete s; }
+
+extern "C" ah_status ah_system_sizes(const ah_system* s, int64_t* n, int* b, int64_t* nnz) {
+  if (!s) { set_error("null system"); return AH_EINVAL; }
+  if (n) *n = s->n;
+  if (b) *b = s->b;
+  if (nnz) *nnz = s->nnz;
+  return AH_OK;
+}
+
+extern "C" ah_status ah_system_export(const ah_system* s, int64_t* row_ptr, int32_t* col, double* val,
+                                      double* h_hat, double* dinv, double* lam_dir, void* stream) {
+  if (!s) { set_error("null system"); return AH_EINVAL; }
+  hipStream_t st = as_stream(stream);
+  if (row_ptr) AH_HIP(hipMemcpyAsync(row_ptr, s->d_rowptr, (s->n + 1) * 8, hipMemcpyDeviceToDevice, st));
+  if (col) AH_HIP(hipMemcpyAsync(col, s->d_col, s->nnz * 4, hipMemcpyDeviceToDevice, st));
+  if (val) AH_HIP(hipMemcpyAsync(val, s->d_val, s->nnz * 8, hipMemcpyDeviceToDevice, st));
+  if (h_hat) AH_HIP(hipMemcpyAsync(h_hat, s->d_Hhat, s->n * 8, hipMemcpyDeviceToDevice, st));
+  if (dinv) AH_HIP(hipMemcpyAsync(dinv, s->d_Dinv, s->nfree * s->b * s->b * 8, hipMemcpyDeviceToDevice, st));
+  if (lam_dir) AH_HIP(hipMemcpyAsync(lam_dir, s->d_lamD, s->mesh->nf * s->b * 8, hipMemcpyDeviceToDevice, st));
+  return AH_OK;
+}

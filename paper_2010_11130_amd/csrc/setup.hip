@@ -1,0 +1,828 @@
+// air_setup: lAIR algebraic multigrid hierarchy on the scaled facet system
+// treated as a scalar matrix (Section 3; solver settings of Section 4).
+//
+// Per level: strength of connection (row-wise |a_ij| >= theta max_{k!=i}
+// |a_ik| (1-1e-12)), PMIS C/F splitting with integer keys
+// (influence count << 44 | 44-bit bijective hash of the index), one-point
+// interpolation (strongest strong C neighbour, ties to the smallest index),
+// distance-one lAIR restriction rows from local dense solves
+// A[N_i,N_i]^T z = -A[i,N_i]^T (one wave per C point, LU with partial
+// pivoting in LDS), and the Galerkin product A_c = R A P (one wave per
+// coarse row, LDS hash; P is one-point so A P is a column relabelling).
+// The coarsest matrix is inverted densely in FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "system.h"
+
+namespace ah {
+
+__device__ inline uint64_t hash44(uint64_t i, int level) {
+  const uint64_t M = (1ull << 44) - 1;
+  uint64_t x = (i + (((uint64_t)(level + 1) * 0x9E3779B97F4A7C15ull) & M)) & M;
+  x ^= x >> 21;
+  x = (x * (0xBF58476D1CE4E5B9ull & M)) & M;
+  x ^= x >> 19;
+  x = (x * (0x94D049BB133111EBull & M)) & M;
+  x ^= x >> 22;
+  return x;
+}
+
+__global__ void k_strength(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, double theta, uint8_t* __restrict__ strong,
+                           int32_t* __restrict__ infl) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m = 0.0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] != i) m = fmax(m, fabs(v[k]));
+  double thr = theta * m * (1.0 - 1e-12);
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    bool s = ci[k] != i && m > 0.0 && fabs(v[k]) >= thr;
+    strong[k] = s;
+    if (s) atomicAdd(&infl[ci[k]], 1);
+  }
+}
+
+// state: 0 undecided, 1 C, 2 F
+__global__ void k_pmis_init(int64_t n, const int32_t* __restrict__ infl, int level, uint64_t* __restrict__ key,
+                            int8_t* __restrict__ state) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = ((uint64_t)infl[i] << 44) | hash44((uint64_t)i, level);
+  state[i] = infl[i] == 0 ? 2 : 0;
+}
+
+__global__ void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const uint8_t* __restrict__ strong, const uint64_t* __restrict__ key,
+                             const int8_t* __restrict__ state, unsigned long long* __restrict__ nbmax) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != 0) return;
+  unsigned long long mx = 0, ki = key[i];
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    if (!strong[k]) continue;
+    int32_t j = ci[k];
+    if (state[j] != 0) continue;
+    mx = mx > key[j] ? mx : key[j];
+    atomicMax(&nbmax[j], ki);      // i depends on j: i is a neighbour of j as well
+  }
+  if (mx) atomicMax(&nbmax[i], mx);
+}
+
+__global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, const unsigned long long* __restrict__ nbmax,
+                              int8_t* __restrict__ state) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != 0) return;
+  if (key[i] > nbmax[i]) state[i] = 1;
+}
+
+__global__ void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
+                             unsigned long long* __restrict__ left) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != 0) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (strong[k] && state[ci[k]] == 1) { state[i] = 2; return; }
+  atomicAdd(left, 1ull);
+}
+
+__global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* __restrict__ cf,
+                           int32_t* __restrict__ isc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int8_t c = state[i] == 1;
+  cf[i] = c;
+  isc[i] = c;
+}
+
+// One-point interpolation and, for C points, the lAIR row length 1 + |N_i|.
+__global__ void k_onepoint(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, const uint8_t* __restrict__ strong,
+                           const int8_t* __restrict__ cf, const int64_t* __restrict__ cidx,
+                           int32_t* __restrict__ pcol, int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
+                           int* __restrict__ maxm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cf[i]) {
+    pcol[i] = (int32_t)cidx[i];
+    int m = 0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (strong[k] && !cf[ci[k]]) ++m;
+    rcnt[cidx[i]] = 1 + m;
+    clist[cidx[i]] = (int32_t)i;
+    atomicMax(maxm, m);
+    return;
+  }
+  double mx = 0.0;
+  bool any = false;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (strong[k] && cf[ci[k]]) { mx = fmax(mx, fabs(v[k])); any = true; }
+  int32_t pc = -1;
+  if (any) {
+    double thr = mx * (1.0 - 1e-12);
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (strong[k] && cf[ci[k]] && fabs(v[k]) >= thr) { pc = (int32_t)cidx[ci[k]]; break; }
+  }
+  pcol[i] = pc;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// lAIR row of one C point per wave: N_i = strong F neighbours (sorted),
+// T = A[N_i,N_i]^T, solve T z = -A[i,N_i]^T by LU with partial pivoting;
+// injection (z = 0, counted) if N_i is empty or a pivot is <= 1e-14 max|T|.
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                             const double* __restrict__ v, const uint8_t* __restrict__ strong,
+                                             const int8_t* __restrict__ cf, const int32_t* __restrict__ clist,
+                                             const int64_t* __restrict__ Rptr, int32_t* __restrict__ Rcol,
+                                             double* __restrict__ Rval, unsigned long long* __restrict__ nfall) {
+  __shared__ int32_t N[MAXM];
+  __shared__ double T[MAXM * MAXM];
+  __shared__ double z[MAXM];
+  __shared__ int s_m;
+  const int64_t ic = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t i = clist[ic];
+  if (lane == 0) s_m = 0;
+  __syncthreads();
+  // gather N_i and the right-hand side in row order (columns are sorted)
+  int base = 0;
+  for (int64_t k0 = rp[i]; k0 < rp[i + 1]; k0 += 64) {
+    int64_t k = k0 + lane;
+    bool f = k < rp[i + 1] && strong[k] && !cf[ci[k]];
+    unsigned long long mask = __ballot(f);
+    int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+    if (f && pos < MAXM) { N[pos] = ci[k]; z[pos] = -v[k]; }
+    base += __popcll(mask);
+  }
+  const int m = base;
+  const int64_t out = Rptr[ic];
+  if (m == 0 || m > MAXM) {
+    // m > MAXM cannot occur: the host picks MAXM >= max |N_i|
+    if (lane == 0) {
+      Rcol[out] = (int32_t)i;
+      Rval[out] = 1.0;
+      atomicAdd(nfall, 1ull);
+    }
+    return;
+  }
+  for (int k = lane; k < m * m; k += 64) T[k] = 0.0;
+  __syncthreads();
+  // T[c][r] = A[N_r, N_c]
+  for (int r = 0; r < m; ++r) {
+    int64_t j = N[r];
+    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
+      int32_t col = ci[k];
+      int lo = 0, hi = m - 1, c = -1;
+      while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (N[mid] == col) { c = mid; break; }
+        if (N[mid] < col) lo = mid + 1; else hi = mid - 1;
+      }
+      if (c >= 0) T[c * m + r] = v[k];
+    }
+  }
+  __syncthreads();
+  double sc = 0.0;
+  for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
+  sc = wave_max(sc);
+  bool bad = false;
+  for (int k = 0; k < m; ++k) {
+    // pivot: largest |T[r][k]|, r >= k, smallest row on ties
+    double best = -1.0;
+    int bi = m;
+    for (int r = k + lane; r < m; r += 64) {
+      double a = fabs(T[r * m + k]);
+      if (a > best) { best = a; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int p = bi;
+    if (fabs(T[p * m + k]) <= 1e-14 * sc) bad = true;
+    if (p != k) {
+      for (int c = lane; c < m; c += 64) {
+        double t = T[k * m + c]; T[k * m + c] = T[p * m + c]; T[p * m + c] = t;
+      }
+      if (lane == 0) { double t = z[k]; z[k] = z[p]; z[p] = t; }
+    }
+    __syncthreads();
+    const double pv = bad ? 1.0 : T[k * m + k];
+    const double zk = z[k];
+    for (int r = k + 1 + lane; r < m; r += 64) {
+      double f = T[r * m + k] / pv;
+      for (int c = k + 1; c < m; ++c) T[r * m + c] -= f * T[k * m + c];
+      z[r] -= f * zk;
+    }
+    __syncthreads();
+  }
+  for (int c = m - 1; c >= 0; --c) {
+    double s = 0.0;
+    for (int j = c + 1 + lane; j < m; j += 64) s += T[c * m + j] * z[j];
+    s = wave_sum(s);
+    if (lane == 0) z[c] = (z[c] - s) / (bad ? 1.0 : T[c * m + c]);
+    __syncthreads();
+  }
+  // row in increasing column order: N is sorted, the C point itself is not in N
+  int ins = 0;
+  for (int r = lane; r < m; r += 64) ins += N[r] < i;
+  for (int o = 32; o > 0; o >>= 1) ins += __shfl_xor(ins, o, 64);
+  for (int r = lane; r < m; r += 64) {
+    int pos = r < ins ? r : r + 1;
+    Rcol[out + pos] = N[r];
+    Rval[out + pos] = bad ? 0.0 : z[r];
+  }
+  if (lane == 0) {
+    Rcol[out + ins] = (int32_t)i;
+    Rval[out + ins] = 1.0;
+    if (bad) atomicAdd(nfall, 1ull);
+  }
+}
+
+// Upper bound of the entries of each coarse row of R A P.
+__global__ void k_rap_cand(int64_t nc, const int64_t* __restrict__ Rptr, const int32_t* __restrict__ Rcol,
+                           const int64_t* __restrict__ rp, int32_t* __restrict__ cand, int* __restrict__ maxcand) {
+  int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ic >= nc) return;
+  int64_t c = 0;
+  for (int64_t k = Rptr[ic]; k < Rptr[ic + 1]; ++k) {
+    int32_t j = Rcol[k];
+    c += rp[j + 1] - rp[j];
+  }
+  int cc = c > 0x3fffffff ? 0x3fffffff : (int)c;
+  cand[ic] = cc;
+  atomicMax(maxcand, cc);
+}
+
+// R A P per coarse row with an LDS open-addressing hash on the coarse
+// column (HS >= candidates, so it never overflows).  NUMERIC = false counts
+// the distinct columns; NUMERIC = true accumulates, sorts and writes.
+template <int HS, bool NUMERIC>
+__global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restrict__ Rptr, const int32_t* __restrict__ Rcol,
+                                            const double* __restrict__ Rval, const int64_t* __restrict__ rp,
+                                            const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                            const int32_t* __restrict__ pcol, int32_t* __restrict__ cnt,
+                                            const int64_t* __restrict__ cptr, int32_t* __restrict__ ccol,
+                                            double* __restrict__ cval) {
+  __shared__ int32_t key[HS];
+  __shared__ double val[NUMERIC ? HS : 1];
+  __shared__ int s_cnt;
+  const int64_t ic = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int k = lane; k < HS; k += 64) {
+    key[k] = -1;
+    if (NUMERIC) val[k] = 0.0;
+  }
+  if (lane == 0) s_cnt = 0;
+  __syncthreads();
+  for (int64_t kr = Rptr[ic]; kr < Rptr[ic + 1]; ++kr) {
+    const int32_t j = Rcol[kr];
+    const double rv = NUMERIC ? Rval[kr] : 0.0;
+    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
+      int32_t c = pcol[ci[k]];
+      if (c < 0) continue;
+      uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
+      while (true) {
+        int32_t prev = atomicCAS(&key[h], -1, c);
+        if (prev == -1 || prev == c) {
+          if (prev == -1) atomicAdd(&s_cnt, 1);
+          if (NUMERIC) atomicAdd(&val[h], rv * v[k]);
+          break;
+        }
+        h = (h + 1) & (HS - 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (!NUMERIC) {
+    if (lane == 0) cnt[ic] = s_cnt;
+    return;
+  }
+  // compact to the front in place: one wave reads a chunk before writing it,
+  // and every write position is <= the positions still to be read
+  const int tot = s_cnt;
+  int32_t* ck = key;
+  double* cv = val;
+  int base = 0;
+  for (int k0 = 0; k0 < HS; k0 += 64) {
+    int k = k0 + lane;
+    int32_t kk = key[k];
+    double vv = val[k];
+    bool occ = kk >= 0;
+    unsigned long long mask = __ballot(occ);
+    int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (occ) { ck[pos] = kk; cv[pos] = vv; }
+    base += __popcll(mask);
+    __syncthreads();
+  }
+  int S = 1;
+  while (S < tot) S <<= 1;
+  for (int k = tot + lane; k < S; k += 64) ck[k] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort by column
+  for (int kk = 2; kk <= S; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int x = lane; x < S; x += 64) {
+        int y = x ^ jj;
+        if (y > x) {
+          bool up = (x & kk) == 0;
+          int32_t a = ck[x], b = ck[y];
+          if ((a > b) == up) {
+            ck[x] = b; ck[y] = a;
+            double t = cv[x]; cv[x] = cv[y]; cv[y] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int64_t o = cptr[ic];
+  for (int k = lane; k < tot; k += 64) {
+    ccol[o + k] = ck[k];
+    cval[o + k] = cv[k];
+  }
+}
+
+__global__ void k_diag(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const double* __restrict__ v, double* __restrict__ d, float* __restrict__ d32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = 0.0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == i) { x = v[k]; break; }
+  d[i] = x;
+  if (d32) d32[i] = (float)x;
+}
+
+__global__ void k_cast32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// Dense copy of the coarsest matrix and its inverse by Gauss-Jordan with
+// partial pivoting in one workgroup.
+__global__ void k_dense(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                        const double* __restrict__ v, double* __restrict__ M) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) M[i * n + ci[k]] = v[k];
+}
+
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M, double* __restrict__ Inv,
+                                                       int* __restrict__ err) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ int s_p;
+  const int t = threadIdx.x;
+  for (int k = t; k < n * n; k += blockDim.x) Inv[k] = (k / n == k % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < n; ++c) {
+    double best = -1.0;
+    int bi = n;
+    for (int r = c + t; r < n; r += blockDim.x) {
+      double a = fabs(M[(int64_t)r * n + c]);
+      if (a > best) { best = a; bi = r; }
+    }
+    sv[t] = best;
+    si[t] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (t < s && (sv[t + s] > sv[t] || (sv[t + s] == sv[t] && si[t + s] < si[t]))) {
+        sv[t] = sv[t + s];
+        si[t] = si[t + s];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      s_p = si[0];
+      if (!(sv[0] > 0.0)) atomicOr(err, 1);
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != c)
+      for (int j = t; j < n; j += blockDim.x) {
+        double x = M[(int64_t)c * n + j]; M[(int64_t)c * n + j] = M[(int64_t)p * n + j]; M[(int64_t)p * n + j] = x;
+        x = Inv[(int64_t)c * n + j]; Inv[(int64_t)c * n + j] = Inv[(int64_t)p * n + j]; Inv[(int64_t)p * n + j] = x;
+      }
+    __syncthreads();
+    double d = M[(int64_t)c * n + c];
+    if (d == 0.0) d = 1.0;
+    __syncthreads();
+    for (int j = t; j < n; j += blockDim.x) {
+      M[(int64_t)c * n + j] /= d;
+      Inv[(int64_t)c * n + j] /= d;
+    }
+    __syncthreads();
+    for (int64_t idx = t; idx < (int64_t)n * n; idx += blockDim.x) {
+      int r = (int)(idx / n), j = (int)(idx % n);
+      if (r == c) continue;
+      double f = M[(int64_t)r * n + c];
+      if (j == c) continue;
+      M[(int64_t)r * n + j] -= f * M[(int64_t)c * n + j];
+      Inv[(int64_t)r * n + j] -= f * Inv[(int64_t)c * n + j];
+    }
+    __syncthreads();
+    for (int r = t; r < n; r += blockDim.x) {
+      if (r == c) continue;
+      double f = M[(int64_t)r * n + c];
+      Inv[(int64_t)r * n + c] -= f * Inv[(int64_t)c * n + c];
+      M[(int64_t)r * n + c] = 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// CSR transpose: counts, offsets, scatter with an atomic cursor, then each
+// row sorted by column so the result does not depend on scheduling.
+__global__ void k_tcount(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         int32_t* __restrict__ cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) atomicAdd(&cnt[ci[k]], 1);
+}
+
+__global__ void k_tscatter(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, const int64_t* __restrict__ tp, int32_t* __restrict__ cur,
+                           int32_t* __restrict__ tc, double* __restrict__ tv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    int32_t j = ci[k];
+    int64_t pos = tp[j] + atomicAdd(&cur[j], 1);
+    tc[pos] = (int32_t)i;
+    if (tv) tv[pos] = v ? v[k] : 1.0;
+  }
+}
+
+__global__ void k_rowsort(int64_t n, const int64_t* __restrict__ tp, int32_t* __restrict__ tc, double* __restrict__ tv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t a = tp[i] + 1; a < tp[i + 1]; ++a) {
+    int32_t kc = tc[a];
+    double kv = tv ? tv[a] : 0.0;
+    int64_t b = a - 1;
+    while (b >= tp[i] && tc[b] > kc) {
+      tc[b + 1] = tc[b];
+      if (tv) tv[b + 1] = tv[b];
+      --b;
+    }
+    tc[b + 1] = kc;
+    if (tv) tv[b + 1] = kv;
+  }
+}
+
+// P as CSR: one entry (pcol[i], 1) per fine point with pcol >= 0.
+__global__ void k_p_rowcnt(int64_t n, const int32_t* __restrict__ pcol, int32_t* __restrict__ cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = pcol[i] >= 0;
+}
+
+__global__ void k_p_fill(int64_t n, const int32_t* __restrict__ pcol, const int64_t* __restrict__ pp,
+                         int32_t* __restrict__ pc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && pcol[i] >= 0) pc[pp[i]] = pcol[i];
+}
+
+static inline dim3 g1(int64_t n, int t = 256) { return dim3((unsigned)cdiv(std::max<int64_t>(n, 1), t)); }
+
+static ah_status transpose(int64_t nrow, int64_t ncol, const int64_t* rp, const int32_t* ci, const double* v,
+                           int64_t nnz, Arena& ar, Arena& tmp, hipStream_t st, int64_t** tp, int32_t** tc,
+                           double** tv) {
+  int32_t* cnt = nullptr;
+  AH_TRY(tmp.get(&cnt, ncol + 1));
+  AH_HIP(hipMemsetAsync(cnt, 0, (ncol + 1) * sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_tcount, g1(nrow), dim3(256), 0, st, nrow, rp, ci, cnt);
+  AH_LAUNCHED();
+  AH_TRY(ar.get(tp, ncol + 1));
+  AH_TRY(scan_i32_to_i64(cnt, *tp, ncol, st, tmp));
+  AH_TRY(ar.get(tc, nnz));
+  if (tv) AH_TRY(ar.get(tv, nnz));
+  AH_HIP(hipMemsetAsync(cnt, 0, (ncol + 1) * sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_tscatter, g1(nrow), dim3(256), 0, st, nrow, rp, ci, v, *tp, cnt, *tc, tv ? *tv : nullptr);
+  AH_LAUNCHED();
+  hipLaunchKernelGGL(k_rowsort, g1(ncol), dim3(256), 0, st, ncol, *tp, *tc, tv ? *tv : nullptr);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+template <int HS>
+static ah_status rap_launch(int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
+                            double* cval, bool numeric, hipStream_t st) {
+  if (nc == 0) return AH_OK;
+  if (numeric)
+    hipLaunchKernelGGL((k_rap<HS, true>), dim3(nc), dim3(64), 0, st, nc, L.Rptr, L.Rcol, L.Rval, L.rowptr, L.col,
+                       L.val, L.pcol, cnt, cptr, ccol, cval);
+  else
+    hipLaunchKernelGGL((k_rap<HS, false>), dim3(nc), dim3(64), 0, st, nc, L.Rptr, L.Rcol, L.Rval, L.rowptr, L.col,
+                       L.val, L.pcol, cnt, cptr, ccol, cval);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
+                              double* cval, bool numeric, hipStream_t st) {
+  switch (hs) {
+    case 256: return rap_launch<256>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+    case 1024: return rap_launch<1024>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+    case 2048: return rap_launch<2048>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+    case 4096: return rap_launch<4096>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+  }
+  set_error("R A P: row candidate count beyond the LDS hash capacity");
+  return AH_EUNSUPPORTED;
+}
+
+}  // namespace ah
+
+using namespace ah;
+
+ah_hier::~ah_hier() {
+  arena.release();
+  if (hhost) (void)hipHostFree(hhost);
+}
+
+extern "C" void ah_air_defaults(ah_air_params* p) {
+  if (!p) return;
+  p->theta = 0.25;
+  p->max_coarse = 500;
+  p->max_levels = 25;
+  p->relax = 0;
+  p->omega = 1.0;
+  p->stall = 0.9;
+  p->fp32_cycle = 0;
+  p->adjoint = 0;
+}
+
+extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, void* stream, ah_hier** out,
+                               ah_setup_info* info) {
+  if (!s || !out) { set_error("air_setup: null argument"); return AH_EINVAL; }
+  *out = nullptr;
+  ah_air_params prm;
+  if (prm_in) prm = *prm_in; else ah_air_defaults(&prm);
+  if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1) {
+    set_error("air_setup: invalid parameters");
+    return AH_EINVAL;
+  }
+  hipStream_t st = as_stream(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  ah_hier* h = new ah_hier();
+  h->sys = s;
+  h->prm = prm;
+  h->arena.stream = st;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  ah_status rc = AH_OK;
+#define CK(x) do { rc = (x); if (rc < 0) { tmp.release(); delete h; return rc; } } while (0)
+#define CKH(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error("air_setup: %s", hipGetErrorString(e_)); tmp.release(); delete h; return AH_EHIP; } } while (0)
+  unsigned long long* d_ull = nullptr;   // [0] undecided count, [1] lAIR fallbacks
+  int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error
+  CK(ar.get(&d_ull, 4));
+  CK(ar.get(&d_int, 4));
+  CKH(hipMemsetAsync(d_ull, 0, 4 * sizeof(unsigned long long), st));
+  // level 0 = the scaled system (shared, not copied)
+  AhLevel L0;
+  L0.n = s->n;
+  L0.nnz = s->nnz;
+  L0.rowptr = s->d_rowptr;
+  L0.col = s->d_col;
+  L0.val = s->d_val;
+  h->lev.push_back(L0);
+  for (int l = 0;; ++l) {
+    AhLevel& L = h->lev[l];
+    const int64_t n = L.n;
+    CK(ar.get(&L.diag, n));
+    if (prm.fp32_cycle) {
+      CK(ar.get(&L.diag32, n));
+      CK(ar.get(&L.val32, L.nnz));
+      hipLaunchKernelGGL(k_cast32, g1(L.nnz), dim3(256), 0, st, L.nnz, L.val, L.val32);
+      CKH(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_diag, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, L.diag, L.diag32);
+    CKH(hipGetLastError());
+    CK(ar.get(&L.b, n)); CK(ar.get(&L.x, n)); CK(ar.get(&L.y, n));
+    if (prm.fp32_cycle) { CK(ar.get(&L.b32, n)); CK(ar.get(&L.x32, n)); CK(ar.get(&L.y32, n)); }
+    if (n <= prm.max_coarse || l == prm.max_levels - 1) break;
+    // strength
+    uint8_t* strong = nullptr;
+    int32_t* infl = nullptr;
+    CK(tmp.get(&strong, L.nnz));
+    CK(tmp.get(&infl, n));
+    CKH(hipMemsetAsync(infl, 0, n * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_strength, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, prm.theta, strong, infl);
+    CKH(hipGetLastError());
+    // PMIS
+    uint64_t* key = nullptr;
+    unsigned long long* nbmax = nullptr;
+    int8_t* state = nullptr;
+    CK(tmp.get(&key, n));
+    CK(tmp.get(&nbmax, n));
+    CK(tmp.get(&state, n));
+    hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, l, key, state);
+    CKH(hipGetLastError());
+    for (int round = 0;; ++round) {
+      if (round > 10000) { set_error("air_setup: PMIS did not terminate"); tmp.release(); delete h; return AH_EINVAL; }
+      CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
+      CKH(hipMemsetAsync(d_ull, 0, sizeof(unsigned long long), st));
+      hipLaunchKernelGGL(k_pmis_nbmax, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
+      hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state);
+      hipLaunchKernelGGL(k_pmis_fmark, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, d_ull);
+      CKH(hipGetLastError());
+      unsigned long long left = 0;
+      CKH(hipMemcpyAsync(&left, d_ull, sizeof(left), hipMemcpyDeviceToHost, st));
+      CKH(hipStreamSynchronize(st));
+      if (left == 0) break;
+    }
+    // coarse numbering
+    int32_t* isc = nullptr;
+    int64_t* cidx = nullptr;
+    CK(ar.get(&L.cf, n));
+    CK(tmp.get(&isc, n));
+    CK(tmp.get(&cidx, n + 1));
+    hipLaunchKernelGGL(k_cf_flags, g1(n), dim3(256), 0, st, n, state, L.cf, isc);
+    CKH(hipGetLastError());
+    CK(scan_i32_to_i64(isc, cidx, n, st, tmp));
+    int64_t nc = 0;
+    CK(read_i64(cidx + n, &nc, st));
+    if (nc == 0 || (double)nc > prm.stall * (double)n) break;
+    L.nc = nc;
+    // one-point P and lAIR row lengths
+    int32_t *rcnt = nullptr, *clist = nullptr;
+    CK(ar.get(&L.pcol, n));
+    CK(tmp.get(&rcnt, nc + 1));
+    CK(tmp.get(&clist, nc));
+    CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
+    hipLaunchKernelGGL(k_onepoint, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
+                       rcnt, clist, d_int);
+    CKH(hipGetLastError());
+    CK(ar.get(&L.Rptr, nc + 1));
+    CK(scan_i32_to_i64(rcnt, L.Rptr, nc, st, tmp));
+    CK(read_i64(L.Rptr + nc, &L.nnzR, st));
+    int hmax[4];
+    CKH(hipMemcpyAsync(hmax, d_int, sizeof(hmax), hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    CK(ar.get(&L.Rcol, L.nnzR));
+    CK(ar.get(&L.Rval, L.nnzR));
+    const int maxm = hmax[0];
+    if (maxm <= 32)
+      hipLaunchKernelGGL(k_lair<32>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 1);
+    else if (maxm <= 64)
+      hipLaunchKernelGGL(k_lair<64>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 1);
+    else {
+      set_error("air_setup: lAIR neighbourhood of %d points exceeds 64", maxm);
+      tmp.release(); delete h; return AH_EUNSUPPORTED;
+    }
+    CKH(hipGetLastError());
+    // R A P
+    int32_t* cand = nullptr;
+    CK(tmp.get(&cand, nc));
+    CKH(hipMemsetAsync(d_int + 1, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_rap_cand, g1(nc), dim3(256), 0, st, nc, L.Rptr, L.Rcol, L.rowptr, cand, d_int + 1);
+    CKH(hipGetLastError());
+    int maxcand = 0;
+    CKH(hipMemcpyAsync(&maxcand, d_int + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    int hs = maxcand < 256 ? 256 : maxcand < 1024 ? 1024 : maxcand < 2048 ? 2048 : maxcand < 4096 ? 4096 : -1;
+    AhLevel C;
+    C.n = nc;
+    int32_t* ccnt = nullptr;
+    CK(tmp.get(&ccnt, nc + 1));
+    CK(rap_dispatch(hs, nc, L, ccnt, nullptr, nullptr, nullptr, false, st));
+    CK(ar.get(&C.rowptr, nc + 1));
+    CK(scan_i32_to_i64(ccnt, C.rowptr, nc, st, tmp));
+    CK(read_i64(C.rowptr + nc, &C.nnz, st));
+    CK(ar.get(&C.col, C.nnz));
+    CK(ar.get(&C.val, C.nnz));
+    CK(rap_dispatch(hs, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
+    if (prm.fp32_cycle) {
+      CK(ar.get(&L.Rval32, L.nnzR));
+      hipLaunchKernelGGL(k_cast32, g1(L.nnzR), dim3(256), 0, st, L.nnzR, L.Rval, L.Rval32);
+      CKH(hipGetLastError());
+    }
+    if (prm.adjoint) {
+      CK(transpose(n, n, L.rowptr, L.col, L.val, L.nnz, ar, tmp, st, &L.ATptr, &L.ATcol, &L.ATval));
+      CK(transpose(nc, n, L.Rptr, L.Rcol, L.Rval, L.nnzR, ar, tmp, st, &L.RTptr, &L.RTcol, &L.RTval));
+      int32_t* pc = nullptr;
+      int64_t* pp = nullptr;
+      int32_t* pcc = nullptr;
+      CK(tmp.get(&pc, n + 1));
+      CK(tmp.get(&pp, n + 1));
+      hipLaunchKernelGGL(k_p_rowcnt, g1(n), dim3(256), 0, st, n, L.pcol, pc);
+      CKH(hipGetLastError());
+      CK(scan_i32_to_i64(pc, pp, n, st, tmp));
+      int64_t nnzp = 0;
+      CK(read_i64(pp + n, &nnzp, st));
+      CK(tmp.get(&pcc, nnzp));
+      hipLaunchKernelGGL(k_p_fill, g1(n), dim3(256), 0, st, n, L.pcol, pp, pcc);
+      CKH(hipGetLastError());
+      CK(transpose(n, nc, pp, pcc, nullptr, nnzp, ar, tmp, st, &L.PTptr, &L.PTcol, nullptr));
+      if (prm.fp32_cycle) {
+        CK(ar.get(&L.ATval32, L.nnz));
+        CK(ar.get(&L.RTval32, L.nnzR));
+        hipLaunchKernelGGL(k_cast32, g1(L.nnz), dim3(256), 0, st, L.nnz, L.ATval, L.ATval32);
+        hipLaunchKernelGGL(k_cast32, g1(L.nnzR), dim3(256), 0, st, L.nnzR, L.RTval, L.RTval32);
+        CKH(hipGetLastError());
+      }
+    }
+    CKH(hipStreamSynchronize(st));
+    tmp.release();
+    h->lev.push_back(C);
+  }
+  // coarsest: dense inverse
+  AhLevel& LL = h->lev.back();
+  const int64_t nL = LL.n;
+  if (nL > 8192) {
+    set_error("air_setup: coarsest level has %lld points (dense limit 8192)", (long long)nL);
+    tmp.release(); delete h; return AH_EUNSUPPORTED;
+  }
+  if (nL > 0) {
+    double* M = nullptr;
+    CK(tmp.get(&M, nL * nL));
+    CK(ar.get(&h->cinv, nL * nL));
+    CKH(hipMemsetAsync(M, 0, nL * nL * sizeof(double), st));
+    hipLaunchKernelGGL(k_dense, g1(nL), dim3(256), 0, st, nL, LL.rowptr, LL.col, LL.val, M);
+    CKH(hipMemsetAsync(d_int + 2, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
+    CKH(hipGetLastError());
+  }
+  if (prm.adjoint && !h->lev[0].ATptr) {
+    // level 0 is the coarsest: the adjoint FGMRES still needs S_hat^T
+    AhLevel& A0 = h->lev[0];
+    CK(transpose(A0.n, A0.n, A0.rowptr, A0.col, A0.val, A0.nnz, ar, tmp, st, &A0.ATptr, &A0.ATcol, &A0.ATval));
+  }
+  unsigned long long fb = 0;
+  int gerr = 0;
+  CKH(hipMemcpyAsync(&fb, d_ull + 1, sizeof(fb), hipMemcpyDeviceToHost, st));
+  CKH(hipMemcpyAsync(&gerr, d_int + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+  CKH(hipStreamSynchronize(st));
+  tmp.release();
+  if (gerr) {
+    set_error("air_setup: singular coarsest matrix");
+    delete h;
+    return AH_ESINGULAR;
+  }
+  h->nfallback = (int64_t)fb;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->levels = (int)h->lev.size();
+    double tot = 0;
+    for (size_t l = 0; l < h->lev.size() && l < 32; ++l) {
+      info->n[l] = h->lev[l].n;
+      info->nnz[l] = h->lev[l].nnz;
+      tot += (double)h->lev[l].nnz;
+    }
+    info->n_fallback = h->nfallback;
+    info->op_complexity = h->lev[0].nnz ? tot / (double)h->lev[0].nnz : 0.0;
+    info->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  *out = h;
+  return AH_OK;
+#undef CK
+#undef CKH
+}
+
+extern "C" void ah_hier_destroy(ah_hier* h) { delete h; }
+
+extern "C" ah_status ah_hier_level_sizes(const ah_hier* h, int l, int64_t* n, int64_t* nnz, int64_t* nnz_r) {
+  if (!h || l < 0 || l >= (int)h->lev.size()) { set_error("bad level"); return AH_EINVAL; }
+  const AhLevel& L = h->lev[l];
+  if (n) *n = L.n;
+  if (nnz) *nnz = L.nnz;
+  if (nnz_r) *nnz_r = L.nnzR;
+  return AH_OK;
+}
+
+extern "C" ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_t* col, double* val,
+                                          int8_t* cf, int32_t* pcol, int64_t* r_row_ptr, int32_t* r_col,
+                                          double* r_val, void* stream) {
+  if (!h || l < 0 || l >= (int)h->lev.size()) { set_error("bad level"); return AH_EINVAL; }
+  const AhLevel& L = h->lev[l];
+  hipStream_t st = as_stream(stream);
+  if (row_ptr) AH_HIP(hipMemcpyAsync(row_ptr, L.rowptr, (L.n + 1) * 8, hipMemcpyDeviceToDevice, st));
+  if (col) AH_HIP(hipMemcpyAsync(col, L.col, L.nnz * 4, hipMemcpyDeviceToDevice, st));
+  if (val) AH_HIP(hipMemcpyAsync(val, L.val, L.nnz * 8, hipMemcpyDeviceToDevice, st));
+  bool coarse = l + 1 < (int)h->lev.size();
+  if (coarse) {
+    if (cf) AH_HIP(hipMemcpyAsync(cf, L.cf, L.n, hipMemcpyDeviceToDevice, st));
+    if (pcol) AH_HIP(hipMemcpyAsync(pcol, L.pcol, L.n * 4, hipMemcpyDeviceToDevice, st));
+    if (r_row_ptr) AH_HIP(hipMemcpyAsync(r_row_ptr, L.Rptr, (L.nc + 1) * 8, hipMemcpyDeviceToDevice, st));
+    if (r_col) AH_HIP(hipMemcpyAsync(r_col, L.Rcol, L.nnzR * 4, hipMemcpyDeviceToDevice, st));
+    if (r_val) AH_HIP(hipMemcpyAsync(r_val, L.Rval, L.nnzR * 8, hipMemcpyDeviceToDevice, st));
+  }
+  return AH_OK;
+}

@@ -1,0 +1,576 @@
+// air_solve / air_solve_adjoint: FGMRES(m) with right preconditioning by one
+// lAIR V-cycle (Section 3 coarse-grid correction; Section 4: no
+// pre-relaxation, post-relaxation on F points then all points, here F,F,C
+// Jacobi sweeps) on the scaled facet system, and the transposed cycle for
+// the adjoint.  Also reconstruction and slab coupling.
+//
+// Sparse kernels: G lanes per CSR row (G chosen from the mean row length),
+// partial sums combined with cross-lane shuffles; rows are contiguous, so a
+// group reads its row's values and column indices with unit stride.  A
+// relaxation sweep on the point set X (F or C) writes a second buffer
+// (Jacobi: every update reads the previous iterate) and copies the other
+// rows.  The FGMRES orthogonalisation is classical Gram-Schmidt applied
+// twice, with multi-vector dot products reduced in a fixed order.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "system.h"
+
+namespace ah {
+
+enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3 };
+
+// MODE SP_MV:    y = A x
+// MODE SP_RES:   y = b - A x
+// MODE SP_SWEEP: y_i = x_i + omega (b_i - (A x)_i) / d_i  for cf_i == X (all rows if cf null), else x_i
+// MODE SP_ADDMV: y = b + A x
+// A values may be null (all ones).
+template <class TA, class TX, class TY, int G, int MODE>
+__global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                             const TA* __restrict__ av, const TX* __restrict__ x,
+                                             const TY* __restrict__ b, const TY* __restrict__ d,
+                                             const int8_t* __restrict__ cf, int X, TY omega, TY* __restrict__ y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / G;
+  const int g = (int)(gid % G);
+  if (i >= n) return;
+  const bool active = MODE != SP_SWEEP || !cf || cf[i] == X;
+  TY acc = 0;
+  if (active) {
+    const int64_t k1 = rp[i + 1];
+    for (int64_t k = rp[i] + g; k < k1; k += G) {
+      TY a = av ? (TY)av[k] : (TY)1;
+      acc += a * (TY)x[ci[k]];
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (g != 0) return;
+  if (MODE == SP_MV) y[i] = acc;
+  else if (MODE == SP_RES) y[i] = b[i] - acc;
+  else if (MODE == SP_ADDMV) y[i] = b[i] + acc;
+  else {
+    TY xi = (TY)x[i];
+    if (active) {
+      TY di = d[i];
+      if (fabs((double)di) >= 1e-30) xi += omega * (b[i] - acc) / di;
+    }
+    y[i] = xi;
+  }
+}
+
+template <class T>
+__global__ void k_interp(int64_t n, const int32_t* __restrict__ pcol, const T* __restrict__ ec, T* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c = pcol[i];
+  x[i] = c >= 0 ? ec[c] : (T)0;
+}
+
+// z = C^-1 r (trans = 0) or C^-T r, FP64 coarsest solve; one wave per row.
+template <class T>
+__global__ __launch_bounds__(64) void k_coarse(int n, const double* __restrict__ Ci, const T* __restrict__ r,
+                                               T* __restrict__ z, int trans) {
+  const int row = blockIdx.x;
+  const int lane = threadIdx.x;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    double c = trans ? Ci[(int64_t)j * n + row] : Ci[(int64_t)row * n + j];
+    acc += c * (double)r[j];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) z[row] = (T)acc;
+}
+
+template <class TA, class TB>
+__global__ void k_cast(int64_t n, const TA* __restrict__ a, TB* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (TB)a[i];
+}
+
+// partial[v][blk] = sum over the block's rows of V_v . w (v < k), and
+// partial[k][blk] = w . w.  Vectors are rows of V with stride ldv.
+constexpr int DOT_T = 256;
+constexpr int DOT_V = 4;
+
+__global__ __launch_bounds__(DOT_T) void k_multidot(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                                                    const double* __restrict__ w, double* __restrict__ partial,
+                                                    int nblk) {
+  __shared__ double red[DOT_V][DOT_T / 64];
+  const int v0 = blockIdx.y * DOT_V;
+  double acc[DOT_V] = {0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * DOT_T + threadIdx.x; i < n; i += (int64_t)nblk * DOT_T) {
+    double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < DOT_V; ++q) {
+      int v = v0 + q;
+      if (v < k) acc[q] += V[(int64_t)v * ldv + i] * wi;
+      else if (v == k) acc[q] += wi * wi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < DOT_V; ++q) {
+    double a = acc[q];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) red[q][wv] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < DOT_V) {
+    int v = v0 + threadIdx.x;
+    if (v <= k) {
+      double s = 0.0;
+      for (int q = 0; q < DOT_T / 64; ++q) s += red[threadIdx.x][q];
+      partial[(int64_t)v * nblk + blockIdx.x] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partial(int nblk, const double* __restrict__ partial,
+                                                        double* __restrict__ out, int accumulate) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(int64_t)v * nblk + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
+}
+
+// w -= sum_v V_v h_v
+template <class TV>
+__global__ void k_maxpy(int64_t n, int k, const TV* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+                        double* __restrict__ w, double sign) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < k; ++v) s += (double)V[(int64_t)v * ldv + i] * h[v];
+  w[i] += sign * s;
+}
+
+__global__ void k_scale(int64_t n, const double* __restrict__ a, double s, double* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i] * s;
+}
+
+// Block scaling of a right-hand side by D_b^-1 (trans = 0) or D_b^-T.
+__global__ void k_blockscale(int64_t nfree, int b, const double* __restrict__ dinv, const double* __restrict__ x,
+                             double* __restrict__ y, int trans) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfree * b) return;
+  int64_t R = i / b;
+  int m = (int)(i % b);
+  double s = 0.0;
+  for (int k = 0; k < b; ++k)
+    s += (trans ? dinv[R * b * b + k * b + m] : dinv[R * b * b + m * b + k]) * x[R * b + k];
+  y[i] = s;
+}
+
+static inline dim3 g1(int64_t n, int t = 256) { return dim3((unsigned)cdiv(std::max<int64_t>(n, 1), t)); }
+
+static int pick_g(int64_t nnz, int64_t n) {
+  double avg = n ? (double)nnz / (double)n : 0.0;
+  if (avg < 6) return 4;
+  if (avg < 14) return 8;
+  if (avg < 40) return 16;
+  return 32;
+}
+
+template <class TA, class TX, class TY, int MODE>
+static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, const TA* av, const TX* x, const TY* b,
+                       const TY* d, const int8_t* cf, int X, TY omega, TY* y, hipStream_t st) {
+  if (n == 0) return AH_OK;
+  dim3 grid((unsigned)cdiv(n * G, 256));
+  switch (G) {
+    case 4: hipLaunchKernelGGL((k_csr<TA, TX, TY, 4, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
+    case 8: hipLaunchKernelGGL((k_csr<TA, TX, TY, 8, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
+    case 16: hipLaunchKernelGGL((k_csr<TA, TX, TY, 16, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
+    default: hipLaunchKernelGGL((k_csr<TA, TX, TY, 32, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
+  }
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+// ------------------------------------------------------------ V-cycles
+template <class T>
+struct Ops;
+template <>
+struct Ops<double> {
+  static const double* A(const AhLevel& L) { return L.val; }
+  static const double* AT(const AhLevel& L) { return L.ATval; }
+  static const double* R(const AhLevel& L) { return L.Rval; }
+  static const double* RT(const AhLevel& L) { return L.RTval; }
+  static const double* d(const AhLevel& L) { return L.diag; }
+  static double* b(AhLevel& L) { return L.b; }
+  static double* x(AhLevel& L) { return L.x; }
+  static double* y(AhLevel& L) { return L.y; }
+};
+template <>
+struct Ops<float> {
+  static const float* A(const AhLevel& L) { return L.val32; }
+  static const float* AT(const AhLevel& L) { return L.ATval32; }
+  static const float* R(const AhLevel& L) { return L.Rval32; }
+  static const float* RT(const AhLevel& L) { return L.RTval32; }
+  static const float* d(const AhLevel& L) { return L.diag32; }
+  static float* b(AhLevel& L) { return L.b32; }
+  static float* x(AhLevel& L) { return L.x32; }
+  static float* y(AhLevel& L) { return L.y32; }
+};
+
+// Forward cycle on level l: b -> out.  out must differ from b and from the
+// level's x buffer; callers pass the level's y buffer or an external vector.
+// The recursion writes the coarse correction into the coarse level's y.
+template <class T>
+static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
+  AhLevel& L = h->lev[l];
+  const int nlev = (int)h->lev.size();
+  if (l == nlev - 1) {
+    if (L.n == 0) return AH_OK;
+    hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)L.n), dim3(64), 0, st, (int)L.n, h->cinv, b, out, 0);
+    AH_LAUNCHED();
+    return AH_OK;
+  }
+  AhLevel& C = h->lev[l + 1];
+  const int G = pick_g(L.nnz, L.n);
+  const int GR = pick_g(L.nnzR, L.nc);
+  AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
+                                (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
+  T* ec = Ops<T>::y(C);
+  AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
+  T* cur = Ops<T>::x(L);
+  T* alt = Ops<T>::y(L);
+  hipLaunchKernelGGL(k_interp<T>, g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, cur);
+  AH_LAUNCHED();
+  const int sets_ffc[3] = {0, 0, 1};   // F, F, C
+  const int nsw = h->prm.relax == 1 ? 1 : 3;
+  const T om = (T)h->prm.omega;
+  for (int s = 0; s < nsw; ++s) {
+    T* dst = (s == nsw - 1) ? out : alt;
+    AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, sets_ffc[s], om,
+                                     dst, st)));
+    alt = cur;
+    cur = dst;
+  }
+  return AH_OK;
+}
+
+// Transposed cycle on level l: g -> out (out may alias g, not the level's
+// x or y).  The recursion writes its result over the coarse level's input
+// (or into the coarsest level's x).
+template <class T>
+static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st) {
+  AhLevel& L = h->lev[l];
+  const int nlev = (int)h->lev.size();
+  if (l == nlev - 1) {
+    if (L.n == 0) return AH_OK;
+    hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)L.n), dim3(64), 0, st, (int)L.n, h->cinv, g, out, 1);
+    AH_LAUNCHED();
+    return AH_OK;
+  }
+  AhLevel& C = h->lev[l + 1];
+  const int G = pick_g(L.nnz, L.n);
+  const T om = (T)h->prm.omega;
+  T* cur = Ops<T>::x(L);
+  T* alt = Ops<T>::y(L);
+  AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
+  const int sets[3] = {1, 0, 0};   // C, F, F
+  const int nsw = h->prm.relax == 1 ? 1 : 3;
+  for (int s = 3 - nsw; s < 3; ++s) {
+    AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.ATptr, L.ATcol, Ops<T>::AT(L), cur, g, Ops<T>::d(L), L.cf, sets[s], om,
+                                     alt, st)));
+    std::swap(cur, alt);
+  }
+  // residual g - A^T y, restricted by P^T
+  AH_TRY((csr_g<T, T, T, SP_RES>(G, L.n, L.ATptr, L.ATcol, Ops<T>::AT(L), cur, g, (const T*)nullptr,
+                                 (const int8_t*)nullptr, 0, (T)0, alt, st)));
+  AH_TRY((csr_g<T, T, T, SP_MV>(4, L.nc, L.PTptr, L.PTcol, (const T*)nullptr, alt, (const T*)nullptr,
+                                (const T*)nullptr, (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
+  T* ec = (l + 1 == nlev - 1) ? Ops<T>::x(C) : Ops<T>::b(C);
+  AH_TRY(vcycle_t<T>(h, l + 1, Ops<T>::b(C), ec, st));
+  // out = y + R^T e_c
+  const int GR = pick_g(L.nnzR, L.n);
+  AH_TRY((csr_g<T, T, T, SP_ADDMV>(GR, L.n, L.RTptr, L.RTcol, Ops<T>::RT(L), ec, cur, (const T*)nullptr,
+                                   (const int8_t*)nullptr, 0, (T)0, out, st)));
+  return AH_OK;
+}
+
+// Preconditioner application on level 0 for the requested precision:
+// r (FP64, level-0 scaled space) -> z (FP64) or z32 (FP32).
+static ah_status precond(ah_hier* h, const double* r, double* z, float* z32, int precision, int transpose,
+                         hipStream_t st) {
+  AhLevel& L = h->lev[0];
+  if (precision == 0) {
+    return transpose ? vcycle_t<double>(h, 0, r, z, st) : vcycle<double>(h, 0, r, z, st);
+  }
+  hipLaunchKernelGGL((k_cast<double, float>), g1(L.n), dim3(256), 0, st, L.n, r, L.b32);
+  AH_LAUNCHED();
+  return transpose ? vcycle_t<float>(h, 0, L.b32, z32, st) : vcycle<float>(h, 0, L.b32, z32, st);
+}
+
+// ------------------------------------------------------------ FGMRES
+static ah_status ensure_workspace(ah_hier* h, int m, int precision) {
+  const int64_t n = h->lev[0].n;
+  if (h->m_alloc >= m && (precision == 0 ? h->Z != nullptr : h->Z32 != nullptr)) return AH_OK;
+  Arena& ar = h->arena;
+  if (h->m_alloc < m) {
+    AH_TRY(ar.get(&h->V, (int64_t)(m + 1) * n));
+    AH_TRY(ar.get(&h->w, n));
+    AH_TRY(ar.get(&h->r, n));
+    AH_TRY(ar.get(&h->bhat, n));
+    AH_TRY(ar.get(&h->partial, (int64_t)(m + 3) * 1024));
+    AH_TRY(ar.get(&h->hdev, 4 * (m + 3)));
+    if (h->hhost) (void)hipHostFree(h->hhost);
+    AH_HIP(hipHostMalloc((void**)&h->hhost, 4 * (m + 3) * sizeof(double), hipHostMallocDefault));
+    h->Z = nullptr;
+    h->Z32 = nullptr;
+    h->m_alloc = m;
+  }
+  if (precision == 0 && !h->Z) AH_TRY(ar.get(&h->Z, (int64_t)m * n));
+  if (precision == 1 && !h->Z32) AH_TRY(ar.get(&h->Z32, (int64_t)m * n));
+  return AH_OK;
+}
+
+// out[0..k] = V[0..k-1].w and w.w (k vectors plus the norm), on the device.
+static ah_status multidot(int64_t n, int k, const double* V, const double* w, double* partial, double* out,
+                          hipStream_t st) {
+  int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, DOT_T * 4)));
+  dim3 grid(nblk, (unsigned)cdiv(k + 1, DOT_V));
+  hipLaunchKernelGGL(k_multidot, grid, dim3(DOT_T), 0, st, n, k, V, n, w, partial, nblk);
+  AH_LAUNCHED();
+  hipLaunchKernelGGL(k_reduce_partial, dim3(k + 1), dim3(256), 0, st, nblk, partial, out, 0);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+struct Op {
+  const int64_t* rp;
+  const int32_t* ci;
+  const double* v;
+};
+
+static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const ah_solve_params& prm, int transpose,
+                        hipStream_t st, ah_solve_info* info) {
+  const int64_t n = h->lev[0].n;
+  const int m = std::max(1, prm.restart);
+  AH_TRY(ensure_workspace(h, m, prm.precision));
+  const int G0 = pick_g(h->lev[0].nnz, n);
+  double* hd = h->hdev;
+  double* hh = h->hhost;
+  auto t0 = std::chrono::steady_clock::now();
+  // ||b||
+  AH_TRY(multidot(n, 0, h->V, bvec, h->partial, hd, st));
+  AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+  AH_HIP(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(hh[0]);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  int its = 0;
+  bool converged = false;
+  double relres = 1.0, true_rel = 1.0;
+  ah_status status = AH_OK;
+  if (!(bnorm > 0.0)) {
+    AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+    if (info) { info->iters = 0; info->converged = 1; info->relres = 0; info->true_relres = 0; }
+    return AH_OK;
+  }
+  if (!std::isfinite(bnorm)) { set_error("air_solve: non-finite right-hand side"); return AH_EBREAKDOWN; }
+  while (true) {
+    // r = b - A x
+    AH_TRY((csr_g<double, double, double, SP_RES>(G0, n, A.rp, A.ci, A.v, x, bvec, (const double*)nullptr,
+                                                  (const int8_t*)nullptr, 0, 0.0, h->r, st)));
+    AH_TRY(multidot(n, 0, h->V, h->r, h->partial, hd, st));
+    AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+    AH_HIP(hipStreamSynchronize(st));
+    const double beta = std::sqrt(hh[0]);
+    true_rel = beta / bnorm;
+    relres = true_rel;
+    if (!std::isfinite(beta)) { set_error("air_solve: breakdown (NaN residual)"); status = AH_EBREAKDOWN; break; }
+    if (beta <= prm.tol * bnorm) { converged = true; break; }
+    if (its >= prm.maxit) break;
+    hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, h->r, 1.0 / beta, h->V);
+    AH_LAUNCHED();
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V + (int64_t)j * n;
+      double* zj = h->Z ? h->Z + (int64_t)j * n : nullptr;
+      float* zj32 = h->Z32 ? h->Z32 + (int64_t)j * n : nullptr;
+      AH_TRY(precond(h, vj, prm.precision == 0 ? zj : nullptr, prm.precision == 1 ? zj32 : nullptr, prm.precision,
+                     transpose, st));
+      if (prm.precision == 0)
+        AH_TRY((csr_g<double, double, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj, (const double*)nullptr,
+                                                     (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st)));
+      else
+        AH_TRY((csr_g<double, float, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj32, (const double*)nullptr,
+                                                    (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st)));
+      ++its;
+      const int k = j + 1;
+      // CGS2
+      double* h1 = hd;               // [k+1]: dots, then ||w0||^2 at [k]
+      double* h2 = hd + (m + 2);     // [k+1]
+      double* hn = hd + 2 * (m + 2); // [1]
+      AH_TRY(multidot(n, k, h->V, h->w, h->partial, h1, st));
+      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, k, h->V, n, h1, h->w, -1.0);
+      AH_LAUNCHED();
+      AH_TRY(multidot(n, k, h->V, h->w, h->partial, h2, st));
+      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, k, h->V, n, h2, h->w, -1.0);
+      AH_LAUNCHED();
+      AH_TRY(multidot(n, 0, h->V, h->w, h->partial, hn, st));
+      AH_HIP(hipMemcpyAsync(hh, hd, (3 * (m + 2)) * sizeof(double), hipMemcpyDeviceToHost, st));
+      AH_HIP(hipStreamSynchronize(st));
+      const double w0 = std::sqrt(hh[k]);
+      const double hnorm = std::sqrt(hh[2 * (m + 2)]);
+      if (!std::isfinite(hnorm) || !std::isfinite(w0)) {
+        set_error("air_solve: breakdown (NaN in Arnoldi)");
+        status = AH_EBREAKDOWN;
+        kdone = j;
+        break;
+      }
+      for (int i = 0; i < k; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 2) + i];
+      H[(size_t)k * m + j] = hnorm;
+      for (int i = 0; i < j; ++i) {
+        double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)k * m + j];
+      const double den = std::hypot(a, bb);
+      if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; } else { cs[j] = a / den; sn[j] = bb / den; }
+      H[(size_t)j * m + j] = cs[j] * a + sn[j] * bb;
+      H[(size_t)k * m + j] = 0.0;
+      g[k] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      kdone = k;
+      relres = std::fabs(g[k]) / bnorm;
+      const bool happy = hnorm <= 1e-14 * w0;
+      if (std::fabs(g[k]) <= prm.tol * bnorm || happy || its >= prm.maxit) break;
+      hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, h->w, 1.0 / hnorm, h->V + (int64_t)k * n);
+      AH_LAUNCHED();
+    }
+    if (status != AH_OK && kdone == 0) break;
+    for (int i = kdone - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < kdone; ++c) s -= H[(size_t)i * m + c] * y[c];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    AH_HIP(hipMemcpyAsync(hd, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, st));
+    if (prm.precision == 0)
+      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, kdone, h->Z, n, hd, x, 1.0);
+    else
+      hipLaunchKernelGGL(k_maxpy<float>, g1(n), dim3(256), 0, st, n, kdone, h->Z32, n, hd, x, 1.0);
+    AH_LAUNCHED();
+    if (status != AH_OK) break;
+  }
+  AH_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = its;
+    info->converged = converged ? 1 : 0;
+    info->relres = relres;
+    info->true_relres = true_rel;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status != AH_OK) return status;
+  return converged ? AH_OK : AH_ENOCONV;
+}
+
+}  // namespace ah
+
+using namespace ah;
+
+extern "C" void ah_solve_defaults(ah_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-8;
+  p->restart = 100;
+  p->maxit = 1000;
+  p->precision = 0;
+  p->x0_given = 0;
+}
+
+static ah_status check_solve(const ah_hier* h, const ah_solve_params* prm, int transpose) {
+  if (!h || !prm) { set_error("air_solve: null argument"); return AH_EINVAL; }
+  if (prm->precision == 1 && !h->prm.fp32_cycle) {
+    set_error("air_solve: FP32 cycle requested but the hierarchy was built without fp32_cycle");
+    return AH_EINVAL;
+  }
+  if (prm->precision < 0 || prm->precision > 1 || prm->restart < 1 || prm->maxit < 0 || !(prm->tol > 0.0)) {
+    set_error("air_solve: invalid parameters");
+    return AH_EINVAL;
+  }
+  if (transpose && !h->prm.adjoint) {
+    set_error("air_solve_adjoint: hierarchy built without adjoint = 1");
+    return AH_EINVAL;
+  }
+  return AH_OK;
+}
+
+extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, const ah_solve_params* prm,
+                               void* stream, ah_solve_info* info) {
+  AH_TRY(check_solve(hc, prm, 0));
+  if (!x) { set_error("air_solve: null x"); return AH_EINVAL; }
+  ah_hier* h = const_cast<ah_hier*>(hc);
+  hipStream_t st = as_stream(stream);
+  const ah_system* s = h->sys;
+  const int64_t n = s->n;
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision));
+  const double* b = s->d_Hhat;
+  if (rhs) {
+    hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, rhs, h->bhat, 0);
+    AH_LAUNCHED();
+    b = h->bhat;
+  }
+  if (!prm->x0_given) AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+  Op A{s->d_rowptr, s->d_col, s->d_val};
+  return fgmres(h, A, b, x, *prm, 0, st, info);
+}
+
+extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, double* lam, const ah_solve_params* prm,
+                                       void* stream, ah_solve_info* info) {
+  AH_TRY(check_solve(hc, prm, 1));
+  if (!g || !lam) { set_error("air_solve_adjoint: null argument"); return AH_EINVAL; }
+  ah_hier* h = const_cast<ah_hier*>(hc);
+  hipStream_t st = as_stream(stream);
+  const ah_system* s = h->sys;
+  const int64_t n = s->n;
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision));
+  double* mu = h->bhat;   // S_hat^T mu = g, then lam = D_b^-T mu
+  AhLevel& L0 = h->lev[0];
+  if (!L0.ATptr) {
+    set_error("air_solve_adjoint: transposed level-0 operator missing");
+    return AH_EINVAL;
+  }
+  AH_HIP(hipMemsetAsync(mu, 0, n * sizeof(double), st));   // zero initial guess
+  Op AT{L0.ATptr, L0.ATcol, L0.ATval};
+  ah_status rc = fgmres(h, AT, g, mu, *prm, 1, st, info);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, mu, lam, 1);
+  AH_LAUNCHED();
+  AH_HIP(hipStreamSynchronize(st));
+  return rc;
+}
+
+extern "C" ah_status ah_vcycle_apply(const ah_hier* hc, const double* r, double* z, int precision, int transpose,
+                                     void* stream) {
+  if (!hc || !r || !z) { set_error("ah_vcycle_apply: null argument"); return AH_EINVAL; }
+  ah_hier* h = const_cast<ah_hier*>(hc);
+  if (precision == 1 && !h->prm.fp32_cycle) { set_error("ah_vcycle_apply: no FP32 operators"); return AH_EINVAL; }
+  if (transpose && !h->prm.adjoint) { set_error("ah_vcycle_apply: no transposes"); return AH_EINVAL; }
+  hipStream_t st = as_stream(stream);
+  const int64_t n = h->lev[0].n;
+  if (precision == 0) return precond(h, r, z, nullptr, 0, transpose, st);
+  float* z32 = nullptr;
+  Arena tmp;
+  tmp.stream = st;
+  AH_TRY(tmp.get(&z32, n));
+  AH_TRY(precond(h, r, nullptr, z32, 1, transpose, st));
+  hipLaunchKernelGGL((k_cast<float, double>), g1(n), dim3(256), 0, st, n, z32, z);
+  AH_LAUNCHED();
+  AH_HIP(hipStreamSynchronize(st));
+  tmp.release();
+  return AH_OK;
+}

@@ -1,0 +1,104 @@
+// Library objects built on the device: the assembled facet system and the
+// AIR hierarchy, plus device utilities shared by the kernels.
+#pragma once
+
+#include "common.h"
+
+struct ah_system {
+  ah_mesh* mesh = nullptr;
+  int D = 0, p = 0, nu = 0, b = 0, nl = 0, nq = 0, nqf = 0;
+  double visc = 0.0, alpha = 0.0;
+  bool keep = false;
+  ah::Arena arena;
+  ah::RefTables tab;
+  int64_t n = 0;        // free DOFs
+  int64_t nfree = 0;    // free facets
+  int64_t nnzb = 0;     // blocks of the free-facet pattern
+  double* d_bval = nullptr;   // [nnzb][b][b] unscaled S
+  double* d_H = nullptr;      // [n] unscaled H after Dirichlet elimination
+  double* d_Hhat = nullptr;   // [n]
+  double* d_Dinv = nullptr;   // [nfree][b][b]
+  double* d_lamD = nullptr;   // [nf][b]
+  int64_t nnz = 0;            // scaled scalar CSR (level 0)
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val = nullptr;
+  // element data kept for reconstruction and the adjoint
+  double* d_Ainv = nullptr;   // [ne][nu][nu]
+  double* d_Bm = nullptr;     // [ne][nu][nl]
+  double* d_Cm = nullptr;     // [ne][nl][nu]
+  double* d_Fv = nullptr;     // [ne][nu]
+  ~ah_system() { arena.release(); }
+};
+
+namespace ah {
+
+// Exclusive prefix sum of n int64 values into out[0..n] (out[n] = total).
+ah_status scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
+// Same for int32 counts producing int64 offsets.
+ah_status scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
+// Read one int64 from the device (synchronizes the stream).
+ah_status read_i64(const int64_t* d, int64_t* h, hipStream_t st);
+
+constexpr int WAVE = 64;
+
+}  // namespace ah
+
+// One level of the AIR hierarchy (scalar CSR, int64 row offsets).
+struct AhLevel {
+  int64_t n = 0, nnz = 0;
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  double* diag = nullptr;
+  float* diag32 = nullptr;
+  // coarsening (all but the coarsest level)
+  int64_t nc = 0;
+  int8_t* cf = nullptr;        // 1 = C, 0 = F
+  int32_t* pcol = nullptr;     // one-point interpolation: coarse column or -1
+  int64_t nnzR = 0;
+  int64_t* Rptr = nullptr;
+  int32_t* Rcol = nullptr;
+  double* Rval = nullptr;
+  float* Rval32 = nullptr;
+  // transposes for the adjoint cycle
+  int64_t* ATptr = nullptr;
+  int32_t* ATcol = nullptr;
+  double* ATval = nullptr;
+  float* ATval32 = nullptr;
+  int64_t* RTptr = nullptr;    // R^T: rows = fine points
+  int32_t* RTcol = nullptr;
+  double* RTval = nullptr;
+  float* RTval32 = nullptr;
+  int64_t* PTptr = nullptr;    // P^T: rows = coarse points, entries = fine points (weight 1)
+  int32_t* PTcol = nullptr;
+  // cycle work vectors
+  double* b = nullptr;
+  double* x = nullptr;
+  double* y = nullptr;
+  float* b32 = nullptr;
+  float* x32 = nullptr;
+  float* y32 = nullptr;
+};
+
+struct ah_hier {
+  const ah_system* sys = nullptr;
+  ah::Arena arena;
+  ah_air_params prm{};
+  std::vector<AhLevel> lev;
+  double* cinv = nullptr;      // dense inverse of the coarsest matrix [nL][nL]
+  int64_t nfallback = 0;
+  // FGMRES workspace (allocated on first solve)
+  int m_alloc = 0;
+  double* V = nullptr;         // [(m+1)][n]
+  double* Z = nullptr;         // [m][n] (FP64 cycle)
+  float* Z32 = nullptr;        // [m][n] (FP32 cycle)
+  double* w = nullptr;
+  double* r = nullptr;
+  double* bhat = nullptr;
+  double* partial = nullptr;   // reduction partials
+  double* hdev = nullptr;      // [2 (m+2)] device scalars
+  double* hhost = nullptr;     // pinned host mirror
+  ~ah_hier();
+};

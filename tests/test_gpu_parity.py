@@ -1,0 +1,188 @@
+"""HIP path vs oracle, element by element on the same seeded inputs.
+
+Tolerances (FP64 everywhere unless stated):
+  * assembled scaled matrix, right-hand side, inverse facet blocks,
+    Dirichlet traces: 1e-12 relative to the largest entry (different element
+    bases and summation orders on the two sides; cond(A_K) <~ 1e3);
+  * C/F splitting, one-point interpolation columns: bit-exact (integers);
+  * lAIR restriction and coarse matrices: 1e-10 relative (they inherit the
+    level matrices' rounding through small dense solves);
+  * one V-cycle: 1e-10 relative;
+  * solution at tol 1e-12: 1e-10 relative; iterations at the workload
+    tolerance within +-1;
+  * FP32 cycle: solution within 1e-8 of the FP64 oracle at tol 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import air as oair, krylov as okry, adjoint as oadj
+from oracle.drivers import setup_problem, air_fgmres_solve, direct_solve, problem_g
+from oracle.hdg import reconstruct as oreconstruct
+from gpu_cases import case, gpu_system, to_scipy, rel_sparse_diff
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["c1", "c1_p3", "slab", "slab_nu0", "kuhn_nu0", "kuhn_nu4", "kuhn_nu2", "c5", "kuhn_p3"]
+SMALL_COARSE = 40
+
+
+def _both(name):
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    return g, o, prob
+
+
+@pytest.fixture(scope="module")
+def built():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = _both(name)
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_assembly_parity(built, name):
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    assert g.n == o.n
+    ex = g.export()
+    S = to_scipy(ex["rowptr"], ex["col"], ex["val"], g.n)
+    assert rel_sparse_diff(S, o.Shat) < 1e-12
+    hh = ex["hhat"].cpu().numpy()
+    assert np.abs(hh - o.Hhat).max() <= 1e-12 * max(np.abs(o.Hhat).max(), 1e-300)
+    dinv = ex["dinv"].cpu().numpy()
+    assert np.abs(dinv - o.Dinv).max() <= 1e-11 * np.abs(o.Dinv).max()
+    lamd = ex["lam_dir"].cpu().numpy()
+    assert np.abs(lamd - o.lamD_full).max() <= 1e-12 * max(np.abs(o.lamD_full).max(), 1.0)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_hierarchy_parity(built, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    assert H.info["levels"] == OH.nlev
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    for l in range(OH.nlev):
+        lv = H.level(l)
+        A = to_scipy(lv["rowptr"], lv["col"], lv["val"], lv["n"])
+        assert rel_sparse_diff(A, OH.levels[l].A) < (1e-12 if l == 0 else 1e-10), l
+        if l + 1 < OH.nlev:
+            ol = OH.levels[l]
+            assert np.array_equal(lv["cf"].cpu().numpy(), ol.cf), l
+            pc = lv["pcol"].cpu().numpy()
+            Pd = ol.P.tocsr()
+            opc = np.full(ol.A.shape[0], -1)
+            rows = np.repeat(np.arange(Pd.shape[0]), np.diff(Pd.indptr))
+            opc[rows] = Pd.indices
+            assert np.array_equal(pc, opc), l
+            R = to_scipy(lv["Rptr"], lv["Rcol"], lv["Rval"], ol.R.shape[0], ol.R.shape[1])
+            assert rel_sparse_diff(R, ol.R) < 1e-10, l
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_vcycle_parity(built, name, transpose):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, transpose, flush=True)
+    g, o, _ = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, adjoint=1)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    r = np.random.default_rng(5).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda"), transpose=transpose).cpu().numpy()
+    zo = oair.vcycle_T(OH, r) if transpose else oair.vcycle(OH, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_solve_parity(built, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    x, info = H.solve(tol=1e-12)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    xg = x.cpu().numpy()
+    assert info["converged"]
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    tol = 1e-10 if name.startswith("c1") else 1e-8
+    _, i8 = H.solve(tol=tol)
+    _, io8 = air_fgmres_solve(o, tol=tol, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "slab_nu0", "kuhn_nu0", "kuhn_nu4"])
+def test_fp32_cycle_accuracy(built, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1)
+    x, info = H.solve(tol=1e-10, precision=1)
+    xo = direct_solve(o)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu2", "c5"])
+def test_reconstruct_parity(built, name):
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    xo = direct_solve(o)
+    U = g.reconstruct(torch.as_tensor(xo, device="cuda")).cpu().numpy()
+    Uo = oreconstruct(o, xo)
+    assert np.abs(U - Uo).max() <= 1e-10 * np.abs(Uo).max()
+
+
+def test_empty_free_set():
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("one_tet")
+    g = gpu_system(v, c, prob, p)
+    assert g.n == 0
+    H = Hierarchy(g)
+    x, info = H.solve(tol=1e-10)
+    assert info["converged"] and info["iters"] == 0
+
+
+def test_single_level_direct():
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("c1")
+    g = gpu_system(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=5000)
+    assert H.info["levels"] == 1
+    x, info = H.solve(tol=1e-12)
+    o = setup_problem(v, c, prob, p)
+    xo = direct_solve(o)
+    assert info["iters"] == 1
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_adjoint_and_gradients_c5(built):
+    from paper_2010_11130_amd import Hierarchy
+    g, o, prob = built("c5")
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, adjoint=1)
+    lam, _ = H.solve(tol=1e-13)
+    rng = np.random.default_rng(9)
+    target = direct_solve(o) + 0.1 * rng.standard_normal(o.n)
+    gvec = lam - torch.as_tensor(target, device="cuda")
+    adj, info = H.solve_adjoint(gvec, tol=1e-13)
+    assert info["converged"]
+    lam_o = direct_solve(o)
+    adj_o = oadj.adjoint_direct(o, lam_o - target)
+    assert np.linalg.norm(adj.cpu().numpy() - adj_o) <= 1e-9 * np.linalg.norm(adj_o)
+    dq, dnu = g.grad(lam, adj)
+    g_fn = problem_g(prob, o.mesh, o.kinds, 0.0, 1.0)
+    J, dc_o, dnu_o, _ = oadj.misfit_and_grads(o, lam_o, target, prob.a, prob.f, g_fn, prob.basis)
+    assert abs(dnu - dnu_o) <= 1e-8 * abs(dnu_o)
+    # source gradient: contract dJ/df_q with the Gaussian basis on the device
+    from paper_2010_11130_amd import source_gauss_T
+    xe, _ = g.mesh.quad_points(g.p)
+    dc = source_gauss_T(xe.reshape(-1, 3), prob.centers, prob.width, dq.reshape(-1)).cpu().numpy()
+    assert np.abs(dc - dc_o).max() <= 1e-8 * np.abs(dc_o).max()
