@@ -1,0 +1,237 @@
+"""Throughput of the space-time HDG + lAIR-FGMRES hot path on one MI355X.
+
+Workload (slab-by-slab, 2+1-D): the unit square split into 64x64 quads ->
+8,192 triangles -> prisms -> 24,576 tets per slab, 64 slabs of dt = 1/64,
+p = 2 (b = 6, 342,528 free facet DOFs per slab), rotating velocity
+a = (-(x2-1/2), x1-1/2), nu = 1e-4, Gaussian hill at (0.3, 0.5) of width
+0.05, f = 0; one assembly + lAIR setup + FGMRES solve to relative residual
+1e-8 + reconstruction per slab, each slab taking the previous slab's trace
+as inflow data.  One step = the whole 64-slab march.  Inputs (mesh, boundary
+data of every slab) are resident on the device before timing.
+
+value = total free DOFs / step time (FP64 cycle), with the FP32-cycle march
+reported beside it.  The dominant kernel's roofline figure uses its
+algorithmic bytes (counted by the library per launch) over its average
+launch duration measured with HIP events on its own stream.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DOF/s to 1e-8 rel. residual (setup+solve), FP32 vs FP64 V-cycle; HBM GB/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="quads per side of the spatial mesh")
+    ap.add_argument("--slabs", type=int, default=64)
+    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--nu", type=float, default=1e-4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+class March:
+    """Device-resident inputs of the slab march and one step of it."""
+
+    def __init__(self, n, slabs, p, nu):
+        import numpy as np
+        import torch
+        from paper_2010_11130_amd import Mesh
+        from workloads import slab_prism_tet_mesh, boundary_kinds
+        from workloads.problems import slab_hill
+        self.np, self.torch = np, torch
+        self.dt = 1.0 / slabs
+        self.slabs, self.p = slabs, p
+        self.prob = slab_hill(nu)
+        v, c = slab_prism_tet_mesh(n, self.dt)
+        self.vert, self.cell = v, c
+        m = Mesh(v, c)
+        fv, _ = m.facets()
+        bf = m.boundary_facets()
+        isb = np.zeros(m.nf, dtype=bool)
+        isb[bf] = True
+        kinds = boundary_kinds(v, fv, isb)
+        m.set_bc(kinds)
+        self.mesh = m
+        _, xb = m.quad_points(p)
+        tb = v[fv[bf]][:, :, 0]
+        bot = torch.as_tensor(np.all(np.abs(tb) <= 1e-12, axis=1), device="cuda")[:, None]
+        kb = torch.as_tensor(kinds[bf], device="cuda")[:, None]
+        g = []
+        for k in range(slabs):
+            x = xb.clone()
+            x[..., 0] += k * self.dt
+            u = self.prob.u(x)
+            g.append(torch.where(kb == 1, u, torch.where(bot, u, torch.zeros_like(u))))
+        self.g = torch.stack(g).contiguous()
+        self.a = torch.as_tensor(self.prob.a(v), device="cuda").contiguous()
+        self.nu = nu
+        torch.cuda.synchronize()
+
+    def step(self, precision, tol, record=None):
+        from paper_2010_11130_amd import System, Hierarchy
+        torch = self.torch
+        prev = None
+        last = None
+        for k in range(self.slabs):
+            g = self.g[k]
+            t0 = time.perf_counter()
+            if prev is not None:
+                prev[0].trace_to_inflow(prev[1], self.mesh, g)
+            s = System(self.mesh, self.p, self.nu, self.a, None, g)
+            t1 = time.perf_counter()
+            h = Hierarchy(s, fp32_cycle=1 if precision else 0)
+            t2 = time.perf_counter()
+            x, info = h.solve(tol=tol, precision=precision)
+            t3 = time.perf_counter()
+            U = s.reconstruct(x)
+            if not info["converged"]:
+                raise RuntimeError("slab %d did not converge: %s" % (k, info))
+            if record is not None:
+                record.append({"assemble": t1 - t0, "setup": t2 - t1, "solve": t3 - t2,
+                               "iters": info["iters"], "levels": h.info["levels"],
+                               "op_complexity": h.info["op_complexity"]})
+            prev = (s, x)
+            last = (x, U)
+        torch.cuda.synchronize()
+        return last
+
+
+def profile_totals(tags):
+    import ctypes as C
+    from paper_2010_11130_amd import lib
+    out = {}
+    for t in tags:
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        lib().ah_profile_read(t.encode(), C.byref(n), C.byref(ms), C.byref(by))
+        if n.value:
+            out[t] = {"launches": n.value, "total_ms": ms.value, "bytes": by.value,
+                      "avg_us": 1e3 * ms.value / n.value,
+                      "gbs": by.value / (ms.value * 1e-3) / 1e9 if ms.value > 0 else 0.0}
+    return out
+
+
+def run_timed(march, precision, steps, warmup, tol):
+    import torch
+    from paper_2010_11130_amd import lib
+    for _ in range(warmup):
+        march.step(precision, tol)
+    lib().ah_profile_reset()
+    lib().ah_profile_enable(1)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        rec = []
+        last = march.step(precision, tol, rec)
+        recs.append(rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib().ah_profile_enable(0)
+    prof = profile_totals(["element", "spmv0", "sweep0", "sweep0_f32", "rap0"])
+    lib().ah_profile_reset()
+    return (t1 - t0) / steps, recs, prof, last
+
+
+def cpu_baseline(n, p, nu, tol, dt):
+    """The oracle on one slab of the same workload (slab 0)."""
+    import numpy as np
+    from workloads import slab_prism_tet_mesh
+    from workloads.problems import slab_hill
+    from oracle.drivers import setup_problem, air_fgmres_solve
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [d.get("num_threads", 1) for d in threadpool_info()])
+    except Exception:
+        threads = 1
+    v, c = slab_prism_tet_mesh(n, dt)
+    t0 = time.perf_counter()
+    s = setup_problem(v, c, slab_hill(nu), p)
+    x, info = air_fgmres_solve(s, tol=tol)
+    t1 = time.perf_counter()
+    return {"value": s.n / (t1 - t0), "unit": "DOF/s", "cores": int(threads), "kind": "oracle",
+            "sample": "slab 0 of the march (%d free DOFs): assembly + lAIR setup + FGMRES to %g, %d iterations, "
+                      "%.1f s" % (s.n, tol, info["iters"], t1 - t0)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus %d requested); the path has no "
+              "multi-GPU sharding" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2010_11130_amd import lib
+    lib()
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    march = March(args.n, args.slabs, args.p, args.nu)
+    ndof = None
+    t64, recs64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol)
+    from paper_2010_11130_amd import System
+    # free DOFs per slab
+    import ctypes as C
+    ndof_slab = last64[0].numel()
+    total = ndof_slab * args.slabs
+    value = total / t64
+    r = recs64[-1]
+    st = {k: 1e3 * sum(x[k] for x in r) for k in ("assemble", "setup", "solve")}
+    iters = [x["iters"] for x in r]
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t64, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "slab-by-slab 2+1D rotating Gaussian hill: %dx%d quads -> %d tets/slab, %d slabs "
+                               "dt=1/%d, p=%d, nu=%g, lAIR-FGMRES to %g per slab"
+                               % (args.n, args.n, 6 * args.n * args.n, args.slabs, args.slabs, args.p, args.nu,
+                                  args.tol),
+                   "free_dofs_per_slab": ndof_slab, "slabs": args.slabs, "total_free_dofs": total},
+        "stages_ms_per_step": st,
+        "setup_solve_dofs_per_s": total / (1e-3 * (st["setup"] + st["solve"])),
+        "fgmres_iters_per_slab": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)},
+        "levels": r[0]["levels"], "op_complexity": r[0]["op_complexity"],
+        "kernels": prof64,
+    }
+    if not args.no_fp32:
+        t32, recs32, prof32, last32 = run_timed(march, 1, args.steps, args.warmup, args.tol)
+        r32 = recs32[-1]
+        st32 = {k: 1e3 * sum(x[k] for x in r32) for k in ("assemble", "setup", "solve")}
+        it32 = [x["iters"] for x in r32]
+        err = (torch.linalg.norm(last32[0] - last64[0]) / torch.linalg.norm(last64[0])).item()
+        out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
+                             "stages_ms_per_step": st32,
+                             "setup_solve_dofs_per_s": total / (1e-3 * (st32["setup"] + st32["solve"])),
+                             "fgmres_iters_per_slab": {"min": min(it32), "max": max(it32),
+                                                       "mean": sum(it32) / len(it32)},
+                             "last_slab_rel_diff_vs_fp64": err, "kernels": prof32}
+    # dominant tagged kernel of the FP64 march
+    if prof64:
+        name = max(prof64, key=lambda k: prof64[k]["total_ms"])
+        k = prof64[name]
+        ach = k["bytes"] / k["launches"] / (k["avg_us"] * 1e-6) / 1e9
+        out["roofline"] = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": k["bytes"] / k["launches"], "avg_launch_us": k["avg_us"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.n, args.p, args.nu, args.tol, 1.0 / args.slabs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -138,13 +138,15 @@ ah_status ah_system_export(const ah_system* s, int64_t* row_ptr, int32_t* col, d
 ah_status hdg_reconstruct(const ah_system* s, const double* lam, double* U, void* stream);
 /* Slab coupling (Section 2.4): the next slab's inflow data on its initial
  * plane is the previous slab's trace on its final plane.  For every
- * boundary facet of next's mesh lying on its initial plane whose spatial
+ * boundary facet of next_mesh lying on its initial plane whose spatial
  * vertices coincide with a final-plane facet of prev's mesh, writes that
- * trace (free DOFs lam_prev dev [n_free(prev)]) evaluated at next's facet
- * quadrature points into g_q_next dev [nbf(next)][nqf]; other rows are left
- * untouched.  The meshes may be the same object. */
+ * trace (free DOFs lam_prev dev [n_free(prev)]) evaluated at next_mesh's
+ * facet quadrature points (degree of prev) into g_q_next dev
+ * [nbf(next)][nqf]; other rows are left untouched.  next_mesh may be prev's
+ * own mesh (a slab mesh reused with shifted time data).  The pairing is
+ * computed on the host on first use and cached in next_mesh. */
 ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev,
-                                const ah_system* next, double* g_q_next, void* stream);
+                                ah_mesh* next_mesh, double* g_q_next, void* stream);
 
 /* ---------------------------------------------------------- air_setup ---
  * lAIR hierarchy on S_hat treated as a scalar matrix (Section 3; Section 4
@@ -157,7 +159,7 @@ ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev,
  * cycle operators; adjoint: also build the transposed operators. */
 typedef struct {
   double theta;        /* strength threshold, default 0.25 */
-  int max_coarse;      /* default 500 */
+  int max_coarse;      /* default 128 */
   int max_levels;      /* default 25 */
   int relax;           /* 0: F,F,C Jacobi sweeps; 1: one F sweep */
   double omega;        /* Jacobi weight, default 1 */
@@ -256,6 +258,18 @@ ah_status ah_source_gauss(int dim_st, int64_t npts, const double* X, int K, cons
 ah_status ah_source_gauss_T(int dim_st, int64_t npts, const double* X, int K,
                             const double* centers, double width, const double* y, double* dc,
                             void* stream);
+
+/* ---------------------------------------------------------- profiling ---
+ * Per-launch timing of the main kernels: when enabled, each launch of a
+ * tagged kernel is bracketed by HIP events recorded on its own stream, and
+ * its algorithmic byte count (what the operation must read and write once)
+ * is accumulated.  Tags: "element" (hdg_assemble element kernel),
+ * "spmv0" (level-0 FP64 product in FGMRES), "sweep0" / "sweep0_f32"
+ * (level-0 Jacobi sweeps), "rap0" (level-0 numeric R A P).
+ * ah_profile_read synchronizes the recorded events. */
+void ah_profile_enable(int on);
+void ah_profile_reset(void);
+ah_status ah_profile_read(const char* tag, int64_t* launches, double* total_ms, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,9 @@ SIGNATURES = {
     "hdg_assemble_grad": (i32, [vp, vp, vp, vp, vp, C.POINTER(C.c_double), vp]),
     "ah_source_gauss": (i32, [i32, i64, vp, i32, vp, dbl, vp, vp, vp]),
     "ah_source_gauss_T": (i32, [i32, i64, vp, i32, vp, dbl, vp, vp, vp]),
+    "ah_profile_enable": (None, [i32]),
+    "ah_profile_reset": (None, []),
+    "ah_profile_read": (i32, [C.c_char_p, P_i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
 
 _lib = None

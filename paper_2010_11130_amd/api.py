@@ -61,6 +61,7 @@ class Mesh:
         check(lib().ah_mesh_sizes(h, C.byref(nf), C.byref(nbf)), "ah_mesh_sizes")
         self.nf, self.nbf = nf.value, nbf.value
         self.vert = vert
+        self.kind = None
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -97,6 +98,8 @@ class System:
     """Assembled, condensed and scaled facet system (``hdg_assemble``)."""
 
     def __init__(self, mesh, p, nu, a_vert, f_q=None, g_q=None, alpha=0.0, keep=True):
+        if mesh.kind is None:
+            raise ValueError("boundary kinds not set (Mesh.set_bc)")
         self.mesh = mesh
         self.p = p
         self.nu = float(nu)
@@ -137,9 +140,10 @@ class System:
         check(lib().hdg_reconstruct(self.h, _p(lam.contiguous()), _p(U), _stream()), "hdg_reconstruct")
         return U
 
-    def inflow_from(self, prev, lam_prev, g_q):
-        """Write ``prev``'s final-plane trace into this system's inflow rows of ``g_q``."""
-        check(lib().hdg_inflow_from_trace(prev.h, _p(lam_prev.contiguous()), self.h, _p(g_q), _stream()),
+    def trace_to_inflow(self, lam, next_mesh, g_q):
+        """Write this system's final-plane trace ``lam`` into the inflow rows
+        of ``g_q`` (boundary data of ``next_mesh``)."""
+        check(lib().hdg_inflow_from_trace(self.h, _p(lam.contiguous()), next_mesh.h, _p(g_q), _stream()),
               "hdg_inflow_from_trace")
         return g_q
 

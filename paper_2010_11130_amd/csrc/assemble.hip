@@ -19,6 +19,7 @@
 // tau = nu alpha / h_K, h_K = |det J|^(1/D); grad = spatial gradient.
 #include <cmath>
 
+#include "prof.h"
 #include "system.h"
 
 namespace ah {
@@ -661,7 +662,17 @@ __global__ __launch_bounds__(64) void k_grad(ElemArgs a) {
 template <int D, int P>
 static ah_status launch_element(const ElemArgs& a, hipStream_t st) {
   if (a.ne == 0) return AH_OK;
+  using S = Sz<D, P>;
+  // algorithmic bytes per element: cell, vertices, vertex velocity, facet
+  // maps, source values in; condensed block, right-hand side and the kept
+  // element blocks out
+  const double per = (D + 1) * (4.0 + D * 8.0 + (D - 1) * 8.0 + 4.0 + D) + S::NQ * 8.0 +
+                     (S::NL * S::NL + S::NL) * 8.0 +
+                     (a.Ainv ? (S::NU * S::NU + 2.0 * S::NU * S::NL + S::NU) * 8.0 : 0.0);
+  ProfScope ps;
+  prof_begin(ps, "element", st, per * (double)a.ne);
   hipLaunchKernelGGL((k_element<D, P>), dim3(a.ne), dim3(64), 0, st, a);
+  prof_end(ps);
   AH_LAUNCHED();
   return AH_OK;
 }

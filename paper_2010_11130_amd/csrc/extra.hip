@@ -165,24 +165,23 @@ extern "C" ah_status hdg_reconstruct(const ah_system* s, const double* lam, doub
   return AH_OK;
 }
 
-extern "C" ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev, const ah_system* next,
+extern "C" ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev, ah_mesh* m,
                                            double* g_q_next, void* stream) {
-  if (!prev || !lam_prev || !next || !g_q_next) { set_error("hdg_inflow_from_trace: null argument"); return AH_EINVAL; }
-  if (prev->p != next->p || prev->D != next->D) { set_error("hdg_inflow_from_trace: p or dimension differ"); return AH_EINVAL; }
+  if (!prev || !lam_prev || !m || !g_q_next) { set_error("hdg_inflow_from_trace: null argument"); return AH_EINVAL; }
+  if (prev->D != m->D) { set_error("hdg_inflow_from_trace: dimensions differ"); return AH_EINVAL; }
   hipStream_t st = as_stream(stream);
-  ah_mesh* m = next->mesh;
   AH_TRY(mesh_pair_time_planes(m, prev->mesh, st));
   if (m->npair == 0) return AH_OK;
   FacetLattice lat{};
   std::vector<int> idx;
-  lattice(next->D - 1, next->p, idx);
-  for (int k = 0; k < next->b; ++k) {
-    int s0 = next->p;
-    for (int a = 0; a < next->D - 1; ++a) { lat.beta[k][a + 1] = (int8_t)idx[k * (next->D - 1) + a]; s0 -= idx[k * (next->D - 1) + a]; }
+  lattice(prev->D - 1, prev->p, idx);
+  for (int k = 0; k < prev->b; ++k) {
+    int s0 = prev->p;
+    for (int a = 0; a < prev->D - 1; ++a) { lat.beta[k][a + 1] = (int8_t)idx[k * (prev->D - 1) + a]; s0 -= idx[k * (prev->D - 1) + a]; }
     lat.beta[k][0] = (int8_t)s0;
   }
-  hipLaunchKernelGGL(k_inflow, dim3((unsigned)cdiv(m->npair * next->nqf, 256)), dim3(256), 0, st, m->npair, next->D,
-                     next->p, next->b, next->nqf, m->d_pair, m->d_pair_perm, next->tab.d_fac_mu,
+  hipLaunchKernelGGL(k_inflow, dim3((unsigned)cdiv(m->npair * prev->nqf, 256)), dim3(256), 0, st, m->npair, prev->D,
+                     prev->p, prev->b, prev->nqf, m->d_pair, m->d_pair_perm, prev->tab.d_fac_mu,
                      prev->mesh->d_free_rank, lam_prev, prev->d_lamD, lat, g_q_next);
   AH_LAUNCHED();
   return AH_OK;

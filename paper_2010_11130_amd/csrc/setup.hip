@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "prof.h"
 #include "system.h"
 
 namespace ah {
@@ -30,19 +31,27 @@ __device__ inline uint64_t hash44(uint64_t i, int level) {
   return x;
 }
 
-__global__ void k_strength(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const double* __restrict__ v, double theta, uint8_t* __restrict__ strong,
-                           int32_t* __restrict__ infl) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Strength of connection, 16 lanes per row: row max of the off-diagonal
+// magnitudes by a cross-lane reduction, then the marks.
+constexpr int SG = 16;
+__global__ __launch_bounds__(256) void k_strength(int64_t n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                  double theta, uint8_t* __restrict__ strong,
+                                                  int32_t* __restrict__ infl) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / SG;
+  const int g = (int)(gid % SG);
   if (i >= n) return;
+  const int64_t k0 = rp[i], k1 = rp[i + 1];
   double m = 0.0;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+  for (int64_t k = k0 + g; k < k1; k += SG)
     if (ci[k] != i) m = fmax(m, fabs(v[k]));
-  double thr = theta * m * (1.0 - 1e-12);
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-    bool s = ci[k] != i && m > 0.0 && fabs(v[k]) >= thr;
-    strong[k] = s;
-    if (s) atomicAdd(&infl[ci[k]], 1);
+  for (int o = SG / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, SG));
+  const double thr = theta * m * (1.0 - 1e-12);
+  for (int64_t k = k0 + g; k < k1; k += SG) {
+    bool sflag = ci[k] != i && m > 0.0 && fabs(v[k]) >= thr;
+    strong[k] = sflag;
+    if (sflag) atomicAdd(&infl[ci[k]], 1);
   }
 }
 
@@ -86,6 +95,14 @@ __global__ void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp, const in
   for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
     if (strong[k] && state[ci[k]] == 1) { state[i] = 2; return; }
   atomicAdd(left, 1ull);
+}
+
+__global__ void k_frows(int64_t n, const int64_t* __restrict__ rp, const int8_t* __restrict__ cf,
+                        unsigned long long* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cf[i]) return;
+  atomicAdd(&out[0], 1ull);
+  atomicAdd(&out[1], (unsigned long long)(rp[i + 1] - rp[i]));
 }
 
 __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* __restrict__ cf,
@@ -446,6 +463,75 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict
   }
 }
 
+// Inverse of a small dense matrix held in LDS (n <= 128): LU with partial
+// pivoting (largest magnitude, smallest row on ties), then one column of
+// the inverse per thread by forward and back substitution.
+constexpr int INV_LDS_MAX = 128;
+
+__global__ __launch_bounds__(1024) void k_inv_lds(int n, const double* __restrict__ M, double* __restrict__ Inv,
+                                                  int* __restrict__ err) {
+  __shared__ double A[INV_LDS_MAX * INV_LDS_MAX];
+  __shared__ int piv[INV_LDS_MAX];
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  for (int k = t; k < n * n; k += NT) A[k] = M[k];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (t < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int r = k + t; r < n; r += 64) {
+        double a = fabs(A[r * n + k]);
+        if (a > best) { best = a; bi = r; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (t == 0) {
+        piv[k] = bi;
+        if (!(best > 0.0)) atomicOr(err, 1);
+      }
+    }
+    __syncthreads();
+    const int p = piv[k];
+    if (p != k)
+      for (int c = t; c < n; c += NT) {
+        double x = A[k * n + c]; A[k * n + c] = A[p * n + c]; A[p * n + c] = x;
+      }
+    __syncthreads();
+    const double d = A[k * n + k] != 0.0 ? A[k * n + k] : 1.0;
+    for (int r = k + 1 + t; r < n; r += NT) A[r * n + k] /= d;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = t; idx < m * m; idx += NT) {
+      int r = k + 1 + idx / m, c = k + 1 + idx % m;
+      A[r * n + c] -= A[r * n + k] * A[k * n + c];
+    }
+    __syncthreads();
+  }
+  for (int j = t; j < n; j += NT) {
+    double x[INV_LDS_MAX];
+    for (int r = 0; r < n; ++r) x[r] = (r == j) ? 1.0 : 0.0;
+    for (int k = 0; k < n; ++k) {
+      int p = piv[k];
+      double tmp = x[k]; x[k] = x[p]; x[p] = tmp;
+    }
+    for (int r = 1; r < n; ++r) {
+      double v = x[r];
+      for (int k = 0; k < r; ++k) v -= A[r * n + k] * x[k];
+      x[r] = v;
+    }
+    for (int r = n - 1; r >= 0; --r) {
+      double v = x[r];
+      for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * x[k];
+      x[r] = v / A[r * n + r];
+    }
+    for (int r = 0; r < n; ++r) Inv[(int64_t)r * n + j] = x[r];
+  }
+}
+
 // CSR transpose: counts, offsets, scatter with an atomic cursor, then each
 // row sorted by column so the result does not depend on scheduling.
 __global__ void k_tcount(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -557,7 +643,7 @@ ah_hier::~ah_hier() {
 extern "C" void ah_air_defaults(ah_air_params* p) {
   if (!p) return;
   p->theta = 0.25;
-  p->max_coarse = 500;
+  p->max_coarse = 128;
   p->max_levels = 25;
   p->relax = 0;
   p->omega = 1.0;
@@ -593,6 +679,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   CK(ar.get(&d_ull, 4));
   CK(ar.get(&d_int, 4));
   CKH(hipMemsetAsync(d_ull, 0, 4 * sizeof(unsigned long long), st));
+  CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
   // level 0 = the scaled system (shared, not copied)
   AhLevel L0;
   L0.n = s->n;
@@ -622,7 +709,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(tmp.get(&strong, L.nnz));
     CK(tmp.get(&infl, n));
     CKH(hipMemsetAsync(infl, 0, n * sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_strength, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, prm.theta, strong, infl);
+    hipLaunchKernelGGL(k_strength, g1(n * SG), dim3(256), 0, st, n, L.rowptr, L.col, L.val, prm.theta, strong, infl);
     CKH(hipGetLastError());
     // PMIS
     uint64_t* key = nullptr;
@@ -659,6 +746,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(read_i64(cidx + n, &nc, st));
     if (nc == 0 || (double)nc > prm.stall * (double)n) break;
     L.nc = nc;
+    {
+      CKH(hipMemsetAsync(d_ull + 2, 0, 2 * sizeof(unsigned long long), st));
+      hipLaunchKernelGGL(k_frows, g1(n), dim3(256), 0, st, n, L.rowptr, L.cf, d_ull + 2);
+      CKH(hipGetLastError());
+      unsigned long long fr[2];
+      CKH(hipMemcpyAsync(fr, d_ull + 2, sizeof(fr), hipMemcpyDeviceToHost, st));
+      CKH(hipStreamSynchronize(st));
+      L.nF = (int64_t)fr[0];
+      L.nnzF = (int64_t)fr[1];
+    }
     // one-point P and lAIR row lengths
     int32_t *rcnt = nullptr, *clist = nullptr;
     CK(ar.get(&L.pcol, n));
@@ -708,7 +805,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(read_i64(C.rowptr + nc, &C.nnz, st));
     CK(ar.get(&C.col, C.nnz));
     CK(ar.get(&C.val, C.nnz));
-    CK(rap_dispatch(hs, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
+    {
+      ProfScope ps;
+      // algorithmic bytes of the numeric product: R once, the A rows it
+      // touches (bounded by the candidate count), P columns, A_c written
+      double by = (double)L.nnzR * 12.0 + (double)(nc + 1) * 8.0 + (double)C.nnz * 12.0 + (double)(nc + 1) * 8.0 +
+                  (double)L.nnz * 12.0 + (double)n * 4.0;
+      prof_begin(ps, l == 0 ? "rap0" : nullptr, st, by);
+      CK(rap_dispatch(hs, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
+      prof_end(ps);
+    }
     if (prm.fp32_cycle) {
       CK(ar.get(&L.Rval32, L.nnzR));
       hipLaunchKernelGGL(k_cast32, g1(L.nnzR), dim3(256), 0, st, L.nnzR, L.Rval, L.Rval32);
@@ -757,7 +863,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CKH(hipMemsetAsync(M, 0, nL * nL * sizeof(double), st));
     hipLaunchKernelGGL(k_dense, g1(nL), dim3(256), 0, st, nL, LL.rowptr, LL.col, LL.val, M);
     CKH(hipMemsetAsync(d_int + 2, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
+    if (nL <= INV_LDS_MAX)
+      hipLaunchKernelGGL(k_inv_lds, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
+    else
+      hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
     CKH(hipGetLastError());
   }
   if (prm.adjoint && !h->lev[0].ATptr) {

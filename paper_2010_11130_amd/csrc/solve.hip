@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "prof.h"
 #include "system.h"
 
 namespace ah {
@@ -184,8 +185,11 @@ static int pick_g(int64_t nnz, int64_t n) {
 
 template <class TA, class TX, class TY, int MODE>
 static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, const TA* av, const TX* x, const TY* b,
-                       const TY* d, const int8_t* cf, int X, TY omega, TY* y, hipStream_t st) {
+                       const TY* d, const int8_t* cf, int X, TY omega, TY* y, hipStream_t st,
+                       const char* tag = nullptr, double bytes = 0.0) {
   if (n == 0) return AH_OK;
+  ProfScope ps;
+  prof_begin(ps, tag, st, bytes);
   dim3 grid((unsigned)cdiv(n * G, 256));
   switch (G) {
     case 4: hipLaunchKernelGGL((k_csr<TA, TX, TY, 4, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
@@ -193,8 +197,19 @@ static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, c
     case 16: hipLaunchKernelGGL((k_csr<TA, TX, TY, 16, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
     default: hipLaunchKernelGGL((k_csr<TA, TX, TY, 32, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
   }
+  prof_end(ps);
   AH_LAUNCHED();
   return AH_OK;
+}
+
+// Algorithmic bytes of a Jacobi sweep on the point set X of level L: the X
+// rows of A once, x once, b and d on X, the X updates written.
+template <class T>
+static double sweep_bytes(const AhLevel& L, int X) {
+  const double w = sizeof(T);
+  const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
+  const int64_t nnzX = X == 0 ? L.nnzF : L.nnz - L.nnzF;
+  return (double)nnzX * (w + 4.0) + (double)(nX + 1) * 8.0 + (double)L.n * w + (double)nX * 3.0 * w;
 }
 
 // ------------------------------------------------------------ V-cycles
@@ -252,8 +267,9 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   const T om = (T)h->prm.omega;
   for (int s = 0; s < nsw; ++s) {
     T* dst = (s == nsw - 1) ? out : alt;
+    const char* tag = l == 0 ? (sizeof(T) == 8 ? "sweep0" : "sweep0_f32") : nullptr;
     AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, sets_ffc[s], om,
-                                     dst, st)));
+                                     dst, st, tag, sweep_bytes<T>(L, sets_ffc[s]))));
     alt = cur;
     cur = dst;
   }
@@ -403,12 +419,18 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       float* zj32 = h->Z32 ? h->Z32 + (int64_t)j * n : nullptr;
       AH_TRY(precond(h, vj, prm.precision == 0 ? zj : nullptr, prm.precision == 1 ? zj32 : nullptr, prm.precision,
                      transpose, st));
+      const int64_t nnz0 = h->lev[0].nnz;
+      // algorithmic bytes: matrix once (8 B value + 4 B column), row offsets, x once, y written
+      const double by = (double)nnz0 * 12.0 + (double)(n + 1) * 8.0 + (double)n * (prm.precision ? 4.0 : 8.0) +
+                        (double)n * 8.0;
       if (prm.precision == 0)
         AH_TRY((csr_g<double, double, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj, (const double*)nullptr,
-                                                     (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st)));
+                                                     (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st,
+                                                     transpose ? nullptr : "spmv0", by)));
       else
         AH_TRY((csr_g<double, float, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj32, (const double*)nullptr,
-                                                    (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st)));
+                                                    (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st,
+                                                    transpose ? nullptr : "spmv0", by)));
       ++its;
       const int k = j + 1;
       // CGS2
@@ -512,6 +534,10 @@ static ah_status check_solve(const ah_hier* h, const ah_solve_params* prm, int t
 extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, const ah_solve_params* prm,
                                void* stream, ah_solve_info* info) {
   AH_TRY(check_solve(hc, prm, 0));
+  if (hc->sys->n == 0) {   // nothing to solve
+    if (info) { std::memset(info, 0, sizeof(*info)); info->converged = 1; }
+    return AH_OK;
+  }
   if (!x) { set_error("air_solve: null x"); return AH_EINVAL; }
   ah_hier* h = const_cast<ah_hier*>(hc);
   hipStream_t st = as_stream(stream);
@@ -532,6 +558,10 @@ extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, 
 extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, double* lam, const ah_solve_params* prm,
                                        void* stream, ah_solve_info* info) {
   AH_TRY(check_solve(hc, prm, 1));
+  if (hc->sys->n == 0) {
+    if (info) { std::memset(info, 0, sizeof(*info)); info->converged = 1; }
+    return AH_OK;
+  }
   if (!g || !lam) { set_error("air_solve_adjoint: null argument"); return AH_EINVAL; }
   ah_hier* h = const_cast<ah_hier*>(hc);
   hipStream_t st = as_stream(stream);

@@ -55,6 +55,7 @@ struct AhLevel {
   float* diag32 = nullptr;
   // coarsening (all but the coarsest level)
   int64_t nc = 0;
+  int64_t nF = 0, nnzF = 0;    // F rows and their stored entries
   int8_t* cf = nullptr;        // 1 = C, 0 = F
   int32_t* pcol = nullptr;     // one-point interpolation: coarse column or -1
   int64_t nnzR = 0;

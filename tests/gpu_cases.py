@@ -24,7 +24,7 @@ def case(name):
     if name == "slab_nu0":
         v, c = slab_prism_tet_mesh(8, 1.0 / 64)
         return v, c, slab_hill(0.0), 2
-    if name.startswith("kuhn"):
+    if name in ("kuhn_nu0", "kuhn_nu4", "kuhn_nu2"):
         nu = {"kuhn_nu0": 0.0, "kuhn_nu4": 1e-4, "kuhn_nu2": 1e-2}[name]
         v, c = kuhn_cube_mesh(6)
         return v, c, SmoothPlusFront(nu, width=0.1), 1

@@ -186,3 +186,69 @@ def test_adjoint_and_gradients_c5(built):
     xe, _ = g.mesh.quad_points(g.p)
     dc = source_gauss_T(xe.reshape(-1, 3), prob.centers, prob.width, dq.reshape(-1)).cpu().numpy()
     assert np.abs(dc - dc_o).max() <= 1e-8 * np.abs(dc_o).max()
+
+
+def _gpu_march(mesh_fn, slabs, prob, p, tol=1e-12, same_mesh=False, dt=None):
+    """Slab march on the HIP path: per slab assemble (inflow = previous trace),
+    set up, solve."""
+    from paper_2010_11130_amd import Mesh, System, Hierarchy
+    from gpu_cases import boundary_data, kinds_for
+    lams = []
+    prev = None
+    mesh0 = None
+    for k in range(slabs):
+        if same_mesh and mesh0 is not None:
+            m, v, fv, bf, kinds, xb0 = mesh0
+        else:
+            v, c = mesh_fn(k)
+            m = Mesh(v, c)
+            fv, _ = m.facets()
+            bf = m.boundary_facets()
+            isb = np.zeros(m.nf, dtype=bool)
+            isb[bf] = True
+            kinds = kinds_for(v, fv, isb)
+            m.set_bc(kinds)
+            _, xb0 = m.quad_points(p)
+            mesh0 = (m, v, fv, bf, kinds, xb0)
+        xb = xb0.clone()
+        if same_mesh:
+            xb[..., 0] += k * dt
+            vs = v.copy()
+            vs[:, 0] += k * dt
+        else:
+            vs = v
+        g = boundary_data(prob, vs, fv, bf, kinds, xb)
+        if prev is not None:
+            prev[0].trace_to_inflow(prev[1], m, g)
+        a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(vs)), device="cuda")
+        s = System(m, p, prob.nu, a, None, g)
+        H = Hierarchy(s, max_coarse=SMALL_COARSE)
+        x, info = H.solve(tol=tol)
+        assert info["converged"]
+        lams.append(x.cpu().numpy())
+        prev = (s, x)
+    return lams
+
+
+def test_slab_march_parity_fixed_mesh():
+    from workloads import slab_prism_tet_mesh
+    from workloads.problems import slab_hill
+    from oracle.drivers import solve_slabs
+    n, S, p, dt = 8, 4, 2, 1.0 / 64
+    prob = slab_hill(1e-4)
+    lg = _gpu_march(lambda k: slab_prism_tet_mesh(n, dt), S, prob, p, same_mesh=True, dt=dt)
+    _, _, lo = solve_slabs(lambda k: slab_prism_tet_mesh(n, dt, t0=k * dt), S, prob, p, err=False)
+    for k in range(S):
+        assert np.linalg.norm(lg[k] - lo[k]) <= 1e-10 * np.linalg.norm(lo[k]), k
+
+
+def test_slab_march_parity_moving_mesh():
+    from workloads import pulse_slab_mesh
+    from workloads.problems import paper_pulse
+    from oracle.drivers import solve_slabs
+    N, S, p = 4, 3, 2
+    prob = paper_pulse(1e-2)
+    lg = _gpu_march(lambda k: pulse_slab_mesh(N, k), S, prob, p)
+    _, _, lo = solve_slabs(lambda k: pulse_slab_mesh(N, k), S, prob, p, err=False)
+    for k in range(S):
+        assert np.linalg.norm(lg[k] - lo[k]) <= 1e-10 * np.linalg.norm(lo[k]), k
