@@ -41,7 +41,77 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 10 times (HBM counter calibration)")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="only summarize the rocprofv3 CSV output found under DIR")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="with --profile-summary: keep only dispatches of this grid size in counters")
     return ap.parse_args()
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    return hits[0] if hits else None
+
+
+def profile_summary(d, grid=0, top=25):
+    """Compact text summary of rocprofv3 --output-format csv results."""
+    import csv
+    from collections import defaultdict
+
+    def key(row, *names):
+        for n in names:
+            if n in row:
+                return row[n]
+        return None
+    ks = _find(d, "kernel_stats.csv")
+    if ks:
+        rows = list(csv.DictReader(open(ks)))
+        tot = sum(float(key(r, "TotalDurationNs")) for r in rows)
+        print("kernel stats: %s (total %.3f ms)" % (os.path.basename(ks), tot / 1e6))
+        print("%-12s %8s %12s %10s  %s" % ("total_ms", "calls", "avg_us", "pct", "kernel"))
+        for r in sorted(rows, key=lambda r: -float(key(r, "TotalDurationNs")))[:top]:
+            print("%-12.3f %8s %12.2f %9.2f%%  %s" % (float(key(r, "TotalDurationNs")) / 1e6, key(r, "Calls"),
+                                                       float(key(r, "AverageNs")) / 1e3,
+                                                       float(key(r, "Percentage")), key(r, "Name")[:110]))
+    api = _find(d, "hip_api_stats.csv")
+    if api:
+        rows = list(csv.DictReader(open(api)))
+        print("HIP API stats: %s" % os.path.basename(api))
+        for r in sorted(rows, key=lambda r: -float(key(r, "TotalDurationNs")))[:top]:
+            print("%-12.3f %8s %12.2f  %s" % (float(key(r, "TotalDurationNs")) / 1e6, key(r, "Calls"),
+                                              float(key(r, "AverageNs")) / 1e3, key(r, "Name")))
+    cc = _find(d, "counter_collection.csv")
+    if cc:
+        acc = defaultdict(lambda: [0, 0.0])
+        for r in csv.DictReader(open(cc)):
+            g = int(float(key(r, "Grid_Size", "Grid_Size_X") or 0))
+            if grid and g != grid:
+                continue
+            name = key(r, "Kernel_Name")
+            cn = key(r, "Counter_Name")
+            a = acc[(name, cn, g)]
+            a[0] += 1
+            a[1] += float(key(r, "Counter_Value"))
+        print("counters: %s%s" % (os.path.basename(cc), " (grid %d)" % grid if grid else ""))
+        print("%-14s %8s %16s %10s  %s" % ("counter", "disp", "mean_per_disp", "grid", "kernel"))
+        for (name, cn, g), (n, v) in sorted(acc.items(), key=lambda t: -t[1][1])[:top]:
+            print("%-14s %8d %16.1f %10d  %s" % (cn, n, v / n, g, name[:100]))
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters of the profiled kernels."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 10}))
 
 
 class March:
@@ -175,7 +245,13 @@ def main():
         print("bench.py: this build measures one GPU only (--gpus %d requested); the path has no "
               "multi-GPU sharding" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.profile_summary:
+        profile_summary(args.profile_summary, args.grid)
+        return
     import torch
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     from paper_2010_11130_amd import lib
     lib()
     if not torch.cuda.is_available():

@@ -159,7 +159,7 @@ ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev,
  * cycle operators; adjoint: also build the transposed operators. */
 typedef struct {
   double theta;        /* strength threshold, default 0.25 */
-  int max_coarse;      /* default 128 */
+  int max_coarse;      /* default 64 */
   int max_levels;      /* default 25 */
   int relax;           /* 0: F,F,C Jacobi sweeps; 1: one F sweep */
   double omega;        /* Jacobi weight, default 1 */

@@ -190,7 +190,7 @@ class Hierarchy:
     pass
 
 
-def setup(A0, theta=0.25, max_coarse=128, max_levels=25, relax="FFC", omega=1.0,
+def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
           stall=0.9, max_dense=8192):
     """Build the lAIR hierarchy on the scaled matrix (treated as scalar)."""
     H = Hierarchy()

@@ -904,11 +904,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   if ((rc = element_dispatch(m->D, prm->p, a, st))) return fail(rc);
   if ((rc = scale_dispatch(t.b, s, m, st, d_err))) return fail(rc);
   int herr = 0;
-  if (hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    set_error("hdg_assemble: %s", hipGetErrorString(hipGetLastError()));
-    return fail(AH_EHIP);
-  }
+  if ((rc = read_bytes(d_err, &herr, sizeof(int), st))) return fail(rc);
   if (herr) {
     set_error("hdg_assemble: singular %s", (herr & 4) ? "facet diagonal block (characteristic facet at nu = 0?)"
                                                       : (herr & 2) ? "element (degenerate cell)" : "element block A_K");

@@ -36,9 +36,14 @@ const char* g_last_error_cstr();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Stream-ordered device allocation owned by a library object.
+// Stream-ordered device memory owned by a library object: requests are
+// carved (256-byte aligned) out of chunks of at least CHUNK bytes, so an
+// object makes a handful of allocation calls instead of one per buffer.
 struct Arena {
+  static constexpr size_t CHUNK = size_t(32) << 20;
   std::vector<void*> ptrs;
+  char* cur = nullptr;
+  size_t left = 0;
   hipStream_t stream = nullptr;
   ah_status alloc(void** p, size_t bytes);
   template <class T>
@@ -47,6 +52,10 @@ struct Arena {
   }
   void release();
 };
+
+// Process-wide pinned host staging buffer (grown on demand, never freed)
+// for small device-to-host reads.
+double* pinned_scratch(size_t doubles);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

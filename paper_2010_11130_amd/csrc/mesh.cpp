@@ -28,19 +28,48 @@ void set_error(const char* fmt, ...) {
 
 ah_status Arena::alloc(void** p, size_t bytes) {
   *p = nullptr;
-  if (bytes == 0) bytes = 16;
-  hipError_t e = hipMallocAsync(p, bytes, stream);
-  if (e != hipSuccess) {
-    set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-    return AH_ENOMEM;
+  bytes = (std::max<size_t>(bytes, 16) + 255) & ~size_t(255);
+  if (bytes > left) {
+    size_t want = std::max(bytes, CHUNK);
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, want, stream);
+    if (e != hipSuccess) {
+      set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+      return AH_ENOMEM;
+    }
+    ptrs.push_back(q);
+    if (want > CHUNK) {          // dedicated chunk for a large buffer
+      *p = q;
+      return AH_OK;
+    }
+    cur = static_cast<char*>(q);
+    left = want;
   }
-  ptrs.push_back(*p);
+  *p = cur;
+  cur += bytes;
+  left -= bytes;
   return AH_OK;
 }
 
 void Arena::release() {
   for (void* p : ptrs) (void)hipFreeAsync(p, stream);
   ptrs.clear();
+  cur = nullptr;
+  left = 0;
+}
+
+double* pinned_scratch(size_t doubles) {
+  static thread_local double* buf = nullptr;
+  static thread_local size_t cap = 0;
+  if (doubles > cap) {
+    size_t want = std::max<size_t>(doubles, 8192);
+    double* nb = nullptr;
+    if (hipHostMalloc((void**)&nb, want * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+    // the previous buffer is kept: a caller may still hold it
+    buf = nb;
+    cap = want;
+  }
+  return buf;
 }
 
 // ------------------------------------------------------------ quadrature

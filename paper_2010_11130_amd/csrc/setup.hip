@@ -80,11 +80,16 @@ __global__ void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp, const in
   if (mx) atomicMax(&nbmax[i], mx);
 }
 
-__global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, const unsigned long long* __restrict__ nbmax,
-                              int8_t* __restrict__ state) {
+// New C points: undecided points whose key beats every undecided neighbour.
+// nbmax is reset for the next round (only undecided points carry a value),
+// and the round's undecided counter is cleared.
+__global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsigned long long* __restrict__ nbmax,
+                              int8_t* __restrict__ state, unsigned long long* __restrict__ left) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *left = 0;
   if (i >= n || state[i] != 0) return;
   if (key[i] > nbmax[i]) state[i] = 1;
+  nbmax[i] = 0;
 }
 
 __global__ void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -97,14 +102,6 @@ __global__ void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp, const in
   atomicAdd(left, 1ull);
 }
 
-__global__ void k_frows(int64_t n, const int64_t* __restrict__ rp, const int8_t* __restrict__ cf,
-                        unsigned long long* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || cf[i]) return;
-  atomicAdd(&out[0], 1ull);
-  atomicAdd(&out[1], (unsigned long long)(rp[i + 1] - rp[i]));
-}
-
 __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* __restrict__ cf,
                            int32_t* __restrict__ isc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,24 +111,34 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
   isc[i] = c;
 }
 
-// One-point interpolation and, for C points, the lAIR row length 1 + |N_i|.
+// One-point interpolation; for C points the lAIR row length 1 + |N_i| and
+// the number of R A P candidates of its coarse row (row lengths of A over
+// {i} and N_i); for F points the F-row statistics (count, entries).
+// imax[0] = max |N_i|, imax[1] = max candidates; fst[0..1] = F rows, entries.
 __global__ void k_onepoint(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const double* __restrict__ v, const uint8_t* __restrict__ strong,
                            const int8_t* __restrict__ cf, const int64_t* __restrict__ cidx,
                            int32_t* __restrict__ pcol, int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
-                           int* __restrict__ maxm) {
+                           int* __restrict__ imax, unsigned long long* __restrict__ fst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (cf[i]) {
     pcol[i] = (int32_t)cidx[i];
     int m = 0;
+    int64_t cand = rp[i + 1] - rp[i];
     for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (strong[k] && !cf[ci[k]]) ++m;
+      if (strong[k] && !cf[ci[k]]) {
+        ++m;
+        cand += rp[ci[k] + 1] - rp[ci[k]];
+      }
     rcnt[cidx[i]] = 1 + m;
     clist[cidx[i]] = (int32_t)i;
-    atomicMax(maxm, m);
+    atomicMax(&imax[0], m);
+    atomicMax(&imax[1], cand > 0x3fffffff ? 0x3fffffff : (int)cand);
     return;
   }
+  atomicAdd(&fst[0], 1ull);
+  atomicAdd(&fst[1], (unsigned long long)(rp[i + 1] - rp[i]));
   double mx = 0.0;
   bool any = false;
   for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -267,21 +274,6 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
     Rval[out + ins] = 1.0;
     if (bad) atomicAdd(nfall, 1ull);
   }
-}
-
-// Upper bound of the entries of each coarse row of R A P.
-__global__ void k_rap_cand(int64_t nc, const int64_t* __restrict__ Rptr, const int32_t* __restrict__ Rcol,
-                           const int64_t* __restrict__ rp, int32_t* __restrict__ cand, int* __restrict__ maxcand) {
-  int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ic >= nc) return;
-  int64_t c = 0;
-  for (int64_t k = Rptr[ic]; k < Rptr[ic + 1]; ++k) {
-    int32_t j = Rcol[k];
-    c += rp[j + 1] - rp[j];
-  }
-  int cc = c > 0x3fffffff ? 0x3fffffff : (int)c;
-  cand[ic] = cc;
-  atomicMax(maxcand, cc);
 }
 
 // R A P per coarse row with an LDS open-addressing hash on the coarse
@@ -463,6 +455,63 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict
   }
 }
 
+// Inverse of a dense matrix of order n <= 64 by Gauss-Jordan elimination
+// with partial pivoting on the augmented matrix [A | I], held entirely in
+// LDS (64 x 128 doubles).
+constexpr int INV_GJ_MAX = 64;
+
+__global__ __launch_bounds__(256) void k_inv_gj(int n, const double* __restrict__ M, double* __restrict__ Inv,
+                                                int* __restrict__ err) {
+  __shared__ double A[INV_GJ_MAX * 2 * INV_GJ_MAX];
+  __shared__ double f[INV_GJ_MAX];
+  __shared__ int s_p;
+  const int t = threadIdx.x;
+  const int W = 2 * n;
+  for (int idx = t; idx < n * W; idx += blockDim.x) {
+    int r = idx / W, c = idx % W;
+    A[idx] = c < n ? M[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (t < 64) {
+      double best = -1.0;
+      int bi = n;
+      int r = k + t;
+      if (r < n) { best = fabs(A[r * W + k]); bi = r; }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (t == 0) {
+        s_p = bi;
+        if (!(best > 0.0)) atomicOr(err, 1);
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != k)
+      for (int c = t; c < W; c += blockDim.x) {
+        double x = A[k * W + c]; A[k * W + c] = A[p * W + c]; A[p * W + c] = x;
+      }
+    __syncthreads();
+    const double d = A[k * W + k] != 0.0 ? A[k * W + k] : 1.0;
+    if (t < n) f[t] = t == k ? 0.0 : A[t * W + k];
+    __syncthreads();
+    for (int c = t; c < W; c += blockDim.x) A[k * W + c] /= d;
+    __syncthreads();
+    for (int idx = t; idx < n * W; idx += blockDim.x) {
+      int r = idx / W, c = idx % W;
+      if (r != k) A[idx] -= f[r] * A[k * W + c];
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < n * n; idx += blockDim.x) {
+    int r = idx / n, c = idx % n;
+    Inv[idx] = A[r * W + n + c];
+  }
+}
+
 // Inverse of a small dense matrix held in LDS (n <= 128): LU with partial
 // pivoting (largest magnitude, smallest row on ties), then one column of
 // the inverse per thread by forward and back substitution.
@@ -635,15 +684,12 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
 
 using namespace ah;
 
-ah_hier::~ah_hier() {
-  arena.release();
-  if (hhost) (void)hipHostFree(hhost);
-}
+ah_hier::~ah_hier() { arena.release(); }
 
 extern "C" void ah_air_defaults(ah_air_params* p) {
   if (!p) return;
   p->theta = 0.25;
-  p->max_coarse = 128;
+  p->max_coarse = 64;
   p->max_levels = 25;
   p->relax = 0;
   p->omega = 1.0;
@@ -674,10 +720,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   ah_status rc = AH_OK;
 #define CK(x) do { rc = (x); if (rc < 0) { tmp.release(); delete h; return rc; } } while (0)
 #define CKH(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error("air_setup: %s", hipGetErrorString(e_)); tmp.release(); delete h; return AH_EHIP; } } while (0)
-  unsigned long long* d_ull = nullptr;   // [0] undecided count, [1] lAIR fallbacks
+  unsigned long long* d_ull = nullptr;   // [0..1] undecided counts (alternating rounds), [2] lAIR fallbacks
   int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error
+  unsigned long long* d_fst = nullptr;   // per level: F rows, F-row entries
   CK(ar.get(&d_ull, 4));
   CK(ar.get(&d_int, 4));
+  CK(ar.get(&d_fst, 64));
+  CKH(hipMemsetAsync(d_fst, 0, 64 * sizeof(unsigned long long), st));
   CKH(hipMemsetAsync(d_ull, 0, 4 * sizeof(unsigned long long), st));
   CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
   // level 0 = the scaled system (shared, not copied)
@@ -720,17 +769,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(tmp.get(&state, n));
     hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, l, key, state);
     CKH(hipGetLastError());
+    CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
     for (int round = 0;; ++round) {
       if (round > 10000) { set_error("air_setup: PMIS did not terminate"); tmp.release(); delete h; return AH_EINVAL; }
-      CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
-      CKH(hipMemsetAsync(d_ull, 0, sizeof(unsigned long long), st));
+      unsigned long long* left_d = d_ull + (round & 1);
       hipLaunchKernelGGL(k_pmis_nbmax, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
-      hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state);
-      hipLaunchKernelGGL(k_pmis_fmark, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, d_ull);
+      hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d);
+      hipLaunchKernelGGL(k_pmis_fmark, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, left_d);
       CKH(hipGetLastError());
       unsigned long long left = 0;
-      CKH(hipMemcpyAsync(&left, d_ull, sizeof(left), hipMemcpyDeviceToHost, st));
-      CKH(hipStreamSynchronize(st));
+      CK(read_bytes(left_d, &left, sizeof(left), st));
       if (left == 0) break;
     }
     // coarse numbering
@@ -746,54 +794,43 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(read_i64(cidx + n, &nc, st));
     if (nc == 0 || (double)nc > prm.stall * (double)n) break;
     L.nc = nc;
-    {
-      CKH(hipMemsetAsync(d_ull + 2, 0, 2 * sizeof(unsigned long long), st));
-      hipLaunchKernelGGL(k_frows, g1(n), dim3(256), 0, st, n, L.rowptr, L.cf, d_ull + 2);
-      CKH(hipGetLastError());
-      unsigned long long fr[2];
-      CKH(hipMemcpyAsync(fr, d_ull + 2, sizeof(fr), hipMemcpyDeviceToHost, st));
-      CKH(hipStreamSynchronize(st));
-      L.nF = (int64_t)fr[0];
-      L.nnzF = (int64_t)fr[1];
-    }
-    // one-point P and lAIR row lengths
+    // one-point P, lAIR row lengths, R A P candidate bound, F-row statistics
     int32_t *rcnt = nullptr, *clist = nullptr;
     CK(ar.get(&L.pcol, n));
     CK(tmp.get(&rcnt, nc + 1));
     CK(tmp.get(&clist, nc));
     CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
     hipLaunchKernelGGL(k_onepoint, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
-                       rcnt, clist, d_int);
+                       rcnt, clist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
     CK(ar.get(&L.Rptr, nc + 1));
     CK(scan_i32_to_i64(rcnt, L.Rptr, nc, st, tmp));
-    CK(read_i64(L.Rptr + nc, &L.nnzR, st));
     int hmax[4];
-    CKH(hipMemcpyAsync(hmax, d_int, sizeof(hmax), hipMemcpyDeviceToHost, st));
-    CKH(hipStreamSynchronize(st));
+    {
+      double* pin = pinned_scratch(4);
+      if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
+      CKH(hipMemcpyAsync(pin, L.Rptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(pin + 1, d_int, sizeof(hmax), hipMemcpyDeviceToHost, st));
+      CKH(hipStreamSynchronize(st));
+      std::memcpy(&L.nnzR, pin, sizeof(int64_t));
+      std::memcpy(hmax, pin + 1, sizeof(hmax));
+    }
     CK(ar.get(&L.Rcol, L.nnzR));
     CK(ar.get(&L.Rval, L.nnzR));
     const int maxm = hmax[0];
     if (maxm <= 32)
       hipLaunchKernelGGL(k_lair<32>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 1);
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
     else if (maxm <= 64)
       hipLaunchKernelGGL(k_lair<64>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 1);
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
     else {
       set_error("air_setup: lAIR neighbourhood of %d points exceeds 64", maxm);
       tmp.release(); delete h; return AH_EUNSUPPORTED;
     }
     CKH(hipGetLastError());
     // R A P
-    int32_t* cand = nullptr;
-    CK(tmp.get(&cand, nc));
-    CKH(hipMemsetAsync(d_int + 1, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_rap_cand, g1(nc), dim3(256), 0, st, nc, L.Rptr, L.Rcol, L.rowptr, cand, d_int + 1);
-    CKH(hipGetLastError());
-    int maxcand = 0;
-    CKH(hipMemcpyAsync(&maxcand, d_int + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-    CKH(hipStreamSynchronize(st));
+    const int maxcand = hmax[1];
     int hs = maxcand < 256 ? 256 : maxcand < 1024 ? 1024 : maxcand < 2048 ? 2048 : maxcand < 4096 ? 4096 : -1;
     AhLevel C;
     C.n = nc;
@@ -863,7 +900,9 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CKH(hipMemsetAsync(M, 0, nL * nL * sizeof(double), st));
     hipLaunchKernelGGL(k_dense, g1(nL), dim3(256), 0, st, nL, LL.rowptr, LL.col, LL.val, M);
     CKH(hipMemsetAsync(d_int + 2, 0, sizeof(int), st));
-    if (nL <= INV_LDS_MAX)
+    if (nL <= INV_GJ_MAX)
+      hipLaunchKernelGGL(k_inv_gj, dim3(1), dim3(256), 0, st, (int)nL, M, h->cinv, d_int + 2);
+    else if (nL <= INV_LDS_MAX)
       hipLaunchKernelGGL(k_inv_lds, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
     else
       hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
@@ -876,9 +915,22 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   }
   unsigned long long fb = 0;
   int gerr = 0;
-  CKH(hipMemcpyAsync(&fb, d_ull + 1, sizeof(fb), hipMemcpyDeviceToHost, st));
-  CKH(hipMemcpyAsync(&gerr, d_int + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-  CKH(hipStreamSynchronize(st));
+  {
+    double* pin = pinned_scratch(70);
+    if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
+    CKH(hipMemcpyAsync(pin, d_ull + 2, sizeof(fb), hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(pin + 1, d_int + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(pin + 2, d_fst, 64 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    std::memcpy(&fb, pin, sizeof(fb));
+    std::memcpy(&gerr, pin + 1, sizeof(int));
+    unsigned long long fst[64];
+    std::memcpy(fst, pin + 2, sizeof(fst));
+    for (size_t l = 0; l + 1 < h->lev.size() && l < 32; ++l) {
+      h->lev[l].nF = (int64_t)fst[2 * l];
+      h->lev[l].nnzF = (int64_t)fst[2 * l + 1];
+    }
+  }
   tmp.release();
   if (gerr) {
     set_error("air_setup: singular coarsest matrix");

@@ -341,8 +341,6 @@ static ah_status ensure_workspace(ah_hier* h, int m, int precision) {
     AH_TRY(ar.get(&h->bhat, n));
     AH_TRY(ar.get(&h->partial, (int64_t)(m + 3) * 1024));
     AH_TRY(ar.get(&h->hdev, 4 * (m + 3)));
-    if (h->hhost) (void)hipHostFree(h->hhost);
-    AH_HIP(hipHostMalloc((void**)&h->hhost, 4 * (m + 3) * sizeof(double), hipHostMallocDefault));
     h->Z = nullptr;
     h->Z32 = nullptr;
     h->m_alloc = m;
@@ -377,7 +375,8 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
   AH_TRY(ensure_workspace(h, m, prm.precision));
   const int G0 = pick_g(h->lev[0].nnz, n);
   double* hd = h->hdev;
-  double* hh = h->hhost;
+  double* hh = pinned_scratch(4 * (m + 3));
+  if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
   auto t0 = std::chrono::steady_clock::now();
   // ||b||
   AH_TRY(multidot(n, 0, h->V, bvec, h->partial, hd, st));

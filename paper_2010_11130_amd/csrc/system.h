@@ -37,8 +37,10 @@ namespace ah {
 ah_status scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
 // Same for int32 counts producing int64 offsets.
 ah_status scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
-// Read one int64 from the device (synchronizes the stream).
+// Read one int64 / a few bytes from the device through the pinned staging
+// buffer (synchronizes the stream).
 ah_status read_i64(const int64_t* d, int64_t* h, hipStream_t st);
+ah_status read_bytes(const void* d, void* h, size_t bytes, hipStream_t st);
 
 constexpr int WAVE = 64;
 
@@ -99,7 +101,6 @@ struct ah_hier {
   double* r = nullptr;
   double* bhat = nullptr;
   double* partial = nullptr;   // reduction partials
-  double* hdev = nullptr;      // [2 (m+2)] device scalars
-  double* hhost = nullptr;     // pinned host mirror
+  double* hdev = nullptr;      // [4 (m+3)] device scalars
   ~ah_hier();
 };

@@ -1,5 +1,7 @@
 // Device utilities: exclusive prefix sums used to turn per-row counts into
 // CSR offsets.
+#include <cstring>
+
 #include "system.h"
 
 namespace ah {
@@ -84,8 +86,20 @@ ah_status scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_
 }
 
 ah_status read_i64(const int64_t* d, int64_t* h, hipStream_t st) {
-  AH_HIP(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  double* pin = pinned_scratch(1);
+  if (!pin) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  AH_HIP(hipMemcpyAsync(pin, d, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   AH_HIP(hipStreamSynchronize(st));
+  std::memcpy(h, pin, sizeof(int64_t));
+  return AH_OK;
+}
+
+ah_status read_bytes(const void* d, void* h, size_t bytes, hipStream_t st) {
+  double* pin = pinned_scratch((bytes + 7) / 8);
+  if (!pin) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  AH_HIP(hipMemcpyAsync(pin, d, bytes, hipMemcpyDeviceToHost, st));
+  AH_HIP(hipStreamSynchronize(st));
+  std::memcpy(h, pin, bytes);
   return AH_OK;
 }
 

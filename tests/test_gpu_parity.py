@@ -252,3 +252,21 @@ def test_slab_march_parity_moving_mesh():
     _, _, lo = solve_slabs(lambda k: pulse_slab_mesh(N, k), S, prob, p, err=False)
     for k in range(S):
         assert np.linalg.norm(lg[k] - lo[k]) <= 1e-10 * np.linalg.norm(lo[k]), k
+
+
+@pytest.mark.parametrize("max_coarse", [40, 100, 200])
+def test_coarsest_solver_paths(max_coarse):
+    """The coarsest level is inverted by Gauss-Jordan in LDS (n <= 64), LU in
+    LDS (n <= 128) or in global memory; each path against the oracle."""
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("slab")
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=max_coarse)
+    OH = oair.setup(o.Shat, max_coarse=max_coarse)
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    print("coarsest", H.info["n"][-1], flush=True)
+    r = np.random.default_rng(2).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
