@@ -93,17 +93,27 @@ struct ElemSmem {
   double F[S::NU];
   double G[S::NL];
   double LD[S::NL];
-  double q_phi[S::QC * S::NU];
-  double q_adv[S::QC * S::NU];
-  double q_gx[S::QC * S::NU * (D - 1)];
-  double q_W[S::QC];
-  double q_f[S::QC];
-  double f_phi[S::NQF * S::NU];
-  double f_dn[S::NQF * S::NU];
-  double f_cA[S::NQF], f_cB[S::NQF], f_cD[S::NQF], f_W[S::NQF], f_g[S::NQF];
-  double Xs[S::NU * S::NR];
-  double Sk[S::NL * S::NL];
-  double Hk[S::NL];
+  // quadrature scratch (integration phase) and condensation arrays (after
+  // the factorization) share storage
+  struct Quad {
+    double q_phi[S::QC * S::NU];
+    double q_adv[S::QC * S::NU];
+    double q_gx[S::QC * S::NU * (D - 1)];
+    double q_W[S::QC];
+    double q_f[S::QC];
+    double f_phi[S::NQF * S::NU];
+    double f_dn[S::NQF * S::NU];
+    double f_cA[S::NQF], f_cB[S::NQF], f_cD[S::NQF], f_W[S::NQF], f_g[S::NQF];
+  };
+  struct Cond {
+    double Xs[S::NU * S::NR];
+    double Sk[S::NL * S::NL];
+    double Hk[S::NL];
+  };
+  union {
+    Quad qd;
+    Cond cd;
+  };
   int piv[S::NU];
 };
 
@@ -230,32 +240,32 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
           adv += beta * dphi[r];
         }
       }
-      sm.q_phi[q * NU + i] = a.vol_phi[qq * NU + i];
-      sm.q_adv[q * NU + i] = adv;
+      sm.qd.q_phi[q * NU + i] = a.vol_phi[qq * NU + i];
+      sm.qd.q_adv[q * NU + i] = adv;
       for (int c = 1; c < D; ++c) {
         double g = 0.0;
         for (int r = 0; r < D; ++r) g += sm.Jinv[r * D + c] * dphi[r];
-        sm.q_gx[(q * NU + i) * (D - 1) + c - 1] = g;
+        sm.qd.q_gx[(q * NU + i) * (D - 1) + c - 1] = g;
       }
     }
     for (int q = t; q < nqc; q += NT) {
-      sm.q_W[q] = a.vol_w[q0 + q] * sm.absdet;
-      sm.q_f[q] = (data && a.f_q) ? a.f_q[e * NQ + q0 + q] : 0.0;
+      sm.qd.q_W[q] = a.vol_w[q0 + q] * sm.absdet;
+      sm.qd.q_f[q] = (data && a.f_q) ? a.f_q[e * NQ + q0 + q] : 0.0;
     }
     __syncthreads();
     for (int idx = t; idx < NU * NU; idx += NT) {
       int i = idx / NU, j = idx % NU;
       double acc = 0.0;
-      for (int q = 0; q < nqc; ++q) {
+      _Pragma("unroll 4") for (int q = 0; q < nqc; ++q) {
         double dif = 0.0;
-        for (int c = 0; c < D - 1; ++c) dif += sm.q_gx[(q * NU + j) * (D - 1) + c] * sm.q_gx[(q * NU + i) * (D - 1) + c];
-        acc += sm.q_W[q] * (-sm.q_phi[q * NU + j] * sm.q_adv[q * NU + i] + nu_eff * dif);
+        for (int c = 0; c < D - 1; ++c) dif += sm.qd.q_gx[(q * NU + j) * (D - 1) + c] * sm.qd.q_gx[(q * NU + i) * (D - 1) + c];
+        acc += sm.qd.q_W[q] * (-sm.qd.q_phi[q * NU + j] * sm.qd.q_adv[q * NU + i] + nu_eff * dif);
       }
       sm.A[idx] += acc;
     }
     for (int i = t; i < NU; i += NT) {
       double acc = 0.0;
-      for (int q = 0; q < nqc; ++q) acc += sm.q_W[q] * sm.q_f[q] * sm.q_phi[q * NU + i];
+      _Pragma("unroll 4") for (int q = 0; q < nqc; ++q) acc += sm.qd.q_W[q] * sm.qd.q_f[q] * sm.qd.q_phi[q * NU + i];
       sm.F[i] += acc;
     }
     __syncthreads();
@@ -274,8 +284,8 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
       double v = mono_eval<D>(a.mono[i], xi, dv);
       double dn = 0.0;
       for (int c = 0; c < D; ++c) dn += dv[c] * sm.eta[lf * D + c];
-      sm.f_phi[q * NU + i] = v;
-      sm.f_dn[q * NU + i] = dn;
+      sm.qd.f_phi[q * NU + i] = v;
+      sm.qd.f_dn[q * NU + i] = dn;
     }
     for (int q = t; q < NQF; q += NT) {
       double lam[D + 1];
@@ -292,56 +302,56 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
       }
       double ap = 0.5 * (an + fabs(an)), am = 0.5 * (an - fabs(an));
       double W = a.fac_w[q] * sm.area[lf];
-      sm.f_W[q] = W;
-      sm.f_cA[q] = W * (ap + sm.tau);
-      sm.f_cB[q] = W * (am - sm.tau);
-      sm.f_cD[q] = -W * (am - sm.tau) + ((isN && advect) ? W * ap : 0.0);
-      sm.f_g[q] = (data && a.g_q && sm.bidx[lf] >= 0) ? a.g_q[(int64_t)sm.bidx[lf] * NQF + q] : 0.0;
+      sm.qd.f_W[q] = W;
+      sm.qd.f_cA[q] = W * (ap + sm.tau);
+      sm.qd.f_cB[q] = W * (am - sm.tau);
+      sm.qd.f_cD[q] = -W * (am - sm.tau) + ((isN && advect) ? W * ap : 0.0);
+      sm.qd.f_g[q] = (data && a.g_q && sm.bidx[lf] >= 0) ? a.g_q[(int64_t)sm.bidx[lf] * NQF + q] : 0.0;
     }
     __syncthreads();
     for (int idx = t; idx < NU * NU; idx += NT) {
       int i = idx / NU, j = idx % NU;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) {
-        double pi = sm.f_phi[q * NU + i], pj = sm.f_phi[q * NU + j];
-        acc += sm.f_cA[q] * pj * pi - nu_eff * sm.f_W[q] * (sm.f_dn[q * NU + j] * pi + pj * sm.f_dn[q * NU + i]);
+      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) {
+        double pi = sm.qd.f_phi[q * NU + i], pj = sm.qd.f_phi[q * NU + j];
+        acc += sm.qd.f_cA[q] * pj * pi - nu_eff * sm.qd.f_W[q] * (sm.qd.f_dn[q * NU + j] * pi + pj * sm.qd.f_dn[q * NU + i]);
       }
       sm.A[idx] += acc;
     }
     for (int idx = t; idx < NU * B; idx += NT) {
       int i = idx / B, m = idx % B;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) {
+      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) {
         double psi = a.fac_psi[q * B + m];
-        acc += sm.f_cB[q] * psi * sm.f_phi[q * NU + i] + nu_eff * sm.f_W[q] * psi * sm.f_dn[q * NU + i];
+        acc += sm.qd.f_cB[q] * psi * sm.qd.f_phi[q * NU + i] + nu_eff * sm.qd.f_W[q] * psi * sm.qd.f_dn[q * NU + i];
       }
       sm.Bm[i * NL + lf * B + m] = acc;
     }
     for (int idx = t; idx < B * NU; idx += NT) {
       int m = idx / NU, j = idx % NU;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) {
+      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) {
         double psi = a.fac_psi[q * B + m];
-        acc += -sm.f_cA[q] * sm.f_phi[q * NU + j] * psi + nu_eff * sm.f_W[q] * sm.f_dn[q * NU + j] * psi;
+        acc += -sm.qd.f_cA[q] * sm.qd.f_phi[q * NU + j] * psi + nu_eff * sm.qd.f_W[q] * sm.qd.f_dn[q * NU + j] * psi;
       }
       sm.Cm[(lf * B + m) * NU + j] = acc;
     }
     for (int idx = t; idx < B * B; idx += NT) {
       int m = idx / B, n = idx % B;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) acc += sm.f_cD[q] * a.fac_psi[q * B + m] * a.fac_psi[q * B + n];
+      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_cD[q] * a.fac_psi[q * B + m] * a.fac_psi[q * B + n];
       sm.Dd[lf * B * B + idx] = acc;
     }
     if (data) {
       for (int m = t; m < B; m += NT) {
         if (isN) {
           double acc = 0.0;
-          for (int q = 0; q < NQF; ++q) acc += sm.f_W[q] * sm.f_g[q] * a.fac_psi[q * B + m];
+          _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_W[q] * sm.qd.f_g[q] * a.fac_psi[q * B + m];
           sm.G[lf * B + m] = acc;
         }
         if (isD) {
           double acc = 0.0;
-          for (int q = 0; q < NQF; ++q) acc += a.fac_proj[m * NQF + q] * sm.f_g[q];
+          _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += a.fac_proj[m * NQF + q] * sm.qd.f_g[q];
           sm.LD[lf * B + m] = acc;
         }
       }
@@ -351,7 +361,7 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
 }
 
 // LU with partial pivoting of sm.A (in place, pivots in sm.piv) and the
-// solve of A X = [B | F | I] into sm.Xs.
+// solve of A X = [B | F | I] into sm.cd.Xs.
 template <int D, int P>
 __device__ void elem_factor_solve(const ElemArgs& a, ElemSmem<D, P>& sm) {
   using S = Sz<D, P>;
@@ -388,22 +398,25 @@ __device__ void elem_factor_solve(const ElemArgs& a, ElemSmem<D, P>& sm) {
     }
     __syncthreads();
   }
+  // one right-hand side per thread, solved in place in its column of Xs
   for (int c = t; c < NR; c += NT) {
-    double x[NU];
+    double* x = sm.cd.Xs + c;
     for (int r = 0; r < NU; ++r)
-      x[r] = c < NL ? sm.Bm[r * NL + c] : (c == NL ? sm.F[r] : (r == c - NL - 1 ? 1.0 : 0.0));
+      x[r * NR] = c < NL ? sm.Bm[r * NL + c] : (c == NL ? sm.F[r] : (r == c - NL - 1 ? 1.0 : 0.0));
     for (int k = 0; k < NU; ++k) {
       int p = sm.piv[k];
-      double tmp = x[k]; x[k] = x[p]; x[p] = tmp;
+      double tmp = x[k * NR]; x[k * NR] = x[p * NR]; x[p * NR] = tmp;
     }
-    for (int r = 1; r < NU; ++r)
-      for (int k = 0; k < r; ++k) x[r] -= sm.A[r * NU + k] * x[k];
+    for (int r = 1; r < NU; ++r) {
+      double v = x[r * NR];
+      for (int k = 0; k < r; ++k) v -= sm.A[r * NU + k] * x[k * NR];
+      x[r * NR] = v;
+    }
     for (int r = NU - 1; r >= 0; --r) {
-      double v = x[r];
-      for (int k = r + 1; k < NU; ++k) v -= sm.A[r * NU + k] * x[k];
-      x[r] = v / sm.A[r * NU + r];
+      double v = x[r * NR];
+      for (int k = r + 1; k < NU; ++k) v -= sm.A[r * NU + k] * x[k * NR];
+      x[r * NR] = v / sm.A[r * NU + r];
     }
-    for (int r = 0; r < NU; ++r) sm.Xs[r * NR + c] = x[r];
   }
   __syncthreads();
 }
@@ -429,23 +442,23 @@ __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
   for (int idx = t; idx < NL * NL; idx += NT) {
     int r = idx / NL, c = idx % NL;
     double v = (r / B == c / B) ? sm.Dd[(r / B) * B * B + (r % B) * B + (c % B)] : 0.0;
-    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.Xs[k * NR + c];
-    sm.Sk[idx] = v;
+    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.cd.Xs[k * NR + c];
+    sm.cd.Sk[idx] = v;
   }
   for (int r = t; r < NL; r += NT) {
     double v = sm.G[r];
-    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.Xs[k * NR + NL];
-    sm.Hk[r] = v;
+    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.cd.Xs[k * NR + NL];
+    sm.cd.Hk[r] = v;
   }
   __syncthreads();
   // Dirichlet elimination: H_K -= S_K[:, Dirichlet] lambda_D
   for (int r = t; r < NL; r += NT) {
-    double v = sm.Hk[r];
+    double v = sm.cd.Hk[r];
     for (int lf = 0; lf <= D; ++lf) {
       if (sm.kindf[lf] != 1) continue;
-      for (int m = 0; m < B; ++m) v -= sm.Sk[r * NL + lf * B + m] * sm.LD[lf * B + m];
+      for (int m = 0; m < B; ++m) v -= sm.cd.Sk[r * NL + lf * B + m] * sm.LD[lf * B + m];
     }
-    sm.Hk[r] = v;
+    sm.cd.Hk[r] = v;
   }
   __syncthreads();
   // scatter: <= 2 contributions per entry, so the atomic sums are order-independent
@@ -453,93 +466,132 @@ __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
   for (int idx = t; idx < NL * NL; idx += NT) {
     int r = idx / NL, c = idx % NL;
     int s = slot[(r / B) * (D + 1) + c / B];
-    if (s >= 0) unsafeAtomicAdd(&a.bval[(int64_t)s * B * B + (r % B) * B + (c % B)], sm.Sk[idx]);
+    if (s >= 0) unsafeAtomicAdd(&a.bval[(int64_t)s * B * B + (r % B) * B + (c % B)], sm.cd.Sk[idx]);
   }
   for (int r = t; r < NL; r += NT) {
     int lf = r / B, f = sm.fid[lf];
     int fr = a.free_rank[f];
-    if (fr >= 0) unsafeAtomicAdd(&a.H[(int64_t)fr * B + r % B], sm.Hk[r]);
+    if (fr >= 0) unsafeAtomicAdd(&a.H[(int64_t)fr * B + r % B], sm.cd.Hk[r]);
     if (sm.kindf[lf] == 1) a.lamD[(int64_t)f * B + r % B] = sm.LD[r];
   }
   if (a.Ainv)
     for (int k = t; k < NU * NU; k += NT) {
       int r = k / NU, c = k % NU;
-      a.Ainv[e * NU * NU + k] = sm.Xs[r * NR + NL + 1 + c];
+      a.Ainv[e * NU * NU + k] = sm.cd.Xs[r * NR + NL + 1 + c];
     }
 }
 
-// Inverse of each free facet's diagonal block (Gauss-Jordan, partial pivoting).
+// Inverse of each free facet's diagonal block (Gauss-Jordan, partial
+// pivoting).  All register arrays are indexed with compile-time indices
+// (unrolled loops, predicated row swaps) so they stay in registers.
 template <int B>
-__global__ void k_diag_inv(int64_t nfree, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+__global__ __launch_bounds__(64) void k_diag_inv(int64_t nfree, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                            const double* __restrict__ bval, double* __restrict__ dinv, int* err) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nfree) return;
   int64_t s = -1;
   for (int64_t k = bptr[r]; k < bptr[r + 1]; ++k)
     if (bcol[k] == r) { s = k; break; }
-  double M[B * B], I[B * B];
-  for (int k = 0; k < B * B; ++k) { M[k] = s >= 0 ? bval[s * B * B + k] : 0.0; I[k] = (k / B == k % B) ? 1.0 : 0.0; }
+  double M[B][B], I[B][B];
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      M[i][j] = s >= 0 ? bval[s * B * B + i * B + j] : 0.0;
+      I[i][j] = i == j ? 1.0 : 0.0;
+    }
   double scale = 0.0;
-  for (int k = 0; k < B * B; ++k) scale = fmax(scale, fabs(M[k]));
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) scale = fmax(scale, fabs(M[i][j]));
   bool bad = !(scale > 0.0) || !isfinite(scale);
+#pragma unroll
   for (int c = 0; c < B; ++c) {
     int p = c;
+    double best = fabs(M[c][c]);
+#pragma unroll
     for (int q = c + 1; q < B; ++q)
-      if (fabs(M[q * B + c]) > fabs(M[p * B + c])) p = q;
-    if (!(fabs(M[p * B + c]) > 1e-14 * scale)) bad = true;
-    for (int j = 0; j < B; ++j) {
-      double x = M[c * B + j]; M[c * B + j] = M[p * B + j]; M[p * B + j] = x;
-      x = I[c * B + j]; I[c * B + j] = I[p * B + j]; I[p * B + j] = x;
+      if (fabs(M[q][c]) > best) { best = fabs(M[q][c]); p = q; }
+    if (!(best > 1e-14 * scale)) bad = true;
+#pragma unroll
+    for (int q = c + 1; q < B; ++q) {
+      if (q == p) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          double x = M[c][j]; M[c][j] = M[q][j]; M[q][j] = x;
+          x = I[c][j]; I[c][j] = I[q][j]; I[q][j] = x;
+        }
+      }
     }
-    double d = M[c * B + c];
+    double d = M[c][c];
     if (d == 0.0) d = 1.0;
-    for (int j = 0; j < B; ++j) { M[c * B + j] /= d; I[c * B + j] /= d; }
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int j = 0; j < B; ++j) { M[c][j] *= inv; I[c][j] *= inv; }
+#pragma unroll
     for (int q = 0; q < B; ++q) {
       if (q == c) continue;
-      double f = M[q * B + c];
-      for (int j = 0; j < B; ++j) { M[q * B + j] -= f * M[c * B + j]; I[q * B + j] -= f * I[c * B + j]; }
+      const double f = M[q][c];
+#pragma unroll
+      for (int j = 0; j < B; ++j) { M[q][j] -= f * M[c][j]; I[q][j] -= f * I[c][j]; }
     }
   }
   if (bad) atomicOr(err, 4);
-  for (int k = 0; k < B * B; ++k) dinv[r * B * B + k] = I[k];
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) dinv[r * B * B + i * B + j] = I[i][j];
 }
 
 // Scaled scalar rows: row R*B+m of D_b^-1 S over the block row R; the
 // diagonal block becomes the identity; exact zeros off the diagonal are
-// dropped.  count pass (vals == nullptr) and fill pass.
+// dropped.  One wave per scalar row: lane c handles candidate (block c/B,
+// node c%B), kept entries are packed in order with a ballot, so a row's
+// stores are contiguous.  Count pass (val == nullptr), then fill pass.
 template <int B>
-__global__ void k_csr_scaled(int64_t nfree, const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-                             const double* __restrict__ bval, const double* __restrict__ dinv,
-                             int32_t* __restrict__ cnt, const int64_t* __restrict__ rowptr,
-                             int32_t* __restrict__ col, double* __restrict__ val) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t* __restrict__ bptr,
+                                                    const int32_t* __restrict__ bcol, const double* __restrict__ bval,
+                                                    const double* __restrict__ dinv, int32_t* __restrict__ cnt,
+                                                    const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                    double* __restrict__ val) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= nfree * B) return;
-  int64_t R = i / B;
-  int m = (int)(i % B);
-  double di[B];
-  for (int k = 0; k < B; ++k) di[k] = dinv[R * B * B + m * B + k];
-  int32_t c = 0;
+  const int64_t R = i / B;
+  const int m = (int)(i % B);
+  const int64_t s0 = bptr[R];
+  const int ncand = (int)(bptr[R + 1] - s0) * B;
   int64_t out = rowptr ? rowptr[i] : 0;
-  for (int64_t s = bptr[R]; s < bptr[R + 1]; ++s) {
-    int32_t C = bcol[s];
-    for (int n = 0; n < B; ++n) {
-      double v;
+  int c0 = 0;
+  for (int base = 0; base < ncand; base += 64) {
+    const int cidx = base + lane;
+    bool keep = false;
+    double v = 0.0;
+    int32_t colv = 0;
+    if (cidx < ncand) {
+      const int64_t s = s0 + cidx / B;
+      const int n = cidx % B;
+      const int32_t C = bcol[s];
+      colv = (int32_t)(C * B + n);
       if (C == R) {
-        v = (n == m) ? 1.0 : 0.0;
+        v = n == m ? 1.0 : 0.0;
+        keep = n == m;
       } else {
-        v = 0.0;
-        for (int k = 0; k < B; ++k) v += di[k] * bval[s * B * B + k * B + n];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * bval[s * B * B + k * B + n];
+        keep = v != 0.0;
       }
-      bool keep = (C == R && n == m) || v != 0.0;
-      if (!keep) continue;
-      if (val) {
-        col[out + c] = (int32_t)(C * B + n);
-        val[out + c] = v;
-      }
-      ++c;
     }
+    const unsigned long long mask = __ballot(keep);
+    if (val && keep) {
+      const int pos = c0 + __popcll(mask & ((1ull << lane) - 1ull));
+      col[out + pos] = colv;
+      val[out + pos] = v;
+    }
+    c0 += __popcll(mask);
   }
-  if (!val) cnt[i] = c;
+  if (!val && lane == 0) cnt[i] = c0;
 }
 
 template <int B>
@@ -694,7 +746,7 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   const int64_t n = nfree * B;
   Arena& ar = s->arena;
   int threads = 128;
-  hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), threads)), dim3(threads), 0, st, nfree,
+  hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), 64)), dim3(64), 0, st, nfree,
                      m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
   AH_LAUNCHED();
   int32_t* cnt = nullptr;
@@ -702,9 +754,9 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   tmp.stream = st;
   AH_TRY(tmp.get(&cnt, n + 1));
   AH_TRY(ar.get(&s->d_rowptr, n + 1));
-  hipLaunchKernelGGL(k_csr_scaled<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree,
-                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, cnt, (const int64_t*)nullptr,
-                     (int32_t*)nullptr, (double*)nullptr);
+  const dim3 gw((unsigned)cdiv(std::max<int64_t>(n, 1) * 64, 256));
+  hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
+                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr);
   AH_LAUNCHED();
   AH_TRY(scan_i32_to_i64(cnt, s->d_rowptr, n, st, tmp));
   AH_TRY(read_i64(s->d_rowptr + n, &s->nnz, st));
@@ -715,8 +767,8 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   }
   AH_TRY(ar.get(&s->d_col, s->nnz));
   AH_TRY(ar.get(&s->d_val, s->nnz));
-  hipLaunchKernelGGL(k_csr_scaled<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree,
-                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, cnt, s->d_rowptr, s->d_col, s->d_val);
+  hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
+                     cnt, s->d_rowptr, s->d_col, s->d_val);
   AH_LAUNCHED();
   hipLaunchKernelGGL(k_hhat<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree, s->d_Dinv,
                      s->d_H, s->d_Hhat);

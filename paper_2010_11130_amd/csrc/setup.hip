@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "prof.h"
@@ -64,25 +65,36 @@ __global__ void k_pmis_init(int64_t n, const int32_t* __restrict__ infl, int lev
   state[i] = infl[i] == 0 ? 2 : 0;
 }
 
-__global__ void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                             const uint8_t* __restrict__ strong, const uint64_t* __restrict__ key,
-                             const int8_t* __restrict__ state, unsigned long long* __restrict__ nbmax) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// 16 lanes per row for the PMIS phases and the one-point kernel.
+constexpr int PG = 16;
+
+__global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci,
+                                                    const uint8_t* __restrict__ strong,
+                                                    const uint64_t* __restrict__ key, const int8_t* __restrict__ state,
+                                                    unsigned long long* __restrict__ nbmax) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / PG;
+  const int g = (int)(gid % PG);
   if (i >= n || state[i] != 0) return;
   unsigned long long mx = 0, ki = key[i];
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+  for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG) {
     if (!strong[k]) continue;
     int32_t j = ci[k];
     if (state[j] != 0) continue;
     mx = mx > key[j] ? mx : key[j];
     atomicMax(&nbmax[j], ki);      // i depends on j: i is a neighbour of j as well
   }
-  if (mx) atomicMax(&nbmax[i], mx);
+  for (int o = PG / 2; o > 0; o >>= 1) {
+    unsigned long long other = __shfl_xor(mx, o, PG);
+    mx = mx > other ? mx : other;
+  }
+  if (g == 0 && mx) atomicMax(&nbmax[i], mx);
 }
 
 // New C points: undecided points whose key beats every undecided neighbour.
 // nbmax is reset for the next round (only undecided points carry a value),
-// and the round's undecided counter is cleared.
+// and the round's undecided flag is cleared.
 __global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsigned long long* __restrict__ nbmax,
                               int8_t* __restrict__ state, unsigned long long* __restrict__ left) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,14 +104,26 @@ __global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsig
   nbmax[i] = 0;
 }
 
-__global__ void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                             const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
-                             unsigned long long* __restrict__ left) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || state[i] != 0) return;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-    if (strong[k] && state[ci[k]] == 1) { state[i] = 2; return; }
-  atomicAdd(left, 1ull);
+// Undecided points with a strong C neighbour become F. The kernels with a
+// per-launch result use a capped grid (grid-stride over rows) and one
+// global write per block: a write per wave to one address serializes.
+__global__ __launch_bounds__(256) void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci,
+                                                    const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
+                                                    unsigned long long* __restrict__ left) {
+  const int g = (int)(threadIdx.x % PG);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
+  int undecided = 0;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; i < n; i += stride) {
+    if (state[i] != 0) continue;
+    int hit = 0;
+    for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG)
+      if (strong[k] && state[ci[k]] == 1) hit = 1;
+    for (int o = PG / 2; o > 0; o >>= 1) hit |= __shfl_xor(hit, o, PG);
+    if (!hit) undecided = 1;
+    else if (g == 0) state[i] = 2;
+  }
+  if (__syncthreads_or(undecided) && threadIdx.x == 0) *left = 1ull;
 }
 
 __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* __restrict__ cf,
@@ -115,41 +139,91 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 // the number of R A P candidates of its coarse row (row lengths of A over
 // {i} and N_i); for F points the F-row statistics (count, entries).
 // imax[0] = max |N_i|, imax[1] = max candidates; fst[0..1] = F rows, entries.
-__global__ void k_onepoint(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const double* __restrict__ v, const uint8_t* __restrict__ strong,
-                           const int8_t* __restrict__ cf, const int64_t* __restrict__ cidx,
-                           int32_t* __restrict__ pcol, int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
-                           int* __restrict__ imax, unsigned long long* __restrict__ fst) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (cf[i]) {
-    pcol[i] = (int32_t)cidx[i];
-    int m = 0;
-    int64_t cand = rp[i + 1] - rp[i];
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (strong[k] && !cf[ci[k]]) {
-        ++m;
-        cand += rp[ci[k] + 1] - rp[ci[k]];
+// 16 lanes per row; the strongest C neighbour is the first in row order
+// (smallest column) within relative 1e-12 of the maximum.
+__global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                  const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
+                                                  const int64_t* __restrict__ cidx, int32_t* __restrict__ pcol,
+                                                  int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
+                                                  int* __restrict__ imax, unsigned long long* __restrict__ fst) {
+  const int g = (int)(threadIdx.x % PG);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
+  int mmax = 0, cmax = 0;
+  unsigned long long fcnt = 0, fent = 0;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; i < n; i += stride) {
+    const int64_t k0 = rp[i], k1 = rp[i + 1];
+    if (cf[i]) {
+      int m = 0;
+      int64_t cand = 0;
+      for (int64_t k = k0 + g; k < k1; k += PG)
+        if (strong[k] && !cf[ci[k]]) {
+          ++m;
+          cand += rp[ci[k] + 1] - rp[ci[k]];
+        }
+      for (int o = PG / 2; o > 0; o >>= 1) {
+        m += __shfl_xor(m, o, PG);
+        cand += __shfl_xor(cand, o, PG);
       }
-    rcnt[cidx[i]] = 1 + m;
-    clist[cidx[i]] = (int32_t)i;
-    atomicMax(&imax[0], m);
-    atomicMax(&imax[1], cand > 0x3fffffff ? 0x3fffffff : (int)cand);
-    return;
+      if (g == 0) {
+        cand += k1 - k0;
+        pcol[i] = (int32_t)cidx[i];
+        rcnt[cidx[i]] = 1 + m;
+        clist[cidx[i]] = (int32_t)i;
+        mmax = m > mmax ? m : mmax;
+        const int c = cand > 0x3fffffff ? 0x3fffffff : (int)cand;
+        cmax = c > cmax ? c : cmax;
+      }
+      continue;
+    }
+    double mx = -1.0;
+    for (int64_t k = k0 + g; k < k1; k += PG)
+      if (strong[k] && cf[ci[k]]) mx = fmax(mx, fabs(v[k]));
+    for (int o = PG / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, PG));
+    int64_t first = k1;
+    if (mx >= 0.0) {
+      const double thr = mx * (1.0 - 1e-12);
+      for (int64_t k = k0 + g; k < k1; k += PG)
+        if (strong[k] && cf[ci[k]] && fabs(v[k]) >= thr) { first = k; break; }
+      for (int o = PG / 2; o > 0; o >>= 1) {
+        int64_t other = __shfl_xor(first, o, PG);
+        first = other < first ? other : first;
+      }
+    }
+    if (g == 0) {
+      pcol[i] = first < k1 ? (int32_t)cidx[ci[first]] : -1;
+      fcnt += 1;
+      fent += (unsigned long long)(k1 - k0);
+    }
   }
-  atomicAdd(&fst[0], 1ull);
-  atomicAdd(&fst[1], (unsigned long long)(rp[i + 1] - rp[i]));
-  double mx = 0.0;
-  bool any = false;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-    if (strong[k] && cf[ci[k]]) { mx = fmax(mx, fabs(v[k])); any = true; }
-  int32_t pc = -1;
-  if (any) {
-    double thr = mx * (1.0 - 1e-12);
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (strong[k] && cf[ci[k]] && fabs(v[k]) >= thr) { pc = (int32_t)cidx[ci[k]]; break; }
+  // block totals, one atomic each
+  for (int o = 32; o > 0; o >>= 1) {
+    int a = __shfl_xor(mmax, o, 64), c = __shfl_xor(cmax, o, 64);
+    mmax = a > mmax ? a : mmax;
+    cmax = c > cmax ? c : cmax;
+    fcnt += __shfl_xor(fcnt, o, 64);
+    fent += __shfl_xor(fent, o, 64);
   }
-  pcol[i] = pc;
+  __shared__ int sm[2][4];
+  __shared__ unsigned long long su[2][4];
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][w] = mmax; sm[1][w] = cmax;
+    su[0][w] = fcnt; su[1][w] = fent;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x / 64); ++k) {
+      mmax = sm[0][k] > mmax ? sm[0][k] : mmax;
+      cmax = sm[1][k] > cmax ? sm[1][k] : cmax;
+      fcnt += su[0][k];
+      fent += su[1][k];
+    }
+    if (mmax) atomicMax(&imax[0], mmax);
+    if (cmax) atomicMax(&imax[1], cmax);
+    if (fcnt) atomicAdd(&fst[0], fcnt);
+    if (fent) atomicAdd(&fst[1], fent);
+  }
 }
 
 __device__ inline double wave_sum(double v) {
@@ -633,6 +707,10 @@ __global__ void k_p_fill(int64_t n, const int32_t* __restrict__ pcol, const int6
 }
 
 static inline dim3 g1(int64_t n, int t = 256) { return dim3((unsigned)cdiv(std::max<int64_t>(n, 1), t)); }
+// Capped grid for the grid-stride kernels with PG lanes per row (256 threads).
+static inline dim3 grows(int64_t n) {
+  return dim3((unsigned)std::min<int64_t>(cdiv(std::max<int64_t>(n, 1), 256 / PG), 2048));
+}
 
 static ah_status transpose(int64_t nrow, int64_t ncol, const int64_t* rp, const int32_t* ci, const double* v,
                            int64_t nnz, Arena& ar, Arena& tmp, hipStream_t st, int64_t** tp, int32_t** tc,
@@ -773,10 +851,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     for (int round = 0;; ++round) {
       if (round > 10000) { set_error("air_setup: PMIS did not terminate"); tmp.release(); delete h; return AH_EINVAL; }
       unsigned long long* left_d = d_ull + (round & 1);
-      hipLaunchKernelGGL(k_pmis_nbmax, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
+      hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
       hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d);
-      hipLaunchKernelGGL(k_pmis_fmark, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, left_d);
+      hipLaunchKernelGGL(k_pmis_fmark, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, left_d);
       CKH(hipGetLastError());
+      // rounds run in pairs between host checks: a round after the last
+      // undecided point is gone changes nothing and leaves its flag at 0
+      if ((round & 1) == 0) continue;
       unsigned long long left = 0;
       CK(read_bytes(left_d, &left, sizeof(left), st));
       if (left == 0) break;
@@ -798,9 +879,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     int32_t *rcnt = nullptr, *clist = nullptr;
     CK(ar.get(&L.pcol, n));
     CK(tmp.get(&rcnt, nc + 1));
-    CK(tmp.get(&clist, nc));
+    CK(ar.get(&clist, nc));
+    L.clist = clist;
     CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
-    hipLaunchKernelGGL(k_onepoint, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
+    hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
                        rcnt, clist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
     CK(ar.get(&L.Rptr, nc + 1));
@@ -938,6 +1020,43 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     return AH_ESINGULAR;
   }
   h->nfallback = (int64_t)fb;
+  // tail: the levels from the first one with at most tail_max rows are run
+  // by one workgroup inside a single launch per cycle
+  {
+    int64_t tail_max = 500;
+    if (const char* e = std::getenv("AH_TAIL_MAX")) tail_max = std::atoll(e);
+    if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
+    if (h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
+    const int nl = (int)h->lev.size();
+    h->tail0 = -1;
+    for (int l = 0; l < nl; ++l)
+      if (h->lev[l].n <= tail_max) { h->tail0 = l; break; }
+    std::vector<TailLevel> tl(nl);
+    for (int l = 0; l < nl; ++l) {
+      const AhLevel& L = h->lev[l];
+      TailLevel& T = tl[l];
+      T = TailLevel{};
+      T.n = L.n; T.nc = L.nc;
+      T.rp = L.rowptr; T.ci = L.col; T.v = L.val; T.v32 = L.val32; T.d = L.diag; T.d32 = L.diag32;
+      T.cf = L.cf; T.pcol = L.pcol;
+      T.Rp = L.Rptr; T.Rc = L.Rcol; T.Rv = L.Rval; T.Rv32 = L.Rval32;
+      T.ATp = L.ATptr; T.ATc = L.ATcol; T.ATv = L.ATval; T.ATv32 = L.ATval32;
+      T.RTp = L.RTptr; T.RTc = L.RTcol; T.RTv = L.RTval; T.RTv32 = L.RTval32;
+      T.PTp = L.PTptr; T.PTc = L.PTcol;
+      T.b = L.b; T.x = L.x; T.y = L.y; T.b32 = L.b32; T.x32 = L.x32; T.y32 = L.y32;
+    }
+    rc = ar.get(&h->d_tail, nl);
+    if (rc < 0) { delete h; return rc; }
+    double* pin = pinned_scratch((nl * sizeof(TailLevel) + 7) / 8);
+    if (!pin) { set_error("pinned host allocation failed"); delete h; return AH_ENOMEM; }
+    std::memcpy(pin, tl.data(), nl * sizeof(TailLevel));
+    if (hipMemcpyAsync(h->d_tail, pin, nl * sizeof(TailLevel), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("air_setup: upload of the level table failed");
+      delete h;
+      return AH_EHIP;
+    }
+  }
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->levels = (int)h->lev.size();

@@ -21,29 +21,44 @@
 
 namespace ah {
 
-enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3 };
+enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5 };
 
-// MODE SP_MV:    y = A x
-// MODE SP_RES:   y = b - A x
-// MODE SP_SWEEP: y_i = x_i + omega (b_i - (A x)_i) / d_i  for cf_i == X (all rows if cf null), else x_i
-// MODE SP_ADDMV: y = b + A x
+// MODE SP_MV:      y = A x
+// MODE SP_RES:     y = b - A x
+// MODE SP_SWEEP:   y_i = x_i + omega (b_i - (A x)_i) / d_i  for cf_i == X (all rows if cf null), else x_i
+// MODE SP_ADDMV:   y = b + A x
+// MODE SP_SWEEP_P: the sweep applied to the interpolated iterate x = P e,
+//                  read on the fly as x_j = e[pc[j]] (0 where pc[j] < 0)
+// MODE SP_SWEEP_LIST: the sweep on the rows listed in pc[0..n) only; other
+//                  rows of y are not written
+// y2 (sweeps, optional): the updated rows are also written there.
 // A values may be null (all ones).
 template <class TA, class TX, class TY, int G, int MODE>
 __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const TA* __restrict__ av, const TX* __restrict__ x,
                                              const TY* __restrict__ b, const TY* __restrict__ d,
-                                             const int8_t* __restrict__ cf, int X, TY omega, TY* __restrict__ y) {
+                                             const int8_t* __restrict__ cf, int X, TY omega, TY* __restrict__ y,
+                                             const int32_t* __restrict__ pc, TY* __restrict__ y2) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = gid / G;
+  const int64_t ii = gid / G;
   const int g = (int)(gid % G);
-  if (i >= n) return;
-  const bool active = MODE != SP_SWEEP || !cf || cf[i] == X;
+  if (ii >= n) return;
+  const int64_t i = MODE == SP_SWEEP_LIST ? (int64_t)pc[ii] : ii;
+  constexpr bool SW = MODE == SP_SWEEP || MODE == SP_SWEEP_P || MODE == SP_SWEEP_LIST;
+  const bool active = MODE == SP_SWEEP_LIST || !SW || !cf || cf[i] == X;
   TY acc = 0;
   if (active) {
     const int64_t k1 = rp[i + 1];
     for (int64_t k = rp[i] + g; k < k1; k += G) {
       TY a = av ? (TY)av[k] : (TY)1;
-      acc += a * (TY)x[ci[k]];
+      TY xv;
+      if (MODE == SP_SWEEP_P) {
+        int32_t c = pc[ci[k]];
+        xv = c >= 0 ? (TY)x[c] : (TY)0;
+      } else {
+        xv = (TY)x[ci[k]];
+      }
+      acc += a * xv;
     }
   }
 #pragma unroll
@@ -53,12 +68,153 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   else if (MODE == SP_RES) y[i] = b[i] - acc;
   else if (MODE == SP_ADDMV) y[i] = b[i] + acc;
   else {
-    TY xi = (TY)x[i];
+    TY xi;
+    if (MODE == SP_SWEEP_P) {
+      int32_t c = pc[i];
+      xi = c >= 0 ? (TY)x[c] : (TY)0;
+    } else {
+      xi = (TY)x[i];
+    }
     if (active) {
       TY di = d[i];
       if (fabs((double)di) >= 1e-30) xi += omega * (b[i] - acc) / di;
+      if (y2) y2[i] = xi;
     }
     y[i] = xi;
+  }
+}
+
+// Coarse end of the cycle in one workgroup: every level from l0 down,
+// one row per thread, phases separated by workgroup barriers.
+template <class T>
+struct TLv;
+template <>
+struct TLv<double> {
+  __device__ static const double* A(const TailLevel& L) { return L.v; }
+  __device__ static const double* AT(const TailLevel& L) { return L.ATv; }
+  __device__ static const double* R(const TailLevel& L) { return L.Rv; }
+  __device__ static const double* RT(const TailLevel& L) { return L.RTv; }
+  __device__ static const double* d(const TailLevel& L) { return L.d; }
+  __device__ static double* b(const TailLevel& L) { return L.b; }
+  __device__ static double* x(const TailLevel& L) { return L.x; }
+  __device__ static double* y(const TailLevel& L) { return L.y; }
+};
+template <>
+struct TLv<float> {
+  __device__ static const float* A(const TailLevel& L) { return L.v32; }
+  __device__ static const float* AT(const TailLevel& L) { return L.ATv32; }
+  __device__ static const float* R(const TailLevel& L) { return L.Rv32; }
+  __device__ static const float* RT(const TailLevel& L) { return L.RTv32; }
+  __device__ static const float* d(const TailLevel& L) { return L.d32; }
+  __device__ static float* b(const TailLevel& L) { return L.b32; }
+  __device__ static float* x(const TailLevel& L) { return L.x32; }
+  __device__ static float* y(const TailLevel& L) { return L.y32; }
+};
+
+template <class T>
+__device__ inline T row_dot(const int64_t* rp, const int32_t* ci, const T* av, const T* x, int64_t i) {
+  T s = 0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += (av ? av[k] : (T)1) * x[ci[k]];
+  return s;
+}
+
+template <class T, bool TR>
+__global__ __launch_bounds__(1024) void k_tail(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                               const double* __restrict__ cinv, const T* b_in, T* out, int nsw,
+                                               T omega) {
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  const int last = nlev - 1;
+  if (!TR) {
+    const T* b = b_in;
+    for (int l = l0; l < last; ++l) {
+      const TailLevel& L = lv[l];
+      T* cb = TLv<T>::b(lv[l + 1]);
+      for (int64_t i = t; i < L.nc; i += NT) cb[i] = row_dot<T>(L.Rp, L.Rc, TLv<T>::R(L), b, i);
+      __syncthreads();
+      b = cb;
+    }
+    {
+      const TailLevel& LL = lv[last];
+      T* z = last == l0 ? out : TLv<T>::y(LL);
+      for (int64_t i = t; i < LL.n; i += NT) {
+        double s = 0.0;
+        for (int64_t j = 0; j < LL.n; ++j) s += cinv[i * LL.n + j] * (double)b[j];
+        z[i] = (T)s;
+      }
+      __syncthreads();
+    }
+    for (int l = last - 1; l >= l0; --l) {
+      const TailLevel& L = lv[l];
+      const T* bl = l == l0 ? b_in : TLv<T>::b(L);
+      T* outl = l == l0 ? out : TLv<T>::y(L);
+      const T* ec = TLv<T>::y(lv[l + 1]);
+      T* cur = TLv<T>::x(L);
+      T* alt = TLv<T>::y(L);
+      for (int64_t i = t; i < L.n; i += NT) cur[i] = L.pcol[i] >= 0 ? ec[L.pcol[i]] : (T)0;
+      __syncthreads();
+      for (int s = 0; s < nsw; ++s) {
+        const int X = (nsw == 1 || s < 2) ? 0 : 1;
+        T* dst = s == nsw - 1 ? outl : alt;
+        for (int64_t i = t; i < L.n; i += NT) {
+          T xi = cur[i];
+          if (L.cf[i] == X) {
+            T di = TLv<T>::d(L)[i];
+            if (fabs((double)di) >= 1e-30) xi += omega * (bl[i] - row_dot<T>(L.rp, L.ci, TLv<T>::A(L), cur, i)) / di;
+          }
+          dst[i] = xi;
+        }
+        __syncthreads();
+        alt = cur;
+        cur = dst;
+      }
+    }
+  } else {
+    const T* g = b_in;
+    for (int l = l0; l < last; ++l) {
+      const TailLevel& L = lv[l];
+      T* cur = TLv<T>::x(L);
+      T* alt = TLv<T>::y(L);
+      for (int64_t i = t; i < L.n; i += NT) cur[i] = 0;
+      __syncthreads();
+      for (int s = 3 - nsw; s < 3; ++s) {
+        const int X = s == 0 ? 1 : 0;   // C, F, F
+        for (int64_t i = t; i < L.n; i += NT) {
+          T yi = cur[i];
+          if (L.cf[i] == X) {
+            T di = TLv<T>::d(L)[i];
+            if (fabs((double)di) >= 1e-30) yi += omega * (g[i] - row_dot<T>(L.ATp, L.ATc, TLv<T>::AT(L), cur, i)) / di;
+          }
+          alt[i] = yi;
+        }
+        __syncthreads();
+        T* tmp = cur; cur = alt; alt = tmp;
+      }
+      for (int64_t i = t; i < L.n; i += NT) alt[i] = g[i] - row_dot<T>(L.ATp, L.ATc, TLv<T>::AT(L), cur, i);
+      __syncthreads();
+      T* cb = TLv<T>::b(lv[l + 1]);
+      for (int64_t c = t; c < L.nc; c += NT) cb[c] = row_dot<T>(L.PTp, L.PTc, (const T*)nullptr, alt, c);
+      __syncthreads();
+      g = cb;
+    }
+    {
+      const TailLevel& LL = lv[last];
+      T* e = last == l0 ? out : TLv<T>::x(LL);
+      for (int64_t i = t; i < LL.n; i += NT) {
+        double s = 0.0;
+        for (int64_t j = 0; j < LL.n; ++j) s += cinv[j * LL.n + i] * (double)g[j];
+        e[i] = (T)s;
+      }
+      __syncthreads();
+    }
+    for (int l = last - 1; l >= l0; --l) {
+      const TailLevel& L = lv[l];
+      const T* ec = (l + 1 == last) ? TLv<T>::x(lv[l + 1]) : TLv<T>::b(lv[l + 1]);
+      const T* yl = TLv<T>::y(L);   // sweeps start in x and end in y for 1 or 3 sweeps
+      T* outl = l == l0 ? out : TLv<T>::b(L);
+      for (int64_t i = t; i < L.n; i += NT) outl[i] = yl[i] + row_dot<T>(L.RTp, L.RTc, TLv<T>::RT(L), ec, i);
+      __syncthreads();
+    }
   }
 }
 
@@ -144,6 +300,29 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int nblk, const double* 
   if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
 }
 
+// w -= sum_v V_v h_v, and the block partial sums of the updated w.w
+__global__ __launch_bounds__(DOT_T) void k_maxpy_norm(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ h, double* __restrict__ w,
+                                                      double* __restrict__ partial, int nblk) {
+  __shared__ double red[DOT_T / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * DOT_T + threadIdx.x; i < n; i += (int64_t)nblk * DOT_T) {
+    double s = 0.0;
+    for (int v = 0; v < k; ++v) s += V[(int64_t)v * ldv + i] * h[v];
+    double wi = w[i] - s;
+    w[i] = wi;
+    acc += wi * wi;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < DOT_T / 64; ++q) s += red[q];
+    partial[blockIdx.x] = s;
+  }
+}
+
 // w -= sum_v V_v h_v
 template <class TV>
 __global__ void k_maxpy(int64_t n, int k, const TV* __restrict__ V, int64_t ldv, const double* __restrict__ h,
@@ -178,24 +357,25 @@ static inline dim3 g1(int64_t n, int t = 256) { return dim3((unsigned)cdiv(std::
 static int pick_g(int64_t nnz, int64_t n) {
   double avg = n ? (double)nnz / (double)n : 0.0;
   if (avg < 6) return 4;
-  if (avg < 14) return 8;
-  if (avg < 40) return 16;
+  if (avg < 40) return 8;
+  if (avg < 80) return 16;
   return 32;
 }
 
 template <class TA, class TX, class TY, int MODE>
 static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, const TA* av, const TX* x, const TY* b,
                        const TY* d, const int8_t* cf, int X, TY omega, TY* y, hipStream_t st,
-                       const char* tag = nullptr, double bytes = 0.0) {
+                       const char* tag = nullptr, double bytes = 0.0, const int32_t* pc = nullptr,
+                       TY* y2 = nullptr) {
   if (n == 0) return AH_OK;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   dim3 grid((unsigned)cdiv(n * G, 256));
   switch (G) {
-    case 4: hipLaunchKernelGGL((k_csr<TA, TX, TY, 4, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
-    case 8: hipLaunchKernelGGL((k_csr<TA, TX, TY, 8, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
-    case 16: hipLaunchKernelGGL((k_csr<TA, TX, TY, 16, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
-    default: hipLaunchKernelGGL((k_csr<TA, TX, TY, 32, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y); break;
+    case 4: hipLaunchKernelGGL((k_csr<TA, TX, TY, 4, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
+    case 8: hipLaunchKernelGGL((k_csr<TA, TX, TY, 8, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
+    case 16: hipLaunchKernelGGL((k_csr<TA, TX, TY, 16, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
+    default: hipLaunchKernelGGL((k_csr<TA, TX, TY, 32, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
   }
   prof_end(ps);
   AH_LAUNCHED();
@@ -245,6 +425,13 @@ template <class T>
 static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   AhLevel& L = h->lev[l];
   const int nlev = (int)h->lev.size();
+  const int nsw = h->prm.relax == 1 ? 1 : 3;
+  if (h->tail0 >= 0 && l >= h->tail0) {
+    hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, b, out, nsw,
+                       (T)h->prm.omega);
+    AH_LAUNCHED();
+    return AH_OK;
+  }
   if (l == nlev - 1) {
     if (L.n == 0) return AH_OK;
     hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)L.n), dim3(64), 0, st, (int)L.n, h->cinv, b, out, 0);
@@ -252,25 +439,34 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     return AH_OK;
   }
   AhLevel& C = h->lev[l + 1];
-  const int G = pick_g(L.nnz, L.n);
+  const int G = (l == 0 && h->g0) ? h->g0 : pick_g(L.nnz, L.n);
   const int GR = pick_g(L.nnzR, L.nc);
   AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
                                 (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
   T* ec = Ops<T>::y(C);
   AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
-  T* cur = Ops<T>::x(L);
+  // first sweep on the interpolated iterate P e_c (read through pcol), then
+  // the remaining sweeps ping-pong between the level's x and y
+  T* cur = nullptr;
   T* alt = Ops<T>::y(L);
-  hipLaunchKernelGGL(k_interp<T>, g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, cur);
-  AH_LAUNCHED();
   const int sets_ffc[3] = {0, 0, 1};   // F, F, C
-  const int nsw = h->prm.relax == 1 ? 1 : 3;
   const T om = (T)h->prm.omega;
+  const char* tag = l == 0 ? (sizeof(T) == 8 ? "sweep0" : "sweep0_f32") : nullptr;
+  // F sweeps over all rows (other rows copied); the second F sweep also
+  // writes its F rows into out, so the closing C sweep visits the C rows
+  // only (from the C-point list) and writes them into out
   for (int s = 0; s < nsw; ++s) {
     T* dst = (s == nsw - 1) ? out : alt;
-    const char* tag = l == 0 ? (sizeof(T) == 8 ? "sweep0" : "sweep0_f32") : nullptr;
-    AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, sets_ffc[s], om,
-                                     dst, st, tag, sweep_bytes<T>(L, sets_ffc[s]))));
-    alt = cur;
+    if (s == 0)
+      AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om, dst,
+                                         st, tag, sweep_bytes<T>(L, 0), L.pcol)));
+    else if (s == 1)
+      AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, 0, om, dst, st,
+                                       tag, sweep_bytes<T>(L, 0), nullptr, out)));
+    else
+      AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, L.nc, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, 1, om,
+                                            out, st, tag, sweep_bytes<T>(L, 1), L.clist)));
+    alt = (s == 0) ? Ops<T>::x(L) : cur;
     cur = dst;
   }
   return AH_OK;
@@ -283,6 +479,12 @@ template <class T>
 static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st) {
   AhLevel& L = h->lev[l];
   const int nlev = (int)h->lev.size();
+  if (h->tail0 >= 0 && l >= h->tail0) {
+    hipLaunchKernelGGL((k_tail<T, true>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, g, out,
+                       h->prm.relax == 1 ? 1 : 3, (T)h->prm.omega);
+    AH_LAUNCHED();
+    return AH_OK;
+  }
   if (l == nlev - 1) {
     if (L.n == 0) return AH_OK;
     hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)L.n), dim3(64), 0, st, (int)L.n, h->cinv, g, out, 1);
@@ -373,7 +575,7 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
   const int64_t n = h->lev[0].n;
   const int m = std::max(1, prm.restart);
   AH_TRY(ensure_workspace(h, m, prm.precision));
-  const int G0 = pick_g(h->lev[0].nnz, n);
+  const int G0 = h->g0 ? h->g0 : pick_g(h->lev[0].nnz, n);
   double* hd = h->hdev;
   double* hh = pinned_scratch(4 * (m + 3));
   if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
@@ -440,9 +642,12 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, k, h->V, n, h1, h->w, -1.0);
       AH_LAUNCHED();
       AH_TRY(multidot(n, k, h->V, h->w, h->partial, h2, st));
-      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, k, h->V, n, h2, h->w, -1.0);
-      AH_LAUNCHED();
-      AH_TRY(multidot(n, 0, h->V, h->w, h->partial, hn, st));
+      {
+        int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, DOT_T * 4)));
+        hipLaunchKernelGGL(k_maxpy_norm, dim3(nblk), dim3(DOT_T), 0, st, n, k, h->V, n, h2, h->w, h->partial, nblk);
+        hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, h->partial, hn, 0);
+        AH_LAUNCHED();
+      }
       AH_HIP(hipMemcpyAsync(hh, hd, (3 * (m + 2)) * sizeof(double), hipMemcpyDeviceToHost, st));
       AH_HIP(hipStreamSynchronize(st));
       const double w0 = std::sqrt(hh[k]);

@@ -60,6 +60,7 @@ struct AhLevel {
   int64_t nF = 0, nnzF = 0;    // F rows and their stored entries
   int8_t* cf = nullptr;        // 1 = C, 0 = F
   int32_t* pcol = nullptr;     // one-point interpolation: coarse column or -1
+  int32_t* clist = nullptr;    // fine index of each C point (coarse order)
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;
@@ -85,8 +86,26 @@ struct AhLevel {
   float* y32 = nullptr;
 };
 
+// Flat copy of a level's device pointers for the single-workgroup kernel
+// that runs the coarse end of a V-cycle.
+struct TailLevel {
+  int64_t n, nc;
+  const int64_t* rp; const int32_t* ci; const double* v; const float* v32;
+  const double* d; const float* d32;
+  const int8_t* cf; const int32_t* pcol;
+  const int64_t* Rp; const int32_t* Rc; const double* Rv; const float* Rv32;
+  const int64_t* ATp; const int32_t* ATc; const double* ATv; const float* ATv32;
+  const int64_t* RTp; const int32_t* RTc; const double* RTv; const float* RTv32;
+  const int64_t* PTp; const int32_t* PTc;
+  double *b, *x, *y;
+  float *b32, *x32, *y32;
+};
+
 struct ah_hier {
   const ah_system* sys = nullptr;
+  int tail0 = -1;              // first level handled by the single-workgroup tail kernel
+  int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
+  TailLevel* d_tail = nullptr; // device copy of every level's pointers
   ah::Arena arena;
   ah_air_params prm{};
   std::vector<AhLevel> lev;
