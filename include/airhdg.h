@@ -121,6 +121,20 @@ typedef struct {
 ah_status hdg_assemble(const ah_mesh* m, const ah_hdg_params* prm, double nu,
                        const double* a_vert, const double* f_q, const double* g_q,
                        void* stream, ah_system** out);
+/* Replace the Neumann data of an assembled system (Section 2.3: the data
+ * term on Neumann facets, i.e. the inflow u(t_n) on a slab's initial plane,
+ * Section 2.4).  g_q dev [nbf][nqf] as in hdg_assemble; only the rows of
+ * Neumann facets are read (NULL = 0).  Recomputes H = H0 + G(g_q) and
+ * H_hat = D_b^-1 H, where H0 is the right-hand side assembled without the
+ * Neumann term; the matrix, Dirichlet data and element data are unchanged,
+ * so a hierarchy built on the system stays valid.  This lets the system and
+ * its hierarchy of slab n+1 be built before slab n is solved.  Does not
+ * synchronize. */
+ah_status hdg_update_neumann(ah_system* s, const double* g_q, void* stream);
+/* Destroy: device memory is released with hipFreeAsync on the stream(s) it
+ * was allocated on (creation stream; the first solving stream for the
+ * solver workspace of a hierarchy).  Work that uses the object on any other
+ * stream must have completed, or be ordered before those streams, first. */
 void ah_system_destroy(ah_system* s);
 /* n_free = number of free facet DOFs; b = facet block size; nnz = stored
  * entries of the scaled level-0 matrix (exact zeros off the diagonal are not

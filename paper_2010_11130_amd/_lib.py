@@ -65,6 +65,7 @@ SIGNATURES = {
     "ah_system_export": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "hdg_reconstruct": (i32, [vp, vp, vp, vp]),
     "hdg_inflow_from_trace": (i32, [vp, vp, vp, vp, vp]),
+    "hdg_update_neumann": (i32, [vp, vp, vp]),
     "ah_air_defaults": (None, [C.POINTER(AirParams)]),
     "air_setup": (i32, [vp, C.POINTER(AirParams), vp, C.POINTER(vp), C.POINTER(SetupInfo)]),
     "ah_hier_destroy": (None, [vp]),

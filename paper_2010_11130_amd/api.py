@@ -147,6 +147,13 @@ class System:
               "hdg_inflow_from_trace")
         return g_q
 
+    def update_neumann(self, g_q):
+        """New Neumann (inflow) data: recompute H and H_hat from ``g_q``
+        without reassembling the matrix (``hdg_update_neumann``)."""
+        self._g = _dev(g_q)
+        check(lib().hdg_update_neumann(self.h, _p(self._g), _stream()), "hdg_update_neumann")
+        return self
+
     def grad(self, lam_fwd, lam_adj, a_vert=None, want_f=True):
         """dJ/df at the element quadrature points and dJ/dnu (``hdg_assemble_grad``)."""
         dq = torch.empty((self.mesh.ne, self.nq), dtype=torch.float64, device="cuda") if want_f else None

@@ -91,7 +91,6 @@ struct ElemSmem {
   double Cm[S::NL * S::NU];
   double Dd[(D + 1) * S::B * S::B];
   double F[S::NU];
-  double G[S::NL];
   double LD[S::NL];
   // quadrature scratch (integration phase) and condensation arrays (after
   // the factorization) share storage
@@ -216,7 +215,7 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
   const int NT = blockDim.x;
   for (int k = t; k < NU * NU; k += NT) sm.A[k] = 0.0;
   for (int k = t; k < NU; k += NT) sm.F[k] = 0.0;
-  for (int k = t; k < NL; k += NT) { sm.G[k] = 0.0; sm.LD[k] = 0.0; }
+  for (int k = t; k < NL; k += NT) sm.LD[k] = 0.0;
   __syncthreads();
   // ---- volume terms
   for (int q0 = 0; q0 < NQ; q0 += QC) {
@@ -344,11 +343,6 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
     }
     if (data) {
       for (int m = t; m < B; m += NT) {
-        if (isN) {
-          double acc = 0.0;
-          _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_W[q] * sm.qd.f_g[q] * a.fac_psi[q * B + m];
-          sm.G[lf * B + m] = acc;
-        }
         if (isD) {
           double acc = 0.0;
           _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += a.fac_proj[m * NQF + q] * sm.qd.f_g[q];
@@ -438,7 +432,8 @@ __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
     for (int k = t; k < NU; k += NT) a.Fv[e * NU + k] = sm.F[k];
   }
   elem_factor_solve<D, P>(a, sm);
-  // S_K = D_K - C_K A_K^-1 B_K, H_K = G_K - C_K A_K^-1 F_K
+  // S_K = D_K - C_K A_K^-1 B_K, H_K = -C_K A_K^-1 F_K (the Neumann term G_K
+  // is added per boundary facet by k_neumann)
   for (int idx = t; idx < NL * NL; idx += NT) {
     int r = idx / NL, c = idx % NL;
     double v = (r / B == c / B) ? sm.Dd[(r / B) * B * B + (r % B) * B + (c % B)] : 0.0;
@@ -446,7 +441,7 @@ __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
     sm.cd.Sk[idx] = v;
   }
   for (int r = t; r < NL; r += NT) {
-    double v = sm.G[r];
+    double v = 0.0;
     for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.cd.Xs[k * NR + NL];
     sm.cd.Hk[r] = v;
   }
@@ -606,6 +601,46 @@ __global__ void k_hhat(int64_t nfree, const double* __restrict__ dinv, const dou
   hhat[i] = v;
 }
 
+// Neumann term of the right-hand side (Section 2.3, the data term on the
+// initial plane and on Neumann facets): H = H0 + G with
+// G_f[m] = |F| sum_q w_q g_q psi_m(x_q) on every free boundary facet of
+// Neumann kind.  |F| from the Gram determinant of the facet's edges; the
+// facet rule weights sum to one.  One thread per (boundary facet, node);
+// each free facet occurs once, so the updates do not collide.
+template <int B>
+__global__ void k_neumann(int64_t nbf, int D, int nqf, const int32_t* __restrict__ bfacets,
+                          const int8_t* __restrict__ kind, const int32_t* __restrict__ free_rank,
+                          const int32_t* __restrict__ facet_vert, const double* __restrict__ vert,
+                          const double* __restrict__ fac_w, const double* __restrict__ fac_psi,
+                          const double* __restrict__ g_q, double* __restrict__ H) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * B) return;
+  const int64_t bf = idx / B;
+  const int m = (int)(idx % B);
+  const int32_t f = bfacets[bf];
+  if (kind[f] != 2) return;
+  const int32_t fr = free_rank[f];
+  if (fr < 0) return;
+  double X[3][3];
+  for (int s = 0; s < D; ++s)
+    for (int c = 0; c < D; ++c) X[s][c] = vert[(int64_t)facet_vert[(int64_t)f * D + s] * D + c];
+  double area;
+  if (D == 2) {
+    double e0 = X[1][0] - X[0][0], e1 = X[1][1] - X[0][1];
+    area = sqrt(e0 * e0 + e1 * e1);
+  } else {
+    double u[3], v[3];
+    for (int c = 0; c < 3; ++c) { u[c] = X[1][c] - X[0][c]; v[c] = X[2][c] - X[0][c]; }
+    double g00 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double g11 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double g01 = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    area = 0.5 * sqrt(fmax(g00 * g11 - g01 * g01, 0.0));
+  }
+  double acc = 0.0;
+  for (int q = 0; q < nqf; ++q) acc += fac_w[q] * g_q[bf * nqf + q] * fac_psi[q * B + m];
+  H[(int64_t)fr * B + m] += area * acc;
+}
+
 // Physical quadrature points (element rule and boundary-facet rule).
 __global__ void k_quad_points_elem(int64_t ne, int D, int nq, const double* __restrict__ vert,
                                    const int32_t* __restrict__ cell, const double* __restrict__ lam,
@@ -745,7 +780,6 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   const int64_t nfree = s->nfree;
   const int64_t n = nfree * B;
   Arena& ar = s->arena;
-  int threads = 128;
   hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), 64)), dim3(64), 0, st, nfree,
                      m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
   AH_LAUNCHED();
@@ -770,11 +804,40 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
                      cnt, s->d_rowptr, s->d_col, s->d_val);
   AH_LAUNCHED();
-  hipLaunchKernelGGL(k_hhat<B>, dim3(cdiv(std::max<int64_t>(n, 1), threads)), dim3(threads), 0, st, nfree, s->d_Dinv,
-                     s->d_H, s->d_Hhat);
-  AH_LAUNCHED();
   tmp.release();
   return AH_OK;
+}
+
+// H = H0 + Neumann term of g_q (NULL: none), then H_hat = D_b^-1 H.
+template <int B>
+static ah_status rhs_from_neumann(ah_system* s, const double* g_q, hipStream_t st) {
+  const ah_mesh* m = s->mesh;
+  const int64_t n = s->nfree * B;
+  if (n == 0) return AH_OK;
+  AH_HIP(hipMemcpyAsync(s->d_H, s->d_H0, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const int64_t nbf = (int64_t)m->bfacets.size();
+  if (g_q && nbf > 0) {
+    hipLaunchKernelGGL(k_neumann<B>, dim3((unsigned)cdiv(nbf * B, 128)), dim3(128), 0, st, nbf, m->D, s->nqf,
+                       m->d_bfacets, m->d_kind, m->d_free_rank, m->d_facet_vert, m->d_vert, s->tab.d_fac_w,
+                       s->tab.d_fac_psi, g_q, s->d_H);
+    AH_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_hhat<B>, dim3((unsigned)cdiv(n, 128)), dim3(128), 0, st, s->nfree, s->d_Dinv, s->d_H,
+                     s->d_Hhat);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+static ah_status rhs_dispatch(int b, ah_system* s, const double* g_q, hipStream_t st) {
+  switch (b) {
+    case 2: return rhs_from_neumann<2>(s, g_q, st);
+    case 3: return rhs_from_neumann<3>(s, g_q, st);
+    case 4: return rhs_from_neumann<4>(s, g_q, st);
+    case 6: return rhs_from_neumann<6>(s, g_q, st);
+    case 10: return rhs_from_neumann<10>(s, g_q, st);
+  }
+  set_error("unsupported facet block size %d", b);
+  return AH_EUNSUPPORTED;
 }
 
 static ah_status scale_dispatch(int b, ah_system* s, const ah_mesh* m, hipStream_t st, int* d_err) {
@@ -920,6 +983,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   Arena& ar = s->arena;
   if ((rc = ar.get(&s->d_bval, s->nnzb * t.b * t.b))) return fail(rc);
   if ((rc = ar.get(&s->d_H, s->n))) return fail(rc);
+  if ((rc = ar.get(&s->d_H0, s->n))) return fail(rc);
   if ((rc = ar.get(&s->d_Hhat, s->n))) return fail(rc);
   if ((rc = ar.get(&s->d_Dinv, s->nfree * t.b * t.b))) return fail(rc);
   if ((rc = ar.get(&s->d_lamD, m->nf * t.b))) return fail(rc);
@@ -933,7 +997,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   if ((rc = ar.get(&d_err, 1))) return fail(rc);
   if (hipMemsetAsync(d_err, 0, sizeof(int), st) != hipSuccess ||
       hipMemsetAsync(s->d_bval, 0, s->nnzb * t.b * t.b * sizeof(double), st) != hipSuccess ||
-      hipMemsetAsync(s->d_H, 0, s->n * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(s->d_H0, 0, s->n * sizeof(double), st) != hipSuccess ||
       hipMemsetAsync(s->d_lamD, 0, m->nf * t.b * sizeof(double), st) != hipSuccess) {
     set_error("hdg_assemble: memset failed");
     return fail(AH_EHIP);
@@ -946,7 +1010,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   a.nu = nu;
   a.alpha = s->alpha;
   a.bval = s->d_bval;
-  a.H = s->d_H;
+  a.H = s->d_H0;
   a.lamD = s->d_lamD;
   a.Ainv = s->d_Ainv;
   a.Bm = s->d_Bm;
@@ -955,6 +1019,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   a.err = d_err;
   if ((rc = element_dispatch(m->D, prm->p, a, st))) return fail(rc);
   if ((rc = scale_dispatch(t.b, s, m, st, d_err))) return fail(rc);
+  if ((rc = rhs_dispatch(t.b, s, g_q, st))) return fail(rc);
   int herr = 0;
   if ((rc = read_bytes(d_err, &herr, sizeof(int), st))) return fail(rc);
   if (herr) {
@@ -964,6 +1029,11 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   }
   *out = s;
   return AH_OK;
+}
+
+extern "C" ah_status hdg_update_neumann(ah_system* s, const double* g_q, void* stream) {
+  if (!s) { set_error("hdg_update_neumann: null system"); return AH_EINVAL; }
+  return rhs_dispatch(s->b, s, g_q, as_stream(stream));
 }
 
 extern "C" void ah_system_destroy(ah_system* s) { delete s; }

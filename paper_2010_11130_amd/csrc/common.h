@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,12 +40,17 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Stream-ordered device memory owned by a library object: requests are
 // carved (256-byte aligned) out of chunks of at least CHUNK bytes, so an
 // object makes a handful of allocation calls instead of one per buffer.
+// Stream-ordered bump allocator: chunks come from hipMallocAsync on the
+// arena's current stream and go back with hipFreeAsync on the stream each
+// chunk came from.  A chunk is only carved on the stream it was allocated
+// on; switching stream starts a new chunk.
 struct Arena {
   static constexpr size_t CHUNK = size_t(32) << 20;
-  std::vector<void*> ptrs;
+  std::vector<std::pair<void*, hipStream_t>> ptrs;
   char* cur = nullptr;
   size_t left = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // stream of the next allocations
+  hipStream_t cur_stream = nullptr;  // stream of the chunk being carved
   ah_status alloc(void** p, size_t bytes);
   template <class T>
   ah_status get(T** p, size_t count) {
@@ -127,6 +133,7 @@ struct ah_mesh {
   int64_t npair = 0;
   // device copies of the topology (uploaded once, hipMalloc'd)
   bool dev_ready = false;
+  std::mutex lazy_mu;                // guards the lazily built device data above
   double* d_vert = nullptr;
   int32_t* d_cell = nullptr;
   int32_t* d_elem_facet = nullptr;

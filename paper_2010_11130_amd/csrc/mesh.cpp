@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <unordered_map>
 
@@ -26,24 +27,52 @@ void set_error(const char* fmt, ...) {
   g_last_error = buf;
 }
 
+// The library's stream-ordered pool on the current device.  Freed memory
+// stays in the pool (release threshold at its maximum) instead of going back
+// to the driver at every synchronization, so the per-slab objects of a time
+// march reuse it without new mappings.
+static hipMemPool_t device_pool() {
+  static std::mutex mu;
+  static hipMemPool_t pools[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    pools[dev] = pool;
+  }
+  return pools[dev];
+}
+
 ah_status Arena::alloc(void** p, size_t bytes) {
   *p = nullptr;
   bytes = (std::max<size_t>(bytes, 16) + 255) & ~size_t(255);
+  if (stream != cur_stream) left = 0;
   if (bytes > left) {
     size_t want = std::max(bytes, CHUNK);
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, want, stream);
+    hipMemPool_t pool = device_pool();
+    hipError_t e = pool ? hipMallocFromPoolAsync(&q, want, pool, stream) : hipMallocAsync(&q, want, stream);
     if (e != hipSuccess) {
       set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
       return AH_ENOMEM;
     }
-    ptrs.push_back(q);
+    ptrs.emplace_back(q, stream);
     if (want > CHUNK) {          // dedicated chunk for a large buffer
       *p = q;
       return AH_OK;
     }
     cur = static_cast<char*>(q);
     left = want;
+    cur_stream = stream;
   }
   *p = cur;
   cur += bytes;
@@ -52,7 +81,7 @@ ah_status Arena::alloc(void** p, size_t bytes) {
 }
 
 void Arena::release() {
-  for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+  for (auto& c : ptrs) (void)hipFreeAsync(c.first, c.second);
   ptrs.clear();
   cur = nullptr;
   left = 0;
@@ -448,6 +477,7 @@ static ah_status up(T** d, const std::vector<T>& h, hipStream_t st) {
 
 // Upload the topology once (after the boundary kinds are set).
 ah_status mesh_upload(ah_mesh* m, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(m->lazy_mu);
   if (m->dev_ready) return AH_OK;
   AH_TRY(up(&m->d_vert, m->vert, st));
   AH_TRY(up(&m->d_cell, m->cell, st));
@@ -469,6 +499,7 @@ ah_status mesh_upload(ah_mesh* m, hipStream_t st) {
 // Pair this mesh's initial-plane boundary facets with src's final-plane
 // facets having the same spatial vertex coordinates.
 ah_status mesh_pair_time_planes(ah_mesh* m, const ah_mesh* src, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(m->lazy_mu);
   if (m->pair_src == src && m->d_pair) return AH_OK;
   const int D = m->D;
   auto on_plane = [](const ah_mesh* mm, int64_t f, double t) {

@@ -827,8 +827,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     }
     hipLaunchKernelGGL(k_diag, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, L.diag, L.diag32);
     CKH(hipGetLastError());
-    CK(ar.get(&L.b, n)); CK(ar.get(&L.x, n)); CK(ar.get(&L.y, n));
-    if (prm.fp32_cycle) { CK(ar.get(&L.b32, n)); CK(ar.get(&L.x32, n)); CK(ar.get(&L.y32, n)); }
+    CK(ar.get(&L.b, n)); CK(ar.get(&L.x, n)); CK(ar.get(&L.y, n)); CK(ar.get(&L.e, n));
+    if (prm.fp32_cycle) {
+      CK(ar.get(&L.b32, n)); CK(ar.get(&L.x32, n)); CK(ar.get(&L.y32, n)); CK(ar.get(&L.e32, n));
+    }
     if (n <= prm.max_coarse || l == prm.max_levels - 1) break;
     // strength
     uint8_t* strong = nullptr;

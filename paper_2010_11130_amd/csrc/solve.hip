@@ -405,6 +405,7 @@ struct Ops<double> {
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
+  static double* e(AhLevel& L) { return L.e; }
 };
 template <>
 struct Ops<float> {
@@ -416,11 +417,14 @@ struct Ops<float> {
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
+  static float* e(AhLevel& L) { return L.e32; }
 };
 
 // Forward cycle on level l: b -> out.  out must differ from b and from the
-// level's x buffer; callers pass the level's y buffer or an external vector.
-// The recursion writes the coarse correction into the coarse level's y.
+// level's sweep buffers x and y (the second F sweep writes its rows into out
+// while other rows still read y): callers pass the level's e buffer or an
+// external vector.  The recursion writes the coarse correction into the
+// coarse level's e.
 template <class T>
 static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   AhLevel& L = h->lev[l];
@@ -443,7 +447,7 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   const int GR = pick_g(L.nnzR, L.nc);
   AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
                                 (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
-  T* ec = Ops<T>::y(C);
+  T* ec = Ops<T>::e(C);
   AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
   // first sweep on the interpolated iterate P e_c (read through pcol), then
   // the remaining sweeps ping-pong between the level's x and y
@@ -451,12 +455,15 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   T* alt = Ops<T>::y(L);
   const int sets_ffc[3] = {0, 0, 1};   // F, F, C
   const T om = (T)h->prm.omega;
-  const char* tag = l == 0 ? (sizeof(T) == 8 ? "sweep0" : "sweep0_f32") : nullptr;
+  // level-0 timing tags, one per sweep kernel
+  static const char* const tags64[3] = {"relax0_f1", "relax0_f2", "relax0_c"};
+  static const char* const tags32[3] = {"relax0_f1_f32", "relax0_f2_f32", "relax0_c_f32"};
   // F sweeps over all rows (other rows copied); the second F sweep also
   // writes its F rows into out, so the closing C sweep visits the C rows
   // only (from the C-point list) and writes them into out
   for (int s = 0; s < nsw; ++s) {
     T* dst = (s == nsw - 1) ? out : alt;
+    const char* tag = l == 0 ? (sizeof(T) == 8 ? tags64[s] : tags32[s]) : nullptr;
     if (s == 0)
       AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om, dst,
                                          st, tag, sweep_bytes<T>(L, 0), L.pcol)));
@@ -532,10 +539,11 @@ static ah_status precond(ah_hier* h, const double* r, double* z, float* z32, int
 }
 
 // ------------------------------------------------------------ FGMRES
-static ah_status ensure_workspace(ah_hier* h, int m, int precision) {
+static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t st) {
   const int64_t n = h->lev[0].n;
   if (h->m_alloc >= m && (precision == 0 ? h->Z != nullptr : h->Z32 != nullptr)) return AH_OK;
   Arena& ar = h->arena;
+  ar.stream = st;   // the workspace is allocated on the solving stream
   if (h->m_alloc < m) {
     AH_TRY(ar.get(&h->V, (int64_t)(m + 1) * n));
     AH_TRY(ar.get(&h->w, n));
@@ -574,7 +582,7 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
                         hipStream_t st, ah_solve_info* info) {
   const int64_t n = h->lev[0].n;
   const int m = std::max(1, prm.restart);
-  AH_TRY(ensure_workspace(h, m, prm.precision));
+  AH_TRY(ensure_workspace(h, m, prm.precision, st));
   const int G0 = h->g0 ? h->g0 : pick_g(h->lev[0].nnz, n);
   double* hd = h->hdev;
   double* hh = pinned_scratch(4 * (m + 3));
@@ -747,7 +755,7 @@ extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, 
   hipStream_t st = as_stream(stream);
   const ah_system* s = h->sys;
   const int64_t n = s->n;
-  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision));
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st));
   const double* b = s->d_Hhat;
   if (rhs) {
     hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, rhs, h->bhat, 0);
@@ -771,7 +779,7 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
   hipStream_t st = as_stream(stream);
   const ah_system* s = h->sys;
   const int64_t n = s->n;
-  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision));
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st));
   double* mu = h->bhat;   // S_hat^T mu = g, then lam = D_b^-T mu
   AhLevel& L0 = h->lev[0];
   if (!L0.ATptr) {

@@ -16,6 +16,7 @@ struct ah_system {
   int64_t nnzb = 0;     // blocks of the free-facet pattern
   double* d_bval = nullptr;   // [nnzb][b][b] unscaled S
   double* d_H = nullptr;      // [n] unscaled H after Dirichlet elimination
+  double* d_H0 = nullptr;     // [n] the same without the Neumann term
   double* d_Hhat = nullptr;   // [n]
   double* d_Dinv = nullptr;   // [nfree][b][b]
   double* d_lamD = nullptr;   // [nf][b]
@@ -77,13 +78,16 @@ struct AhLevel {
   float* RTval32 = nullptr;
   int64_t* PTptr = nullptr;    // P^T: rows = coarse points, entries = fine points (weight 1)
   int32_t* PTcol = nullptr;
-  // cycle work vectors
+  // cycle work vectors; e receives the level's correction from the finer
+  // level's recursion, so it never aliases the sweep buffers x and y
   double* b = nullptr;
   double* x = nullptr;
   double* y = nullptr;
+  double* e = nullptr;
   float* b32 = nullptr;
   float* x32 = nullptr;
   float* y32 = nullptr;
+  float* e32 = nullptr;
 };
 
 // Flat copy of a level's device pointers for the single-workgroup kernel

@@ -282,3 +282,79 @@ def test_coarsest_solver_paths(max_coarse):
     z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
     zo = oair.vcycle(OH, r)
     assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+def test_update_neumann_reproduces_assembly():
+    """Assembling with other Neumann data and then setting the data with
+    hdg_update_neumann gives the right-hand side of a direct assembly bit for
+    bit (both routes add the Neumann term in the same kernel), and the
+    Neumann term matters (the other data give another right-hand side)."""
+    from paper_2010_11130_amd import System
+    v, c, prob, p = case("slab")
+    s1 = gpu_system(v, c, prob, p)
+    m, xe, xb, f, g, a = s1._keep_alive
+    kb = torch.as_tensor(m.kind[m.boundary_facets()], device="cuda")[:, None]
+    g_other = torch.where(kb == 2, torch.full_like(g, 0.37), g).contiguous()
+    s2 = System(m, p, prob.nu, a, f, g_other)
+    h_other = s2.export()["hhat"].clone()
+    s2.update_neumann(g)
+    e1, e2 = s1.export(), s2.export()
+    assert torch.equal(e1["hhat"], e2["hhat"])
+    assert torch.equal(e1["val"], e2["val"])
+    assert not torch.equal(h_other, e1["hhat"])
+    # the matrix did not change, so a hierarchy of s2 solves the new data
+    o = setup_problem(v, c, prob, p)
+    assert np.abs(e2["hhat"].cpu().numpy() - o.Hhat).max() <= 1e-12 * np.abs(o.Hhat).max()
+
+
+def _march_inputs(n, S, p, dt, prob):
+    from paper_2010_11130_amd import Mesh
+    from gpu_cases import boundary_data, kinds_for
+    from workloads import slab_prism_tet_mesh
+    v, c = slab_prism_tet_mesh(n, dt)
+    m = Mesh(v, c)
+    fv, _ = m.facets()
+    bf = m.boundary_facets()
+    isb = np.zeros(m.nf, dtype=bool)
+    isb[bf] = True
+    kinds = kinds_for(v, fv, isb)
+    m.set_bc(kinds)
+    _, xb0 = m.quad_points(p)
+    gs = []
+    for k in range(S):
+        xb = xb0.clone()
+        xb[..., 0] += k * dt
+        vs = v.copy()
+        vs[:, 0] += k * dt
+        gs.append(boundary_data(prob, vs, fv, bf, kinds, xb))
+    a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(v)), device="cuda")
+    return m, a, gs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pipelined_march_matches_sequential_and_oracle(precision):
+    """The two-stream march (slab k+1 assembled and set up on a second stream
+    while slab k solves) equals the sequential march bit for bit, and both
+    match the oracle's slab march."""
+    from paper_2010_11130_amd import SlabMarch
+    from workloads import slab_prism_tet_mesh
+    from workloads.problems import slab_hill
+    from oracle.drivers import solve_slabs
+    n, S, p, dt = 8, 5, 2, 1.0 / 64
+    prob = slab_hill(1e-4)
+    res = {}
+    for pipelined in (False, True):
+        m, a, gs = _march_inputs(n, S, p, dt, prob)
+        lams = []
+        march = SlabMarch(m, p, prob.nu, a, air_kw={"max_coarse": SMALL_COARSE, "fp32_cycle": precision},
+                          solve_kw={"tol": 1e-12, "precision": precision})
+        march.run(gs, pipelined=pipelined, on_slab=lambda k, s, h, x, info: lams.append(x.clone()))
+        torch.cuda.synchronize()
+        res[pipelined] = [x.cpu().numpy() for x in lams]
+        print("pipelined", pipelined, "slabs", len(lams), flush=True)
+    for k in range(S):
+        assert np.array_equal(res[False][k], res[True][k]), k
+    _, _, lo = solve_slabs(lambda k: slab_prism_tet_mesh(n, dt, t0=k * dt), S, prob, p, err=False)
+    tol = 1e-10 if precision == 0 else 1e-8
+    for k in range(S):
+        assert np.linalg.norm(res[True][k] - lo[k]) <= tol * np.linalg.norm(lo[k]), k
