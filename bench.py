@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the sequential pass that gives the stage split")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 10 times (HBM counter calibration)")
@@ -51,6 +53,11 @@ def parse():
                     help="only summarize the rocprofv3 CSV output found under DIR")
     ap.add_argument("--grid", type=int, default=0,
                     help="with --profile-summary: keep only dispatches of this grid size in counters")
+    ap.add_argument("--traffic", nargs=7, default=None,
+                    metavar=("TAG", "KERNEL_SUBSTR", "GRID", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                             "COPY_WRITE_DIR"),
+                    help="only print the HBM traffic record of one kernel from rocprofv3 --pmc FETCH_SIZE / "
+                         "WRITE_SIZE runs of the bench and of --copy-probe")
     return ap.parse_args()
 
 
@@ -145,6 +152,73 @@ def profile_summary(d, grid=0, top=25):
             print("%-14s %8d %16.1f %10d  %s" % (cn, n, v / n, g, name[:100]))
 
 
+KERNEL_SOURCES = {"element": "paper_2010_11130_amd/csrc/assemble.hip",
+                  "spmv0": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_f1": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_f2": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_c": "paper_2010_11130_amd/csrc/solve.hip",
+                  "rap0": "paper_2010_11130_amd/csrc/setup.hip"}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+
+
+def _sha256(path):
+    import hashlib
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _counter_mean(d, counter, substr, grid):
+    """Mean per-dispatch value of ``counter`` over dispatches of kernels whose
+    name contains ``substr`` (and of grid size ``grid`` if nonzero)."""
+    import csv
+    cc = _find(d, "counter_collection.csv")
+    tot, n = 0.0, 0
+    for r in csv.DictReader(open(cc)):
+        if r.get("Counter_Name") != counter or substr not in r.get("Kernel_Name", ""):
+            continue
+        g = int(float(r.get("Grid_Size") or r.get("Grid_Size_X") or 0))
+        if grid and g != grid:
+            continue
+        tot += float(r["Counter_Value"])
+        n += 1
+    return tot / n if n else None, n
+
+
+def traffic_record(tag, substr, grid, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """HBM bytes per dispatch of one kernel: FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch) scaled by what the same counters read for a plain device
+    copy of known size (``--copy-probe``)."""
+    grid = int(grid)
+    fk, nf = _counter_mean(fetch_dir, "FETCH_SIZE", substr, grid)
+    wk, nw = _counter_mean(write_dir, "WRITE_SIZE", substr, grid)
+    cf, _ = _counter_mean(copy_fetch_dir, "FETCH_SIZE", "copyBuffer", 0)
+    cw, _ = _counter_mean(copy_write_dir, "WRITE_SIZE", "copyBuffer", 0)
+    probe = 1024 * (1 << 20)          # bytes read and written by one --copy-probe 1024 launch
+    f_fac = probe / (cf * 1024.0)
+    w_fac = probe / (cw * 1024.0)
+    rec = {"tag": tag, "kernel_substr": substr, "grid": grid, "dispatches": [nf, nw],
+           "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+           "copy_probe_fetch_kib": cf, "copy_probe_write_kib": cw,
+           "fetch_factor": f_fac, "write_factor": w_fac,
+           "bytes_per_launch": fk * 1024.0 * f_fac + wk * 1024.0 * w_fac,
+           "source": KERNEL_SOURCES[tag], "source_sha256": _sha256(KERNEL_SOURCES[tag])}
+    print(json.dumps(rec))
+
+
+def measured_traffic(tag):
+    """Counter-measured HBM bytes per launch of ``tag``, or None when no
+    record exists or the kernel's source changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            recs = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = recs.get(tag)
+    if not rec or rec.get("source_sha256") != _sha256(rec["source"]):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def copy_probe(mib):
     """A plain device-to-device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters of the profiled kernels."""
@@ -227,7 +301,7 @@ def profile_totals(tags):
     return out
 
 
-def run_timed(march, precision, steps, warmup, tol):
+def run_timed(march, precision, steps, warmup, tol, sequential=True):
     """Pipelined march: ``warmup`` untimed passes, then ``steps`` timed ones
     with the library's per-kernel HIP-event timing on.  Then one sequential
     pass for the stage split (assembly / setup / solve)."""
@@ -247,6 +321,8 @@ def run_timed(march, precision, steps, warmup, tol):
     lib().ah_profile_enable(0)
     prof = profile_totals(PROFILE_TAGS)
     lib().ah_profile_reset()
+    if not sequential:
+        return (t1 - t0) / steps, None, None, prof, last
     stages = []
     t2 = time.perf_counter()
     march.step(precision, tol, pipelined=False, stages=stages)
@@ -287,12 +363,12 @@ def roofline(prof, p, D, ne):
         flops = element_flops(D, p) * ne
         ach = flops / sec / 1e12
         return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic(name), "flops_per_launch": flops,
                 "avg_launch_us": k["avg_us"]}
     ach = k["bytes"] / k["launches"] / sec / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": k["bytes"] / k["launches"],
-            "avg_launch_us": k["avg_us"]}
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+            "bytes_per_launch": k["bytes"] / k["launches"], "avg_launch_us": k["avg_us"]}
 
 
 def cpu_baseline(n, p, nu, tol, dt):
@@ -325,6 +401,9 @@ def main():
     if args.profile_summary:
         profile_summary(args.profile_summary, args.grid)
         return
+    if args.traffic:
+        traffic_record(*args.traffic)
+        return
     import torch
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -335,12 +414,15 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
     march = March(args.n, args.slabs, args.p, args.nu)
-    t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol)
+    seq = not args.no_sequential
+    t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol, seq)
     ndof_slab = last64[0].numel()
     total = ndof_slab * args.slabs
     value = total / t64
 
     def split(stages, tseq):
+        if stages is None:
+            return None, {}
         st = {k: 1e3 * sum(x[k] for x in stages) for k in ("assemble", "setup", "solve")}
         iters = [x["iters"] for x in stages]
         return st, {"stages_ms_per_step": st,
@@ -361,12 +443,14 @@ def main():
                                % (args.n, args.n, 6 * args.n * args.n, args.slabs, args.slabs, args.p, args.nu,
                                   args.tol),
                    "free_dofs_per_slab": ndof_slab, "slabs": args.slabs, "total_free_dofs": total},
-        "levels": stages64[0]["levels"], "op_complexity": stages64[0]["op_complexity"],
         "kernels": prof64,
     }
+    if stages64:
+        out["levels"] = stages64[0]["levels"]
+        out["op_complexity"] = stages64[0]["op_complexity"]
     out.update(extra)
     if not args.no_fp32:
-        t32, stages32, tseq32, prof32, last32 = run_timed(march, 1, args.steps, args.warmup, args.tol)
+        t32, stages32, tseq32, prof32, last32 = run_timed(march, 1, args.steps, args.warmup, args.tol, seq)
         _, extra32 = split(stages32, tseq32)
         err = (torch.linalg.norm(last32[0] - last64[0]) / torch.linalg.norm(last64[0])).item()
         out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
