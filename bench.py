@@ -27,8 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # kernels timed with HIP events inside the library (ah_profile_*)
-PROFILE_TAGS = ["element", "spmv0", "relax0_f1", "relax0_f2", "relax0_c", "relax0_f1_f32", "relax0_f2_f32",
-                "relax0_c_f32", "rap0"]
+PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "rap0"]
 METRIC = "DOF/s to 1e-8 rel. residual (setup+solve), FP32 vs FP64 V-cycle; HBM GB/s"
 
 
@@ -44,6 +43,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--builders", type=int, default=2,
+                    help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the sequential pass that gives the stage split")
     ap.add_argument("--quiet", action="store_true")
@@ -154,8 +155,7 @@ def profile_summary(d, grid=0, top=25):
 
 KERNEL_SOURCES = {"element": "paper_2010_11130_amd/csrc/assemble.hip",
                   "spmv0": "paper_2010_11130_amd/csrc/solve.hip",
-                  "relax0_f1": "paper_2010_11130_amd/csrc/solve.hip",
-                  "relax0_f2": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_f": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax0_c": "paper_2010_11130_amd/csrc/solve.hip",
                   "rap0": "paper_2010_11130_amd/csrc/setup.hip"}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
@@ -268,6 +268,7 @@ class March:
         self.g = torch.stack(g).contiguous()
         self.a = torch.as_tensor(self.prob.a(v), device="cuda").contiguous()
         self.nu = nu
+        self.builders = 2
         torch.cuda.synchronize()
 
     def step(self, precision, tol, pipelined=True, stages=None):
@@ -280,7 +281,7 @@ class March:
             out["U"] = s.reconstruct(x)
 
         m = SlabMarch(self.mesh, self.p, self.nu, self.a, air_kw={"fp32_cycle": 1 if precision else 0},
-                      solve_kw={"tol": tol, "precision": precision})
+                      solve_kw={"tol": tol, "precision": precision}, builders=self.builders)
         s, x, info = m.run([self.g[k] for k in range(self.slabs)], pipelined=pipelined, on_slab=keep_u,
                            stages=stages)
         self.torch.cuda.synchronize()
@@ -414,6 +415,7 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
     march = March(args.n, args.slabs, args.p, args.nu)
+    march.builders = args.builders
     seq = not args.no_sequential
     t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol, seq)
     ndof_slab = last64[0].numel()

@@ -137,7 +137,8 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 
 // One-point interpolation; for C points the lAIR row length 1 + |N_i| and
 // the number of R A P candidates of its coarse row (row lengths of A over
-// {i} and N_i); for F points the F-row statistics (count, entries).
+// {i} and N_i); for F points their list and the F-row statistics (count,
+// entries).
 // imax[0] = max |N_i|, imax[1] = max candidates; fst[0..1] = F rows, entries.
 // 16 lanes per row; the strongest C neighbour is the first in row order
 // (smallest column) within relative 1e-12 of the maximum.
@@ -146,7 +147,8 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
                                                   const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
                                                   const int64_t* __restrict__ cidx, int32_t* __restrict__ pcol,
                                                   int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
-                                                  int* __restrict__ imax, unsigned long long* __restrict__ fst) {
+                                                  int32_t* __restrict__ flist, int* __restrict__ imax,
+                                                  unsigned long long* __restrict__ fst) {
   const int g = (int)(threadIdx.x % PG);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
   int mmax = 0, cmax = 0;
@@ -192,6 +194,7 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
     }
     if (g == 0) {
       pcol[i] = first < k1 ? (int32_t)cidx[ci[first]] : -1;
+      flist[i - cidx[i]] = (int32_t)i;   // F points in increasing order
       fcnt += 1;
       fent += (unsigned long long)(k1 - k0);
     }
@@ -882,10 +885,11 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(ar.get(&L.pcol, n));
     CK(tmp.get(&rcnt, nc + 1));
     CK(ar.get(&clist, nc));
+    CK(ar.get(&L.flist, n - nc));
     L.clist = clist;
     CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
     hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
-                       rcnt, clist, d_int, d_fst + 2 * l);
+                       rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
     CK(ar.get(&L.Rptr, nc + 1));
     CK(scan_i32_to_i64(rcnt, L.Rptr, nc, st, tmp));
@@ -1025,20 +1029,17 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   // tail: the levels from the first one with at most tail_max rows are run
   // by one workgroup inside a single launch per cycle
   {
-    int64_t tail_max = 500;
+    int64_t tail_max = 4096;
     if (const char* e = std::getenv("AH_TAIL_MAX")) tail_max = std::atoll(e);
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
     if (h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();
-    h->tail0 = -1;
-    for (int l = 0; l < nl; ++l)
-      if (h->lev[l].n <= tail_max) { h->tail0 = l; break; }
     std::vector<TailLevel> tl(nl);
     for (int l = 0; l < nl; ++l) {
       const AhLevel& L = h->lev[l];
       TailLevel& T = tl[l];
       T = TailLevel{};
-      T.n = L.n; T.nc = L.nc;
+      T.n = L.n; T.nc = L.nc; T.nnz = L.nnz; T.nnzR = L.nnzR;
       T.rp = L.rowptr; T.ci = L.col; T.v = L.val; T.v32 = L.val32; T.d = L.diag; T.d32 = L.diag32;
       T.cf = L.cf; T.pcol = L.pcol;
       T.Rp = L.Rptr; T.Rc = L.Rcol; T.Rv = L.Rval; T.Rv32 = L.Rval32;
@@ -1047,6 +1048,28 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       T.PTp = L.PTptr; T.PTc = L.PTcol;
       T.b = L.b; T.x = L.x; T.y = L.y; T.b32 = L.b32; T.x32 = L.x32; T.y32 = L.y32;
     }
+    // the tail starts at the first level with at most tail_max rows whose
+    // levels, down to the coarsest, fit in LDS as an FP64 image
+    h->tail0 = -1;
+    h->tail_lds = false;
+    if (nl <= TAIL_MAX_LEVELS) {
+      for (int l = 0; l < nl; ++l) {
+        if (h->lev[l].n > tail_max) continue;
+        TailLds lo[TAIL_MAX_LEVELS];
+        int64_t oc = 0;
+        const int64_t b64 = tail_lds_layout<8>(tl.data(), l, nl, lo, &oc);
+        if (b64 <= TAIL_LDS_MAX) {
+          h->tail0 = l;
+          h->tail_lds = true;
+          h->tail_bytes[0] = b64;
+          h->tail_bytes[1] = tail_lds_layout<4>(tl.data(), l, nl, lo, &oc);
+          break;
+        }
+      }
+    }
+    if (h->tail0 < 0)   // no LDS image fits: small levels run from global memory
+      for (int l = 0; l < nl; ++l)
+        if (h->lev[l].n <= std::min<int64_t>(tail_max, 500)) { h->tail0 = l; break; }
     rc = ar.get(&h->d_tail, nl);
     if (rc < 0) { delete h; return rc; }
     double* pin = pinned_scratch((nl * sizeof(TailLevel) + 7) / 8);

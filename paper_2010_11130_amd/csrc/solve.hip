@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "prof.h"
 #include "system.h"
@@ -28,7 +29,8 @@ enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWE
 // MODE SP_SWEEP:   y_i = x_i + omega (b_i - (A x)_i) / d_i  for cf_i == X (all rows if cf null), else x_i
 // MODE SP_ADDMV:   y = b + A x
 // MODE SP_SWEEP_P: the sweep applied to the interpolated iterate x = P e,
-//                  read on the fly as x_j = e[pc[j]] (0 where pc[j] < 0)
+//                  read on the fly as x_j = e[pc[j]] (0 where pc[j] < 0);
+//                  rows outside X get x_i = e[pc[i]]
 // MODE SP_SWEEP_LIST: the sweep on the rows listed in pc[0..n) only; other
 //                  rows of y are not written
 // y2 (sweeps, optional): the updated rows are also written there.
@@ -51,14 +53,12 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
     const int64_t k1 = rp[i + 1];
     for (int64_t k = rp[i] + g; k < k1; k += G) {
       TY a = av ? (TY)av[k] : (TY)1;
-      TY xv;
       if (MODE == SP_SWEEP_P) {
-        int32_t c = pc[ci[k]];
-        xv = c >= 0 ? (TY)x[c] : (TY)0;
+        const int32_t c = pc[ci[k]];
+        acc += c >= 0 ? a * (TY)x[c] : (TY)0;
       } else {
-        xv = (TY)x[ci[k]];
+        acc += a * (TY)x[ci[k]];
       }
-      acc += a * xv;
     }
   }
 #pragma unroll
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   else {
     TY xi;
     if (MODE == SP_SWEEP_P) {
-      int32_t c = pc[i];
+      const int32_t c = pc[i];
       xi = c >= 0 ? (TY)x[c] : (TY)0;
     } else {
       xi = (TY)x[i];
@@ -116,6 +116,127 @@ __device__ inline T row_dot(const int64_t* rp, const int32_t* ci, const T* av, c
   T s = 0;
   for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += (av ? av[k] : (T)1) * x[ci[k]];
   return s;
+}
+
+// Forward coarse end of the cycle from an LDS image: every array of levels
+// l0 .. nlev-1 and the coarsest inverse are copied into LDS once, then the
+// restriction, coarsest solve, interpolation and F, F, C sweeps of all these
+// levels run out of LDS with workgroup barriers between the phases.  The
+// result of level l0 is written to out.
+template <class T>
+__device__ inline T row_dot_s(const int32_t* rp, const int32_t* ci, const T* av, const T* x, int i) {
+  T s = 0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s += av[k] * x[ci[k]];
+  return s;
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                                   const double* __restrict__ cinv, const T* __restrict__ b_in,
+                                                   T* __restrict__ out, int nsw, T omega) {
+  extern __shared__ __align__(16) char sm[];
+  __shared__ TailLds lo[TAIL_MAX_LEVELS];
+  __shared__ int64_t s_cinv;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  const int last = nlev - 1;
+  if (t == 0) {
+    int64_t oc = 0;
+    tail_lds_layout<(int)sizeof(T)>(lv, l0, nlev, lo, &oc);
+    s_cinv = oc;
+  }
+  __syncthreads();
+#define TL_PTR(type, l, f) reinterpret_cast<type*>(sm + lo[(l) - l0].f)
+  // stage the operators (independent loads, one barrier)
+  for (int l = l0; l < last; ++l) {
+    const TailLevel& L = lv[l];
+    const int n = (int)L.n, nc = (int)L.nc, nnz = (int)L.nnz, nnzR = (int)L.nnzR;
+    int32_t* rp = TL_PTR(int32_t, l, rp);
+    int32_t* ci = TL_PTR(int32_t, l, ci);
+    T* v = TL_PTR(T, l, v);
+    T* d = TL_PTR(T, l, d);
+    int8_t* cf = TL_PTR(int8_t, l, cf);
+    int32_t* pc = TL_PTR(int32_t, l, pc);
+    int32_t* Rp = TL_PTR(int32_t, l, Rp);
+    int32_t* Rc = TL_PTR(int32_t, l, Rc);
+    T* Rv = TL_PTR(T, l, Rv);
+    const T* Ag = TLv<T>::A(L);
+    const T* dg = TLv<T>::d(L);
+    const T* Rg = TLv<T>::R(L);
+    for (int i = t; i <= n; i += NT) rp[i] = (int32_t)L.rp[i];
+    for (int k = t; k < nnz; k += NT) { ci[k] = L.ci[k]; v[k] = Ag[k]; }
+    for (int i = t; i < n; i += NT) { d[i] = dg[i]; cf[i] = L.cf[i]; pc[i] = L.pcol[i]; }
+    for (int i = t; i <= nc; i += NT) Rp[i] = (int32_t)L.Rp[i];
+    for (int k = t; k < nnzR; k += NT) { Rc[k] = L.Rc[k]; Rv[k] = Rg[k]; }
+  }
+  const int nL = (int)lv[last].n;
+  double* ci_s = reinterpret_cast<double*>(sm + s_cinv);
+  for (int k = t; k < nL * nL; k += NT) ci_s[k] = cinv[k];
+  {
+    T* b0 = TL_PTR(T, l0, b);
+    for (int i = t; i < (int)lv[l0].n; i += NT) b0[i] = b_in[i];
+  }
+  __syncthreads();
+  // restriction down to the coarsest level
+  for (int l = l0; l < last; ++l) {
+    const int nc = (int)lv[l].nc;
+    const int32_t* Rp = TL_PTR(int32_t, l, Rp);
+    const int32_t* Rc = TL_PTR(int32_t, l, Rc);
+    const T* Rv = TL_PTR(T, l, Rv);
+    const T* b = TL_PTR(T, l, b);
+    T* cb = TL_PTR(T, l + 1, b);
+    for (int i = t; i < nc; i += NT) cb[i] = row_dot_s<T>(Rp, Rc, Rv, b, i);
+    __syncthreads();
+  }
+  // coarsest: y = C^-1 b (FP64 accumulation)
+  {
+    const T* b = TL_PTR(T, last, b);
+    T* z = TL_PTR(T, last, y);
+    for (int i = t; i < nL; i += NT) {
+      double s = 0.0;
+      for (int j = 0; j < nL; ++j) s += ci_s[i * nL + j] * (double)b[j];
+      z[i] = (T)s;
+    }
+    __syncthreads();
+  }
+  // up: x = P e_c, then the sweeps ping-pong x -> y -> x -> y
+  for (int l = last - 1; l >= l0; --l) {
+    const int n = (int)lv[l].n;
+    const int32_t* rp = TL_PTR(int32_t, l, rp);
+    const int32_t* ci = TL_PTR(int32_t, l, ci);
+    const T* v = TL_PTR(T, l, v);
+    const T* d = TL_PTR(T, l, d);
+    const int8_t* cf = TL_PTR(int8_t, l, cf);
+    const int32_t* pc = TL_PTR(int32_t, l, pc);
+    const T* bl = TL_PTR(T, l, b);
+    const T* ec = TL_PTR(T, l + 1, y);
+    T* cur = TL_PTR(T, l, x);
+    T* alt = TL_PTR(T, l, y);
+    for (int i = t; i < n; i += NT) cur[i] = pc[i] >= 0 ? ec[pc[i]] : (T)0;
+    __syncthreads();
+    for (int s = 0; s < nsw; ++s) {
+      const int X = (nsw == 1 || s < 2) ? 0 : 1;
+      T* dst = (s % 2 == 0) ? TL_PTR(T, l, y) : TL_PTR(T, l, x);
+      for (int i = t; i < n; i += NT) {
+        T xi = cur[i];
+        if (cf[i] == X) {
+          const T di = d[i];
+          if (fabs((double)di) >= 1e-30) xi += omega * (bl[i] - row_dot_s<T>(rp, ci, v, cur, i)) / di;
+        }
+        dst[i] = xi;
+      }
+      __syncthreads();
+      alt = cur;
+      cur = dst;
+    }
+    (void)alt;
+  }
+  // the level-l0 result is in y (odd number of sweeps) or in y (coarsest only)
+  {
+    const T* r = (l0 == last) ? TL_PTR(T, last, y) : TL_PTR(T, l0, y);
+    for (int i = t; i < (int)lv[l0].n; i += NT) out[i] = r[i];
+  }
+#undef TL_PTR
 }
 
 template <class T, bool TR>
@@ -224,6 +345,18 @@ __global__ void k_interp(int64_t n, const int32_t* __restrict__ pcol, const T* _
   if (i >= n) return;
   int32_t c = pcol[i];
   x[i] = c >= 0 ? ec[c] : (T)0;
+}
+
+// x = y = P e_c (one-point interpolation, both sweep buffers)
+template <class T>
+__global__ void k_interp2(int64_t n, const int32_t* __restrict__ pcol, const T* __restrict__ ec,
+                          T* __restrict__ x, T* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c = pcol[i];
+  T v = c >= 0 ? ec[c] : (T)0;
+  x[i] = v;
+  y[i] = v;
 }
 
 // z = C^-1 r (trans = 0) or C^-T r, FP64 coarsest solve; one wave per row.
@@ -431,8 +564,21 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   const int nlev = (int)h->lev.size();
   const int nsw = h->prm.relax == 1 ? 1 : 3;
   if (h->tail0 >= 0 && l >= h->tail0) {
-    hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, b, out, nsw,
-                       (T)h->prm.omega);
+    if (h->tail_lds) {
+      static std::once_flag once;
+      std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)k_tail_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)TAIL_LDS_MAX);
+        (void)hipFuncSetAttribute((const void*)k_tail_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)TAIL_LDS_MAX);
+      });
+      const int64_t bytes = h->tail_bytes[sizeof(T) == 8 ? 0 : 1];
+      hipLaunchKernelGGL((k_tail_lds<T>), dim3(1), dim3(1024), (unsigned)bytes, st, h->d_tail, l, nlev, h->cinv, b,
+                         out, nsw, (T)h->prm.omega);
+    } else {
+      hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, b, out, nsw,
+                         (T)h->prm.omega);
+    }
     AH_LAUNCHED();
     return AH_OK;
   }
@@ -449,33 +595,47 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                                 (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
   T* ec = Ops<T>::e(C);
   AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
-  // first sweep on the interpolated iterate P e_c (read through pcol), then
-  // the remaining sweeps ping-pong between the level's x and y
-  T* cur = nullptr;
-  T* alt = Ops<T>::y(L);
-  const int sets_ffc[3] = {0, 0, 1};   // F, F, C
   const T om = (T)h->prm.omega;
-  // level-0 timing tags, one per sweep kernel
-  static const char* const tags64[3] = {"relax0_f1", "relax0_f2", "relax0_c"};
-  static const char* const tags32[3] = {"relax0_f1_f32", "relax0_f2_f32", "relax0_c_f32"};
-  // F sweeps over all rows (other rows copied); the second F sweep also
-  // writes its F rows into out, so the closing C sweep visits the C rows
-  // only (from the C-point list) and writes them into out
-  for (int s = 0; s < nsw; ++s) {
-    T* dst = (s == nsw - 1) ? out : alt;
-    const char* tag = l == 0 ? (sizeof(T) == 8 ? tags64[s] : tags32[s]) : nullptr;
-    if (s == 0)
-      AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om, dst,
-                                         st, tag, sweep_bytes<T>(L, 0), L.pcol)));
-    else if (s == 1)
-      AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, 0, om, dst, st,
-                                       tag, sweep_bytes<T>(L, 0), nullptr, out)));
-    else
-      AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, L.nc, L.rowptr, L.col, Ops<T>::A(L), cur, b, Ops<T>::d(L), L.cf, 1, om,
-                                            out, st, tag, sweep_bytes<T>(L, 1), L.clist)));
-    alt = (s == 0) ? Ops<T>::x(L) : cur;
-    cur = dst;
+  const int64_t nF = L.n - L.nc;
+  if (l > 0) {
+    // coarse levels (launch-latency bound): the first F sweep reads P e_c
+    // through pcol and writes every row of y (C rows: P e_c); the second F
+    // sweep writes every row of x and its F rows into out; the C sweep
+    // visits the C points from their list and writes them into out
+    if (nsw == 1) {
+      AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om,
+                                         out, st, nullptr, 0.0, L.pcol)));
+      return AH_OK;
+    }
+    T* x = Ops<T>::x(L);
+    T* y = Ops<T>::y(L);
+    AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om, y,
+                                       st, nullptr, 0.0, L.pcol)));
+    AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), y, b, Ops<T>::d(L), L.cf, 0, om, x, st,
+                                     nullptr, 0.0, nullptr, out)));
+    AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, L.nc, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 1, om,
+                                          out, st, nullptr, 0.0, L.clist)));
+    return AH_OK;
   }
+  // level 0 (bandwidth bound): x = y = P e_c, then the F sweeps visit the F
+  // points only (from the F list) and the C sweep the C points only, so the
+  // C entries of x and y keep the interpolated values through the F sweeps:
+  // F1 x -> y, F2 y -> x (its rows also written into out), C x -> out.  With
+  // one F sweep, y is out.
+  T* x = Ops<T>::x(L);
+  T* y = nsw == 1 ? out : Ops<T>::y(L);
+  hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
+  AH_LAUNCHED();
+  // level-0 timing tags, one per sweep kernel and grid
+  const char* tf = sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
+  const char* tc = sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
+  AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,
+                                        st, tf, sweep_bytes<T>(L, 0), L.flist)));
+  if (nsw == 1) return AH_OK;
+  AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), y, b, Ops<T>::d(L), L.cf, 0, om, x,
+                                        st, tf, sweep_bytes<T>(L, 0), L.flist, out)));
+  AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, L.nc, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 1, om,
+                                        out, st, tc, sweep_bytes<T>(L, 1), L.clist)));
   return AH_OK;
 }
 

@@ -62,6 +62,7 @@ struct AhLevel {
   int8_t* cf = nullptr;        // 1 = C, 0 = F
   int32_t* pcol = nullptr;     // one-point interpolation: coarse column or -1
   int32_t* clist = nullptr;    // fine index of each C point (coarse order)
+  int32_t* flist = nullptr;    // fine index of each F point (increasing)
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;
@@ -93,7 +94,7 @@ struct AhLevel {
 // Flat copy of a level's device pointers for the single-workgroup kernel
 // that runs the coarse end of a V-cycle.
 struct TailLevel {
-  int64_t n, nc;
+  int64_t n, nc, nnz, nnzR;
   const int64_t* rp; const int32_t* ci; const double* v; const float* v32;
   const double* d; const float* d32;
   const int8_t* cf; const int32_t* pcol;
@@ -105,9 +106,58 @@ struct TailLevel {
   float *b32, *x32, *y32;
 };
 
+// Byte offsets of one level's arrays in the LDS image of the forward tail
+// cycle (row offsets and indices as int32, values and vectors of width W).
+struct TailLds {
+  int32_t rp, ci, v, d, cf, pc, Rp, Rc, Rv, b, x, y;
+};
+
+// Layout of levels l0 .. nlev-1 (the last one is the coarsest: vectors
+// only) followed by the coarsest inverse (FP64).  Every array starts on a
+// 16-byte boundary.  Returns the total size in bytes.
+template <int W>
+__host__ __device__ inline int64_t tail_lds_layout(const TailLevel* lv, int l0, int nlev, TailLds* o,
+                                                   int64_t* o_cinv) {
+  int64_t off = 0;
+  auto take = [&off](int64_t bytes) {
+    const int64_t r = off;
+    off += (bytes + 15) & ~int64_t(15);
+    return (int32_t)r;
+  };
+  for (int l = l0; l < nlev; ++l) {
+    const TailLevel& L = lv[l];
+    TailLds& q = o[l - l0];
+    q = TailLds{};
+    q.b = take(L.n * W);
+    q.x = take(L.n * W);
+    q.y = take(L.n * W);
+    if (l < nlev - 1) {
+      q.rp = take((L.n + 1) * 4);
+      q.ci = take(L.nnz * 4);
+      q.v = take(L.nnz * W);
+      q.d = take(L.n * W);
+      q.cf = take(L.n);
+      q.pc = take(L.n * 4);
+      q.Rp = take((L.nc + 1) * 4);
+      q.Rc = take(L.nnzR * 4);
+      q.Rv = take(L.nnzR * W);
+    }
+  }
+  const int64_t nL = lv[nlev - 1].n;
+  *o_cinv = take(nL * nL * 8);
+  return off;
+}
+
+// Largest LDS image the staged tail kernel may use (160 KiB per workgroup on
+// gfx950, less the kernel's static layout table).
+constexpr int64_t TAIL_LDS_MAX = 160 * 1024 - 4096;
+constexpr int TAIL_MAX_LEVELS = 32;
+
 struct ah_hier {
   const ah_system* sys = nullptr;
   int tail0 = -1;              // first level handled by the single-workgroup tail kernel
+  bool tail_lds = false;       // the forward tail runs from an LDS image of its levels
+  int64_t tail_bytes[2] = {0, 0};   // size of that image with FP64 / FP32 values
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
   TailLevel* d_tail = nullptr; // device copy of every level's pointers
   ah::Arena arena;

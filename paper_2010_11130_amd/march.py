@@ -6,13 +6,14 @@ hierarchy (``air_setup``, Section 3) and is solved by FGMRES (``air_solve``).
 
 Pipelined mode: the matrix of slab n+1 and therefore its hierarchy do not
 depend on slab n's solution -- only the Neumann rows of its right-hand side
-do.  A builder thread assembles and sets up slab n+1 on a second HIP stream
-while the calling thread solves slab n; the calling thread then writes the
-inflow rows (``hdg_inflow_from_trace``) and refreshes the right-hand side
-(``hdg_update_neumann``).  Both modes run the same kernels on the same data,
-so their results agree bit for bit.
+do.  Builder threads assemble and set up the next slabs, each on its own HIP
+stream, while the calling thread solves slab n; the calling thread then
+writes the inflow rows (``hdg_inflow_from_trace``) and refreshes the
+right-hand side (``hdg_update_neumann``).  Assembly and setup are bound by
+host synchronizations (sizes read back between phases), so two builders
+overlap each other's waits.  Both modes run the same kernels on the same
+data, so their results agree bit for bit.
 """
-import queue
 import threading
 import time
 
@@ -28,11 +29,15 @@ class SlabMarch:
     mesh:    a ``Mesh`` with boundary kinds set, or a sequence of them (one per slab)
     a_vert:  velocity at the vertices (device tensor), or a sequence (one per slab)
     air_kw:  ``Hierarchy`` options; solve_kw: ``Hierarchy.solve`` options
+    builders: pipelined mode, number of builder threads (each with its own
+              stream); slab k is built by thread k mod builders
     """
 
-    def __init__(self, mesh, p, nu, a_vert, f_q=None, alpha=0.0, air_kw=None, solve_kw=None, keep=True):
+    def __init__(self, mesh, p, nu, a_vert, f_q=None, alpha=0.0, air_kw=None, solve_kw=None, keep=True,
+                 builders=2):
         self.mesh, self.p, self.nu, self.a, self.f = mesh, p, float(nu), a_vert, f_q
         self.alpha, self.keep = alpha, keep
+        self.builders = builders
         self.air_kw = dict(air_kw or {})
         self.solve_kw = dict(solve_kw or {})
 
@@ -94,46 +99,55 @@ class SlabMarch:
             last = (s, x, info)
         return last
 
-    def _run_pipelined(self, g_slabs, on_slab, depth=1):
+    def _run_pipelined(self, g_slabs, on_slab):
         S = len(g_slabs)
+        nb = max(1, int(self.builders))
         main = torch.cuda.current_stream()
-        side = torch.cuda.Stream()          # default priority
-        ready = queue.Queue(maxsize=depth)
-        stop = threading.Event()
+        sides = [torch.cuda.Stream() for _ in range(nb)]      # default priority
+        cond = threading.Condition()
+        ready = {}              # slab -> (system, hierarchy, event) or exception
+        state = {"next": 0, "stop": False}
 
-        def hand_over(item):
-            while not stop.is_set():
-                try:
-                    ready.put(item, timeout=0.1)
-                    return
-                except queue.Full:
-                    pass
-
-        def builder():
+        def builder(j):
             try:
-                with torch.cuda.stream(side):
-                    for k in range(S):
-                        if stop.is_set():
-                            return
+                with torch.cuda.stream(sides[j]):
+                    for k in range(j, S, nb):
+                        with cond:
+                            # bounded lookahead: at most nb slabs built ahead
+                            while not state["stop"] and k - state["next"] > nb:
+                                cond.wait()
+                            if state["stop"]:
+                                return
                         s, h = self._build(k, g_slabs[k])
                         ev = torch.cuda.Event()
-                        ev.record(side)
-                        hand_over((k, s, h, ev))
+                        ev.record(sides[j])
+                        with cond:
+                            ready[k] = (s, h, ev)
+                            cond.notify_all()
             except BaseException as e:   # re-raised by the solving thread
-                hand_over((None, e, None, None))
+                with cond:
+                    ready[-1] = e
+                    cond.notify_all()
 
-        th = threading.Thread(target=builder, daemon=True)
-        # the builder reads the boundary data written on the calling stream
-        side.wait_stream(main)
-        th.start()
+        # the builders read the boundary data written on the calling stream
+        for sd in sides:
+            sd.wait_stream(main)
+        ths = [threading.Thread(target=builder, args=(j,), daemon=True) for j in range(nb)]
+        for th in ths:
+            th.start()
         prev = None
         held = None
         last = None
         try:
             for k in range(S):
-                kk, s, h, ev = ready.get()
-                if kk is None:
-                    raise s
+                with cond:
+                    while k not in ready and -1 not in ready:
+                        cond.wait()
+                    if -1 in ready:
+                        raise ready[-1]
+                    s, h, ev = ready.pop(k)
+                    state["next"] = k + 1
+                    cond.notify_all()
                 main.wait_event(ev)
                 x, info = self._solve(k, s, h, g_slabs[k], prev, on_slab)
                 # slab k-1's objects were last used before this solve's final
@@ -143,8 +157,12 @@ class SlabMarch:
                 held = (s, h)
                 last = (s, x, info)
         finally:
-            stop.set()
-            th.join()
-        # work of the side stream (the last build) is complete: the calling
-        # stream waited for its event
+            with cond:
+                state["stop"] = True
+                cond.notify_all()
+            for th in ths:
+                th.join()
+            ready.clear()
+        # every build the calling stream consumed was waited for through its
+        # event; builds not consumed (after an error) are dropped after join
         return last
