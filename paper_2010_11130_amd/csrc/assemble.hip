@@ -33,7 +33,6 @@ struct Sz {
   static constexpr int N1 = P + 2;
   static constexpr int NQ = D == 2 ? N1 * N1 : N1 * N1 * N1;
   static constexpr int NQF = D == 2 ? N1 : N1 * N1;
-  static constexpr int QC = NQ < 32 ? NQ : 32;
   static constexpr int NR = NL + 1 + NU;   // right-hand sides of the element solve
 };
 
@@ -58,6 +57,8 @@ struct ElemArgs {
   const double* fac_mu;
   const double* fac_psi;
   const double* fac_proj;
+  const double* ten_adv;   // [(D+1) D][nu nu] reference advection tensor
+  const double* ten_dif;   // [D D][nu nu] reference diffusion tensor
   double nu, alpha;
   double* bval;
   double* H;
@@ -92,28 +93,17 @@ struct ElemSmem {
   double Dd[(D + 1) * S::B * S::B];
   double F[S::NU];
   double LD[S::NL];
-  // quadrature scratch (integration phase) and condensation arrays (after
-  // the factorization) share storage
+  double vcoef[(D + 1) * D + D * D];   // beta_kr, then G_rs
+  // quadrature scratch of the integration phase
   struct Quad {
-    double q_phi[S::QC * S::NU];
-    double q_adv[S::QC * S::NU];
-    double q_gx[S::QC * S::NU * (D - 1)];
-    double q_W[S::QC];
-    double q_f[S::QC];
+    double q_wf[S::NQ];             // W_q f_q at the element points
     double f_phi[S::NQF * S::NU];
     double f_dn[S::NQF * S::NU];
     double f_cA[S::NQF], f_cB[S::NQF], f_cD[S::NQF], f_W[S::NQF], f_g[S::NQF];
+    double f_psi[S::NQF * S::B];    // facet basis at the facet points (staged)
+    double f_proj[S::B * S::NQF];   // facet L2 projection weights (staged)
   };
-  struct Cond {
-    double Xs[S::NU * S::NR];
-    double Sk[S::NL * S::NL];
-    double Hk[S::NL];
-  };
-  union {
-    Quad qd;
-    Cond cd;
-  };
-  int piv[S::NU];
+  Quad qd;
 };
 
 // Element geometry: inverse Jacobian, penalty, facet normals/areas.
@@ -210,81 +200,78 @@ template <int D, int P>
 __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e, double nu_eff, bool advect,
                                bool data) {
   using S = Sz<D, P>;
-  constexpr int NU = S::NU, NL = S::NL, B = S::B, NQ = S::NQ, NQF = S::NQF, QC = S::QC;
+  constexpr int NU = S::NU, NL = S::NL, B = S::B, NQ = S::NQ, NQF = S::NQF;
   const int t = threadIdx.x;
   const int NT = blockDim.x;
-  for (int k = t; k < NU * NU; k += NT) sm.A[k] = 0.0;
-  for (int k = t; k < NU; k += NT) sm.F[k] = 0.0;
   for (int k = t; k < NL; k += NT) sm.LD[k] = 0.0;
-  __syncthreads();
-  // ---- volume terms
-  for (int q0 = 0; q0 < NQ; q0 += QC) {
-    const int nqc = (NQ - q0) < QC ? (NQ - q0) : QC;
-    for (int idx = t; idx < nqc * NU; idx += NT) {
-      int q = idx / NU, i = idx % NU, qq = q0 + q;
-      double dphi[D];
-      for (int c = 0; c < D; ++c) dphi[c] = a.vol_dphi[((int64_t)qq * NU + i) * D + c];
-      double adv = 0.0;
-      if (advect) {
-        double ah[D];
-        ah[0] = 1.0;
-        for (int c = 1; c < D; ++c) {
-          double v = 0.0;
-          for (int k = 0; k <= D; ++k) v += a.vol_lam[qq * (D + 1) + k] * sm.av[k * (D - 1) + c - 1];
-          ah[c] = v;
-        }
-        for (int r = 0; r < D; ++r) {
-          double beta = 0.0;
-          for (int c = 0; c < D; ++c) beta += sm.Jinv[r * D + c] * ah[c];
-          adv += beta * dphi[r];
-        }
-      }
-      sm.qd.q_phi[q * NU + i] = a.vol_phi[qq * NU + i];
-      sm.qd.q_adv[q * NU + i] = adv;
-      for (int c = 1; c < D; ++c) {
-        double g = 0.0;
-        for (int r = 0; r < D; ++r) g += sm.Jinv[r * D + c] * dphi[r];
-        sm.qd.q_gx[(q * NU + i) * (D - 1) + c - 1] = g;
-      }
+  // ---- volume terms from the reference tensors (the element map and the
+  // velocity are affine on K): with a_k = (1, a at vertex k),
+  // beta_kr = (J^-1 a_k)_r and G_rs = sum over the spatial c of
+  // Jinv[r][c] Jinv[s][c],
+  //   A_ij = |det J| (nu sum_rs G_rs M^rs_ij - sum_kr beta_kr T^kr_ij),
+  //   F_i  = sum_q w_q |det J| f(x_q) phi_i(x_q).
+  if (t < (D + 1) * D) {
+    const int k = t / D, r = t % D;
+    double v = 0.0;
+    if (advect) {
+      v = sm.Jinv[r * D];
+      for (int c = 1; c < D; ++c) v += sm.Jinv[r * D + c] * sm.av[k * (D - 1) + c - 1];
     }
-    for (int q = t; q < nqc; q += NT) {
-      sm.qd.q_W[q] = a.vol_w[q0 + q] * sm.absdet;
-      sm.qd.q_f[q] = (data && a.f_q) ? a.f_q[e * NQ + q0 + q] : 0.0;
-    }
-    __syncthreads();
-    for (int idx = t; idx < NU * NU; idx += NT) {
-      int i = idx / NU, j = idx % NU;
-      double acc = 0.0;
-      _Pragma("unroll 4") for (int q = 0; q < nqc; ++q) {
-        double dif = 0.0;
-        for (int c = 0; c < D - 1; ++c) dif += sm.qd.q_gx[(q * NU + j) * (D - 1) + c] * sm.qd.q_gx[(q * NU + i) * (D - 1) + c];
-        acc += sm.qd.q_W[q] * (-sm.qd.q_phi[q * NU + j] * sm.qd.q_adv[q * NU + i] + nu_eff * dif);
-      }
-      sm.A[idx] += acc;
-    }
-    for (int i = t; i < NU; i += NT) {
-      double acc = 0.0;
-      _Pragma("unroll 4") for (int q = 0; q < nqc; ++q) acc += sm.qd.q_W[q] * sm.qd.q_f[q] * sm.qd.q_phi[q * NU + i];
-      sm.F[i] += acc;
-    }
-    __syncthreads();
+    sm.vcoef[t] = v;
+  } else if (t < (D + 1) * D + D * D) {
+    const int u = t - (D + 1) * D, r = u / D, s2 = u % D;
+    double g = 0.0;
+    for (int c = 1; c < D; ++c) g += sm.Jinv[r * D + c] * sm.Jinv[s2 * D + c];
+    sm.vcoef[t] = g;
   }
+  const bool has_f = data && a.f_q;
+  if (has_f)
+    for (int q = t; q < NQ; q += NT) sm.qd.q_wf[q] = a.vol_w[q] * sm.absdet * a.f_q[e * NQ + q];
+  __syncthreads();
+  for (int idx = t; idx < NU * NU; idx += NT) {
+    double adv = 0.0, dif = 0.0;
+    _Pragma("unroll") for (int kr = 0; kr < (D + 1) * D; ++kr)
+      adv += sm.vcoef[kr] * a.ten_adv[(size_t)kr * NU * NU + idx];
+    _Pragma("unroll") for (int rs = 0; rs < D * D; ++rs)
+      dif += sm.vcoef[(D + 1) * D + rs] * a.ten_dif[(size_t)rs * NU * NU + idx];
+    sm.A[idx] = sm.absdet * (nu_eff * dif - adv);
+  }
+  for (int i = t; i < NU; i += NT) {
+    double acc = 0.0;
+    if (has_f)
+      for (int q = 0; q < NQ; ++q) acc += sm.qd.q_wf[q] * a.vol_phi[q * NU + i];
+    sm.F[i] = acc;
+  }
+  __syncthreads();
   // ---- facet terms
+  for (int k = t; k < NQF * B; k += NT) {
+    sm.qd.f_psi[k] = a.fac_psi[k];
+    sm.qd.f_proj[k] = a.fac_proj[k];
+  }
   for (int lf = 0; lf <= D; ++lf) {
     const bool isN = sm.kindf[lf] == 2;
     const bool isD = sm.kindf[lf] == 1;
-    for (int idx = t; idx < NQF * NU; idx += NT) {
-      int q = idx / NU, i = idx % NU;
-      double lam[D + 1];
-      for (int k = 0; k <= D; ++k) lam[k] = 0.0;
-      for (int s = 0; s < D; ++s) lam[sm.loc[lf * D + s]] = a.fac_mu[q * D + s];
-      double xi[D], dv[D];
-      for (int c = 0; c < D; ++c) xi[c] = lam[c + 1];
-      double v = mono_eval<D>(a.mono[i], xi, dv);
-      double dn = 0.0;
-      for (int c = 0; c < D; ++c) dn += dv[c] * sm.eta[lf * D + c];
-      sm.qd.f_phi[q * NU + i] = v;
-      sm.qd.f_dn[q * NU + i] = dn;
+    {
+      constexpr int FPART = (NQF * 4 <= 64) ? 4 : (NQF * 2 <= 64 ? 2 : 1);
+      constexpr int FIPP = (NU + FPART - 1) / FPART;
+      for (int idx = t; idx < NQF * FPART; idx += NT) {
+        const int q = idx % NQF, part = idx / NQF;
+        double lam[D + 1];
+        for (int k = 0; k <= D; ++k) lam[k] = 0.0;
+        for (int s2 = 0; s2 < D; ++s2) lam[sm.loc[lf * D + s2]] = a.fac_mu[q * D + s2];
+        double xi[D];
+        for (int c = 0; c < D; ++c) xi[c] = lam[c + 1];
+        for (int ii = 0; ii < FIPP; ++ii) {
+          const int i = part * FIPP + ii;
+          if (i >= NU) break;
+          double dv[D];
+          double v = mono_eval<D>(a.mono[i], xi, dv);
+          double dn = 0.0;
+          for (int c = 0; c < D; ++c) dn += dv[c] * sm.eta[lf * D + c];
+          sm.qd.f_phi[q * NU + i] = v;
+          sm.qd.f_dn[q * NU + i] = dn;
+        }
+      }
     }
     for (int q = t; q < NQF; q += NT) {
       double lam[D + 1];
@@ -321,7 +308,7 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
       int i = idx / B, m = idx % B;
       double acc = 0.0;
       _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) {
-        double psi = a.fac_psi[q * B + m];
+        double psi = sm.qd.f_psi[q * B + m];
         acc += sm.qd.f_cB[q] * psi * sm.qd.f_phi[q * NU + i] + nu_eff * sm.qd.f_W[q] * psi * sm.qd.f_dn[q * NU + i];
       }
       sm.Bm[i * NL + lf * B + m] = acc;
@@ -330,7 +317,7 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
       int m = idx / NU, j = idx % NU;
       double acc = 0.0;
       _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) {
-        double psi = a.fac_psi[q * B + m];
+        double psi = sm.qd.f_psi[q * B + m];
         acc += -sm.qd.f_cA[q] * sm.qd.f_phi[q * NU + j] * psi + nu_eff * sm.qd.f_W[q] * sm.qd.f_dn[q * NU + j] * psi;
       }
       sm.Cm[(lf * B + m) * NU + j] = acc;
@@ -338,14 +325,14 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
     for (int idx = t; idx < B * B; idx += NT) {
       int m = idx / B, n = idx % B;
       double acc = 0.0;
-      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_cD[q] * a.fac_psi[q * B + m] * a.fac_psi[q * B + n];
+      _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_cD[q] * sm.qd.f_psi[q * B + m] * sm.qd.f_psi[q * B + n];
       sm.Dd[lf * B * B + idx] = acc;
     }
     if (data) {
       for (int m = t; m < B; m += NT) {
         if (isD) {
           double acc = 0.0;
-          _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += a.fac_proj[m * NQF + q] * sm.qd.f_g[q];
+          _Pragma("unroll 4") for (int q = 0; q < NQF; ++q) acc += sm.qd.f_proj[m * NQF + q] * sm.qd.f_g[q];
           sm.LD[lf * B + m] = acc;
         }
       }
@@ -354,71 +341,22 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
   }
 }
 
-// LU with partial pivoting of sm.A (in place, pivots in sm.piv) and the
-// solve of A X = [B | F | I] into sm.cd.Xs.
-template <int D, int P>
-__device__ void elem_factor_solve(const ElemArgs& a, ElemSmem<D, P>& sm) {
-  using S = Sz<D, P>;
-  constexpr int NU = S::NU, NL = S::NL, NR = S::NR;
-  const int t = threadIdx.x;
-  const int NT = blockDim.x;
-  for (int k = 0; k < NU; ++k) {
-    if (t == 0) {
-      int p = k;
-      double best = fabs(sm.A[k * NU + k]);
-      for (int r = k + 1; r < NU; ++r) {
-        double v = fabs(sm.A[r * NU + k]);
-        if (v > best) { best = v; p = r; }
-      }
-      sm.piv[k] = p;
-      if (!(best > 0.0) || !isfinite(best)) atomicOr(a.err, 1);
-    }
-    __syncthreads();
-    int p = sm.piv[k];
-    if (p != k)
-      for (int c = t; c < NU; c += NT) {
-        double x = sm.A[k * NU + c];
-        sm.A[k * NU + c] = sm.A[p * NU + c];
-        sm.A[p * NU + c] = x;
-      }
-    __syncthreads();
-    double d = sm.A[k * NU + k];
-    for (int r = k + 1 + t; r < NU; r += NT) sm.A[r * NU + k] /= d;
-    __syncthreads();
-    const int m = NU - k - 1;
-    for (int idx = t; idx < m * m; idx += NT) {
-      int r = k + 1 + idx / m, c = k + 1 + idx % m;
-      sm.A[r * NU + c] -= sm.A[r * NU + k] * sm.A[k * NU + c];
-    }
-    __syncthreads();
-  }
-  // one right-hand side per thread, solved in place in its column of Xs
-  for (int c = t; c < NR; c += NT) {
-    double* x = sm.cd.Xs + c;
-    for (int r = 0; r < NU; ++r)
-      x[r * NR] = c < NL ? sm.Bm[r * NL + c] : (c == NL ? sm.F[r] : (r == c - NL - 1 ? 1.0 : 0.0));
-    for (int k = 0; k < NU; ++k) {
-      int p = sm.piv[k];
-      double tmp = x[k * NR]; x[k * NR] = x[p * NR]; x[p * NR] = tmp;
-    }
-    for (int r = 1; r < NU; ++r) {
-      double v = x[r * NR];
-      for (int k = 0; k < r; ++k) v -= sm.A[r * NU + k] * x[k * NR];
-      x[r * NR] = v;
-    }
-    for (int r = NU - 1; r >= 0; --r) {
-      double v = x[r * NR];
-      for (int k = r + 1; k < NU; ++k) v -= sm.A[r * NU + k] * x[k * NR];
-      x[r * NR] = v / sm.A[r * NU + r];
-    }
-  }
-  __syncthreads();
+// Value of a double in lane src (uniform) for the whole wave.
+__device__ inline double wave_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
 }
+
+__device__ inline int wave_bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
 
 template <int D, int P>
 __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
   using S = Sz<D, P>;
   constexpr int NU = S::NU, NL = S::NL, B = S::B, NR = S::NR;
+  // columns of [A | B F I], lane l holds columns l + 64 u
+  constexpr int NC = NU + NR;
+  constexpr int CPL = (NC + 63) / 64;
   __shared__ ElemSmem<D, P> sm;
   const int64_t e = blockIdx.x;
   const int t = threadIdx.x;
@@ -431,49 +369,141 @@ __global__ __launch_bounds__(64) void k_element(ElemArgs a) {
     for (int k = t; k < NL * NU; k += NT) a.Cm[e * NL * NU + k] = sm.Cm[k];
     for (int k = t; k < NU; k += NT) a.Fv[e * NU + k] = sm.F[k];
   }
-  elem_factor_solve<D, P>(a, sm);
-  // S_K = D_K - C_K A_K^-1 B_K, H_K = -C_K A_K^-1 F_K (the Neumann term G_K
-  // is added per boundary facet by k_neumann)
-  for (int idx = t; idx < NL * NL; idx += NT) {
-    int r = idx / NL, c = idx % NL;
-    double v = (r / B == c / B) ? sm.Dd[(r / B) * B * B + (r % B) * B + (c % B)] : 0.0;
-    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.cd.Xs[k * NR + c];
-    sm.cd.Sk[idx] = v;
-  }
-  for (int r = t; r < NL; r += NT) {
-    double v = 0.0;
-    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * sm.cd.Xs[k * NR + NL];
-    sm.cd.Hk[r] = v;
-  }
-  __syncthreads();
-  // Dirichlet elimination: H_K -= S_K[:, Dirichlet] lambda_D
-  for (int r = t; r < NL; r += NT) {
-    double v = sm.cd.Hk[r];
-    for (int lf = 0; lf <= D; ++lf) {
-      if (sm.kindf[lf] != 1) continue;
-      for (int m = 0; m < B; ++m) v -= sm.cd.Sk[r * NL + lf * B + m] * sm.LD[lf * B + m];
+  // Gauss-Jordan with partial pivoting on [A | B F I] in registers: the
+  // pivot row and the pivot column are broadcast from the lane holding
+  // column k; no barriers.  Afterwards the columns right of A hold
+  // X = A^-1 [B | F | I].
+  double col[CPL][NU];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int c = t + 64 * u;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      double v = 0.0;
+      if (c < NU) v = sm.A[r * NU + c];
+      else if (c < NU + NL) v = sm.Bm[r * NL + (c - NU)];
+      else if (c == NU + NL) v = sm.F[r];
+      else if (c < NC) v = (r == c - NU - NL - 1) ? 1.0 : 0.0;
+      col[u][r] = v;
     }
-    sm.cd.Hk[r] = v;
   }
-  __syncthreads();
-  // scatter: <= 2 contributions per entry, so the atomic sums are order-independent
+  bool singular = false;
+  for (int k = 0; k < NU; ++k) {
+    // pivot search in column k (lane k, slot 0): first largest |a_rk|, r >= k
+    double best = -1.0;
+    int p = k;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      const double v = fabs(col[0][r]);
+      if (r >= k && v > best) { best = v; p = r; }
+    }
+    p = wave_bcast(p, k);
+    best = wave_bcast(best, k);
+    if (!(best > 0.0) || !isfinite(best)) singular = true;
+    // swap rows k and p (selects keep the register indices static)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      double vk = 0.0, vp = 0.0;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        vk = (r == k) ? col[u][r] : vk;
+        vp = (r == p) ? col[u][r] : vp;
+      }
+#pragma unroll
+      for (int r = 0; r < NU; ++r) col[u][r] = (r == k) ? vp : ((r == p) ? vk : col[u][r]);
+    }
+    // the pivot column, now in lane k
+    double f[NU];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) f[r] = wave_bcast(col[0][r], k);
+    double piv = 0.0;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) piv = (r == k) ? f[r] : piv;
+    const double inv = 1.0 / piv;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      double xk = 0.0;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) xk = (r == k) ? col[u][r] : xk;
+      xk *= inv;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) col[u][r] = (r == k) ? xk : col[u][r] - f[r] * xk;
+    }
+  }
+  if (singular && t == 0) atomicOr(a.err, 1);
+  // Dirichlet part: w = A^-1 B[:, Dir] lambda_D (broadcast from the lanes of
+  // the Dirichlet columns), then y = A^-1 F - w
+  double w[NU];
+#pragma unroll
+  for (int r = 0; r < NU; ++r) w[r] = 0.0;
+  for (int lf = 0; lf <= D; ++lf) {
+    if (sm.kindf[lf] != 1) continue;
+    for (int m = 0; m < B; ++m) {
+      const int c = NU + lf * B + m;
+      const int src = c & 63, us = c >> 6;
+      const double ld = sm.LD[lf * B + m];
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        double v = col[0][r];
+#pragma unroll
+        for (int u = 1; u < CPL; ++u) v = (us == u) ? col[u][r] : v;
+        w[r] += wave_bcast(v, src) * ld;
+      }
+    }
+  }
+  double y[NU];
+  {
+    const int c = NU + NL;
+    const int src = c & 63, us = c >> 6;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      double v = col[0][r];
+#pragma unroll
+      for (int u = 1; u < CPL; ++u) v = (us == u) ? col[u][r] : v;
+      y[r] = wave_bcast(v, src) - w[r];
+    }
+  }
+  // S_K = D_K - C_K A^-1 B_K column by column (lane of column NU + cc),
+  // scattered at once: <= 2 contributions per entry, so the atomic sums are
+  // order-independent
   const int32_t* slot = a.elem_slot + e * (D + 1) * (D + 1);
-  for (int idx = t; idx < NL * NL; idx += NT) {
-    int r = idx / NL, c = idx % NL;
-    int s = slot[(r / B) * (D + 1) + c / B];
-    if (s >= 0) unsafeAtomicAdd(&a.bval[(int64_t)s * B * B + (r % B) * B + (c % B)], sm.cd.Sk[idx]);
-  }
-  for (int r = t; r < NL; r += NT) {
-    int lf = r / B, f = sm.fid[lf];
-    int fr = a.free_rank[f];
-    if (fr >= 0) unsafeAtomicAdd(&a.H[(int64_t)fr * B + r % B], sm.cd.Hk[r]);
-    if (sm.kindf[lf] == 1) a.lamD[(int64_t)f * B + r % B] = sm.LD[r];
-  }
-  if (a.Ainv)
-    for (int k = t; k < NU * NU; k += NT) {
-      int r = k / NU, c = k % NU;
-      a.Ainv[e * NU * NU + k] = sm.cd.Xs[r * NR + NL + 1 + c];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int cc = t + 64 * u - NU;
+    if (cc < 0 || cc >= NL) continue;
+    const int cb = cc / B, cm = cc % B;
+    for (int r = 0; r < NL; ++r) {
+      const int rb = r / B, rm = r % B;
+      double v = (rb == cb) ? sm.Dd[rb * B * B + rm * B + cm] : 0.0;
+#pragma unroll
+      for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * col[u][k];
+      const int sl = slot[rb * (D + 1) + cb];
+      if (sl >= 0) unsafeAtomicAdd(&a.bval[(int64_t)sl * B * B + rm * B + cm], v);
     }
+  }
+  // H_K = -C_K (A^-1 F - A^-1 B[:,Dir] lambda_D) - D_K[:,Dir] lambda_D
+  for (int r = t; r < NL; r += NT) {
+    const int lf = r / B, rm = r % B;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) v -= sm.Cm[r * NU + k] * y[k];
+    if (sm.kindf[lf] == 1)
+      for (int n = 0; n < B; ++n) v -= sm.Dd[lf * B * B + rm * B + n] * sm.LD[lf * B + n];
+    const int f = sm.fid[lf];
+    const int fr = a.free_rank[f];
+    if (fr >= 0) unsafeAtomicAdd(&a.H[(int64_t)fr * B + rm], v);
+    if (sm.kindf[lf] == 1) a.lamD[(int64_t)f * B + rm] = sm.LD[r];
+  }
+  // kept element inverse: the identity columns now hold A^-1
+  if (a.Ainv) {
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int ci = t + 64 * u - NU - NL - 1;
+      if (ci < 0 || ci >= NU) continue;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) a.Ainv[e * NU * NU + r * NU + ci] = col[u][r];
+    }
+  }
 }
 
 // Inverse of each free facet's diagonal block (Gauss-Jordan, partial
@@ -870,6 +900,8 @@ static void fill_common(ElemArgs& a, const ah_mesh* m, const RefTables& t) {
   a.fac_mu = t.d_fac_mu;
   a.fac_psi = t.d_fac_psi;
   a.fac_proj = t.d_fac_proj;
+  a.ten_adv = t.d_ten_adv;
+  a.ten_dif = t.d_ten_dif;
   for (int i = 0; i < 20; ++i)
     for (int c = 0; c < 3; ++c) a.mono[i][c] = (i < t.nu && c < t.D) ? (int8_t)t.mono[i * t.D + c] : 0;
 }

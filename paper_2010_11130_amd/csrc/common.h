@@ -83,6 +83,11 @@ struct RefTables {
   std::vector<double> fac_proj;               // [b][nqf]  L2 projection onto P_p(F)
   std::vector<int> mono;                      // [nu][D] exponents of the element basis
   std::vector<double> lat_phi;                // [nu lattice nodes][nu] basis at element lattice
+  // reference tensors of the volume terms (affine element, velocity linear
+  // in each element), by the element rule:
+  //   ten_adv[k][r][i][j] = sum_q w_q lam_k phi_j d_r phi_i   (k <= D, r < D)
+  //   ten_dif[r][s][i][j] = sum_q w_q d_r phi_j d_s phi_i     (r, s < D)
+  std::vector<double> ten_adv, ten_dif;
   // device copies
   double* d_vol_w = nullptr;
   double* d_vol_lam = nullptr;
@@ -93,6 +98,8 @@ struct RefTables {
   double* d_fac_psi = nullptr;
   double* d_fac_proj = nullptr;
   double* d_lat_phi = nullptr;
+  double* d_ten_adv = nullptr;
+  double* d_ten_dif = nullptr;
 };
 
 ah_status build_ref_tables(int D, int p, RefTables& t);

@@ -304,6 +304,27 @@ ah_status build_ref_tables(int D, int p, RefTables& t) {
       for (int k = 0; k < t.b; ++k) v += M[m * t.b + k] * t.fac_psi[q * t.b + k] * t.fac_w[q];
       t.fac_proj[m * t.nqf + q] = v;
     }
+  // reference tensors of the volume terms
+  {
+    const int nu = t.nu, nn = nu * nu;
+    t.ten_adv.assign((size_t)(D + 1) * D * nn, 0.0);
+    t.ten_dif.assign((size_t)D * D * nn, 0.0);
+    for (int q = 0; q < t.nq; ++q) {
+      const double wq = t.vol_w[q];
+      const double* ph = &t.vol_phi[(size_t)q * nu];
+      const double* dp = &t.vol_dphi[(size_t)q * nu * D];
+      for (int i = 0; i < nu; ++i)
+        for (int j = 0; j < nu; ++j) {
+          for (int r = 0; r < D; ++r) {
+            const double gi = wq * dp[i * D + r] * ph[j];
+            for (int k = 0; k <= D; ++k)
+              t.ten_adv[((size_t)(k * D + r) * nn) + i * nu + j] += t.vol_lam[q * (D + 1) + k] * gi;
+            for (int s2 = 0; s2 < D; ++s2)
+              t.ten_dif[((size_t)(r * D + s2) * nn) + i * nu + j] += wq * dp[j * D + r] * dp[i * D + s2];
+          }
+        }
+    }
+  }
   // monomial basis at the element lattice nodes
   std::vector<int> elat;
   lattice(D, p, elat);
@@ -333,6 +354,8 @@ ah_status upload_ref_tables(RefTables& t, Arena& ar) {
   AH_TRY(upload(ar, t.fac_psi, &t.d_fac_psi));
   AH_TRY(upload(ar, t.fac_proj, &t.d_fac_proj));
   AH_TRY(upload(ar, t.lat_phi, &t.d_lat_phi));
+  AH_TRY(upload(ar, t.ten_adv, &t.d_ten_adv));
+  AH_TRY(upload(ar, t.ten_dif, &t.d_ten_dif));
   return AH_OK;
 }
 
