@@ -33,19 +33,29 @@ def problem_g(prob, mesh, kinds, t_min, t_max):
     return g
 
 
-def setup_problem(vert, cell, prob, p, alpha=None, g_fn=None):
+def setup_problem(vert, cell, prob, p, alpha=None, g_fn=None, block_scale=True):
     mesh = Mesh(vert, cell)
     t_min, t_max = float(mesh.vert[:, 0].min()), float(mesh.vert[:, 0].max())
     kinds = boundary_kinds(mesh.vert, mesh.facet_vert, mesh.is_boundary, t_min, t_max)
     if g_fn is None:
         g_fn = problem_g(prob, mesh, kinds, t_min, t_max)
-    sys = assemble(mesh, p, prob.nu, prob.a, prob.f, kinds, g_fn, alpha=alpha)
+    sys = assemble(mesh, p, prob.nu, prob.a, prob.f, kinds, g_fn, alpha=alpha, block_scale=block_scale)
     return sys
 
 
 def direct_solve(sys):
     """Sparse LU of the (unscaled) condensed free system ``S Lambda = H``."""
     return spla.spsolve(sys.S.tocsc(), sys.H)
+
+
+def air_bicgstab_solve(sys, air_params=None, tol=1e-8, maxit=1000, x0=None, hier=None):
+    """BiCGSTAB on ``S_hat Lambda = H_hat`` preconditioned on the right by one
+    lAIR V-cycle (the paper's solver, Section 4)."""
+    if hier is None:
+        hier = air.setup(sys.Shat, **(air_params or {}))
+    x, info = krylov.bicgstab(sys.Shat, sys.Hhat, lambda r: air.vcycle(hier, r), tol=tol, maxit=maxit, x0=x0)
+    info["hier"] = hier
+    return x, info
 
 
 def air_fgmres_solve(sys, air_params=None, tol=1e-8, restart=100, maxit=1000, x0=None,

@@ -112,7 +112,7 @@ class System:
     pass
 
 
-def assemble(mesh, p, nu, a_fn, f_fn, kinds, g_fn, alpha=None, chunk=4096, blocks_only=False):
+def assemble(mesh, p, nu, a_fn, f_fn, kinds, g_fn, alpha=None, chunk=4096, blocks_only=False, block_scale=True):
     """Element blocks, condensation, global facet system (Sections 2.3, 2.5).
 
     ``a_fn(X)`` -> ``[..., d]``, ``f_fn(X)`` -> ``[...]``; ``kinds[nf]`` in
@@ -209,7 +209,7 @@ def assemble(mesh, p, nu, a_fn, f_fn, kinds, g_fn, alpha=None, chunk=4096, block
         return sys
     _condense_and_assemble(sys)
     sys.lamD_full = lamD_full
-    _dirichlet_and_scale(sys)
+    _dirichlet_and_scale(sys, block_scale)
     return sys
 
 
@@ -242,9 +242,11 @@ def _condense_and_assemble(sys):
     sys.H_all = np.bincount(gd.ravel(), weights=HK.ravel(), minlength=N)
 
 
-def _dirichlet_and_scale(sys):
+def _dirichlet_and_scale(sys, block_scale=True):
     """Eliminate Dirichlet facets (``mu = 0`` there, Section 2.3) and scale on
-    the left by the inverse facet diagonal blocks (Section 4)."""
+    the left by the inverse facet diagonal blocks (Section 4).  With
+    ``block_scale=False`` (the "no block inverse" ablation of Section 4.1)
+    ``S_hat = S``, ``H_hat = H`` and ``Dinv`` holds identity blocks."""
     mesh, b = sys.mesh, sys.b
     isdir = sys.kinds == DIRICHLET
     free_f = np.nonzero(~isdir)[0]
@@ -267,6 +269,14 @@ def _dirichlet_and_scale(sys):
     blocks[rf[on], coo.row[on] % b, coo.col[on] % b] = coo.data[on]
     Dinv = np.linalg.inv(blocks)
     sys.Db, sys.Dinv = blocks, Dinv
+    if not block_scale:
+        sys.Dinv = np.broadcast_to(np.eye(b), (nfree, b, b)).copy()
+        Shat = S_ff.copy()
+        Shat.sort_indices()
+        sys.Shat = Shat
+        sys.Hhat = H.copy()
+        sys.n = n
+        return
     # scaled off-diagonal part + exact identity diagonal blocks
     off = sp.csr_matrix((coo.data[~on], (coo.row[~on], coo.col[~on])), shape=(n, n))
     bd_inv = sp.block_diag(list(Dinv), format="csr") if nfree else sp.csr_matrix((0, 0))

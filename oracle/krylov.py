@@ -69,3 +69,63 @@ def fgmres(A, b, M, tol=1e-8, restart=100, maxit=1000, x0=None):
         for i in range(k - 1, -1, -1):
             y[i] = (g[i] - Hs[i, i + 1:k] @ y[i + 1:k]) / Hs[i, i]
         x = x + Z[:k].T @ y
+
+
+def bicgstab(A, b, M, tol=1e-8, maxit=1000, x0=None):
+    """BiCGSTAB with right preconditioning (van der Vorst's method), the
+    Krylov accelerator the paper pairs with AIR (Section 4).
+
+    Each step applies the preconditioner twice: p_hat = M p, v = A p_hat,
+    alpha = rho / (r_hat, v), s = r - alpha v; s_hat = M s, t = A s_hat,
+    omega = (t, s) / (t, t), x += alpha p_hat + omega s_hat,
+    r = s - omega t.  Convergence when the recursively updated residual
+    (s after the first half, r after the second) satisfies
+    ||.|| <= tol ||b||; it is confirmed by the true residual, and the method
+    restarts from the current iterate (r_hat = r) if that check fails or
+    rho vanishes.  Iterations = BiCGSTAB steps (a step that converges on s
+    counts as one)."""
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.astype(np.float64).copy()
+    bnorm = np.linalg.norm(b)
+    hist = []
+    its = 0
+    if bnorm == 0.0:
+        return np.zeros(n), {"iters": 0, "converged": True, "relres": 0.0, "hist": hist}
+    while True:
+        r = b - A @ x
+        rel = np.linalg.norm(r) / bnorm
+        hist.append(rel)
+        if rel <= tol:
+            return x, {"iters": its, "converged": True, "relres": rel, "hist": hist}
+        if its >= maxit:
+            return x, {"iters": its, "converged": False, "relres": rel, "hist": hist}
+        rh = r.copy()
+        rho_old = alpha = omega = 1.0
+        p = np.zeros(n)
+        v = np.zeros(n)
+        while its < maxit:
+            rho = rh @ r
+            if rho == 0.0:
+                break                       # restart with r_hat = r
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            ph = M(p)
+            v = A @ ph
+            its += 1
+            rv = rh @ v
+            if rv == 0.0:
+                break
+            alpha = rho / rv
+            s = r - alpha * v
+            if np.linalg.norm(s) <= tol * bnorm:
+                x = x + alpha * ph
+                break
+            sh = M(s)
+            t = A @ sh
+            tt = t @ t
+            omega = (t @ s) / tt if tt > 0.0 else 0.0
+            x = x + alpha * ph + omega * sh
+            r = s - omega * t
+            rho_old = rho
+            if np.linalg.norm(r) <= tol * bnorm or omega == 0.0:
+                break

@@ -219,3 +219,64 @@ def test_pure_advection_air_converges():
     s = setup_problem(v, c, prob, 1)
     x, info = air_fgmres_solve(s, tol=1e-10)
     assert info["converged"] and info["iters"] <= 15
+
+
+def test_bicgstab_exact_preconditioner_one_step(c1_sys):
+    """With M = A^-1 the first half-step gives s = 0 (BiCGSTAB definition)."""
+    A = c1_sys.Shat
+    Ad = A.toarray()
+    inv = np.linalg.inv(Ad)
+    x, info = krylov.bicgstab(A, c1_sys.Hhat, lambda r: inv @ r, tol=1e-12)
+    assert info["converged"] and info["iters"] == 1
+    assert np.allclose(x, np.linalg.solve(Ad, c1_sys.Hhat), atol=1e-10)
+
+
+def test_bicgstab_unpreconditioned_matches_scipy():
+    """Without preconditioning the iteration is the textbook one; scipy's
+    implementation of the same method takes the same number of steps
+    (within one, for the placement of the convergence test) to the same
+    solution."""
+    from scipy.sparse.linalg import bicgstab as sp_bicgstab
+    rng = np.random.default_rng(4)
+    n = 60
+    A = sp.csr_matrix(np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3)
+    b = rng.standard_normal(n)
+    x, info = krylov.bicgstab(A, b, lambda r: r, tol=1e-10, maxit=500)
+    count = [0]
+    xs, flag = sp_bicgstab(A, b, rtol=1e-10, atol=0.0, maxiter=500, callback=lambda xk: count.__setitem__(0, count[0] + 1))
+    assert flag == 0 and info["converged"]
+    assert abs(info["iters"] - count[0]) <= 1, (info["iters"], count[0])
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_air_bicgstab_matches_direct(which, c1_sys, slab_sys):
+    from oracle.drivers import air_bicgstab_solve
+    s = c1_sys if which == "c1" else slab_sys
+    x, info = air_bicgstab_solve(s, tol=1e-12)
+    ref = direct_solve(s)
+    assert info["converged"]
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    _, i8f = air_fgmres_solve(s, tol=1e-8)
+    _, i8b = air_bicgstab_solve(s, tol=1e-8)
+    # two preconditioner applications per BiCGSTAB step
+    assert i8b["iters"] <= i8f["iters"] + 2
+
+
+def test_no_block_inverse_same_solution_more_iterations():
+    """Without the facet-block scaling the system is S itself; its solution
+    is the same Lambda, and AIR converges far worse on it (Section 4.1)."""
+    v, c = slab_prism_tet_mesh(6, 1 / 6)
+    prob = slab_hill(1e-3)
+    s1 = setup_problem(v, c, prob, 2)
+    s0 = setup_problem(v, c, prob, 2, block_scale=False)
+    assert np.array_equal(np.eye(s0.b)[None].repeat(s0.Dinv.shape[0], 0), s0.Dinv)
+    assert abs(s0.Shat - s1.S).max() == 0.0
+    l1, l0 = direct_solve(s1), direct_solve(s0)
+    assert np.linalg.norm(l1 - l0) <= 1e-12 * np.linalg.norm(l1)
+    x0, i0 = air_fgmres_solve(s0, tol=1e-8, maxit=200)
+    x1, i1 = air_fgmres_solve(s1, tol=1e-8)
+    # with Jacobi relaxation the unscaled system stalls (relres ~0.7 after
+    # 200 iterations); the scaled one converges in about a dozen
+    assert i1["converged"] and i1["iters"] < 20
+    assert not i0["converged"] or i0["iters"] > 3 * i1["iters"]
