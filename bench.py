@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bicgstab", action="store_true",
+                    help="skip the BiCGSTAB march and the no-block-inverse ablation")
     ap.add_argument("--builders", type=int, default=2,
                     help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
@@ -271,17 +273,20 @@ class March:
         self.builders = 2
         torch.cuda.synchronize()
 
-    def step(self, precision, tol, pipelined=True, stages=None):
+    def step(self, precision, tol, pipelined=True, stages=None, method=0, iters=None):
         """One pass of the march over all slabs: per slab assembly, lAIR
-        setup, FGMRES to ``tol`` and reconstruction of u_h."""
+        setup, the Krylov solve to ``tol`` (FGMRES, or BiCGSTAB with
+        method=1) and reconstruction of u_h."""
         from paper_2010_11130_amd import SlabMarch
         out = {}
 
         def keep_u(k, s, h, x, info):
             out["U"] = s.reconstruct(x)
+            if iters is not None:
+                iters.append(info["iters"])
 
         m = SlabMarch(self.mesh, self.p, self.nu, self.a, air_kw={"fp32_cycle": 1 if precision else 0},
-                      solve_kw={"tol": tol, "precision": precision}, builders=self.builders)
+                      solve_kw={"tol": tol, "precision": precision, "method": method}, builders=self.builders)
         s, x, info = m.run([self.g[k] for k in range(self.slabs)], pipelined=pipelined, on_slab=keep_u,
                            stages=stages)
         self.torch.cuda.synchronize()
@@ -458,6 +463,26 @@ def main():
         out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
                              "last_slab_rel_diff_vs_fp64": err, "kernels": prof32}
         out["fp32_cycle"].update(extra32)
+    # the paper's Krylov method: BiCGSTAB steps (two V-cycles each), same march
+    if not args.no_bicgstab:
+        march.step(0, args.tol, method=1)
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            its.clear()
+            march.step(0, args.tol, method=1, iters=its)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.steps
+        out["bicgstab"] = {"value": total / tb, "ms_per_step": 1e3 * tb,
+                           "steps_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+        # ablation (Section 4.1): AIR on the system without the facet-block
+        # scaling, slab 0, FGMRES capped at 100 iterations
+        from paper_2010_11130_amd import System, Hierarchy
+        s0 = System(march.mesh, args.p, args.nu, march.a, None, march.g[0], block_scale=False)
+        x0, i0 = Hierarchy(s0).solve(tol=args.tol, maxit=100)
+        out["no_block_inverse_slab0"] = {"converged": i0["converged"], "iters": i0["iters"],
+                                         "relres": i0["true_relres"]}
     # dominant tagged kernel of the FP64 march
     if prof64:
         out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])

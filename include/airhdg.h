@@ -116,6 +116,8 @@ typedef struct {
   int p;
   double alpha;
   int keep_element_data;   /* nonzero: keep blocks for reconstruct/adjoint */
+  int no_block_scale;      /* nonzero: S_hat = S, H_hat = H, D_b^-1 = I (the
+                              "no block inverse" ablation of Section 4.1) */
 } ah_hdg_params;
 
 ah_status hdg_assemble(const ah_mesh* m, const ah_hdg_params* prm, double nu,
@@ -208,7 +210,7 @@ ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_
                                int32_t* r_col, double* r_val, void* stream);
 
 /* ---------------------------------------------------------- air_solve ---
- * FGMRES(restart) with right preconditioning by one V-cycle (no
+ * method 0: FGMRES(restart) with right preconditioning by one V-cycle (no
  * pre-relaxation, post-relaxation F,F,C; Section 4) on S_hat x = D_b^-1 rhs.
  * rhs dev [n_free] unscaled, or NULL for the assembled H; x dev [n_free]
  * (initial guess if x0_given, else zero; overwritten by the solution).
@@ -216,13 +218,19 @@ ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_
  * recurrence and confirmed by a true residual in FP64 (restart otherwise).
  * precision 1: the V-cycle runs in FP32 (FP32 operators, FP32 accumulation)
  * inside the FP64 FGMRES; the coarsest solve stays FP64.  Returns AH_ENOCONV
- * if maxit is reached (x holds the best iterate), AH_EBREAKDOWN on NaN. */
+ * if maxit is reached (x holds the best iterate), AH_EBREAKDOWN on NaN.
+ * method 1: BiCGSTAB with right preconditioning by one V-cycle per half
+ * step (the paper's Krylov method, Section 4); convergence on the
+ * recursively updated residual, confirmed by the true residual, restart
+ * from the current iterate on breakdown; iters counts BiCGSTAB steps (two
+ * V-cycles each). */
 typedef struct {
   double tol;       /* default 1e-8 */
   int restart;      /* default 100 */
   int maxit;        /* default 1000 */
   int precision;    /* 0 FP64 cycle, 1 FP32 cycle */
   int x0_given;
+  int method;       /* 0 FGMRES(restart), 1 BiCGSTAB (restart unused) */
 } ah_solve_params;
 
 typedef struct {

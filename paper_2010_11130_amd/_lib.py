@@ -16,7 +16,8 @@ STATUS_NAMES = {0: "AH_OK", 1: "AH_ENOCONV", -1: "AH_EINVAL", -2: "AH_ESINGULAR"
 
 
 class HdgParams(C.Structure):
-    _fields_ = [("p", C.c_int), ("alpha", C.c_double), ("keep_element_data", C.c_int)]
+    _fields_ = [("p", C.c_int), ("alpha", C.c_double), ("keep_element_data", C.c_int),
+                ("no_block_scale", C.c_int)]
 
 
 class AirParams(C.Structure):
@@ -32,7 +33,7 @@ class SetupInfo(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
-                ("precision", C.c_int), ("x0_given", C.c_int)]
+                ("precision", C.c_int), ("x0_given", C.c_int), ("method", C.c_int)]
 
 
 class SolveInfo(C.Structure):

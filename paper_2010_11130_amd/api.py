@@ -97,7 +97,7 @@ class Mesh:
 class System:
     """Assembled, condensed and scaled facet system (``hdg_assemble``)."""
 
-    def __init__(self, mesh, p, nu, a_vert, f_q=None, g_q=None, alpha=0.0, keep=True):
+    def __init__(self, mesh, p, nu, a_vert, f_q=None, g_q=None, alpha=0.0, keep=True, block_scale=True):
         if mesh.kind is None:
             raise ValueError("boundary kinds not set (Mesh.set_bc)")
         self.mesh = mesh
@@ -106,7 +106,7 @@ class System:
         self._a = _dev(a_vert)
         self._f = _dev(f_q)
         self._g = _dev(g_q)
-        prm = HdgParams(p, float(alpha), 1 if keep else 0)
+        prm = HdgParams(p, float(alpha), 1 if keep else 0, 0 if block_scale else 1)
         h = C.c_void_p()
         check(lib().hdg_assemble(mesh.h, C.byref(prm), float(nu), _p(self._a), _p(self._f), _p(self._g),
                                  _stream(), C.byref(h)), "hdg_assemble")

@@ -571,7 +571,8 @@ __global__ __launch_bounds__(64) void k_diag_inv(int64_t nfree, const int64_t* _
 
 // Scaled scalar rows: row R*B+m of D_b^-1 S over the block row R; the
 // diagonal block becomes the identity; exact zeros off the diagonal are
-// dropped.  One wave per scalar row: lane c handles candidate (block c/B,
+// dropped.  unscaled: the rows of S itself (the diagonal entry is always
+// kept).  One wave per scalar row: lane c handles candidate (block c/B,
 // node c%B), kept entries are packed in order with a ballot, so a row's
 // stores are contiguous.  Count pass (val == nullptr), then fill pass.
 template <int B>
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
                                                     const int32_t* __restrict__ bcol, const double* __restrict__ bval,
                                                     const double* __restrict__ dinv, int32_t* __restrict__ cnt,
                                                     const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                    double* __restrict__ val) {
+                                                    double* __restrict__ val, int unscaled) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= nfree * B) return;
@@ -599,9 +600,12 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
       const int n = cidx % B;
       const int32_t C = bcol[s];
       colv = (int32_t)(C * B + n);
-      if (C == R) {
+      if (C == R && !unscaled) {
         v = n == m ? 1.0 : 0.0;
         keep = n == m;
+      } else if (unscaled) {
+        v = bval[s * B * B + m * B + n];
+        keep = v != 0.0 || (C == R && n == m);
       } else {
 #pragma unroll
         for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * bval[s * B * B + k * B + n];
@@ -617,6 +621,14 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
     c0 += __popcll(mask);
   }
   if (!val && lane == 0) cnt[i] = c0;
+}
+
+template <int B>
+__global__ void k_ident_blocks(int64_t nfree, double* __restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfree * B * B) return;
+  const int k = (int)(i % (B * B));
+  dinv[i] = (k / B == k % B) ? 1.0 : 0.0;
 }
 
 template <int B>
@@ -810,8 +822,12 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   const int64_t nfree = s->nfree;
   const int64_t n = nfree * B;
   Arena& ar = s->arena;
-  hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), 64)), dim3(64), 0, st, nfree,
-                     m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
+  if (s->unscaled)
+    hipLaunchKernelGGL(k_ident_blocks<B>, dim3(cdiv(std::max<int64_t>(nfree * B * B, 1), 256)), dim3(256), 0, st,
+                       nfree, s->d_Dinv);
+  else
+    hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), 64)), dim3(64), 0, st, nfree,
+                       m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
   AH_LAUNCHED();
   int32_t* cnt = nullptr;
   Arena tmp;
@@ -820,7 +836,7 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   AH_TRY(ar.get(&s->d_rowptr, n + 1));
   const dim3 gw((unsigned)cdiv(std::max<int64_t>(n, 1) * 64, 256));
   hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr);
+                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int)s->unscaled);
   AH_LAUNCHED();
   AH_TRY(scan_i32_to_i64(cnt, s->d_rowptr, n, st, tmp));
   AH_TRY(read_i64(s->d_rowptr + n, &s->nnz, st));
@@ -832,7 +848,7 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   AH_TRY(ar.get(&s->d_col, s->nnz));
   AH_TRY(ar.get(&s->d_val, s->nnz));
   hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, s->d_rowptr, s->d_col, s->d_val);
+                     cnt, s->d_rowptr, s->d_col, s->d_val, (int)s->unscaled);
   AH_LAUNCHED();
   tmp.release();
   return AH_OK;
@@ -1003,6 +1019,7 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   s->visc = nu;
   s->alpha = prm->alpha > 0.0 ? prm->alpha : 10.0 * prm->p * prm->p;
   s->keep = prm->keep_element_data != 0;
+  s->unscaled = prm->no_block_scale != 0;
   auto fail = [&](ah_status code) { delete s; return code; };
   ah_status rc = build_ref_tables(m->D, prm->p, s->tab);
   if (rc) return fail(rc);

@@ -720,6 +720,80 @@ static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t 
   return AH_OK;
 }
 
+// ---------------------------------------------------------- BiCGSTAB
+// Device scalars: [0] rho = r_hat.r, [1] r.r, [2] r_hat.v, [3] v.v,
+// [4] s.t, [5] t.t, [6] s.s, [7] r.r after the step, [8] rho_old,
+// [9] alpha, [10] omega.
+enum { BC_RHO = 0, BC_RV = 2, BC_ST = 4, BC_TT = 5, BC_SS = 6, BC_RR = 7, BC_RHOOLD = 8, BC_ALPHA = 9,
+       BC_OMEGA = 10, BC_N = 11 };
+
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
+__global__ void k_bicg_p(int64_t n, const double* __restrict__ r, const double* __restrict__ v,
+                         double* __restrict__ p, const double* __restrict__ sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = (sc[BC_RHO] / sc[BC_RHOOLD]) * (sc[BC_ALPHA] / sc[BC_OMEGA]);
+  p[i] = r[i] + beta * (p[i] - sc[BC_OMEGA] * v[i]);
+}
+
+// alpha = rho / (r_hat.v), s = r - alpha v, block partial sums of s.s
+__global__ __launch_bounds__(256) void k_bicg_s(int64_t n, const double* __restrict__ r,
+                                                const double* __restrict__ v, double* __restrict__ s,
+                                                double* __restrict__ sc, double* __restrict__ partial, int nblk) {
+  __shared__ double red[4];
+  const double alpha = sc[BC_RHO] / sc[BC_RV];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+    const double si = r[i] - alpha * v[i];
+    s[i] = si;
+    acc += si * si;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (blockIdx.x == 0) sc[BC_ALPHA] = alpha;
+  }
+}
+
+// x += alpha p_hat (the step ended on s)
+__global__ void k_bicg_xhalf(int64_t n, const double* __restrict__ ph, double* __restrict__ x,
+                             const double* __restrict__ sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += sc[BC_ALPHA] * ph[i];
+}
+
+// omega = (t.s) / (t.t), x += alpha p_hat + omega s_hat, r = s - omega t,
+// block partial sums of r.r; rho_old = rho
+__global__ __launch_bounds__(256) void k_bicg_xr(int64_t n, const double* __restrict__ ph,
+                                                 const double* __restrict__ sh, const double* __restrict__ s,
+                                                 const double* __restrict__ t, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ sc,
+                                                 double* __restrict__ partial, int nblk) {
+  __shared__ double red[4];
+  const double tt = sc[BC_TT];
+  const double omega = tt > 0.0 ? sc[BC_ST] / tt : 0.0;
+  const double alpha = sc[BC_ALPHA];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+    x[i] += alpha * ph[i] + omega * sh[i];
+    const double ri = s[i] - omega * t[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (blockIdx.x == 0) {
+      sc[BC_OMEGA] = omega;
+      sc[BC_RHOOLD] = sc[BC_RHO];
+    }
+  }
+}
+
 // out[0..k] = V[0..k-1].w and w.w (k vectors plus the norm), on the device.
 static ah_status multidot(int64_t n, int k, const double* V, const double* w, double* partial, double* out,
                           hipStream_t st) {
@@ -873,6 +947,136 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
   return converged ? AH_OK : AH_ENOCONV;
 }
 
+// Right-preconditioned BiCGSTAB (the paper's Krylov method, Section 4) on
+// A x = b: per step p_hat = M p, v = A p_hat, s = r - alpha v, then
+// s_hat = M s, t = A s_hat, x += alpha p_hat + omega s_hat, r = s - omega t.
+// The scalars stay on the device; the host reads ||s|| and ||r|| once per
+// half step.  Convergence is confirmed by the true residual; a vanishing
+// or non-finite rho, r_hat.v or omega restarts from the current iterate.
+static ah_status bicgstab(ah_hier* h, Op A, const double* bvec, double* x, const ah_solve_params& prm,
+                          int transpose, hipStream_t st, ah_solve_info* info) {
+  const int64_t n = h->lev[0].n;
+  // workspace: 8 vectors, then 3072 reduction partials (two dots of at most
+  // 1024 blocks each), then the BC_N device scalars
+  if (!h->bcg) {
+    h->arena.stream = st;
+    AH_TRY(h->arena.get(&h->bcg, 8 * n + 3072 + 16));
+  }
+  if (prm.precision == 1 && !h->bcg32) {
+    h->arena.stream = st;
+    AH_TRY(h->arena.get(&h->bcg32, n));
+  }
+  double* r = h->bcg;
+  double* rh = r + n;
+  double* p = rh + n;
+  double* v = p + n;
+  double* sv = v + n;
+  double* tv = sv + n;
+  double* ph = tv + n;
+  double* sh = ph + n;
+  double* part = h->bcg + 8 * n;
+  double* sc = part + 3072;
+  const int G0 = h->g0 ? h->g0 : pick_g(h->lev[0].nnz, n);
+  const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, 256 * 4)));
+  double* hh = pinned_scratch(16);
+  if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  auto read_sc = [&](int count) -> ah_status {
+    AH_HIP(hipMemcpyAsync(hh, sc, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    AH_HIP(hipStreamSynchronize(st));
+    return AH_OK;
+  };
+  auto apply_m = [&](const double* in, double* out) -> ah_status {
+    if (prm.precision == 0) return precond(h, in, out, nullptr, 0, transpose, st);
+    AH_TRY(precond(h, in, nullptr, h->bcg32, 1, transpose, st));
+    hipLaunchKernelGGL((k_cast<float, double>), g1(n), dim3(256), 0, st, n, h->bcg32, out);
+    AH_LAUNCHED();
+    return AH_OK;
+  };
+  auto spmv = [&](const double* in, double* out) -> ah_status {
+    return csr_g<double, double, double, SP_MV>(G0, n, A.rp, A.ci, A.v, in, (const double*)nullptr,
+                                                (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, out, st,
+                                                transpose ? nullptr : "spmv0",
+                                                (double)h->lev[0].nnz * 12.0 + (double)(n + 1) * 8.0 + 16.0 * n);
+  };
+  auto t0 = std::chrono::steady_clock::now();
+  AH_TRY(multidot(n, 0, rh, bvec, part, sc, st));
+  AH_TRY(read_sc(1));
+  const double bnorm = std::sqrt(hh[0]);
+  int its = 0;
+  bool converged = false;
+  double relres = 1.0, true_rel = 1.0;
+  ah_status status = AH_OK;
+  if (!(bnorm > 0.0)) {
+    AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+    if (info) { info->iters = 0; info->converged = 1; info->relres = 0; info->true_relres = 0; }
+    return AH_OK;
+  }
+  if (!std::isfinite(bnorm)) { set_error("air_solve: non-finite right-hand side"); return AH_EBREAKDOWN; }
+  const double ones[3] = {1.0, 1.0, 1.0};
+  while (true) {
+    // (re)start: r = b - A x, r_hat = r, p = v = 0, rho_old = alpha = omega = 1
+    AH_TRY((csr_g<double, double, double, SP_RES>(G0, n, A.rp, A.ci, A.v, x, bvec, (const double*)nullptr,
+                                                  (const int8_t*)nullptr, 0, 0.0, r, st)));
+    AH_TRY(multidot(n, 0, rh, r, part, sc + BC_RR, st));
+    AH_TRY(read_sc(BC_N));
+    true_rel = std::sqrt(hh[BC_RR]) / bnorm;
+    relres = true_rel;
+    if (!std::isfinite(true_rel)) { set_error("air_solve: breakdown (NaN residual)"); status = AH_EBREAKDOWN; break; }
+    if (true_rel <= prm.tol) { converged = true; break; }
+    if (its >= prm.maxit) break;
+    AH_HIP(hipMemcpyAsync(rh, r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    AH_HIP(hipMemsetAsync(p, 0, 2 * n * sizeof(double), st));   // p and v
+    std::memcpy(hh + 8, ones, sizeof(ones));
+    AH_HIP(hipMemcpyAsync(sc + BC_RHOOLD, hh + 8, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    bool restart = false;
+    while (its < prm.maxit) {
+      AH_TRY(multidot(n, 1, rh, r, part, sc + BC_RHO, st));      // rho, r.r
+      hipLaunchKernelGGL(k_bicg_p, g1(n), dim3(256), 0, st, n, r, v, p, sc);
+      AH_LAUNCHED();
+      AH_TRY(apply_m(p, ph));
+      AH_TRY(spmv(ph, v));
+      ++its;
+      AH_TRY(multidot(n, 1, rh, v, part, sc + BC_RV, st));      // r_hat.v, v.v
+      hipLaunchKernelGGL(k_bicg_s, dim3(nblk), dim3(256), 0, st, n, r, v, sv, sc, part, nblk);
+      AH_LAUNCHED();
+      hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, part, sc + BC_SS, 0);
+      AH_LAUNCHED();
+      AH_TRY(read_sc(BC_N));
+      const double snorm = std::sqrt(hh[BC_SS]);
+      if (!std::isfinite(snorm) || hh[BC_RHO] == 0.0 || hh[BC_RV] == 0.0) { restart = true; break; }
+      if (snorm <= prm.tol * bnorm) {
+        hipLaunchKernelGGL(k_bicg_xhalf, g1(n), dim3(256), 0, st, n, ph, x, sc);
+        AH_LAUNCHED();
+        relres = snorm / bnorm;
+        break;
+      }
+      AH_TRY(apply_m(sv, sh));
+      AH_TRY(spmv(sh, tv));
+      AH_TRY(multidot(n, 1, sv, tv, part, sc + BC_ST, st));     // s.t, t.t
+      hipLaunchKernelGGL(k_bicg_xr, dim3(nblk), dim3(256), 0, st, n, ph, sh, sv, tv, x, r, sc, part, nblk);
+      AH_LAUNCHED();
+      hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, part, sc + BC_RR, 0);
+      AH_LAUNCHED();
+      AH_TRY(read_sc(BC_N));
+      const double rnorm = std::sqrt(hh[BC_RR]);
+      relres = rnorm / bnorm;
+      if (!std::isfinite(rnorm)) { restart = true; break; }
+      if (rnorm <= prm.tol * bnorm || hh[BC_OMEGA] == 0.0) break;
+    }
+    (void)restart;   // either way the outer loop recomputes the true residual
+  }
+  AH_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = its;
+    info->converged = converged ? 1 : 0;
+    info->relres = relres;
+    info->true_relres = true_rel;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status != AH_OK) return status;
+  return converged ? AH_OK : AH_ENOCONV;
+}
+
 }  // namespace ah
 
 using namespace ah;
@@ -884,6 +1088,7 @@ extern "C" void ah_solve_defaults(ah_solve_params* p) {
   p->maxit = 1000;
   p->precision = 0;
   p->x0_given = 0;
+  p->method = 0;
 }
 
 static ah_status check_solve(const ah_hier* h, const ah_solve_params* prm, int transpose) {
@@ -892,7 +1097,8 @@ static ah_status check_solve(const ah_hier* h, const ah_solve_params* prm, int t
     set_error("air_solve: FP32 cycle requested but the hierarchy was built without fp32_cycle");
     return AH_EINVAL;
   }
-  if (prm->precision < 0 || prm->precision > 1 || prm->restart < 1 || prm->maxit < 0 || !(prm->tol > 0.0)) {
+  if (prm->precision < 0 || prm->precision > 1 || prm->restart < 1 || prm->maxit < 0 || !(prm->tol > 0.0) ||
+      prm->method < 0 || prm->method > 1) {
     set_error("air_solve: invalid parameters");
     return AH_EINVAL;
   }
@@ -924,6 +1130,7 @@ extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, 
   }
   if (!prm->x0_given) AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
   Op A{s->d_rowptr, s->d_col, s->d_val};
+  if (prm->method == 1) return bicgstab(h, A, b, x, *prm, 0, st, info);
   return fgmres(h, A, b, x, *prm, 0, st, info);
 }
 
@@ -948,7 +1155,7 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
   }
   AH_HIP(hipMemsetAsync(mu, 0, n * sizeof(double), st));   // zero initial guess
   Op AT{L0.ATptr, L0.ATcol, L0.ATval};
-  ah_status rc = fgmres(h, AT, g, mu, *prm, 1, st, info);
+  ah_status rc = prm->method == 1 ? bicgstab(h, AT, g, mu, *prm, 1, st, info) : fgmres(h, AT, g, mu, *prm, 1, st, info);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, mu, lam, 1);
   AH_LAUNCHED();

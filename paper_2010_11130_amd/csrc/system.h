@@ -9,6 +9,7 @@ struct ah_system {
   int D = 0, p = 0, nu = 0, b = 0, nl = 0, nq = 0, nqf = 0;
   double visc = 0.0, alpha = 0.0;
   bool keep = false;
+  bool unscaled = false;      // no facet-block scaling (S_hat = S, D_b^-1 = I)
   ah::Arena arena;
   ah::RefTables tab;
   int64_t n = 0;        // free DOFs
@@ -173,6 +174,8 @@ struct ah_hier {
   double* w = nullptr;
   double* r = nullptr;
   double* bhat = nullptr;
+  double* bcg = nullptr;       // BiCGSTAB vectors [8][n] (allocated on first use)
+  float* bcg32 = nullptr;      // FP32 cycle output [n]
   double* partial = nullptr;   // reduction partials
   double* hdev = nullptr;      // [4 (m+3)] device scalars
   ~ah_hier();

@@ -60,7 +60,7 @@ def boundary_data(prob, vert, fv, bf, kinds, xb):
     return torch.where(kb == 1, gD, torch.where(bot, gN0, gN1)).contiguous()
 
 
-def gpu_system(vert, cell, prob, p, keep=True):
+def gpu_system(vert, cell, prob, p, keep=True, block_scale=True):
     from paper_2010_11130_amd import Mesh, System
     m = Mesh(vert, cell)
     fv, _ = m.facets()
@@ -73,7 +73,7 @@ def gpu_system(vert, cell, prob, p, keep=True):
     f = prob.f(xe).contiguous()
     g = boundary_data(prob, vert, fv, bf, kinds, xb)
     a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(vert)), device="cuda")
-    s = System(m, p, prob.nu, a, f, g, keep=keep)
+    s = System(m, p, prob.nu, a, f, g, keep=keep, block_scale=block_scale)
     s._keep_alive = (m, xe, xb, f, g, a)
     return s
 

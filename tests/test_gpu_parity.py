@@ -358,3 +358,63 @@ def test_pipelined_march_matches_sequential_and_oracle(precision):
     tol = 1e-10 if precision == 0 else 1e-8
     for k in range(S):
         assert np.linalg.norm(res[True][k] - lo[k]) <= tol * np.linalg.norm(lo[k]), k
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5"])
+def test_bicgstab_parity(built, name):
+    """BiCGSTAB (the paper's Krylov method) against the oracle's: solution at
+    tol 1e-12, steps at the workload tolerance within one."""
+    from paper_2010_11130_amd import Hierarchy
+    from oracle.drivers import air_bicgstab_solve
+    print("case", name, flush=True)
+    g, o, _ = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    x, info = H.solve(tol=1e-12, method=1)
+    xo, io = air_bicgstab_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"] and io["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    tol = 1e-10 if name.startswith("c1") else 1e-8
+    _, i8 = H.solve(tol=tol, method=1)
+    _, io8 = air_bicgstab_solve(o, tol=tol, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+def test_bicgstab_fp32_cycle_and_adjoint(built):
+    from paper_2010_11130_amd import Hierarchy
+    g, o, _ = built("c5")
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1, adjoint=1)
+    ref = direct_solve(o)
+    x, info = H.solve(tol=1e-10, method=1, precision=1)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - ref) <= 1e-8 * np.linalg.norm(ref)
+    gvec = torch.as_tensor(np.random.default_rng(3).standard_normal(g.n), device="cuda")
+    lam, ia = H.solve_adjoint(gvec, tol=1e-12, method=1)
+    assert ia["converged"]
+    lam_o = oadj.adjoint_direct(o, gvec.cpu().numpy())
+    assert np.linalg.norm(lam.cpu().numpy() - lam_o) <= 1e-9 * np.linalg.norm(lam_o)
+
+
+@pytest.mark.parametrize("name", ["slab", "c1"])
+def test_unscaled_system_parity(name):
+    """The "no block inverse" system (S unscaled): assembly, hierarchy and one
+    V-cycle against the oracle's."""
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p, block_scale=False)
+    o = setup_problem(v, c, prob, p, block_scale=False)
+    ex = g.export()
+    S = to_scipy(ex["rowptr"], ex["col"], ex["val"], g.n)
+    assert rel_sparse_diff(S, o.Shat) < 1e-12
+    hh = ex["hhat"].cpu().numpy()
+    assert np.abs(hh - o.Hhat).max() <= 1e-12 * np.abs(o.Hhat).max()
+    assert np.array_equal(ex["dinv"].cpu().numpy(), o.Dinv)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    for l in range(OH.nlev - 1):
+        assert np.array_equal(H.level(l)["cf"].cpu().numpy(), OH.levels[l].cf), l
+    r = np.random.default_rng(6).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
