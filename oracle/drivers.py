@@ -115,10 +115,12 @@ def trace_at_points(sys, lam_full, fid, Xq):
     return Psi @ lam_full[fid * b:(fid + 1) * b]
 
 
-def solve_slabs(mesh_fn, nslab, prob, p, solver="direct", err=True, **kw):
+def solve_slabs(mesh_fn, nslab, prob, p, solver="direct", err=True, last_u=False, **kw):
     """Slab-by-slab march (Section 2.4): slab ``n+1`` takes as inflow data on its
     initial plane the trace ``lambda_h`` of slab ``n`` on its final plane (which
-    equals ``u_h`` there: the outflow facet equation gives ``lambda = u``)."""
+    equals ``u_h`` there: the outflow facet equation gives ``lambda = u``).
+    Returns (L2 error, infos, per-slab solutions) and, with ``last_u``, the
+    element solution of the last slab."""
     from .hdg import full_trace
     prev = None
     err2 = 0.0
@@ -155,4 +157,6 @@ def solve_slabs(mesh_fn, nslab, prob, p, solver="direct", err=True, **kw):
         if err:
             err2 += l2_error(sys, U, prob.u) ** 2
         prev = (sys, full_trace(sys, lam))
+    if last_u:
+        return np.sqrt(err2), infos, lams, U
     return np.sqrt(err2), infos, lams

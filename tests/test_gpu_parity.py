@@ -418,3 +418,27 @@ def test_unscaled_system_parity(name):
     z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
     zo = oair.vcycle(OH, r)
     assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+def test_all_at_once_equals_slab_march_pure_advection():
+    """At nu = 0 the all-at-once space-time system on the stacked slabs and the
+    slab march (Section 2.4) are the same discrete problem: the last slab's
+    element solution agrees.  (With nu > 0 the penalty on the interior time
+    planes couples both sides in the all-at-once system only.)"""
+    from paper_2010_11130_amd import SlabMarch, Hierarchy
+    from workloads import stacked_prism_tet_mesh
+    from workloads.problems import slab_hill
+    n, S, p, dt = 6, 3, 2, 1.0 / 8
+    prob = slab_hill(0.0)
+    v, c = stacked_prism_tet_mesh(n, S, T=S * dt)
+    g = gpu_system(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    x, info = H.solve(tol=1e-13)
+    assert info["converged"]
+    U = g.reconstruct(x).cpu().numpy()[(S - 1) * 6 * n * n:]
+    m, a, gs = _march_inputs(n, S, p, dt, prob)
+    out = {}
+    march = SlabMarch(m, p, prob.nu, a, air_kw={"max_coarse": SMALL_COARSE}, solve_kw={"tol": 1e-13})
+    march.run(gs, pipelined=False, on_slab=lambda k, s, h, xx, inf: out.__setitem__("U", s.reconstruct(xx)))
+    Ul = out["U"].cpu().numpy()
+    assert np.linalg.norm(U - Ul) <= 1e-10 * np.linalg.norm(Ul)

@@ -8,9 +8,9 @@ solver) and is the only code shared by the oracle and the HIP path.
 
 Coordinates are space-time: column 0 is t, columns 1..d are space.
 """
-from .meshes import (square_tri_mesh, slab_prism_tet_mesh, kuhn_cube_mesh,
+from .meshes import (square_tri_mesh, slab_prism_tet_mesh, stacked_prism_tet_mesh, kuhn_cube_mesh,
                      map_vertices_c5, pulse_slab_mesh, boundary_kinds)
 from . import problems
 
-__all__ = ["square_tri_mesh", "slab_prism_tet_mesh", "kuhn_cube_mesh",
+__all__ = ["square_tri_mesh", "slab_prism_tet_mesh", "stacked_prism_tet_mesh", "kuhn_cube_mesh",
            "map_vertices_c5", "pulse_slab_mesh", "boundary_kinds", "problems"]

@@ -84,6 +84,26 @@ def slab_prism_tet_mesh(n, dt, t0=0.0):
     return _extrude_prisms(xy, tri, t0, t0 + dt)
 
 
+def stacked_prism_tet_mesh(n, nt, T=1.0):
+    """All-at-once mesh of ``nt`` stacked slabs over ``[0,T] x [0,1]^2``: layer
+    ``k`` is ``slab_prism_tet_mesh(n, T/nt, k T/nt)`` with its vertices
+    renumbered ``k * nv2 + spatial id``, so elements ``[6 n^2 k, 6 n^2 (k+1))``
+    are the tets of slab ``k`` in the same order and orientation."""
+    xy, tri = _unit_square_triangles(n)
+    nv2 = xy.shape[0]
+    ts = np.linspace(0.0, T, nt + 1)
+    vert = np.concatenate([np.concatenate([np.full((nv2, 1), t), xy], axis=1) for t in ts], axis=0)
+    s = np.sort(tri, axis=1)
+    cells = []
+    for k in range(nt):
+        a, b, c = s[:, 0] + k * nv2, s[:, 1] + k * nv2, s[:, 2] + k * nv2
+        ap, bp, cp = a + nv2, b + nv2, c + nv2
+        cells.append(np.stack([np.stack([a, b, c, cp], 1),
+                               np.stack([a, b, bp, cp], 1),
+                               np.stack([a, ap, bp, cp], 1)], axis=1).reshape(-1, 4))
+    return vert.astype(np.float64), np.concatenate(cells, axis=0).astype(np.int32)
+
+
 def kuhn_cube_mesh(n, reflect_x1=True, t_extent=1.0):
     """All-at-once space-time cube ``[0,T] x [0,1]^2``: ``n^3`` cubes, 6 tets each.
 
