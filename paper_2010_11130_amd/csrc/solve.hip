@@ -51,7 +51,21 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   TY acc = 0;
   if (active) {
     const int64_t k1 = rp[i + 1];
-    for (int64_t k = rp[i] + g; k < k1; k += G) {
+    int64_t kb = rp[i] + g;
+    if (MODE != SP_SWEEP_P && av) {
+      // four independent column / value / x loads in flight per lane
+      TY acc1 = 0, acc2 = 0, acc3 = 0;
+      for (; kb + 3 * G < k1; kb += 4 * G) {
+        const int32_t c0 = ci[kb], c1 = ci[kb + G], c2 = ci[kb + 2 * G], c3 = ci[kb + 3 * G];
+        const TY a0 = (TY)av[kb], a1 = (TY)av[kb + G], a2 = (TY)av[kb + 2 * G], a3 = (TY)av[kb + 3 * G];
+        acc += a0 * (TY)x[c0];
+        acc1 += a1 * (TY)x[c1];
+        acc2 += a2 * (TY)x[c2];
+        acc3 += a3 * (TY)x[c3];
+      }
+      acc += (acc1 + acc2) + acc3;
+    }
+    for (int64_t k = kb; k < k1; k += G) {
       TY a = av ? (TY)av[k] : (TY)1;
       if (MODE == SP_SWEEP_P) {
         const int32_t c = pc[ci[k]];
