@@ -5,6 +5,7 @@ fallback path.
 """
 import ctypes as C
 import os
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libairhdg.so")
@@ -101,6 +102,15 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def destroy(name, h, _finalizing=sys.is_finalizing):
+    """Call the destructor ``name`` on handle ``h`` from a finaliser.  Skipped
+    while the interpreter shuts down (module globals may already be cleared;
+    process exit returns the device memory)."""
+    if _finalizing() or _lib is None:
+        return
+    getattr(_lib, name)(h)
 
 
 class AirHdgError(RuntimeError):

@@ -8,7 +8,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (lib, check, HdgParams, AirParams, SetupInfo, SolveParams, SolveInfo,
+from ._lib import (lib, check, destroy, HdgParams, AirParams, SetupInfo, SolveParams, SolveInfo,
                    AH_OK, AH_ENOCONV)
 
 
@@ -63,9 +63,9 @@ class Mesh:
         self.vert = vert
         self.kind = None
 
-    def __del__(self):
+    def __del__(self, _destroy=destroy):
         if getattr(self, "h", None):
-            lib().ah_mesh_destroy(self.h)
+            _destroy("ah_mesh_destroy", self.h)
             self.h = None
 
     def facets(self):
@@ -116,9 +116,9 @@ class System:
         self.n, self.b, self.nnz = n.value, b.value, nnz.value
         self.nq, self.nqf, self.nu_dofs, _ = sizes(mesh.D, p)
 
-    def __del__(self):
+    def __del__(self, _destroy=destroy):
         if getattr(self, "h", None):
-            lib().ah_system_destroy(self.h)
+            _destroy("ah_system_destroy", self.h)
             self.h = None
 
     def export(self):
@@ -194,9 +194,9 @@ class Hierarchy:
                      "nnz": list(info.nnz[:info.levels]), "n_fallback": info.n_fallback,
                      "op_complexity": info.op_complexity, "t_setup_ms": info.t_setup_ms}
 
-    def __del__(self):
+    def __del__(self, _destroy=destroy):
         if getattr(self, "h", None):
-            lib().ah_hier_destroy(self.h)
+            _destroy("ah_hier_destroy", self.h)
             self.h = None
 
     def solve(self, rhs=None, x0=None, out=None, **kw):
