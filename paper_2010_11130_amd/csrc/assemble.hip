@@ -580,7 +580,8 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
                                                     const int32_t* __restrict__ bcol, const double* __restrict__ bval,
                                                     const double* __restrict__ dinv, int32_t* __restrict__ cnt,
                                                     const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                    double* __restrict__ val, int unscaled) {
+                                                    double* __restrict__ val, int unscaled,
+                                                    const int64_t* __restrict__ optr, double* __restrict__ oval) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= nfree * B) return;
@@ -589,6 +590,12 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
   const int64_t s0 = bptr[R];
   const int ncand = (int)(bptr[R + 1] - s0) * B;
   int64_t out = rowptr ? rowptr[i] : 0;
+  // off-diagonal facet-block copy of row i (fill pass of a scaled system)
+  double* orow = nullptr;
+  if (oval) {
+    const int64_t o0 = optr[R];
+    orow = oval + o0 * B * B + (int64_t)m * (optr[R + 1] - o0) * B;
+  }
   int c0 = 0;
   for (int base = 0; base < ncand; base += 64) {
     const int cidx = base + lane;
@@ -610,6 +617,8 @@ __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t
 #pragma unroll
         for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * bval[s * B * B + k * B + n];
         keep = v != 0.0;
+        // blocks after the diagonal one sit one slot earlier in the copy
+        if (orow) orow[cidx - (C > R ? B : 0)] = v;
       }
     }
     const unsigned long long mask = __ballot(keep);
@@ -836,7 +845,8 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   AH_TRY(ar.get(&s->d_rowptr, n + 1));
   const dim3 gw((unsigned)cdiv(std::max<int64_t>(n, 1) * 64, 256));
   hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int)s->unscaled);
+                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int)s->unscaled,
+                     (const int64_t*)nullptr, (double*)nullptr);
   AH_LAUNCHED();
   AH_TRY(scan_i32_to_i64(cnt, s->d_rowptr, n, st, tmp));
   AH_TRY(read_i64(s->d_rowptr + n, &s->nnz, st));
@@ -847,8 +857,9 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
   }
   AH_TRY(ar.get(&s->d_col, s->nnz));
   AH_TRY(ar.get(&s->d_val, s->nnz));
+  if (!s->unscaled) AH_TRY(ar.get(&s->d_odv, (int64_t)m->odb_col.size() * B * B));
   hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, s->d_rowptr, s->d_col, s->d_val, (int)s->unscaled);
+                     cnt, s->d_rowptr, s->d_col, s->d_val, (int)s->unscaled, (const int64_t*)m->d_odb_ptr, s->d_odv);
   AH_LAUNCHED();
   tmp.release();
   return AH_OK;

@@ -129,6 +129,8 @@ struct ah_mesh {
   std::vector<int32_t> free_rank;    // [nf] -> free facet rank or -1
   std::vector<int64_t> bsr_ptr;      // [nfree+1]
   std::vector<int32_t> bsr_col;      // [nnzb] free facet ranks, sorted per row
+  std::vector<int64_t> odb_ptr;      // [nfree+1] the same pattern without the diagonal block
+  std::vector<int32_t> odb_col;      // [nnzb - nfree]
   std::vector<int32_t> elem_slot;    // [ne][(D+1)^2] block index or -1
   // time planes and the pairing used for slab coupling: boundary facets of
   // this mesh on t_min matched (by spatial vertex coordinates) with facets on
@@ -153,6 +155,8 @@ struct ah_mesh {
   int32_t* d_elem_slot = nullptr;
   int64_t* d_bsr_ptr = nullptr;
   int32_t* d_bsr_col = nullptr;
+  int64_t* d_odb_ptr = nullptr;
+  int32_t* d_odb_col = nullptr;
   ~ah_mesh();
 };
 

@@ -480,7 +480,8 @@ extern "C" ah_status ah_mesh_create(int D, int64_t nv, const double* vert, int64
 
 ah_mesh::~ah_mesh() {
   void* ptrs[] = {d_vert, d_cell, d_elem_facet, d_facet_loc, d_kind, d_bf_index, d_bfacets,
-                  d_facet_vert, d_free_rank, d_elem_slot, d_bsr_ptr, d_bsr_col, d_pair, d_pair_perm};
+                  d_facet_vert, d_free_rank, d_elem_slot, d_bsr_ptr, d_bsr_col, d_odb_ptr, d_odb_col,
+                  d_pair, d_pair_perm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -514,6 +515,8 @@ ah_status mesh_upload(ah_mesh* m, hipStream_t st) {
   AH_TRY(up(&m->d_elem_slot, m->elem_slot, st));
   AH_TRY(up(&m->d_bsr_ptr, m->bsr_ptr, st));
   AH_TRY(up(&m->d_bsr_col, m->bsr_col, st));
+  AH_TRY(up(&m->d_odb_ptr, m->odb_ptr, st));
+  AH_TRY(up(&m->d_odb_col, m->odb_col, st));
   AH_HIP(hipStreamSynchronize(st));
   m->dev_ready = true;
   return AH_OK;
@@ -635,6 +638,15 @@ extern "C" ah_status ah_mesh_set_bc(ah_mesh* m, const int8_t* kind) {
     tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
     for (int32_t c : tmp) m->bsr_col.push_back(c);
     m->bsr_ptr[m->free_rank[f] + 1] = (int64_t)m->bsr_col.size();
+  }
+  // off-diagonal blocks only (every free facet couples to itself once)
+  m->odb_ptr.assign(nfree + 1, 0);
+  m->odb_col.clear();
+  m->odb_col.reserve(m->bsr_col.size() - (size_t)nfree);
+  for (int64_t r = 0; r < nfree; ++r) {
+    for (int64_t k = m->bsr_ptr[r]; k < m->bsr_ptr[r + 1]; ++k)
+      if (m->bsr_col[k] != r) m->odb_col.push_back(m->bsr_col[k]);
+    m->odb_ptr[r + 1] = (int64_t)m->odb_col.size();
   }
   const int nb = (D + 1) * (D + 1);
   m->elem_slot.assign(m->ne * nb, -1);

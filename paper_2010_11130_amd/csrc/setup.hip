@@ -454,6 +454,27 @@ __global__ void k_diag(int64_t n, const int64_t* __restrict__ rp, const int32_t*
   if (d32) d32[i] = (float)x;
 }
 
+// Stored values of the listed level-0 rows in the off-diagonal facet-block
+// layout (B per off-diagonal block of the row's block row), one atomic per
+// block.
+__global__ __launch_bounds__(256) void k_list_vals(int64_t nl, const int32_t* __restrict__ list,
+                                                   const int64_t* __restrict__ optr, int B,
+                                                   unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long red[4];
+  unsigned long long acc = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t R = list[k] / B;
+    acc += (unsigned long long)(optr[R + 1] - optr[R]) * (unsigned long long)B;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(out, t);
+  }
+}
+
 __global__ void k_cast32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -806,8 +827,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   unsigned long long* d_fst = nullptr;   // per level: F rows, F-row entries
   CK(ar.get(&d_ull, 4));
   CK(ar.get(&d_int, 4));
-  CK(ar.get(&d_fst, 64));
-  CKH(hipMemsetAsync(d_fst, 0, 64 * sizeof(unsigned long long), st));
+  CK(ar.get(&d_fst, 66));   // [2 l], [2 l + 1] per level; [64] level-0 F values in the facet-block layout
+  CKH(hipMemsetAsync(d_fst, 0, 66 * sizeof(unsigned long long), st));
   CKH(hipMemsetAsync(d_ull, 0, 4 * sizeof(unsigned long long), st));
   CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
   // level 0 = the scaled system (shared, not copied)
@@ -817,6 +838,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   L0.rowptr = s->d_rowptr;
   L0.col = s->d_col;
   L0.val = s->d_val;
+  if (s->d_odv) {
+    L0.ob = s->b;
+    L0.nov = (int64_t)s->mesh->odb_col.size() * s->b * s->b;
+    L0.optr = s->mesh->d_odb_ptr;
+    L0.ocol = s->mesh->d_odb_col;
+    L0.oval = s->d_odv;
+  }
   h->lev.push_back(L0);
   for (int l = 0;; ++l) {
     AhLevel& L = h->lev[l];
@@ -827,6 +855,11 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       CK(ar.get(&L.val32, L.nnz));
       hipLaunchKernelGGL(k_cast32, g1(L.nnz), dim3(256), 0, st, L.nnz, L.val, L.val32);
       CKH(hipGetLastError());
+      if (L.ob) {
+        CK(ar.get(&L.oval32, L.nov));
+        hipLaunchKernelGGL(k_cast32, g1(L.nov), dim3(256), 0, st, L.nov, L.oval, L.oval32);
+        CKH(hipGetLastError());
+      }
     }
     hipLaunchKernelGGL(k_diag, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, L.diag, L.diag32);
     CKH(hipGetLastError());
@@ -891,6 +924,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
                        rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
+    if (L.ob) {
+      hipLaunchKernelGGL(k_list_vals, grows(n - nc), dim3(256), 0, st, n - nc, L.flist, L.optr, L.ob, d_fst + 64);
+      CKH(hipGetLastError());
+    }
     CK(ar.get(&L.Rptr, nc + 1));
     CK(scan_i32_to_i64(rcnt, L.Rptr, nc, st, tmp));
     int hmax[4];
@@ -1008,12 +1045,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
     CKH(hipMemcpyAsync(pin, d_ull + 2, sizeof(fb), hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(pin + 1, d_int + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-    CKH(hipMemcpyAsync(pin + 2, d_fst, 64 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(pin + 2, d_fst, 65 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CKH(hipStreamSynchronize(st));
     std::memcpy(&fb, pin, sizeof(fb));
     std::memcpy(&gerr, pin + 1, sizeof(int));
-    unsigned long long fst[64];
+    unsigned long long fst[65];
     std::memcpy(fst, pin + 2, sizeof(fst));
+    h->lev[0].novF = (int64_t)fst[64];
     for (size_t l = 0; l + 1 < h->lev.size() && l < 32; ++l) {
       h->lev[l].nF = (int64_t)fst[2 * l];
       h->lev[l].nnzF = (int64_t)fst[2 * l + 1];

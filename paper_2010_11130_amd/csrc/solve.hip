@@ -98,6 +98,59 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   }
 }
 
+// Level-0 operator by off-diagonal facet blocks (scaled system: identity
+// diagonal blocks).  Scalar row i = R B + m holds, for each of the nb
+// off-diagonal blocks of block row R, B contiguous values whose columns are
+// B ocol[s] + 0..B-1; one column index serves B values and all B rows of the
+// block row, so the row stream is the values alone.  Modes SP_MV, SP_RES and
+// SP_SWEEP_LIST as in k_csr, with d_i = 1.
+template <class TA, class TX, class TY, int B, int G, int MODE>
+__global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict__ optr,
+                                            const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
+                                            const TX* __restrict__ x, const TY* __restrict__ b, TY omega,
+                                            TY* __restrict__ y, const int32_t* __restrict__ list,
+                                            TY* __restrict__ y2) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ii = gid / G;
+  const int g = (int)(gid % G);
+  if (ii >= n) return;
+  const int64_t i = MODE == SP_SWEEP_LIST ? (int64_t)list[ii] : ii;
+  const int64_t R = i / B;
+  const int m = (int)(i - R * B);
+  const int64_t o0 = optr[R];
+  const int len = (int)(optr[R + 1] - o0) * B;
+  const TA* __restrict__ v = ov + o0 * (B * B) + (int64_t)m * len;
+  const int32_t* __restrict__ cb = ocol + o0;
+  TY acc = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  int e = g;
+  for (; e + 3 * G < len; e += 4 * G) {
+    const int e1 = e + G, e2 = e + 2 * G, e3 = e + 3 * G;
+    const int64_t c0 = (int64_t)cb[e / B] * B + e % B, c1 = (int64_t)cb[e1 / B] * B + e1 % B;
+    const int64_t c2 = (int64_t)cb[e2 / B] * B + e2 % B, c3 = (int64_t)cb[e3 / B] * B + e3 % B;
+    const TY a0 = (TY)v[e], a1 = (TY)v[e1], a2 = (TY)v[e2], a3 = (TY)v[e3];
+    acc += a0 * (TY)x[c0];
+    acc1 += a1 * (TY)x[c1];
+    acc2 += a2 * (TY)x[c2];
+    acc3 += a3 * (TY)x[c3];
+  }
+  for (; e < len; e += G) acc += (TY)v[e] * (TY)x[(int64_t)cb[e / B] * B + e % B];
+  acc += (acc1 + acc2) + acc3;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (g != 0) return;
+  const TY xi = (TY)x[i];
+  acc += xi;
+  if (MODE == SP_MV) {
+    y[i] = acc;
+  } else if (MODE == SP_RES) {
+    y[i] = b[i] - acc;
+  } else {
+    const TY xn = xi + omega * (b[i] - acc);
+    y[i] = xn;
+    if (y2) y2[i] = xn;
+  }
+}
+
 // Coarse end of the cycle in one workgroup: every level from l0 down,
 // one row per thread, phases separated by workgroup barriers.
 template <class T>
@@ -529,6 +582,40 @@ static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, c
   return AH_OK;
 }
 
+template <class TA, class TX, class TY, int MODE, int B>
+static void fb_launch(int G, dim3 grid, hipStream_t st, int64_t n, const int64_t* optr, const int32_t* ocol,
+                      const TA* ov, const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2) {
+  switch (G) {
+    case 4: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 4, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 8: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 8, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    default: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 16, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+  }
+}
+
+// Level-0 rows in the off-diagonal facet-block layout (k_fb): n rows (the
+// listed ones for SP_SWEEP_LIST), block size B, G in {4, 8, 16}.
+template <class TA, class TX, class TY, int MODE>
+static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_t* ocol, const TA* ov, const TX* x,
+                      const TY* b, TY omega, TY* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
+                      const int32_t* list = nullptr, TY* y2 = nullptr) {
+  if (n == 0) return AH_OK;
+  if (G != 4 && G != 8) G = 16;
+  ProfScope ps;
+  prof_begin(ps, tag, st, bytes);
+  const dim3 grid((unsigned)cdiv(n * G, 256));
+  switch (B) {
+    case 2: fb_launch<TA, TX, TY, MODE, 2>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 3: fb_launch<TA, TX, TY, MODE, 3>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 4: fb_launch<TA, TX, TY, MODE, 4>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 6: fb_launch<TA, TX, TY, MODE, 6>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 10: fb_launch<TA, TX, TY, MODE, 10>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    default: set_error("unsupported facet block size %d", B); return AH_EUNSUPPORTED;
+  }
+  prof_end(ps);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
 // Algorithmic bytes of a Jacobi sweep on the point set X of level L: the X
 // rows of A once, x once, b and d on X, the X updates written.
 template <class T>
@@ -537,6 +624,18 @@ static double sweep_bytes(const AhLevel& L, int X) {
   const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
   const int64_t nnzX = X == 0 ? L.nnzF : L.nnz - L.nnzF;
   return (double)nnzX * (w + 4.0) + (double)(nX + 1) * 8.0 + (double)L.n * w + (double)nX * 3.0 * w;
+}
+
+// The same for a level-0 sweep in the off-diagonal facet-block layout: the
+// X rows' values, every block column index and block-row offset, the list,
+// x once, b on X, the X updates written (twice with a second output).
+template <class T>
+static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
+  const double w = sizeof(T);
+  const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
+  const int64_t nvX = X == 0 ? L.novF : L.nov - L.novF;
+  return (double)nvX * w + (double)(L.nov / (L.ob * L.ob)) * 4.0 + (double)(L.n / L.ob + 1) * 8.0 +
+         (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 3.0 : 2.0) * w;
 }
 
 // ------------------------------------------------------------ V-cycles
@@ -549,6 +648,7 @@ struct Ops<double> {
   static const double* R(const AhLevel& L) { return L.Rval; }
   static const double* RT(const AhLevel& L) { return L.RTval; }
   static const double* d(const AhLevel& L) { return L.diag; }
+  static const double* O(const AhLevel& L) { return L.oval; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -561,6 +661,7 @@ struct Ops<float> {
   static const float* R(const AhLevel& L) { return L.Rval32; }
   static const float* RT(const AhLevel& L) { return L.RTval32; }
   static const float* d(const AhLevel& L) { return L.diag32; }
+  static const float* O(const AhLevel& L) { return L.oval32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -643,6 +744,18 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   // level-0 timing tags, one per sweep kernel and grid
   const char* tf = sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
   const char* tc = sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
+  if (L.ob && Ops<T>::O(L)) {
+    const int Gb = h->g0 ? h->g0 : pick_g(L.nov, L.n);
+    const T* ov = Ops<T>::O(L);
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, x, b, om, y, st, tf,
+                                         fb_sweep_bytes<T>(L, 0, false), L.flist)));
+    if (nsw == 1) return AH_OK;
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, y, b, om, x, st, tf,
+                                         fb_sweep_bytes<T>(L, 0, true), L.flist, out)));
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, L.nc, L.optr, L.ocol, ov, x, b, om, out, st, tc,
+                                         fb_sweep_bytes<T>(L, 1, false), L.clist)));
+    return AH_OK;
+  }
   AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,
                                         st, tf, sweep_bytes<T>(L, 0), L.flist)));
   if (nsw == 1) return AH_OK;
@@ -820,18 +933,49 @@ static ah_status multidot(int64_t n, int k, const double* V, const double* w, do
   return AH_OK;
 }
 
+// Level-0 operator of a Krylov solve: scalar CSR, and for a scaled system's
+// forward operator also the off-diagonal facet-block layout (ob > 0), which
+// is then the one applied.
 struct Op {
   const int64_t* rp;
   const int32_t* ci;
   const double* v;
+  int ob = 0;
+  const int64_t* optr = nullptr;
+  const int32_t* ocol = nullptr;
+  const double* ov = nullptr;
+  int64_t nov = 0;
 };
+
+static int op_lanes(const ah_hier* h, const Op& A, int64_t n) {
+  if (h->g0) return h->g0;
+  return A.ob ? pick_g(A.nov, n) : pick_g(h->lev[0].nnz, n);
+}
+
+// Algorithmic bytes of y = A x (x of width wx): the operator once, x once,
+// y written.
+static double op_mv_bytes(const ah_hier* h, const Op& A, int64_t n, double wx) {
+  if (A.ob) return (double)A.nov * 8.0 + (double)(A.nov / (A.ob * A.ob)) * 4.0 + (double)(n / A.ob + 1) * 8.0 +
+                   (double)n * wx + (double)n * 8.0;
+  return (double)h->lev[0].nnz * 12.0 + (double)(n + 1) * 8.0 + (double)n * wx + (double)n * 8.0;
+}
+
+// y = A x (SP_MV) or y = b - A x (SP_RES).
+template <class TX, int MODE>
+static ah_status op_apply(const Op& A, int G, int64_t n, const TX* x, const double* b, double* y, hipStream_t st,
+                          const char* tag = nullptr, double bytes = 0.0) {
+  if (A.ob)
+    return fb_g<double, TX, double, MODE>(A.ob, G, n, A.optr, A.ocol, A.ov, x, b, 0.0, y, st, tag, bytes);
+  return csr_g<double, TX, double, MODE>(G, n, A.rp, A.ci, A.v, x, b, (const double*)nullptr,
+                                         (const int8_t*)nullptr, 0, 0.0, y, st, tag, bytes);
+}
 
 static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const ah_solve_params& prm, int transpose,
                         hipStream_t st, ah_solve_info* info) {
   const int64_t n = h->lev[0].n;
   const int m = std::max(1, prm.restart);
   AH_TRY(ensure_workspace(h, m, prm.precision, st));
-  const int G0 = h->g0 ? h->g0 : pick_g(h->lev[0].nnz, n);
+  const int G0 = op_lanes(h, A, n);
   double* hd = h->hdev;
   double* hh = pinned_scratch(4 * (m + 3));
   if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
@@ -854,8 +998,7 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
   if (!std::isfinite(bnorm)) { set_error("air_solve: non-finite right-hand side"); return AH_EBREAKDOWN; }
   while (true) {
     // r = b - A x
-    AH_TRY((csr_g<double, double, double, SP_RES>(G0, n, A.rp, A.ci, A.v, x, bvec, (const double*)nullptr,
-                                                  (const int8_t*)nullptr, 0, 0.0, h->r, st)));
+    AH_TRY((op_apply<double, SP_RES>(A, G0, n, x, bvec, h->r, st)));
     AH_TRY(multidot(n, 0, h->V, h->r, h->partial, hd, st));
     AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
     AH_HIP(hipStreamSynchronize(st));
@@ -876,18 +1019,13 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       float* zj32 = h->Z32 ? h->Z32 + (int64_t)j * n : nullptr;
       AH_TRY(precond(h, vj, prm.precision == 0 ? zj : nullptr, prm.precision == 1 ? zj32 : nullptr, prm.precision,
                      transpose, st));
-      const int64_t nnz0 = h->lev[0].nnz;
-      // algorithmic bytes: matrix once (8 B value + 4 B column), row offsets, x once, y written
-      const double by = (double)nnz0 * 12.0 + (double)(n + 1) * 8.0 + (double)n * (prm.precision ? 4.0 : 8.0) +
-                        (double)n * 8.0;
+      const double by = op_mv_bytes(h, A, n, prm.precision ? 4.0 : 8.0);
       if (prm.precision == 0)
-        AH_TRY((csr_g<double, double, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj, (const double*)nullptr,
-                                                     (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st,
-                                                     transpose ? nullptr : "spmv0", by)));
+        AH_TRY((op_apply<double, SP_MV>(A, G0, n, zj, (const double*)nullptr, h->w, st,
+                                        transpose ? nullptr : "spmv0", by)));
       else
-        AH_TRY((csr_g<double, float, double, SP_MV>(G0, n, A.rp, A.ci, A.v, zj32, (const double*)nullptr,
-                                                    (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, h->w, st,
-                                                    transpose ? nullptr : "spmv0", by)));
+        AH_TRY((op_apply<float, SP_MV>(A, G0, n, zj32, (const double*)nullptr, h->w, st,
+                                       transpose ? nullptr : "spmv0", by)));
       ++its;
       const int k = j + 1;
       // CGS2
@@ -990,7 +1128,7 @@ static ah_status bicgstab(ah_hier* h, Op A, const double* bvec, double* x, const
   double* sh = ph + n;
   double* part = h->bcg + 8 * n;
   double* sc = part + 3072;
-  const int G0 = h->g0 ? h->g0 : pick_g(h->lev[0].nnz, n);
+  const int G0 = op_lanes(h, A, n);
   const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, 256 * 4)));
   double* hh = pinned_scratch(16);
   if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
@@ -1007,10 +1145,8 @@ static ah_status bicgstab(ah_hier* h, Op A, const double* bvec, double* x, const
     return AH_OK;
   };
   auto spmv = [&](const double* in, double* out) -> ah_status {
-    return csr_g<double, double, double, SP_MV>(G0, n, A.rp, A.ci, A.v, in, (const double*)nullptr,
-                                                (const double*)nullptr, (const int8_t*)nullptr, 0, 0.0, out, st,
-                                                transpose ? nullptr : "spmv0",
-                                                (double)h->lev[0].nnz * 12.0 + (double)(n + 1) * 8.0 + 16.0 * n);
+    return op_apply<double, SP_MV>(A, G0, n, in, (const double*)nullptr, out, st, transpose ? nullptr : "spmv0",
+                                   op_mv_bytes(h, A, n, 8.0));
   };
   auto t0 = std::chrono::steady_clock::now();
   AH_TRY(multidot(n, 0, rh, bvec, part, sc, st));
@@ -1029,8 +1165,7 @@ static ah_status bicgstab(ah_hier* h, Op A, const double* bvec, double* x, const
   const double ones[3] = {1.0, 1.0, 1.0};
   while (true) {
     // (re)start: r = b - A x, r_hat = r, p = v = 0, rho_old = alpha = omega = 1
-    AH_TRY((csr_g<double, double, double, SP_RES>(G0, n, A.rp, A.ci, A.v, x, bvec, (const double*)nullptr,
-                                                  (const int8_t*)nullptr, 0, 0.0, r, st)));
+    AH_TRY((op_apply<double, SP_RES>(A, G0, n, x, bvec, r, st)));
     AH_TRY(multidot(n, 0, rh, r, part, sc + BC_RR, st));
     AH_TRY(read_sc(BC_N));
     true_rel = std::sqrt(hh[BC_RR]) / bnorm;
@@ -1144,6 +1279,14 @@ extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, 
   }
   if (!prm->x0_given) AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
   Op A{s->d_rowptr, s->d_col, s->d_val};
+  const AhLevel& L0 = h->lev[0];
+  if (L0.ob) {
+    A.ob = L0.ob;
+    A.optr = L0.optr;
+    A.ocol = L0.ocol;
+    A.ov = L0.oval;
+    A.nov = L0.nov;
+  }
   if (prm->method == 1) return bicgstab(h, A, b, x, *prm, 0, st, info);
   return fgmres(h, A, b, x, *prm, 0, st, info);
 }

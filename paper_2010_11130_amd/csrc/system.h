@@ -25,6 +25,11 @@ struct ah_system {
   int64_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
   double* d_val = nullptr;
+  // the same operator by off-diagonal facet blocks (scaled systems only; the
+  // diagonal blocks of S_hat are the identity): block row R with nb blocks
+  // holds [b][nb][b] values from (mesh odb_ptr[R]) b^2 on, so scalar row
+  // R b + m is contiguous and its entry (s, c) has column b odb_col[.] + c
+  double* d_odv = nullptr;    // [nnzb - nfree][b][b]
   // element data kept for reconstruction and the adjoint
   double* d_Ainv = nullptr;   // [ne][nu][nu]
   double* d_Bm = nullptr;     // [ne][nu][nl]
@@ -64,6 +69,15 @@ struct AhLevel {
   int32_t* pcol = nullptr;     // one-point interpolation: coarse column or -1
   int32_t* clist = nullptr;    // fine index of each C point (coarse order)
   int32_t* flist = nullptr;    // fine index of each F point (increasing)
+  // level 0 of a scaled system: the operator by off-diagonal facet blocks
+  // (identity diagonal blocks), ob = block size, 0 where not available
+  int ob = 0;
+  int64_t nov = 0;             // stored values (off-diagonal blocks * ob^2)
+  int64_t novF = 0;            // of which in F rows
+  const int64_t* optr = nullptr;
+  const int32_t* ocol = nullptr;
+  const double* oval = nullptr;
+  float* oval32 = nullptr;
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;
