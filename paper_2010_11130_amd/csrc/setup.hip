@@ -1070,7 +1070,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     int64_t tail_max = 4096;
     if (const char* e = std::getenv("AH_TAIL_MAX")) tail_max = std::atoll(e);
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
-    if (h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
+    if (h->g0 != 2 && h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();
     std::vector<TailLevel> tl(nl);
     for (int l = 0; l < nl; ++l) {
@@ -1113,8 +1113,14 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     double* pin = pinned_scratch((nl * sizeof(TailLevel) + 7) / 8);
     if (!pin) { set_error("pinned host allocation failed"); delete h; return AH_ENOMEM; }
     std::memcpy(pin, tl.data(), nl * sizeof(TailLevel));
-    if (hipMemcpyAsync(h->d_tail, pin, nl * sizeof(TailLevel), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
+    if (hipMemcpyAsync(h->d_tail, pin, nl * sizeof(TailLevel), hipMemcpyHostToDevice, st) != hipSuccess) {
+      set_error("air_setup: upload of the level table failed");
+      delete h;
+      return AH_EHIP;
+    }
+    rc = tail_image_build(h, st);
+    if (rc < 0) { delete h; return rc; }
+    if (hipStreamSynchronize(st) != hipSuccess) {
       set_error("air_setup: upload of the level table failed");
       delete h;
       return AH_EHIP;

@@ -14,8 +14,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "prof.h"
 #include "system.h"
@@ -197,11 +199,63 @@ __device__ inline T row_dot_s(const int32_t* rp, const int32_t* ci, const T* av,
   return s;
 }
 
+// Global -> LDS staging for the tail kernel: n elements, eight independent
+// loads in flight per thread (the image is re-staged on every cycle, so the
+// copy must not be one dependent load per iteration).
+template <class D, class S>
+__device__ inline void tail_stage(D* __restrict__ dst, const S* __restrict__ src, int n, int t, int NT) {
+  int k = t;
+  for (; k + 7 * NT < n; k += 8 * NT) {
+    S a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = src[k + q * NT];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[k + q * NT] = (D)a[q];
+  }
+  for (; k < n; k += NT) dst[k] = (D)src[k];
+}
+
+// Lanes per row for a tail phase over n rows of mean length avg: as many as
+// the workgroup allows (power of two, at most 32), not more than the row has.
+__device__ inline int tail_lanes(int n, int avg, int NT) {
+  int g = 1;
+  while (g < 32 && 2 * g * n <= NT && g < avg) g *= 2;
+  return g;
+}
+
+// Run f(G) with G the compile-time lane count for the runtime value g.
+template <class F>
+__device__ inline void tail_with_lanes(int g, F&& f) {
+  switch (g) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 32>{}); break;
+  }
+}
+
+// Row i of an LDS CSR matrix times x, split over the G lanes of a group
+// (lane g takes entries g, g+G, ...); the sum is returned in every lane.
+template <int G, class T, class TS>
+__device__ inline TS tail_row(const int32_t* rp, const int32_t* ci, const T* av, const T* x, int i, int g) {
+  TS s = 0;
+  const int k1 = rp[i + 1];
+#pragma unroll 4
+  for (int k = rp[i] + g; k < k1; k += G) s += (TS)av[k] * (TS)x[ci[k]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  return s;
+}
+
+// The tail's LDS image written to global memory (layout of
+// tail_lds_layout): int32 row offsets, operator values, diagonals, C/F flags,
+// one-point columns, R, and the coarsest inverse; the work vectors are left
+// unset.
 template <class T>
-__global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__ lv, int l0, int nlev,
-                                                   const double* __restrict__ cinv, const T* __restrict__ b_in,
-                                                   T* __restrict__ out, int nsw, T omega) {
-  extern __shared__ __align__(16) char sm[];
+__global__ __launch_bounds__(1024) void k_tail_image(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                                     const double* __restrict__ cinv, char* __restrict__ img) {
   __shared__ TailLds lo[TAIL_MAX_LEVELS];
   __shared__ int64_t s_cinv;
   const int t = threadIdx.x;
@@ -213,36 +267,67 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__
     s_cinv = oc;
   }
   __syncthreads();
-#define TL_PTR(type, l, f) reinterpret_cast<type*>(sm + lo[(l) - l0].f)
-  // stage the operators (independent loads, one barrier)
+#define TI_PTR(type, l, f) reinterpret_cast<type*>(img + lo[(l) - l0].f)
   for (int l = l0; l < last; ++l) {
     const TailLevel& L = lv[l];
     const int n = (int)L.n, nc = (int)L.nc, nnz = (int)L.nnz, nnzR = (int)L.nnzR;
-    int32_t* rp = TL_PTR(int32_t, l, rp);
-    int32_t* ci = TL_PTR(int32_t, l, ci);
-    T* v = TL_PTR(T, l, v);
-    T* d = TL_PTR(T, l, d);
-    int8_t* cf = TL_PTR(int8_t, l, cf);
-    int32_t* pc = TL_PTR(int32_t, l, pc);
-    int32_t* Rp = TL_PTR(int32_t, l, Rp);
-    int32_t* Rc = TL_PTR(int32_t, l, Rc);
-    T* Rv = TL_PTR(T, l, Rv);
-    const T* Ag = TLv<T>::A(L);
-    const T* dg = TLv<T>::d(L);
-    const T* Rg = TLv<T>::R(L);
-    for (int i = t; i <= n; i += NT) rp[i] = (int32_t)L.rp[i];
-    for (int k = t; k < nnz; k += NT) { ci[k] = L.ci[k]; v[k] = Ag[k]; }
-    for (int i = t; i < n; i += NT) { d[i] = dg[i]; cf[i] = L.cf[i]; pc[i] = L.pcol[i]; }
-    for (int i = t; i <= nc; i += NT) Rp[i] = (int32_t)L.Rp[i];
-    for (int k = t; k < nnzR; k += NT) { Rc[k] = L.Rc[k]; Rv[k] = Rg[k]; }
+    tail_stage(TI_PTR(int32_t, l, rp), L.rp, n + 1, t, NT);
+    tail_stage(TI_PTR(int32_t, l, ci), L.ci, nnz, t, NT);
+    tail_stage(TI_PTR(T, l, v), TLv<T>::A(L), nnz, t, NT);
+    tail_stage(TI_PTR(T, l, d), TLv<T>::d(L), n, t, NT);
+    tail_stage(TI_PTR(int8_t, l, cf), L.cf, n, t, NT);
+    tail_stage(TI_PTR(int32_t, l, pc), L.pcol, n, t, NT);
+    tail_stage(TI_PTR(int32_t, l, Rp), L.Rp, nc + 1, t, NT);
+    tail_stage(TI_PTR(int32_t, l, Rc), L.Rc, nnzR, t, NT);
+    tail_stage(TI_PTR(T, l, Rv), TLv<T>::R(L), nnzR, t, NT);
+  }
+#undef TI_PTR
+  const int nL = (int)lv[last].n;
+  tail_stage(reinterpret_cast<double*>(img + s_cinv), cinv, nL * nL, t, NT);
+}
+
+// Forward coarse end of the cycle from an LDS image: every array of levels
+// l0 .. nlev-1 and the coarsest inverse are copied into LDS, then the
+// restriction, coarsest solve, interpolation and F, F, C sweeps of all these
+// levels run out of LDS with workgroup barriers between the phases; each
+// phase gives a row to a group of lanes sized to the level.  The result of
+// level l0 is written to out.
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                                   const char* __restrict__ img, const T* __restrict__ b_in,
+                                                   T* __restrict__ out, int nsw, T omega) {
+  extern __shared__ __align__(16) char sm[];
+  __shared__ TailLds lo[TAIL_MAX_LEVELS];
+  __shared__ int64_t s_cinv, s_bytes;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  const int last = nlev - 1;
+  if (t == 0) {
+    int64_t oc = 0;
+    s_bytes = tail_lds_layout<(int)sizeof(T)>(lv, l0, nlev, lo, &oc);
+    s_cinv = oc;
+  }
+  __syncthreads();
+#define TL_PTR(type, l, f) reinterpret_cast<type*>(sm + lo[(l) - l0].f)
+  // stage the image past level l0's input vector in 16-byte chunks, all of a
+  // thread's loads issued before its stores; the input goes into that vector
+  {
+    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(img);
+    uint4* dst = reinterpret_cast<uint4*>(sm);
+    const int c1 = (int)(s_bytes >> 4);
+    int c = (int)(lo[0].x >> 4) + t;
+    for (; c + 7 * NT < c1; c += 8 * NT) {
+      uint4 a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = src[c + q * NT];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dst[c + q * NT] = a[q];
+    }
+    for (; c < c1; c += NT) dst[c] = src[c];
+    tail_stage(TL_PTR(T, l0, b), b_in, (int)lv[l0].n, t, NT);
   }
   const int nL = (int)lv[last].n;
-  double* ci_s = reinterpret_cast<double*>(sm + s_cinv);
-  for (int k = t; k < nL * nL; k += NT) ci_s[k] = cinv[k];
-  {
-    T* b0 = TL_PTR(T, l0, b);
-    for (int i = t; i < (int)lv[l0].n; i += NT) b0[i] = b_in[i];
-  }
+  const double* ci_s = reinterpret_cast<const double*>(sm + s_cinv);
   __syncthreads();
   // restriction down to the coarsest level
   for (int l = l0; l < last; ++l) {
@@ -252,18 +337,32 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__
     const T* Rv = TL_PTR(T, l, Rv);
     const T* b = TL_PTR(T, l, b);
     T* cb = TL_PTR(T, l + 1, b);
-    for (int i = t; i < nc; i += NT) cb[i] = row_dot_s<T>(Rp, Rc, Rv, b, i);
+    const int gR = tail_lanes(nc, nc ? (int)(lv[l].nnzR / nc) : 1, NT);
+    tail_with_lanes(gR, [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int g = t % G;
+      for (int i = t / G; i < nc; i += NT / G) {
+        const T r = tail_row<G, T, T>(Rp, Rc, Rv, b, i, g);
+        if (g == 0) cb[i] = r;
+      }
+    });
     __syncthreads();
   }
   // coarsest: y = C^-1 b (FP64 accumulation)
   {
     const T* b = TL_PTR(T, last, b);
     T* z = TL_PTR(T, last, y);
-    for (int i = t; i < nL; i += NT) {
-      double s = 0.0;
-      for (int j = 0; j < nL; ++j) s += ci_s[i * nL + j] * (double)b[j];
-      z[i] = (T)s;
-    }
+    tail_with_lanes(tail_lanes(nL, nL, NT), [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int g = t % G;
+      for (int i = t / G; i < nL; i += NT / G) {
+        double s = 0.0;
+        for (int j = g; j < nL; j += G) s += ci_s[i * nL + j] * (double)b[j];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (g == 0) z[i] = (T)s;
+      }
+    });
     __syncthreads();
   }
   // up: x = P e_c, then the sweeps ping-pong x -> y -> x -> y
@@ -278,25 +377,28 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__
     const T* bl = TL_PTR(T, l, b);
     const T* ec = TL_PTR(T, l + 1, y);
     T* cur = TL_PTR(T, l, x);
-    T* alt = TL_PTR(T, l, y);
     for (int i = t; i < n; i += NT) cur[i] = pc[i] >= 0 ? ec[pc[i]] : (T)0;
     __syncthreads();
+    const int gA = tail_lanes(n, n ? (int)(lv[l].nnz / n) : 1, NT);
     for (int s = 0; s < nsw; ++s) {
       const int X = (nsw == 1 || s < 2) ? 0 : 1;
       T* dst = (s % 2 == 0) ? TL_PTR(T, l, y) : TL_PTR(T, l, x);
-      for (int i = t; i < n; i += NT) {
-        T xi = cur[i];
-        if (cf[i] == X) {
-          const T di = d[i];
-          if (fabs((double)di) >= 1e-30) xi += omega * (bl[i] - row_dot_s<T>(rp, ci, v, cur, i)) / di;
+      tail_with_lanes(gA, [&](auto GC) {
+        constexpr int G = decltype(GC)::value;
+        const int g = t % G;
+        for (int i = t / G; i < n; i += NT / G) {
+          T xi = cur[i];
+          if (cf[i] == X) {
+            const T di = d[i];
+            const T r = tail_row<G, T, T>(rp, ci, v, cur, i, g);
+            if (fabs((double)di) >= 1e-30) xi += omega * (bl[i] - r) / di;
+          }
+          if (g == 0) dst[i] = xi;
         }
-        dst[i] = xi;
-      }
+      });
       __syncthreads();
-      alt = cur;
       cur = dst;
     }
-    (void)alt;
   }
   // the level-l0 result is in y (odd number of sweeps) or in y (coarsest only)
   {
@@ -582,10 +684,22 @@ static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, c
   return AH_OK;
 }
 
+// Lanes per row of the facet-block kernels: about eight values per lane
+// (the row is one chain of dependent loads per lane, so short rows per lane
+// and more rows per wave keep more loads in flight).
+static int fb_lanes(int64_t nvals, int64_t n) {
+  const double avg = n ? (double)nvals / (double)n : 0.0;
+  if (avg < 12) return 2;
+  if (avg < 48) return 4;
+  if (avg < 96) return 8;
+  return 16;
+}
+
 template <class TA, class TX, class TY, int MODE, int B>
 static void fb_launch(int G, dim3 grid, hipStream_t st, int64_t n, const int64_t* optr, const int32_t* ocol,
                       const TA* ov, const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2) {
   switch (G) {
+    case 2: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 2, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
     case 4: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 4, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
     case 8: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 8, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
     default: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 16, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
@@ -593,13 +707,13 @@ static void fb_launch(int G, dim3 grid, hipStream_t st, int64_t n, const int64_t
 }
 
 // Level-0 rows in the off-diagonal facet-block layout (k_fb): n rows (the
-// listed ones for SP_SWEEP_LIST), block size B, G in {4, 8, 16}.
+// listed ones for SP_SWEEP_LIST), block size B, G in {2, 4, 8, 16}.
 template <class TA, class TX, class TY, int MODE>
 static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_t* ocol, const TA* ov, const TX* x,
                       const TY* b, TY omega, TY* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
                       const int32_t* list = nullptr, TY* y2 = nullptr) {
   if (n == 0) return AH_OK;
-  if (G != 4 && G != 8) G = 16;
+  if (G != 2 && G != 4 && G != 8) G = 16;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   const dim3 grid((unsigned)cdiv(n * G, 256));
@@ -636,6 +750,25 @@ static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
   const int64_t nvX = X == 0 ? L.novF : L.nov - L.novF;
   return (double)nvX * w + (double)(L.nov / (L.ob * L.ob)) * 4.0 + (double)(L.n / L.ob + 1) * 8.0 +
          (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 3.0 : 2.0) * w;
+}
+
+ah_status tail_image_build(ah_hier* h, hipStream_t st) {
+  if (!h->tail_lds || h->tail0 < 0) return AH_OK;
+  const int nlev = (int)h->lev.size();
+  for (int w = 0; w < 2; ++w) {
+    if (w == 1 && !h->prm.fp32_cycle) break;
+    double* img = nullptr;
+    AH_TRY(h->arena.get(&img, (h->tail_bytes[w] + 15) / 8 + 2));
+    if (w == 0)
+      hipLaunchKernelGGL(k_tail_image<double>, dim3(1), dim3(1024), 0, st, h->d_tail, h->tail0, nlev, h->cinv,
+                         reinterpret_cast<char*>(img));
+    else
+      hipLaunchKernelGGL(k_tail_image<float>, dim3(1), dim3(1024), 0, st, h->d_tail, h->tail0, nlev, h->cinv,
+                         reinterpret_cast<char*>(img));
+    AH_LAUNCHED();
+    h->tail_img[w] = reinterpret_cast<const char*>(img);
+  }
+  return AH_OK;
 }
 
 // ------------------------------------------------------------ V-cycles
@@ -688,8 +821,8 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                                   (int)TAIL_LDS_MAX);
       });
       const int64_t bytes = h->tail_bytes[sizeof(T) == 8 ? 0 : 1];
-      hipLaunchKernelGGL((k_tail_lds<T>), dim3(1), dim3(1024), (unsigned)bytes, st, h->d_tail, l, nlev, h->cinv, b,
-                         out, nsw, (T)h->prm.omega);
+      hipLaunchKernelGGL((k_tail_lds<T>), dim3(1), dim3(1024), (unsigned)bytes, st, h->d_tail, l, nlev,
+                         h->tail_img[sizeof(T) == 8 ? 0 : 1], b, out, nsw, (T)h->prm.omega);
     } else {
       hipLaunchKernelGGL((k_tail<T, false>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, b, out, nsw,
                          (T)h->prm.omega);
@@ -745,7 +878,7 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   const char* tf = sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
   const char* tc = sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
   if (L.ob && Ops<T>::O(L)) {
-    const int Gb = h->g0 ? h->g0 : pick_g(L.nov, L.n);
+    const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
     const T* ov = Ops<T>::O(L);
     AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, x, b, om, y, st, tf,
                                          fb_sweep_bytes<T>(L, 0, false), L.flist)));
@@ -949,7 +1082,7 @@ struct Op {
 
 static int op_lanes(const ah_hier* h, const Op& A, int64_t n) {
   if (h->g0) return h->g0;
-  return A.ob ? pick_g(A.nov, n) : pick_g(h->lev[0].nnz, n);
+  return A.ob ? fb_lanes(A.nov, n) : pick_g(h->lev[0].nnz, n);
 }
 
 // Algorithmic bytes of y = A x (x of width wx): the operator once, x once,

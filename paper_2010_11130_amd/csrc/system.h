@@ -40,6 +40,10 @@ struct ah_system {
 
 namespace ah {
 
+// Build the LDS image of the forward tail in global memory (once per
+// hierarchy; the cycle then stages it with one contiguous copy).
+ah_status tail_image_build(ah_hier* h, hipStream_t st);
+
 // Exclusive prefix sum of n int64 values into out[0..n] (out[n] = total).
 ah_status scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
 // Same for int32 counts producing int64 offsets.
@@ -175,6 +179,7 @@ struct ah_hier {
   int64_t tail_bytes[2] = {0, 0};   // size of that image with FP64 / FP32 values
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
   TailLevel* d_tail = nullptr; // device copy of every level's pointers
+  const char* tail_img[2] = {nullptr, nullptr};   // the tail's LDS image (FP64 / FP32), built at setup
   ah::Arena arena;
   ah_air_params prm{};
   std::vector<AhLevel> lev;
