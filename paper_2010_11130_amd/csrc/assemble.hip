@@ -569,67 +569,81 @@ __global__ __launch_bounds__(64) void k_diag_inv(int64_t nfree, const int64_t* _
     for (int j = 0; j < B; ++j) dinv[r * B * B + i * B + j] = I[i][j];
 }
 
-// Scaled scalar rows: row R*B+m of D_b^-1 S over the block row R; the
-// diagonal block becomes the identity; exact zeros off the diagonal are
-// dropped.  unscaled: the rows of S itself (the diagonal entry is always
-// kept).  One wave per scalar row: lane c handles candidate (block c/B,
-// node c%B), kept entries are packed in order with a ballot, so a row's
-// stores are contiguous.  Count pass (val == nullptr), then fill pass.
+// Scalar CSR of the level-0 operator on the structural pattern of the free
+// facets (entries that happen to be zero are kept).  Scaled system: row
+// R*B+m of D_b^-1 S, whose diagonal block is the identity, so the row holds
+// its diagonal entry 1 and the B entries of every off-diagonal block, in
+// column order; unscaled: the B entries of every block of S, the diagonal
+// block included.  Row offsets follow from the block pattern (scaled:
+// B R + B^2 odb_ptr[R] for the block row, 1 + B (nb - 1) per row).
+template <int B>
+__global__ void k_scaled_rowptr(int64_t nfree, const int64_t* __restrict__ bptr,
+                                const int64_t* __restrict__ optr, int unscaled, int64_t* __restrict__ rowptr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = nfree * B;
+  if (i > n) return;
+  const int64_t R = i / B;
+  const int m = (int)(i - R * B);
+  if (unscaled) {
+    const int64_t nb = R < nfree ? bptr[R + 1] - bptr[R] : 0;
+    rowptr[i] = (int64_t)B * B * bptr[R] + (int64_t)m * B * nb;
+  } else {
+    const int64_t nob = R < nfree ? optr[R + 1] - optr[R] : 0;
+    rowptr[i] = (int64_t)B * R + (int64_t)B * B * optr[R] + (int64_t)m * (1 + B * nob);
+  }
+}
+
+// One wave per block row R: lane c takes column c of the block row (block
+// c/B, node c%B), reads that column of S's block once and writes its B
+// scaled entries into the B scalar rows, and into the off-diagonal
+// facet-block copy (oval, scaled systems).
 template <int B>
 __global__ __launch_bounds__(256) void k_csr_scaled(int64_t nfree, const int64_t* __restrict__ bptr,
                                                     const int32_t* __restrict__ bcol, const double* __restrict__ bval,
-                                                    const double* __restrict__ dinv, int32_t* __restrict__ cnt,
-                                                    const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                    const double* __restrict__ dinv, int32_t* __restrict__ col,
                                                     double* __restrict__ val, int unscaled,
                                                     const int64_t* __restrict__ optr, double* __restrict__ oval) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t R = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (i >= nfree * B) return;
-  const int64_t R = i / B;
-  const int m = (int)(i % B);
+  if (R >= nfree) return;
   const int64_t s0 = bptr[R];
-  const int ncand = (int)(bptr[R + 1] - s0) * B;
-  int64_t out = rowptr ? rowptr[i] : 0;
-  // off-diagonal facet-block copy of row i (fill pass of a scaled system)
-  double* orow = nullptr;
-  if (oval) {
-    const int64_t o0 = optr[R];
-    orow = oval + o0 * B * B + (int64_t)m * (optr[R + 1] - o0) * B;
-  }
-  int c0 = 0;
-  for (int base = 0; base < ncand; base += 64) {
-    const int cidx = base + lane;
-    bool keep = false;
-    double v = 0.0;
-    int32_t colv = 0;
-    if (cidx < ncand) {
-      const int64_t s = s0 + cidx / B;
-      const int n = cidx % B;
-      const int32_t C = bcol[s];
-      colv = (int32_t)(C * B + n);
-      if (C == R && !unscaled) {
-        v = n == m ? 1.0 : 0.0;
-        keep = n == m;
-      } else if (unscaled) {
-        v = bval[s * B * B + m * B + n];
-        keep = v != 0.0 || (C == R && n == m);
-      } else {
+  const int nb = (int)(bptr[R + 1] - s0);
+  const int64_t o0 = unscaled ? 0 : optr[R];
+  const int nob = unscaled ? 0 : (int)(optr[R + 1] - o0);
+  // first entry of the block row and the length of each of its rows
+  const int64_t base = unscaled ? (int64_t)B * B * s0 : (int64_t)B * R + (int64_t)B * B * o0;
+  const int rlen = unscaled ? B * nb : 1 + B * nob;
+  for (int c = lane; c < nb * B; c += 64) {
+    const int j = c / B, n = c % B;
+    const int64_t s = s0 + j;
+    const int32_t C = bcol[s];
+    double bc[B];
 #pragma unroll
-        for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * bval[s * B * B + k * B + n];
-        keep = v != 0.0;
-        // blocks after the diagonal one sit one slot earlier in the copy
-        if (orow) orow[cidx - (C > R ? B : 0)] = v;
+    for (int k = 0; k < B; ++k) bc[k] = bval[s * B * B + k * B + n];
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      const int64_t rs = base + (int64_t)m * rlen;
+      if (unscaled) {
+        col[rs + c] = (int32_t)(C * B + n);
+        val[rs + c] = bc[m];
+      } else if (C == R) {
+        if (n == m) {
+          col[rs + j * B] = (int32_t)(R * B + m);
+          val[rs + j * B] = 1.0;
+        }
+      } else {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k) v += dinv[R * B * B + m * B + k] * bc[k];
+        // one diagonal entry precedes the blocks after the diagonal block
+        const int pos = C < R ? c : c - B + 1;
+        col[rs + pos] = (int32_t)(C * B + n);
+        val[rs + pos] = v;
+        const int jo = C < R ? j : j - 1;
+        oval[o0 * B * B + (int64_t)m * nob * B + jo * B + n] = v;
       }
     }
-    const unsigned long long mask = __ballot(keep);
-    if (val && keep) {
-      const int pos = c0 + __popcll(mask & ((1ull << lane) - 1ull));
-      col[out + pos] = colv;
-      val[out + pos] = v;
-    }
-    c0 += __popcll(mask);
   }
-  if (!val && lane == 0) cnt[i] = c0;
 }
 
 template <int B>
@@ -838,30 +852,23 @@ static ah_status scale_to_csr(ah_system* s, const ah_mesh* m, hipStream_t st, in
     hipLaunchKernelGGL(k_diag_inv<B>, dim3(cdiv(std::max<int64_t>(nfree, 1), 64)), dim3(64), 0, st, nfree,
                        m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv, d_err);
   AH_LAUNCHED();
-  int32_t* cnt = nullptr;
-  Arena tmp;
-  tmp.stream = st;
-  AH_TRY(tmp.get(&cnt, n + 1));
-  AH_TRY(ar.get(&s->d_rowptr, n + 1));
-  const dim3 gw((unsigned)cdiv(std::max<int64_t>(n, 1) * 64, 256));
-  hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, (const int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int)s->unscaled,
-                     (const int64_t*)nullptr, (double*)nullptr);
-  AH_LAUNCHED();
-  AH_TRY(scan_i32_to_i64(cnt, s->d_rowptr, n, st, tmp));
-  AH_TRY(read_i64(s->d_rowptr + n, &s->nnz, st));
+  const int64_t nob = (int64_t)m->odb_col.size();
+  s->nnz = s->unscaled ? (int64_t)B * B * s->nnzb : n + (int64_t)B * B * nob;
   if (s->nnz >= ((int64_t)1 << 31)) {
-    tmp.release();
     set_error("level-0 matrix has %lld entries (limit 2^31)", (long long)s->nnz);
     return AH_EUNSUPPORTED;
   }
+  AH_TRY(ar.get(&s->d_rowptr, n + 1));
   AH_TRY(ar.get(&s->d_col, s->nnz));
   AH_TRY(ar.get(&s->d_val, s->nnz));
-  if (!s->unscaled) AH_TRY(ar.get(&s->d_odv, (int64_t)m->odb_col.size() * B * B));
-  hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
-                     cnt, s->d_rowptr, s->d_col, s->d_val, (int)s->unscaled, (const int64_t*)m->d_odb_ptr, s->d_odv);
+  if (!s->unscaled) AH_TRY(ar.get(&s->d_odv, nob * B * B));
+  hipLaunchKernelGGL(k_scaled_rowptr<B>, dim3((unsigned)cdiv(n + 1, 256)), dim3(256), 0, st, nfree, m->d_bsr_ptr,
+                     (const int64_t*)m->d_odb_ptr, (int)s->unscaled, s->d_rowptr);
   AH_LAUNCHED();
-  tmp.release();
+  const dim3 gw((unsigned)cdiv(std::max<int64_t>(nfree, 1) * 64, 256));
+  hipLaunchKernelGGL(k_csr_scaled<B>, gw, dim3(256), 0, st, nfree, m->d_bsr_ptr, m->d_bsr_col, s->d_bval, s->d_Dinv,
+                     s->d_col, s->d_val, (int)s->unscaled, (const int64_t*)m->d_odb_ptr, s->d_odv);
+  AH_LAUNCHED();
   return AH_OK;
 }
 
