@@ -443,13 +443,26 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
   }
 }
 
-__global__ void k_diag(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                       const double* __restrict__ v, double* __restrict__ d, float* __restrict__ d32) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Diagonal of a CSR matrix (0 where a row has no diagonal entry), PG lanes
+// per row.
+__global__ __launch_bounds__(256) void k_diag(int64_t n, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                              double* __restrict__ d, float* __restrict__ d32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / PG;
+  const int g = (int)(gid % PG);
   if (i >= n) return;
   double x = 0.0;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-    if (ci[k] == i) { x = v[k]; break; }
+  int hit = 0;
+  for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG)
+    if (ci[k] == i) { x = v[k]; hit = 1; break; }
+  // the row holds at most one diagonal entry: its lane passes it on
+  for (int o = PG / 2; o > 0; o >>= 1) {
+    const double ox = __shfl_xor(x, o, PG);
+    const int oh = __shfl_xor(hit, o, PG);
+    if (oh) { x = ox; hit = 1; }
+  }
+  if (g != 0) return;
   d[i] = x;
   if (d32) d32[i] = (float)x;
 }
@@ -756,6 +769,24 @@ static ah_status transpose(int64_t nrow, int64_t ncol, const int64_t* rp, const 
   return AH_OK;
 }
 
+// out[0] = max(out[0], max of a[0..n)): grid-stride, one atomic per block.
+__global__ __launch_bounds__(256) void k_max_i32(int64_t n, const int32_t* __restrict__ a, int* __restrict__ out) {
+  __shared__ int red[4];
+  int m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = a[i] > m ? a[i] : m;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int q = __shfl_xor(m, o, 64);
+    m = q > m ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int b = max(max(red[0], red[1]), max(red[2], red[3]));
+    if (b) atomicMax(out, b);
+  }
+}
+
 template <int HS>
 static ah_status rap_launch(int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
                             double* cval, bool numeric, hipStream_t st) {
@@ -773,6 +804,8 @@ static ah_status rap_launch(int64_t nc, const AhLevel& L, int32_t* cnt, const in
 static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
                               double* cval, bool numeric, hipStream_t st) {
   switch (hs) {
+    case 64: return rap_launch<64>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+    case 128: return rap_launch<128>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 256: return rap_launch<256>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 1024: return rap_launch<1024>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 2048: return rap_launch<2048>(nc, L, cnt, cptr, ccol, cval, numeric, st);
@@ -823,7 +856,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
 #define CK(x) do { rc = (x); if (rc < 0) { tmp.release(); delete h; return rc; } } while (0)
 #define CKH(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error("air_setup: %s", hipGetErrorString(e_)); tmp.release(); delete h; return AH_EHIP; } } while (0)
   unsigned long long* d_ull = nullptr;   // [0..1] undecided counts (alternating rounds), [2] lAIR fallbacks
-  int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error
+  int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error, [3] max A_c row
   unsigned long long* d_fst = nullptr;   // per level: F rows, F-row entries
   CK(ar.get(&d_ull, 4));
   CK(ar.get(&d_int, 4));
@@ -861,7 +894,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
         CKH(hipGetLastError());
       }
     }
-    hipLaunchKernelGGL(k_diag, g1(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, L.diag, L.diag32);
+    hipLaunchKernelGGL(k_diag, g1(n * PG), dim3(256), 0, st, n, L.rowptr, L.col, L.val, L.diag, L.diag32);
     CKH(hipGetLastError());
     CK(ar.get(&L.b, n)); CK(ar.get(&L.x, n)); CK(ar.get(&L.y, n)); CK(ar.get(&L.e, n));
     if (prm.fp32_cycle) {
@@ -943,7 +976,15 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(ar.get(&L.Rcol, L.nnzR));
     CK(ar.get(&L.Rval, L.nnzR));
     const int maxm = hmax[0];
-    if (maxm <= 32)
+    // the smallest local-system capacity that holds every neighbourhood
+    // (LDS per workgroup, hence occupancy, grows with its square)
+    if (maxm <= 8)
+      hipLaunchKernelGGL(k_lair<8>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
+    else if (maxm <= 16)
+      hipLaunchKernelGGL(k_lair<16>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
+                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
+    else if (maxm <= 32)
       hipLaunchKernelGGL(k_lair<32>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
                          L.Rptr, L.Rcol, L.Rval, d_ull + 2);
     else if (maxm <= 64)
@@ -964,7 +1005,23 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(rap_dispatch(hs, nc, L, ccnt, nullptr, nullptr, nullptr, false, st));
     CK(ar.get(&C.rowptr, nc + 1));
     CK(scan_i32_to_i64(ccnt, C.rowptr, nc, st, tmp));
-    CK(read_i64(C.rowptr + nc, &C.nnz, st));
+    // the numeric pass hashes a row's distinct coarse columns only: size its
+    // table from the largest row of A_c
+    int rmax = 0;
+    {
+      hipLaunchKernelGGL(k_max_i32, dim3((unsigned)std::min<int64_t>(cdiv(nc, 256), 256)), dim3(256), 0, st, nc, ccnt,
+                         d_int + 3);
+      CKH(hipGetLastError());
+      double* pin = pinned_scratch(2);
+      if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
+      CKH(hipMemcpyAsync(pin, C.rowptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(pin + 1, d_int + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+      CKH(hipStreamSynchronize(st));
+      std::memcpy(&C.nnz, pin, sizeof(int64_t));
+      std::memcpy(&rmax, pin + 1, sizeof(int));
+    }
+    int hsn = 64;
+    while (hsn < 2 * rmax && hsn < hs) hsn *= 2;
     CK(ar.get(&C.col, C.nnz));
     CK(ar.get(&C.val, C.nnz));
     {
@@ -974,7 +1031,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       double by = (double)L.nnzR * 12.0 + (double)(nc + 1) * 8.0 + (double)C.nnz * 12.0 + (double)(nc + 1) * 8.0 +
                   (double)L.nnz * 12.0 + (double)n * 4.0;
       prof_begin(ps, l == 0 ? "rap0" : nullptr, st, by);
-      CK(rap_dispatch(hs, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
+      CK(rap_dispatch(hsn, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
       prof_end(ps);
     }
     if (prm.fp32_cycle) {
