@@ -602,15 +602,52 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int nblk, const double* 
   if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
 }
 
-// w -= sum_v V_v h_v, and the block partial sums of the updated w.w
+// hs[v] = sum over b of partial[v][b] for v < nv, into LDS: wave v % 4
+// sums a lane-strided slice and reduces it across the wave.  The order is
+// fixed, so every block of a launch obtains the same values.
+__device__ inline void partials_to_lds(const double* __restrict__ partial, int nblk, int nv, double* hs) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wv; v < nv; v += nw) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)v * nblk + b];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) hs[v] = s;
+  }
+  __syncthreads();
+}
+
+// Classical Gram-Schmidt step from the block partials of k_multidot
+// (V_v.w for v < k, w.w at k): h = their sums, w -= sum_{v<k} V_v h_v; block
+// 0 also stores h[0..k] in hout.  Dynamic LDS: (k+1) doubles.
+__global__ __launch_bounds__(DOT_T) void k_maxpy_p(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ partial, int nblk,
+                                                   double* __restrict__ w, double* __restrict__ hout) {
+  extern __shared__ double hs[];
+  partials_to_lds(partial, nblk, k + 1, hs);
+  if (blockIdx.x == 0)
+    for (int v = threadIdx.x; v <= k; v += DOT_T) hout[v] = hs[v];
+  for (int64_t i = (int64_t)blockIdx.x * DOT_T + threadIdx.x; i < n; i += (int64_t)gridDim.x * DOT_T) {
+    double s = 0.0;
+    for (int v = 0; v < k; ++v) s += V[(int64_t)v * ldv + i] * hs[v];
+    w[i] -= s;
+  }
+}
+
+// The same step with the block partial sums of the updated w.w written to
+// pout[blockIdx.x] (nblk blocks; pout must not overlap partial).
 __global__ __launch_bounds__(DOT_T) void k_maxpy_norm(int64_t n, int k, const double* __restrict__ V, int64_t ldv,
-                                                      const double* __restrict__ h, double* __restrict__ w,
-                                                      double* __restrict__ partial, int nblk) {
+                                                      const double* __restrict__ partial, int nblk,
+                                                      double* __restrict__ w, double* __restrict__ hout,
+                                                      double* __restrict__ pout) {
+  extern __shared__ double hs[];
   __shared__ double red[DOT_T / 64];
+  partials_to_lds(partial, nblk, k + 1, hs);
+  if (blockIdx.x == 0)
+    for (int v = threadIdx.x; v <= k; v += DOT_T) hout[v] = hs[v];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * DOT_T + threadIdx.x; i < n; i += (int64_t)nblk * DOT_T) {
     double s = 0.0;
-    for (int v = 0; v < k; ++v) s += V[(int64_t)v * ldv + i] * h[v];
+    for (int v = 0; v < k; ++v) s += V[(int64_t)v * ldv + i] * hs[v];
     double wi = w[i] - s;
     w[i] = wi;
     acc += wi * wi;
@@ -621,7 +658,7 @@ __global__ __launch_bounds__(DOT_T) void k_maxpy_norm(int64_t n, int k, const do
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int q = 0; q < DOT_T / 64; ++q) s += red[q];
-    partial[blockIdx.x] = s;
+    pout[blockIdx.x] = s;
   }
 }
 
@@ -1054,6 +1091,10 @@ __global__ __launch_bounds__(256) void k_bicg_xr(int64_t n, const double* __rest
   }
 }
 
+// Blocks of the multi-vector dot kernels (at most 1024, about four rows per
+// thread).
+static int dot_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, DOT_T * 4))); }
+
 // out[0..k] = V[0..k-1].w and w.w (k vectors plus the norm), on the device.
 static ah_status multidot(int64_t n, int k, const double* V, const double* w, double* partial, double* out,
                           hipStream_t st) {
@@ -1165,14 +1206,20 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       double* h1 = hd;               // [k+1]: dots, then ||w0||^2 at [k]
       double* h2 = hd + (m + 2);     // [k+1]
       double* hn = hd + 2 * (m + 2); // [1]
-      AH_TRY(multidot(n, k, h->V, h->w, h->partial, h1, st));
-      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, k, h->V, n, h1, h->w, -1.0);
-      AH_LAUNCHED();
-      AH_TRY(multidot(n, k, h->V, h->w, h->partial, h2, st));
+      // each pass: block partials of the dots, then one kernel that sums
+      // them (every block, fixed order) and updates w
       {
-        int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, DOT_T * 4)));
-        hipLaunchKernelGGL(k_maxpy_norm, dim3(nblk), dim3(DOT_T), 0, st, n, k, h->V, n, h2, h->w, h->partial, nblk);
-        hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, h->partial, hn, 0);
+        const int nblk = dot_blocks(n);
+        const unsigned hb = (unsigned)((k + 1) * sizeof(double));
+        double* p3 = h->partial + (int64_t)(m + 2) * 1024;   // clear of the (k+1) nblk dot partials
+        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, h->V, n,
+                           h->w, h->partial, nblk);
+        hipLaunchKernelGGL(k_maxpy_p, dim3(nblk), dim3(DOT_T), hb, st, n, k, h->V, n, h->partial, nblk, h->w, h1);
+        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, h->V, n,
+                           h->w, h->partial, nblk);
+        hipLaunchKernelGGL(k_maxpy_norm, dim3(nblk), dim3(DOT_T), hb, st, n, k, h->V, n, h->partial, nblk, h->w, h2,
+                           p3);
+        hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, p3, hn, 0);
         AH_LAUNCHED();
       }
       AH_HIP(hipMemcpyAsync(hh, hd, (3 * (m + 2)) * sizeof(double), hipMemcpyDeviceToHost, st));
