@@ -47,7 +47,7 @@ def parse():
                     help="skip the all-at-once solve of the stacked slabs")
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB march and the no-block-inverse ablation")
-    ap.add_argument("--builders", type=int, default=2,
+    ap.add_argument("--builders", type=int, default=1,
                     help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the sequential pass that gives the stage split")
@@ -272,7 +272,7 @@ class March:
         self.g = torch.stack(g).contiguous()
         self.a = torch.as_tensor(self.prob.a(v), device="cuda").contiguous()
         self.nu = nu
-        self.builders = 2
+        self.builders = 1
         torch.cuda.synchronize()
 
     def step(self, precision, tol, pipelined=True, stages=None, method=0, iters=None):
@@ -292,6 +292,7 @@ class March:
         s, x, info = m.run([self.g[k] for k in range(self.slabs)], pipelined=pipelined, on_slab=keep_u,
                            stages=stages)
         self.torch.cuda.synchronize()
+        self.wait_s = getattr(self, "wait_s", 0.0) + getattr(m, "wait_s", 0.0)
         return x, out["U"]
 
 
@@ -320,12 +321,15 @@ def run_timed(march, precision, steps, warmup, tol, sequential=True):
     lib().ah_profile_reset()
     lib().ah_profile_enable(1)
     torch.cuda.synchronize()
+    march.wait_s = 0.0
     t0 = time.perf_counter()
     last = None
     for _ in range(steps):
         last = march.step(precision, tol)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # time the solving thread spent waiting for the builder, per step
+    march.wait_ms_per_step = 1e3 * march.wait_s / steps
     lib().ah_profile_enable(0)
     prof = profile_totals(PROFILE_TAGS)
     lib().ah_profile_reset()
@@ -497,6 +501,7 @@ def main():
                                   args.tol),
                    "free_dofs_per_slab": ndof_slab, "slabs": args.slabs, "total_free_dofs": total},
         "kernels": prof64,
+        "build_wait_ms_per_step": march.wait_ms_per_step,
     }
     if stages64:
         out["levels"] = stages64[0]["levels"]

@@ -286,9 +286,10 @@ ah_status ah_source_gauss_T(int dim_st, int64_t npts, const double* X, int K,
  * tagged kernel is bracketed by HIP events recorded on its own stream, and
  * its algorithmic byte count (what the operation must read and write once)
  * is accumulated.  Tags: "element" (hdg_assemble element kernel),
- * "spmv0" (level-0 FP64 product in FGMRES), "sweep0" / "sweep0_f32"
- * (level-0 Jacobi sweeps), "rap0" (level-0 numeric R A P).
- * ah_profile_read synchronizes the recorded events. */
+ * "spmv0" (level-0 FP64 product of the Krylov solver), "relax0_f" /
+ * "relax0_c" (level-0 F and C Jacobi sweeps; "_f32" suffix: FP32 cycle),
+ * "rap0" (level-0 numeric R A P).  ah_profile_read synchronizes the
+ * recorded events. */
 void ah_profile_enable(int on);
 void ah_profile_reset(void);
 ah_status ah_profile_read(const char* tag, int64_t* launches, double* total_ms, double* bytes);

@@ -9,10 +9,12 @@ depend on slab n's solution -- only the Neumann rows of its right-hand side
 do.  Builder threads assemble and set up the next slabs, each on its own HIP
 stream, while the calling thread solves slab n; the calling thread then
 writes the inflow rows (``hdg_inflow_from_trace``) and refreshes the
-right-hand side (``hdg_update_neumann``).  Assembly and setup are bound by
-host synchronizations (sizes read back between phases), so two builders
-overlap each other's waits.  Both modes run the same kernels on the same
-data, so their results agree bit for bit.
+right-hand side (``hdg_update_neumann``).  The solve of slab n is the
+critical path: every kernel a builder runs competes with it for the GPU, so
+one builder (one slab of lookahead) is the default; more builders overlap
+each other's host waits but slow the solve down more than they gain.  Both
+modes run the same kernels on the same data, so their results agree bit for
+bit.
 """
 import threading
 import time
@@ -34,7 +36,7 @@ class SlabMarch:
     """
 
     def __init__(self, mesh, p, nu, a_vert, f_q=None, alpha=0.0, air_kw=None, solve_kw=None, keep=True,
-                 builders=2):
+                 builders=1):
         self.mesh, self.p, self.nu, self.a, self.f = mesh, p, float(nu), a_vert, f_q
         self.alpha, self.keep = alpha, keep
         self.builders = builders
@@ -138,11 +140,14 @@ class SlabMarch:
         prev = None
         held = None
         last = None
+        self.wait_s = 0.0       # time the solving thread waited for builds
         try:
             for k in range(S):
                 with cond:
+                    t_w = time.perf_counter()
                     while k not in ready and -1 not in ready:
                         cond.wait()
+                    self.wait_s += time.perf_counter() - t_w
                     if -1 in ready:
                         raise ready[-1]
                     s, h, ev = ready.pop(k)
