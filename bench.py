@@ -47,6 +47,8 @@ def parse():
                     help="skip the all-at-once solve of the stacked slabs")
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB march and the no-block-inverse ablation")
+    ap.add_argument("--no-internal-layer", action="store_true",
+                    help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--builders", type=int, default=1,
                     help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
@@ -386,6 +388,47 @@ def all_at_once(args, U_march_last):
             "levels": h.info["levels"], "last_slab_rel_diff_vs_march": diff}
 
 
+def internal_layer(n=48, p=1, tol=1e-8):
+    """The moving internal layer of Section 4.2 (nu = 0, discontinuous exact
+    solution) on the uniform n^3 Kuhn mesh of the space-time unit cube, all
+    at once: assembly, lAIR setup, FGMRES and reconstruction, timed after one
+    warm-up run with the mesh and boundary data on the device."""
+    import numpy as np
+    import torch
+    from paper_2010_11130_amd import Mesh, System, Hierarchy
+    from workloads import kuhn_cube_mesh, boundary_kinds
+    from workloads.problems import MovingInternalLayer
+    prob = MovingInternalLayer()
+    v, c = kuhn_cube_mesh(n)
+    m = Mesh(v, c)
+    fv, _ = m.facets()
+    bf = m.boundary_facets()
+    isb = np.zeros(m.nf, dtype=bool)
+    isb[bf] = True
+    kinds = boundary_kinds(v, fv, isb)
+    m.set_bc(kinds)
+    _, xb = m.quad_points(p)
+    kb = torch.as_tensor(kinds[bf], device="cuda")[:, None]
+    # Dirichlet: the exact solution; initial plane: u(0) = 0; final plane: 0
+    g = torch.where(kb == 1, prob.u(xb), torch.zeros_like(xb[..., 0])).contiguous()
+    a = torch.as_tensor(prob.a(v), device="cuda").contiguous()
+    res = None
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = System(m, p, 0.0, a, None, g)
+        h = Hierarchy(s)
+        x, info = h.solve(tol=tol)
+        s.reconstruct(x)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res = (s, h, info, t)
+    s, h, info, t = res
+    return {"value": s.n / t, "unit": "DOF/s", "ms": 1e3 * t, "mesh": "%d^3 Kuhn cubes, %d tets" % (n, 6 * n ** 3),
+            "p": p, "free_dofs": s.n, "iters": info["iters"], "levels": h.info["levels"],
+            "op_complexity": h.info["op_complexity"]}
+
+
 def element_flops(D, p):
     """Algorithmic FP64 flops of one space-time element (the element kernel):
     the quadrature sums of A, B, C, the diagonal facet blocks of D and F
@@ -537,6 +580,8 @@ def main():
     # all-at-once: the 64 slabs as one space-time system on one GPU
     if not args.no_all_at_once:
         out["all_at_once"] = all_at_once(args, last64[1])
+    if not args.no_internal_layer:
+        out["internal_layer"] = internal_layer(tol=args.tol)
     # dominant tagged kernel of the FP64 march
     if prof64:
         out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])

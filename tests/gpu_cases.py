@@ -7,7 +7,7 @@ import torch
 from workloads import (square_tri_mesh, slab_prism_tet_mesh, kuhn_cube_mesh, map_vertices_c5,
                        pulse_slab_mesh, boundary_kinds)
 from workloads.problems import (C1Advection1D, slab_hill, SmoothPlusFront, GaussianSources,
-                                PolynomialProblem, c5_sources, paper_pulse)
+                                PolynomialProblem, c5_sources, paper_pulse, MovingInternalLayer)
 
 
 def case(name):
@@ -28,6 +28,12 @@ def case(name):
         nu = {"kuhn_nu0": 0.0, "kuhn_nu4": 1e-4, "kuhn_nu2": 1e-2}[name]
         v, c = kuhn_cube_mesh(6)
         return v, c, SmoothPlusFront(nu, width=0.1), 1
+    if name == "layer":
+        v, c = kuhn_cube_mesh(6)
+        return v, c, MovingInternalLayer(), 1
+    if name == "layer_p2":
+        v, c = kuhn_cube_mesh(4)
+        return v, c, MovingInternalLayer(), 2
     if name == "c5":
         v, c = kuhn_cube_mesh(3)
         v = map_vertices_c5(v)

@@ -23,7 +23,7 @@ from gpu_cases import case, gpu_system, to_scipy, rel_sparse_diff
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["c1", "c1_p3", "slab", "slab_nu0", "kuhn_nu0", "kuhn_nu4", "kuhn_nu2", "c5", "kuhn_p3"]
+CASES = ["c1", "c1_p3", "slab", "slab_nu0", "kuhn_nu0", "kuhn_nu4", "kuhn_nu2", "c5", "kuhn_p3", "layer", "layer_p2"]
 SMALL_COARSE = 40
 
 

@@ -14,7 +14,7 @@ from oracle.drivers import (setup_problem, direct_solve, solve_all_at_once, solv
 from workloads import (square_tri_mesh, slab_prism_tet_mesh, kuhn_cube_mesh,
                        pulse_slab_mesh, boundary_kinds)
 from workloads.problems import (PolynomialProblem, C1Advection1D, paper_pulse,
-                                SmoothPlusFront, slab_hill)
+                                SmoothPlusFront, slab_hill, MovingInternalLayer)
 
 HERE = os.path.dirname(__file__)
 
@@ -164,6 +164,22 @@ def test_pure_advection_transported_profile_rate():
         s, lam, U, _ = solve_all_at_once(v, c, prob, 1)
         errs.append(l2_error(s, U, prob.u))
     assert 1.6 < math.log2(errs[0] / errs[1]) < 2.6, errs
+
+
+def test_moving_internal_layer_converges():
+    # Section 4.2, uniform meshes: nu = 0, a = (x2, -x1), a discontinuous
+    # front entering through x1 = 0.  The L2 error of a discontinuous
+    # solution falls like h^(1/2); with the velocity or the inflow data
+    # wrong the discrete solution does not approach u (reversed rotation
+    # leaves the error at 0.50 on both meshes).
+    prob = MovingInternalLayer()
+    errs = []
+    for n in (4, 8):
+        v, c = kuhn_cube_mesh(n)
+        s, lam, U, _ = solve_all_at_once(v, c, prob, 1)
+        errs.append(l2_error(s, U, prob.u))
+    assert errs[1] < 0.16, errs
+    assert 0.25 < math.log2(errs[0] / errs[1]) < 1.0, errs
 
 
 def test_lemma31_acyclic_facet_graph_pure_advection():

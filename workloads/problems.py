@@ -282,3 +282,26 @@ def c5_sources(n_src=256, seed_centers=1, seed_target=0, seed_eval=2):
     c_target = np.random.default_rng(seed_target).standard_normal(n_src)
     c_eval = np.random.default_rng(seed_eval).standard_normal(n_src)
     return centers, c_target, c_eval
+
+
+class MovingInternalLayer(Problem):
+    """Moving internal layer (Section 4.2) on the space-time unit cube:
+    ``nu = 0``, ``f = 0``, ``a = (x2, -x1)``; ``u = 1`` where ``|x| < 1`` and
+    ``atan2(x2, x1) > pi/2 - t``, else 0.  The characteristics are circles
+    about the origin run clockwise, so the front enters through ``x1 = 0``
+    (value 1 for ``x2 < 1``) and sweeps the square; the initial data is 0.
+    The spatial boundary data is this exact solution."""
+
+    def __init__(self):
+        self.d = 2
+        self.nu = 0.0
+
+    def a(self, X):
+        xp = _ns(X)
+        return xp.stack([X[..., 2], -X[..., 1]], axis=-1)
+
+    def u(self, X):
+        xp = _ns(X)
+        t, x1, x2 = X[..., 0], X[..., 1], X[..., 2]
+        inside = (x1 * x1 + x2 * x2 < 1.0) & (xp.arctan2(x2, x1) > math.pi / 2 - t)
+        return xp.where(inside, xp.ones_like(t), xp.zeros_like(t))
