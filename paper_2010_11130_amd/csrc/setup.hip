@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "prof.h"
 #include "system.h"
@@ -65,8 +66,8 @@ __global__ void k_pmis_init(int64_t n, const int32_t* __restrict__ infl, int lev
   state[i] = infl[i] == 0 ? 2 : 0;
 }
 
-// 16 lanes per row for the PMIS phases and the one-point kernel.
-constexpr int PG = 16;
+// 8 lanes per row for the PMIS phases and the one-point kernel.
+constexpr int PG = 8;
 
 __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
@@ -126,6 +127,71 @@ __global__ __launch_bounds__(256) void k_pmis_fmark(int64_t n, const int64_t* __
   if (__syncthreads_or(undecided) && threadIdx.x == 0) *left = 1ull;
 }
 
+// Every PMIS round of a small level in one workgroup: keys, neighbour maxima
+// and states live in LDS (17 bytes per row), the strength graph is read from
+// global memory, phases are separated by barriers.  Same rounds as
+// k_pmis_nbmax / k_pmis_select / k_pmis_fmark, so the same splitting.
+// Dynamic LDS: n (8 + 8 + 1) bytes (8-byte aligned).  *err is set if the
+// rounds exceed n + 1 (cannot happen: the largest undecided key always
+// becomes C).
+constexpr int PMIS_WG_MAX = 8192;
+
+__global__ __launch_bounds__(1024) void k_pmis_wg(int n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const uint8_t* __restrict__ strong,
+                                                  const uint64_t* __restrict__ key_g, int8_t* __restrict__ state_g,
+                                                  unsigned long long* __restrict__ err) {
+  extern __shared__ __align__(16) unsigned long long pm[];
+  unsigned long long* key = pm;
+  unsigned long long* nb = pm + n;
+  int8_t* st = reinterpret_cast<int8_t*>(pm + 2 * n);
+  const int t = threadIdx.x, NT = blockDim.x;
+  for (int i = t; i < n; i += NT) {
+    key[i] = key_g[i];
+    nb[i] = 0ull;
+    st[i] = state_g[i];
+  }
+  __syncthreads();
+  for (int round = 0;; ++round) {
+    if (round > n + 1) {
+      if (t == 0) atomicOr(err, 1ull);
+      break;
+    }
+    // largest undecided key among the symmetrised strong neighbours
+    for (int i = t; i < n; i += NT) {
+      if (st[i] != 0) continue;
+      unsigned long long mx = 0ull;
+      const unsigned long long ki = key[i];
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (!strong[k]) continue;
+        const int32_t j = ci[k];
+        if (st[j] != 0) continue;
+        mx = mx > key[j] ? mx : key[j];
+        atomicMax(&nb[j], ki);
+      }
+      if (mx) atomicMax(&nb[i], mx);
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += NT) {
+      if (st[i] != 0) continue;
+      if (key[i] > nb[i]) st[i] = 1;
+      nb[i] = 0ull;
+    }
+    __syncthreads();
+    int undecided = 0;
+    for (int i = t; i < n; i += NT) {
+      if (st[i] != 0) continue;
+      int hit = 0;
+      for (int64_t k = rp[i]; k < rp[i + 1] && !hit; ++k)
+        if (strong[k] && st[ci[k]] == 1) hit = 1;
+      if (hit) st[i] = 2;
+      else undecided = 1;
+    }
+    if (!__syncthreads_or(undecided)) break;
+  }
+  for (int i = t; i < n; i += NT) state_g[i] = st[i];
+}
+
 __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* __restrict__ cf,
                            int32_t* __restrict__ isc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +206,7 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 // {i} and N_i); for F points their list and the F-row statistics (count,
 // entries).
 // imax[0] = max |N_i|, imax[1] = max candidates; fst[0..1] = F rows, entries.
-// 16 lanes per row; the strongest C neighbour is the first in row order
+// PG lanes per row; the strongest C neighbour is the first in row order
 // (smallest column) within relative 1e-12 of the maximum.
 __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
@@ -855,7 +921,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   ah_status rc = AH_OK;
 #define CK(x) do { rc = (x); if (rc < 0) { tmp.release(); delete h; return rc; } } while (0)
 #define CKH(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error("air_setup: %s", hipGetErrorString(e_)); tmp.release(); delete h; return AH_EHIP; } } while (0)
-  unsigned long long* d_ull = nullptr;   // [0..1] undecided counts (alternating rounds), [2] lAIR fallbacks
+  unsigned long long* d_ull = nullptr;   // [0..1] undecided counts (alternating rounds), [2] lAIR fallbacks,
+                                         // [3] single-workgroup PMIS round overflow
   int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error, [3] max A_c row
   unsigned long long* d_fst = nullptr;   // per level: F rows, F-row entries
   CK(ar.get(&d_ull, 4));
@@ -919,7 +986,19 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, l, key, state);
     CKH(hipGetLastError());
     CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
-    for (int round = 0;; ++round) {
+    if (n <= PMIS_WG_MAX) {
+      // small level: every round in one workgroup, no host checks
+      static std::once_flag once;
+      std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)k_pmis_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(PMIS_WG_MAX * 17 + 64));
+      });
+      const unsigned lds = (unsigned)(((n * 17 + 7) / 8) * 8);
+      hipLaunchKernelGGL(k_pmis_wg, dim3(1), dim3(1024), lds, st, (int)n, L.rowptr, L.col, strong, key, state,
+                         d_ull + 3);
+      CKH(hipGetLastError());
+    }
+    for (int round = 0; n > PMIS_WG_MAX; ++round) {
       if (round > 10000) { set_error("air_setup: PMIS did not terminate"); tmp.release(); delete h; return AH_EINVAL; }
       unsigned long long* left_d = d_ull + (round & 1);
       hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
@@ -1103,6 +1182,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CKH(hipMemcpyAsync(pin, d_ull + 2, sizeof(fb), hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(pin + 1, d_int + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     CKH(hipMemcpyAsync(pin + 2, d_fst, 65 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    CKH(hipMemcpyAsync(pin + 67, d_ull + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CKH(hipStreamSynchronize(st));
     std::memcpy(&fb, pin, sizeof(fb));
     std::memcpy(&gerr, pin + 1, sizeof(int));
@@ -1112,6 +1192,14 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     for (size_t l = 0; l + 1 < h->lev.size() && l < 32; ++l) {
       h->lev[l].nF = (int64_t)fst[2 * l];
       h->lev[l].nnzF = (int64_t)fst[2 * l + 1];
+    }
+    unsigned long long perr = 0;
+    std::memcpy(&perr, pin + 67, sizeof(perr));
+    if (perr) {
+      tmp.release();
+      set_error("air_setup: PMIS did not terminate");
+      delete h;
+      return AH_EINVAL;
     }
   }
   tmp.release();
