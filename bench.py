@@ -47,6 +47,8 @@ def parse():
                     help="skip the all-at-once solve of the stacked slabs")
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB march and the no-block-inverse ablation")
+    ap.add_argument("--solve-alone", type=int, default=0, metavar="N",
+                    help="only time N FGMRES solves of slab 0 with nothing else on the GPU")
     ap.add_argument("--no-internal-layer", action="store_true",
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--builders", type=int, default=1,
@@ -384,8 +386,54 @@ def all_at_once(args, U_march_last):
     ne_slab = 6 * args.n * args.n
     Ul = U[(args.slabs - 1) * ne_slab:]
     diff = (torch.linalg.norm(Ul - U_march_last) / torch.linalg.norm(U_march_last)).item()
+    # the same system with BiCGSTAB (the paper's Krylov method): no growing
+    # orthogonalisation basis
+    bres = None
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sb = System(m, args.p, args.nu, a, None, g)
+        hb = Hierarchy(sb)
+        xb_, infob = hb.solve(tol=args.tol, method=1)
+        sb.reconstruct(xb_)
+        torch.cuda.synchronize()
+        bres = (sb, infob, time.perf_counter() - t0)
+        del hb
+    sb, infob, tb_ = bres
     return {"value": s.n / t, "unit": "DOF/s", "ms": 1e3 * t, "free_dofs": s.n, "iters": info["iters"],
-            "levels": h.info["levels"], "last_slab_rel_diff_vs_march": diff}
+            "levels": h.info["levels"], "last_slab_rel_diff_vs_march": diff,
+            "bicgstab": {"value": sb.n / tb_, "ms": 1e3 * tb_, "steps": infob["iters"]}}
+
+
+def solve_alone(march, repeats, tol):
+    """Slab 0 of the march assembled and set up once, then ``repeats``
+    FGMRES solves with nothing else on the GPU: the solve's kernels without
+    the builder's competition (per-kernel HIP-event averages included)."""
+    import torch
+    from paper_2010_11130_amd import System, Hierarchy, lib
+    s = System(march.mesh, march.p, march.nu, march.a, None, march.g[0])
+    h = Hierarchy(s)
+    for _ in range(3):
+        h.solve(tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(repeats):
+        _, info = h.solve(tol=tol)
+        its += info["iters"]
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # a second pass with the per-kernel HIP events on
+    lib().ah_profile_reset()
+    lib().ah_profile_enable(1)
+    for _ in range(repeats):
+        h.solve(tol=tol)
+    torch.cuda.synchronize()
+    lib().ah_profile_enable(0)
+    prof = profile_totals(PROFILE_TAGS)
+    lib().ah_profile_reset()
+    return {"free_dofs": s.n, "repeats": repeats, "ms_per_solve": 1e3 * t / repeats,
+            "us_per_iteration": 1e6 * t / its, "iters": its // repeats, "kernels": prof}
 
 
 def internal_layer(n=48, p=1, tol=1e-8):
@@ -514,6 +562,9 @@ def main():
         sys.exit(1)
     march = March(args.n, args.slabs, args.p, args.nu)
     march.builders = args.builders
+    if args.solve_alone:
+        print(json.dumps({"solve_alone": solve_alone(march, args.solve_alone, args.tol)}))
+        return
     seq = not args.no_sequential
     t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol, seq)
     ndof_slab = last64[0].numel()
