@@ -16,7 +16,10 @@ the design notes):
     as the integer key ``influence_count * 2^44 + hash44(i, level)`` (a
     bijective 44-bit mix, so keys never tie); points nothing depends on
     strongly start as F; coarse index = rank of the C point;
-  * lAIR restriction row of C point i: ``N_i`` = strong F neighbours (sorted),
+  * lAIR restriction row of C point i: ``N_i`` = strong F neighbours (sorted)
+    for distance one; for distance two also the strong F neighbours of those
+    (paths through F points only); the strength tolerance of R may differ
+    from that of the coarsening (Section 4 uses 0.3 and 0.2);
     ``A[N_i,N_i]^T z = -A[i,N_i]^T`` by LU with partial pivoting,
     ``R[i,i] = 1``, ``R[i,N_i] = z``; injection when ``N_i`` is empty or a pivot
     satisfies ``|pivot| <= 1e-14 max |A[N_i,N_i]|``;
@@ -144,16 +147,38 @@ def batched_lu_solve(M, rhs):
     return x, bad
 
 
-def lair_R(A, strong, cf, cidx):
-    """Distance-one lAIR restriction: ``(R A)[i, j] = 0`` for ``j in N_i``."""
+def lair_neighbourhoods(A, strong, cf, distance=1):
+    """``N_i`` of every C point, sorted: the F points reachable from i by at
+    most ``distance`` strong connections that pass through F points only
+    (distance one: the strong F neighbours of i)."""
+    sF = strong & (cf[A.indices] == 0)
+    nb = {}
+    for i in np.nonzero(cf == 1)[0]:
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        front = set(A.indices[lo:hi][sF[lo:hi]].tolist())
+        N = set(front)
+        for _ in range(distance - 1):
+            nxt = set()
+            for j in front:
+                lj, hj = A.indptr[j], A.indptr[j + 1]
+                nxt.update(A.indices[lj:hj][sF[lj:hj]].tolist())
+            nxt -= N
+            N |= nxt
+            front = nxt
+        nb[int(i)] = np.array(sorted(N), dtype=np.int64)
+    return nb
+
+
+def lair_R(A, strong, cf, cidx, distance=1):
+    """lAIR restriction: ``(R A)[i, j] = 0`` for ``j in N_i``, with ``N_i``
+    from ``lair_neighbourhoods``."""
     n = A.shape[0]
     nc = int(cf.sum())
     Cpts = np.nonzero(cf == 1)[0]
-    r = _rows(A)
-    sF = strong & (cf[A.indices] == 0)
-    Ni = {}
+    nbh = lair_neighbourhoods(A, strong, cf, distance)
     cnt = np.zeros(n, dtype=np.int64)
-    np.add.at(cnt, r[sF], 1)
+    for i, N in nbh.items():
+        cnt[i] = len(N)
     rows, cols, vals = [], [], []
     nfall = 0
     for m in np.unique(cnt[Cpts]):
@@ -164,8 +189,7 @@ def lair_R(A, strong, cf, cidx):
             continue
         N = np.zeros((len(pts), m), dtype=np.int64)
         for t, i in enumerate(pts):
-            lo, hi = A.indptr[i], A.indptr[i + 1]
-            N[t] = A.indices[lo:hi][sF[lo:hi]]
+            N[t] = nbh[int(i)]
         rr = np.repeat(N, m, axis=1).ravel()
         cc = np.tile(N, (1, m)).ravel()
         Mloc = np.asarray(A[rr, cc]).reshape(len(pts), m, m)
@@ -191,8 +215,11 @@ class Hierarchy:
 
 
 def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
-          stall=0.9, max_dense=8192):
-    """Build the lAIR hierarchy on the scaled matrix (treated as scalar)."""
+          stall=0.9, max_dense=8192, theta_r=None, distance=1):
+    """Build the lAIR hierarchy on the scaled matrix (treated as scalar).
+    ``theta`` is the strength tolerance of the coarsening (and of P);
+    ``theta_r`` that of the restriction neighbourhoods (default: theta);
+    ``distance`` the neighbourhood distance of lAIR (1 or 2)."""
     H = Hierarchy()
     H.levels = []
     H.relax, H.omega = relax, omega
@@ -217,7 +244,8 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
         lev.cf = cf
         lev.strong = strong
         lev.P = one_point_P(A, strong, cf, cidx)
-        lev.R, nf = lair_R(A, strong, cf, cidx)
+        strong_r = strong if theta_r is None or theta_r == theta else strength(A, theta_r)
+        lev.R, nf = lair_R(A, strong_r, cf, cidx, distance)
         H.n_fallback += nf
         Ac = (lev.R @ A @ lev.P).tocsr()
         Ac.sort_indices()

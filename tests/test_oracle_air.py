@@ -141,6 +141,69 @@ def test_lair_rows_annihilate_f_neighbourhood(which, c1_sys, slab_sys):
     assert checked > 0
 
 
+def _bfs_f_neighbourhood(A, st, cf, i, distance):
+    """Points reachable from i through at most ``distance`` strong entries
+    whose column is an F point, by breadth-first search on the dense mask."""
+    D = A.toarray()
+    n = D.shape[0]
+    S = np.zeros((n, n), dtype=bool)
+    r = np.repeat(np.arange(n), np.diff(A.indptr))
+    S[r[st], A.indices[st]] = True
+    seen, front = set(), {i}
+    for _ in range(distance):
+        nxt = set()
+        for u in front:
+            nxt |= {int(j) for j in np.nonzero(S[u])[0] if cf[j] == 0}
+        nxt -= seen | {i}
+        seen |= nxt
+        front = nxt
+    return sorted(seen)
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_lair_distance_two(which, c1_sys, slab_sys):
+    # Section 4 names distance-one lAIR; distance two widens N_i to the
+    # F points two strong steps (through F points) from the C point.  Its
+    # neighbourhoods equal a breadth-first search on the strength mask, and
+    # every row still annihilates (R A)[i, N_i].
+    s = c1_sys if which == "c1" else slab_sys
+    A = s.Shat.tocsr()
+    st = air.strength(A, 0.25)
+    cf = air.pmis(A, st, 0)
+    cidx = np.cumsum(cf) - 1
+    nb1 = air.lair_neighbourhoods(A, st, cf, 1)
+    nb2 = air.lair_neighbourhoods(A, st, cf, 2)
+    Cpts = np.nonzero(cf == 1)[0]
+    rng = np.random.default_rng(5)
+    for i in rng.choice(Cpts, size=min(40, len(Cpts)), replace=False):
+        assert list(nb2[int(i)]) == _bfs_f_neighbourhood(A, st, cf, int(i), 2)
+        assert list(nb1[int(i)]) == _bfs_f_neighbourhood(A, st, cf, int(i), 1)
+        assert set(nb1[int(i)]) <= set(nb2[int(i)])
+    assert sum(len(v) for v in nb2.values()) > sum(len(v) for v in nb1.values())
+    R, nfall = air.lair_R(A, st, cf, cidx, distance=2)
+    RA = (R @ A).tocsr()
+    checked = 0
+    for ci, i in enumerate(Cpts):
+        N = nb2[int(i)]
+        if len(N) == 0 or R[ci].nnz == 1:
+            continue
+        rownorm = np.abs(A[i].data).max()
+        assert np.all(np.abs(RA[ci, N].toarray()) <= 1e-11 * max(rownorm, 1.0))
+        checked += 1
+    assert checked > 0
+
+
+def test_separate_restriction_threshold():
+    # theta_R != theta_C: the splitting follows theta_C, the neighbourhoods
+    # theta_R (a larger tolerance gives fewer strong F neighbours)
+    v, c = kuhn_cube_mesh(4)
+    s = setup_problem(v, c, SmoothPlusFront(1e-3), 1)
+    H1 = air.setup(s.Shat, theta=0.2)
+    H2 = air.setup(s.Shat, theta=0.2, theta_r=0.5)
+    assert np.array_equal(H1.levels[0].cf, H2.levels[0].cf)
+    assert H2.levels[0].R.nnz < H1.levels[0].R.nnz
+
+
 def test_batched_lu_matches_library_solve():
     rng = np.random.default_rng(3)
     M = rng.standard_normal((50, 7, 7))
