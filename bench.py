@@ -49,6 +49,8 @@ def parse():
                     help="skip the BiCGSTAB march and the no-block-inverse ablation")
     ap.add_argument("--solve-alone", type=int, default=0, metavar="N",
                     help="only time N FGMRES solves of slab 0 with nothing else on the GPU")
+    ap.add_argument("--no-lair-d2", action="store_true",
+                    help="skip the march with distance-two lAIR neighbourhoods")
     ap.add_argument("--no-internal-layer", action="store_true",
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--builders", type=int, default=1,
@@ -279,7 +281,7 @@ class March:
         self.builders = 1
         torch.cuda.synchronize()
 
-    def step(self, precision, tol, pipelined=True, stages=None, method=0, iters=None):
+    def step(self, precision, tol, pipelined=True, stages=None, method=0, iters=None, air_extra=None):
         """One pass of the march over all slabs: per slab assembly, lAIR
         setup, the Krylov solve to ``tol`` (FGMRES, or BiCGSTAB with
         method=1) and reconstruction of u_h."""
@@ -291,7 +293,9 @@ class March:
             if iters is not None:
                 iters.append(info["iters"])
 
-        m = SlabMarch(self.mesh, self.p, self.nu, self.a, air_kw={"fp32_cycle": 1 if precision else 0},
+        air_kw = {"fp32_cycle": 1 if precision else 0}
+        air_kw.update(air_extra or {})
+        m = SlabMarch(self.mesh, self.p, self.nu, self.a, air_kw=air_kw,
                       solve_kw={"tol": tol, "precision": precision, "method": method}, builders=self.builders)
         s, x, info = m.run([self.g[k] for k in range(self.slabs)], pipelined=pipelined, on_slab=keep_u,
                            stages=stages)
@@ -628,6 +632,21 @@ def main():
         x0, i0 = Hierarchy(s0).solve(tol=args.tol, maxit=100)
         out["no_block_inverse_slab0"] = {"converged": i0["converged"], "iters": i0["iters"],
                                          "relres": i0["true_relres"]}
+    # distance-two lAIR neighbourhoods (a NEXT option of the paper's
+    # Section 4 settings): same march, FGMRES
+    if not args.no_lair_d2:
+        d2 = {"lair_distance": 2}
+        march.step(0, args.tol, air_extra=d2)
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            its.clear()
+            march.step(0, args.tol, iters=its, air_extra=d2)
+        torch.cuda.synchronize()
+        td = (time.perf_counter() - t0) / args.steps
+        out["lair_distance2"] = {"value": total / td, "ms_per_step": 1e3 * td,
+                                 "iters_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
     # all-at-once: the 64 slabs as one space-time system on one GPU
     if not args.no_all_at_once:
         out["all_at_once"] = all_at_once(args, last64[1])

@@ -172,7 +172,12 @@ ah_status hdg_inflow_from_trace(const ah_system* prev, const double* lam_prev,
  * solves A[N_i,N_i]^T z = -A[i,N_i]^T; A_c = R A P; coarsest level inverted
  * densely.  Stops at n <= max_coarse, at max_levels, or when the coarse grid
  * is empty or larger than stall * n.  fp32_cycle: also keep FP32 copies of the
- * cycle operators; adjoint: also build the transposed operators. */
+ * cycle operators; adjoint: also build the transposed operators.
+ * lair_distance 2 widens N_i to the strong F neighbours of i's strong F
+ * neighbours (paths through F points only; at most 64 points, else
+ * AH_EUNSUPPORTED); theta_r > 0 gives the restriction neighbourhoods their
+ * own strength threshold (Section 4 uses 0.3 for R and 0.2 for the
+ * coarsening), theta stays that of the coarsening and of P. */
 typedef struct {
   double theta;        /* strength threshold, default 0.25 */
   int max_coarse;      /* default 64 */
@@ -182,6 +187,8 @@ typedef struct {
   double stall;        /* default 0.9 */
   int fp32_cycle;
   int adjoint;
+  int lair_distance;   /* 1 (default) or 2 */
+  double theta_r;      /* restriction strength threshold; <= 0: theta (default) */
 } ah_air_params;
 
 typedef struct {

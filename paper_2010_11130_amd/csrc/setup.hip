@@ -210,7 +210,8 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 // (smallest column) within relative 1e-12 of the maximum.
 __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
-                                                  const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
+                                                  const uint8_t* __restrict__ strong,
+                                                  const uint8_t* __restrict__ strong_r, const int8_t* __restrict__ cf,
                                                   const int64_t* __restrict__ cidx, int32_t* __restrict__ pcol,
                                                   int32_t* __restrict__ rcnt, int32_t* __restrict__ clist,
                                                   int32_t* __restrict__ flist, int* __restrict__ imax,
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
       int m = 0;
       int64_t cand = 0;
       for (int64_t k = k0 + g; k < k1; k += PG)
-        if (strong[k] && !cf[ci[k]]) {
+        if (strong_r[k] && !cf[ci[k]]) {
           ++m;
           cand += rp[ci[k] + 1] - rp[ci[k]];
         }
@@ -308,32 +309,148 @@ __device__ inline double wave_max(double v) {
 // lAIR row of one C point per wave: N_i = strong F neighbours (sorted),
 // T = A[N_i,N_i]^T, solve T z = -A[i,N_i]^T by LU with partial pivoting;
 // injection (z = 0, counted) if N_i is empty or a pivot is <= 1e-14 max|T|.
-template <int MAXM>
+// Distance-two lAIR neighbourhood of C point i by one 64-lane wave: the
+// strong F neighbours of i, then the strong F neighbours of those (paths
+// through F points only), gathered into cand[0..CAP) (LDS), sorted and made
+// unique.  Returns the size m (the sorted set is cand[0..m)); returns -1 if
+// more than CAP candidates arise.  *s_cnt is an LDS counter.
+constexpr int NB2_CAP = 1024;
+
+__device__ int nbhd2(int64_t i, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                     const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf, int32_t* cand, int* s_cnt) {
+  const int lane = threadIdx.x;
+  if (lane == 0) *s_cnt = 0;
+  __syncthreads();
+  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64)
+    if (strong[k] && !cf[ci[k]]) {
+      const int pos = atomicAdd(s_cnt, 1);
+      if (pos < NB2_CAP) cand[pos] = ci[k];
+    }
+  __syncthreads();
+  const int m1 = min(*s_cnt, NB2_CAP);
+  for (int t = 0; t < m1; ++t) {
+    const int32_t j = cand[t];
+    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
+      const int32_t c = ci[k];
+      if (strong[k] && !cf[c] && c != (int32_t)i) {
+        const int pos = atomicAdd(s_cnt, 1);
+        if (pos < NB2_CAP) cand[pos] = c;
+      }
+    }
+  }
+  __syncthreads();
+  const int tot = *s_cnt;
+  if (tot > NB2_CAP) return -1;
+  int S = 1;
+  while (S < tot) S <<= 1;
+  for (int k = tot + lane; k < S; k += 64) cand[k] = 0x7fffffff;
+  __syncthreads();
+  for (int kk = 2; kk <= S; kk <<= 1)
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int x = lane; x < S; x += 64) {
+        const int y = x ^ jj;
+        if (y > x) {
+          const bool up = (x & kk) == 0;
+          const int32_t a = cand[x], b = cand[y];
+          if ((a > b) == up) { cand[x] = b; cand[y] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  // unique, in place: a chunk compares each entry with its predecessor in
+  // the sorted order (the previous chunk's last entry is carried in a
+  // register, since that chunk's writes may already have replaced it)
+  int base = 0;
+  int32_t carry = 0;
+  for (int k0 = 0; k0 < tot; k0 += 64) {
+    const int k = k0 + lane;
+    const int32_t v = k < tot ? cand[k] : 0x7fffffff;
+    int32_t pv = __shfl_up(v, 1, 64);
+    if (lane == 0) pv = carry;
+    const bool keep = k < tot && (k == 0 || v != pv);
+    carry = __shfl(v, 63, 64);
+    const unsigned long long mask = __ballot(keep);
+    __syncthreads();
+    if (keep) cand[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+    base += __popcll(mask);
+    __syncthreads();
+  }
+  return base;
+}
+
+// Distance-two lAIR: per C point the R row length 1 + |N_i| (rcnt), |N_i|
+// (mcnt, -1 if the gather overflowed) and the R A P candidate bound (row
+// lengths of A over {i} and N_i, ccnt).
+__global__ __launch_bounds__(64) void k_lair_count2(int64_t nc, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                    const int8_t* __restrict__ cf, const int32_t* __restrict__ clist,
+                                                    int32_t* __restrict__ rcnt, int32_t* __restrict__ mcnt,
+                                                    int32_t* __restrict__ ccnt) {
+  __shared__ int32_t cand[NB2_CAP];
+  __shared__ int s_cnt;
+  const int64_t ic = blockIdx.x;
+  const int64_t i = clist[ic];
+  const int m = nbhd2(i, rp, ci, strong, cf, cand, &s_cnt);
+  int64_t c = 0;
+  if (m > 0)
+    for (int t = threadIdx.x; t < m; t += 64) c += rp[cand[t] + 1] - rp[cand[t]];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (threadIdx.x == 0) {
+    c += rp[i + 1] - rp[i];
+    rcnt[ic] = 1 + (m > 0 ? m : 0);
+    mcnt[ic] = m;
+    ccnt[ic] = c > 0x3fffffff ? 0x3fffffff : (int32_t)c;
+  }
+}
+
+template <int MAXM, bool D2>
 __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const double* __restrict__ v, const uint8_t* __restrict__ strong,
                                              const int8_t* __restrict__ cf, const int32_t* __restrict__ clist,
                                              const int64_t* __restrict__ Rptr, int32_t* __restrict__ Rcol,
                                              double* __restrict__ Rval, unsigned long long* __restrict__ nfall) {
-  __shared__ int32_t N[MAXM];
+  __shared__ int32_t Nbuf[D2 ? NB2_CAP : MAXM];
   __shared__ double T[MAXM * MAXM];
   __shared__ double z[MAXM];
   __shared__ int s_m;
+  int32_t* N = Nbuf;
   const int64_t ic = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t i = clist[ic];
   if (lane == 0) s_m = 0;
   __syncthreads();
-  // gather N_i and the right-hand side in row order (columns are sorted)
-  int base = 0;
-  for (int64_t k0 = rp[i]; k0 < rp[i + 1]; k0 += 64) {
-    int64_t k = k0 + lane;
-    bool f = k < rp[i + 1] && strong[k] && !cf[ci[k]];
-    unsigned long long mask = __ballot(f);
-    int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-    if (f && pos < MAXM) { N[pos] = ci[k]; z[pos] = -v[k]; }
-    base += __popcll(mask);
+  int m;
+  if (D2) {
+    // distance two: the sorted neighbourhood, then the right-hand side
+    // -A[i, N_i] (zero where row i has no entry)
+    m = nbhd2(i, rp, ci, strong, cf, Nbuf, &s_m);
+    if (m < 0) m = MAXM + 1;
+    for (int t = lane; t < MAXM; t += 64) z[t] = 0.0;
+    __syncthreads();
+    if (m <= MAXM)
+      for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) {
+        const int32_t col = ci[k];
+        int lo = 0, hi = m - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          if (N[mid] == col) { z[mid] = -v[k]; break; }
+          if (N[mid] < col) lo = mid + 1; else hi = mid - 1;
+        }
+      }
+    __syncthreads();
+  } else {
+    // gather N_i and the right-hand side in row order (columns are sorted)
+    int base = 0;
+    for (int64_t k0 = rp[i]; k0 < rp[i + 1]; k0 += 64) {
+      int64_t k = k0 + lane;
+      bool f = k < rp[i + 1] && strong[k] && !cf[ci[k]];
+      unsigned long long mask = __ballot(f);
+      int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+      if (f && pos < MAXM) { N[pos] = ci[k]; z[pos] = -v[k]; }
+      base += __popcll(mask);
+    }
+    m = base;
   }
-  const int m = base;
   const int64_t out = Rptr[ic];
   if (m == 0 || m > MAXM) {
     // m > MAXM cannot occur: the host picks MAXM >= max |N_i|
@@ -853,6 +970,28 @@ __global__ __launch_bounds__(256) void k_max_i32(int64_t n, const int32_t* __res
   }
 }
 
+template <int M, bool D2>
+static void lair_launch(int64_t nc, const AhLevel& L, const uint8_t* strong, const int32_t* clist,
+                        unsigned long long* nfall, hipStream_t st) {
+  hipLaunchKernelGGL((k_lair<M, D2>), dim3((unsigned)nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf,
+                     clist, L.Rptr, L.Rcol, L.Rval, nfall);
+}
+
+// lAIR restriction rows with local systems of capacity cap (8, 16, 32, 64)
+// and distance-one or distance-two neighbourhoods.
+static ah_status lair_dispatch(int cap, bool d2, int64_t nc, const AhLevel& L, const uint8_t* strong,
+                               const int32_t* clist, unsigned long long* nfall, hipStream_t st) {
+  if (nc == 0) return AH_OK;
+  switch (cap) {
+    case 8: d2 ? lair_launch<8, true>(nc, L, strong, clist, nfall, st) : lair_launch<8, false>(nc, L, strong, clist, nfall, st); break;
+    case 16: d2 ? lair_launch<16, true>(nc, L, strong, clist, nfall, st) : lair_launch<16, false>(nc, L, strong, clist, nfall, st); break;
+    case 32: d2 ? lair_launch<32, true>(nc, L, strong, clist, nfall, st) : lair_launch<32, false>(nc, L, strong, clist, nfall, st); break;
+    default: d2 ? lair_launch<64, true>(nc, L, strong, clist, nfall, st) : lair_launch<64, false>(nc, L, strong, clist, nfall, st); break;
+  }
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
 template <int HS>
 static ah_status rap_launch(int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
                             double* cval, bool numeric, hipStream_t st) {
@@ -897,6 +1036,8 @@ extern "C" void ah_air_defaults(ah_air_params* p) {
   p->stall = 0.9;
   p->fp32_cycle = 0;
   p->adjoint = 0;
+  p->lair_distance = 1;
+  p->theta_r = 0.0;
 }
 
 extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, void* stream, ah_hier** out,
@@ -905,7 +1046,9 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   *out = nullptr;
   ah_air_params prm;
   if (prm_in) prm = *prm_in; else ah_air_defaults(&prm);
-  if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1) {
+  if (prm.lair_distance == 0) prm.lair_distance = 1;
+  if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1 ||
+      (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0)) {
     set_error("air_setup: invalid parameters");
     return AH_EINVAL;
   }
@@ -1033,9 +1176,36 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(ar.get(&L.flist, n - nc));
     L.clist = clist;
     CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
-    hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, L.cf, cidx, L.pcol,
-                       rcnt, clist, L.flist, d_int, d_fst + 2 * l);
+    // strength of the restriction neighbourhoods (theta_r; the same mask
+    // when it equals theta)
+    uint8_t* strong_r = strong;
+    if (prm.theta_r > 0.0 && prm.theta_r != prm.theta) {
+      int32_t* infl_r = nullptr;
+      CK(tmp.get(&strong_r, L.nnz));
+      CK(tmp.get(&infl_r, n));
+      CKH(hipMemsetAsync(infl_r, 0, n * sizeof(int32_t), st));
+      hipLaunchKernelGGL(k_strength, g1(n * SG), dim3(256), 0, st, n, L.rowptr, L.col, L.val, prm.theta_r, strong_r,
+                         infl_r);
+      CKH(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, strong_r, L.cf,
+                       cidx, L.pcol, rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
+    const bool d2 = prm.lair_distance == 2;
+    if (d2) {
+      // distance-two neighbourhoods: R row lengths, |N_i| and the R A P bound
+      int32_t *mcnt = nullptr, *c2 = nullptr;
+      CK(tmp.get(&mcnt, nc));
+      CK(tmp.get(&c2, nc));
+      hipLaunchKernelGGL(k_lair_count2, dim3((unsigned)nc), dim3(64), 0, st, nc, L.rowptr, L.col, strong_r, L.cf,
+                         clist, rcnt, mcnt, c2);
+      CKH(hipGetLastError());
+      CKH(hipMemsetAsync(d_int, 0, 2 * sizeof(int), st));
+      const dim3 gm((unsigned)std::min<int64_t>(cdiv(nc, 256), 256));
+      hipLaunchKernelGGL(k_max_i32, gm, dim3(256), 0, st, nc, mcnt, d_int);
+      hipLaunchKernelGGL(k_max_i32, gm, dim3(256), 0, st, nc, c2, d_int + 1);
+      CKH(hipGetLastError());
+    }
     if (L.ob) {
       hipLaunchKernelGGL(k_list_vals, grows(n - nc), dim3(256), 0, st, n - nc, L.flist, L.optr, L.ob, d_fst + 64);
       CKH(hipGetLastError());
@@ -1057,22 +1227,12 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     const int maxm = hmax[0];
     // the smallest local-system capacity that holds every neighbourhood
     // (LDS per workgroup, hence occupancy, grows with its square)
-    if (maxm <= 8)
-      hipLaunchKernelGGL(k_lair<8>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
-    else if (maxm <= 16)
-      hipLaunchKernelGGL(k_lair<16>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
-    else if (maxm <= 32)
-      hipLaunchKernelGGL(k_lair<32>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
-    else if (maxm <= 64)
-      hipLaunchKernelGGL(k_lair<64>, dim3(nc), dim3(64), 0, st, nc, L.rowptr, L.col, L.val, strong, L.cf, clist,
-                         L.Rptr, L.Rcol, L.Rval, d_ull + 2);
-    else {
+    if (maxm > 64) {
       set_error("air_setup: lAIR neighbourhood of %d points exceeds 64", maxm);
       tmp.release(); delete h; return AH_EUNSUPPORTED;
     }
+    const int cap = maxm <= 8 ? 8 : maxm <= 16 ? 16 : maxm <= 32 ? 32 : 64;
+    CK(lair_dispatch(cap, d2, nc, L, strong_r, clist, d_ull + 2, st));
     CKH(hipGetLastError());
     // R A P
     const int maxcand = hmax[1];

@@ -442,3 +442,45 @@ def test_all_at_once_equals_slab_march_pure_advection():
     march.run(gs, pipelined=False, on_slab=lambda k, s, h, xx, inf: out.__setitem__("U", s.reconstruct(xx)))
     Ul = out["U"].cpu().numpy()
     assert np.linalg.norm(U - Ul) <= 1e-10 * np.linalg.norm(Ul)
+
+
+LAIR_VARIANTS = {"d2": dict(lair_distance=2), "theta_r": dict(theta=0.2, theta_r=0.3),
+                 "d2_theta_r": dict(lair_distance=2, theta=0.2, theta_r=0.3)}
+
+
+@pytest.mark.parametrize("variant", sorted(LAIR_VARIANTS))
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5", "layer"])
+def test_lair_variant_parity(built, name, variant):
+    """Distance-two neighbourhoods and a separate restriction threshold:
+    C/F splitting and P bit for bit, R and the coarse operators to 1e-10,
+    the solution to 1e-10 and the iteration count within one."""
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, variant, flush=True)
+    g, o, _ = built(name)
+    kw = LAIR_VARIANTS[variant]
+    okw = {"theta": kw.get("theta", 0.25), "theta_r": kw.get("theta_r"), "distance": kw.get("lair_distance", 1)}
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, **kw)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, **okw)
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    for l in range(OH.nlev - 1):
+        lv = H.level(l)
+        ol = OH.levels[l]
+        assert np.array_equal(lv["cf"].cpu().numpy(), ol.cf), l
+        R = to_scipy(lv["Rptr"], lv["Rcol"], lv["Rval"], ol.R.shape[0], ol.R.shape[1])
+        assert rel_sparse_diff(R, ol.R) < 1e-10, l
+        A = to_scipy(H.level(l + 1)["rowptr"], H.level(l + 1)["col"], H.level(l + 1)["val"], H.info["n"][l + 1])
+        assert rel_sparse_diff(A, OH.levels[l + 1].A) < 1e-10, l
+    x, info = H.solve(tol=1e-12)
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    _, i8 = H.solve(tol=1e-8)
+    _, io8 = air_fgmres_solve(o, tol=1e-8, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+def test_lair_distance_bad_parameter(built):
+    from paper_2010_11130_amd import Hierarchy, AirHdgError
+    g, _, _ = built("c1")
+    with pytest.raises(AirHdgError):
+        Hierarchy(g, lair_distance=3)
