@@ -187,18 +187,6 @@ __device__ inline T row_dot(const int64_t* rp, const int32_t* ci, const T* av, c
   return s;
 }
 
-// Forward coarse end of the cycle from an LDS image: every array of levels
-// l0 .. nlev-1 and the coarsest inverse are copied into LDS once, then the
-// restriction, coarsest solve, interpolation and F, F, C sweeps of all these
-// levels run out of LDS with workgroup barriers between the phases.  The
-// result of level l0 is written to out.
-template <class T>
-__device__ inline T row_dot_s(const int32_t* rp, const int32_t* ci, const T* av, const T* x, int i) {
-  T s = 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += av[k] * x[ci[k]];
-  return s;
-}
-
 // Global -> LDS staging for the tail kernel: n elements, eight independent
 // loads in flight per thread (the image is re-staged on every cycle, so the
 // copy must not be one dependent load per iteration).
