@@ -1012,6 +1012,7 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
     case 64: return rap_launch<64>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 128: return rap_launch<128>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 256: return rap_launch<256>(nc, L, cnt, cptr, ccol, cval, numeric, st);
+    case 512: return rap_launch<512>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 1024: return rap_launch<1024>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 2048: return rap_launch<2048>(nc, L, cnt, cptr, ccol, cval, numeric, st);
     case 4096: return rap_launch<4096>(nc, L, cnt, cptr, ccol, cval, numeric, st);
