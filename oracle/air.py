@@ -27,7 +27,11 @@ the design notes):
     strong C neighbour (ties within relative 1e-12 -> smallest index), or
     a zero row when it has none;
   * relaxation: Jacobi (omega = 1) sweeps on F, F, C ("FFC") or one F sweep
-    ("F") instead of Gauss-Seidel; no filtering of R, P or R A P;
+    ("F") instead of Gauss-Seidel; or, on level 0 only, forward Gauss-Seidel
+    in the flow order of Lemma 3.1 (Section 3.3): over all points
+    ("ordered", the exact solve of the advective part) or on F points then
+    on all points ("ordered_fa", the schedule of Section 4); coarser levels
+    keep F, F, C Jacobi; no filtering of R, P or R A P;
   * hierarchy stops when the coarse grid has at most ``max_coarse`` points,
     when ``max_levels`` is reached, or when coarsening stalls
     (``n_c == 0`` or ``n_c > 0.9 n``); coarsest level: dense LU.
@@ -206,6 +210,119 @@ def lair_R(A, strong, cf, cidx, distance=1):
     return R, nfall
 
 
+def block_weights(A, b):
+    """Off-diagonal blocks of the level-0 matrix (facet blocks of size ``b``):
+    sorted keys ``I * nb + J`` (``I != J``) of the blocks holding a stored
+    entry, and ``w_IJ = max |a_ij|`` over each block."""
+    C = A.tocoo()
+    nb = A.shape[0] // b
+    I = C.row // b
+    J = C.col // b
+    off = I != J
+    key = I[off].astype(np.int64) * nb + J[off]
+    uk, inv = np.unique(key, return_inverse=True)
+    w = np.zeros(len(uk))
+    np.maximum.at(w, inv, np.abs(C.data[off]))
+    return uk, w
+
+
+def flow_levels(A, b):
+    """Flow order of the facet blocks (Lemma 3.1, Section 3.3).
+
+    Every coupled pair of blocks ``I != J`` (``w_IJ > 0`` or ``w_JI > 0``) is
+    oriented along the dominant coupling: ``J`` precedes ``I`` when
+    ``w_IJ > w_JI``, or when ``w_IJ == w_JI`` and ``J < I``.  For pure
+    advection on an acyclic element graph the block below the diagonal of
+    the upwind flux is the only coupling of a pair, so this is the upwind
+    order of the lemma.  Levels by Kahn rounds: round k takes every block
+    whose predecessors are all placed; when blocks remain but none is ready
+    (a cycle), the remaining block with the fewest unplaced predecessors
+    (then the smallest index) forms the round alone.
+    Returns ``(level[nb], rounds, cycle_breaks)``."""
+    nb = A.shape[0] // b
+    uk, w = block_weights(A, b)
+    I, J = uk // nb, uk % nb
+    rk = J * nb + I
+    pos = np.searchsorted(uk, rk)
+    pos = np.minimum(pos, max(len(uk) - 1, 0))
+    w_rev = np.where((len(uk) > 0) & (uk[pos] == rk), w[pos], 0.0) if len(uk) else w
+    coupled = (w > 0) | (w_rev > 0)
+    pred = coupled & ((w > w_rev) | ((w == w_rev) & (J < I)))
+    # successor lists: edge J -> I for every predecessor J of I
+    succ = sp.csr_matrix((np.ones(int(pred.sum())), (J[pred], I[pred])), shape=(nb, nb))
+    indeg = np.bincount(I[pred], minlength=nb).astype(np.int64)
+    level = np.full(nb, -1, dtype=np.int64)
+    done = np.zeros(nb, dtype=bool)
+    frontier = np.nonzero(indeg == 0)[0]
+    k = 0
+    breaks = 0
+    placed = 0
+    while placed < nb:
+        if len(frontier) == 0:
+            cand = np.nonzero(~done)[0]
+            frontier = cand[[int(np.argmin(indeg[cand]))]]
+            breaks += 1
+        level[frontier] = k
+        done[frontier] = True
+        placed += len(frontier)
+        dec = np.asarray(succ[frontier].sum(axis=0)).ravel().astype(np.int64)
+        indeg -= dec
+        frontier = np.nonzero((dec > 0) & (indeg == 0) & ~done)[0]
+        k += 1
+    return level, k, breaks
+
+
+class OrderedSweep:
+    """Forward Gauss-Seidel on the rows ``X`` in the flow order: the
+    splitting matrix ``M`` holds the diagonal and every entry ``(i, j)``,
+    ``i, j in X``, whose block ``J`` lies on an earlier level than block
+    ``I``.  One sweep is ``x_X <- x_X + M^-1 (b - A x)_X``; the transposed
+    sweep is ``y_X <- y_X + M^-T (g - A^T y)_X``."""
+
+    def __init__(self, A, b, blev, X):
+        self.X = X
+        rl = blev[X // b]
+        order = np.lexsort((X, rl))
+        self.perm = order                      # position in X of the k-th row of the order
+        AX = A[X][:, X].tocoo()
+        li = rl[AX.row]
+        lj = rl[AX.col]
+        keep = (AX.row == AX.col) | (li > lj)
+        same = (AX.row != AX.col) & (li == lj) & (AX.data != 0)
+        if np.any(same & (X[AX.row] // b == X[AX.col] // b)):
+            raise ValueError("ordered relaxation needs identity diagonal blocks (the scaled system)")
+        if np.any(same):
+            raise ValueError("blocks on one level are coupled")
+        inv = np.empty_like(order)
+        inv[order] = np.arange(len(order))
+        M = sp.csr_matrix((AX.data[keep], (inv[AX.row[keep]], inv[AX.col[keep]])), shape=(len(X), len(X)))
+        M.sort_indices()
+        self.M = M
+        self.MT = M.T.tocsr()
+
+    def _solve(self, r, transpose):
+        from scipy.sparse.linalg import spsolve_triangular
+        if len(r) == 0:
+            return r
+        rp = r[self.perm]
+        y = spsolve_triangular(self.MT if transpose else self.M, rp, lower=not transpose)
+        out = np.empty_like(y)
+        out[self.perm] = y
+        return out
+
+    def apply(self, A, b, x):
+        r = b - A @ x
+        x = x.copy()
+        x[self.X] += self._solve(r[self.X], False)
+        return x
+
+    def apply_T(self, AT, g, y):
+        r = g - AT @ y
+        y = y.copy()
+        y[self.X] += self._solve(r[self.X], True)
+        return y
+
+
 class Level:
     pass
 
@@ -215,11 +332,15 @@ class Hierarchy:
 
 
 def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
-          stall=0.9, max_dense=8192, theta_r=None, distance=1):
+          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1):
     """Build the lAIR hierarchy on the scaled matrix (treated as scalar).
     ``theta`` is the strength tolerance of the coarsening (and of P);
     ``theta_r`` that of the restriction neighbourhoods (default: theta);
-    ``distance`` the neighbourhood distance of lAIR (1 or 2)."""
+    ``distance`` the neighbourhood distance of lAIR (1 or 2); ``relax`` one
+    of "FFC", "F", "ordered", "ordered_fa"; ``block`` the facet block size
+    of level 0 (the unit of the flow order)."""
+    if relax not in ("FFC", "F", "ordered", "ordered_fa"):
+        raise ValueError("unknown relaxation %r" % (relax,))
     H = Hierarchy()
     H.levels = []
     H.relax, H.omega = relax, omega
@@ -247,6 +368,10 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
         strong_r = strong if theta_r is None or theta_r == theta else strength(A, theta_r)
         lev.R, nf = lair_R(A, strong_r, cf, cidx, distance)
         H.n_fallback += nf
+        if l == 0 and relax in ("ordered", "ordered_fa"):
+            lev.blev, lev.rounds, lev.breaks = flow_levels(A, block)
+            lev.gs_all = OrderedSweep(A, block, lev.blev, np.arange(n))
+            lev.gs_F = OrderedSweep(A, block, lev.blev, np.nonzero(cf == 0)[0])
         Ac = (lev.R @ A @ lev.P).tocsr()
         Ac.sort_indices()
         A = Ac
@@ -262,8 +387,14 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
 def _sweep_sets(H, lev, transpose):
     F = np.nonzero(lev.cf == 0)[0]
     C = np.nonzero(lev.cf == 1)[0]
-    sets = [F, F, C] if H.relax == "FFC" else [F]
+    sets = [F] if H.relax == "F" else [F, F, C]
     return sets[::-1] if transpose else sets
+
+
+def _ordered_sweeps(H, lev, transpose):
+    """Level-0 sweeps of the ordered relaxations, in application order."""
+    sw = [lev.gs_F, lev.gs_all] if H.relax == "ordered_fa" else [lev.gs_all]
+    return sw[::-1] if transpose else sw
 
 
 def _coarse_solve(last, b, trans=0):
@@ -280,6 +411,10 @@ def vcycle(H, b, l=0):
         return _coarse_solve(lev, b)
     ec = vcycle(H, lev.R @ b, l + 1)
     x = lev.P @ ec
+    if hasattr(lev, "gs_all"):
+        for sw in _ordered_sweeps(H, lev, False):
+            x = sw.apply(lev.A, b, x)
+        return x
     d = lev.diag
     for X in _sweep_sets(H, lev, False):
         X = X[np.abs(d[X]) >= 1e-30]
@@ -297,10 +432,14 @@ def vcycle_T(H, g, l=0):
     y = np.zeros_like(g)
     d = lev.diag
     AT = lev.A.T.tocsr()
-    for X in _sweep_sets(H, lev, True):
-        X = X[np.abs(d[X]) >= 1e-30]
-        r = g - AT @ y
-        y[X] += H.omega * r[X] / d[X]
+    if hasattr(lev, "gs_all"):
+        for sw in _ordered_sweeps(H, lev, True):
+            y = sw.apply_T(AT, g, y)
+    else:
+        for X in _sweep_sets(H, lev, True):
+            X = X[np.abs(d[X]) >= 1e-30]
+            r = g - AT @ y
+            y[X] += H.omega * r[X] / d[X]
     y = y + lev.R.T @ vcycle_T(H, lev.P.T @ (g - AT @ y), l + 1)
     return y
 
