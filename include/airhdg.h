@@ -182,7 +182,10 @@ typedef struct {
   double theta;        /* strength threshold, default 0.25 */
   int max_coarse;      /* default 64 */
   int max_levels;      /* default 25 */
-  int relax;           /* 0: F,F,C Jacobi sweeps; 1: one F sweep */
+  int relax;           /* 0: F,F,C Jacobi sweeps; 1: one F sweep; 2: ordered
+                          Gauss-Seidel on level 0 over all points; 3: ordered
+                          Gauss-Seidel on level 0, F points then all points
+                          (2 and 3: coarser levels F,F,C Jacobi) */
   double omega;        /* Jacobi weight, default 1 */
   double stall;        /* default 0.9 */
   int fp32_cycle;
@@ -215,6 +218,23 @@ ah_status ah_hier_level_sizes(const ah_hier* h, int l, int64_t* n, int64_t* nnz,
 ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_t* col,
                                double* val, int8_t* cf, int32_t* pcol, int64_t* r_row_ptr,
                                int32_t* r_col, double* r_val, void* stream);
+
+/* Flow order of the ordered relaxations (relax 2 or 3; Lemma 3.1, Section
+ * 3.3).  The level-0 facet blocks (block size b, nblocks = n_free / b) are
+ * ordered along the dominant coupling of every coupled pair: with
+ * w_IJ = max |S_hat entries of off-diagonal block (I, J)|, J precedes I when
+ * w_IJ > w_JI, or when they are equal and J < I.  Levels come from Kahn
+ * rounds; a round that finds no ready block (a cycle) places the unplaced
+ * block with the fewest unplaced predecessors, then the smallest index,
+ * alone.  Blocks on one level are never coupled, so the level-by-level
+ * forward sweep is the sequential Gauss-Seidel sweep in this order; for pure
+ * advection on an acyclic element graph S_hat is block lower triangular in it
+ * and one sweep solves exactly.  The facet-block pattern must be
+ * structurally symmetric (air_setup returns AH_EUNSUPPORTED otherwise, and
+ * for an unscaled system).  level: host [nblocks] or NULL; nblocks, rounds,
+ * breaks (rounds that broke a cycle) may be NULL.  A hierarchy without an
+ * ordered relaxation reports nblocks = rounds = 0.  Synchronous. */
+ah_status ah_hier_flow_levels(const ah_hier* h, int32_t* level, int64_t* nblocks, int* rounds, int* breaks);
 
 /* ---------------------------------------------------------- air_solve ---
  * method 0: FGMRES(restart) with right preconditioning by one V-cycle (no
@@ -295,6 +315,8 @@ ah_status ah_source_gauss_T(int dim_st, int64_t npts, const double* X, int K,
  * is accumulated.  Tags: "element" (hdg_assemble element kernel),
  * "spmv0" (level-0 FP64 product of the Krylov solver), "relax0_f" /
  * "relax0_c" (level-0 F and C Jacobi sweeps; "_f32" suffix: FP32 cycle),
+ * "gs0" / "gs0_f" (one whole ordered sweep of level 0 over all points / F
+ * points, all its per-level launches; "_f32" suffix: FP32 cycle),
  * "rap0" (level-0 numeric R A P).  ah_profile_read synchronizes the
  * recorded events. */
 void ah_profile_enable(int on);

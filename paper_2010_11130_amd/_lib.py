@@ -74,6 +74,7 @@ SIGNATURES = {
     "ah_hier_destroy": (None, [vp]),
     "ah_hier_level_sizes": (i32, [vp, i32, P_i64, P_i64, P_i64]),
     "ah_hier_level_export": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+    "ah_hier_flow_levels": (i32, [vp, vp, P_i64, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ah_solve_defaults": (None, [C.POINTER(SolveParams)]),
     "air_solve": (i32, [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveInfo)]),
     "air_solve_adjoint": (i32, [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveInfo)]),

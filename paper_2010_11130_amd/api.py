@@ -227,6 +227,18 @@ class Hierarchy:
                                     _stream()), "ah_vcycle_apply")
         return z
 
+    def flow_levels(self):
+        """Level of every level-0 facet block in the flow order of the ordered
+        relaxations (``relax`` 2 or 3), the number of rounds and of cycle
+        breaks."""
+        nb, rounds, breaks = C.c_int64(), C.c_int(), C.c_int()
+        check(lib().ah_hier_flow_levels(self.h, None, C.byref(nb), C.byref(rounds), C.byref(breaks)),
+              "flow_levels")
+        lev = torch.empty(nb.value, dtype=torch.int32)
+        if nb.value:
+            check(lib().ah_hier_flow_levels(self.h, C.c_void_p(lev.data_ptr()), None, None, None), "flow_levels")
+        return lev.numpy(), rounds.value, breaks.value
+
     def level(self, l):
         n, nnz, nnzr = C.c_int64(), C.c_int64(), C.c_int64()
         check(lib().ah_hier_level_sizes(self.h, l, C.byref(n), C.byref(nnz), C.byref(nnzr)), "level_sizes")

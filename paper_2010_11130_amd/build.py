@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libairhdg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mesh.cpp", "prof.cpp", "util.hip", "assemble.hip", "setup.hip", "solve.hip", "extra.hip"]
+SOURCES = ["mesh.cpp", "prof.cpp", "util.hip", "assemble.hip", "setup.hip", "order.hip", "solve.hip", "extra.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1049,7 +1049,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   if (prm_in) prm = *prm_in; else ah_air_defaults(&prm);
   if (prm.lair_distance == 0) prm.lair_distance = 1;
   if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1 ||
-      (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0)) {
+      (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0) || prm.relax < 0 ||
+      prm.relax > 3) {
     set_error("air_setup: invalid parameters");
     return AH_EINVAL;
   }
@@ -1335,6 +1336,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     AhLevel& A0 = h->lev[0];
     CK(transpose(A0.n, A0.n, A0.rowptr, A0.col, A0.val, A0.nnz, ar, tmp, st, &A0.ATptr, &A0.ATcol, &A0.ATval));
   }
+  if (prm.relax >= 2) {
+    rc = flow_order_build(h, st);
+    if (rc < 0) { tmp.release(); delete h; return rc; }
+  }
   unsigned long long fb = 0;
   int gerr = 0;
   {
@@ -1394,10 +1399,12 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     }
     // the tail starts at the first level with at most tail_max rows whose
     // levels, down to the coarsest, fit in LDS as an FP64 image
+    // (with an ordered relaxation, level 0 is swept outside the tail)
+    const int lt = prm.relax >= 2 ? 1 : 0;
     h->tail0 = -1;
     h->tail_lds = false;
     if (nl <= TAIL_MAX_LEVELS) {
-      for (int l = 0; l < nl; ++l) {
+      for (int l = lt; l < nl; ++l) {
         if (h->lev[l].n > tail_max) continue;
         TailLds lo[TAIL_MAX_LEVELS];
         int64_t oc = 0;
@@ -1412,7 +1419,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       }
     }
     if (h->tail0 < 0)   // no LDS image fits: small levels run from global memory
-      for (int l = 0; l < nl; ++l)
+      for (int l = lt; l < nl; ++l)
         if (h->lev[l].n <= std::min<int64_t>(tail_max, 500)) { h->tail0 = l; break; }
     rc = ar.get(&h->d_tail, nl);
     if (rc < 0) { delete h; return rc; }

@@ -43,6 +43,9 @@ namespace ah {
 // Build the LDS image of the forward tail in global memory (once per
 // hierarchy; the cycle then stages it with one contiguous copy).
 ah_status tail_image_build(ah_hier* h, hipStream_t st);
+// Flow order of the level-0 facet blocks for the ordered relaxations
+// (Lemma 3.1): block levels, blocks and F rows grouped by level.
+ah_status flow_order_build(ah_hier* h, hipStream_t st);
 
 // Exclusive prefix sum of n int64 values into out[0..n] (out[n] = total).
 ah_status scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st, Arena& tmp);
@@ -185,6 +188,14 @@ struct ah_hier {
   std::vector<AhLevel> lev;
   double* cinv = nullptr;      // dense inverse of the coarsest matrix [nL][nL]
   int64_t nfallback = 0;
+  // flow order of the level-0 facet blocks (ordered relaxations): level k
+  // holds the blocks ord[ord_lptr[k] .. ord_lptr[k+1]) and the F rows
+  // ord_frows[ord_lptrF[k] .. ord_lptrF[k+1])
+  int32_t* ord = nullptr;
+  int32_t* ord_level = nullptr;  // [blocks] level of each block
+  int32_t* ord_frows = nullptr;
+  std::vector<int64_t> ord_lptr, ord_lptrF;
+  int ord_breaks = 0;            // rounds that broke a cycle
   // FGMRES workspace (allocated on first solve)
   int m_alloc = 0;
   double* V = nullptr;         // [(m+1)][n]
