@@ -28,9 +28,11 @@ the design notes):
     a zero row when it has none;
   * relaxation: Jacobi (omega = 1) sweeps on F, F, C ("FFC") or one F sweep
     ("F") instead of Gauss-Seidel; or, on level 0 only, forward Gauss-Seidel
-    in the flow order of Lemma 3.1 (Section 3.3): over all points
-    ("ordered", the exact solve of the advective part) or on F points then
-    on all points ("ordered_fa", the schedule of Section 4); coarser levels
+    over the levels of the flow order of Lemma 3.1 (Section 3.3), Jacobi
+    inside a level: over all points ("ordered", the exact solve of the
+    advective part) or on F points then on all points ("ordered_fa", the
+    schedule of Section 4); a pair of facet blocks is ordered only when one
+    coupling exceeds ``order_ratio`` (1.5) times the other; coarser levels
     keep F, F, C Jacobi; no filtering of R, P or R A P;
   * hierarchy stops when the coarse grid has at most ``max_coarse`` points,
     when ``max_levels`` is reached, or when coarsening stalls
@@ -226,28 +228,30 @@ def block_weights(A, b):
     return uk, w
 
 
-def flow_levels(A, b):
+def flow_levels(A, b, ratio=1.5):
     """Flow order of the facet blocks (Lemma 3.1, Section 3.3).
 
-    Every coupled pair of blocks ``I != J`` (``w_IJ > 0`` or ``w_JI > 0``) is
-    oriented along the dominant coupling: ``J`` precedes ``I`` when
-    ``w_IJ > w_JI``, or when ``w_IJ == w_JI`` and ``J < I``.  For pure
-    advection on an acyclic element graph the block below the diagonal of
-    the upwind flux is the only coupling of a pair, so this is the upwind
-    order of the lemma.  Levels by Kahn rounds: round k takes every block
-    whose predecessors are all placed; when blocks remain but none is ready
-    (a cycle), the remaining block with the fewest unplaced predecessors
-    (then the smallest index) forms the round alone.
-    Returns ``(level[nb], rounds, cycle_breaks)``."""
+    A coupled pair of blocks ``I != J`` is oriented along its dominant
+    coupling when that dominance is clear: ``J`` precedes ``I`` when
+    ``w_IJ > ratio * w_JI``.  For pure advection on an acyclic element graph
+    the upwind flux couples each pair one way only (``w_JI = 0``), so every
+    coupled pair is oriented and this is the upwind order of the lemma;
+    pairs whose two couplings are within the ratio (diffusion-dominated
+    facets) stay unordered.  Levels by Kahn rounds over the oriented pairs:
+    round k takes every block whose predecessors are all placed; when
+    blocks remain but none is ready (a cycle), the remaining block with the
+    fewest unplaced predecessors (then the smallest index) forms the round
+    alone.  Returns ``(level[nb], rounds, cycle_breaks)``."""
     nb = A.shape[0] // b
     uk, w = block_weights(A, b)
     I, J = uk // nb, uk % nb
-    rk = J * nb + I
-    pos = np.searchsorted(uk, rk)
-    pos = np.minimum(pos, max(len(uk) - 1, 0))
-    w_rev = np.where((len(uk) > 0) & (uk[pos] == rk), w[pos], 0.0) if len(uk) else w
-    coupled = (w > 0) | (w_rev > 0)
-    pred = coupled & ((w > w_rev) | ((w == w_rev) & (J < I)))
+    if len(uk):
+        rk = J * nb + I
+        pos = np.minimum(np.searchsorted(uk, rk), len(uk) - 1)
+        w_rev = np.where(uk[pos] == rk, w[pos], 0.0)
+    else:
+        w_rev = w
+    pred = w > ratio * w_rev
     # successor lists: edge J -> I for every predecessor J of I
     succ = sp.csr_matrix((np.ones(int(pred.sum())), (J[pred], I[pred])), shape=(nb, nb))
     indeg = np.bincount(I[pred], minlength=nb).astype(np.int64)
@@ -273,11 +277,13 @@ def flow_levels(A, b):
 
 
 class OrderedSweep:
-    """Forward Gauss-Seidel on the rows ``X`` in the flow order: the
-    splitting matrix ``M`` holds the diagonal and every entry ``(i, j)``,
-    ``i, j in X``, whose block ``J`` lies on an earlier level than block
-    ``I``.  One sweep is ``x_X <- x_X + M^-1 (b - A x)_X``; the transposed
-    sweep is ``y_X <- y_X + M^-T (g - A^T y)_X``."""
+    """Forward Gauss-Seidel over the levels of the flow order on the rows
+    ``X``, Jacobi inside a level: the splitting matrix ``M`` holds the
+    diagonal and every entry ``(i, j)``, ``i, j in X``, whose block ``J``
+    lies on an earlier level than block ``I``.  One sweep is
+    ``x_X <- x_X + M^-1 (b - A x)_X``; the transposed sweep is
+    ``y_X <- y_X + M^-T (g - A^T y)_X``.  When no two blocks of a level are
+    coupled this is the sequential Gauss-Seidel sweep in level order."""
 
     def __init__(self, A, b, blev, X):
         self.X = X
@@ -287,12 +293,9 @@ class OrderedSweep:
         AX = A[X][:, X].tocoo()
         li = rl[AX.row]
         lj = rl[AX.col]
-        keep = (AX.row == AX.col) | (li > lj)
-        same = (AX.row != AX.col) & (li == lj) & (AX.data != 0)
-        if np.any(same & (X[AX.row] // b == X[AX.col] // b)):
+        if np.any((AX.row != AX.col) & (X[AX.row] // b == X[AX.col] // b) & (AX.data != 0)):
             raise ValueError("ordered relaxation needs identity diagonal blocks (the scaled system)")
-        if np.any(same):
-            raise ValueError("blocks on one level are coupled")
+        keep = (AX.row == AX.col) | (lj < li)
         inv = np.empty_like(order)
         inv[order] = np.arange(len(order))
         M = sp.csr_matrix((AX.data[keep], (inv[AX.row[keep]], inv[AX.col[keep]])), shape=(len(X), len(X)))
@@ -332,13 +335,14 @@ class Hierarchy:
 
 
 def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
-          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1):
+          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1, order_ratio=1.5):
     """Build the lAIR hierarchy on the scaled matrix (treated as scalar).
     ``theta`` is the strength tolerance of the coarsening (and of P);
     ``theta_r`` that of the restriction neighbourhoods (default: theta);
     ``distance`` the neighbourhood distance of lAIR (1 or 2); ``relax`` one
     of "FFC", "F", "ordered", "ordered_fa"; ``block`` the facet block size
-    of level 0 (the unit of the flow order)."""
+    of level 0 (the unit of the flow order); ``order_ratio`` the dominance
+    ratio that orients a pair of blocks in the flow order."""
     if relax not in ("FFC", "F", "ordered", "ordered_fa"):
         raise ValueError("unknown relaxation %r" % (relax,))
     H = Hierarchy()
@@ -369,7 +373,7 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
         lev.R, nf = lair_R(A, strong_r, cf, cidx, distance)
         H.n_fallback += nf
         if l == 0 and relax in ("ordered", "ordered_fa"):
-            lev.blev, lev.rounds, lev.breaks = flow_levels(A, block)
+            lev.blev, lev.rounds, lev.breaks = flow_levels(A, block, order_ratio)
             lev.gs_all = OrderedSweep(A, block, lev.blev, np.arange(n))
             lev.gs_F = OrderedSweep(A, block, lev.blev, np.nonzero(cf == 0)[0])
         Ac = (lev.R @ A @ lev.P).tocsr()

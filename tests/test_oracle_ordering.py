@@ -37,12 +37,11 @@ def _block_dense_weights(A, b):
     return W
 
 
-def _longest_path_levels(W):
+def _longest_path_levels(W, ratio=1.5):
     """Level = length of the longest chain of predecessors, by memoised
     recursion over the dominance relation (DAG case)."""
     nb = W.shape[0]
-    preds = [[J for J in range(nb) if J != I and (W[I, J] > 0 or W[J, I] > 0)
-              and (W[I, J] > W[J, I] or (W[I, J] == W[J, I] and J < I))] for I in range(nb)]
+    preds = [[J for J in range(nb) if J != I and W[I, J] > ratio * W[J, I]] for I in range(nb)]
     memo = {}
 
     def lev(I, depth=0):
@@ -88,13 +87,32 @@ def test_cycle_break_rule():
     assert (rounds, breaks) == (4, 1)
 
 
-def test_tie_orders_by_index():
-    A = np.eye(3)
-    A[0, 2] = A[2, 0] = 0.3          # equal couplings: the smaller index goes first
+def test_balanced_pairs_stay_unordered():
+    A = np.eye(4)
+    A[0, 2], A[2, 0] = 0.3, 0.25     # within the ratio 1.5: no order between 0 and 2
     A[1, 0] = 0.2                    # 0 precedes 1 (A[0, 1] = 0)
+    A[3, 1], A[1, 3] = 0.5, 0.25     # ratio 2: 1 precedes 3
     lev, rounds, breaks = air.flow_levels(sp.csr_matrix(A), 1)
-    np.testing.assert_array_equal(lev, [0, 1, 1])
-    assert breaks == 0
+    np.testing.assert_array_equal(lev, [0, 1, 0, 2])
+    assert (rounds, breaks) == (3, 0)
+    lev, _, _ = air.flow_levels(sp.csr_matrix(A), 1, ratio=1.1)   # now 2 precedes 0
+    np.testing.assert_array_equal(lev, [1, 2, 0, 3])
+
+
+def _level_gs(A, b_, x, rows, row_level):
+    """Gauss-Seidel over levels, Jacobi inside a level, one row at a time:
+    a row reads the values of its own level as they were when the level
+    began and the current values of every other row."""
+    Ad = A.toarray()
+    x = x.copy()
+    for k in np.unique(row_level):
+        snap = x.copy()
+        same = np.zeros(len(x), dtype=bool)
+        same[rows[row_level == k]] = True
+        for i in rows[row_level == k]:
+            xt = np.where(same, snap, x)
+            x[i] = snap[i] + (b_[i] - Ad[i] @ xt) / Ad[i, i]
+    return x
 
 
 def _sequential_gs(A, b_, x, rows_in_order):
@@ -107,19 +125,33 @@ def _sequential_gs(A, b_, x, rows_in_order):
 
 
 @pytest.mark.parametrize("which", ["all", "F"])
-def test_ordered_sweep_is_sequential_gauss_seidel(slab_diff, which):
+@pytest.mark.parametrize("ratio", [1.5, 1.0])
+def test_ordered_sweep_by_rows(slab_diff, which, ratio):
     A, b = slab_diff.Shat, slab_diff.b
-    H = air.setup(A, relax="ordered_fa", block=b)
+    H = air.setup(A, relax="ordered_fa", block=b, order_ratio=ratio)
     L0 = H.levels[0]
     sw = L0.gs_all if which == "all" else L0.gs_F
     X = sw.X
     rng = np.random.default_rng(3)
     rhs = rng.standard_normal(A.shape[0])
     x0 = rng.standard_normal(A.shape[0])
-    rows = X[np.lexsort((X, L0.blev[X // b]))]
-    ref = _sequential_gs(A, rhs, x0, rows)
+    ref = _level_gs(A, rhs, x0, X, L0.blev[X // b])
     got = sw.apply(A, rhs, x0)
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_ordered_sweep_without_level_couplings_is_gauss_seidel(kuhn_nu0):
+    """Pure advection: no two blocks of a level are coupled, so the sweep is
+    the textbook sequential sweep in level order."""
+    A, b = kuhn_nu0.Shat, kuhn_nu0.b
+    H = air.setup(A, relax="ordered", block=b)
+    L0 = H.levels[0]
+    n = A.shape[0]
+    rng = np.random.default_rng(8)
+    rhs, x0 = rng.standard_normal((2, n))
+    X = np.arange(n)
+    ref = _sequential_gs(A, rhs, x0, X[np.lexsort((X, L0.blev[X // b]))])
+    np.testing.assert_allclose(L0.gs_all.apply(A, rhs, x0), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
 def test_ordered_sweep_is_exact_for_pure_advection(kuhn_nu0):
