@@ -53,6 +53,8 @@ def parse():
                     help="skip the march with distance-two lAIR neighbourhoods")
     ap.add_argument("--no-internal-layer", action="store_true",
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
+    ap.add_argument("--no-ordered", action="store_true",
+                    help="skip the ordered Gauss-Seidel relaxations (internal layer, slab 0)")
     ap.add_argument("--builders", type=int, default=1,
                     help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
@@ -440,11 +442,12 @@ def solve_alone(march, repeats, tol):
             "us_per_iteration": 1e6 * t / its, "iters": its // repeats, "kernels": prof}
 
 
-def internal_layer(n=48, p=1, tol=1e-8):
+def internal_layer(n=48, p=1, tol=1e-8, air=None):
     """The moving internal layer of Section 4.2 (nu = 0, discontinuous exact
     solution) on the uniform n^3 Kuhn mesh of the space-time unit cube, all
-    at once: assembly, lAIR setup, FGMRES and reconstruction, timed after one
-    warm-up run with the mesh and boundary data on the device."""
+    at once: assembly, lAIR setup (parameters ``air``), FGMRES and
+    reconstruction, timed after one warm-up run with the mesh and boundary
+    data on the device."""
     import numpy as np
     import torch
     from paper_2010_11130_amd import Mesh, System, Hierarchy
@@ -469,16 +472,72 @@ def internal_layer(n=48, p=1, tol=1e-8):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = System(m, p, 0.0, a, None, g)
-        h = Hierarchy(s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h = Hierarchy(s, **(air or {}))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         x, info = h.solve(tol=tol)
         s.reconstruct(x)
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        res = (s, h, info, t)
-    s, h, info, t = res
-    return {"value": s.n / t, "unit": "DOF/s", "ms": 1e3 * t, "mesh": "%d^3 Kuhn cubes, %d tets" % (n, 6 * n ** 3),
-            "p": p, "free_dofs": s.n, "iters": info["iters"], "levels": h.info["levels"],
-            "op_complexity": h.info["op_complexity"]}
+        t3 = time.perf_counter()
+        res = (s, h, info, t3 - t0, t1 - t0, t2 - t1, t3 - t2)
+    s, h, info, t, ta, tsu, tso = res
+    out = {"value": s.n / t, "unit": "DOF/s", "ms": 1e3 * t, "mesh": "%d^3 Kuhn cubes, %d tets" % (n, 6 * n ** 3),
+           "p": p, "free_dofs": s.n, "iters": info["iters"], "levels": h.info["levels"],
+           "op_complexity": h.info["op_complexity"],
+           "stages_ms": {"assemble": 1e3 * ta, "setup": 1e3 * tsu, "solve_and_reconstruct": 1e3 * tso}}
+    if air and air.get("relax", 0) >= 2:
+        _, rounds, breaks = h.flow_levels()
+        out["flow_order"] = {"rounds": rounds, "cycle_breaks": breaks}
+    return out
+
+
+def ordered_slab(s, relax, tol, repeats=3):
+    """lAIR setup and FGMRES solves of one assembled slab with the given
+    relaxation (0: F,F,C Jacobi; 2, 3: ordered Gauss-Seidel on level 0),
+    plus the per-sweep time of the ordered sweeps from the HIP events."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy, lib
+    Hierarchy(s, relax=relax).solve(tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = Hierarchy(s, relax=relax)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    its = 0
+    for _ in range(repeats):
+        _, info = h.solve(tol=tol)
+        its += info["iters"]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"iters": its // repeats, "setup_ms": 1e3 * (t1 - t0), "solve_ms": 1e3 * (t2 - t1) / repeats,
+           "dofs_per_s_setup_solve": s.n / ((t1 - t0) + (t2 - t1) / repeats)}
+    if relax >= 2:
+        _, rounds, breaks = h.flow_levels()
+        out["flow_order"] = {"rounds": rounds, "cycle_breaks": breaks}
+        lib().ah_profile_reset()
+        lib().ah_profile_enable(1)
+        h.solve(tol=tol)
+        torch.cuda.synchronize()
+        lib().ah_profile_enable(0)
+        out["sweeps"] = profile_totals(["gs0", "gs0_f"])
+        lib().ah_profile_reset()
+    return out
+
+
+def ordered_relaxation(args, march):
+    """Ordered Gauss-Seidel in the flow order of Lemma 3.1 against F,F,C
+    Jacobi: the moving internal layer (nu = 0: one ordered sweep inverts level
+    0) all at once, and slab 0 of the march."""
+    from paper_2010_11130_amd import System
+    out = {}
+    for relax in (2, 3):
+        out["internal_layer_relax%d" % relax] = internal_layer(tol=args.tol, air={"relax": relax})
+    s0 = System(march.mesh, args.p, args.nu, march.a, None, march.g[0])
+    for relax in (0, 2, 3):
+        out["slab0_relax%d" % relax] = ordered_slab(s0, relax, args.tol)
+    return out
 
 
 def element_flops(D, p):
@@ -652,6 +711,8 @@ def main():
         out["all_at_once"] = all_at_once(args, last64[1])
     if not args.no_internal_layer:
         out["internal_layer"] = internal_layer(tol=args.tol)
+    if not args.no_ordered:
+        out["ordered_relaxation"] = ordered_relaxation(args, march)
     # dominant tagged kernel of the FP64 march
     if prof64:
         out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])

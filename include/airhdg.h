@@ -192,6 +192,8 @@ typedef struct {
   int adjoint;
   int lair_distance;   /* 1 (default) or 2 */
   double theta_r;      /* restriction strength threshold; <= 0: theta (default) */
+  double order_ratio;  /* relax 2, 3: dominance ratio that orders a pair of
+                          facet blocks (>= 1; default 1.5) */
 } ah_air_params;
 
 typedef struct {
@@ -221,15 +223,16 @@ ah_status ah_hier_level_export(const ah_hier* h, int l, int64_t* row_ptr, int32_
 
 /* Flow order of the ordered relaxations (relax 2 or 3; Lemma 3.1, Section
  * 3.3).  The level-0 facet blocks (block size b, nblocks = n_free / b) are
- * ordered along the dominant coupling of every coupled pair: with
+ * ordered along the clearly dominant coupling of a pair: with
  * w_IJ = max |S_hat entries of off-diagonal block (I, J)|, J precedes I when
- * w_IJ > w_JI, or when they are equal and J < I.  Levels come from Kahn
- * rounds; a round that finds no ready block (a cycle) places the unplaced
- * block with the fewest unplaced predecessors, then the smallest index,
- * alone.  Blocks on one level are never coupled, so the level-by-level
- * forward sweep is the sequential Gauss-Seidel sweep in this order; for pure
- * advection on an acyclic element graph S_hat is block lower triangular in it
- * and one sweep solves exactly.  The facet-block pattern must be
+ * w_IJ > order_ratio w_JI; pairs within the ratio stay unordered.  Levels
+ * come from Kahn rounds; a round that finds no ready block (a cycle) places
+ * the unplaced block with the fewest unplaced predecessors, then the
+ * smallest index, alone.  The sweep is Gauss-Seidel across levels and Jacobi
+ * inside a level (the splitting matrix holds the entries whose column block
+ * lies on an earlier level); for pure advection on an acyclic element graph
+ * S_hat is block lower triangular in this order, no two blocks of a level
+ * are coupled, and one sweep solves exactly.  The facet-block pattern must be
  * structurally symmetric (air_setup returns AH_EUNSUPPORTED otherwise, and
  * for an unscaled system).  level: host [nblocks] or NULL; nblocks, rounds,
  * breaks (rounds that broke a cycle) may be NULL.  A hierarchy without an

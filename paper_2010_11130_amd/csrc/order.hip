@@ -1,16 +1,18 @@
 // Flow order of the level-0 facet blocks for the ordered Gauss-Seidel
 // relaxations (Lemma 3.1, Section 3.3), built on the device.
 //
-// Every coupled pair of off-diagonal blocks (I, J) is oriented along its
-// dominant coupling, w_IJ = max |S_hat entries of block (I, J)|: J precedes
-// I when w_IJ > w_JI, or when the two are equal and J < I.  Levels come
-// from Kahn rounds: round k places every block whose predecessors are all
-// placed; when blocks remain and none is ready (a cycle), the remaining
-// block with the fewest unplaced predecessors (then the smallest index) is
-// placed alone.  For pure advection on an acyclic element graph the scaled
-// matrix is block lower triangular in this order, and a forward sweep in
-// it is the exact solve.  Blocks of one level are never coupled, so a
-// sweep that updates one level per launch is the sequential sweep.
+// A coupled pair of off-diagonal blocks (I, J) is oriented along its
+// dominant coupling, w_IJ = max |S_hat entries of block (I, J)|, when that
+// dominance is clear: J precedes I when w_IJ > ratio w_JI.  Levels come from
+// Kahn rounds over the oriented pairs: round k places every block whose
+// predecessors are all placed; when blocks remain and none is ready (a
+// cycle), the remaining block with the fewest unplaced predecessors (then
+// the smallest index) is placed alone.  For pure advection on an acyclic
+// element graph the upwind flux couples each pair one way only, the scaled
+// matrix is block lower triangular in this order, and a forward sweep in it
+// is the exact solve.  The sweep is Gauss-Seidel across levels and Jacobi
+// inside a level (a level reads its own blocks' values from before the
+// level), one launch per level.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -44,11 +46,11 @@ __global__ void k_ord_weights(int64_t nbr, int B, const int64_t* __restrict__ op
 }
 
 // dir[s] for slot s of row R with column J: 1 when J precedes R, 2 when R
-// precedes J, 0 for an uncoupled pair; indeg[R] = predecessors of R.  A
-// slot without its transposed slot sets *bad.
-__global__ void k_ord_orient(int64_t nbr, const int64_t* __restrict__ optr, const int32_t* __restrict__ ocol,
-                             const double* __restrict__ w, uint8_t* __restrict__ dir, int32_t* __restrict__ indeg,
-                             int* __restrict__ bad) {
+// precedes J, 0 for a pair left unordered; indeg[R] = predecessors of R.
+// A slot without its transposed slot sets *bad.
+__global__ void k_ord_orient(int64_t nbr, double ratio, const int64_t* __restrict__ optr,
+                             const int32_t* __restrict__ ocol, const double* __restrict__ w,
+                             uint8_t* __restrict__ dir, int32_t* __restrict__ indeg, int* __restrict__ bad) {
   const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (R >= nbr) return;
   int cnt = 0;
@@ -59,8 +61,7 @@ __global__ void k_ord_orient(int64_t nbr, const int64_t* __restrict__ optr, cons
       if (ocol[t] == (int32_t)R) { wr = w[t]; break; }
     if (wr < 0.0) { *bad = 1; wr = 0.0; }
     const double ws = w[s];
-    uint8_t d = 0;
-    if (ws > 0.0 || wr > 0.0) d = (ws > wr || (ws == wr && (int64_t)J < R)) ? 1 : 2;
+    const uint8_t d = ws > ratio * wr ? 1 : wr > ratio * ws ? 2 : 0;
     dir[s] = d;
     cnt += d == 1;
   }
@@ -134,6 +135,20 @@ __global__ void k_ord_frows(int64_t nbr, int B, const int32_t* __restrict__ ord,
     if (cf[R * B + m] == 0) frows[j++] = (int32_t)(R * B + m);
 }
 
+// Column blocks of the facet-block layout for the sweeps: ~J where block J
+// lies on the row's own level (read from the values before the level), J
+// otherwise.
+__global__ void k_ord_cols(int64_t nbr, const int64_t* __restrict__ optr, const int32_t* __restrict__ ocol,
+                           const int32_t* __restrict__ level, int32_t* __restrict__ out) {
+  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= nbr) return;
+  const int32_t lr = level[R];
+  for (int64_t s = optr[R]; s < optr[R + 1]; ++s) {
+    const int32_t J = ocol[s];
+    out[s] = level[J] == lr ? ~J : J;
+  }
+}
+
 __global__ void k_ord_gather(int64_t m, const int64_t* __restrict__ idx, const int64_t* __restrict__ src,
                              int64_t* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,8 +186,8 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
   OK_(h->arena.get(&h->ord_level, nbr));
   HIP_(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned), st));
   hipLaunchKernelGGL(k_ord_weights, grid1(nbr), dim3(256), 0, st, nbr, B, L.optr, L.oval, w);
-  hipLaunchKernelGGL(k_ord_orient, grid1(nbr), dim3(256), 0, st, nbr, L.optr, L.ocol, w, dir, indeg,
-                     reinterpret_cast<int*>(cnt + 2));
+  hipLaunchKernelGGL(k_ord_orient, grid1(nbr), dim3(256), 0, st, nbr, h->prm.order_ratio, L.optr, L.ocol, w, dir,
+                     indeg, reinterpret_cast<int*>(cnt + 2));
   hipLaunchKernelGGL(k_ord_init, grid1(nbr), dim3(256), 0, st, nbr, indeg, h->ord_level, h->ord, cnt);
   HIP_(hipGetLastError());
   unsigned head[3] = {0, 0, 0};
@@ -212,6 +227,9 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
     hi += next;
   }
   h->ord_breaks = breaks;
+  OK_(h->arena.get(&h->ord_cols, nslot));
+  hipLaunchKernelGGL(k_ord_cols, grid1(nbr), dim3(256), 0, st, nbr, L.optr, L.ocol, h->ord_level, h->ord_cols);
+  HIP_(hipGetLastError());
   // F rows by level
   const int64_t nl = (int64_t)lptr.size();
   int32_t* fc = nullptr;

@@ -1039,6 +1039,7 @@ extern "C" void ah_air_defaults(ah_air_params* p) {
   p->adjoint = 0;
   p->lair_distance = 1;
   p->theta_r = 0.0;
+  p->order_ratio = 1.5;
 }
 
 extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, void* stream, ah_hier** out,
@@ -1048,9 +1049,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   ah_air_params prm;
   if (prm_in) prm = *prm_in; else ah_air_defaults(&prm);
   if (prm.lair_distance == 0) prm.lair_distance = 1;
+  if (prm.order_ratio == 0.0) prm.order_ratio = 1.5;
   if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1 ||
       (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0) || prm.relax < 0 ||
-      prm.relax > 3) {
+      prm.relax > 3 || !(prm.order_ratio >= 1.0 && prm.order_ratio < 1e300)) {
     set_error("air_setup: invalid parameters");
     return AH_EINVAL;
   }

@@ -153,16 +153,19 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
   }
 }
 
-// One level of the ordered forward Gauss-Seidel sweep on level 0 (flow
-// order of Lemma 3.1), in place on x: x_i <- b_i - sum of a_ij x_j over
-// the off-diagonal blocks (the diagonal blocks are the identity).  No two
-// rows of one level are coupled, so updating a level at once is the
-// sequential sweep.  BLK: items are blocks and row k is
-// items[k / B] B + k mod B; otherwise items are rows.
+// One level of the ordered forward sweep on level 0 (flow order of Lemma
+// 3.1): x_i <- b_i - sum of a_ij x_j over the off-diagonal blocks (the
+// diagonal blocks are the identity), written to xn.  Blocks of earlier
+// levels are read from xn (already swept), blocks of the row's own level
+// from xo (values before the level: Jacobi inside a level), later levels
+// from xn (still equal to xo).  cols holds ~J for a block J on the row's
+// level.  BLK: items are blocks and row k is items[k / B] B + k mod B;
+// otherwise items are rows.
 template <class TA, class T, int B, int G, bool BLK>
 __global__ __launch_bounds__(256) void k_gs_fb(int64_t n, const int32_t* __restrict__ items,
-                                               const int64_t* __restrict__ optr, const int32_t* __restrict__ ocol,
-                                               const TA* __restrict__ ov, const T* __restrict__ b, T* x) {
+                                               const int64_t* __restrict__ optr, const int32_t* __restrict__ cols,
+                                               const TA* __restrict__ ov, const T* __restrict__ b,
+                                               const T* __restrict__ xo, T* xn) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / G;
   const int g = (int)(gid % G);
@@ -173,40 +176,50 @@ __global__ __launch_bounds__(256) void k_gs_fb(int64_t n, const int32_t* __restr
   const int64_t o0 = optr[R];
   const int len = (int)(optr[R + 1] - o0) * B;
   const TA* __restrict__ v = ov + o0 * (B * B) + (int64_t)m * len;
-  const int32_t* __restrict__ cb = ocol + o0;
+  const int32_t* __restrict__ cb = cols + o0;
   T acc = 0, acc1 = 0;
   int e = g;
   for (; e + G < len; e += 2 * G) {
     const int e1 = e + G;
-    const int64_t c0 = (int64_t)cb[e / B] * B + e % B, c1 = (int64_t)cb[e1 / B] * B + e1 % B;
-    acc += (T)v[e] * x[c0];
-    acc1 += (T)v[e1] * x[c1];
+    const int32_t j0 = cb[e / B], j1 = cb[e1 / B];
+    const T* s0 = j0 < 0 ? xo : xn;
+    const T* s1 = j1 < 0 ? xo : xn;
+    acc += (T)v[e] * s0[(int64_t)(j0 < 0 ? ~j0 : j0) * B + e % B];
+    acc1 += (T)v[e1] * s1[(int64_t)(j1 < 0 ? ~j1 : j1) * B + e1 % B];
   }
-  if (e < len) acc += (T)v[e] * x[(int64_t)cb[e / B] * B + e % B];
+  if (e < len) {
+    const int32_t j0 = cb[e / B];
+    acc += (T)v[e] * (j0 < 0 ? xo : xn)[(int64_t)(j0 < 0 ? ~j0 : j0) * B + e % B];
+  }
   acc += acc1;
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-  if (g == 0) x[i] = b[i] - acc;
+  if (g == 0) xn[i] = b[i] - acc;
 }
 
-// One level of the transposed (backward) ordered sweep of the adjoint
-// cycle, on the rows of A^T (scalar CSR with its diagonal), in place on y:
-// y_i <- y_i + (g_i - (A^T y)_i) / d_i.
+// One level k of the transposed (backward) ordered sweep of the adjoint
+// cycle, on the rows of A^T (scalar CSR with its diagonal):
+// yn_i = yo_i + (g_i - (A^T y~)_i) / d_i, y~ from yo on the row's own level
+// (lev of the column's block == k) and from yn elsewhere.
 template <class T, int G, bool BLK>
 __global__ __launch_bounds__(256) void k_gs_csr(int64_t n, const int32_t* __restrict__ items, int B,
                                                 const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                 const T* __restrict__ v, const T* __restrict__ d,
-                                                const T* __restrict__ g, T* y) {
+                                                const T* __restrict__ g, const int32_t* __restrict__ lev, int k,
+                                                const T* __restrict__ yo, T* yn) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / G;
   const int lane = (int)(gid % G);
   if (ii >= n) return;
   const int64_t i = BLK ? (int64_t)items[ii / B] * B + ii % B : (int64_t)items[ii];
   T acc = 0;
-  for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += G) acc += v[k] * y[ci[k]];
+  for (int64_t q = rp[i] + lane; q < rp[i + 1]; q += G) {
+    const int32_t j = ci[q];
+    acc += v[q] * (lev[j / B] == k ? yo : yn)[j];
+  }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-  if (lane == 0) y[i] = y[i] + (g[i] - acc) / d[i];
+  if (lane == 0) yn[i] = yo[i] + (g[i] - acc) / d[i];
 }
 
 // Coarse end of the cycle in one workgroup: every level from l0 down,
@@ -883,19 +896,24 @@ struct Ops<float> {
 };
 
 // Ordered sweeps on level 0 (relax 2: all points; relax 3: F points, then
-// all points), one launch per level of the flow order.
+// all points), one launch per level of the flow order, from xo into xn
+// (xn must hold the same values as xo on entry).
 template <class TA, class T, int B, int G>
-static void gs_fb_level(bool blk, int64_t nrows, const int32_t* items, const AhLevel& L, const TA* ov, const T* b,
-                        T* x, hipStream_t st) {
+static void gs_fb_level(bool blk, int64_t nrows, const int32_t* items, const ah_hier* h, const TA* ov, const T* b,
+                        const T* xo, T* xn, hipStream_t st) {
+  const AhLevel& L = h->lev[0];
   const dim3 grid((unsigned)cdiv(nrows * G, 256));
   if (blk)
-    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, true>), grid, dim3(256), 0, st, nrows, items, L.optr, L.ocol, ov, b, x);
+    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, true>), grid, dim3(256), 0, st, nrows, items, L.optr, h->ord_cols, ov,
+                       b, xo, xn);
   else
-    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, false>), grid, dim3(256), 0, st, nrows, items, L.optr, L.ocol, ov, b, x);
+    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, false>), grid, dim3(256), 0, st, nrows, items, L.optr, h->ord_cols, ov,
+                       b, xo, xn);
 }
 
 template <class T, int B>
-static ah_status gs_fb_sweep_b(const ah_hier* h, bool fonly, const T* ov, const T* b, T* x, hipStream_t st) {
+static ah_status gs_fb_sweep_b(const ah_hier* h, bool fonly, const T* ov, const T* b, const T* xo, T* xn,
+                               hipStream_t st) {
   const AhLevel& L = h->lev[0];
   const int G = fb_lanes(L.nov, L.n) <= 4 ? 4 : 8;
   const std::vector<int64_t>& lp = fonly ? h->ord_lptrF : h->ord_lptr;
@@ -905,9 +923,9 @@ static ah_status gs_fb_sweep_b(const ah_hier* h, bool fonly, const T* ov, const 
     const int64_t nr = (lp[k + 1] - lp[k]) * scale;
     if (nr == 0) continue;
     if (G == 4)
-      gs_fb_level<T, T, B, 4>(!fonly, nr, items + lp[k], L, ov, b, x, st);
+      gs_fb_level<T, T, B, 4>(!fonly, nr, items + lp[k], h, ov, b, xo, xn, st);
     else
-      gs_fb_level<T, T, B, 8>(!fonly, nr, items + lp[k], L, ov, b, x, st);
+      gs_fb_level<T, T, B, 8>(!fonly, nr, items + lp[k], h, ov, b, xo, xn, st);
   }
   AH_LAUNCHED();
   return AH_OK;
@@ -926,28 +944,30 @@ static double gs_sweep_bytes(const AhLevel& L, bool fonly) {
 }
 
 template <class T>
-static ah_status gs_fb_sweep(const ah_hier* h, bool fonly, const T* ov, const T* b, T* x, hipStream_t st) {
+static ah_status gs_fb_sweep(const ah_hier* h, bool fonly, const T* ov, const T* b, const T* xo, T* xn,
+                             hipStream_t st) {
   const AhLevel& L = h->lev[0];
   ProfScope ps;
   prof_begin(ps, fonly ? (sizeof(T) == 8 ? "gs0_f" : "gs0_f_f32") : (sizeof(T) == 8 ? "gs0" : "gs0_f32"), st,
              gs_sweep_bytes<T>(L, fonly));
   ah_status rc = AH_OK;
   switch (L.ob) {
-    case 2: rc = gs_fb_sweep_b<T, 2>(h, fonly, ov, b, x, st); break;
-    case 3: rc = gs_fb_sweep_b<T, 3>(h, fonly, ov, b, x, st); break;
-    case 4: rc = gs_fb_sweep_b<T, 4>(h, fonly, ov, b, x, st); break;
-    case 6: rc = gs_fb_sweep_b<T, 6>(h, fonly, ov, b, x, st); break;
-    case 10: rc = gs_fb_sweep_b<T, 10>(h, fonly, ov, b, x, st); break;
+    case 2: rc = gs_fb_sweep_b<T, 2>(h, fonly, ov, b, xo, xn, st); break;
+    case 3: rc = gs_fb_sweep_b<T, 3>(h, fonly, ov, b, xo, xn, st); break;
+    case 4: rc = gs_fb_sweep_b<T, 4>(h, fonly, ov, b, xo, xn, st); break;
+    case 6: rc = gs_fb_sweep_b<T, 6>(h, fonly, ov, b, xo, xn, st); break;
+    case 10: rc = gs_fb_sweep_b<T, 10>(h, fonly, ov, b, xo, xn, st); break;
     default: set_error("unsupported facet block size %d", L.ob); rc = AH_EUNSUPPORTED;
   }
   prof_end(ps);
   return rc;
 }
 
-// Transposed ordered sweep on the rows of A_0^T, levels in reverse order.
+// Transposed ordered sweep on the rows of A_0^T, levels in reverse order,
+// from yo into yn (equal on entry).
 template <class T>
-static ah_status gs_csr_sweep_t(const ah_hier* h, bool fonly, const T* atv, const T* d, const T* g, T* y,
-                                hipStream_t st) {
+static ah_status gs_csr_sweep_t(const ah_hier* h, bool fonly, const T* atv, const T* d, const T* g, const T* yo,
+                                T* yn, hipStream_t st) {
   const AhLevel& L = h->lev[0];
   const std::vector<int64_t>& lp = fonly ? h->ord_lptrF : h->ord_lptr;
   const int B = L.ob;
@@ -959,10 +979,10 @@ static ah_status gs_csr_sweep_t(const ah_hier* h, bool fonly, const T* atv, cons
     const dim3 grid((unsigned)cdiv(nr * 8, 256));
     if (fonly)
       hipLaunchKernelGGL((k_gs_csr<T, 8, false>), grid, dim3(256), 0, st, nr, items + lp[k], B, L.ATptr, L.ATcol,
-                         atv, d, g, y);
+                         atv, d, g, h->ord_level, (int)k, yo, yn);
     else
       hipLaunchKernelGGL((k_gs_csr<T, 8, true>), grid, dim3(256), 0, st, nr, items + lp[k], B, L.ATptr, L.ATcol,
-                         atv, d, g, y);
+                         atv, d, g, h->ord_level, (int)k, yo, yn);
   }
   AH_LAUNCHED();
   return AH_OK;
@@ -1038,12 +1058,17 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   // F1 x -> y, F2 y -> x (its rows also written into out), C x -> out.  With
   // one F sweep, y is out.
   if (h->prm.relax >= 2) {
-    // ordered Gauss-Seidel in the flow order, in place on out = P e_c
-    hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, out, Ops<T>::y(L));
+    // ordered sweeps in the flow order: y = out = P e_c; (relax 3: F sweep
+    // y -> out, y = out;) sweep over all points y -> out
+    T* y = Ops<T>::y(L);
+    hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, y, out);
     AH_LAUNCHED();
     const T* ov = Ops<T>::O(L);
-    if (h->prm.relax == 3) AH_TRY(gs_fb_sweep<T>(h, true, ov, b, out, st));
-    return gs_fb_sweep<T>(h, false, ov, b, out, st);
+    if (h->prm.relax == 3) {
+      AH_TRY(gs_fb_sweep<T>(h, true, ov, b, y, out, st));
+      AH_HIP(hipMemcpyAsync(y, out, L.n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    return gs_fb_sweep<T>(h, false, ov, b, y, out, st);
   }
   T* x = Ops<T>::x(L);
   T* y = nsw == 1 ? out : Ops<T>::y(L);
@@ -1101,8 +1126,14 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
   AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
   if (l == 0 && h->prm.relax >= 2) {
     // transposed ordered sweeps: all points, then (relax 3) F points
-    AH_TRY(gs_csr_sweep_t<T>(h, false, Ops<T>::AT(L), Ops<T>::d(L), g, cur, st));
-    if (h->prm.relax == 3) AH_TRY(gs_csr_sweep_t<T>(h, true, Ops<T>::AT(L), Ops<T>::d(L), g, cur, st));
+    AH_HIP(hipMemsetAsync(alt, 0, L.n * sizeof(T), st));
+    AH_TRY(gs_csr_sweep_t<T>(h, false, Ops<T>::AT(L), Ops<T>::d(L), g, cur, alt, st));
+    std::swap(cur, alt);
+    if (h->prm.relax == 3) {
+      AH_HIP(hipMemcpyAsync(alt, cur, L.n * sizeof(T), hipMemcpyDeviceToDevice, st));
+      AH_TRY(gs_csr_sweep_t<T>(h, true, Ops<T>::AT(L), Ops<T>::d(L), g, cur, alt, st));
+      std::swap(cur, alt);
+    }
   } else {
     const int sets[3] = {1, 0, 0};   // C, F, F
     const int nsw = h->prm.relax == 1 ? 1 : 3;

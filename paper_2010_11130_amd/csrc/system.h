@@ -194,6 +194,7 @@ struct ah_hier {
   int32_t* ord = nullptr;
   int32_t* ord_level = nullptr;  // [blocks] level of each block
   int32_t* ord_frows = nullptr;
+  int32_t* ord_cols = nullptr;   // level-0 block columns, ~J where J is on the row's level
   std::vector<int64_t> ord_lptr, ord_lptrF;
   int ord_breaks = 0;            // rounds that broke a cycle
   // FGMRES workspace (allocated on first solve)

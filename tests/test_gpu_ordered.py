@@ -1,8 +1,9 @@
 """GPU parity of the ordered Gauss-Seidel relaxations (relax 2: all points,
-relax 3: F points then all points; flow order of Lemma 3.1, Section 3.3)
-against the oracle: the flow order bit for bit, one V-cycle and its
-transpose to 1e-10, FGMRES solutions to 1e-10 with iteration counts within
-one, and the exact one-step solve of pure advection."""
+relax 3: F points then all points; flow order of Lemma 3.1, Section 3.3;
+Gauss-Seidel across levels, Jacobi inside a level) against the oracle: the
+flow order bit for bit, one V-cycle and its transpose to 1e-10 (FP32 cycle
+1e-5), FGMRES solutions to 1e-10 with iteration counts within one, and the
+exact one-step solve of pure advection."""
 import numpy as np
 import pytest
 import torch
@@ -37,19 +38,20 @@ def _hier(g, relax, **kw):
 
 
 @pytest.mark.parametrize("name", CASES)
-def test_flow_order_parity(built, name):
+@pytest.mark.parametrize("ratio", [1.5, 1.0])
+def test_flow_order_parity(built, name, ratio):
     """Levels, rounds and cycle breaks equal the oracle's order of the same
     matrix (the GPU's level 0) and of the oracle's own scaled matrix."""
-    print("case", name, flush=True)
+    print("case", name, ratio, flush=True)
     g, o = built(name)
-    H = _hier(g, 2)
+    H = _hier(g, 2, order_ratio=ratio)
     lev, rounds, breaks = H.flow_levels()
     l0 = H.level(0)
     A = to_scipy(l0["rowptr"], l0["col"], l0["val"], l0["n"])
-    ref, rr, rb = oair.flow_levels(A, o.b)
+    ref, rr, rb = oair.flow_levels(A, o.b, ratio)
     assert np.array_equal(lev, ref)
     assert (rounds, breaks) == (rr, rb)
-    ref2, _, _ = oair.flow_levels(o.Shat, o.b)
+    ref2, _, _ = oair.flow_levels(o.Shat, o.b, ratio)
     assert np.array_equal(lev, ref2)
 
 
@@ -57,11 +59,12 @@ def test_flow_order_parity(built, name):
 @pytest.mark.parametrize("relax", [2, 3])
 @pytest.mark.parametrize("transpose", [False, True])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_ordered_vcycle_parity(built, name, relax, transpose, fp32):
-    print("case", name, relax, transpose, fp32, flush=True)
+@pytest.mark.parametrize("ratio", [1.5, 1.0])
+def test_ordered_vcycle_parity(built, name, relax, transpose, fp32, ratio):
+    print("case", name, relax, transpose, fp32, ratio, flush=True)
     g, o = built(name)
-    H = _hier(g, relax, adjoint=1, fp32_cycle=1 if fp32 else 0)
-    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax=RELAX[relax], block=o.b)
+    H = _hier(g, relax, adjoint=1, fp32_cycle=1 if fp32 else 0, order_ratio=ratio)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax=RELAX[relax], block=o.b, order_ratio=ratio)
     r = np.random.default_rng(7).standard_normal(g.n)
     z = H.vcycle(torch.as_tensor(r, device="cuda"), precision=1 if fp32 else 0,
                  transpose=transpose).cpu().numpy()
@@ -131,3 +134,5 @@ def test_relax_bad_parameter(built):
     g, _ = built("c1")
     with pytest.raises(AirHdgError):
         Hierarchy(g, relax=4)
+    with pytest.raises(AirHdgError):
+        Hierarchy(g, relax=2, order_ratio=0.5)
