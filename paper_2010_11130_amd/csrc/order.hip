@@ -15,6 +15,7 @@
 // level), one launch per level.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -68,35 +69,55 @@ __global__ void k_ord_orient(int64_t nbr, double ratio, const int64_t* __restric
   indeg[R] = cnt;
 }
 
+// Round state on the device: ds[0] = lo, ds[1] = hi (the current round is
+// ord[lo .. hi)), ds[2] = blocks appended for the next round, ds[3] = round.
 __global__ void k_ord_init(int64_t nbr, const int32_t* __restrict__ indeg, int32_t* __restrict__ level,
-                           int32_t* __restrict__ ord, unsigned* __restrict__ cnt) {
+                           int32_t* __restrict__ ord, unsigned long long* __restrict__ ds) {
   const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (R >= nbr) return;
   level[R] = -1;
-  if (indeg[R] == 0) ord[atomicAdd(cnt, 1u)] = (int32_t)R;
+  if (indeg[R] == 0) ord[atomicAdd(ds + 1, 1ull)] = (int32_t)R;
 }
 
-// Round k: the blocks ord[lo .. lo+m) take level k; each successor whose
-// last predecessor this is joins the next round at ord[lo+m ..).
-__global__ void k_ord_round(int64_t nbr, int64_t lo, int64_t m, int k, const int64_t* __restrict__ optr,
+// One round: the blocks ord[lo .. hi) take level ds[3]; each successor whose
+// last predecessor this is joins the next round at ord[hi ..).  Nothing to
+// do when lo == hi (finished, or a cycle for the host to break).
+__global__ void k_ord_round(int64_t nbr, const unsigned long long* __restrict__ ds0, const int64_t* __restrict__ optr,
                             const int32_t* __restrict__ ocol, const uint8_t* __restrict__ dir,
                             int32_t* __restrict__ indeg, int32_t* __restrict__ level, int32_t* __restrict__ ord,
-                            unsigned* __restrict__ next) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  const int32_t R = ord[lo + t];
-  if (R < 0 || (int64_t)R >= nbr) return;
-  level[R] = k;
-  for (int64_t s = optr[R]; s < optr[R + 1]; ++s) {
-    if (dir[s] != 2) continue;
-    const int32_t J = ocol[s];
-    if (atomicSub(&indeg[J], 1) == 1 && level[J] < 0) {
-      // every block joins a round once, so the appends stay below nbr; the
-      // host checks the count against it
-      const int64_t q = lo + m + (int64_t)atomicAdd(next, 1u);
-      if (q < nbr) ord[q] = J;
+                            unsigned long long* __restrict__ next) {
+  const int64_t lo = (int64_t)ds0[0], hi = (int64_t)ds0[1];
+  if (lo >= hi) return;
+  const int k = (int)ds0[3];
+  for (int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < hi;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t R = ord[t];
+    if (R < 0 || (int64_t)R >= nbr) continue;
+    level[R] = k;
+    for (int64_t s = optr[R]; s < optr[R + 1]; ++s) {
+      if (dir[s] != 2) continue;
+      const int32_t J = ocol[s];
+      if (atomicSub(&indeg[J], 1) == 1 && level[J] < 0) {
+        // every block joins a round once, so the appends stay below nbr
+        const int64_t q = hi + (int64_t)atomicAdd(next, 1ull);
+        if (q < nbr) ord[q] = J;
+      }
     }
   }
+}
+
+// After a round: record its end in lptr and move to the next round.
+__global__ void k_ord_advance(int64_t nbr, unsigned long long* __restrict__ ds, int64_t* __restrict__ lptr) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long lo = ds[0], hi = ds[1];
+  if (lo >= hi) return;
+  const unsigned long long k = ds[3];
+  lptr[k + 1] = (int64_t)hi;
+  const unsigned long long nx = hi + ds[2];
+  ds[0] = hi;
+  ds[1] = nx < (unsigned long long)nbr ? nx : (unsigned long long)nbr;
+  ds[2] = 0;
+  ds[3] = k + 1;
 }
 
 // Cycle break: the unplaced block with the fewest unplaced predecessors,
@@ -108,8 +129,14 @@ __global__ void k_ord_argmin(int64_t nbr, const int32_t* __restrict__ indeg, con
   atomicMin(key, ((unsigned long long)(unsigned)indeg[R] << 32) | (unsigned long long)R);
 }
 
-__global__ void k_ord_place(int64_t pos, const unsigned long long* __restrict__ key, int32_t* __restrict__ ord) {
-  if (threadIdx.x == 0) ord[pos] = *key == ~0ull ? -1 : (int32_t)(*key & 0xffffffffull);
+// The chosen block forms the round ord[lo .. lo+1).
+__global__ void k_ord_place(int64_t nbr, const unsigned long long* __restrict__ key, int32_t* __restrict__ ord,
+                            unsigned long long* __restrict__ ds) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long lo = ds[0];
+  if (lo >= (unsigned long long)nbr) return;
+  ord[lo] = *key == ~0ull ? -1 : (int32_t)(*key & 0xffffffffull);
+  ds[1] = lo + 1;
 }
 
 // F rows of the blocks in order: counts, then the rows themselves.
@@ -175,56 +202,77 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
   double* w = nullptr;
   uint8_t* dir = nullptr;
   int32_t* indeg = nullptr;
-  unsigned* cnt = nullptr;
+  unsigned long long* ds = nullptr;   // [0..3] round state, [4] asymmetric-pattern flag
   unsigned long long* key = nullptr;
+  int64_t* dlp = nullptr;
   OK_(tmp.get(&w, nslot));
   OK_(tmp.get(&dir, nslot));
   OK_(tmp.get(&indeg, nbr));
-  OK_(tmp.get(&cnt, 4));
+  OK_(tmp.get(&ds, 5));
   OK_(tmp.get(&key, 1));
+  OK_(tmp.get(&dlp, nbr + 2));
   OK_(h->arena.get(&h->ord, nbr));
   OK_(h->arena.get(&h->ord_level, nbr));
-  HIP_(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned), st));
+  HIP_(hipMemsetAsync(ds, 0, 5 * sizeof(unsigned long long), st));
+  HIP_(hipMemsetAsync(dlp, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL(k_ord_weights, grid1(nbr), dim3(256), 0, st, nbr, B, L.optr, L.oval, w);
   hipLaunchKernelGGL(k_ord_orient, grid1(nbr), dim3(256), 0, st, nbr, h->prm.order_ratio, L.optr, L.ocol, w, dir,
-                     indeg, reinterpret_cast<int*>(cnt + 2));
-  hipLaunchKernelGGL(k_ord_init, grid1(nbr), dim3(256), 0, st, nbr, indeg, h->ord_level, h->ord, cnt);
+                     indeg, reinterpret_cast<int*>(ds + 4));
+  hipLaunchKernelGGL(k_ord_init, grid1(nbr), dim3(256), 0, st, nbr, indeg, h->ord_level, h->ord, ds);
   HIP_(hipGetLastError());
-  unsigned head[3] = {0, 0, 0};
-  OK_(read_bytes(cnt, head, sizeof(head), st));
-  if (head[2]) {
+  unsigned long long state[5] = {0, 0, 0, 0, 0};
+  OK_(read_bytes(ds, state, sizeof(state), st));
+  if (state[4]) {
     set_error("air_setup: the facet-block pattern is not structurally symmetric");
     tmp.release();
     return AH_EUNSUPPORTED;
   }
-  std::vector<int64_t>& lptr = h->ord_lptr;
-  lptr.assign(1, 0);
-  int64_t lo = 0, hi = head[0];
+  // rounds are queued in batches on the device state; the host looks at the
+  // state between batches and breaks a cycle when a round came out empty
+  // (32 rounds per batch; 2 right after a broken cycle, where more breaks
+  // tend to follow)
+  const dim3 rgrid((unsigned)std::min<int64_t>(cdiv(nbr, 256), 512));
   int breaks = 0;
-  for (int k = 0;; ++k) {
-    if (k > nbr || hi > nbr) {
+  int batch = 32;
+  int64_t batches = 0;
+  for (;;) {
+    for (int r = 0; r < batch; ++r) {
+      hipLaunchKernelGGL(k_ord_round, rgrid, dim3(256), 0, st, nbr, ds, L.optr, L.ocol, dir, indeg, h->ord_level,
+                         h->ord, ds + 2);
+      hipLaunchKernelGGL(k_ord_advance, dim3(1), dim3(64), 0, st, nbr, ds, dlp);
+    }
+    HIP_(hipGetLastError());
+    OK_(read_bytes(ds, state, 4 * sizeof(unsigned long long), st));
+    if (state[0] == state[1] && state[1] >= (unsigned long long)nbr) break;
+    batch = state[0] == state[1] ? 2 : 32;
+    // every batch either advances a round or ends in a cycle that is broken
+    if (++batches > 2 * nbr + 4) {
       set_error("air_setup: flow order did not terminate");
       tmp.release();
       return AH_EINVAL;
     }
-    if (hi == lo) {
+    if (state[0] == state[1]) {
       HIP_(hipMemsetAsync(key, 0xff, sizeof(unsigned long long), st));
       hipLaunchKernelGGL(k_ord_argmin, grid1(nbr), dim3(256), 0, st, nbr, indeg, h->ord_level, key);
-      hipLaunchKernelGGL(k_ord_place, dim3(1), dim3(64), 0, st, lo, key, h->ord);
+      hipLaunchKernelGGL(k_ord_place, dim3(1), dim3(64), 0, st, nbr, key, h->ord, ds);
       HIP_(hipGetLastError());
-      hi = lo + 1;
       ++breaks;
     }
-    lptr.push_back(hi);
-    HIP_(hipMemsetAsync(cnt + 1, 0, sizeof(unsigned), st));
-    hipLaunchKernelGGL(k_ord_round, grid1(hi - lo), dim3(256), 0, st, nbr, lo, hi - lo, k, L.optr, L.ocol, dir, indeg,
-                       h->ord_level, h->ord, cnt + 1);
-    HIP_(hipGetLastError());
-    if (hi == nbr) break;
-    unsigned next = 0;
-    OK_(read_bytes(cnt + 1, &next, sizeof(next), st));
-    lo = hi;
-    hi += next;
+  }
+  const int64_t rounds = (int64_t)state[3];
+  std::vector<int64_t>& lptr = h->ord_lptr;
+  lptr.assign(rounds + 1, 0);
+  {
+    double* pin = pinned_scratch((size_t)rounds + 1);
+    if (!pin) { set_error("pinned host allocation failed"); tmp.release(); return AH_ENOMEM; }
+    HIP_(hipMemcpyAsync(pin, dlp, (rounds + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_(hipStreamSynchronize(st));
+    std::memcpy(lptr.data(), pin, (rounds + 1) * sizeof(int64_t));
+  }
+  if (lptr.back() != nbr) {
+    set_error("air_setup: flow order lost blocks");
+    tmp.release();
+    return AH_EINVAL;
   }
   h->ord_breaks = breaks;
   OK_(h->arena.get(&h->ord_cols, nslot));
