@@ -114,6 +114,65 @@ def test_c2_full_slab_vs_oracle():
           flush=True)
 
 
+def test_c2_full_slab_ordered_relaxation():
+    """Ordered Gauss-Seidel (F points, then all points) on the full C2 slab:
+    the flow order bit for bit against the oracle's order of the same
+    matrix, the iteration count against the oracle's solve, the solution
+    to 1e-10 and the true residual."""
+    from paper_2010_11130_amd import Hierarchy
+    from workloads import slab_prism_tet_mesh
+    from workloads.problems import slab_hill
+    print("case C2 full slab, ordered relaxation", flush=True)
+    v, c = slab_prism_tet_mesh(64, 1.0 / 64)
+    prob = slab_hill(1e-4)
+    m, fv, bf, kinds = _mesh(v, c)
+    s = _system(m, v, fv, bf, kinds, prob, 2)
+    H = Hierarchy(s, relax=3)
+    lev, rounds, breaks = H.flow_levels()
+    x12, _ = H.solve(tol=1e-12)
+    x8, info8 = H.solve(tol=1e-8)
+    assert info8["converged"]
+    ex = s.export()
+    A0 = to_scipy(ex["rowptr"], ex["col"], ex["val"], s.n)
+    ref, rr, rb = oair.flow_levels(A0, 6)
+    assert np.array_equal(lev, ref) and (rounds, breaks) == (rr, rb)
+    o = setup_problem(v, c, prob, 2)
+    OH = oair.setup(o.Shat, relax="ordered_fa", block=o.b)
+    xo8, io8 = air_fgmres_solve(o, tol=1e-8, hier=OH)
+    assert abs(info8["iters"] - io8["iters"]) <= 1, (info8["iters"], io8["iters"])
+    xo12, _ = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert np.linalg.norm(x12.cpu().numpy() - xo12) <= 1e-10 * np.linalg.norm(xo12)
+    assert _true_residual(s, x8) <= 1e-8
+    print("levels %d, iterations %d (oracle %d)" % (rounds, info8["iters"], io8["iters"]), flush=True)
+
+
+def test_internal_layer_full_size_ordered_exact():
+    """The moving internal layer on the 48^3 Kuhn mesh (nu = 0), as the
+    benchmark runs it with the ordered relaxation: the flow order bit for
+    bit against the oracle's order of the same matrix, no broken cycle, and
+    the exact inversion of level 0 (Lemma 3.1): FGMRES stops after one
+    iteration with a true residual at rounding level."""
+    from paper_2010_11130_amd import Hierarchy
+    from workloads import kuhn_cube_mesh
+    from workloads.problems import MovingInternalLayer
+    print("case internal layer 48^3, ordered relaxation", flush=True)
+    v, c = kuhn_cube_mesh(48)
+    prob = MovingInternalLayer()
+    m, fv, bf, kinds = _mesh(v, c)
+    s = _system(m, v, fv, bf, kinds, prob, 1)
+    H = Hierarchy(s, relax=2)
+    lev, rounds, breaks = H.flow_levels()
+    x, info = H.solve(tol=1e-8)
+    assert breaks == 0
+    assert info["converged"] and info["iters"] == 1
+    assert _true_residual(s, x) <= 1e-10
+    ex = s.export()
+    A0 = to_scipy(ex["rowptr"], ex["col"], ex["val"], s.n)
+    ref, rr, rb = oair.flow_levels(A0, 3)
+    assert np.array_equal(lev, ref) and (rounds, breaks) == (rr, rb)
+    print("levels %d" % rounds, flush=True)
+
+
 @pytest.fixture(scope="module")
 def c3_mesh():
     from workloads import kuhn_cube_mesh
