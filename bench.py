@@ -53,6 +53,8 @@ def parse():
                     help="skip the march with distance-two lAIR neighbourhoods")
     ap.add_argument("--no-internal-layer", action="store_true",
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
+    ap.add_argument("--relax", type=int, default=0,
+                    help="with --solve-alone: relaxation (0 F,F,C Jacobi; 2, 3 ordered Gauss-Seidel)")
     ap.add_argument("--no-ordered", action="store_true",
                     help="skip the ordered Gauss-Seidel relaxations (internal layer, slab 0)")
     ap.add_argument("--builders", type=int, default=1,
@@ -411,21 +413,23 @@ def all_at_once(args, U_march_last):
             "bicgstab": {"value": sb.n / tb_, "ms": 1e3 * tb_, "steps": infob["iters"]}}
 
 
-def solve_alone(march, repeats, tol):
+def solve_alone(march, repeats, tol, precision=0, relax=0):
     """Slab 0 of the march assembled and set up once, then ``repeats``
-    FGMRES solves with nothing else on the GPU: the solve's kernels without
-    the builder's competition (per-kernel HIP-event averages included)."""
+    FGMRES solves (V-cycle in FP64, or FP32 with ``precision=1``) with nothing
+    else on the GPU: the solve's kernels without the builder's competition
+    (per-kernel HIP-event averages included); ``relax`` selects the
+    relaxation (2, 3: ordered Gauss-Seidel on level 0)."""
     import torch
     from paper_2010_11130_amd import System, Hierarchy, lib
     s = System(march.mesh, march.p, march.nu, march.a, None, march.g[0])
-    h = Hierarchy(s)
+    h = Hierarchy(s, fp32_cycle=1 if precision else 0, relax=relax)
     for _ in range(3):
-        h.solve(tol=tol)
+        h.solve(tol=tol, precision=precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     its = 0
     for _ in range(repeats):
-        _, info = h.solve(tol=tol)
+        _, info = h.solve(tol=tol, precision=precision)
         its += info["iters"]
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -433,10 +437,10 @@ def solve_alone(march, repeats, tol):
     lib().ah_profile_reset()
     lib().ah_profile_enable(1)
     for _ in range(repeats):
-        h.solve(tol=tol)
+        h.solve(tol=tol, precision=precision)
     torch.cuda.synchronize()
     lib().ah_profile_enable(0)
-    prof = profile_totals(PROFILE_TAGS)
+    prof = profile_totals(PROFILE_TAGS + ["gs0", "gs0_f"])
     lib().ah_profile_reset()
     return {"free_dofs": s.n, "repeats": repeats, "ms_per_solve": 1e3 * t / repeats,
             "us_per_iteration": 1e6 * t / its, "iters": its // repeats, "kernels": prof}
@@ -522,6 +526,8 @@ def ordered_slab(s, relax, tol, repeats=3):
         torch.cuda.synchronize()
         lib().ah_profile_enable(0)
         out["sweeps"] = profile_totals(["gs0", "gs0_f"])
+        for v in out["sweeps"].values():
+            v["us_per_level"] = v["avg_us"] / rounds
         lib().ah_profile_reset()
     return out
 
@@ -626,7 +632,7 @@ def main():
     march = March(args.n, args.slabs, args.p, args.nu)
     march.builders = args.builders
     if args.solve_alone:
-        print(json.dumps({"solve_alone": solve_alone(march, args.solve_alone, args.tol)}))
+        print(json.dumps({"solve_alone": solve_alone(march, args.solve_alone, args.tol, relax=args.relax)}))
         return
     seq = not args.no_sequential
     t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol, seq)
@@ -669,8 +675,17 @@ def main():
         _, extra32 = split(stages32, tseq32)
         err = (torch.linalg.norm(last32[0] - last64[0]) / torch.linalg.norm(last64[0])).item()
         out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
-                             "last_slab_rel_diff_vs_fp64": err, "kernels": prof32}
+                             "last_slab_rel_diff_vs_fp64": err, "kernels": prof32,
+                             "build_wait_ms_per_step": march.wait_ms_per_step}
         out["fp32_cycle"].update(extra32)
+        # the two cycle precisions with nothing else on the GPU (in the march
+        # the solve shares the GPU with the next slab's assembly and setup)
+        a64 = solve_alone(march, 10, args.tol, 0)
+        a32 = solve_alone(march, 10, args.tol, 1)
+        out["fp32_cycle"]["solve_alone"] = {
+            "fp64_ms_per_solve": a64["ms_per_solve"], "fp32_ms_per_solve": a32["ms_per_solve"],
+            "fp64_us_per_iteration": a64["us_per_iteration"], "fp32_us_per_iteration": a32["us_per_iteration"],
+            "iters": [a64["iters"], a32["iters"]], "speedup_vs_fp64": a64["ms_per_solve"] / a32["ms_per_solve"]}
     # the paper's Krylov method: BiCGSTAB steps (two V-cycles each), same march
     if not args.no_bicgstab:
         march.step(0, args.tol, method=1)
