@@ -55,6 +55,8 @@ def parse():
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--relax", type=int, default=0,
                     help="with --solve-alone: relaxation (0 F,F,C Jacobi; 2, 3 ordered Gauss-Seidel)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint solve and gradients on slab 0")
     ap.add_argument("--no-ordered", action="store_true",
                     help="skip the ordered Gauss-Seidel relaxations (internal layer, slab 0)")
     ap.add_argument("--builders", type=int, default=1,
@@ -497,6 +499,43 @@ def internal_layer(n=48, p=1, tol=1e-8, air=None):
     return out
 
 
+def adjoint_slab(march, tol, repeats=3):
+    """The differentiation form on slab 0 of the march: lAIR setup with the
+    transposed operators, the forward FGMRES solve, the adjoint solve
+    S^T lam = dJ/dLambda of the misfit J = |Lambda|^2 / 2 with the transposed
+    cycle, and the gradients dJ/df (at the element quadrature points) and
+    dJ/dnu; FP64 and FP32 cycles."""
+    import torch
+    from paper_2010_11130_amd import System, Hierarchy
+    s = System(march.mesh, march.p, march.nu, march.a, None, march.g[0])
+    out = {"free_dofs": s.n}
+    for prec in (0, 1):
+        Hierarchy(s, adjoint=1, fp32_cycle=prec).solve(tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = Hierarchy(s, adjoint=1, fp32_cycle=prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tf = ta = tg = 0.0
+        for _ in range(repeats):
+            ta0 = time.perf_counter()
+            x, fi = h.solve(tol=tol, precision=prec)
+            torch.cuda.synchronize()
+            ta1 = time.perf_counter()
+            lam, ai = h.solve_adjoint(x, tol=tol, precision=prec)
+            torch.cuda.synchronize()
+            ta2 = time.perf_counter()
+            s.grad(x, lam)
+            torch.cuda.synchronize()
+            ta3 = time.perf_counter()
+            tf, ta, tg = tf + ta1 - ta0, ta + ta2 - ta1, tg + ta3 - ta2
+        out["fp64" if prec == 0 else "fp32_cycle"] = {
+            "setup_ms": 1e3 * (t1 - t0), "forward_ms": 1e3 * tf / repeats, "adjoint_ms": 1e3 * ta / repeats,
+            "gradient_ms": 1e3 * tg / repeats, "forward_iters": fi["iters"], "adjoint_iters": ai["iters"],
+            "adjoint_converged": ai["converged"]}
+    return out
+
+
 def ordered_slab(s, relax, tol, repeats=3):
     """lAIR setup and FGMRES solves of one assembled slab with the given
     relaxation (0: F,F,C Jacobi; 2, 3: ordered Gauss-Seidel on level 0),
@@ -728,6 +767,8 @@ def main():
         out["internal_layer"] = internal_layer(tol=args.tol)
     if not args.no_ordered:
         out["ordered_relaxation"] = ordered_relaxation(args, march)
+    if not args.no_adjoint:
+        out["adjoint_slab0"] = adjoint_slab(march, args.tol)
     # dominant tagged kernel of the FP64 march
     if prof64:
         out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])

@@ -932,6 +932,31 @@ static inline dim3 grows(int64_t n) {
   return dim3((unsigned)std::min<int64_t>(cdiv(std::max<int64_t>(n, 1), 256 / PG), 2048));
 }
 
+// Transposed level-0 operator in the facet-block layout: block row I, slot
+// s (column block J) receives the transpose of block (J, I), found in the
+// slots of block row J; a slot without a transposed slot sets *bad.
+__global__ void k_fb_transpose(int64_t nbr, int B, const int64_t* __restrict__ optr,
+                               const int32_t* __restrict__ ocol, const double* __restrict__ ov,
+                               double* __restrict__ otv, int* __restrict__ bad) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nbr) return;
+  const int64_t oi = optr[I];
+  const int64_t leni = (optr[I + 1] - oi) * B;
+  for (int64_t s = oi; s < optr[I + 1]; ++s) {
+    const int32_t J = ocol[s];
+    const int64_t oj = optr[J];
+    int64_t t = -1;
+    for (int64_t q = oj; q < optr[J + 1]; ++q)
+      if (ocol[q] == (int32_t)I) { t = q; break; }
+    if (t < 0) { *bad = 1; continue; }
+    const int64_t lenj = (optr[J + 1] - oj) * B;
+    const double* __restrict__ src = ov + oj * B * B + (t - oj) * B;
+    double* __restrict__ dst = otv + oi * B * B + (s - oi) * B;
+    for (int m = 0; m < B; ++m)
+      for (int c = 0; c < B; ++c) dst[m * leni + c] = src[c * lenj + m];
+  }
+}
+
 static ah_status transpose(int64_t nrow, int64_t ncol, const int64_t* rp, const int32_t* ci, const double* v,
                            int64_t nnz, Arena& ar, Arena& tmp, hipStream_t st, int64_t** tp, int32_t** tc,
                            double** tv) {
@@ -1093,6 +1118,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     L0.oval = s->d_odv;
   }
   h->lev.push_back(L0);
+  // the tail never holds level 0 when it has more rows than this
+  int64_t tail_max = 4096;
+  if (const char* e = std::getenv("AH_TAIL_MAX")) tail_max = std::atoll(e);
+  // adjoint: level 0 of a scaled system gets its transpose in the
+  // facet-block layout, and no CSR transpose unless the ordered sweeps or the
+  // tail need it
+  bool at0_csr = true;
   for (int l = 0;; ++l) {
     AhLevel& L = h->lev[l];
     const int64_t n = L.n;
@@ -1282,8 +1314,29 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       hipLaunchKernelGGL(k_cast32, g1(L.nnzR), dim3(256), 0, st, L.nnzR, L.Rval, L.Rval32);
       CKH(hipGetLastError());
     }
+    if (prm.adjoint && l == 0 && L.ob && prm.relax < 2 && n > tail_max) {
+      const int64_t nbr = n / L.ob;
+      CK(ar.get(&L.otval, L.nov));
+      CKH(hipMemsetAsync(d_int + 2, 0, sizeof(int), st));
+      hipLaunchKernelGGL(k_fb_transpose, g1(nbr), dim3(256), 0, st, nbr, L.ob, L.optr, L.ocol, L.oval, L.otval,
+                         d_int + 2);
+      CKH(hipGetLastError());
+      int bad = 0;
+      CK(read_bytes(d_int + 2, &bad, sizeof(int), st));
+      if (bad) {
+        L.otval = nullptr;
+      } else {
+        at0_csr = false;
+        if (prm.fp32_cycle) {
+          CK(ar.get(&L.otval32, L.nov));
+          hipLaunchKernelGGL(k_cast32, g1(L.nov), dim3(256), 0, st, L.nov, L.otval, L.otval32);
+          CKH(hipGetLastError());
+        }
+      }
+    }
     if (prm.adjoint) {
-      CK(transpose(n, n, L.rowptr, L.col, L.val, L.nnz, ar, tmp, st, &L.ATptr, &L.ATcol, &L.ATval));
+      if (l > 0 || at0_csr)
+        CK(transpose(n, n, L.rowptr, L.col, L.val, L.nnz, ar, tmp, st, &L.ATptr, &L.ATcol, &L.ATval));
       CK(transpose(nc, n, L.Rptr, L.Rcol, L.Rval, L.nnzR, ar, tmp, st, &L.RTptr, &L.RTcol, &L.RTval));
       int32_t* pc = nullptr;
       int64_t* pp = nullptr;
@@ -1300,9 +1353,11 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       CKH(hipGetLastError());
       CK(transpose(n, nc, pp, pcc, nullptr, nnzp, ar, tmp, st, &L.PTptr, &L.PTcol, nullptr));
       if (prm.fp32_cycle) {
-        CK(ar.get(&L.ATval32, L.nnz));
+        if (L.ATval) {
+          CK(ar.get(&L.ATval32, L.nnz));
+          hipLaunchKernelGGL(k_cast32, g1(L.nnz), dim3(256), 0, st, L.nnz, L.ATval, L.ATval32);
+        }
         CK(ar.get(&L.RTval32, L.nnzR));
-        hipLaunchKernelGGL(k_cast32, g1(L.nnz), dim3(256), 0, st, L.nnz, L.ATval, L.ATval32);
         hipLaunchKernelGGL(k_cast32, g1(L.nnzR), dim3(256), 0, st, L.nnzR, L.RTval, L.RTval32);
         CKH(hipGetLastError());
       }
@@ -1333,7 +1388,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
     CKH(hipGetLastError());
   }
-  if (prm.adjoint && !h->lev[0].ATptr) {
+  if (prm.adjoint && !h->lev[0].ATptr && !h->lev[0].otval) {
     // level 0 is the coarsest: the adjoint FGMRES still needs S_hat^T
     AhLevel& A0 = h->lev[0];
     CK(transpose(A0.n, A0.n, A0.rowptr, A0.col, A0.val, A0.nnz, ar, tmp, st, &A0.ATptr, &A0.ATcol, &A0.ATval));
@@ -1380,8 +1435,6 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   // tail: the levels from the first one with at most tail_max rows are run
   // by one workgroup inside a single launch per cycle
   {
-    int64_t tail_max = 4096;
-    if (const char* e = std::getenv("AH_TAIL_MAX")) tail_max = std::atoll(e);
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
     if (h->g0 != 2 && h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();

@@ -585,6 +585,20 @@ __global__ void k_interp2(int64_t n, const int32_t* __restrict__ pcol, const T* 
   y[i] = v;
 }
 
+// First Jacobi sweep of the transposed cycle from y = 0 on the points of
+// set X (cf == X): y_X = omega g_X / d_X, zero elsewhere, into both buffers.
+template <class T>
+__global__ void k_sweep_from_zero(int64_t n, const int8_t* __restrict__ cf, int X, const T* __restrict__ g,
+                                  const T* __restrict__ d, T omega, T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T v = cf[i] == X && fabs((double)d[i]) >= 1e-30 ? omega * g[i] / d[i] : (T)0;
+  x[i] = v;
+  y[i] = v;
+}
+
+static inline int64_t nF0(const AhLevel& L) { return L.n - L.nc; }
+
 // z = C^-1 r (trans = 0) or C^-T r, FP64 coarsest solve; one wave per row.
 template <class T>
 __global__ __launch_bounds__(64) void k_coarse(int n, const double* __restrict__ Ci, const T* __restrict__ r,
@@ -876,6 +890,7 @@ struct Ops<double> {
   static const double* RT(const AhLevel& L) { return L.RTval; }
   static const double* d(const AhLevel& L) { return L.diag; }
   static const double* O(const AhLevel& L) { return L.oval; }
+  static const double* OT(const AhLevel& L) { return L.otval; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -889,6 +904,7 @@ struct Ops<float> {
   static const float* RT(const AhLevel& L) { return L.RTval32; }
   static const float* d(const AhLevel& L) { return L.diag32; }
   static const float* O(const AhLevel& L) { return L.oval32; }
+  static const float* OT(const AhLevel& L) { return L.otval32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -1123,7 +1139,8 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
   const T om = (T)h->prm.omega;
   T* cur = Ops<T>::x(L);
   T* alt = Ops<T>::y(L);
-  AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
+  const bool fbt = l == 0 && h->prm.relax < 2 && Ops<T>::OT(L);
+  if (!fbt) AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
   if (l == 0 && h->prm.relax >= 2) {
     // transposed ordered sweeps: all points, then (relax 3) F points
     AH_HIP(hipMemsetAsync(alt, 0, L.n * sizeof(T), st));
@@ -1134,6 +1151,31 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
       AH_TRY(gs_csr_sweep_t<T>(h, true, Ops<T>::AT(L), Ops<T>::d(L), g, cur, alt, st));
       std::swap(cur, alt);
     }
+  } else if (fbt) {
+    // A_0^T by facet blocks: the first sweep (C points, or the F points
+    // with one sweep) starts from zero, y_X = omega g_X / d_X, written to
+    // both buffers; the F sweeps then alternate over the F list
+    const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
+    const int X = h->prm.relax == 1 ? 0 : 1;
+    hipLaunchKernelGGL((k_sweep_from_zero<T>), g1(L.n), dim3(256), 0, st, L.n, L.cf, X, g, Ops<T>::d(L), om, cur,
+                       alt);
+    AH_LAUNCHED();
+    if (h->prm.relax != 1) {
+      AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF0(L), L.optr, L.ocol, Ops<T>::OT(L), cur, g, om, alt, st,
+                                           nullptr, 0.0, L.flist)));
+      AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF0(L), L.optr, L.ocol, Ops<T>::OT(L), alt, g, om, cur, st,
+                                           nullptr, 0.0, L.flist)));
+    }
+    // residual g - A^T y, restricted by P^T
+    AH_TRY((fb_g<T, T, T, SP_RES>(L.ob, Gb, L.n, L.optr, L.ocol, Ops<T>::OT(L), cur, g, (T)0, alt, st)));
+    AH_TRY((csr_g<T, T, T, SP_MV>(4, L.nc, L.PTptr, L.PTcol, (const T*)nullptr, alt, (const T*)nullptr,
+                                  (const T*)nullptr, (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
+    T* ec = (l + 1 == nlev - 1) ? Ops<T>::x(C) : Ops<T>::b(C);
+    AH_TRY(vcycle_t<T>(h, l + 1, Ops<T>::b(C), ec, st));
+    const int GR = pick_g(L.nnzR, L.n);
+    AH_TRY((csr_g<T, T, T, SP_ADDMV>(GR, L.n, L.RTptr, L.RTcol, Ops<T>::RT(L), ec, cur, (const T*)nullptr,
+                                     (const int8_t*)nullptr, 0, (T)0, out, st)));
+    return AH_OK;
   } else {
     const int sets[3] = {1, 0, 0};   // C, F, F
     const int nsw = h->prm.relax == 1 ? 1 : 3;
@@ -1661,12 +1703,19 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
   AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st));
   double* mu = h->bhat;   // S_hat^T mu = g, then lam = D_b^-T mu
   AhLevel& L0 = h->lev[0];
-  if (!L0.ATptr) {
+  if (!L0.ATptr && !L0.otval) {
     set_error("air_solve_adjoint: transposed level-0 operator missing");
     return AH_EINVAL;
   }
   AH_HIP(hipMemsetAsync(mu, 0, n * sizeof(double), st));   // zero initial guess
   Op AT{L0.ATptr, L0.ATcol, L0.ATval};
+  if (L0.otval) {
+    AT.ob = L0.ob;
+    AT.optr = L0.optr;
+    AT.ocol = L0.ocol;
+    AT.ov = L0.otval;
+    AT.nov = L0.nov;
+  }
   ah_status rc = prm->method == 1 ? bicgstab(h, AT, g, mu, *prm, 1, st, info) : fgmres(h, AT, g, mu, *prm, 1, st, info);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, mu, lam, 1);

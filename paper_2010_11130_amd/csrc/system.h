@@ -85,6 +85,10 @@ struct AhLevel {
   const int32_t* ocol = nullptr;
   const double* oval = nullptr;
   float* oval32 = nullptr;
+  // the transposed operator in the same layout (adjoint cycle): block (I, J)
+  // holds the transpose of block (J, I); null where the CSR A^T is used
+  double* otval = nullptr;
+  float* otval32 = nullptr;
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;
