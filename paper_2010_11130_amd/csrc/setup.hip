@@ -1200,17 +1200,23 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     hipLaunchKernelGGL(k_cf_flags, g1(n), dim3(256), 0, st, n, state, L.cf, isc);
     CKH(hipGetLastError());
     CK(scan_i32_to_i64(isc, cidx, n, st, tmp));
+    const bool d2 = prm.lair_distance == 2;
     int64_t nc = 0;
-    CK(read_i64(cidx + n, &nc, st));
-    if (nc == 0 || (double)nc > prm.stall * (double)n) break;
-    L.nc = nc;
+    // distance one: the point lists and R's row counts are sized for n, and
+    // the C-point count is read back together with R's size (one host sync
+    // per level instead of two); distance two needs it for its launches
+    if (d2) {
+      CK(read_i64(cidx + n, &nc, st));
+      if (nc == 0 || (double)nc > prm.stall * (double)n) break;
+    }
+    const int64_t ncap = d2 ? nc : n;
     // one-point P, lAIR row lengths, R A P candidate bound, F-row statistics
     int32_t *rcnt = nullptr, *clist = nullptr;
     CK(ar.get(&L.pcol, n));
-    CK(tmp.get(&rcnt, nc + 1));
-    CK(ar.get(&clist, nc));
-    CK(ar.get(&L.flist, n - nc));
-    L.clist = clist;
+    CK(tmp.get(&rcnt, ncap + 1));
+    CK(ar.get(&clist, ncap));
+    CK(ar.get(&L.flist, n - (d2 ? nc : 0)));
+    if (!d2) CKH(hipMemsetAsync(rcnt, 0, (n + 1) * sizeof(int32_t), st));
     CKH(hipMemsetAsync(d_int, 0, 4 * sizeof(int), st));
     // strength of the restriction neighbourhoods (theta_r; the same mask
     // when it equals theta)
@@ -1227,7 +1233,6 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, strong_r, L.cf,
                        cidx, L.pcol, rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
-    const bool d2 = prm.lair_distance == 2;
     if (d2) {
       // distance-two neighbourhoods: R row lengths, |N_i| and the R A P bound
       int32_t *mcnt = nullptr, *c2 = nullptr;
@@ -1242,21 +1247,33 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       hipLaunchKernelGGL(k_max_i32, gm, dim3(256), 0, st, nc, c2, d_int + 1);
       CKH(hipGetLastError());
     }
-    if (L.ob) {
-      hipLaunchKernelGGL(k_list_vals, grows(n - nc), dim3(256), 0, st, n - nc, L.flist, L.optr, L.ob, d_fst + 64);
-      CKH(hipGetLastError());
-    }
-    CK(ar.get(&L.Rptr, nc + 1));
-    CK(scan_i32_to_i64(rcnt, L.Rptr, nc, st, tmp));
+    CK(ar.get(&L.Rptr, ncap + 1));
+    CK(scan_i32_to_i64(rcnt, L.Rptr, ncap, st, tmp));
     int hmax[4];
     {
-      double* pin = pinned_scratch(4);
+      double* pin = pinned_scratch(6);
       if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
-      CKH(hipMemcpyAsync(pin, L.Rptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(pin, L.Rptr + ncap, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       CKH(hipMemcpyAsync(pin + 1, d_int, sizeof(hmax), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(pin + 3, cidx + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       CKH(hipStreamSynchronize(st));
       std::memcpy(&L.nnzR, pin, sizeof(int64_t));
       std::memcpy(hmax, pin + 1, sizeof(hmax));
+      std::memcpy(&nc, pin + 3, sizeof(int64_t));
+    }
+    if (!d2 && (nc == 0 || (double)nc > prm.stall * (double)n)) {
+      // coarsening stalled: this level is the coarsest
+      L.pcol = nullptr;
+      L.flist = nullptr;
+      L.Rptr = nullptr;
+      L.nnzR = 0;
+      break;
+    }
+    L.nc = nc;
+    L.clist = clist;
+    if (L.ob) {
+      hipLaunchKernelGGL(k_list_vals, grows(n - nc), dim3(256), 0, st, n - nc, L.flist, L.optr, L.ob, d_fst + 64);
+      CKH(hipGetLastError());
     }
     CK(ar.get(&L.Rcol, L.nnzR));
     CK(ar.get(&L.Rval, L.nnzR));
@@ -1362,7 +1379,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
         CKH(hipGetLastError());
       }
     }
-    CKH(hipStreamSynchronize(st));
+    // (the temporary buffers go back to the pool in stream order)
     tmp.release();
     h->lev.push_back(C);
   }
