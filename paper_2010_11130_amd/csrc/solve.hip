@@ -1140,8 +1140,8 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
   T* cur = Ops<T>::x(L);
   T* alt = Ops<T>::y(L);
   const bool fbt = l == 0 && h->prm.relax < 2 && Ops<T>::OT(L);
-  if (!fbt) AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
   if (l == 0 && h->prm.relax >= 2) {
+    AH_HIP(hipMemsetAsync(cur, 0, L.n * sizeof(T), st));
     // transposed ordered sweeps: all points, then (relax 3) F points
     AH_HIP(hipMemsetAsync(alt, 0, L.n * sizeof(T), st));
     AH_TRY(gs_csr_sweep_t<T>(h, false, Ops<T>::AT(L), Ops<T>::d(L), g, cur, alt, st));
@@ -1177,12 +1177,18 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
                                      (const int8_t*)nullptr, 0, (T)0, out, st)));
     return AH_OK;
   } else {
-    const int sets[3] = {1, 0, 0};   // C, F, F
-    const int nsw = h->prm.relax == 1 ? 1 : 3;
-    for (int s = 3 - nsw; s < 3; ++s) {
-      AH_TRY((csr_g<T, T, T, SP_SWEEP>(G, L.n, L.ATptr, L.ATcol, Ops<T>::AT(L), cur, g, Ops<T>::d(L), L.cf, sets[s],
-                                       om, alt, st)));
-      std::swap(cur, alt);
+    // the first sweep (C points, or the F points with one sweep) starts from
+    // zero, y_X = omega g_X / d_X, written to both buffers; the F sweeps then
+    // alternate over the F list
+    const int X = h->prm.relax == 1 ? 0 : 1;
+    hipLaunchKernelGGL((k_sweep_from_zero<T>), g1(L.n), dim3(256), 0, st, L.n, L.cf, X, g, Ops<T>::d(L), om, cur,
+                       alt);
+    AH_LAUNCHED();
+    if (h->prm.relax != 1) {
+      AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF0(L), L.ATptr, L.ATcol, Ops<T>::AT(L), cur, g, Ops<T>::d(L), L.cf, 0,
+                                            om, alt, st, nullptr, 0.0, L.flist)));
+      AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF0(L), L.ATptr, L.ATcol, Ops<T>::AT(L), alt, g, Ops<T>::d(L), L.cf, 0,
+                                            om, cur, st, nullptr, 0.0, L.flist)));
     }
   }
   // residual g - A^T y, restricted by P^T
