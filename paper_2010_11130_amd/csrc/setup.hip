@@ -1369,6 +1369,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       hipLaunchKernelGGL(k_p_fill, g1(n), dim3(256), 0, st, n, L.pcol, pp, pcc);
       CKH(hipGetLastError());
       CK(transpose(n, nc, pp, pcc, nullptr, nnzp, ar, tmp, st, &L.PTptr, &L.PTcol, nullptr));
+      L.nnzP = nnzp;
       if (prm.fp32_cycle) {
         if (L.ATval) {
           CK(ar.get(&L.ATval32, L.nnz));
@@ -1460,7 +1461,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       const AhLevel& L = h->lev[l];
       TailLevel& T = tl[l];
       T = TailLevel{};
-      T.n = L.n; T.nc = L.nc; T.nnz = L.nnz; T.nnzR = L.nnzR;
+      T.n = L.n; T.nc = L.nc; T.nnz = L.nnz; T.nnzR = L.nnzR; T.nnzP = L.nnzP;
       T.rp = L.rowptr; T.ci = L.col; T.v = L.val; T.v32 = L.val32; T.d = L.diag; T.d32 = L.diag32;
       T.cf = L.cf; T.pcol = L.pcol;
       T.Rp = L.Rptr; T.Rc = L.Rcol; T.Rv = L.Rval; T.Rv32 = L.Rval32;
@@ -1488,6 +1489,17 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
           h->tail_bytes[1] = tail_lds_layout<4>(tl.data(), l, nl, lo, &oc);
           break;
         }
+      }
+    }
+    // the adjoint's transposed tail from an LDS image of the same levels
+    if (prm.adjoint && h->tail0 >= 0 && nl <= TAIL_MAX_LEVELS) {
+      TailLdsT lt_[TAIL_MAX_LEVELS];
+      int64_t oc = 0;
+      const int64_t b64 = tail_lds_layout_t<8>(tl.data(), h->tail0, nl, lt_, &oc);
+      if (b64 <= TAIL_LDS_MAX) {
+        h->tail_lds_t = true;
+        h->tail_bytes_t[0] = b64;
+        h->tail_bytes_t[1] = tail_lds_layout_t<4>(tl.data(), h->tail0, nl, lt_, &oc);
       }
     }
     if (h->tail0 < 0)   // no LDS image fits: small levels run from global memory

@@ -465,6 +465,192 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const TailLevel* __restrict__
 #undef TL_PTR
 }
 
+// The transposed tail's LDS image in global memory (layout of
+// tail_lds_layout_t): A^T, the diagonal, C/F flags, P^T and R^T of every
+// tail level but the coarsest, then the coarsest inverse.
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail_image_t(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                                       const double* __restrict__ cinv, char* __restrict__ img) {
+  __shared__ TailLdsT lo[TAIL_MAX_LEVELS];
+  __shared__ int64_t s_cinv;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  const int last = nlev - 1;
+  if (t == 0) {
+    int64_t oc = 0;
+    tail_lds_layout_t<(int)sizeof(T)>(lv, l0, nlev, lo, &oc);
+    s_cinv = oc;
+  }
+  __syncthreads();
+#define TI_PTR(type, l, f) reinterpret_cast<type*>(img + lo[(l) - l0].f)
+  for (int l = l0; l < last; ++l) {
+    const TailLevel& L = lv[l];
+    const int n = (int)L.n, nc = (int)L.nc, nnz = (int)L.nnz, nnzR = (int)L.nnzR, nnzP = (int)L.nnzP;
+    tail_stage(TI_PTR(int32_t, l, ATp), L.ATp, n + 1, t, NT);
+    tail_stage(TI_PTR(int32_t, l, ATc), L.ATc, nnz, t, NT);
+    tail_stage(TI_PTR(T, l, ATv), TLv<T>::AT(L), nnz, t, NT);
+    tail_stage(TI_PTR(T, l, d), TLv<T>::d(L), n, t, NT);
+    tail_stage(TI_PTR(int8_t, l, cf), L.cf, n, t, NT);
+    tail_stage(TI_PTR(int32_t, l, PTp), L.PTp, nc + 1, t, NT);
+    tail_stage(TI_PTR(int32_t, l, PTc), L.PTc, nnzP, t, NT);
+    tail_stage(TI_PTR(int32_t, l, RTp), L.RTp, n + 1, t, NT);
+    tail_stage(TI_PTR(int32_t, l, RTc), L.RTc, nnzR, t, NT);
+    tail_stage(TI_PTR(T, l, RTv), TLv<T>::RT(L), nnzR, t, NT);
+  }
+#undef TI_PTR
+  const int nL = (int)lv[last].n;
+  tail_stage(reinterpret_cast<double*>(img + s_cinv), cinv, nL * nL, t, NT);
+}
+
+// Transposed coarse end of the cycle (adjoint) from an LDS image: on each
+// level the first sweep from zero (C points; F points with one sweep), the
+// F sweeps with A^T, the residual restricted by P^T; the transposed
+// coarsest solve; then on the way up y + R^T e_c.  The result of level l0
+// is written to out.
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail_lds_t(const TailLevel* __restrict__ lv, int l0, int nlev,
+                                                     const char* __restrict__ img, const T* __restrict__ g_in,
+                                                     T* __restrict__ out, int nsw, T omega) {
+  extern __shared__ __align__(16) char sm[];
+  __shared__ TailLdsT lo[TAIL_MAX_LEVELS];
+  __shared__ int64_t s_cinv, s_bytes;
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  const int last = nlev - 1;
+  if (t == 0) {
+    int64_t oc = 0;
+    s_bytes = tail_lds_layout_t<(int)sizeof(T)>(lv, l0, nlev, lo, &oc);
+    s_cinv = oc;
+  }
+  __syncthreads();
+#define TL_PTR(type, l, f) reinterpret_cast<type*>(sm + lo[(l) - l0].f)
+  {
+    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(img);
+    uint4* dst = reinterpret_cast<uint4*>(sm);
+    const int c1 = (int)(s_bytes >> 4);
+    int c = (int)(lo[0].x >> 4) + t;
+    for (; c + 7 * NT < c1; c += 8 * NT) {
+      uint4 a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = src[c + q * NT];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dst[c + q * NT] = a[q];
+    }
+    for (; c < c1; c += NT) dst[c] = src[c];
+    tail_stage(TL_PTR(T, l0, g), g_in, (int)lv[l0].n, t, NT);
+  }
+  const int nL = (int)lv[last].n;
+  const double* ci_s = reinterpret_cast<const double*>(sm + s_cinv);
+  __syncthreads();
+  for (int l = l0; l < last; ++l) {
+    const int n = (int)lv[l].n, nc = (int)lv[l].nc;
+    const int32_t* rp = TL_PTR(int32_t, l, ATp);
+    const int32_t* ci = TL_PTR(int32_t, l, ATc);
+    const T* v = TL_PTR(T, l, ATv);
+    const T* d = TL_PTR(T, l, d);
+    const int8_t* cf = TL_PTR(int8_t, l, cf);
+    const T* g = TL_PTR(T, l, g);
+    T* x = TL_PTR(T, l, x);
+    T* y = TL_PTR(T, l, y);
+    const int X0 = nsw == 1 ? 0 : 1;
+    for (int i = t; i < n; i += NT) {
+      const T di = d[i];
+      x[i] = (cf[i] == X0 && fabs((double)di) >= 1e-30) ? omega * g[i] / di : (T)0;
+    }
+    __syncthreads();
+    const int gA = tail_lanes(n, n ? (int)(lv[l].nnz / n) : 1, NT);
+    // F sweeps x -> y -> x
+    for (int s = 1; s < nsw; ++s) {
+      const T* cur = (s == 1) ? x : y;
+      T* dst = (s == 1) ? y : x;
+      tail_with_lanes(gA, [&](auto GC) {
+        constexpr int G = decltype(GC)::value;
+        const int gl = t % G;
+        for (int i = t / G; i < n; i += NT / G) {
+          T yi = cur[i];
+          if (cf[i] == 0) {
+            const T di = d[i];
+            const T r = tail_row<G, T, T>(rp, ci, v, cur, i, gl);
+            if (fabs((double)di) >= 1e-30) yi += omega * (g[i] - r) / di;
+          }
+          if (gl == 0) dst[i] = yi;
+        }
+      });
+      __syncthreads();
+    }
+    // residual into y, restricted by P^T into the next level's g
+    tail_with_lanes(gA, [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int gl = t % G;
+      for (int i = t / G; i < n; i += NT / G) {
+        const T r = tail_row<G, T, T>(rp, ci, v, x, i, gl);
+        if (gl == 0) y[i] = g[i] - r;
+      }
+    });
+    __syncthreads();
+    const int32_t* pp = TL_PTR(int32_t, l, PTp);
+    const int32_t* pc = TL_PTR(int32_t, l, PTc);
+    T* cg = TL_PTR(T, l + 1, g);
+    const int gP = tail_lanes(nc, nc ? (int)(lv[l].nnzP / nc) : 1, NT);
+    tail_with_lanes(gP, [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int gl = t % G;
+      for (int c = t / G; c < nc; c += NT / G) {
+        T s = 0;
+        for (int k = pp[c] + gl; k < pp[c + 1]; k += G) s += y[pc[k]];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (gl == 0) cg[c] = s;
+      }
+    });
+    __syncthreads();
+  }
+  // coarsest: e = C^-T g (FP64 accumulation), into the coarsest x (or out)
+  {
+    const T* g = TL_PTR(T, last, g);
+    T* e = TL_PTR(T, last, x);
+    tail_with_lanes(tail_lanes(nL, nL, NT), [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int gl = t % G;
+      for (int i = t / G; i < nL; i += NT / G) {
+        double s = 0.0;
+        for (int j = gl; j < nL; j += G) s += ci_s[j * nL + i] * (double)g[j];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (gl == 0) {
+          if (l0 == last) out[i] = (T)s;
+          else e[i] = (T)s;
+        }
+      }
+    });
+    __syncthreads();
+  }
+  // up: out_l = y_l + R^T e_c (y_l is in x), into the level's g (out at l0)
+  for (int l = last - 1; l >= l0; --l) {
+    const int n = (int)lv[l].n;
+    const T* ec = (l + 1 == last) ? TL_PTR(T, last, x) : TL_PTR(T, l + 1, g);
+    const int32_t* rp = TL_PTR(int32_t, l, RTp);
+    const int32_t* ci = TL_PTR(int32_t, l, RTc);
+    const T* v = TL_PTR(T, l, RTv);
+    const T* yl = TL_PTR(T, l, x);
+    T* gl_out = TL_PTR(T, l, g);
+    const int gR = tail_lanes(n, n ? (int)(lv[l].nnzR / n) : 1, NT);
+    tail_with_lanes(gR, [&](auto GC) {
+      constexpr int G = decltype(GC)::value;
+      const int gl = t % G;
+      for (int i = t / G; i < n; i += NT / G) {
+        const T r = tail_row<G, T, T>(rp, ci, v, ec, i, gl);
+        if (gl == 0) {
+          if (l == l0) out[i] = yl[i] + r;
+          else gl_out[i] = yl[i] + r;
+        }
+      }
+    });
+    __syncthreads();
+  }
+#undef TL_PTR
+}
+
 template <class T, bool TR>
 __global__ __launch_bounds__(1024) void k_tail(const TailLevel* __restrict__ lv, int l0, int nlev,
                                                const double* __restrict__ cinv, const T* b_in, T* out, int nsw,
@@ -876,6 +1062,21 @@ ah_status tail_image_build(ah_hier* h, hipStream_t st) {
     AH_LAUNCHED();
     h->tail_img[w] = reinterpret_cast<const char*>(img);
   }
+  if (h->tail_lds_t) {
+    for (int w = 0; w < 2; ++w) {
+      if (w == 1 && !h->prm.fp32_cycle) break;
+      double* img = nullptr;
+      AH_TRY(h->arena.get(&img, (h->tail_bytes_t[w] + 15) / 8 + 2));
+      if (w == 0)
+        hipLaunchKernelGGL(k_tail_image_t<double>, dim3(1), dim3(1024), 0, st, h->d_tail, h->tail0, nlev, h->cinv,
+                           reinterpret_cast<char*>(img));
+      else
+        hipLaunchKernelGGL(k_tail_image_t<float>, dim3(1), dim3(1024), 0, st, h->d_tail, h->tail0, nlev, h->cinv,
+                           reinterpret_cast<char*>(img));
+      AH_LAUNCHED();
+      h->tail_img_t[w] = reinterpret_cast<const char*>(img);
+    }
+  }
   return AH_OK;
 }
 
@@ -1123,8 +1324,22 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
   AhLevel& L = h->lev[l];
   const int nlev = (int)h->lev.size();
   if (h->tail0 >= 0 && l >= h->tail0) {
-    hipLaunchKernelGGL((k_tail<T, true>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, g, out,
-                       h->prm.relax == 1 ? 1 : 3, (T)h->prm.omega);
+    if (h->tail_lds_t && l == h->tail0) {
+      static std::once_flag once;
+      std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)k_tail_lds_t<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)TAIL_LDS_MAX);
+        (void)hipFuncSetAttribute((const void*)k_tail_lds_t<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)TAIL_LDS_MAX);
+      });
+      const int64_t bytes = h->tail_bytes_t[sizeof(T) == 8 ? 0 : 1];
+      hipLaunchKernelGGL((k_tail_lds_t<T>), dim3(1), dim3(1024), (unsigned)bytes, st, h->d_tail, l, nlev,
+                         h->tail_img_t[sizeof(T) == 8 ? 0 : 1], g, out, h->prm.relax == 1 ? 1 : 3,
+                         (T)h->prm.omega);
+    } else {
+      hipLaunchKernelGGL((k_tail<T, true>), dim3(1), dim3(1024), 0, st, h->d_tail, l, nlev, h->cinv, g, out,
+                         h->prm.relax == 1 ? 1 : 3, (T)h->prm.omega);
+    }
     AH_LAUNCHED();
     return AH_OK;
   }

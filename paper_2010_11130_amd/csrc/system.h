@@ -104,6 +104,7 @@ struct AhLevel {
   double* RTval = nullptr;
   float* RTval32 = nullptr;
   int64_t* PTptr = nullptr;    // P^T: rows = coarse points, entries = fine points (weight 1)
+  int64_t nnzP = 0;
   int32_t* PTcol = nullptr;
   // cycle work vectors; e receives the level's correction from the finer
   // level's recursion, so it never aliases the sweep buffers x and y
@@ -120,7 +121,7 @@ struct AhLevel {
 // Flat copy of a level's device pointers for the single-workgroup kernel
 // that runs the coarse end of a V-cycle.
 struct TailLevel {
-  int64_t n, nc, nnz, nnzR;
+  int64_t n, nc, nnz, nnzR, nnzP;
   const int64_t* rp; const int32_t* ci; const double* v; const float* v32;
   const double* d; const float* d32;
   const int8_t* cf; const int32_t* pcol;
@@ -174,6 +175,47 @@ __host__ __device__ inline int64_t tail_lds_layout(const TailLevel* lv, int l0, 
   return off;
 }
 
+// The same for the transposed tail cycle of the adjoint: A^T, the diagonal,
+// C/F flags, P^T (coarse rows) and R^T (fine rows) per level; vectors g
+// (input), x and y.
+struct TailLdsT {
+  int32_t ATp, ATc, ATv, d, cf, PTp, PTc, RTp, RTc, RTv, g, x, y;
+};
+
+template <int W>
+__host__ __device__ inline int64_t tail_lds_layout_t(const TailLevel* lv, int l0, int nlev, TailLdsT* o,
+                                                     int64_t* o_cinv) {
+  int64_t off = 0;
+  auto take = [&off](int64_t bytes) {
+    const int64_t r = off;
+    off += (bytes + 15) & ~int64_t(15);
+    return (int32_t)r;
+  };
+  for (int l = l0; l < nlev; ++l) {
+    const TailLevel& L = lv[l];
+    TailLdsT& q = o[l - l0];
+    q = TailLdsT{};
+    q.g = take(L.n * W);
+    q.x = take(L.n * W);
+    q.y = take(L.n * W);
+    if (l < nlev - 1) {
+      q.ATp = take((L.n + 1) * 4);
+      q.ATc = take(L.nnz * 4);
+      q.ATv = take(L.nnz * W);
+      q.d = take(L.n * W);
+      q.cf = take(L.n);
+      q.PTp = take((L.nc + 1) * 4);
+      q.PTc = take(L.nnzP * 4);
+      q.RTp = take((L.n + 1) * 4);
+      q.RTc = take(L.nnzR * 4);
+      q.RTv = take(L.nnzR * W);
+    }
+  }
+  const int64_t nL = lv[nlev - 1].n;
+  *o_cinv = take(nL * nL * 8);
+  return off;
+}
+
 // Largest LDS image the staged tail kernel may use (160 KiB per workgroup on
 // gfx950, less the kernel's static layout table).
 constexpr int64_t TAIL_LDS_MAX = 160 * 1024 - 4096;
@@ -184,6 +226,9 @@ struct ah_hier {
   int tail0 = -1;              // first level handled by the single-workgroup tail kernel
   bool tail_lds = false;       // the forward tail runs from an LDS image of its levels
   int64_t tail_bytes[2] = {0, 0};   // size of that image with FP64 / FP32 values
+  bool tail_lds_t = false;     // the transposed tail runs from an LDS image too
+  int64_t tail_bytes_t[2] = {0, 0};
+  const char* tail_img_t[2] = {nullptr, nullptr};
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
   TailLevel* d_tail = nullptr; // device copy of every level's pointers
   const char* tail_img[2] = {nullptr, nullptr};   // the tail's LDS image (FP64 / FP32), built at setup
