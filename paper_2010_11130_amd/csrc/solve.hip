@@ -853,7 +853,7 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int nblk, const double* 
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
@@ -1190,6 +1190,7 @@ static ah_status gs_csr_sweep_t(const ah_hier* h, bool fonly, const T* atv, cons
   const int B = L.ob;
   const int64_t scale = fonly ? 1 : B;
   const int32_t* items = fonly ? h->ord_frows : h->ord;
+  if (lp.size() < 2) return AH_OK;
   for (size_t k = lp.size() - 1; k-- > 0;) {
     const int64_t nr = (lp[k + 1] - lp[k]) * scale;
     if (nr == 0) continue;
