@@ -136,3 +136,22 @@ def test_relax_bad_parameter(built):
         Hierarchy(g, relax=4)
     with pytest.raises(AirHdgError):
         Hierarchy(g, relax=2, order_ratio=0.5)
+
+
+@pytest.mark.parametrize("name", ["slab", "layer", "kuhn_nu4"])
+@pytest.mark.parametrize("relax", [2, 3])
+def test_ordered_bicgstab_parity(built, name, relax):
+    """The ordered relaxations under the paper's Krylov method (BiCGSTAB,
+    Section 4): solution to 1e-10 and step count within one."""
+    from oracle.drivers import air_bicgstab_solve
+    print("case", name, relax, flush=True)
+    g, o = built(name)
+    H = _hier(g, relax)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax=RELAX[relax], block=o.b)
+    x, info = H.solve(tol=1e-12, method=1)
+    xo, io = air_bicgstab_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"] and io["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    _, i8 = H.solve(tol=1e-8, method=1)
+    _, io8 = air_bicgstab_solve(o, tol=1e-8, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
