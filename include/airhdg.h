@@ -205,6 +205,12 @@ typedef struct {
   double t_setup_ms;
 } ah_setup_info;
 
+/* Environment (read by air_setup; for tests and tuning): AH_TAIL_MAX (rows,
+ * default 4096) bounds the first level of the single-workgroup coarse end of
+ * the cycle (0: every level runs with grid-wide kernels); AH_TAIL_LDS=0 runs
+ * that coarse end from global memory instead of an LDS image; AH_G0 (2, 4,
+ * 8, 16, 32) fixes the lanes per row of the level-0 kernels. */
+
 /* Defaults for ah_air_params / ah_solve_params. */
 void ah_air_defaults(ah_air_params* p);
 

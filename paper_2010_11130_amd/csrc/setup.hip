@@ -1476,7 +1476,10 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     const int lt = prm.relax >= 2 ? 1 : 0;
     h->tail0 = -1;
     h->tail_lds = false;
-    if (nl <= TAIL_MAX_LEVELS) {
+    // AH_TAIL_LDS=0 keeps the tail in global memory (both directions)
+    bool lds_ok = true;
+    if (const char* e = std::getenv("AH_TAIL_LDS")) lds_ok = std::atoi(e) != 0;
+    if (lds_ok && nl <= TAIL_MAX_LEVELS) {
       for (int l = lt; l < nl; ++l) {
         if (h->lev[l].n > tail_max) continue;
         TailLds lo[TAIL_MAX_LEVELS];
@@ -1492,7 +1495,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       }
     }
     // the adjoint's transposed tail from an LDS image of the same levels
-    if (prm.adjoint && h->tail0 >= 0 && nl <= TAIL_MAX_LEVELS) {
+    if (prm.adjoint && h->tail_lds && nl <= TAIL_MAX_LEVELS) {
       TailLdsT lt_[TAIL_MAX_LEVELS];
       int64_t oc = 0;
       const int64_t b64 = tail_lds_layout_t<8>(tl.data(), h->tail0, nl, lt_, &oc);

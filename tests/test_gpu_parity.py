@@ -87,11 +87,13 @@ def test_hierarchy_parity(built, name):
             assert rel_sparse_diff(R, ol.R) < 1e-10, l
 
 
-@pytest.fixture(params=["tail", "notail"])
+@pytest.fixture(params=["tail", "tail_global", "notail"])
 def tail_mode(request, monkeypatch):
     """Run the coarse end of the cycle in the single-workgroup kernel (levels
-    up to 6000 rows) or level by level with grid-wide kernels."""
-    monkeypatch.setenv("AH_TAIL_MAX", "6000" if request.param == "tail" else "0")
+    up to 6000 rows) from its LDS image or from global memory, or level by
+    level with grid-wide kernels."""
+    monkeypatch.setenv("AH_TAIL_MAX", "0" if request.param == "notail" else "6000")
+    monkeypatch.setenv("AH_TAIL_LDS", "0" if request.param == "tail_global" else "1")
     return request.param
 
 
