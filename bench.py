@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--solve-alone", type=int, default=0, metavar="N",
                     help="only time N FGMRES solves of slab 0 with nothing else on the GPU")
     ap.add_argument("--no-lair-d2", action="store_true",
-                    help="skip the march with distance-two lAIR neighbourhoods")
+                    help="skip the marches with distance-two lAIR neighbourhoods and with the Section 4 "
+                         "strength thresholds")
     ap.add_argument("--no-internal-layer", action="store_true",
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--relax", type=int, default=0,
@@ -760,6 +761,22 @@ def main():
         td = (time.perf_counter() - t0) / args.steps
         out["lair_distance2"] = {"value": total / td, "ms_per_step": 1e3 * td,
                                  "iters_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+    # the strength thresholds of the paper's Section 4 settings (0.2 for the
+    # coarsening and P, 0.3 for the restriction neighbourhoods)
+    if not args.no_lair_d2:
+        th = {"theta": 0.2, "theta_r": 0.3}
+        march.step(0, args.tol, air_extra=th)
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            its.clear()
+            march.step(0, args.tol, iters=its, air_extra=th)
+        torch.cuda.synchronize()
+        tt = (time.perf_counter() - t0) / args.steps
+        out["paper_thresholds"] = {"value": total / tt, "ms_per_step": 1e3 * tt, "theta": 0.2, "theta_r": 0.3,
+                                   "iters_per_slab": {"min": min(its), "max": max(its),
+                                                      "mean": sum(its) / len(its)}}
     # all-at-once: the 64 slabs as one space-time system on one GPU
     if not args.no_all_at_once:
         out["all_at_once"] = all_at_once(args, last64[1])
