@@ -56,6 +56,8 @@ def parse():
                     help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--relax", type=int, default=0,
                     help="with --solve-alone: relaxation (0 F,F,C Jacobi; 2, 3 ordered Gauss-Seidel)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the C3 (96^3, 31.8M DOFs) and C5 (48^3 mapped, adjoint) workloads")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint solve and gradients on slab 0")
     ap.add_argument("--no-ordered", action="store_true",
@@ -247,6 +249,140 @@ def copy_probe(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 10}))
+
+
+def copy_bandwidth(mib=1024, reps=20):
+    """Achieved bandwidth of a plain device-to-device copy (bytes read plus
+    written per second), the practical ceiling to set beside the nominal HBM
+    peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    return 2.0 * n * 8 / t / 1e9
+
+
+def workload_inputs(v, c, prob, p, f_q=None):
+    """Host mesh topology and boundary kinds, then the device inputs of
+    hdg_assemble: quadrature points, boundary data (g_D on Dirichlet facets,
+    u(t0) on the initial plane, 0 on the final plane), vertex velocity and
+    source values."""
+    import numpy as np
+    import torch
+    from paper_2010_11130_amd import Mesh
+    from workloads import boundary_kinds
+    m = Mesh(v, c)
+    fv, _ = m.facets()
+    bf = m.boundary_facets()
+    isb = np.zeros(m.nf, dtype=bool)
+    isb[bf] = True
+    kinds = boundary_kinds(v, fv, isb)
+    m.set_bc(kinds)
+    xe, xb = m.quad_points(p)
+    t = v[fv[bf]][:, :, 0]
+    bot = torch.as_tensor(np.all(np.abs(t - v[:, 0].min()) <= 1e-12, axis=1), device="cuda")[:, None]
+    kb = torch.as_tensor(kinds[bf], device="cuda")[:, None]
+    g = torch.where(kb == 1, prob.g_dirichlet(xb),
+                    torch.where(bot, prob.g_neumann(xb, True), prob.g_neumann(xb, False))).contiguous()
+    a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(v)), device="cuda")
+    if f_q is None:
+        f_q = prob.f(xe).contiguous()
+    elif f_q is False:
+        f_q = None
+    return m, xe, g, a, f_q
+
+
+def c3_all_at_once(tol):
+    """The C3 workload: the 96^3 Kuhn mesh of the space-time cube (5.3M
+    tets, p = 1, 31.8M free DOFs), smooth solution plus a front of width
+    1e-2, a = (1, 0.5), nu = 1e-4, all at once: assembly, lAIR setup and
+    FGMRES to tol, FP64 cycle and FP32 cycle (second run, same system)."""
+    import torch
+    from paper_2010_11130_amd import System, Hierarchy
+    from workloads import kuhn_cube_mesh
+    from workloads.problems import SmoothPlusFront
+    prob = SmoothPlusFront(1e-4)
+    v, c = kuhn_cube_mesh(96)
+    m, _, g, a, f = workload_inputs(v, c, prob, 1)
+    out = {"mesh": "96^3 Kuhn cubes, 5308416 tets", "p": 1, "nu": 1e-4}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = System(m, 1, prob.nu, a, f, g, keep=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out["free_dofs"] = s.n
+    for prec in (0, 1):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        h = Hierarchy(s, fp32_cycle=prec)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        x, info = h.solve(tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        out["fp64" if prec == 0 else "fp32_cycle"] = {
+            "dofs_per_s_setup_solve": s.n / (tc - ta), "setup_ms": 1e3 * (tb - ta), "solve_ms": 1e3 * (tc - tb),
+            "iters": info["iters"], "converged": info["converged"], "levels": h.info["levels"]}
+        del h, x
+    out["assemble_ms"] = 1e3 * (t1 - t0)
+    return out
+
+
+def c5_adjoint(tol):
+    """The C5 workload: the 48^3 Kuhn mesh mapped by the time-dependent
+    domain map (663,552 tets, p = 2, 7.9M free DOFs), 256 Gaussian sources,
+    nu = 1e-3: assembly with the element data kept, lAIR setup with the
+    transposed operators, the forward FGMRES solve, the adjoint solve of the
+    misfit J = |Lambda|^2 / 2 and the gradients with respect to the source
+    values and nu; FP64 and FP32 cycles, and FP64 with strength threshold
+    0.5 (the facet couplings are diffusion-dominated here: tau = nu alpha /
+    h_K exceeds |a|)."""
+    import torch
+    from paper_2010_11130_amd import System, Hierarchy, source_gauss
+    from workloads import kuhn_cube_mesh, map_vertices_c5
+    from workloads.problems import GaussianSources, c5_sources
+    centers, _, c0 = c5_sources(256)
+    prob = GaussianSources(1e-3, centers, c0)
+    v, c = kuhn_cube_mesh(48)
+    v = map_vertices_c5(v)
+    m, xe, g, a, _ = workload_inputs(v, c, prob, 2, f_q=False)
+    f = source_gauss(xe.reshape(-1, 3), centers, prob.width, c0).reshape(xe.shape[:-1]).contiguous()
+    out = {"mesh": "48^3 Kuhn cubes mapped, 663552 tets", "p": 2, "nu": 1e-3}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = System(m, 2, prob.nu, a, f, g, keep=True)
+    torch.cuda.synchronize()
+    out["assemble_ms"] = 1e3 * (time.perf_counter() - t0)
+    out["free_dofs"] = s.n
+    for prec, theta, key in ((0, 0.25, "fp64"), (1, 0.25, "fp32_cycle"), (0, 0.5, "fp64_theta_0.5")):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        h = Hierarchy(s, adjoint=1, fp32_cycle=prec, theta=theta)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        x, fi = h.solve(tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        lam, ai = h.solve_adjoint(x, tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        s.grad(x, lam)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        out[key] = {
+            "setup_ms": 1e3 * (tb - ta), "forward_ms": 1e3 * (tc - tb), "adjoint_ms": 1e3 * (td - tc),
+            "gradient_ms": 1e3 * (te - td), "forward_iters": fi["iters"], "adjoint_iters": ai["iters"],
+            "converged": fi["converged"] and ai["converged"],
+            "dofs_per_s_setup_forward_adjoint": s.n / (td - ta)}
+        del h, x, lam
+    return out
 
 
 class March:
@@ -786,9 +922,16 @@ def main():
         out["ordered_relaxation"] = ordered_relaxation(args, march)
     if not args.no_adjoint:
         out["adjoint_slab0"] = adjoint_slab(march, args.tol)
+    if not args.no_large:
+        out["c3_all_at_once"] = c3_all_at_once(args.tol)
+        out["c5_adjoint"] = c5_adjoint(args.tol)
     # dominant tagged kernel of the FP64 march
     if prof64:
         out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])
+        if out["roofline"]["unit"] == "GB/s":
+            cb = copy_bandwidth()
+            out["roofline"]["copy_gbs"] = cb
+            out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n, args.p, args.nu, args.tol, 1.0 / args.slabs)
     print(json.dumps(out))
