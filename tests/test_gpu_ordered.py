@@ -155,3 +155,29 @@ def test_ordered_bicgstab_parity(built, name, relax):
     _, i8 = H.solve(tol=1e-8, method=1)
     _, io8 = air_bicgstab_solve(o, tol=1e-8, hier=OH)
     assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+@pytest.mark.parametrize("relax", [2, 3])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ordered_cycles_repeat_bit_for_bit(built, relax, fp32):
+    """Six cycles on one hierarchy, with other GPU work and synchronizations
+    between them, give the same result bit for bit (the level sweeps take no
+    decision from the order in which workgroups run), and that result
+    matches the oracle."""
+    print("case slab", relax, fp32, flush=True)
+    g, o = built("slab")
+    H = _hier(g, relax, fp32_cycle=1 if fp32 else 0)
+    other = _hier(built("c5")[0], 0)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax=RELAX[relax], block=o.b)
+    r = np.random.default_rng(9).standard_normal(g.n)
+    rt = torch.as_tensor(r, device="cuda")
+    zs = []
+    for _ in range(6):
+        zs.append(H.vcycle(rt, precision=1 if fp32 else 0).cpu().numpy())
+        other.solve(tol=1e-8)
+        torch.cuda.synchronize()
+    for z in zs[1:]:
+        assert np.array_equal(z, zs[0])
+    zo = oair.vcycle(OH, r)
+    tol = 1e-5 if fp32 else 1e-10
+    assert np.linalg.norm(zs[0] - zo) <= tol * np.linalg.norm(zo)
