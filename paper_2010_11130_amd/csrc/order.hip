@@ -176,6 +176,18 @@ __global__ void k_ord_cols(int64_t nbr, const int64_t* __restrict__ optr, const 
   }
 }
 
+// Sweep records: {item, first slot of its block row, blocks in that row, 0}
+// where item is a block (ord) or a scalar row (F rows, block size B).
+__global__ void k_ord_records(int64_t m, int B, const int32_t* __restrict__ items, const int64_t* __restrict__ optr,
+                              int4* __restrict__ rec) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const int32_t it = items[t];
+  const int64_t R = B > 1 ? it / B : it;
+  const int64_t o0 = optr[R];
+  rec[t] = make_int4(it, (int)o0, (int)(optr[R + 1] - o0), 0);
+}
+
 __global__ void k_ord_gather(int64_t m, const int64_t* __restrict__ idx, const int64_t* __restrict__ src,
                              int64_t* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,6 +320,17 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
     set_error("air_setup: flow order lost F rows");
     return AH_EINVAL;
   }
+  // sweep records (value slots as int32)
+  if (nslot >= ((int64_t)1 << 31)) {
+    set_error("air_setup: level 0 too large for the ordered sweeps");
+    return AH_EUNSUPPORTED;
+  }
+  const int64_t nF = L.n - L.nc;
+  OK_(h->arena.get(&h->ord_info, nbr));
+  OK_(h->arena.get(&h->ord_finfo, nF + 1));
+  hipLaunchKernelGGL(k_ord_records, grid1(nbr), dim3(256), 0, st, nbr, 1, h->ord, L.optr, h->ord_info);
+  if (nF) hipLaunchKernelGGL(k_ord_records, grid1(nF), dim3(256), 0, st, nF, B, h->ord_frows, L.optr, h->ord_finfo);
+  HIP_(hipGetLastError());
   return AH_OK;
 #undef OK_
 #undef HIP_

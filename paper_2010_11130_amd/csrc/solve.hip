@@ -159,22 +159,22 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
 // levels are read from xn (already swept), blocks of the row's own level
 // from xo (values before the level: Jacobi inside a level), later levels
 // from xn (still equal to xo).  cols holds ~J for a block J on the row's
-// level.  BLK: items are blocks and row k is items[k / B] B + k mod B;
-// otherwise items are rows.
+// level.  rec: one record per item {item, first value slot of its block row,
+// blocks in the row, 0}; BLK: items are blocks and row k is
+// rec[k / B].x B + k mod B, otherwise items are rows.
 template <class TA, class T, int B, int G, bool BLK>
-__global__ __launch_bounds__(256) void k_gs_fb(int64_t n, const int32_t* __restrict__ items,
-                                               const int64_t* __restrict__ optr, const int32_t* __restrict__ cols,
-                                               const TA* __restrict__ ov, const T* __restrict__ b,
-                                               const T* __restrict__ xo, T* xn) {
+__global__ __launch_bounds__(256) void k_gs_fb(int64_t n, const int4* __restrict__ rec,
+                                               const int32_t* __restrict__ cols, const TA* __restrict__ ov,
+                                               const T* __restrict__ b, const T* __restrict__ xo, T* xn) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / G;
   const int g = (int)(gid % G);
   if (ii >= n) return;
-  const int64_t i = BLK ? (int64_t)items[ii / B] * B + ii % B : (int64_t)items[ii];
-  const int64_t R = i / B;
-  const int m = (int)(i - R * B);
-  const int64_t o0 = optr[R];
-  const int len = (int)(optr[R + 1] - o0) * B;
+  const int4 r = rec[BLK ? ii / B : ii];
+  const int64_t i = BLK ? (int64_t)r.x * B + ii % B : (int64_t)r.x;
+  const int m = (int)(i % B);
+  const int64_t o0 = r.y;
+  const int len = r.z * B;
   const TA* __restrict__ v = ov + o0 * (B * B) + (int64_t)m * len;
   const int32_t* __restrict__ cb = cols + o0;
   T acc = 0, acc1 = 0;
@@ -1116,16 +1116,13 @@ struct Ops<float> {
 // all points), one launch per level of the flow order, from xo into xn
 // (xn must hold the same values as xo on entry).
 template <class TA, class T, int B, int G>
-static void gs_fb_level(bool blk, int64_t nrows, const int32_t* items, const ah_hier* h, const TA* ov, const T* b,
+static void gs_fb_level(bool blk, int64_t nrows, const int4* rec, const ah_hier* h, const TA* ov, const T* b,
                         const T* xo, T* xn, hipStream_t st) {
-  const AhLevel& L = h->lev[0];
   const dim3 grid((unsigned)cdiv(nrows * G, 256));
   if (blk)
-    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, true>), grid, dim3(256), 0, st, nrows, items, L.optr, h->ord_cols, ov,
-                       b, xo, xn);
+    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, true>), grid, dim3(256), 0, st, nrows, rec, h->ord_cols, ov, b, xo, xn);
   else
-    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, false>), grid, dim3(256), 0, st, nrows, items, L.optr, h->ord_cols, ov,
-                       b, xo, xn);
+    hipLaunchKernelGGL((k_gs_fb<TA, T, B, G, false>), grid, dim3(256), 0, st, nrows, rec, h->ord_cols, ov, b, xo, xn);
 }
 
 template <class T, int B>
@@ -1135,14 +1132,14 @@ static ah_status gs_fb_sweep_b(const ah_hier* h, bool fonly, const T* ov, const 
   const int G = fb_lanes(L.nov, L.n) <= 4 ? 4 : 8;
   const std::vector<int64_t>& lp = fonly ? h->ord_lptrF : h->ord_lptr;
   const int64_t scale = fonly ? 1 : B;
-  const int32_t* items = fonly ? h->ord_frows : h->ord;
+  const int4* rec = fonly ? h->ord_finfo : h->ord_info;
   for (size_t k = 0; k + 1 < lp.size(); ++k) {
     const int64_t nr = (lp[k + 1] - lp[k]) * scale;
     if (nr == 0) continue;
     if (G == 4)
-      gs_fb_level<T, T, B, 4>(!fonly, nr, items + lp[k], h, ov, b, xo, xn, st);
+      gs_fb_level<T, T, B, 4>(!fonly, nr, rec + lp[k], h, ov, b, xo, xn, st);
     else
-      gs_fb_level<T, T, B, 8>(!fonly, nr, items + lp[k], h, ov, b, xo, xn, st);
+      gs_fb_level<T, T, B, 8>(!fonly, nr, rec + lp[k], h, ov, b, xo, xn, st);
   }
   AH_LAUNCHED();
   return AH_OK;

@@ -244,6 +244,11 @@ struct ah_hier {
   int32_t* ord_level = nullptr;  // [blocks] level of each block
   int32_t* ord_frows = nullptr;
   int32_t* ord_cols = nullptr;   // level-0 block columns, ~J where J is on the row's level
+  // per position of ord / ord_frows: {block or row, first value slot of the
+  // block row, its number of blocks, 0}, so a sweep reads one record per row
+  // before its values
+  int4* ord_info = nullptr;
+  int4* ord_finfo = nullptr;
   std::vector<int64_t> ord_lptr, ord_lptrF;
   int ord_breaks = 0;            // rounds that broke a cycle
   // FGMRES workspace (allocated on first solve)
