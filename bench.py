@@ -868,6 +868,7 @@ def main():
         out["levels"] = stages64[0]["levels"]
         out["op_complexity"] = stages64[0]["op_complexity"]
     out.update(extra)
+    alone64 = None
     if not args.no_fp32:
         t32, stages32, tseq32, prof32, last32 = run_timed(march, 1, args.steps, args.warmup, args.tol, seq)
         _, extra32 = split(stages32, tseq32)
@@ -878,7 +879,7 @@ def main():
         out["fp32_cycle"].update(extra32)
         # the two cycle precisions with nothing else on the GPU (in the march
         # the solve shares the GPU with the next slab's assembly and setup)
-        a64 = solve_alone(march, 10, args.tol, 0)
+        a64 = alone64 = solve_alone(march, 10, args.tol, 0)
         a32 = solve_alone(march, 10, args.tol, 1)
         out["fp32_cycle"]["solve_alone"] = {
             "fp64_ms_per_solve": a64["ms_per_solve"], "fp32_ms_per_solve": a32["ms_per_solve"],
@@ -954,6 +955,12 @@ def main():
             cb = copy_bandwidth()
             out["roofline"]["copy_gbs"] = cb
             out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cb
+            # the same kernel with the GPU to itself (slab 0 solved alone)
+            k = (alone64 or {}).get("kernels", {}).get(out["roofline"]["kernel"])
+            if k:
+                ach = k["bytes"] / k["launches"] / (k["avg_us"] * 1e-6) / 1e9
+                out["roofline"]["alone"] = {"avg_launch_us": k["avg_us"], "achieved": ach,
+                                            "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / cb}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n, args.p, args.nu, args.tol, 1.0 / args.slabs)
     print(json.dumps(out))
