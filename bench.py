@@ -809,7 +809,7 @@ def cpu_baseline(n, p, nu, tol, dt):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus %d requested); the path has no "
+        print("bench.py measures one GPU only (--gpus %d requested): the path has no "
               "multi-GPU sharding" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.profile_summary:
