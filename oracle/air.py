@@ -402,49 +402,75 @@ def _ordered_sweeps(H, lev, transpose):
 
 
 def _coarse_solve(last, b, trans=0):
+    """Coarsest level: dense LU in FP64 whatever the cycle's precision (the
+    input is widened to FP64 and the result rounded back to its type)."""
     if last.lu is None:
-        return np.zeros(0)
-    return sla.lu_solve(last.lu, b, trans=trans)
+        return np.zeros(0, dtype=b.dtype)
+    return sla.lu_solve(last.lu, b.astype(np.float64), trans=trans).astype(b.dtype)
 
 
-def vcycle(H, b, l=0):
+def _level_ops(lev, dtype):
+    """``A``, ``R``, ``P``, diagonal and ``A^T`` of a level with their values
+    rounded to ``dtype`` (FP64: the level's own matrices)."""
+    cache = lev.__dict__.setdefault("_ops", {})
+    key = np.dtype(dtype).name
+    if key not in cache:
+        A = lev.A.astype(dtype)
+        R = lev.R.astype(dtype) if hasattr(lev, "R") else None
+        P = lev.P.astype(dtype) if hasattr(lev, "P") else None
+        cache[key] = (A, R, P, lev.diag.astype(dtype), A.T.tocsr())
+    return cache[key]
+
+
+def vcycle(H, b, l=0, dtype=np.float64):
     """One V-cycle with zero initial guess (Section 3 coarse-grid correction,
-    post-relaxation only)."""
+    post-relaxation only).  ``dtype=np.float32`` runs the cycle with every
+    operator rounded to FP32 and FP32 arithmetic throughout (products
+    accumulate in FP32), except the FP64 coarsest solve: the reduced-precision
+    cycle of the precision form (F, F, C or F sweeps only)."""
     lev = H.levels[l]
+    b = np.asarray(b).astype(dtype, copy=False)
     if l == H.nlev - 1:
         return _coarse_solve(lev, b)
-    ec = vcycle(H, lev.R @ b, l + 1)
-    x = lev.P @ ec
+    A, R, P, d, _ = _level_ops(lev, dtype)
+    ec = vcycle(H, R @ b, l + 1, dtype)
+    x = P @ ec
     if hasattr(lev, "gs_all"):
+        if np.dtype(dtype) != np.float64:
+            raise NotImplementedError("ordered sweeps are emulated in FP64 only")
         for sw in _ordered_sweeps(H, lev, False):
             x = sw.apply(lev.A, b, x)
         return x
-    d = lev.diag
+    om = np.asarray(H.omega, dtype=dtype)
     for X in _sweep_sets(H, lev, False):
-        X = X[np.abs(d[X]) >= 1e-30]
-        r = b - lev.A @ x
-        x[X] += H.omega * r[X] / d[X]
+        X = X[np.abs(lev.diag[X]) >= 1e-30]
+        r = b - A @ x
+        x[X] += om * r[X] / d[X]
     return x
 
 
-def vcycle_T(H, g, l=0):
+def vcycle_T(H, g, l=0, dtype=np.float64):
     """Transpose of :func:`vcycle`: sweeps C, F, F with ``A^T``, then restriction
-    by ``P^T`` and interpolation by ``R^T``; coarsest ``LU^T`` solve."""
+    by ``P^T`` and interpolation by ``R^T``; coarsest ``LU^T`` solve.
+    ``dtype`` as in :func:`vcycle`."""
     lev = H.levels[l]
+    g = np.asarray(g).astype(dtype, copy=False)
     if l == H.nlev - 1:
         return _coarse_solve(lev, g, trans=1)
+    A, R, P, d, AT = _level_ops(lev, dtype)
     y = np.zeros_like(g)
-    d = lev.diag
-    AT = lev.A.T.tocsr()
     if hasattr(lev, "gs_all"):
+        if np.dtype(dtype) != np.float64:
+            raise NotImplementedError("ordered sweeps are emulated in FP64 only")
         for sw in _ordered_sweeps(H, lev, True):
             y = sw.apply_T(AT, g, y)
     else:
+        om = np.asarray(H.omega, dtype=dtype)
         for X in _sweep_sets(H, lev, True):
-            X = X[np.abs(d[X]) >= 1e-30]
+            X = X[np.abs(lev.diag[X]) >= 1e-30]
             r = g - AT @ y
-            y[X] += H.omega * r[X] / d[X]
-    y = y + lev.R.T @ vcycle_T(H, lev.P.T @ (g - AT @ y), l + 1)
+            y[X] += om * r[X] / d[X]
+    y = y + R.T @ vcycle_T(H, P.T @ (g - AT @ y), l + 1, dtype)
     return y
 
 

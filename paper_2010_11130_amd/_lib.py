@@ -116,8 +116,12 @@ def destroy(name, h, _finalizing=sys.is_finalizing):
 
 
 class AirHdgError(RuntimeError):
-    def __init__(self, status, where):
-        msg = lib().ah_last_error().decode(errors="replace")
+    """A library call failed (``status``); the message is the library's
+    ``ah_last_error()`` unless ``msg`` is given."""
+
+    def __init__(self, status, where, msg=None):
+        if msg is None:
+            msg = lib().ah_last_error().decode(errors="replace")
         super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
         self.status = status
 

@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from ._lib import (lib, check, destroy, HdgParams, AirParams, SetupInfo, SolveParams, SolveInfo,
-                   AH_OK, AH_ENOCONV)
+                   AH_OK, AH_ENOCONV, AirHdgError)
 
 
 def _p(t):
@@ -27,6 +27,36 @@ def _dev(x, dtype=torch.float64):
     if t.device.type != "cuda":
         t = t.cuda()
     return t.contiguous()
+
+
+def _vec(t, n, name, shape=None, out=False):
+    """Check a tensor argument that the library reads or writes as ``n``
+    float64 values in device memory.  Inputs of another float type are
+    widened and non-contiguous inputs copied (marshalling); an output must
+    already be a contiguous float64 device tensor.  Raises ``ValueError``
+    before any library call otherwise: the C-ABI cannot see sizes or types of
+    device buffers."""
+    if t is None:
+        return None
+    if not torch.is_tensor(t):
+        if out:
+            raise ValueError("%s: expected a torch tensor" % name)
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    if out:
+        if t.dtype != torch.float64:
+            raise ValueError("%s: output must be float64, got %s" % (name, t.dtype))
+    elif not t.dtype.is_floating_point:
+        raise ValueError("%s: expected a floating-point tensor, got %s" % (name, t.dtype))
+    if t.numel() != n:
+        raise ValueError("%s: expected %d values%s, got %d (shape %s)"
+                         % (name, n, "" if shape is None else " %s" % (shape,), t.numel(), tuple(t.shape)))
+    if t.device.type != "cuda":
+        raise ValueError("%s: expected a tensor in device memory, got device %s" % (name, t.device))
+    if out:
+        if not t.is_contiguous():
+            raise ValueError("%s: output must be contiguous" % name)
+        return t
+    return t.to(torch.float64).contiguous()
 
 
 def sizes(dim_st, p):
@@ -103,9 +133,11 @@ class System:
         self.mesh = mesh
         self.p = p
         self.nu = float(nu)
-        self._a = _dev(a_vert)
-        self._f = _dev(f_q)
-        self._g = _dev(g_q)
+        nq, nqf, _, _ = sizes(mesh.D, p)
+        d = mesh.D - 1
+        self._a = _vec(_dev(a_vert), mesh.nv * d, "a_vert", (mesh.nv, d))
+        self._f = _vec(f_q, mesh.ne * nq, "f_q", (mesh.ne, nq))
+        self._g = _vec(g_q, mesh.nbf * nqf, "g_q", (mesh.nbf, nqf))
         prm = HdgParams(p, float(alpha), 1 if keep else 0, 0 if block_scale else 1)
         h = C.c_void_p()
         check(lib().hdg_assemble(mesh.h, C.byref(prm), float(nu), _p(self._a), _p(self._f), _p(self._g),
@@ -136,30 +168,36 @@ class System:
                 "dinv": dinv[:self.n // self.b], "lam_dir": lamd}
 
     def reconstruct(self, lam):
+        lam = _vec(lam, self.n, "lam")
         U = torch.empty((self.mesh.ne, self.nu_dofs), dtype=torch.float64, device="cuda")
-        check(lib().hdg_reconstruct(self.h, _p(lam.contiguous()), _p(U), _stream()), "hdg_reconstruct")
+        check(lib().hdg_reconstruct(self.h, _p(lam), _p(U), _stream()), "hdg_reconstruct")
         return U
 
     def trace_to_inflow(self, lam, next_mesh, g_q):
         """Write this system's final-plane trace ``lam`` into the inflow rows
         of ``g_q`` (boundary data of ``next_mesh``)."""
-        check(lib().hdg_inflow_from_trace(self.h, _p(lam.contiguous()), next_mesh.h, _p(g_q), _stream()),
+        lam = _vec(lam, self.n, "lam")
+        _vec(g_q, next_mesh.nbf * self.nqf, "g_q", (next_mesh.nbf, self.nqf), out=True)
+        check(lib().hdg_inflow_from_trace(self.h, _p(lam), next_mesh.h, _p(g_q), _stream()),
               "hdg_inflow_from_trace")
         return g_q
 
     def update_neumann(self, g_q):
         """New Neumann (inflow) data: recompute H and H_hat from ``g_q``
         without reassembling the matrix (``hdg_update_neumann``)."""
-        self._g = _dev(g_q)
+        self._g = _vec(g_q, self.mesh.nbf * self.nqf, "g_q", (self.mesh.nbf, self.nqf))
         check(lib().hdg_update_neumann(self.h, _p(self._g), _stream()), "hdg_update_neumann")
         return self
 
     def grad(self, lam_fwd, lam_adj, a_vert=None, want_f=True):
         """dJ/df at the element quadrature points and dJ/dnu (``hdg_assemble_grad``)."""
+        lam_fwd = _vec(lam_fwd, self.n, "lam_fwd")
+        lam_adj = _vec(lam_adj, self.n, "lam_adj")
+        d = self.mesh.D - 1
+        a = self._a if a_vert is None else _vec(_dev(a_vert), self.mesh.nv * d, "a_vert", (self.mesh.nv, d))
         dq = torch.empty((self.mesh.ne, self.nq), dtype=torch.float64, device="cuda") if want_f else None
         dnu = C.c_double()
-        a = self._a if a_vert is None else _dev(a_vert)
-        check(lib().hdg_assemble_grad(self.h, _p(a), _p(lam_fwd.contiguous()), _p(lam_adj.contiguous()),
+        check(lib().hdg_assemble_grad(self.h, _p(a), _p(lam_fwd), _p(lam_adj),
                                       _p(dq), C.byref(dnu), _stream()), "hdg_assemble_grad")
         return dq, dnu.value
 
@@ -203,9 +241,11 @@ class Hierarchy:
         """FGMRES + V-cycle: ``S Lambda = rhs`` (unscaled; ``None`` = assembled H)."""
         prm = solve_params(**kw)
         n = self.system.n
-        x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+        rhs = _vec(rhs, n, "rhs")
+        x = _vec(out, n, "out", out=True) if out is not None else torch.empty(n, dtype=torch.float64,
+                                                                               device="cuda")
         if x0 is not None:
-            x.copy_(x0)
+            x.copy_(_vec(x0, n, "x0"))
             prm.x0_given = 1
         info = SolveInfo()
         st = check(lib().air_solve(self.h, _p(rhs), _p(x), C.byref(prm), _stream(), C.byref(info)),
@@ -215,15 +255,19 @@ class Hierarchy:
     def solve_adjoint(self, g, out=None, **kw):
         """``S^T lam = g`` with the transposed cycle."""
         prm = solve_params(**kw)
-        lam = out if out is not None else torch.empty(self.system.n, dtype=torch.float64, device="cuda")
+        n = self.system.n
+        g = _vec(g, n, "g")
+        lam = _vec(out, n, "out", out=True) if out is not None else torch.empty(n, dtype=torch.float64,
+                                                                                 device="cuda")
         info = SolveInfo()
-        st = check(lib().air_solve_adjoint(self.h, _p(g.contiguous()), _p(lam), C.byref(prm), _stream(),
+        st = check(lib().air_solve_adjoint(self.h, _p(g), _p(lam), C.byref(prm), _stream(),
                                            C.byref(info)), "air_solve_adjoint", allow=(AH_OK, AH_ENOCONV))
         return lam, _info(info, st)
 
     def vcycle(self, r, precision=0, transpose=False):
+        r = _vec(r, self.system.n, "r")
         z = torch.empty_like(r)
-        check(lib().ah_vcycle_apply(self.h, _p(r.contiguous()), _p(z), int(precision), int(bool(transpose)),
+        check(lib().ah_vcycle_apply(self.h, _p(r), _p(z), int(precision), int(bool(transpose)),
                                     _stream()), "ah_vcycle_apply")
         return z
 
@@ -268,14 +312,28 @@ def _info(info, st):
             "true_relres": info.true_relres, "t_solve_ms": info.t_solve_ms, "status": st}
 
 
+def _points(X):
+    if not torch.is_tensor(X) or X.device.type != "cuda" or X.dim() < 2:
+        raise ValueError("X: expected a device tensor of points [..., dim_st]")
+    D = X.shape[-1]
+    if D not in (2, 3):
+        raise ValueError("X: points of dimension 2 or 3 expected, got %d" % D)
+    return X.to(torch.float64).contiguous(), D, X.numel() // D
+
+
+def _centers(centers, D):
+    cen = _dev(centers)
+    if cen.dim() != 2 or cen.shape[1] != D:
+        raise ValueError("centers: expected [K][%d], got %s" % (D, tuple(cen.shape)))
+    return cen
+
+
 def source_gauss(X, centers, width, c):
     """``f(X) = sum_k c_k exp(-|X - X_k|^2 / (2 width^2))`` (device)."""
-    X = X.contiguous()
-    D = X.shape[-1]
-    npts = X.numel() // D
+    X, D, npts = _points(X)
+    cen = _centers(centers, D)
+    cc = _vec(_dev(c), cen.shape[0], "c")
     f = torch.empty(X.shape[:-1], dtype=torch.float64, device="cuda")
-    cen = _dev(centers)
-    cc = _dev(c)
     check(lib().ah_source_gauss(D, npts, _p(X), cen.shape[0], _p(cen), float(width), _p(cc), _p(f), _stream()),
           "ah_source_gauss")
     return f
@@ -283,44 +341,76 @@ def source_gauss(X, centers, width, c):
 
 def source_gauss_T(X, centers, width, y):
     """``dc_k = sum_points y(X) phi_k(X)`` (device)."""
-    X = X.contiguous()
-    D = X.shape[-1]
-    npts = X.numel() // D
-    cen = _dev(centers)
+    X, D, npts = _points(X)
+    cen = _centers(centers, D)
+    y = _vec(y, npts, "y")
     dc = torch.empty(cen.shape[0], dtype=torch.float64, device="cuda")
-    check(lib().ah_source_gauss_T(D, npts, _p(X), cen.shape[0], _p(cen), float(width), _p(y.contiguous()),
+    check(lib().ah_source_gauss_T(D, npts, _p(X), cen.shape[0], _p(cen), float(width), _p(y),
                                   _p(dc), _stream()), "ah_source_gauss_T")
     return dc
 
 
-class AIRSolve(torch.autograd.Function):
-    """``Lambda = S^-1 rhs``; the backward pass solves ``S^T lam = dL/dLambda``
-    with the transposed hierarchy (P^T restriction, R^T interpolation)."""
+def _require_converged(info, what):
+    if not info["converged"]:
+        raise AirHdgError(AH_ENOCONV, what, "no convergence in %d iterations, relative residual %.3e"
+                          % (info["iters"], info["true_relres"]))
+
+
+class GaussSource(torch.autograd.Function):
+    """``f_q = sum_k c_k phi_k(X)`` with Gaussian bumps
+    ``phi_k(X) = exp(-|X - X_k|^2 / (2 width^2))`` at the points ``X``
+    (e.g. the element quadrature points); the backward pass contracts
+    ``dL/df_q`` with the same bumps (``ah_source_gauss_T``).  Differentiable
+    in the amplitudes ``c`` only."""
 
     @staticmethod
-    def forward(ctx, rhs, hier, tol=1e-8, precision=0):
-        x, info = hier.solve(rhs.detach(), tol=tol, precision=precision)
+    def forward(ctx, c, X, centers, width):
+        ctx.X, ctx.centers, ctx.width = X, centers, width
+        return source_gauss(X, centers, width, c.detach())
+
+    @staticmethod
+    def backward(ctx, gf):
+        return source_gauss_T(ctx.X, ctx.centers, ctx.width, gf.reshape(-1)), None, None, None
+
+
+class AIRSolve(torch.autograd.Function):
+    """``Lambda = S^-1 rhs``; the backward pass solves ``S^T lam = dL/dLambda``
+    with the transposed hierarchy (P^T restriction, R^T interpolation).  The
+    hierarchy must be built with ``adjoint=1`` (and ``fp32_cycle=1`` for
+    ``precision=1``).  Raises ``AirHdgError`` when either solve does not
+    converge."""
+
+    @staticmethod
+    def forward(ctx, rhs, hier, tol=1e-8, precision=0, maxit=1000, adjoint_maxit=None):
+        x, info = hier.solve(rhs.detach(), tol=tol, precision=precision, maxit=maxit)
+        _require_converged(info, "AIRSolve forward")
         ctx.hier, ctx.tol, ctx.precision = hier, tol, precision
+        ctx.maxit = maxit if adjoint_maxit is None else adjoint_maxit
         ctx.info = info
         return x
 
     @staticmethod
     def backward(ctx, g):
-        lam, _ = ctx.hier.solve_adjoint(g.contiguous(), tol=ctx.tol, precision=ctx.precision)
-        return lam, None, None, None
+        lam, info = ctx.hier.solve_adjoint(g, tol=ctx.tol, precision=ctx.precision, maxit=ctx.maxit)
+        _require_converged(info, "AIRSolve adjoint")
+        return lam, None, None, None, None, None
 
 
 class HDGSolve(torch.autograd.Function):
     """``Lambda(f_q, nu)``: assembly, AIR setup and solve in the forward pass;
     the backward pass returns ``dJ/df_q`` (at the element quadrature points)
-    and ``dJ/dnu`` from one adjoint solve and the element adjoint."""
+    and ``dJ/dnu`` from one adjoint solve and the element adjoint.  Raises
+    ``AirHdgError`` when the forward or the adjoint solve does not
+    converge."""
 
     @staticmethod
     def forward(ctx, f_q, nu, mesh, p, a_vert, g_q, tol=1e-12, precision=0, air_kw=None):
         sysm = System(mesh, p, float(nu), a_vert, f_q.detach(), g_q)
         hier = Hierarchy(sysm, adjoint=1, fp32_cycle=1 if precision else 0, **(air_kw or {}))
         lam, info = hier.solve(tol=tol, precision=precision)
+        _require_converged(info, "HDGSolve forward")
         ctx.sysm, ctx.hier, ctx.tol, ctx.precision = sysm, hier, tol, precision
+        ctx.info = info
         ctx.save_for_backward(lam)
         ctx.nu_is_tensor = torch.is_tensor(nu)
         return lam
@@ -328,7 +418,9 @@ class HDGSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (lam,) = ctx.saved_tensors
-        adj, _ = ctx.hier.solve_adjoint(g.contiguous(), tol=ctx.tol, precision=ctx.precision)
+        adj, info = ctx.hier.solve_adjoint(g, tol=ctx.tol, precision=ctx.precision)
+        _require_converged(info, "HDGSolve adjoint")
+        ctx.adj_info = info
         dq, dnu = ctx.sysm.grad(lam, adj)
         gnu = torch.tensor(dnu, dtype=torch.float64) if ctx.nu_is_tensor else None
         return dq, gnu, None, None, None, None, None, None, None

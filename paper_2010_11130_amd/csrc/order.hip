@@ -206,6 +206,12 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
   const int B = L.ob;
   const int64_t nbr = L.n / B;
   const int64_t nslot = L.nov / ((int64_t)B * B);
+  // the sweep records hold a block row's first slot as a 32-bit offset
+  if (nslot > (int64_t)INT32_MAX) {
+    set_error("air_setup: ordered relaxation needs fewer than 2^31 off-diagonal facet blocks (%lld)",
+              (long long)nslot);
+    return AH_EUNSUPPORTED;
+  }
   Arena tmp;
   tmp.stream = st;
   ah_status rc = AH_OK;

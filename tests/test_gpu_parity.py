@@ -7,7 +7,8 @@ Tolerances (FP64 everywhere unless stated):
   * C/F splitting, one-point interpolation columns: bit-exact (integers);
   * lAIR restriction and coarse matrices: 1e-10 relative (they inherit the
     level matrices' rounding through small dense solves);
-  * one V-cycle: 1e-10 relative;
+  * one V-cycle: 1e-10 relative; FP32 cycle: within 4x the error of the
+    oracle's FP32 emulation of the same cycle (a few 1e-7);
   * solution at tol 1e-12: 1e-10 relative; iterations at the workload
     tolerance within +-1;
   * FP32 cycle: solution within 1e-8 of the FP64 oracle at tol 1e-10.
@@ -110,9 +111,21 @@ def test_vcycle_parity(built, name, transpose, fp32, tail_mode):
     z = H.vcycle(torch.as_tensor(r, device="cuda"), precision=1 if fp32 else 0,
                  transpose=transpose).cpu().numpy()
     zo = oair.vcycle_T(OH, r) if transpose else oair.vcycle(OH, r)
-    # FP32 cycle: FP32 operators and accumulation; one cycle agrees to ~1e-6
-    tol = 1e-5 if fp32 else 1e-10
-    assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    if not fp32:
+        assert err <= 1e-10
+        return
+    # FP32 cycle: the tolerance is what FP32 arithmetic gives for this cycle
+    # on this input, measured by the oracle's FP32 emulation of the same
+    # cycle (operators rounded to FP32, FP32 accumulation, FP64 coarsest
+    # solve).  The HIP path rounds in another order (fused multiply-adds,
+    # other summation orders), so it may differ from the emulation by errors
+    # of the same size, not by more than a small factor.
+    z32 = (oair.vcycle_T(OH, r, dtype=np.float32) if transpose else oair.vcycle(OH, r, dtype=np.float32))
+    err32 = np.linalg.norm(z32.astype(np.float64) - zo) / np.linalg.norm(zo)
+    print("fp32 cycle error: hip %.3e  emulated %.3e" % (err, err32), flush=True)
+    assert err32 < 1e-5
+    assert err <= 4.0 * err32 + 1e-12
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -343,3 +343,72 @@ def test_no_block_inverse_same_solution_more_iterations():
     # 200 iterations); the scaled one converges in about a dozen
     assert i1["converged"] and i1["iters"] < 20
     assert not i0["converged"] or i0["iters"] > 3 * i1["iters"]
+
+
+def _dense_cycle_matrix(H, l, sets_order, omega=1.0, transpose=False):
+    """The V-cycle of Section 3 written out as one dense matrix: with
+    ``E_k = I - M_k A`` and ``M_k = omega I_X D^-1 I_X^T`` the sweep on the
+    set X_k, a post-relaxed cycle with zero initial guess is
+    ``B = M_3 + E_3 M_2 + E_3 E_2 M_1 + E_3 E_2 E_1 P B_c R`` (sweeps 1, 2, 3
+    in application order), and the coarsest level is ``A_L^-1``."""
+    lev = H.levels[l]
+    A = lev.A.toarray()
+    n = A.shape[0]
+    if l == H.nlev - 1:
+        return np.linalg.inv(A)
+    Bc = _dense_cycle_matrix(H, l + 1, sets_order, omega)
+    d = np.diag(A)
+    F = np.nonzero(lev.cf == 0)[0]
+    C = np.nonzero(lev.cf == 1)[0]
+    Ms = []
+    for name in sets_order:
+        X = F if name == "F" else C
+        X = X[np.abs(d[X]) >= 1e-30]
+        M = np.zeros((n, n))
+        M[X, X] = omega / d[X]
+        Ms.append(M)
+    Id = np.eye(n)
+    B = lev.P.toarray() @ Bc @ lev.R.toarray()
+    for M in Ms:                          # B <- M + (I - M A) B, sweep by sweep
+        B = M + (Id - M @ A) @ B
+    return B.T if transpose else B
+
+
+@pytest.mark.parametrize("relax, order", [("FFC", "FFC"), ("F", "F")])
+def test_vcycle_equals_dense_cycle_formula(relax, order):
+    """Pin of the cycle schedule: the oracle's V-cycle and its transpose equal
+    the dense matrix of the coarse-grid correction followed by the post
+    sweeps (F, F, C or F), to rounding, on a 3-level hierarchy; the wrong
+    schedules (C first, or the C sweep dropped) are far from it."""
+    v, c = square_tri_mesh(6)
+    s = setup_problem(v, c, C1Advection1D(1e-3), 2)
+    H = air.setup(s.Shat, max_coarse=40, relax=relax)
+    assert H.nlev >= 3
+    B = _dense_cycle_matrix(H, 0, order)
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((s.n, 4))
+    nb = np.linalg.norm(B, 2)
+    for k in range(X.shape[1]):
+        x = X[:, k]
+        assert np.linalg.norm(air.vcycle(H, x) - B @ x) <= 1e-13 * nb * np.linalg.norm(x)
+        assert np.linalg.norm(air.vcycle_T(H, x) - B.T @ x) <= 1e-13 * nb * np.linalg.norm(x)
+    if relax == "FFC":
+        for wrong in ("CFF", "FF", "FCF"):
+            Bw = _dense_cycle_matrix(H, 0, wrong)
+            assert np.linalg.norm(Bw - B, 2) > 1e-6 * nb, wrong
+
+
+def test_fp32_cycle_emulation():
+    """The FP32 emulation of the cycle is the FP64 cycle up to FP32 rounding:
+    its output is FP32, it agrees with the dense FP64 cycle matrix to about
+    the FP32 unit roundoff, and not to FP64 accuracy (it really rounds)."""
+    v, c = square_tri_mesh(6)
+    s = setup_problem(v, c, C1Advection1D(1e-3), 2)
+    H = air.setup(s.Shat, max_coarse=40)
+    B = _dense_cycle_matrix(H, 0, "FFC")
+    x = np.random.default_rng(22).standard_normal(s.n)
+    ref, refT = B @ x, B.T @ x
+    for z, zr in ((air.vcycle(H, x, dtype=np.float32), ref), (air.vcycle_T(H, x, dtype=np.float32), refT)):
+        assert z.dtype == np.float32
+        e = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+        assert 1e-9 < e < 1e-5, e
