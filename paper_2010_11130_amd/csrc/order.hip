@@ -326,11 +326,7 @@ ah_status flow_order_build(ah_hier* h, hipStream_t st) {
     set_error("air_setup: flow order lost F rows");
     return AH_EINVAL;
   }
-  // sweep records (value slots as int32)
-  if (nslot >= ((int64_t)1 << 31)) {
-    set_error("air_setup: level 0 too large for the ordered sweeps");
-    return AH_EUNSUPPORTED;
-  }
+  // sweep records (value slots as int32, checked above)
   const int64_t nF = L.n - L.nc;
   OK_(h->arena.get(&h->ord_info, nbr));
   OK_(h->arena.get(&h->ord_finfo, nF + 1));
