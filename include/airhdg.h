@@ -282,6 +282,26 @@ void ah_solve_defaults(ah_solve_params* p);
 ah_status air_solve(const ah_hier* h, const double* rhs, double* x, const ah_solve_params* prm,
                     void* stream, ah_solve_info* info);
 
+/* Allocation-free air_solve, for callers that cannot allocate device or
+ * pinned host memory (code under HIP graph capture elsewhere on the stream,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * semantics and results as air_solve with method 0 (FGMRES); the FGMRES
+ * workspace comes from a static device array of AH_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every GPU it runs on until the process ends,
+ * and the host staging is a static per-thread array.  It needs
+ * 8 ((2 m + 4) n + 1024 (m + 3) + 4 (m + 3)) bytes (FP32 cycle: the m Z
+ * vectors take 4 bytes per value), rounded up to 256-byte pieces, with
+ * m = restart <= AH_NOALLOC_MAX_RESTART.  Returns AH_EUNSUPPORTED for a
+ * larger workspace, a larger restart or method 1, before any device work.
+ * Every call on a GPU shares that GPU's array and leaves its last contents
+ * there: calls that overlap on one GPU (from several threads or streams)
+ * race.  The hierarchy, x and rhs must belong to the current device.
+ * Synchronizes the stream. */
+#define AH_NOALLOC_SCRATCH_BYTES (64ll * 1024 * 1024)
+#define AH_NOALLOC_MAX_RESTART 128
+ah_status air_solve_noalloc(const ah_hier* h, const double* rhs, double* x, const ah_solve_params* prm,
+                            void* stream, ah_solve_info* info);
+
 /* Adjoint solve S^T lam = g: FGMRES on S_hat^T mu = g with the transposed
  * V-cycle (sweeps C,F,F with A_l^T, restriction by P_l^T, interpolation by
  * R_l^T, transposed coarsest solve), then lam = D_b^-T mu.  g dev [n_free],

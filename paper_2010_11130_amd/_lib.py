@@ -78,6 +78,7 @@ SIGNATURES = {
     "ah_solve_defaults": (None, [C.POINTER(SolveParams)]),
     "air_solve": (i32, [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveInfo)]),
     "air_solve_adjoint": (i32, [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveInfo)]),
+    "air_solve_noalloc": (i32, [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveInfo)]),
     "ah_vcycle_apply": (i32, [vp, vp, vp, i32, i32, vp]),
     "hdg_assemble_grad": (i32, [vp, vp, vp, vp, vp, C.POINTER(C.c_double), vp]),
     "ah_source_gauss": (i32, [i32, i64, vp, i32, vp, dbl, vp, vp, vp]),

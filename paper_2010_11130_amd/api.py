@@ -237,8 +237,10 @@ class Hierarchy:
             _destroy("ah_hier_destroy", self.h)
             self.h = None
 
-    def solve(self, rhs=None, x0=None, out=None, **kw):
-        """FGMRES + V-cycle: ``S Lambda = rhs`` (unscaled; ``None`` = assembled H)."""
+    def solve(self, rhs=None, x0=None, out=None, noalloc=False, **kw):
+        """FGMRES + V-cycle: ``S Lambda = rhs`` (unscaled; ``None`` = assembled H).
+        ``noalloc``: through ``air_solve_noalloc`` (workspace in the library's
+        static scratch array; pass ``out`` to allocate nothing here either)."""
         prm = solve_params(**kw)
         n = self.system.n
         rhs = _vec(rhs, n, "rhs")
@@ -248,8 +250,9 @@ class Hierarchy:
             x.copy_(_vec(x0, n, "x0"))
             prm.x0_given = 1
         info = SolveInfo()
-        st = check(lib().air_solve(self.h, _p(rhs), _p(x), C.byref(prm), _stream(), C.byref(info)),
-                   "air_solve", allow=(AH_OK, AH_ENOCONV))
+        fn = lib().air_solve_noalloc if noalloc else lib().air_solve
+        st = check(fn(self.h, _p(rhs), _p(x), C.byref(prm), _stream(), C.byref(info)),
+                   "air_solve_noalloc" if noalloc else "air_solve", allow=(AH_OK, AH_ENOCONV))
         return x, _info(info, st)
 
     def solve_adjoint(self, g, out=None, **kw):

@@ -1432,24 +1432,53 @@ static ah_status precond(ah_hier* h, const double* r, double* z, float* z32, int
 }
 
 // ------------------------------------------------------------ FGMRES
-static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t st) {
+// Workspace of one FGMRES solve: basis V [(m+1)][n], preconditioned vectors
+// Z [m][n] (FP64 cycle) or Z32 (FP32 cycle), w, r, the scaled right-hand
+// side, the reduction partials [(m+3)][1024], the device scalars [4 (m+3)]
+// and a host staging array of 4 (m+3) doubles for the Hessenberg column.
+// air_solve takes it from buffers the hierarchy keeps; air_solve_noalloc
+// carves it out of the library's static scratch array.
+struct KWork {
+  double* V = nullptr;
+  double* Z = nullptr;
+  float* Z32 = nullptr;
+  double* w = nullptr;
+  double* r = nullptr;
+  double* bhat = nullptr;
+  double* partial = nullptr;
+  double* hdev = nullptr;
+  double* host = nullptr;
+};
+
+static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t st, KWork* W) {
   const int64_t n = h->lev[0].n;
-  if (h->m_alloc >= m && (precision == 0 ? h->Z != nullptr : h->Z32 != nullptr)) return AH_OK;
-  Arena& ar = h->arena;
-  ar.stream = st;   // the workspace is allocated on the solving stream
-  if (h->m_alloc < m) {
-    AH_TRY(ar.get(&h->V, (int64_t)(m + 1) * n));
-    AH_TRY(ar.get(&h->w, n));
-    AH_TRY(ar.get(&h->r, n));
-    AH_TRY(ar.get(&h->bhat, n));
-    AH_TRY(ar.get(&h->partial, (int64_t)(m + 3) * 1024));
-    AH_TRY(ar.get(&h->hdev, 4 * (m + 3)));
-    h->Z = nullptr;
-    h->Z32 = nullptr;
-    h->m_alloc = m;
+  if (!(h->m_alloc >= m && (precision == 0 ? h->Z != nullptr : h->Z32 != nullptr))) {
+    Arena& ar = h->arena;
+    ar.stream = st;   // the workspace is allocated on the solving stream
+    if (h->m_alloc < m) {
+      AH_TRY(ar.get(&h->V, (int64_t)(m + 1) * n));
+      AH_TRY(ar.get(&h->w, n));
+      AH_TRY(ar.get(&h->r, n));
+      AH_TRY(ar.get(&h->bhat, n));
+      AH_TRY(ar.get(&h->partial, (int64_t)(m + 3) * 1024));
+      AH_TRY(ar.get(&h->hdev, 4 * (m + 3)));
+      h->Z = nullptr;
+      h->Z32 = nullptr;
+      h->m_alloc = m;
+    }
+    if (precision == 0 && !h->Z) AH_TRY(ar.get(&h->Z, (int64_t)m * n));
+    if (precision == 1 && !h->Z32) AH_TRY(ar.get(&h->Z32, (int64_t)m * n));
   }
-  if (precision == 0 && !h->Z) AH_TRY(ar.get(&h->Z, (int64_t)m * n));
-  if (precision == 1 && !h->Z32) AH_TRY(ar.get(&h->Z32, (int64_t)m * n));
+  W->V = h->V;
+  W->Z = precision == 0 ? h->Z : nullptr;
+  W->Z32 = precision == 1 ? h->Z32 : nullptr;
+  W->w = h->w;
+  W->r = h->r;
+  W->bhat = h->bhat;
+  W->partial = h->partial;
+  W->hdev = h->hdev;
+  W->host = pinned_scratch(4 * (m + 3));
+  if (!W->host) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
   return AH_OK;
 }
 
@@ -1580,18 +1609,16 @@ static ah_status op_apply(const Op& A, int G, int64_t n, const TX* x, const doub
                                          (const int8_t*)nullptr, 0, 0.0, y, st, tag, bytes);
 }
 
-static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const ah_solve_params& prm, int transpose,
-                        hipStream_t st, ah_solve_info* info) {
+static ah_status fgmres(ah_hier* h, const KWork& W, Op A, const double* bvec, double* x, const ah_solve_params& prm,
+                        int transpose, hipStream_t st, ah_solve_info* info) {
   const int64_t n = h->lev[0].n;
   const int m = std::max(1, prm.restart);
-  AH_TRY(ensure_workspace(h, m, prm.precision, st));
   const int G0 = op_lanes(h, A, n);
-  double* hd = h->hdev;
-  double* hh = pinned_scratch(4 * (m + 3));
-  if (!hh) { set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  double* hd = W.hdev;
+  double* hh = W.host;
   auto t0 = std::chrono::steady_clock::now();
   // ||b||
-  AH_TRY(multidot(n, 0, h->V, bvec, h->partial, hd, st));
+  AH_TRY(multidot(n, 0, W.V, bvec, W.partial, hd, st));
   AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
   AH_HIP(hipStreamSynchronize(st));
   const double bnorm = std::sqrt(hh[0]);
@@ -1608,8 +1635,8 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
   if (!std::isfinite(bnorm)) { set_error("air_solve: non-finite right-hand side"); return AH_EBREAKDOWN; }
   while (true) {
     // r = b - A x
-    AH_TRY((op_apply<double, SP_RES>(A, G0, n, x, bvec, h->r, st)));
-    AH_TRY(multidot(n, 0, h->V, h->r, h->partial, hd, st));
+    AH_TRY((op_apply<double, SP_RES>(A, G0, n, x, bvec, W.r, st)));
+    AH_TRY(multidot(n, 0, W.V, W.r, W.partial, hd, st));
     AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
     AH_HIP(hipStreamSynchronize(st));
     const double beta = std::sqrt(hh[0]);
@@ -1618,23 +1645,23 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
     if (!std::isfinite(beta)) { set_error("air_solve: breakdown (NaN residual)"); status = AH_EBREAKDOWN; break; }
     if (beta <= prm.tol * bnorm) { converged = true; break; }
     if (its >= prm.maxit) break;
-    hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, h->r, 1.0 / beta, h->V);
+    hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, W.r, 1.0 / beta, W.V);
     AH_LAUNCHED();
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int kdone = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->V + (int64_t)j * n;
-      double* zj = h->Z ? h->Z + (int64_t)j * n : nullptr;
-      float* zj32 = h->Z32 ? h->Z32 + (int64_t)j * n : nullptr;
+      double* vj = W.V + (int64_t)j * n;
+      double* zj = W.Z ? W.Z + (int64_t)j * n : nullptr;
+      float* zj32 = W.Z32 ? W.Z32 + (int64_t)j * n : nullptr;
       AH_TRY(precond(h, vj, prm.precision == 0 ? zj : nullptr, prm.precision == 1 ? zj32 : nullptr, prm.precision,
                      transpose, st));
       const double by = op_mv_bytes(h, A, n, prm.precision ? 4.0 : 8.0);
       if (prm.precision == 0)
-        AH_TRY((op_apply<double, SP_MV>(A, G0, n, zj, (const double*)nullptr, h->w, st,
+        AH_TRY((op_apply<double, SP_MV>(A, G0, n, zj, (const double*)nullptr, W.w, st,
                                         transpose ? nullptr : "spmv0", by)));
       else
-        AH_TRY((op_apply<float, SP_MV>(A, G0, n, zj32, (const double*)nullptr, h->w, st,
+        AH_TRY((op_apply<float, SP_MV>(A, G0, n, zj32, (const double*)nullptr, W.w, st,
                                        transpose ? nullptr : "spmv0", by)));
       ++its;
       const int k = j + 1;
@@ -1647,13 +1674,13 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       {
         const int nblk = dot_blocks(n);
         const unsigned hb = (unsigned)((k + 1) * sizeof(double));
-        double* p3 = h->partial + (int64_t)(m + 2) * 1024;   // clear of the (k+1) nblk dot partials
-        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, h->V, n,
-                           h->w, h->partial, nblk);
-        hipLaunchKernelGGL(k_maxpy_p, dim3(nblk), dim3(DOT_T), hb, st, n, k, h->V, n, h->partial, nblk, h->w, h1);
-        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, h->V, n,
-                           h->w, h->partial, nblk);
-        hipLaunchKernelGGL(k_maxpy_norm, dim3(nblk), dim3(DOT_T), hb, st, n, k, h->V, n, h->partial, nblk, h->w, h2,
+        double* p3 = W.partial + (int64_t)(m + 2) * 1024;   // clear of the (k+1) nblk dot partials
+        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, W.V, n,
+                           W.w, W.partial, nblk);
+        hipLaunchKernelGGL(k_maxpy_p, dim3(nblk), dim3(DOT_T), hb, st, n, k, W.V, n, W.partial, nblk, W.w, h1);
+        hipLaunchKernelGGL(k_multidot, dim3(nblk, (unsigned)cdiv(k + 1, DOT_V)), dim3(DOT_T), 0, st, n, k, W.V, n,
+                           W.w, W.partial, nblk);
+        hipLaunchKernelGGL(k_maxpy_norm, dim3(nblk), dim3(DOT_T), hb, st, n, k, W.V, n, W.partial, nblk, W.w, h2,
                            p3);
         hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, st, nblk, p3, hn, 0);
         AH_LAUNCHED();
@@ -1686,7 +1713,7 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
       relres = std::fabs(g[k]) / bnorm;
       const bool happy = hnorm <= 1e-14 * w0;
       if (std::fabs(g[k]) <= prm.tol * bnorm || happy || its >= prm.maxit) break;
-      hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, h->w, 1.0 / hnorm, h->V + (int64_t)k * n);
+      hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, W.w, 1.0 / hnorm, W.V + (int64_t)k * n);
       AH_LAUNCHED();
     }
     if (status != AH_OK && kdone == 0) break;
@@ -1697,9 +1724,9 @@ static ah_status fgmres(ah_hier* h, Op A, const double* bvec, double* x, const a
     }
     AH_HIP(hipMemcpyAsync(hd, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, st));
     if (prm.precision == 0)
-      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, kdone, h->Z, n, hd, x, 1.0);
+      hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, kdone, W.Z, n, hd, x, 1.0);
     else
-      hipLaunchKernelGGL(k_maxpy<float>, g1(n), dim3(256), 0, st, n, kdone, h->Z32, n, hd, x, 1.0);
+      hipLaunchKernelGGL(k_maxpy<float>, g1(n), dim3(256), 0, st, n, kdone, W.Z32, n, hd, x, 1.0);
     AH_LAUNCHED();
     if (status != AH_OK) break;
   }
@@ -1842,6 +1869,59 @@ static ah_status bicgstab(ah_hier* h, Op A, const double* bvec, double* x, const
   return converged ? AH_OK : AH_ENOCONV;
 }
 
+// ------------------------------------------------ allocation-free solve
+// The FGMRES workspace of air_solve_noalloc lives in this file-scope device
+// array (one copy per GPU, held until the process ends).  In host code the
+// name is only a stand-in for the symbol: the device address of each GPU's
+// copy comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and only that address is passed to kernels.
+constexpr size_t kScratchBytes = (size_t)AH_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<char*> g_scratch_addr;   // indexed by device id
+
+static ah_status scratch_address(char** out) {
+  int dev = 0;
+  AH_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("air_solve_noalloc: hipGetSymbolAddress of the scratch array failed (%s)", hipGetErrorString(e));
+      return AH_EHIP;
+    }
+    g_scratch_addr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return AH_OK;
+}
+
+// Lays the FGMRES workspace for n unknowns and restart m out from base in
+// 256-byte aligned pieces (base == nullptr: sizes only); returns the bytes.
+static size_t carve_workspace(char* base, int64_t n, int m, int precision, KWork* W) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t nd = (size_t)n * sizeof(double);
+  W->V = reinterpret_cast<double*>(take((size_t)(m + 1) * nd));
+  if (precision == 0)
+    W->Z = reinterpret_cast<double*>(take((size_t)m * nd));
+  else
+    W->Z32 = reinterpret_cast<float*>(take((size_t)m * (size_t)n * sizeof(float)));
+  W->w = reinterpret_cast<double*>(take(nd));
+  W->r = reinterpret_cast<double*>(take(nd));
+  W->bhat = reinterpret_cast<double*>(take(nd));
+  W->partial = reinterpret_cast<double*>(take((size_t)(m + 3) * 1024 * sizeof(double)));
+  W->hdev = reinterpret_cast<double*>(take((size_t)4 * (m + 3) * sizeof(double)));
+  return off;
+}
+
 }  // namespace ah
 
 using namespace ah;
@@ -1874,6 +1954,32 @@ static ah_status check_solve(const ah_hier* h, const ah_solve_params* prm, int t
   return AH_OK;
 }
 
+// Forward solve with a given workspace (W.bhat holds the scaled
+// right-hand side when rhs is given).
+static ah_status solve_forward(ah_hier* h, const KWork& W, const double* rhs, double* x, const ah_solve_params& prm,
+                               hipStream_t st, ah_solve_info* info) {
+  const ah_system* s = h->sys;
+  const int64_t n = s->n;
+  const double* b = s->d_Hhat;
+  if (rhs) {
+    hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, rhs, W.bhat, 0);
+    AH_LAUNCHED();
+    b = W.bhat;
+  }
+  if (!prm.x0_given) AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+  Op A{s->d_rowptr, s->d_col, s->d_val};
+  const AhLevel& L0 = h->lev[0];
+  if (L0.ob) {
+    A.ob = L0.ob;
+    A.optr = L0.optr;
+    A.ocol = L0.ocol;
+    A.ov = L0.oval;
+    A.nov = L0.nov;
+  }
+  if (prm.method == 1) return bicgstab(h, A, b, x, prm, 0, st, info);
+  return fgmres(h, W, A, b, x, prm, 0, st, info);
+}
+
 extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, const ah_solve_params* prm,
                                void* stream, ah_solve_info* info) {
   AH_TRY(check_solve(hc, prm, 0));
@@ -1884,27 +1990,44 @@ extern "C" ah_status air_solve(const ah_hier* hc, const double* rhs, double* x, 
   if (!x) { set_error("air_solve: null x"); return AH_EINVAL; }
   ah_hier* h = const_cast<ah_hier*>(hc);
   hipStream_t st = as_stream(stream);
-  const ah_system* s = h->sys;
-  const int64_t n = s->n;
-  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st));
-  const double* b = s->d_Hhat;
-  if (rhs) {
-    hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, rhs, h->bhat, 0);
-    AH_LAUNCHED();
-    b = h->bhat;
+  KWork W;
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st, &W));
+  return solve_forward(h, W, rhs, x, *prm, st, info);
+}
+
+extern "C" ah_status air_solve_noalloc(const ah_hier* hc, const double* rhs, double* x,
+                                       const ah_solve_params* prm, void* stream, ah_solve_info* info) {
+  AH_TRY(check_solve(hc, prm, 0));
+  if (prm->method != 0) {
+    set_error("air_solve_noalloc: only FGMRES (method 0) runs without allocation");
+    return AH_EUNSUPPORTED;
   }
-  if (!prm->x0_given) AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
-  Op A{s->d_rowptr, s->d_col, s->d_val};
-  const AhLevel& L0 = h->lev[0];
-  if (L0.ob) {
-    A.ob = L0.ob;
-    A.optr = L0.optr;
-    A.ocol = L0.ocol;
-    A.ov = L0.oval;
-    A.nov = L0.nov;
+  if (prm->restart > AH_NOALLOC_MAX_RESTART) {
+    set_error("air_solve_noalloc: restart %d exceeds %d", prm->restart, AH_NOALLOC_MAX_RESTART);
+    return AH_EUNSUPPORTED;
   }
-  if (prm->method == 1) return bicgstab(h, A, b, x, *prm, 0, st, info);
-  return fgmres(h, A, b, x, *prm, 0, st, info);
+  if (hc->sys->n == 0) {
+    if (info) { std::memset(info, 0, sizeof(*info)); info->converged = 1; }
+    return AH_OK;
+  }
+  if (!x) { set_error("air_solve_noalloc: null x"); return AH_EINVAL; }
+  ah_hier* h = const_cast<ah_hier*>(hc);
+  hipStream_t st = as_stream(stream);
+  const int m = std::max(1, prm->restart);
+  const int64_t n = h->sys->n;
+  KWork W;
+  const size_t need = carve_workspace(nullptr, n, m, prm->precision, &W);
+  if (need > kScratchBytes) {
+    set_error("air_solve_noalloc: workspace of %zu bytes (n = %lld, restart = %d) exceeds the %zu-byte scratch array",
+              need, (long long)n, m, kScratchBytes);
+    return AH_EUNSUPPORTED;
+  }
+  char* base = nullptr;
+  AH_TRY(scratch_address(&base));
+  carve_workspace(base, n, m, prm->precision, &W);
+  static thread_local double stage[4 * (AH_NOALLOC_MAX_RESTART + 3)];   // pageable host staging
+  W.host = stage;
+  return solve_forward(h, W, rhs, x, *prm, st, info);
 }
 
 extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, double* lam, const ah_solve_params* prm,
@@ -1919,8 +2042,9 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
   hipStream_t st = as_stream(stream);
   const ah_system* s = h->sys;
   const int64_t n = s->n;
-  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st));
-  double* mu = h->bhat;   // S_hat^T mu = g, then lam = D_b^-T mu
+  KWork W;
+  AH_TRY(ensure_workspace(h, std::max(1, prm->restart), prm->precision, st, &W));
+  double* mu = W.bhat;   // S_hat^T mu = g, then lam = D_b^-T mu
   AhLevel& L0 = h->lev[0];
   if (!L0.ATptr && !L0.otval) {
     set_error("air_solve_adjoint: transposed level-0 operator missing");
@@ -1935,7 +2059,8 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
     AT.ov = L0.otval;
     AT.nov = L0.nov;
   }
-  ah_status rc = prm->method == 1 ? bicgstab(h, AT, g, mu, *prm, 1, st, info) : fgmres(h, AT, g, mu, *prm, 1, st, info);
+  ah_status rc = prm->method == 1 ? bicgstab(h, AT, g, mu, *prm, 1, st, info)
+                                   : fgmres(h, W, AT, g, mu, *prm, 1, st, info);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_blockscale, g1(n), dim3(256), 0, st, s->nfree, s->b, s->d_Dinv, mu, lam, 1);
   AH_LAUNCHED();
