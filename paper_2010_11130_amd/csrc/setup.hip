@@ -1454,6 +1454,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   // by one workgroup inside a single launch per cycle
   {
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
+    if (const char* e = std::getenv("AH_DCGS_MIN")) h->dcgs_min = std::atoll(e);
     if (h->g0 != 2 && h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();
     std::vector<TailLevel> tl(nl);

@@ -919,6 +919,96 @@ __global__ __launch_bounds__(DOT_T) void k_maxpy_norm(int64_t n, int k, const do
   }
 }
 
+// Delayed CGS2 (the second projection of each basis vector is done one
+// step late, together with the first projection of the next one), dot pass.
+// With the j finished basis vectors Q_l = V[l] (l < j), the candidate
+// u = V[j] and the new vector w (or none): block partials of Q_l.u at row l,
+// Q_l.w at row j + l, then u.u, u.w, w.w at rows 2j, 2j+1, 2j+2.  Blocks
+// along y take DD_V basis vectors each; the blocks of y = 0 also form the
+// three scalars.
+constexpr int DD_V = 16;
+
+__global__ __launch_bounds__(256) void k_dcgs_dot(int64_t n, int j, const double* __restrict__ V,
+                                                  const double* __restrict__ w, double* __restrict__ partial,
+                                                  int nblk) {
+  __shared__ double red[2 * DD_V + 3][4];
+  const int l0 = blockIdx.y * DD_V;
+  const int nl = min(DD_V, j - l0);
+  const double* __restrict__ u = V + (int64_t)j * n;
+  const bool first = blockIdx.y == 0;
+  double aa[DD_V], cc[DD_V];
+#pragma unroll
+  for (int q = 0; q < DD_V; ++q) aa[q] = cc[q] = 0.0;
+  double su = 0.0, sw = 0.0, ww = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+    const double ui = u[i];
+    const double wi = w ? w[i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < DD_V; ++q)
+      if (q < nl) {
+        const double qv = V[(int64_t)(l0 + q) * n + i];
+        aa[q] += qv * ui;
+        cc[q] += qv * wi;
+      }
+    if (first) {
+      su += ui * ui;
+      sw += ui * wi;
+      ww += wi * wi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  auto wave_sum = [&](double a) {
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
+  };
+#pragma unroll
+  for (int q = 0; q < DD_V; ++q) {
+    const double a = wave_sum(aa[q]);
+    const double c = wave_sum(cc[q]);
+    if (lane == 0) { red[q][wv] = a; red[DD_V + q][wv] = c; }
+  }
+  {
+    const double a = wave_sum(su), b = wave_sum(sw), c = wave_sum(ww);
+    if (lane == 0) { red[2 * DD_V][wv] = a; red[2 * DD_V + 1][wv] = b; red[2 * DD_V + 2][wv] = c; }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * DD_V + 3) {
+    const double s = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+    int row = -1;
+    if (t < DD_V) { if (t < nl) row = l0 + t; }
+    else if (t < 2 * DD_V) { if (t - DD_V < nl) row = j + l0 + (t - DD_V); }
+    else if (first) row = 2 * j + (t - 2 * DD_V);
+    if (row >= 0) partial[(int64_t)row * nblk + blockIdx.x] = s;
+  }
+}
+
+// Delayed CGS2, update pass: with coef = [a (j), c (j), d, 1/r], the
+// finished vector q = (u - Q a) / r is written over u = V[j] and the next
+// candidate (w - Q c - q d) / r into V[j+1] (one read of Q for both).
+// Dynamic LDS: 2j + 2 doubles.
+__global__ __launch_bounds__(256) void k_dcgs_update(int64_t n, int j, double* __restrict__ V,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ coef) {
+  extern __shared__ double cf[];
+  for (int t = threadIdx.x; t < 2 * j + 2; t += blockDim.x) cf[t] = coef[t];
+  __syncthreads();
+  const double d = cf[2 * j], rinv = cf[2 * j + 1];
+  double* __restrict__ u = V + (int64_t)j * n;
+  double* __restrict__ un = V + (int64_t)(j + 1) * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double sa = 0.0, sc = 0.0;
+    for (int l = 0; l < j; ++l) {
+      const double qv = V[(int64_t)l * n + i];
+      sa += qv * cf[l];
+      sc += qv * cf[j + l];
+    }
+    const double q = (u[i] - sa) * rinv;
+    u[i] = q;
+    un[i] = (w[i] - sc - q * d) * rinv;
+  }
+}
+
 // w -= sum_v V_v h_v
 template <class TV>
 __global__ void k_maxpy(int64_t n, int k, const TV* __restrict__ V, int64_t ldv, const double* __restrict__ h,
@@ -1434,7 +1524,7 @@ static ah_status precond(ah_hier* h, const double* r, double* z, float* z32, int
 // ------------------------------------------------------------ FGMRES
 // Workspace of one FGMRES solve: basis V [(m+1)][n], preconditioned vectors
 // Z [m][n] (FP64 cycle) or Z32 (FP32 cycle), w, r, the scaled right-hand
-// side, the reduction partials [(m+3)][1024], the device scalars [4 (m+3)]
+// side, the reduction partials [(2m+4)][1024], the device scalars [4 (m+3)]
 // and a host staging array of 4 (m+3) doubles for the Hessenberg column.
 // air_solve takes it from buffers the hierarchy keeps; air_solve_noalloc
 // carves it out of the library's static scratch array.
@@ -1460,7 +1550,7 @@ static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t 
       AH_TRY(ar.get(&h->w, n));
       AH_TRY(ar.get(&h->r, n));
       AH_TRY(ar.get(&h->bhat, n));
-      AH_TRY(ar.get(&h->partial, (int64_t)(m + 3) * 1024));
+      AH_TRY(ar.get(&h->partial, (int64_t)(2 * m + 4) * 1024));
       AH_TRY(ar.get(&h->hdev, 4 * (m + 3)));
       h->Z = nullptr;
       h->Z32 = nullptr;
@@ -1609,9 +1699,13 @@ static ah_status op_apply(const Op& A, int G, int64_t n, const TX* x, const doub
                                          (const int8_t*)nullptr, 0, 0.0, y, st, tag, bytes);
 }
 
+static ah_status fgmres_dcgs2(ah_hier* h, const KWork& W, Op A, const double* bvec, double* x,
+                              const ah_solve_params& prm, int transpose, hipStream_t st, ah_solve_info* info);
+
 static ah_status fgmres(ah_hier* h, const KWork& W, Op A, const double* bvec, double* x, const ah_solve_params& prm,
                         int transpose, hipStream_t st, ah_solve_info* info) {
   const int64_t n = h->lev[0].n;
+  if (n >= h->dcgs_min) return fgmres_dcgs2(h, W, A, bvec, x, prm, transpose, st, info);
   const int m = std::max(1, prm.restart);
   const int G0 = op_lanes(h, A, n);
   double* hd = W.hdev;
@@ -1728,6 +1822,189 @@ static ah_status fgmres(ah_hier* h, const KWork& W, Op A, const double* bvec, do
     else
       hipLaunchKernelGGL(k_maxpy<float>, g1(n), dim3(256), 0, st, n, kdone, W.Z32, n, hd, x, 1.0);
     AH_LAUNCHED();
+    if (status != AH_OK) break;
+  }
+  AH_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = its;
+    info->converged = converged ? 1 : 0;
+    info->relres = relres;
+    info->true_relres = true_rel;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status != AH_OK) return status;
+  return converged ? AH_OK : AH_ENOCONV;
+}
+
+// FGMRES with delayed CGS2 orthogonalisation: the basis is read twice per
+// iteration instead of four times.  The candidate u_j (w_{j-1} projected
+// once, not normalised) is preconditioned and multiplied right away,
+// z~_j = M u_j, w_j = A z~_j; one dot pass then gives Q^T u_j, |u_j|^2,
+// Q^T w_j and u_j.w_j.  The second projection of u_j finishes it,
+// u_j = Q a + r_jj q_j with r_jj = sqrt(|u_j|^2 - |a|^2), and completes
+// Hessenberg column j-1 (+a, subdiagonal r_jj).  Since A is linear,
+// A z_j = (w_j - A Z a) / r_jj for z_j = (z~_j - Z a) / r_jj, which gives
+// column j from the dots and the finished columns, and the next candidate
+// u_{j+1} = (w_j - Q c - q_j d) / r_jj, formed in one update pass together
+// with q_j.  The solution uses z~ directly: Z~ = Z R with R upper triangular
+// (column j = [a; r_jj]), so x += Z~ (R^-1 y).  Convergence of column j-1
+// is known one step late, after z~_j and w_j are formed: one extra cycle
+// per restart cycle, which is why the plain CGS2 loop is kept for small
+// systems.
+static ah_status fgmres_dcgs2(ah_hier* h, const KWork& W, Op A, const double* bvec, double* x,
+                              const ah_solve_params& prm, int transpose, hipStream_t st, ah_solve_info* info) {
+  const int64_t n = h->lev[0].n;
+  const int m = std::max(1, prm.restart);
+  const int G0 = op_lanes(h, A, n);
+  double* hd = W.hdev;
+  double* hh = W.host;
+  double* coef_d = hd + (2 * m + 3);
+  double* coef_h = hh + (2 * m + 3);
+  const int nblk = dot_blocks(n);
+  auto t0 = std::chrono::steady_clock::now();
+  AH_TRY(multidot(n, 0, W.V, bvec, W.partial, hd, st));
+  AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+  AH_HIP(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(hh[0]);
+  if (!(bnorm > 0.0)) {
+    AH_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+    if (info) { info->iters = 0; info->converged = 1; info->relres = 0; info->true_relres = 0; }
+    return AH_OK;
+  }
+  if (!std::isfinite(bnorm)) { set_error("air_solve: non-finite right-hand side"); return AH_EBREAKDOWN; }
+  // Hr: Hessenberg columns as formed (rows 0..m); Hg: the same after the
+  // Givens rotations; Rt: the triangular factor of Z~ = Z R
+  std::vector<double> Hr((size_t)(m + 1) * m), Hg((size_t)(m + 1) * m), Rt((size_t)m * m), cs(m), sn(m),
+      g(m + 1), y(m), t(m);
+  int its = 0;
+  bool converged = false;
+  double relres = 1.0, true_rel = 1.0;
+  ah_status status = AH_OK;
+  while (true) {
+    // u_0 = r = b - A x, the first candidate (r_00 = ||r||)
+    AH_TRY((op_apply<double, SP_RES>(A, G0, n, x, bvec, W.V, st)));
+    AH_TRY(multidot(n, 0, W.V, W.V, W.partial, hd, st));
+    AH_HIP(hipMemcpyAsync(hh, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+    AH_HIP(hipStreamSynchronize(st));
+    const double beta = std::sqrt(hh[0]);
+    true_rel = beta / bnorm;
+    relres = true_rel;
+    if (!std::isfinite(beta)) { set_error("air_solve: breakdown (NaN residual)"); status = AH_EBREAKDOWN; break; }
+    if (beta <= prm.tol * bnorm) { converged = true; break; }
+    if (its >= prm.maxit) break;
+    std::fill(Hr.begin(), Hr.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kdone = 0;
+    double wnorm_prev = 0.0;   // ||A z_{j-1}||, for the breakdown test
+    for (int j = 0; j <= m; ++j) {
+      double* uj = W.V + (int64_t)j * n;
+      const bool more = j < m && its + (j >= 1 ? 1 : 0) < prm.maxit;
+      if (more) {
+        double* zj = W.Z ? W.Z + (int64_t)j * n : nullptr;
+        float* zj32 = W.Z32 ? W.Z32 + (int64_t)j * n : nullptr;
+        AH_TRY(precond(h, uj, prm.precision == 0 ? zj : nullptr, prm.precision == 1 ? zj32 : nullptr,
+                       prm.precision, transpose, st));
+        const double by = op_mv_bytes(h, A, n, prm.precision ? 4.0 : 8.0);
+        if (prm.precision == 0)
+          AH_TRY((op_apply<double, SP_MV>(A, G0, n, zj, (const double*)nullptr, W.w, st,
+                                          transpose ? nullptr : "spmv0", by)));
+        else
+          AH_TRY((op_apply<float, SP_MV>(A, G0, n, zj32, (const double*)nullptr, W.w, st,
+                                         transpose ? nullptr : "spmv0", by)));
+      }
+      {
+        ProfScope ps;
+        prof_begin(ps, transpose ? nullptr : "arnoldi_dot", st, (double)(j + 2) * n * 8.0);
+        hipLaunchKernelGGL(k_dcgs_dot, dim3(nblk, (unsigned)std::max<int64_t>(1, cdiv(j, DD_V))), dim3(256), 0, st,
+                           n, j, W.V, more ? W.w : nullptr, W.partial, nblk);
+        prof_end(ps);
+        AH_LAUNCHED();
+      }
+      hipLaunchKernelGGL(k_reduce_partial, dim3(2 * j + 3), dim3(256), 0, st, nblk, W.partial, hd, 0);
+      AH_LAUNCHED();
+      AH_HIP(hipMemcpyAsync(hh, hd, (2 * j + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
+      AH_HIP(hipStreamSynchronize(st));
+      const double* a = hh;
+      const double* c = hh + j;
+      const double alpha = hh[2 * j], gamma = hh[2 * j + 1], omega = hh[2 * j + 2];
+      double aa = 0.0, ac = 0.0;
+      for (int i = 0; i < j; ++i) { aa += a[i] * a[i]; ac += a[i] * c[i]; }
+      if (!std::isfinite(alpha) || !std::isfinite(gamma) || !std::isfinite(omega) || !std::isfinite(aa)) {
+        set_error("air_solve: breakdown (NaN in Arnoldi)");
+        status = AH_EBREAKDOWN;
+        break;
+      }
+      const double rjj = alpha > aa ? std::sqrt(alpha - aa) : 0.0;
+      if (j >= 1) {
+        // column j-1 is complete: A z_{j-1} = Q (h + a) + r_jj q_j
+        const int k = j - 1;
+        for (int i = 0; i < j; ++i) Hr[(size_t)i * m + k] += a[i];
+        Hr[(size_t)j * m + k] = rjj;
+        for (int i = 0; i <= j; ++i) Hg[(size_t)i * m + k] = Hr[(size_t)i * m + k];
+        for (int i = 0; i < k; ++i) {
+          const double p = Hg[(size_t)i * m + k], q = Hg[(size_t)(i + 1) * m + k];
+          Hg[(size_t)i * m + k] = cs[i] * p + sn[i] * q;
+          Hg[(size_t)(i + 1) * m + k] = -sn[i] * p + cs[i] * q;
+        }
+        const double p = Hg[(size_t)k * m + k], q = Hg[(size_t)j * m + k];
+        const double den = std::hypot(p, q);
+        if (den == 0.0) { cs[k] = 1.0; sn[k] = 0.0; } else { cs[k] = p / den; sn[k] = q / den; }
+        Hg[(size_t)k * m + k] = cs[k] * p + sn[k] * q;
+        Hg[(size_t)j * m + k] = 0.0;
+        g[j] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        ++its;
+        kdone = j;
+        relres = std::fabs(g[j]) / bnorm;
+        const bool happy = rjj <= 1e-14 * wnorm_prev;
+        if (std::fabs(g[j]) <= prm.tol * bnorm || happy || its >= prm.maxit) break;
+      }
+      if (!more || !(rjj > 0.0)) break;
+      // R column j, then Hessenberg column j as formed (rows 0..j)
+      for (int i = 0; i < j; ++i) Rt[(size_t)i * m + j] = a[i];
+      Rt[(size_t)j * m + j] = rjj;
+      const double d = (gamma - ac) / rjj;
+      for (int i = 0; i <= j; ++i) {
+        double s = i < j ? c[i] : d;
+        for (int l = std::max(0, i - 1); l < j; ++l) s -= Hr[(size_t)i * m + l] * a[l];
+        Hr[(size_t)i * m + j] = s / rjj;
+      }
+      wnorm_prev = std::sqrt(omega) / rjj;
+      for (int i = 0; i < j; ++i) { coef_h[i] = a[i]; coef_h[j + i] = c[i]; }
+      coef_h[2 * j] = d;
+      coef_h[2 * j + 1] = 1.0 / rjj;
+      AH_HIP(hipMemcpyAsync(coef_d, coef_h, (2 * j + 2) * sizeof(double), hipMemcpyHostToDevice, st));
+      {
+        ProfScope ps;
+        prof_begin(ps, transpose ? nullptr : "arnoldi_update", st, (double)(j + 4) * n * 8.0);
+        hipLaunchKernelGGL(k_dcgs_update, dim3(nblk), dim3(256), (unsigned)((2 * j + 2) * sizeof(double)), st, n, j,
+                           W.V, W.w, coef_d);
+        prof_end(ps);
+        AH_LAUNCHED();
+      }
+    }
+    if (status != AH_OK && kdone == 0) break;
+    // y from the rotated Hessenberg, then t = R^-1 y, x += Z~ t
+    for (int i = kdone - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int cc = i + 1; cc < kdone; ++cc) s -= Hg[(size_t)i * m + cc] * y[cc];
+      y[i] = s / Hg[(size_t)i * m + i];
+    }
+    for (int i = kdone - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int cc = i + 1; cc < kdone; ++cc) s -= Rt[(size_t)i * m + cc] * t[cc];
+      t[i] = s / Rt[(size_t)i * m + i];
+    }
+    for (int i = 0; i < kdone; ++i) coef_h[i] = t[i];
+    AH_HIP(hipMemcpyAsync(coef_d, coef_h, kdone * sizeof(double), hipMemcpyHostToDevice, st));
+    if (kdone > 0) {
+      if (prm.precision == 0)
+        hipLaunchKernelGGL(k_maxpy<double>, g1(n), dim3(256), 0, st, n, kdone, W.Z, n, coef_d, x, 1.0);
+      else
+        hipLaunchKernelGGL(k_maxpy<float>, g1(n), dim3(256), 0, st, n, kdone, W.Z32, n, coef_d, x, 1.0);
+      AH_LAUNCHED();
+    }
     if (status != AH_OK) break;
   }
   AH_HIP(hipStreamSynchronize(st));
@@ -1917,7 +2194,7 @@ static size_t carve_workspace(char* base, int64_t n, int m, int precision, KWork
   W->w = reinterpret_cast<double*>(take(nd));
   W->r = reinterpret_cast<double*>(take(nd));
   W->bhat = reinterpret_cast<double*>(take(nd));
-  W->partial = reinterpret_cast<double*>(take((size_t)(m + 3) * 1024 * sizeof(double)));
+  W->partial = reinterpret_cast<double*>(take((size_t)(2 * m + 4) * 1024 * sizeof(double)));
   W->hdev = reinterpret_cast<double*>(take((size_t)4 * (m + 3) * sizeof(double)));
   return off;
 }

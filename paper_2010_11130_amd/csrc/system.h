@@ -230,6 +230,7 @@ struct ah_hier {
   int64_t tail_bytes_t[2] = {0, 0};
   const char* tail_img_t[2] = {nullptr, nullptr};
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
+  int64_t dcgs_min = (int64_t)1 << 21;   // FGMRES uses delayed CGS2 from this many unknowns on
   TailLevel* d_tail = nullptr; // device copy of every level's pointers
   const char* tail_img[2] = {nullptr, nullptr};   // the tail's LDS image (FP64 / FP32), built at setup
   ah::Arena arena;

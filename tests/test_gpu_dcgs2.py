@@ -1,0 +1,99 @@
+"""FGMRES with the delayed CGS2 orthogonalisation (the solver's default from
+2^21 unknowns on; forced here on the small parity cases with AH_DCGS_MIN=0)
+against the oracle, which orthogonalises by modified Gram-Schmidt: the two
+differ only in rounding.
+
+Tolerances as in the other parity tests: solution at tol 1e-12 within 1e-10
+relative of the oracle's, iteration counts at the workload tolerance within
++-1 of the oracle's; FP32 cycle within 1e-8 of the direct solve at 1e-10;
+adjoint within 1e-10 of the direct transposed solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import air as oair, adjoint as oadj
+from oracle.drivers import setup_problem, air_fgmres_solve, direct_solve
+from gpu_cases import case, gpu_system
+
+pytestmark = pytest.mark.gpu
+
+SMALL_COARSE = 40
+
+
+@pytest.fixture(scope="module")
+def built():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            v, c, prob, p = case(name)
+            cache[name] = (gpu_system(v, c, prob, p), setup_problem(v, c, prob, p))
+        return cache[name]
+    return get
+
+
+@pytest.fixture
+def dcgs(monkeypatch):
+    monkeypatch.setenv("AH_DCGS_MIN", "0")
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu0", "kuhn_nu4", "kuhn_nu2", "c5", "layer"])
+def test_dcgs2_solve_parity(built, dcgs, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    g, o = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE)
+    x, info = H.solve(tol=1e-12)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    tol = 1e-10 if name.startswith("c1") else 1e-8
+    _, i8 = H.solve(tol=tol)
+    _, io8 = air_fgmres_solve(o, tol=tol, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4"])
+def test_dcgs2_restarts_and_fp32_cycle(built, dcgs, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    g, o = built(name)
+    xo = direct_solve(o)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1)
+    for restart in (1, 3, 7):
+        x, info = H.solve(tol=1e-11, restart=restart, maxit=2000)
+        assert info["converged"], restart
+        assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo), restart
+    x, info = H.solve(tol=1e-10, precision=1)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dcgs2_adjoint(built, dcgs, precision):
+    from paper_2010_11130_amd import Hierarchy
+    g, o = built("c5")
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, adjoint=1, fp32_cycle=precision)
+    rhs = np.random.default_rng(51).standard_normal(g.n)
+    lam, info = H.solve_adjoint(torch.as_tensor(rhs, device="cuda"), tol=1e-12, precision=precision)
+    assert info["converged"]
+    ref = oadj.adjoint_direct(o, rhs)
+    assert np.linalg.norm(lam.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_dcgs2_iteration_limit_and_same_iterations_as_cgs2(built, monkeypatch):
+    """maxit caps the finished columns (AH_ENOCONV, best iterate written),
+    and the two orthogonalisations take the same number of iterations."""
+    from paper_2010_11130_amd import Hierarchy
+    g, o = built("kuhn_nu4")
+    monkeypatch.setenv("AH_DCGS_MIN", "0")
+    Hd = Hierarchy(g, max_coarse=SMALL_COARSE)
+    x, info = Hd.solve(tol=1e-12, maxit=3)
+    assert not info["converged"] and info["iters"] == 3 and info["status"] == 1
+    assert np.all(np.isfinite(x.cpu().numpy()))
+    _, idc = Hd.solve(tol=1e-9)
+    monkeypatch.setenv("AH_DCGS_MIN", str(1 << 40))
+    Hc = Hierarchy(g, max_coarse=SMALL_COARSE)
+    _, icg = Hc.solve(tol=1e-9)
+    assert abs(idc["iters"] - icg["iters"]) <= 1, (idc["iters"], icg["iters"])
