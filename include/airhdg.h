@@ -289,7 +289,7 @@ ah_status air_solve(const ah_hier* h, const double* rhs, double* x, const ah_sol
  * workspace comes from a static device array of AH_NOALLOC_SCRATCH_BYTES
  * that the library holds on every GPU it runs on until the process ends,
  * and the host staging is a static per-thread array.  It needs
- * 8 ((2 m + 4) n + 1024 (m + 3) + 4 (m + 3)) bytes (FP32 cycle: the m Z
+ * 8 ((2 m + 4) n + 1024 (2 m + 4) + 4 (m + 3)) bytes (FP32 cycle: the m Z
  * vectors take 4 bytes per value), rounded up to 256-byte pieces, with
  * m = restart <= AH_NOALLOC_MAX_RESTART.  Returns AH_EUNSUPPORTED for a
  * larger workspace, a larger restart or method 1, before any device work.
