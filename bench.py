@@ -1,18 +1,20 @@
 """Throughput of the space-time HDG + lAIR-FGMRES hot path on one MI355X.
 
-Workload (slab-by-slab, 2+1-D): the unit square split into 64x64 quads ->
-8,192 triangles -> prisms -> 24,576 tets per slab, 64 slabs of dt = 1/64,
-p = 2 (b = 6, 342,528 free facet DOFs per slab), rotating velocity
-a = (-(x2-1/2), x1-1/2), nu = 1e-4, Gaussian hill at (0.3, 0.5) of width
-0.05, f = 0; one assembly + lAIR setup + FGMRES solve to relative residual
-1e-8 + reconstruction per slab, each slab taking the previous slab's trace
-as inflow data.  One step = the whole 64-slab march.  Inputs (mesh, boundary
-data of every slab) are resident on the device before timing.
+Headline workload (all at once, 2+1-D): the space-time cube [0,1]^3 split
+into 96^3 cubes -> 5,308,416 tets (x1-reflected Kuhn split), p = 1 (b = 3,
+31,795,200 free facet DOFs), a = (1, 0.5), nu = 1e-4, smooth solution plus a
+tanh front of width 1e-2 (data from the manufactured solution).  The system
+is assembled once; one step is lAIR setup + FGMRES(100) to relative
+residual 1e-8 (F, F, C Jacobi post-sweeps), the metric's "setup+solve", on
+the assembled system resident in HBM.
 
-value = total free DOFs / step time (FP64 cycle), with the FP32-cycle march
-reported beside it.  The dominant kernel's roofline figure uses its
-algorithmic bytes (counted by the library per launch) over its average
-launch duration measured with HIP events on its own stream.
+value = free DOFs / step time with the FP64 cycle; the FP32-cycle figure
+sits beside it.  The roofline entry is the tagged kernel with the largest
+total time in the timed FP64 steps: its algorithmic bytes (counted by the
+library per launch) over its average launch duration, measured with HIP
+events on the stream it runs on.  Secondary records: the 64-slab
+slab-by-slab march (2+1-D rotating hill, 64x64 quads, p = 2) and the
+differentiation form on the mapped 48^3 mesh.
 """
 import argparse
 import json
@@ -27,7 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # kernels timed with HIP events inside the library (ah_profile_*)
-PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "rap0"]
+PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "rap0",
+                "arnoldi_dot", "arnoldi_update"]
 METRIC = "DOF/s to 1e-8 rel. residual (setup+solve), FP32 vs FP64 V-cycle; HBM GB/s"
 
 
@@ -36,32 +39,29 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=64, help="quads per side of the spatial mesh")
+    ap.add_argument("--c3-n", type=int, default=96, help="cubes per side of the headline space-time mesh")
+    ap.add_argument("--c3-nu", type=float, default=1e-4)
+    ap.add_argument("--no-c3-variants", action="store_true",
+                    help="skip BiCGSTAB, ordered relaxations and nu = 0, 1e-2 on the headline mesh")
+    ap.add_argument("--no-march", action="store_true", help="skip the slab-by-slab march record")
+    ap.add_argument("--march-steps", type=int, default=3, help="timed passes of the slab march")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the march's BiCGSTAB, distance-two lAIR, Section 4 thresholds, all-at-once, "
+                         "internal-layer, ordered-relaxation and slab-0 adjoint records")
+    ap.add_argument("--cpu-n", type=int, default=24, help="mesh of the oracle's CPU baseline sample")
+    ap.add_argument("--n", type=int, default=64, help="quads per side of the march's spatial mesh")
     ap.add_argument("--slabs", type=int, default=64)
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--nu", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-all-at-once", action="store_true",
-                    help="skip the all-at-once solve of the stacked slabs")
-    ap.add_argument("--no-bicgstab", action="store_true",
-                    help="skip the BiCGSTAB march and the no-block-inverse ablation")
     ap.add_argument("--solve-alone", type=int, default=0, metavar="N",
                     help="only time N FGMRES solves of slab 0 with nothing else on the GPU")
-    ap.add_argument("--no-lair-d2", action="store_true",
-                    help="skip the marches with distance-two lAIR neighbourhoods and with the Section 4 "
-                         "strength thresholds")
-    ap.add_argument("--no-internal-layer", action="store_true",
-                    help="skip the moving internal layer (Section 4.2) all-at-once solve")
     ap.add_argument("--relax", type=int, default=0,
                     help="with --solve-alone: relaxation (0 F,F,C Jacobi; 2, 3 ordered Gauss-Seidel)")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the C3 (96^3, 31.8M DOFs) and C5 (48^3 mapped, adjoint) workloads")
-    ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the adjoint solve and gradients on slab 0")
-    ap.add_argument("--no-ordered", action="store_true",
-                    help="skip the ordered Gauss-Seidel relaxations (internal layer, slab 0)")
+                    help="skip the C5 (48^3 mapped, adjoint) workload")
     ap.add_argument("--builders", type=int, default=1,
                     help="builder threads (streams) of the pipelined march")
     ap.add_argument("--no-sequential", action="store_true",
@@ -176,6 +176,10 @@ KERNEL_SOURCES = {"element": "paper_2010_11130_amd/csrc/assemble.hip",
                   "spmv0": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax0_f": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax0_c": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_f_f32": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax0_c_f32": "paper_2010_11130_amd/csrc/solve.hip",
+                  "arnoldi_dot": "paper_2010_11130_amd/csrc/solve.hip",
+                  "arnoldi_update": "paper_2010_11130_amd/csrc/solve.hip",
                   "rap0": "paper_2010_11130_amd/csrc/setup.hip"}
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
 
@@ -206,7 +210,7 @@ def _counter_mean(d, counter, substr, grid):
 def traffic_record(tag, substr, grid, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     """HBM bytes per dispatch of one kernel: FETCH_SIZE and WRITE_SIZE (KiB
     per dispatch) scaled by what the same counters read for a plain device
-    copy of known size (``--copy-probe``)."""
+    copy of known size (``--copy-probe``).  ``tag`` is "workload:tag"."""
     grid = int(grid)
     fk, nf = _counter_mean(fetch_dir, "FETCH_SIZE", substr, grid)
     wk, nw = _counter_mean(write_dir, "WRITE_SIZE", substr, grid)
@@ -220,13 +224,15 @@ def traffic_record(tag, substr, grid, fetch_dir, write_dir, copy_fetch_dir, copy
            "copy_probe_fetch_kib": cf, "copy_probe_write_kib": cw,
            "fetch_factor": f_fac, "write_factor": w_fac,
            "bytes_per_launch": fk * 1024.0 * f_fac + wk * 1024.0 * w_fac,
-           "source": KERNEL_SOURCES[tag], "source_sha256": _sha256(KERNEL_SOURCES[tag])}
+           "source": KERNEL_SOURCES[tag.split(":")[-1]],
+           "source_sha256": _sha256(KERNEL_SOURCES[tag.split(":")[-1]])}
     print(json.dumps(rec))
 
 
 def measured_traffic(tag):
-    """Counter-measured HBM bytes per launch of ``tag``, or None when no
-    record exists or the kernel's source changed since it was taken."""
+    """Counter-measured HBM bytes per launch of ``tag`` ("workload:tag"), or
+    None when no record exists or the kernel's source changed since it was
+    taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             recs = json.load(f)
@@ -299,55 +305,110 @@ def workload_inputs(v, c, prob, p, f_q=None):
     return m, xe, g, a, f_q
 
 
-def c3_all_at_once(tol):
-    """The C3 workload: the 96^3 Kuhn mesh of the space-time cube (5.3M
-    tets, p = 1, 31.8M free DOFs), smooth solution plus a front of width
-    1e-2, a = (1, 0.5), all at once, nu = 1e-4, 0 and 1e-2: assembly, then
-    lAIR setup and FGMRES to tol with F,F,C Jacobi (FP64 and FP32 cycles)
-    and with the ordered Gauss-Seidel relaxation (relax 2, FP64); at nu =
-    1e-2 (diffusion-dominated: mesh Peclet number about 1) F,F,C Jacobi with
-    strength threshold 0.1, the setting that converges there.  Per variant: the
-    setup, a first solve (which allocates the FGMRES basis, 51 GB at restart
-    100, from the stream-ordered pool) and a second solve; DOF/s counts the
-    setup and the second solve."""
+def c3_inputs(n, nu):
+    """Mesh, device inputs and the assembled C3 system (96^3 Kuhn cubes of
+    the space-time cube, p = 1, a = (1, 0.5), smooth solution plus a tanh
+    front), with the assembly time."""
     import torch
-    from paper_2010_11130_amd import System, Hierarchy
+    from paper_2010_11130_amd import System
     from workloads import kuhn_cube_mesh
     from workloads.problems import SmoothPlusFront
-    v, c = kuhn_cube_mesh(96)
-    m, xe, g, a, _ = workload_inputs(v, c, SmoothPlusFront(1e-4), 1, f_q=False)
-    out = {"mesh": "96^3 Kuhn cubes, 5308416 tets", "p": 1}
-    for nu, variants in ((1e-4, (("fp64", 0, 0, 0.25), ("fp32_cycle", 1, 0, 0.25), ("fp64_ordered", 0, 2, 0.25))),
-                         (0.0, (("fp64", 0, 0, 0.25), ("fp64_ordered", 0, 2, 0.25))),
-                         (1e-2, (("fp64_theta_0.1", 0, 0, 0.1),))):
-        prob = SmoothPlusFront(nu)
-        f = prob.f(xe).contiguous()
+    v, c = kuhn_cube_mesh(n)
+    m, xe, g, a, _ = workload_inputs(v, c, SmoothPlusFront(nu), 1, f_q=False)
+    f = SmoothPlusFront(nu).f(xe).contiguous()
+    t = []
+    s = None
+    for _ in range(2):
+        del s
+        s = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = System(m, 1, nu, a, f, g, keep=False)
         torch.cuda.synchronize()
-        rec = {"assemble_ms": 1e3 * (time.perf_counter() - t0), "free_dofs": s.n}
-        for key, prec, relax, theta in variants:
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            h = Hierarchy(s, fp32_cycle=prec, relax=relax, theta=theta)
-            torch.cuda.synchronize()
-            tb = time.perf_counter()
-            h.solve(tol=tol, precision=prec)
-            torch.cuda.synchronize()
-            tc = time.perf_counter()
-            x, info = h.solve(tol=tol, precision=prec)
-            torch.cuda.synchronize()
-            td = time.perf_counter()
-            r = {"dofs_per_s_setup_solve": s.n / ((tb - ta) + (td - tc)), "setup_ms": 1e3 * (tb - ta),
-                 "solve_ms": 1e3 * (td - tc), "first_solve_ms": 1e3 * (tc - tb), "iters": info["iters"],
-                 "converged": info["converged"], "levels": h.info["levels"]}
-            if relax >= 2:
-                r["flow_order_levels"] = h.flow_levels()[1]
-            del h, x
+        t.append(time.perf_counter() - t0)
+    return {"mesh": m, "xe": xe, "g": g, "a": a, "f": f, "system": s, "assemble_ms": 1e3 * t[-1],
+            "tets": c.shape[0]}
+
+
+def setup_solve_steps(s, steps, warmup, tol, precision=0, profile=False, method=0, **air):
+    """``warmup`` untimed, then ``steps`` timed passes of lAIR setup + Krylov
+    solve on the assembled system ``s`` (each pass builds its own hierarchy
+    and solver workspace); with ``profile`` the library's per-kernel HIP
+    events are on during the timed passes."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy, lib
+    kw = dict(air)
+    kw["fp32_cycle"] = 1 if precision else 0
+    for _ in range(warmup):
+        h = Hierarchy(s, **kw)
+        h.solve(tol=tol, precision=precision, method=method)
+        del h
+    if profile:
+        lib().ah_profile_reset()
+        lib().ah_profile_enable(1)
+    torch.cuda.synchronize()
+    setup, solve, iters = [], [], []
+    x = info = h = None
+    T0 = time.perf_counter()
+    for _ in range(steps):
+        del h, x
+        t0 = time.perf_counter()
+        h = Hierarchy(s, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = h.solve(tol=tol, precision=precision, method=method)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        setup.append(1e3 * (t1 - t0))
+        solve.append(1e3 * (t2 - t1))
+        iters.append(info["iters"])
+    T = (time.perf_counter() - T0) / steps
+    prof = None
+    if profile:
+        lib().ah_profile_enable(0)
+        prof = profile_totals(PROFILE_TAGS)
+        lib().ah_profile_reset()
+    med = lambda v: sorted(v)[len(v) // 2]
+    rec = {"value": s.n / T, "ms_per_step": 1e3 * T, "setup_ms_median": med(setup), "solve_ms_median": med(solve),
+           "iters": iters[-1], "converged": info["converged"], "true_relres": info["true_relres"],
+           "levels": h.info["levels"], "op_complexity": h.info["op_complexity"]}
+    if air.get("relax", 0) >= 2:
+        rec["flow_order_levels"] = h.flow_levels()[1]
+    return rec, prof, x
+
+
+def c3_variants(c3, tol, x64):
+    """One timed setup + solve (after a warm one) of other settings on the
+    same 96^3 workload: BiCGSTAB (the paper's Krylov method), the ordered
+    Gauss-Seidel relaxations of Lemma 3.1 (relax 2: all points in flow
+    order; relax 3: F points then all points, the Section 4 schedule), FP64
+    and FP32 cycles; and the same mesh at nu = 0 and nu = 1e-2."""
+    import torch
+    from paper_2010_11130_amd import System
+    from workloads.problems import SmoothPlusFront
+    s = c3["system"]
+    out = {}
+    for key, prec, kw in (("bicgstab", 0, {"method": 1}), ("ordered_relax2", 0, {"relax": 2}),
+                          ("ordered_relax2_fp32_cycle", 1, {"relax": 2}), ("ordered_relax3", 0, {"relax": 3})):
+        r, _, x = setup_solve_steps(s, 1, 1, tol, prec, **kw)
+        r["rel_diff_vs_fp64_jacobi"] = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
+        out[key] = r
+        del x
+    for nu, variants in ((0.0, (("jacobi", {}), ("ordered_relax2", {"relax": 2}))),
+                         (1e-2, (("jacobi_theta_0.1", {"theta": 0.1}),))):
+        prob = SmoothPlusFront(nu)
+        f = prob.f(c3["xe"]).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sn = System(c3["mesh"], 1, nu, c3["a"], f, c3["g"], keep=False)
+        torch.cuda.synchronize()
+        rec = {"assemble_ms": 1e3 * (time.perf_counter() - t0)}
+        for key, kw in variants:
+            r, _, x = setup_solve_steps(sn, 1, 1, tol, 0, **kw)
             rec[key] = r
+            del x
         out["nu=%g" % nu] = rec
-        del s
+        del sn
     return out
 
 
@@ -766,44 +827,153 @@ def element_flops(D, p):
     return vol + fac + cond
 
 
-def roofline(prof, p, D, ne):
+def roofline(prof, workload, p, D, ne):
     """Roofline entry of the tagged kernel with the largest total time: the
-    element kernel against FP64 vector peak (flops above), the sparse
-    kernels against HBM bandwidth (algorithmic bytes of the library)."""
+    element kernel against FP64 vector peak (flops above), the sparse and
+    Arnoldi kernels against HBM bandwidth (algorithmic bytes counted by the
+    library per launch)."""
     name = max(prof, key=lambda k: prof[k]["total_ms"])
     k = prof[name]
     sec = k["avg_us"] * 1e-6
+    traffic = measured_traffic("%s:%s" % (workload, name))
     if name == "element":
         flops = element_flops(D, p) * ne
         ach = flops / sec / 1e12
         return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic(name), "flops_per_launch": flops,
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": traffic, "flops_per_launch": flops,
                 "avg_launch_us": k["avg_us"]}
     ach = k["bytes"] / k["launches"] / sec / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name),
-            "bytes_per_launch": k["bytes"] / k["launches"], "avg_launch_us": k["avg_us"]}
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": k["bytes"] / k["launches"], "avg_launch_us": k["avg_us"],
+            "launches": k["launches"]}
 
 
-def cpu_baseline(n, p, nu, tol, dt):
-    """The oracle on one slab of the same workload (slab 0)."""
-    import numpy as np
-    from workloads import slab_prism_tet_mesh
-    from workloads.problems import slab_hill
-    from oracle.drivers import setup_problem, air_fgmres_solve
+def cpu_baseline(n=24, nu=1e-4, tol=1e-8):
+    """The oracle (plain FP64 numpy/scipy) on a bounded sample of the
+    headline workload's mesh family: the n^3 Kuhn mesh of the same problem,
+    p = 1, with the BLAS thread pools held at one thread (the oracle's sparse
+    products and loops run on one core anyway).  value = free DOFs /
+    (lAIR setup + FGMRES) as in the headline; assembly timed apart."""
+    from workloads import kuhn_cube_mesh
+    from workloads.problems import SmoothPlusFront
+    from oracle.drivers import setup_problem
+    from oracle import air, krylov
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([1] + [d.get("num_threads", 1) for d in threadpool_info()])
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
     except Exception:
-        threads = 1
-    v, c = slab_prism_tet_mesh(n, dt)
+        limiter = None
+    v, c = kuhn_cube_mesh(n)
     t0 = time.perf_counter()
-    s = setup_problem(v, c, slab_hill(nu), p)
-    x, info = air_fgmres_solve(s, tol=tol)
+    s = setup_problem(v, c, SmoothPlusFront(nu), 1)
     t1 = time.perf_counter()
-    return {"value": s.n / (t1 - t0), "unit": "DOF/s", "cores": int(threads), "kind": "oracle",
-            "sample": "slab 0 of the march (%d free DOFs): assembly + lAIR setup + FGMRES to %g, %d iterations, "
-                      "%.1f s" % (s.n, tol, info["iters"], t1 - t0)}
+    H = air.setup(s.Shat)
+    t2 = time.perf_counter()
+    x, info = krylov.fgmres(s.Shat, s.Hhat, lambda r: air.vcycle(H, r), tol=tol)
+    t3 = time.perf_counter()
+    if limiter is not None:
+        limiter.unregister()
+    return {"value": s.n / (t3 - t1), "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": "%d^3 Kuhn mesh of the headline problem (p=1, nu=%g, %d free DOFs, 1/%d of the headline's): "
+                      "lAIR setup %.1f s + FGMRES to %g %.1f s (%d iterations), one thread; assembly %.1f s apart"
+                      % (n, nu, s.n, round(31795200 / s.n), t2 - t1, tol, t3 - t2, info["iters"], t1 - t0)}
+
+
+def march_record(args):
+    """The slab-by-slab march (secondary record): pipelined FP64 and FP32-cycle
+    marches, the sequential stage split, and the slab solved alone; with
+    ``--extras`` the other march and slab-0 records."""
+    import torch
+    march = March(args.n, args.slabs, args.p, args.nu)
+    march.builders = args.builders
+    seq = not args.no_sequential
+    steps, warmup = args.march_steps, 1
+    t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, steps, warmup, args.tol, seq)
+    ndof_slab = last64[0].numel()
+    total = ndof_slab * args.slabs
+
+    def split(stages, tseq):
+        if stages is None:
+            return {}
+        st = {k: 1e3 * sum(x[k] for x in stages) for k in ("assemble", "setup", "solve")}
+        iters = [x["iters"] for x in stages]
+        return {"stages_ms_per_step": st,
+                "sequential_march": {"dofs_per_s": total / tseq, "ms_per_step": 1e3 * tseq},
+                "setup_solve_dofs_per_s": total / (1e-3 * (st["setup"] + st["solve"])),
+                "fgmres_iters_per_slab": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)}}
+
+    out = {"value": total / t64, "unit": "DOF/s", "ms_per_step": 1e3 * t64, "steps": steps,
+           "workload": "slab-by-slab 2+1D rotating Gaussian hill: %dx%d quads -> %d tets/slab, %d slabs dt=1/%d, "
+                       "p=%d, nu=%g, lAIR-FGMRES to %g per slab; per slab assembly + lAIR setup + solve + "
+                       "reconstruction, the next slab's assembly and setup overlapped with the current solve on a "
+                       "second stream" % (args.n, args.n, 6 * args.n * args.n, args.slabs, args.slabs, args.p,
+                                          args.nu, args.tol),
+           "free_dofs_per_slab": ndof_slab, "total_free_dofs": total, "kernels": prof64,
+           "build_wait_ms_per_step": march.wait_ms_per_step}
+    if stages64:
+        out["levels"] = stages64[0]["levels"]
+        out["op_complexity"] = stages64[0]["op_complexity"]
+    out.update(split(stages64, tseq64))
+    alone64 = None
+    if not args.no_fp32:
+        t32, stages32, tseq32, prof32, last32 = run_timed(march, 1, steps, warmup, args.tol, seq)
+        err = (torch.linalg.norm(last32[0] - last64[0]) / torch.linalg.norm(last64[0])).item()
+        out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
+                             "last_slab_rel_diff_vs_fp64": err, "kernels": prof32,
+                             "build_wait_ms_per_step": march.wait_ms_per_step}
+        out["fp32_cycle"].update(split(stages32, tseq32))
+        a64 = alone64 = solve_alone(march, 10, args.tol, 0)
+        a32 = solve_alone(march, 10, args.tol, 1)
+        out["fp32_cycle"]["solve_alone"] = {
+            "fp64_ms_per_solve": a64["ms_per_solve"], "fp32_ms_per_solve": a32["ms_per_solve"],
+            "fp64_us_per_iteration": a64["us_per_iteration"], "fp32_us_per_iteration": a32["us_per_iteration"],
+            "iters": [a64["iters"], a32["iters"]], "speedup_vs_fp64": a64["ms_per_solve"] / a32["ms_per_solve"]}
+    if prof64:
+        # the slab's level-0 operator (about 84 MB) stays in the 256 MB
+        # Infinity Cache: a cache-resident figure, not an HBM one
+        rf = roofline(prof64, "c2", args.p, march.vert.shape[1], march.cell.shape[0])
+        rf["note"] = "cache-resident working set (level-0 operator about 84 MB < 256 MB Infinity Cache)"
+        k = (alone64 or {}).get("kernels", {}).get(rf["kernel"])
+        if k:
+            ach = k["bytes"] / k["launches"] / (k["avg_us"] * 1e-6) / 1e9
+            rf["alone"] = {"avg_launch_us": k["avg_us"], "achieved": ach, "frac": ach / HBM_PEAK_GBS}
+        out["roofline"] = rf
+    if args.extras:
+        from paper_2010_11130_amd import System, Hierarchy
+        march.step(0, args.tol, method=1)
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            its.clear()
+            march.step(0, args.tol, method=1, iters=its)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / steps
+        out["bicgstab"] = {"value": total / tb, "ms_per_step": 1e3 * tb,
+                           "steps_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+        s0 = System(march.mesh, args.p, args.nu, march.a, None, march.g[0], block_scale=False)
+        x0, i0 = Hierarchy(s0).solve(tol=args.tol, maxit=100)
+        out["no_block_inverse_slab0"] = {"converged": i0["converged"], "iters": i0["iters"],
+                                         "relres": i0["true_relres"]}
+        for key, extra in (("lair_distance2", {"lair_distance": 2}),
+                           ("paper_thresholds", {"theta": 0.2, "theta_r": 0.3})):
+            march.step(0, args.tol, air_extra=extra)
+            its = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                its.clear()
+                march.step(0, args.tol, iters=its, air_extra=extra)
+            torch.cuda.synchronize()
+            td = (time.perf_counter() - t0) / steps
+            out[key] = {"value": total / td, "ms_per_step": 1e3 * td, "params": extra,
+                        "iters_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+        out["all_at_once"] = all_at_once(args, last64[1])
+        out["internal_layer"] = internal_layer(tol=args.tol)
+        out["ordered_relaxation"] = ordered_relaxation(args, march)
+        out["adjoint_slab0"] = adjoint_slab(march, args.tol)
+    return out
 
 
 def main():
@@ -827,142 +997,58 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
-    march = March(args.n, args.slabs, args.p, args.nu)
-    march.builders = args.builders
     if args.solve_alone:
+        march = March(args.n, args.slabs, args.p, args.nu)
         print(json.dumps({"solve_alone": solve_alone(march, args.solve_alone, args.tol, relax=args.relax)}))
         return
-    seq = not args.no_sequential
-    t64, stages64, tseq64, prof64, last64 = run_timed(march, 0, args.steps, args.warmup, args.tol, seq)
-    ndof_slab = last64[0].numel()
-    total = ndof_slab * args.slabs
-    value = total / t64
-
-    def split(stages, tseq):
-        if stages is None:
-            return None, {}
-        st = {k: 1e3 * sum(x[k] for x in stages) for k in ("assemble", "setup", "solve")}
-        iters = [x["iters"] for x in stages]
-        return st, {"stages_ms_per_step": st,
-                    "sequential_march": {"dofs_per_s": total / tseq, "ms_per_step": 1e3 * tseq},
-                    "setup_solve_dofs_per_s": total / (1e-3 * (st["setup"] + st["solve"])),
-                    "fgmres_iters_per_slab": {"min": min(iters), "max": max(iters),
-                                              "mean": sum(iters) / len(iters)}}
-
-    st, extra = split(stages64, tseq64)
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    # headline: the C3 workload, setup + solve on the assembled system
+    c3 = c3_inputs(args.c3_n, args.c3_nu)
+    s = c3["system"]
+    log("bench: C3 %d^3 assembled, %d free DOFs, %.1f ms" % (args.c3_n, s.n, c3["assemble_ms"]))
+    r64, prof64, x64 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 0, profile=True)
+    log("bench: FP64 %.1f ms/step, %d iterations" % (r64["ms_per_step"], r64["iters"]))
     out = {
-        "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t64, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": r64["value"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "slab-by-slab 2+1D rotating Gaussian hill: %dx%d quads -> %d tets/slab, %d slabs "
-                               "dt=1/%d, p=%d, nu=%g, lAIR-FGMRES to %g per slab; per slab assembly + lAIR setup + "
-                               "solve + reconstruction, the next slab's assembly and setup overlapped with the "
-                               "current solve on a second stream"
-                               % (args.n, args.n, 6 * args.n * args.n, args.slabs, args.slabs, args.p, args.nu,
-                                  args.tol),
-                   "free_dofs_per_slab": ndof_slab, "slabs": args.slabs, "total_free_dofs": total},
+        "config": {"workload": "all-at-once 2+1D space-time cube: %d^3 Kuhn cubes -> %d tets, p=1 (b=3), "
+                               "a=(1,0.5), nu=%g, smooth solution + tanh front of width 1e-2; one step = lAIR setup "
+                               "(theta 0.25, PMIS, one-point P, distance-1 lAIR) + FGMRES(100) to %g with F,F,C "
+                               "Jacobi post-sweeps, on the assembled system in HBM"
+                               % (args.c3_n, c3["tets"], args.c3_nu, args.tol),
+                   "free_dofs": s.n, "tol": args.tol},
+        "fp64": r64, "assemble_ms": c3["assemble_ms"],
+        "end_to_end_dofs_per_s": s.n / (1e-3 * (c3["assemble_ms"] + r64["ms_per_step"])),
         "kernels": prof64,
-        "build_wait_ms_per_step": march.wait_ms_per_step,
     }
-    if stages64:
-        out["levels"] = stages64[0]["levels"]
-        out["op_complexity"] = stages64[0]["op_complexity"]
-    out.update(extra)
-    alone64 = None
     if not args.no_fp32:
-        t32, stages32, tseq32, prof32, last32 = run_timed(march, 1, args.steps, args.warmup, args.tol, seq)
-        _, extra32 = split(stages32, tseq32)
-        err = (torch.linalg.norm(last32[0] - last64[0]) / torch.linalg.norm(last64[0])).item()
-        out["fp32_cycle"] = {"value": total / t32, "ms_per_step": 1e3 * t32, "speedup_vs_fp64": t64 / t32,
-                             "last_slab_rel_diff_vs_fp64": err, "kernels": prof32,
-                             "build_wait_ms_per_step": march.wait_ms_per_step}
-        out["fp32_cycle"].update(extra32)
-        # the two cycle precisions with nothing else on the GPU (in the march
-        # the solve shares the GPU with the next slab's assembly and setup)
-        a64 = alone64 = solve_alone(march, 10, args.tol, 0)
-        a32 = solve_alone(march, 10, args.tol, 1)
-        out["fp32_cycle"]["solve_alone"] = {
-            "fp64_ms_per_solve": a64["ms_per_solve"], "fp32_ms_per_solve": a32["ms_per_solve"],
-            "fp64_us_per_iteration": a64["us_per_iteration"], "fp32_us_per_iteration": a32["us_per_iteration"],
-            "iters": [a64["iters"], a32["iters"]], "speedup_vs_fp64": a64["ms_per_solve"] / a32["ms_per_solve"]}
-    # the paper's Krylov method: BiCGSTAB steps (two V-cycles each), same march
-    if not args.no_bicgstab:
-        march.step(0, args.tol, method=1)
-        its = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            its.clear()
-            march.step(0, args.tol, method=1, iters=its)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / args.steps
-        out["bicgstab"] = {"value": total / tb, "ms_per_step": 1e3 * tb,
-                           "steps_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
-        # ablation (Section 4.1): AIR on the system without the facet-block
-        # scaling, slab 0, FGMRES capped at 100 iterations
-        from paper_2010_11130_amd import System, Hierarchy
-        s0 = System(march.mesh, args.p, args.nu, march.a, None, march.g[0], block_scale=False)
-        x0, i0 = Hierarchy(s0).solve(tol=args.tol, maxit=100)
-        out["no_block_inverse_slab0"] = {"converged": i0["converged"], "iters": i0["iters"],
-                                         "relres": i0["true_relres"]}
-    # distance-two lAIR neighbourhoods (a NEXT option of the paper's
-    # Section 4 settings): same march, FGMRES
-    if not args.no_lair_d2:
-        d2 = {"lair_distance": 2}
-        march.step(0, args.tol, air_extra=d2)
-        its = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            its.clear()
-            march.step(0, args.tol, iters=its, air_extra=d2)
-        torch.cuda.synchronize()
-        td = (time.perf_counter() - t0) / args.steps
-        out["lair_distance2"] = {"value": total / td, "ms_per_step": 1e3 * td,
-                                 "iters_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
-    # the strength thresholds of the paper's Section 4 settings (0.2 for the
-    # coarsening and P, 0.3 for the restriction neighbourhoods)
-    if not args.no_lair_d2:
-        th = {"theta": 0.2, "theta_r": 0.3}
-        march.step(0, args.tol, air_extra=th)
-        its = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            its.clear()
-            march.step(0, args.tol, iters=its, air_extra=th)
-        torch.cuda.synchronize()
-        tt = (time.perf_counter() - t0) / args.steps
-        out["paper_thresholds"] = {"value": total / tt, "ms_per_step": 1e3 * tt, "theta": 0.2, "theta_r": 0.3,
-                                   "iters_per_slab": {"min": min(its), "max": max(its),
-                                                      "mean": sum(its) / len(its)}}
-    # all-at-once: the 64 slabs as one space-time system on one GPU
-    if not args.no_all_at_once:
-        out["all_at_once"] = all_at_once(args, last64[1])
-    if not args.no_internal_layer:
-        out["internal_layer"] = internal_layer(tol=args.tol)
-    if not args.no_ordered:
-        out["ordered_relaxation"] = ordered_relaxation(args, march)
-    if not args.no_adjoint:
-        out["adjoint_slab0"] = adjoint_slab(march, args.tol)
-    if not args.no_large:
-        out["c3_all_at_once"] = c3_all_at_once(args.tol)
-        out["c5_adjoint"] = c5_adjoint(args.tol)
-    # dominant tagged kernel of the FP64 march
+        r32, prof32, x32 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 1, profile=True)
+        log("bench: FP32 cycle %.1f ms/step, %d iterations" % (r32["ms_per_step"], r32["iters"]))
+        r32["speedup_vs_fp64"] = r64["ms_per_step"] / r32["ms_per_step"]
+        r32["rel_diff_vs_fp64"] = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+        r32["kernels"] = prof32
+        out["fp32_cycle"] = r32
+        del x32
     if prof64:
-        out["roofline"] = roofline(prof64, args.p, march.vert.shape[1], march.cell.shape[0])
-        if out["roofline"]["unit"] == "GB/s":
-            cb = copy_bandwidth()
-            out["roofline"]["copy_gbs"] = cb
-            out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cb
-            # the same kernel with the GPU to itself (slab 0 solved alone)
-            k = (alone64 or {}).get("kernels", {}).get(out["roofline"]["kernel"])
-            if k:
-                ach = k["bytes"] / k["launches"] / (k["avg_us"] * 1e-6) / 1e9
-                out["roofline"]["alone"] = {"avg_launch_us": k["avg_us"], "achieved": ach,
-                                            "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / cb}
+        rf = roofline(prof64, "c3", 1, 3, c3["tets"])
+        cb = copy_bandwidth()
+        rf["copy_gbs"] = cb
+        rf["frac_of_copy"] = rf["achieved"] / cb
+        out["roofline"] = rf
+    if not args.no_c3_variants:
+        out["c3_variants"] = c3_variants(c3, args.tol, x64)
+        log("bench: C3 variants done")
+    del x64, s, c3
+    torch.cuda.empty_cache()
+    if not args.no_march:
+        out["slab_march"] = march_record(args)
+        log("bench: march done")
+    if not args.no_large:
+        out["c5_adjoint"] = c5_adjoint(args.tol)
+        log("bench: C5 done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.n, args.p, args.nu, args.tol, 1.0 / args.slabs)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.c3_nu, args.tol)
     print(json.dumps(out))
 
 

@@ -25,7 +25,7 @@ def test_roofline_takes_the_kernel_with_most_time(monkeypatch):
         "relax0_f": {"launches": 4, "total_ms": 0.12, "bytes": 4 * 75e6, "avg_us": 30.0},
         "spmv0": {"launches": 2, "total_ms": 0.05, "bytes": 2 * 90e6, "avg_us": 25.0},
     }
-    r = bench.roofline(prof, 2, 3, 24576)
+    r = bench.roofline(prof, "c3", 2, 3, 24576)
     assert r["kernel"] == "relax0_f" and r["bound"] == "hbm" and r["unit"] == "GB/s"
     # algorithmic bytes per launch over the mean launch duration
     assert r["bytes_per_launch"] == 75e6
@@ -33,3 +33,12 @@ def test_roofline_takes_the_kernel_with_most_time(monkeypatch):
     assert r["peak"] == 8000.0
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
     assert r["traffic"] is None
+
+
+def test_roofline_traffic_is_keyed_by_workload(monkeypatch):
+    seen = []
+    monkeypatch.setattr(bench, "measured_traffic", lambda key: seen.append(key) or 123.0)
+    prof = {"arnoldi_dot": {"launches": 3, "total_ms": 3.0, "bytes": 3 * 9e9, "avg_us": 1000.0}}
+    r = bench.roofline(prof, "c3", 1, 3, 10)
+    assert seen == ["c3:arnoldi_dot"] and r["traffic"] == 123.0
+    assert r["achieved"] == pytest.approx(9e9 / 1e-3 / 1e9)
