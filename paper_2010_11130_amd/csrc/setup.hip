@@ -1455,6 +1455,9 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   {
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
     if (const char* e = std::getenv("AH_DCGS_MIN")) h->dcgs_min = std::atoll(e);
+    if (const char* e = std::getenv("AH_GC")) h->gc = std::atoi(e);
+    if (h->gc != 2 && h->gc != 4 && h->gc != 8 && h->gc != 16 && h->gc != 32) h->gc = 0;
+    if (const char* e = std::getenv("AH_LIST_MIN")) h->list_min = std::atoll(e);
     if (h->g0 != 2 && h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();
     std::vector<TailLevel> tl(nl);

@@ -65,6 +65,13 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
         acc2 += a2 * (TY)x[c2];
         acc3 += a3 * (TY)x[c3];
       }
+      if (kb + G < k1) {   // two more in flight
+        const int32_t c0 = ci[kb], c1 = ci[kb + G];
+        const TY a0 = (TY)av[kb], a1 = (TY)av[kb + G];
+        acc += a0 * (TY)x[c0];
+        acc1 += a1 * (TY)x[c1];
+        kb += 2 * G;
+      }
       acc += (acc1 + acc2) + acc3;
     }
     for (int64_t k = kb; k < k1; k += G) {
@@ -1042,8 +1049,8 @@ static inline dim3 g1(int64_t n, int t = 256) { return dim3((unsigned)cdiv(std::
 
 static int pick_g(int64_t nnz, int64_t n) {
   double avg = n ? (double)nnz / (double)n : 0.0;
-  if (avg < 6) return 4;
-  if (avg < 40) return 8;
+  if (avg < 24) return 4;
+  if (avg < 48) return 8;
   if (avg < 80) return 16;
   return 32;
 }
@@ -1058,6 +1065,7 @@ static ah_status csr_g(int G, int64_t n, const int64_t* rp, const int32_t* ci, c
   prof_begin(ps, tag, st, bytes);
   dim3 grid((unsigned)cdiv(n * G, 256));
   switch (G) {
+    case 2: hipLaunchKernelGGL((k_csr<TA, TX, TY, 2, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
     case 4: hipLaunchKernelGGL((k_csr<TA, TX, TY, 4, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
     case 8: hipLaunchKernelGGL((k_csr<TA, TX, TY, 8, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
     case 16: hipLaunchKernelGGL((k_csr<TA, TX, TY, 16, MODE>), grid, dim3(256), 0, st, n, rp, ci, av, x, b, d, cf, X, omega, y, pc, y2); break;
@@ -1329,7 +1337,7 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     return AH_OK;
   }
   AhLevel& C = h->lev[l + 1];
-  const int G = (l == 0 && h->g0) ? h->g0 : pick_g(L.nnz, L.n);
+  const int G = (l == 0 && h->g0) ? h->g0 : (l > 0 && h->gc) ? h->gc : pick_g(L.nnz, L.n);
   const int GR = pick_g(L.nnzR, L.nc);
   AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
                                 (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
@@ -1337,11 +1345,11 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
   const T om = (T)h->prm.omega;
   const int64_t nF = L.n - L.nc;
-  if (l > 0) {
-    // coarse levels (launch-latency bound): the first F sweep reads P e_c
-    // through pcol and writes every row of y (C rows: P e_c); the second F
-    // sweep writes every row of x and its F rows into out; the C sweep
-    // visits the C points from their list and writes them into out
+  if (l > 0 && L.n < h->list_min) {
+    // small coarse levels (launch-latency bound): the first F sweep reads
+    // P e_c through pcol and writes every row of y (C rows: P e_c); the
+    // second F sweep writes every row of x and its F rows into out; the C
+    // sweep visits the C points from their list and writes them into out
     if (nsw == 1) {
       AH_TRY((csr_g<T, T, T, SP_SWEEP_P>(G, L.n, L.rowptr, L.col, Ops<T>::A(L), ec, b, Ops<T>::d(L), L.cf, 0, om,
                                          out, st, nullptr, 0.0, L.pcol)));
@@ -1357,12 +1365,12 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                                           out, st, nullptr, 0.0, L.clist)));
     return AH_OK;
   }
-  // level 0 (bandwidth bound): x = y = P e_c, then the F sweeps visit the F
-  // points only (from the F list) and the C sweep the C points only, so the
-  // C entries of x and y keep the interpolated values through the F sweeps:
-  // F1 x -> y, F2 y -> x (its rows also written into out), C x -> out.  With
-  // one F sweep, y is out.
-  if (h->prm.relax >= 2) {
+  // level 0 and large coarse levels (bandwidth bound): x = y = P e_c, then
+  // the F sweeps visit the F points only (from the F list) and the C sweep
+  // the C points only, so the C entries of x and y keep the interpolated
+  // values through the F sweeps: F1 x -> y, F2 y -> x (its rows also written
+  // into out), C x -> out.  With one F sweep, y is out.
+  if (l == 0 && h->prm.relax >= 2) {
     // ordered sweeps in the flow order: y = out = P e_c; (relax 3: F sweep
     // y -> out, y = out;) sweep over all points y -> out
     T* y = Ops<T>::y(L);
@@ -1379,10 +1387,10 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   T* y = nsw == 1 ? out : Ops<T>::y(L);
   hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
   AH_LAUNCHED();
-  // level-0 timing tags, one per sweep kernel and grid
-  const char* tf = sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
-  const char* tc = sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
-  if (L.ob && Ops<T>::O(L)) {
+  // level-0 timing tags, one per sweep kernel and grid (coarse levels: none)
+  const char* tf = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
+  const char* tc = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
+  if (l == 0 && L.ob && Ops<T>::O(L)) {
     const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
     const T* ov = Ops<T>::O(L);
     AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, x, b, om, y, st, tf,

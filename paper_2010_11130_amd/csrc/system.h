@@ -231,6 +231,8 @@ struct ah_hier {
   const char* tail_img_t[2] = {nullptr, nullptr};
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
   int64_t dcgs_min = (int64_t)1 << 21;   // FGMRES uses delayed CGS2 from this many unknowns on
+  int gc = 0;                  // lanes per row of the coarse-level kernels (0: from the mean row length)
+  int64_t list_min = (int64_t)1 << 16;   // coarse levels from this many rows on sweep their F and C lists
   TailLevel* d_tail = nullptr; // device copy of every level's pointers
   const char* tail_img[2] = {nullptr, nullptr};   // the tail's LDS image (FP64 / FP32), built at setup
   ah::Arena arena;

@@ -1,7 +1,11 @@
-"""FGMRES with the delayed CGS2 orthogonalisation (the solver's default from
-2^21 unknowns on; forced here on the small parity cases with AH_DCGS_MIN=0)
-against the oracle, which orthogonalises by modified Gram-Schmidt: the two
-differ only in rounding.
+"""Solver code paths that the library picks by problem size, forced on the
+small parity cases and compared with the oracle:
+  * FGMRES with the delayed CGS2 orthogonalisation (default from 2^21
+    unknowns; AH_DCGS_MIN=0 here); the oracle orthogonalises by modified
+    Gram-Schmidt, so the two differ only in rounding;
+  * coarse levels swept through their F and C point lists after an explicit
+    interpolation (default from 2^16 rows; AH_LIST_MIN=0 here), with 2, 4
+    and 8 lanes per row (AH_GC).
 
 Tolerances as in the other parity tests: solution at tol 1e-12 within 1e-10
 relative of the oracle's, iteration counts at the workload tolerance within
@@ -97,3 +101,42 @@ def test_dcgs2_iteration_limit_and_same_iterations_as_cgs2(built, monkeypatch):
     Hc = Hierarchy(g, max_coarse=SMALL_COARSE)
     _, icg = Hc.solve(tol=1e-9)
     assert abs(idc["iters"] - icg["iters"]) <= 1, (idc["iters"], icg["iters"])
+
+
+@pytest.fixture(params=["2", "4", "8"])
+def coarse_lists(request, monkeypatch):
+    monkeypatch.setenv("AH_LIST_MIN", "0")
+    monkeypatch.setenv("AH_GC", request.param)
+    return request.param
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_coarse_list_sweeps_vcycle(built, coarse_lists, name, fp32):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, fp32, coarse_lists, flush=True)
+    g, o = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1 if fp32 else 0)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+    r = np.random.default_rng(52).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda"), precision=1 if fp32 else 0).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    if not fp32:
+        assert err <= 1e-10
+    else:
+        z32 = oair.vcycle(OH, r, dtype=np.float32).astype(np.float64)
+        assert err <= 4.0 * np.linalg.norm(z32 - zo) / np.linalg.norm(zo) + 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "layer"])
+def test_coarse_list_sweeps_solve(built, coarse_lists, name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, coarse_lists, flush=True)
+    g, o = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, relax=1 if name == "layer" else 0)
+    x, info = H.solve(tol=1e-12)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax="F" if name == "layer" else "FFC")
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
