@@ -58,6 +58,25 @@ typedef struct ah_hier ah_hier;
 /* Last error message of the calling thread (never NULL). */
 const char* ah_last_error(void);
 
+/* ------------------------------------------------------------ memory ---
+ * Device memory of library objects (ah_system, ah_hier, the solver
+ * workspace a hierarchy allocates on its first solve, temporaries) comes
+ * from a library-owned stream-ordered pool unless the caller registers its
+ * own allocator (e.g. torch's caching allocator, so both share one pool):
+ *   alloc(ctx, bytes, stream): device memory of at least bytes (256-byte
+ *     aligned) usable in stream order on stream (a hipStream_t), or NULL
+ *     (the library call then fails with AH_ENOMEM);
+ *   free(ctx, ptr, bytes, stream): gives it back, with the stream and size
+ *     of the allocation, after the last work using it has been enqueued on
+ *     that stream (destroy calls, end of temporaries).
+ * Memory keeps the allocator it came from when the registration changes.
+ * Both NULL restores the pool; one NULL is AH_EINVAL.  The registration is
+ * process-wide and may be changed from any thread; the callbacks may run on
+ * any thread that calls the library. */
+typedef void* (*ah_alloc_fn)(void* ctx, int64_t bytes, void* stream);
+typedef void (*ah_free_fn)(void* ctx, void* ptr, int64_t bytes, void* stream);
+ah_status ah_set_allocator(ah_alloc_fn alloc, ah_free_fn free, void* ctx);
+
 /* ---------------------------------------------------------------- mesh ---
  * Space-time simplex mesh (Section 2.2: slab-by-slab slabs or one
  * all-at-once triangulation).  vert: host [nv][dim_st]; cell: host

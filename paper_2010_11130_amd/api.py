@@ -59,6 +59,35 @@ def _vec(t, n, name, shape=None, out=False):
     return t.to(torch.float64).contiguous()
 
 
+_torch_alloc = None
+
+
+def use_torch_allocator(on=True):
+    """Route the library's device allocations through torch's caching
+    allocator (``ah_set_allocator``), so the library and torch share one
+    pool and ``torch.cuda.memory_allocated`` counts the library's objects;
+    ``on=False`` restores the library's own pool.  Memory keeps the allocator
+    it came from."""
+    from ._lib import ALLOC_FN, FREE_FN
+    global _torch_alloc
+    if not on:
+        check(lib().ah_set_allocator(ALLOC_FN(), FREE_FN(), None), "ah_set_allocator")
+        return
+
+    def alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:          # out of memory: the library reports AH_ENOMEM
+            return None
+
+    def free(ctx, ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (ALLOC_FN(alloc), FREE_FN(free))
+    check(lib().ah_set_allocator(cbs[0], cbs[1], None), "ah_set_allocator")
+    _torch_alloc = cbs        # the callbacks must outlive every allocation made through them
+
+
 def sizes(dim_st, p):
     """(nq, nqf, nu, b) for space-time dimension ``dim_st`` and degree ``p``."""
     a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()

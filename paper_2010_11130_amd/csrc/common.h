@@ -46,7 +46,16 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // on; switching stream starts a new chunk.
 struct Arena {
   static constexpr size_t CHUNK = size_t(32) << 20;
-  std::vector<std::pair<void*, hipStream_t>> ptrs;
+  // a chunk with the stream it was allocated on and, for memory from a
+  // caller-registered allocator (ah_set_allocator), that allocator's free
+  struct Chunk {
+    void* p;
+    hipStream_t stream;
+    size_t bytes;
+    ah_free_fn free_fn;
+    void* ctx;
+  };
+  std::vector<Chunk> ptrs;
   char* cur = nullptr;
   size_t left = 0;
   hipStream_t stream = nullptr;      // stream of the next allocations

@@ -52,6 +52,12 @@ static hipMemPool_t device_pool() {
   return pools[dev];
 }
 
+// The caller's device allocator (ah_set_allocator), if one is registered.
+static std::mutex g_alloc_mu;
+static ah_alloc_fn g_alloc = nullptr;
+static ah_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+
 ah_status Arena::alloc(void** p, size_t bytes) {
   *p = nullptr;
   bytes = (std::max<size_t>(bytes, 16) + 255) & ~size_t(255);
@@ -59,13 +65,31 @@ ah_status Arena::alloc(void** p, size_t bytes) {
   if (bytes > left) {
     size_t want = std::max(bytes, CHUNK);
     void* q = nullptr;
-    hipMemPool_t pool = device_pool();
-    hipError_t e = pool ? hipMallocFromPoolAsync(&q, want, pool, stream) : hipMallocAsync(&q, want, stream);
-    if (e != hipSuccess) {
-      set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
-      return AH_ENOMEM;
+    ah_alloc_fn afn;
+    ah_free_fn ffn;
+    void* ctx;
+    {
+      std::lock_guard<std::mutex> lock(g_alloc_mu);
+      afn = g_alloc;
+      ffn = g_free;
+      ctx = g_alloc_ctx;
     }
-    ptrs.emplace_back(q, stream);
+    if (afn) {
+      q = afn(ctx, (int64_t)want, (void*)stream);
+      if (!q) {
+        set_error("device allocation of %zu bytes failed (caller's allocator)", want);
+        return AH_ENOMEM;
+      }
+    } else {
+      ffn = nullptr;
+      hipMemPool_t pool = device_pool();
+      hipError_t e = pool ? hipMallocFromPoolAsync(&q, want, pool, stream) : hipMallocAsync(&q, want, stream);
+      if (e != hipSuccess) {
+        set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+        return AH_ENOMEM;
+      }
+    }
+    ptrs.push_back({q, stream, want, ffn, ctx});
     if (want > CHUNK) {          // dedicated chunk for a large buffer
       *p = q;
       return AH_OK;
@@ -81,7 +105,12 @@ ah_status Arena::alloc(void** p, size_t bytes) {
 }
 
 void Arena::release() {
-  for (auto& c : ptrs) (void)hipFreeAsync(c.first, c.second);
+  for (auto& c : ptrs) {
+    if (c.free_fn)
+      c.free_fn(c.ctx, c.p, (int64_t)c.bytes, (void*)c.stream);
+    else
+      (void)hipFreeAsync(c.p, c.stream);
+  }
   ptrs.clear();
   cur = nullptr;
   left = 0;
@@ -687,3 +716,15 @@ extern "C" ah_status ah_quad_rule(int dim, int n, double* xi, double* w) {
 }
 
 extern "C" const char* ah_last_error(void) { return ah::g_last_error_cstr(); }
+
+extern "C" ah_status ah_set_allocator(ah_alloc_fn alloc, ah_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    ah::set_error("ah_set_allocator: alloc and free must both be set or both be NULL");
+    return AH_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(ah::g_alloc_mu);
+  ah::g_alloc = alloc;
+  ah::g_free = free_fn;
+  ah::g_alloc_ctx = alloc ? ctx : nullptr;
+  return AH_OK;
+}

@@ -933,7 +933,7 @@ __global__ __launch_bounds__(DOT_T) void k_maxpy_norm(int64_t n, int k, const do
 // Q_l.w at row j + l, then u.u, u.w, w.w at rows 2j, 2j+1, 2j+2.  Blocks
 // along y take DD_V basis vectors each; the blocks of y = 0 also form the
 // three scalars.
-constexpr int DD_V = 16;
+constexpr int DD_V = 8;
 
 __global__ __launch_bounds__(256) void k_dcgs_dot(int64_t n, int j, const double* __restrict__ V,
                                                   const double* __restrict__ w, double* __restrict__ partial,

@@ -99,3 +99,11 @@ def test_sizes(L):
     assert sizes(2, 1) == (9, 3, 3, 2)
     assert sizes(3, 2) == (64, 16, 10, 6)
     assert sizes(3, 1) == (27, 9, 4, 3)
+
+
+def test_set_allocator_needs_both_callbacks(L):
+    from paper_2010_11130_amd._lib import ALLOC_FN, FREE_FN, AH_EINVAL, AH_OK
+    keep = ALLOC_FN(lambda ctx, n, s: None)
+    assert L.ah_set_allocator(keep, FREE_FN(), None) == AH_EINVAL
+    assert b"both" in L.ah_last_error()
+    assert L.ah_set_allocator(ALLOC_FN(), FREE_FN(), None) == AH_OK
