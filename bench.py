@@ -441,6 +441,33 @@ def c3_variants(c3, tol, x64):
     return out
 
 
+def c1_record(n=16, p=1, nu=1e-4, tol=1e-10, steps=20):
+    """The C1 problem (1+1D, (0,1)^2 as n x n quads -> 2 n^2 triangles, p = 1,
+    a = 1, manufactured u = sin 2 pi (x - t) e^-t, 1,536 free DOFs at n = 16):
+    assembly, then setup + solve to 1e-10 timed over ``steps`` passes, FP64
+    and FP32 cycles.  Latency bound (a few thousand unknowns): no roofline
+    claim."""
+    import torch
+    from paper_2010_11130_amd import System
+    from workloads import square_tri_mesh
+    from workloads.problems import C1Advection1D
+    prob = C1Advection1D(nu)
+    v, c = square_tri_mesh(n)
+    m, xe, g, a, f = workload_inputs(v, c, prob, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = System(m, p, nu, a, f, g, keep=False)
+    torch.cuda.synchronize()
+    out = {"mesh": "%dx%d quads -> %d triangles" % (n, n, c.shape[0]), "p": p, "free_dofs": s.n,
+           "assemble_ms": 1e3 * (time.perf_counter() - t0)}
+    for prec in (0, 1):
+        r, _, x = setup_solve_steps(s, steps, 2, tol, prec)
+        out["fp64" if prec == 0 else "fp32_cycle"] = {k: r[k] for k in ("value", "ms_per_step", "setup_ms_median",
+                                                                        "solve_ms_median", "iters", "levels")}
+        del x
+    return out
+
+
 def c5_adjoint(tol):
     """The C5 workload: the 48^3 Kuhn mesh mapped by the time-dependent
     domain map (663,552 tets, p = 2, 7.9M free DOFs), 256 Gaussian sources,
@@ -1076,6 +1103,7 @@ def main():
     if not args.no_large:
         out["c5_adjoint"] = c5_adjoint(args.tol)
         log("bench: C5 done")
+    out["c1"] = c1_record()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.c3_nu, args.tol)
     print(json.dumps(out))

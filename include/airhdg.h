@@ -113,6 +113,10 @@ ah_status ah_quad_rule(int dim, int n, double* xi, double* w);
  * [ne][nq][dim_st], xq_bfacet dev [nbf][nqf][dim_st] (either may be NULL). */
 ah_status ah_quad_points(const ah_mesh* m, int p, double* xq_elem, double* xq_bfacet,
                          void* stream);
+/* The same facet rule at every facet: xq_facet dev [nf][nqf][dim_st] (facet
+ * point q is the same physical point seen from either adjacent cell), where
+ * the caller evaluates a velocity field for hdg_assemble_q.  Synchronizes. */
+ah_status ah_quad_points_facets(const ah_mesh* m, int p, double* xq_facet, void* stream);
 
 /* ------------------------------------------------------- hdg_assemble ---
  * Space-time HDG discretization (Section 2.3, bilinear form with upwind
@@ -124,7 +128,8 @@ ah_status ah_quad_points(const ah_mesh* m, int p, double* xq_elem, double* xq_bf
  * facets.
  *   alpha <= 0 selects 10 p^2 (Section 4).
  *   a_vert: dev [nv][d] velocity at the vertices, interpolated linearly in
- *           each cell (exact for affine velocity fields).
+ *           each cell (exact for affine velocity fields; hdg_assemble_q
+ *           takes any field at the quadrature points).
  *   f_q:    dev [ne][nq] source at ah_quad_points' element points, or NULL (0).
  *   g_q:    dev [nbf][nqf] boundary data at the boundary-facet points:
  *           g_D on Dirichlet facets, g_N on Neumann facets; NULL = 0.
@@ -142,6 +147,18 @@ typedef struct {
 ah_status hdg_assemble(const ah_mesh* m, const ah_hdg_params* prm, double nu,
                        const double* a_vert, const double* f_q, const double* g_q,
                        void* stream, ah_system** out);
+/* hdg_assemble with the velocity given at the quadrature points instead of
+ * the vertices, for fields that are not affine in each cell (Section 2.3:
+ * the advective volume term integrates u a.grad v with a(x) at the element
+ * points; the upwind flux takes a.n at each facet point):
+ *   a_qe: dev [ne][nq][d] at ah_quad_points' element points;
+ *   a_qf: dev [nf][nqf][d] at ah_quad_points_facets' points.
+ * For an affine field the result equals hdg_assemble's with the field's
+ * vertex values (to rounding).  Other arguments, results and errors as in
+ * hdg_assemble. */
+ah_status hdg_assemble_q(const ah_mesh* m, const ah_hdg_params* prm, double nu, const double* a_qe,
+                         const double* a_qf, const double* f_q, const double* g_q, void* stream,
+                         ah_system** out);
 /* Replace the Neumann data of an assembled system (Section 2.3: the data
  * term on Neumann facets, i.e. the inflow u(t_n) on a slab's initial plane,
  * Section 2.4).  g_q dev [nbf][nqf] as in hdg_assemble; only the rows of
@@ -342,7 +359,9 @@ ah_status ah_vcycle_apply(const ah_hier* h, const double* r, double* z, int prec
  *          in nu), sum over elements of
  *          -w_K.(A1 U + B1 Lambda) - lam_K.(C1 U + D1 Lambda),
  *          w_K = -A_K^-T C_K^T lam_K.
- * Requires keep_element_data.  Synchronizes the stream. */
+ * a_vert is not read (the nu-dependent part of the blocks has no advective
+ * term) and may be NULL.  Requires keep_element_data.  Synchronizes the
+ * stream. */
 ah_status hdg_assemble_grad(const ah_system* s, const double* a_vert, const double* lam_fwd,
                             const double* lam_adj, double* dJdf_q, double* dJdnu, void* stream);
 

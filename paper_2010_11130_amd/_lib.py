@@ -66,6 +66,8 @@ SIGNATURES = {
     "ah_sizes": (i32, [i32, i32, P_i32, P_i32, P_i32, P_i32]),
     "ah_quad_rule": (i32, [i32, i32, vp, vp]),
     "ah_quad_points": (i32, [vp, i32, vp, vp, vp]),
+    "ah_quad_points_facets": (i32, [vp, i32, vp, vp]),
+    "hdg_assemble_q": (i32, [vp, C.POINTER(HdgParams), dbl, vp, vp, vp, vp, vp, C.POINTER(vp)]),
     "hdg_assemble": (i32, [vp, C.POINTER(HdgParams), dbl, vp, vp, vp, vp, C.POINTER(vp)]),
     "ah_system_destroy": (None, [vp]),
     "ah_system_sizes": (i32, [vp, P_i64, P_i32, P_i64]),

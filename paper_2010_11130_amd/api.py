@@ -152,25 +152,47 @@ class Mesh:
         check(lib().ah_quad_points(self.h, p, _p(xe), _p(xb), _stream()), "ah_quad_points")
         return xe, xb[:self.nbf]
 
+    def facet_points(self, p):
+        """Quadrature points of every facet, [nf][nqf][D] (device)."""
+        _, nqf, _, _ = sizes(self.D, p)
+        xf = torch.empty((max(self.nf, 1), nqf, self.D), dtype=torch.float64, device="cuda")
+        check(lib().ah_quad_points_facets(self.h, p, _p(xf), _stream()), "ah_quad_points_facets")
+        return xf[:self.nf]
+
 
 class System:
     """Assembled, condensed and scaled facet system (``hdg_assemble``)."""
 
-    def __init__(self, mesh, p, nu, a_vert, f_q=None, g_q=None, alpha=0.0, keep=True, block_scale=True):
+    def __init__(self, mesh, p, nu, a_vert=None, f_q=None, g_q=None, alpha=0.0, keep=True, block_scale=True,
+                 a_q=None):
+        """``a_vert``: velocity at the vertices ``[nv][d]`` (affine fields), or
+        ``a_q = (a_elem, a_facet)``: velocity at the element quadrature points
+        ``[ne][nq][d]`` and at every facet's points ``[nf][nqf][d]``
+        (``hdg_assemble_q``)."""
         if mesh.kind is None:
             raise ValueError("boundary kinds not set (Mesh.set_bc)")
+        if (a_vert is None) == (a_q is None):
+            raise ValueError("give the velocity either at the vertices (a_vert) or at the quadrature points (a_q)")
         self.mesh = mesh
         self.p = p
         self.nu = float(nu)
         nq, nqf, _, _ = sizes(mesh.D, p)
         d = mesh.D - 1
-        self._a = _vec(_dev(a_vert), mesh.nv * d, "a_vert", (mesh.nv, d))
         self._f = _vec(f_q, mesh.ne * nq, "f_q", (mesh.ne, nq))
         self._g = _vec(g_q, mesh.nbf * nqf, "g_q", (mesh.nbf, nqf))
         prm = HdgParams(p, float(alpha), 1 if keep else 0, 0 if block_scale else 1)
         h = C.c_void_p()
-        check(lib().hdg_assemble(mesh.h, C.byref(prm), float(nu), _p(self._a), _p(self._f), _p(self._g),
-                                 _stream(), C.byref(h)), "hdg_assemble")
+        if a_q is None:
+            self._a = _vec(_dev(a_vert), mesh.nv * d, "a_vert", (mesh.nv, d))
+            check(lib().hdg_assemble(mesh.h, C.byref(prm), float(nu), _p(self._a), _p(self._f), _p(self._g),
+                                     _stream(), C.byref(h)), "hdg_assemble")
+        else:
+            self._a = None
+            ae = _vec(a_q[0], mesh.ne * nq * d, "a_q[0]", (mesh.ne, nq, d))
+            af = _vec(a_q[1], mesh.nf * nqf * d, "a_q[1]", (mesh.nf, nqf, d))
+            self._aq = (ae, af)
+            check(lib().hdg_assemble_q(mesh.h, C.byref(prm), float(nu), _p(ae), _p(af), _p(self._f), _p(self._g),
+                                       _stream(), C.byref(h)), "hdg_assemble_q")
         self.h = h
         n, b, nnz = C.c_int64(), C.c_int(), C.c_int64()
         check(lib().ah_system_sizes(h, C.byref(n), C.byref(b), C.byref(nnz)), "ah_system_sizes")

@@ -47,6 +47,8 @@ struct ElemArgs {
   const int32_t* free_rank;
   const int32_t* elem_slot;
   const double* a_vert;
+  const double* a_qe;      // velocity at the element quadrature points [ne][nq][D-1], or null
+  const double* a_qf;      // velocity at the facet quadrature points [nf][nqf][D-1], or null
   const double* f_q;
   const double* g_q;
   const double* vol_w;
@@ -97,8 +99,13 @@ struct ElemSmem {
   // quadrature scratch of the integration phase
   struct Quad {
     double q_wf[S::NQ];             // W_q f_q at the element points
-    double f_phi[S::NQF * S::NU];
-    double f_dn[S::NQF * S::NU];
+    union {
+      struct {
+        double f_phi[S::NQF * S::NU];
+        double f_dn[S::NQF * S::NU];
+      };
+      double beta[S::NQ * D];       // J^-1 (1, a(x_q)) of the volume phase (velocity at points)
+    };
     double f_cA[S::NQF], f_cB[S::NQF], f_cD[S::NQF], f_W[S::NQF], f_g[S::NQF];
     double f_psi[S::NQF * S::B];    // facet basis at the facet points (staged)
     double f_proj[S::B * S::NQF];   // facet L2 projection weights (staged)
@@ -227,15 +234,35 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
   const bool has_f = data && a.f_q;
   if (has_f)
     for (int q = t; q < NQ; q += NT) sm.qd.q_wf[q] = a.vol_w[q] * sm.absdet * a.f_q[e * NQ + q];
+  // velocity given at the quadrature points: beta_q = J^-1 (1, a(x_q)), and
+  // the advective part of A_ij is sum_q w_q phi_j(x_q) beta_q . grad phi_i(x_q)
+  const bool aq = advect && a.a_qe;
+  if (aq)
+    for (int k = t; k < NQ * D; k += NT) {
+      const int q = k / D, r = k % D;
+      double v = sm.Jinv[r * D];
+      for (int c = 1; c < D; ++c) v += sm.Jinv[r * D + c] * a.a_qe[((int64_t)e * NQ + q) * (D - 1) + c - 1];
+      sm.qd.beta[k] = v;
+    }
   __syncthreads();
   for (int idx = t; idx < NU * NU; idx += NT) {
     double adv = 0.0, dif = 0.0;
-    _Pragma("unroll") for (int kr = 0; kr < (D + 1) * D; ++kr)
-      adv += sm.vcoef[kr] * a.ten_adv[(size_t)kr * NU * NU + idx];
+    if (aq) {
+      const int i = idx / NU, j = idx % NU;
+      for (int q = 0; q < NQ; ++q) {
+        double g = 0.0;
+        _Pragma("unroll") for (int r = 0; r < D; ++r) g += sm.qd.beta[q * D + r] * a.vol_dphi[(q * NU + i) * D + r];
+        adv += a.vol_w[q] * a.vol_phi[q * NU + j] * g;
+      }
+    } else {
+      _Pragma("unroll") for (int kr = 0; kr < (D + 1) * D; ++kr)
+        adv += sm.vcoef[kr] * a.ten_adv[(size_t)kr * NU * NU + idx];
+    }
     _Pragma("unroll") for (int rs = 0; rs < D * D; ++rs)
       dif += sm.vcoef[(D + 1) * D + rs] * a.ten_dif[(size_t)rs * NU * NU + idx];
     sm.A[idx] = sm.absdet * (nu_eff * dif - adv);
   }
+  __syncthreads();
   for (int i = t; i < NU; i += NT) {
     double acc = 0.0;
     if (has_f)
@@ -282,7 +309,10 @@ __device__ void elem_integrate(const ElemArgs& a, ElemSmem<D, P>& sm, int64_t e,
         an = sm.nrm[lf * D];
         for (int c = 1; c < D; ++c) {
           double v = 0.0;
-          for (int k = 0; k <= D; ++k) v += lam[k] * sm.av[k * (D - 1) + c - 1];
+          if (a.a_qf)
+            v = a.a_qf[((int64_t)sm.fid[lf] * NQF + q) * (D - 1) + c - 1];
+          else
+            for (int k = 0; k <= D; ++k) v += lam[k] * sm.av[k * (D - 1) + c - 1];
           an += v * sm.nrm[lf * D + c];
         }
       }
@@ -1020,9 +1050,9 @@ extern "C" ah_status ah_quad_points(const ah_mesh* mc, int p, double* xq_elem, d
   return AH_OK;
 }
 
-extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, double nu, const double* a_vert,
-                                  const double* f_q, const double* g_q, void* stream, ah_system** out) {
-  if (!mc || !prm || !out || !a_vert) { set_error("hdg_assemble: null argument"); return AH_EINVAL; }
+static ah_status assemble_impl(const ah_mesh* mc, const ah_hdg_params* prm, double nu, const double* a_vert,
+                               const double* a_qe, const double* a_qf, const double* f_q, const double* g_q,
+                               void* stream, ah_system** out) {
   if (!(nu >= 0.0) || !std::isfinite(nu)) { set_error("hdg_assemble: nu must be finite and >= 0"); return AH_EINVAL; }
   if (!mc->bc_set) { set_error("hdg_assemble: boundary kinds not set"); return AH_EINVAL; }
   *out = nullptr;
@@ -1072,6 +1102,8 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   ElemArgs a{};
   fill_common(a, m, t);
   a.a_vert = a_vert;
+  a.a_qe = a_qe;
+  a.a_qf = a_qf;
   a.f_q = f_q;
   a.g_q = g_q;
   a.nu = nu;
@@ -1096,6 +1128,47 @@ extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, d
   }
   *out = s;
   return AH_OK;
+}
+
+extern "C" ah_status ah_quad_points_facets(const ah_mesh* mc, int p, double* xq_facet, void* stream) {
+  if (!mc || !xq_facet) { set_error("ah_quad_points_facets: null argument"); return AH_EINVAL; }
+  ah_mesh* m = const_cast<ah_mesh*>(mc);
+  if (m->nf == 0) return AH_OK;
+  hipStream_t st = as_stream(stream);
+  RefTables t;
+  AH_TRY(build_ref_tables(m->D, p, t));
+  Arena tmp;
+  tmp.stream = st;
+  AH_TRY(upload_ref_tables(t, tmp));
+  std::vector<int32_t> ids((size_t)m->nf);
+  for (int64_t f = 0; f < m->nf; ++f) ids[(size_t)f] = (int32_t)f;
+  double* d_vert = nullptr;
+  int32_t *d_ids = nullptr, *d_fv = nullptr;
+  AH_TRY(tmp.get(&d_vert, m->vert.size()));
+  AH_TRY(tmp.get(&d_ids, ids.size()));
+  AH_TRY(tmp.get(&d_fv, m->facet_vert.size()));
+  AH_HIP(hipMemcpyAsync(d_vert, m->vert.data(), m->vert.size() * 8, hipMemcpyHostToDevice, st));
+  AH_HIP(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st));
+  AH_HIP(hipMemcpyAsync(d_fv, m->facet_vert.data(), m->facet_vert.size() * 4, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_quad_points_bfacet, dim3(cdiv(m->nf * t.nqf, 256)), dim3(256), 0, st, m->nf, m->D, t.nqf,
+                     d_vert, d_ids, d_fv, t.d_fac_mu, xq_facet);
+  AH_LAUNCHED();
+  AH_HIP(hipStreamSynchronize(st));
+  tmp.release();
+  return AH_OK;
+}
+
+extern "C" ah_status hdg_assemble(const ah_mesh* mc, const ah_hdg_params* prm, double nu, const double* a_vert,
+                                  const double* f_q, const double* g_q, void* stream, ah_system** out) {
+  if (!mc || !prm || !out || !a_vert) { set_error("hdg_assemble: null argument"); return AH_EINVAL; }
+  return assemble_impl(mc, prm, nu, a_vert, nullptr, nullptr, f_q, g_q, stream, out);
+}
+
+extern "C" ah_status hdg_assemble_q(const ah_mesh* mc, const ah_hdg_params* prm, double nu, const double* a_qe,
+                                    const double* a_qf, const double* f_q, const double* g_q, void* stream,
+                                    ah_system** out) {
+  if (!mc || !prm || !out || !a_qe || !a_qf) { set_error("hdg_assemble_q: null argument"); return AH_EINVAL; }
+  return assemble_impl(mc, prm, nu, nullptr, a_qe, a_qf, f_q, g_q, stream, out);
 }
 
 extern "C" ah_status hdg_update_neumann(ah_system* s, const double* g_q, void* stream) {

@@ -189,7 +189,7 @@ extern "C" ah_status hdg_inflow_from_trace(const ah_system* prev, const double* 
 
 extern "C" ah_status hdg_assemble_grad(const ah_system* s, const double* a_vert, const double* lam_fwd,
                                        const double* lam_adj, double* dJdf_q, double* dJdnu, void* stream) {
-  if (!s || !a_vert || !lam_fwd || !lam_adj) { set_error("hdg_assemble_grad: null argument"); return AH_EINVAL; }
+  if (!s || !lam_fwd || !lam_adj) { set_error("hdg_assemble_grad: null argument"); return AH_EINVAL; }
   if (!s->keep) { set_error("hdg_assemble_grad: system assembled without keep_element_data"); return AH_EINVAL; }
   hipStream_t st = as_stream(stream);
   const int64_t ne = s->mesh->ne;

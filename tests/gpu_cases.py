@@ -66,7 +66,10 @@ def boundary_data(prob, vert, fv, bf, kinds, xb):
     return torch.where(kb == 1, gD, torch.where(bot, gN0, gN1)).contiguous()
 
 
-def gpu_system(vert, cell, prob, p, keep=True, block_scale=True):
+def gpu_system(vert, cell, prob, p, keep=True, block_scale=True, at_points=False):
+    """The problem assembled on the HIP path; ``at_points``: the velocity is
+    passed at the quadrature points (``hdg_assemble_q``) instead of the
+    vertices."""
     from paper_2010_11130_amd import Mesh, System
     m = Mesh(vert, cell)
     fv, _ = m.facets()
@@ -78,8 +81,12 @@ def gpu_system(vert, cell, prob, p, keep=True, block_scale=True):
     xe, xb = m.quad_points(p)
     f = prob.f(xe).contiguous()
     g = boundary_data(prob, vert, fv, bf, kinds, xb)
-    a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(vert)), device="cuda")
-    s = System(m, p, prob.nu, a, f, g, keep=keep, block_scale=block_scale)
+    if at_points:
+        a = (prob.a(xe).contiguous(), prob.a(m.facet_points(p)).contiguous())
+        s = System(m, p, prob.nu, None, f, g, keep=keep, block_scale=block_scale, a_q=a)
+    else:
+        a = torch.as_tensor(np.ascontiguousarray(prob.a_vertices(vert)), device="cuda")
+        s = System(m, p, prob.nu, a, f, g, keep=keep, block_scale=block_scale)
     s._keep_alive = (m, xe, xb, f, g, a)
     return s
 

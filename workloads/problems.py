@@ -305,3 +305,34 @@ class MovingInternalLayer(Problem):
         t, x1, x2 = X[..., 0], X[..., 1], X[..., 2]
         inside = (x1 * x1 + x2 * x2 < 1.0) & (xp.arctan2(x2, x1) > math.pi / 2 - t)
         return xp.where(inside, xp.ones_like(t), xp.zeros_like(t))
+
+
+class SwirlFlow(Problem):
+    """A velocity that is not affine in x, for the assembly with the velocity
+    at the quadrature points: 1+1-D ``a = 1 + 0.5 sin(2 pi x) cos(t)``,
+    2+1-D ``a = (1 + 0.3 sin(pi x2) cos(t), 0.5 + 0.3 sin(pi x1))``.  Boundary
+    and initial data from ``u = sin(pi x1) e^-t`` (times ``sin(pi x2) + 1`` in
+    2+1-D), ``f = 0``; no exact solution."""
+    has_exact = False
+
+    def __init__(self, d, nu):
+        self.d = d
+        self.nu = nu
+
+    def a(self, X):
+        xp = _ns(X)
+        t = X[..., 0]
+        if self.d == 1:
+            return (1.0 + 0.5 * xp.sin(2 * math.pi * X[..., 1]) * xp.cos(t))[..., None]
+        return xp.stack([1.0 + 0.3 * xp.sin(math.pi * X[..., 2]) * xp.cos(t),
+                         0.5 + 0.3 * xp.sin(math.pi * X[..., 1])], axis=-1)
+
+    def a_vertices(self, vert):
+        return self.a(vert)
+
+    def u(self, X):
+        xp = _ns(X)
+        v = xp.sin(math.pi * X[..., 1]) * xp.exp(-X[..., 0])
+        if self.d == 2:
+            v = v * (xp.sin(math.pi * X[..., 2]) + 1.0)
+        return v
