@@ -230,6 +230,10 @@ typedef struct {
   double theta_r;      /* restriction strength threshold; <= 0: theta (default) */
   double order_ratio;  /* relax 2, 3: dominance ratio that orders a pair of
                           facet blocks (>= 1; default 1.5) */
+  int coarsening;      /* 0: PMIS (default, data-parallel); 1: Ruge-Stueben
+                          first pass, the single-process form of the Falgout
+                          coarsening of Section 4 (largest measure first, ties
+                          to the smallest index; sequential, on the host) */
 } ah_air_params;
 
 typedef struct {

@@ -15,7 +15,10 @@ the design notes):
   * coarsening: PMIS on the symmetrised strength graph, point weights compared
     as the integer key ``influence_count * 2^44 + hash44(i, level)`` (a
     bijective 44-bit mix, so keys never tie); points nothing depends on
-    strongly start as F; coarse index = rank of the C point;
+    strongly start as F; coarse index = rank of the C point; or, as an
+    option, the sequential Ruge-Stueben first pass (largest measure first,
+    ties to the smallest index), the single-process form of the Falgout
+    coarsening the paper uses;
   * lAIR restriction row of C point i: ``N_i`` = strong F neighbours (sorted)
     for distance one; for distance two also the strong F neighbours of those
     (paths through F points only); the strength tolerance of R may differ
@@ -99,6 +102,58 @@ def pmis(A, strong, level):
         dep[si[hit]] = True
         state[dep & (state == 0)] = -1
     return (state == 1).astype(np.int8)
+
+
+def rs_first_pass(A, strong):
+    """Ruge-Stueben first-pass coarsening (the single-process form of the
+    Falgout coarsening of Section 4): returns ``cf`` with 1 = C, 0 = F.
+
+    With ``S_i`` the strong dependencies of i and ``S_i^T`` the points that
+    depend strongly on i, the measure of an undecided point is the number of
+    undecided points of ``S_i^T``.  Points with measure 0 at the start (nothing
+    depends on them) are F.  Then, while points are undecided: the undecided
+    point of largest measure (ties: smallest index) becomes C; the undecided
+    points of ``S_i^T`` become F, and each undecided point that a new F point
+    depends on gains one in measure; each undecided point of ``S_i`` loses
+    one, and an undecided point whose measure reaches 0 becomes F."""
+    import heapq
+    n = A.shape[0]
+    r = _rows(A)
+    si, sj = r[strong], A.indices[strong]            # i depends strongly on j
+    S = [[] for _ in range(n)]
+    ST = [[] for _ in range(n)]
+    for a, b in zip(si.tolist(), sj.tolist()):
+        S[a].append(b)
+        ST[b].append(a)
+    lam = [len(ST[i]) for i in range(n)]
+    state = [0] * n                                  # 0 undecided, 1 C, -1 F
+    heap = []
+    for i in range(n):
+        if lam[i] == 0:
+            state[i] = -1
+        else:
+            heap.append((-lam[i], i))
+    heapq.heapify(heap)
+    while heap:
+        m, i = heapq.heappop(heap)
+        if state[i] != 0 or -m != lam[i]:
+            continue                                 # stale entry
+        state[i] = 1
+        for j in ST[i]:
+            if state[j] == 0:
+                state[j] = -1
+                for k in S[j]:
+                    if state[k] == 0:
+                        lam[k] += 1
+                        heapq.heappush(heap, (-lam[k], k))
+        for k in S[i]:
+            if state[k] == 0:
+                lam[k] -= 1
+                if lam[k] == 0:
+                    state[k] = -1
+                else:
+                    heapq.heappush(heap, (-lam[k], k))
+    return (np.array(state) == 1).astype(np.int8)
 
 
 def one_point_P(A, strong, cf, cidx):
@@ -335,16 +390,19 @@ class Hierarchy:
 
 
 def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
-          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1, order_ratio=1.5):
+          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1, order_ratio=1.5, coarsening="pmis"):
     """Build the lAIR hierarchy on the scaled matrix (treated as scalar).
     ``theta`` is the strength tolerance of the coarsening (and of P);
     ``theta_r`` that of the restriction neighbourhoods (default: theta);
     ``distance`` the neighbourhood distance of lAIR (1 or 2); ``relax`` one
     of "FFC", "F", "ordered", "ordered_fa"; ``block`` the facet block size
     of level 0 (the unit of the flow order); ``order_ratio`` the dominance
-    ratio that orients a pair of blocks in the flow order."""
+    ratio that orients a pair of blocks in the flow order; ``coarsening``
+    "pmis" or "rs" (Ruge-Stueben first pass)."""
     if relax not in ("FFC", "F", "ordered", "ordered_fa"):
         raise ValueError("unknown relaxation %r" % (relax,))
+    if coarsening not in ("pmis", "rs"):
+        raise ValueError("unknown coarsening %r" % (coarsening,))
     H = Hierarchy()
     H.levels = []
     H.relax, H.omega = relax, omega
@@ -361,7 +419,7 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
         if n <= max_coarse or l == max_levels - 1:
             break
         strong = strength(A, theta)
-        cf = pmis(A, strong, l)
+        cf = pmis(A, strong, l) if coarsening == "pmis" else rs_first_pass(A, strong)
         nc = int(cf.sum())
         if nc == 0 or nc > stall * n:
             break

@@ -17,6 +17,8 @@
 #include <cstring>
 #include <mutex>
 
+#include <queue>
+
 #include "prof.h"
 #include "system.h"
 
@@ -1050,6 +1052,61 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
 
 using namespace ah;
 
+// Ruge-Stueben first-pass coarsening on the host (the single-process form of
+// the Falgout coarsening of Section 4; sequential by nature): from the
+// strong entries of the CSR pattern, state[i] = 1 (C) or 2 (F).  The measure
+// of an undecided point is the number of undecided points that depend on it
+// strongly; points with measure 0 at the start are F; then the undecided
+// point of largest measure (ties: smallest index) becomes C, the undecided
+// points depending on it become F, each undecided point a new F point
+// depends on gains one, each undecided point the new C point depends on
+// loses one, and an undecided point whose measure reaches 0 becomes F.
+static void rs_first_pass_host(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
+                               const std::vector<uint8_t>& strong, std::vector<int8_t>& state) {
+  std::vector<int64_t> sp(n + 1, 0), tp(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (strong[k]) { ++sp[i + 1]; ++tp[col[k] + 1]; }
+  for (int64_t i = 0; i < n; ++i) { sp[i + 1] += sp[i]; tp[i + 1] += tp[i]; }
+  std::vector<int32_t> sc(sp[n]), tc(tp[n]);
+  {
+    std::vector<int64_t> fs(sp.begin(), sp.end() - 1), ft(tp.begin(), tp.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k]) { sc[fs[i]++] = col[k]; tc[ft[col[k]]++] = (int32_t)i; }
+  }
+  std::vector<int32_t> lam(n);
+  state.assign(n, 0);
+  std::priority_queue<std::pair<int32_t, int32_t>> heap;   // (measure, -index): largest, then smallest index
+  for (int64_t i = 0; i < n; ++i) {
+    lam[i] = (int32_t)(tp[i + 1] - tp[i]);
+    if (lam[i] == 0) state[i] = 2;
+    else heap.push({lam[i], -(int32_t)i});
+  }
+  while (!heap.empty()) {
+    const auto top = heap.top();
+    heap.pop();
+    const int32_t i = -top.second;
+    if (state[i] != 0 || top.first != lam[i]) continue;   // stale entry
+    state[i] = 1;
+    for (int64_t a = tp[i]; a < tp[i + 1]; ++a) {
+      const int32_t j = tc[a];
+      if (state[j] != 0) continue;
+      state[j] = 2;
+      for (int64_t b = sp[j]; b < sp[j + 1]; ++b) {
+        const int32_t k = sc[b];
+        if (state[k] == 0) heap.push({++lam[k], -k});
+      }
+    }
+    for (int64_t b = sp[i]; b < sp[i + 1]; ++b) {
+      const int32_t k = sc[b];
+      if (state[k] != 0) continue;
+      if (--lam[k] == 0) state[k] = 2;
+      else heap.push({lam[k], -k});
+    }
+  }
+}
+
 ah_hier::~ah_hier() { arena.release(); }
 
 extern "C" void ah_air_defaults(ah_air_params* p) {
@@ -1065,6 +1122,7 @@ extern "C" void ah_air_defaults(ah_air_params* p) {
   p->lair_distance = 1;
   p->theta_r = 0.0;
   p->order_ratio = 1.5;
+  p->coarsening = 0;
 }
 
 extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, void* stream, ah_hier** out,
@@ -1077,7 +1135,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   if (prm.order_ratio == 0.0) prm.order_ratio = 1.5;
   if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1 ||
       (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0) || prm.relax < 0 ||
-      prm.relax > 3 || !(prm.order_ratio >= 1.0 && prm.order_ratio < 1e300)) {
+      prm.relax > 3 || !(prm.order_ratio >= 1.0 && prm.order_ratio < 1e300) || prm.coarsening < 0 ||
+      prm.coarsening > 1) {
     set_error("air_setup: invalid parameters");
     return AH_EINVAL;
   }
@@ -1162,6 +1221,20 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CK(tmp.get(&key, n));
     CK(tmp.get(&nbmax, n));
     CK(tmp.get(&state, n));
+    if (prm.coarsening == 1) {
+      // Ruge-Stueben first pass on the host from the strong pattern
+      std::vector<int64_t> hrp(n + 1);
+      std::vector<int32_t> hcol(L.nnz);
+      std::vector<uint8_t> hst(L.nnz);
+      std::vector<int8_t> hstate;
+      CKH(hipMemcpyAsync(hrp.data(), L.rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(hcol.data(), L.col, L.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(hst.data(), strong, L.nnz, hipMemcpyDeviceToHost, st));
+      CKH(hipStreamSynchronize(st));
+      rs_first_pass_host(n, hrp, hcol, hst, hstate);
+      CKH(hipMemcpyAsync(state, hstate.data(), n, hipMemcpyHostToDevice, st));
+      CKH(hipStreamSynchronize(st));
+    } else {
     hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, l, key, state);
     CKH(hipGetLastError());
     CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
@@ -1190,6 +1263,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       unsigned long long left = 0;
       CK(read_bytes(left_d, &left, sizeof(left), st));
       if (left == 0) break;
+    }
     }
     // coarse numbering
     int32_t* isc = nullptr;

@@ -412,3 +412,59 @@ def test_fp32_cycle_emulation():
         assert z.dtype == np.float32
         e = np.linalg.norm(z - zr) / np.linalg.norm(zr)
         assert 1e-9 < e < 1e-5, e
+
+
+def _rs_brute(n, S_rows):
+    """Ruge-Stueben first pass with a plain scan for the next C point (tiny
+    inputs only): the same rules as the oracle's, without its heap."""
+    ST = [[] for _ in range(n)]
+    for i in range(n):
+        for j in S_rows[i]:
+            ST[j].append(i)
+    lam = [len(ST[i]) for i in range(n)]
+    state = [0 if lam[i] else -1 for i in range(n)]
+    while any(s == 0 for s in state):
+        best = None
+        for i in range(n):
+            if state[i] == 0 and (best is None or lam[i] > lam[best]):
+                best = i
+        i = best
+        state[i] = 1
+        for j in ST[i]:
+            if state[j] == 0:
+                state[j] = -1
+                for k in S_rows[j]:
+                    if state[k] == 0:
+                        lam[k] += 1
+        for k in S_rows[i]:
+            if state[k] == 0:
+                lam[k] -= 1
+                if lam[k] == 0:
+                    state[k] = -1
+    return np.array([1 if s == 1 else 0 for s in state], dtype=np.int8)
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_rs_first_pass_matches_scan_definition(which, c1_sys, slab_sys):
+    s = c1_sys if which == "c1" else slab_sys
+    A = s.Shat[:600, :600].tocsr()
+    A.sort_indices()
+    st = air.strength(A, 0.25)
+    r = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    S_rows = [[] for _ in range(A.shape[0])]
+    for a, b in zip(r[st], A.indices[st]):
+        S_rows[a].append(int(b))
+    cf = air.rs_first_pass(A, st)
+    assert np.array_equal(cf, _rs_brute(A.shape[0], S_rows))
+    # every F point that something depends on has a strong C dependency,
+    # unless its own measure fell to zero
+    assert 0 < cf.sum() < A.shape[0]
+
+
+def test_rs_coarsening_hierarchy_solves(slab_sys):
+    H = air.setup(slab_sys.Shat, max_coarse=50, coarsening="rs")
+    assert H.nlev >= 3
+    x, info = krylov.fgmres(slab_sys.Shat, slab_sys.Hhat, lambda r: air.vcycle(H, r), tol=1e-10)
+    assert info["converged"] and info["iters"] < 40
+    ref = direct_solve(slab_sys)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
