@@ -283,6 +283,73 @@ def block_weights(A, b):
     return uk, w
 
 
+def block_graph(A, b):
+    """Block graph of the level-0 matrix in facet blocks of size ``b``: CSR
+    ``W`` (nb x nb) with ``W[I, J] = w_IJ = max |a_ij|`` over each off-diagonal
+    block that holds a stored entry."""
+    uk, w = block_weights(A, b)
+    nb = A.shape[0] // b
+    W = sp.csr_matrix((w, (uk // nb, uk % nb)), shape=(nb, nb))
+    W.sort_indices()
+    return W
+
+
+def block_air_level(A, b, theta, theta_r, level):
+    """Block AIR on a level with facet-block structure (the block variant of
+    the Section 3 construction; facet blocks of size ``b`` are the unknowns):
+    strength, PMIS and one-point interpolation on the block graph
+    (``w_IJ``), the C/F splitting and P expanded to the rows of each block
+    (``P = P_blocks (x) I_b``), and the lAIR rows of each C block from one
+    local system over the rows of its strong F blocks,
+    ``A[N, N]^T Z = -A[I, N]^T`` with ``b`` right-hand sides, ``R[I, I] = I_b``.
+    Returns ``cf, P, R, n_fallback`` (scalar)."""
+    W = block_graph(A, b)
+    sb = strength(W, theta)
+    cfb = pmis(W, sb, level)
+    cidxb = np.cumsum(cfb) - 1
+    Pb = one_point_P(W, sb, cfb, cidxb)
+    P = sp.kron(Pb, sp.identity(b, format="csr")).tocsr()
+    P.eliminate_zeros()                               # kron keeps the zeros of the identity blocks
+    P.sort_indices()
+    cf = np.repeat(cfb, b).astype(np.int8)
+    cidx = np.cumsum(cf) - 1
+    nc = int(cf.sum())
+    sbr = sb if theta_r is None or theta_r == theta else strength(W, theta_r)
+    nbh = {}
+    for I in np.nonzero(cfb == 1)[0]:
+        lo, hi = W.indptr[I], W.indptr[I + 1]
+        J = W.indices[lo:hi][sbr[lo:hi] & (cfb[W.indices[lo:hi]] == 0)]
+        nbh[int(I)] = np.sort(J)
+    rows, cols, vals = [], [], []
+    nfall = 0
+    Cb = np.nonzero(cfb == 1)[0]
+    cnt = np.array([len(nbh[int(I)]) for I in Cb], dtype=np.int64)
+    for m in np.unique(cnt):
+        blocks = Cb[cnt == m]
+        own = (blocks[:, None] * b + np.arange(b)).ravel()          # the C rows
+        if m == 0:
+            rows.append(cidx[own]); cols.append(own); vals.append(np.ones(len(own)))
+            nfall += len(own)
+            continue
+        N = np.stack([nbh[int(I)] for I in blocks])                  # [k][m] blocks
+        rN = (N[:, :, None] * b + np.arange(b)).reshape(len(blocks), m * b)   # sorted rows
+        q = m * b
+        Mloc = np.asarray(A[np.repeat(rN, q, axis=1).ravel(), np.tile(rN, (1, q)).ravel()]).reshape(len(blocks), q, q)
+        MT = np.transpose(Mloc, (0, 2, 1))
+        for r in range(b):
+            ci = blocks * b + r
+            ai = np.asarray(A[np.repeat(ci, q), rN.ravel()]).reshape(len(blocks), q)
+            z, bad = batched_lu_solve(MT, -ai)
+            good = ~bad
+            nfall += int(bad.sum())
+            rows.append(cidx[ci]); cols.append(ci); vals.append(np.ones(len(ci)))
+            rows.append(np.repeat(cidx[ci[good]], q)); cols.append(rN[good].ravel())
+            vals.append(z[good].ravel())
+    R = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nc, A.shape[0]))
+    R.sort_indices()
+    return cf, P, R, nfall
+
+
 def flow_levels(A, b, ratio=1.5):
     """Flow order of the facet blocks (Lemma 3.1, Section 3.3).
 
@@ -390,7 +457,8 @@ class Hierarchy:
 
 
 def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
-          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1, order_ratio=1.5, coarsening="pmis"):
+          stall=0.9, max_dense=8192, theta_r=None, distance=1, block=1, order_ratio=1.5, coarsening="pmis",
+          block_air=False):
     """Build the lAIR hierarchy on the scaled matrix (treated as scalar).
     ``theta`` is the strength tolerance of the coarsening (and of P);
     ``theta_r`` that of the restriction neighbourhoods (default: theta);
@@ -398,7 +466,9 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
     of "FFC", "F", "ordered", "ordered_fa"; ``block`` the facet block size
     of level 0 (the unit of the flow order); ``order_ratio`` the dominance
     ratio that orients a pair of blocks in the flow order; ``coarsening``
-    "pmis" or "rs" (Ruge-Stueben first pass)."""
+    "pmis" or "rs" (Ruge-Stueben first pass); ``block_air``: level 0 is
+    coarsened by block AIR on its facet blocks of size ``block``
+    (``block_air_level``, distance one), the coarser levels by scalar AIR."""
     if relax not in ("FFC", "F", "ordered", "ordered_fa"):
         raise ValueError("unknown relaxation %r" % (relax,))
     if coarsening not in ("pmis", "rs"):
@@ -418,18 +488,28 @@ def setup(A0, theta=0.25, max_coarse=64, max_levels=25, relax="FFC", omega=1.0,
         H.levels.append(lev)
         if n <= max_coarse or l == max_levels - 1:
             break
-        strong = strength(A, theta)
-        cf = pmis(A, strong, l) if coarsening == "pmis" else rs_first_pass(A, strong)
-        nc = int(cf.sum())
-        if nc == 0 or nc > stall * n:
-            break
-        cidx = np.cumsum(cf) - 1
-        lev.cf = cf
-        lev.strong = strong
-        lev.P = one_point_P(A, strong, cf, cidx)
-        strong_r = strong if theta_r is None or theta_r == theta else strength(A, theta_r)
-        lev.R, nf = lair_R(A, strong_r, cf, cidx, distance)
-        H.n_fallback += nf
+        if l == 0 and block_air:
+            if block < 2 or distance != 1 or coarsening != "pmis":
+                raise ValueError("block AIR needs facet blocks, distance one and PMIS")
+            cf, Pb, Rb, nf = block_air_level(A, block, theta, theta_r, l)
+            nc = int(cf.sum())
+            if nc == 0 or nc > stall * n:
+                break
+            lev.cf, lev.P, lev.R = cf, Pb, Rb
+            H.n_fallback += nf
+        else:
+            strong = strength(A, theta)
+            cf = pmis(A, strong, l) if coarsening == "pmis" else rs_first_pass(A, strong)
+            nc = int(cf.sum())
+            if nc == 0 or nc > stall * n:
+                break
+            cidx = np.cumsum(cf) - 1
+            lev.cf = cf
+            lev.strong = strong
+            lev.P = one_point_P(A, strong, cf, cidx)
+            strong_r = strong if theta_r is None or theta_r == theta else strength(A, theta_r)
+            lev.R, nf = lair_R(A, strong_r, cf, cidx, distance)
+            H.n_fallback += nf
         if l == 0 and relax in ("ordered", "ordered_fa"):
             lev.blev, lev.rounds, lev.breaks = flow_levels(A, block, order_ratio)
             lev.gs_all = OrderedSweep(A, block, lev.blev, np.arange(n))

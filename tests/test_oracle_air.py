@@ -468,3 +468,78 @@ def test_rs_coarsening_hierarchy_solves(slab_sys):
     assert info["converged"] and info["iters"] < 40
     ref = direct_solve(slab_sys)
     assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("which", ["c1", "slab"])
+def test_block_air_level_pins(which, c1_sys, slab_sys):
+    """Block AIR on the facet blocks: the C/F splitting is constant on each
+    block and is PMIS (its loop definition) on the strong block graph, whose
+    weights are the blocks' largest magnitudes; every F block that something
+    depends on has a strong C block; P is the block one-point interpolation times the identity of
+    the block (each row of an F block takes weight 1 at the same row of its
+    strongest C block); and every restriction row annihilates the rows of its
+    block's strong F neighbourhood."""
+    s = c1_sys if which == "c1" else slab_sys
+    A = sp.csr_matrix(s.Shat)
+    A.sort_indices()
+    b = s.b
+    cf, P, R, nf = air.block_air_level(A, b, 0.25, None, 0)
+    nb = A.shape[0] // b
+    cfb = cf.reshape(nb, b)
+    assert np.all(cfb == cfb[:, :1])
+    cfb = cfb[:, 0]
+    W = air.block_graph(A, b)
+    # the block weights are the largest magnitudes of the blocks' entries
+    Ad = A.toarray()
+    for I, J in [(int(i), int(W.indices[k])) for i in range(0, nb, max(1, nb // 25))
+                 for k in range(W.indptr[i], W.indptr[i + 1])]:
+        assert W[I, J] == np.abs(Ad[I * b:(I + 1) * b, J * b:(J + 1) * b]).max()
+    sb = air.strength(W, 0.25)
+    rW = np.repeat(np.arange(nb), np.diff(W.indptr))
+    si, sj = rW[sb], W.indices[sb]
+    S_rows = [[] for _ in range(nb)]
+    for i, j in zip(si, sj):
+        S_rows[i].append(j)
+    assert np.array_equal(cfb, _pmis_loops(nb, S_rows, 0))
+    infl = np.bincount(sj, minlength=nb)
+    for I in np.nonzero((cfb == 0) & (infl > 0))[0]:
+        assert np.any(cfb[sj[si == I]] == 1), I
+    # P: weight 1 at the same row m of one C block, for every row of an F block
+    Pd = P.tocsr()
+    cidx = np.cumsum(cf) - 1
+    for I in range(nb):
+        cols = [Pd.indices[Pd.indptr[I * b + m]:Pd.indptr[I * b + m + 1]] for m in range(b)]
+        if cfb[I] == 1:
+            assert all(list(c) == [cidx[I * b + m]] for m, c in enumerate(cols))
+        elif len(cols[0]):
+            J = int(np.nonzero(cf == 1)[0][cols[0][0]]) // b
+            assert all(list(c) == [cidx[J * b + m]] for m, c in enumerate(cols))
+            assert np.allclose(Pd.data[Pd.indptr[I * b]:Pd.indptr[I * b + b]], 1.0)
+    # lAIR: (R A)[row, rows of the strong F blocks] = 0
+    RA = (R @ A).tocsr()
+    Cb = np.nonzero(cfb == 1)[0]
+    for I in Cb[:200]:
+        lo, hi = W.indptr[I], W.indptr[I + 1]
+        N = W.indices[lo:hi][sb[lo:hi] & (cfb[W.indices[lo:hi]] == 0)]
+        if len(N) == 0:
+            continue
+        rN = (N[:, None] * b + np.arange(b)).ravel()
+        for m in range(b):
+            r = cidx[I * b + m]
+            row = RA[r].toarray().ravel()
+            assert np.abs(row[rN]).max() <= 1e-12 * np.abs(A[I * b + m].toarray()).max()
+            assert R[r, I * b + m] == 1.0
+
+
+def test_block_air_hierarchy_solves(slab_sys):
+    H = air.setup(slab_sys.Shat, max_coarse=50, block_air=True, block=slab_sys.b)
+    assert H.nlev >= 3
+    x, info = krylov.fgmres(slab_sys.Shat, slab_sys.Hhat, lambda r: air.vcycle(H, r), tol=1e-10)
+    assert info["converged"] and info["iters"] < 40
+    ref = direct_solve(slab_sys)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+    # the transposed cycle is still the adjoint of the cycle
+    rng = np.random.default_rng(23)
+    u, v = rng.standard_normal(slab_sys.n), rng.standard_normal(slab_sys.n)
+    lhs, rhs = air.vcycle(H, u) @ v, u @ air.vcycle_T(H, v)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
