@@ -93,16 +93,22 @@ def test_ordered_solve_parity(built, name, relax):
 @pytest.mark.parametrize("name", ["kuhn_nu0", "layer", "slab_nu0"])
 def test_ordered_sweep_solves_pure_advection(built, name):
     """Pure advection on an acyclic flow: the ordered sweep inverts level 0
-    exactly, so FGMRES stops after one step (Lemma 3.1)."""
+    exactly, so FGMRES stops after one step (Lemma 3.1).  Where the facet
+    graph of the mesh has cycles (the rotating flow of the slab), the oracle
+    breaks the same number of them and the sweep is no longer exact, but the
+    solve still converges in a few steps."""
     print("case", name, flush=True)
     g, o = built(name)
     H = _hier(g, 2)
-    _, _, breaks = H.flow_levels()
-    if breaks:
-        pytest.skip("the flow graph of this mesh has cycles")
+    _, rounds, breaks = H.flow_levels()
     x, info = H.solve(tol=1e-10)
-    assert info["converged"] and info["iters"] == 1
-    assert info["true_relres"] <= 1e-10
+    assert info["converged"] and info["true_relres"] <= 1e-10
+    if breaks == 0:
+        assert info["iters"] == 1
+    else:
+        _, orounds, obreaks = oair.flow_levels(o.Shat, g.b)
+        assert (orounds, obreaks) == (rounds, breaks)
+        assert info["iters"] <= 10, info["iters"]
 
 
 @pytest.mark.parametrize("relax", [2, 3])
