@@ -234,6 +234,15 @@ typedef struct {
                           first pass, the single-process form of the Falgout
                           coarsening of Section 4 (largest measure first, ties
                           to the smallest index; sequential, on the host) */
+  int block_air;       /* 1: level 0 is coarsened by block AIR on its facet
+                          blocks: strength and PMIS on the block graph with
+                          weights w_IJ = max |a_ij| over block (I, J), every
+                          row of a block shares its block's C/F label, P =
+                          P_blocks (x) I_b with one-point P_blocks, and the
+                          lAIR rows of a C block solve over all rows of its
+                          strong F blocks; coarser levels scalar.  Needs a
+                          scaled system, lair_distance 1 and coarsening 0
+                          (else AH_EINVAL).  0: scalar AIR (default) */
 } ah_air_params;
 
 typedef struct {

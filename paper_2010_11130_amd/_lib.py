@@ -25,7 +25,8 @@ class AirParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("relax", C.c_int), ("omega", C.c_double), ("stall", C.c_double),
                 ("fp32_cycle", C.c_int), ("adjoint", C.c_int), ("lair_distance", C.c_int),
-                ("theta_r", C.c_double), ("order_ratio", C.c_double), ("coarsening", C.c_int)]
+                ("theta_r", C.c_double), ("order_ratio", C.c_double), ("coarsening", C.c_int),
+                ("block_air", C.c_int)]
 
 
 class SetupInfo(C.Structure):

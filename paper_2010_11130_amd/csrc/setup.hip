@@ -997,6 +997,82 @@ __global__ __launch_bounds__(256) void k_max_i32(int64_t n, const int32_t* __res
   }
 }
 
+// Block AIR on a scaled level 0 (facet blocks of b rows; the facet-block
+// copy holds block row I as [b][nob][b] values from optr[I] b^2 on).
+// Block weight of every off-diagonal block slot: w = max |a_ij| over the
+// block.  SG lanes per block row, a lane per slot.
+__global__ __launch_bounds__(256) void k_block_weights(int64_t nbr, int b, const int64_t* __restrict__ optr,
+                                                       const double* __restrict__ oval, double* __restrict__ w) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = gid / SG;
+  const int g = (int)(gid % SG);
+  if (I >= nbr) return;
+  const int64_t s0 = optr[I];
+  const int nob = (int)(optr[I + 1] - s0);
+  const double* row = oval + s0 * b * b;
+  for (int s = g; s < nob; s += SG) {
+    double m = 0.0;
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c) m = fmax(m, fabs(row[((int64_t)r * nob + s) * b + c]));
+    w[s0 + s] = m;
+  }
+}
+
+// Every row of a block takes its block's PMIS state.
+__global__ void k_block_expand(int64_t n, int b, const int8_t* __restrict__ sb, int8_t* __restrict__ state) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) state[i] = sb[i / b];
+}
+
+// Scalar strong mask of the level-0 CSR from the block marks: entry (i, j)
+// is strong when blocks i/b != j/b are joined by a strong block slot (the
+// slots of a block row are sorted by column).  PG lanes per row.
+__global__ __launch_bounds__(256) void k_block_mask(int64_t n, int b, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const int64_t* __restrict__ optr,
+                                                    const int32_t* __restrict__ ocol,
+                                                    const uint8_t* __restrict__ sb, uint8_t* __restrict__ strong) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gid / PG;
+  const int g = (int)(gid % PG);
+  if (i >= n) return;
+  const int64_t I = i / b, lo0 = optr[I], hi0 = optr[I + 1] - 1;
+  for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG) {
+    const int32_t J = ci[k] / b;
+    uint8_t f = 0;
+    if (J != I) {
+      int64_t lo = lo0, hi = hi0;
+      while (lo <= hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ocol[mid] == J) { f = sb[mid]; break; }
+        if (ocol[mid] < J) lo = mid + 1; else hi = mid - 1;
+      }
+    }
+    strong[k] = f;
+  }
+}
+
+// Block one-point interpolation: an F block takes the strongest strong C
+// block (largest w, ties to the smallest block index, within relative
+// 1e-12 of the maximum), and row m of it interpolates from row m of that
+// block: pcol[I b + m] = cidx[J b + m]; -1 without a strong C block.
+__global__ void k_block_pcol(int64_t nbr, int b, const int64_t* __restrict__ optr, const int32_t* __restrict__ ocol,
+                             const double* __restrict__ w, const uint8_t* __restrict__ sb,
+                             const int8_t* __restrict__ cf, const int64_t* __restrict__ cidx,
+                             int32_t* __restrict__ pcol) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nbr || cf[I * b]) return;
+  double mx = -1.0;
+  for (int64_t q = optr[I]; q < optr[I + 1]; ++q)
+    if (sb[q] && cf[(int64_t)ocol[q] * b]) mx = fmax(mx, w[q]);
+  int64_t J = -1;
+  if (mx >= 0.0) {
+    const double thr = mx * (1.0 - 1e-12);
+    for (int64_t q = optr[I]; q < optr[I + 1] && J < 0; ++q)
+      if (sb[q] && cf[(int64_t)ocol[q] * b] && w[q] >= thr) J = ocol[q];
+  }
+  for (int m = 0; m < b; ++m) pcol[I * b + m] = J >= 0 ? (int32_t)cidx[J * b + m] : -1;
+}
+
 template <int M, bool D2>
 static void lair_launch(int64_t nc, const AhLevel& L, const uint8_t* strong, const int32_t* clist,
                         unsigned long long* nfall, hipStream_t st) {
@@ -1046,6 +1122,44 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
   }
   set_error("R A P: row candidate count beyond the LDS hash capacity");
   return AH_EUNSUPPORTED;
+}
+
+// PMIS C/F splitting of the graph (n, rp, ci) over its strong entries:
+// state[i] = 1 (C) or 2 (F).  key and nbmax hold n entries of scratch;
+// flags[0..1] are the undecided flags of alternating rounds, flags[3] the
+// single-workgroup round-overflow flag.
+static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, const uint8_t* strong,
+                            const int32_t* infl, int level, uint64_t* key, unsigned long long* nbmax, int8_t* state,
+                            unsigned long long* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, level, key, state);
+  AH_HIP(hipGetLastError());
+  AH_HIP(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
+  if (n <= PMIS_WG_MAX) {
+    // small graph: every round in one workgroup, no host checks
+    static std::once_flag once;
+    std::call_once(once, [] {
+      (void)hipFuncSetAttribute((const void*)k_pmis_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(PMIS_WG_MAX * 17 + 64));
+    });
+    const unsigned lds = (unsigned)(((n * 17 + 7) / 8) * 8);
+    hipLaunchKernelGGL(k_pmis_wg, dim3(1), dim3(1024), lds, st, (int)n, rp, ci, strong, key, state, flags + 3);
+    AH_HIP(hipGetLastError());
+    return AH_OK;
+  }
+  for (int round = 0;; ++round) {
+    if (round > 10000) { set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
+    unsigned long long* left_d = flags + (round & 1);
+    hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, rp, ci, strong, key, state, nbmax);
+    hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d);
+    hipLaunchKernelGGL(k_pmis_fmark, grows(n), dim3(256), 0, st, n, rp, ci, strong, state, left_d);
+    AH_HIP(hipGetLastError());
+    // rounds run in pairs between host checks: a round after the last
+    // undecided point is gone changes nothing and leaves its flag at 0
+    if ((round & 1) == 0) continue;
+    unsigned long long left = 0;
+    AH_TRY(read_bytes(left_d, &left, sizeof(left), st));
+    if (left == 0) return AH_OK;
+  }
 }
 
 }  // namespace ah
@@ -1123,6 +1237,7 @@ extern "C" void ah_air_defaults(ah_air_params* p) {
   p->theta_r = 0.0;
   p->order_ratio = 1.5;
   p->coarsening = 0;
+  p->block_air = 0;
 }
 
 extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, void* stream, ah_hier** out,
@@ -1136,8 +1251,12 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   if (prm.max_levels < 1 || prm.max_levels > 32 || !(prm.theta >= 0.0) || prm.max_coarse < 1 ||
       (prm.lair_distance != 1 && prm.lair_distance != 2) || !(prm.theta_r <= 1.0) || prm.relax < 0 ||
       prm.relax > 3 || !(prm.order_ratio >= 1.0 && prm.order_ratio < 1e300) || prm.coarsening < 0 ||
-      prm.coarsening > 1) {
+      prm.coarsening > 1 || prm.block_air < 0 || prm.block_air > 1) {
     set_error("air_setup: invalid parameters");
+    return AH_EINVAL;
+  }
+  if (prm.block_air && (!s->d_odv || s->b < 2 || prm.lair_distance != 1 || prm.coarsening != 0)) {
+    set_error("air_setup: block AIR needs a scaled system with facet blocks, lAIR distance one and PMIS");
     return AH_EINVAL;
   }
   hipStream_t st = as_stream(stream);
@@ -1206,10 +1325,48 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       CK(ar.get(&L.b32, n)); CK(ar.get(&L.x32, n)); CK(ar.get(&L.y32, n)); CK(ar.get(&L.e32, n));
     }
     if (n <= prm.max_coarse || l == prm.max_levels - 1) break;
-    // strength
+    // block AIR on level 0: strength and PMIS on the facet-block graph, the
+    // scalar strong mask (restriction threshold) and the states expanded
+    // to the rows of each block; P follows after the scalar pass below
+    const bool blk = prm.block_air && l == 0;
+    const int64_t nbr = blk ? n / L.ob : 0;
+    double* bw = nullptr;
+    uint8_t* sb = nullptr;
     uint8_t* strong = nullptr;
-    int32_t* infl = nullptr;
+    int8_t* state = nullptr;
     CK(tmp.get(&strong, L.nnz));
+    CK(tmp.get(&state, n));
+    if (blk) {
+      const int64_t nslot = (int64_t)s->mesh->odb_col.size();
+      int32_t* infl = nullptr;
+      uint64_t* key = nullptr;
+      unsigned long long* nbmax = nullptr;
+      int8_t* sbstate = nullptr;
+      CK(tmp.get(&bw, nslot));
+      CK(tmp.get(&sb, nslot));
+      CK(tmp.get(&infl, nbr));
+      CK(tmp.get(&key, nbr));
+      CK(tmp.get(&nbmax, nbr));
+      CK(tmp.get(&sbstate, nbr));
+      hipLaunchKernelGGL(k_block_weights, g1(nbr * SG), dim3(256), 0, st, nbr, (int)L.ob, L.optr, L.oval, bw);
+      CKH(hipMemsetAsync(infl, 0, nbr * sizeof(int32_t), st));
+      hipLaunchKernelGGL(k_strength, g1(nbr * SG), dim3(256), 0, st, nbr, L.optr, L.ocol, bw, prm.theta, sb, infl);
+      CKH(hipGetLastError());
+      CK(pmis_split(nbr, L.optr, L.ocol, sb, infl, l, key, nbmax, sbstate, d_ull, st));
+      hipLaunchKernelGGL(k_block_expand, g1(n), dim3(256), 0, st, n, (int)L.ob, sbstate, state);
+      uint8_t* sbr = sb;
+      if (prm.theta_r > 0.0 && prm.theta_r != prm.theta) {
+        CK(tmp.get(&sbr, nslot));
+        CKH(hipMemsetAsync(infl, 0, nbr * sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_strength, g1(nbr * SG), dim3(256), 0, st, nbr, L.optr, L.ocol, bw, prm.theta_r, sbr,
+                           infl);
+      }
+      hipLaunchKernelGGL(k_block_mask, g1(n * PG), dim3(256), 0, st, n, (int)L.ob, L.rowptr, L.col, L.optr, L.ocol,
+                         sbr, strong);
+      CKH(hipGetLastError());
+    } else {
+    // strength
+    int32_t* infl = nullptr;
     CK(tmp.get(&infl, n));
     CKH(hipMemsetAsync(infl, 0, n * sizeof(int32_t), st));
     hipLaunchKernelGGL(k_strength, g1(n * SG), dim3(256), 0, st, n, L.rowptr, L.col, L.val, prm.theta, strong, infl);
@@ -1217,10 +1374,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     // PMIS
     uint64_t* key = nullptr;
     unsigned long long* nbmax = nullptr;
-    int8_t* state = nullptr;
     CK(tmp.get(&key, n));
     CK(tmp.get(&nbmax, n));
-    CK(tmp.get(&state, n));
     if (prm.coarsening == 1) {
       // Ruge-Stueben first pass on the host from the strong pattern
       std::vector<int64_t> hrp(n + 1);
@@ -1235,34 +1390,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       CKH(hipMemcpyAsync(state, hstate.data(), n, hipMemcpyHostToDevice, st));
       CKH(hipStreamSynchronize(st));
     } else {
-    hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, l, key, state);
-    CKH(hipGetLastError());
-    CKH(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
-    if (n <= PMIS_WG_MAX) {
-      // small level: every round in one workgroup, no host checks
-      static std::once_flag once;
-      std::call_once(once, [] {
-        (void)hipFuncSetAttribute((const void*)k_pmis_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(PMIS_WG_MAX * 17 + 64));
-      });
-      const unsigned lds = (unsigned)(((n * 17 + 7) / 8) * 8);
-      hipLaunchKernelGGL(k_pmis_wg, dim3(1), dim3(1024), lds, st, (int)n, L.rowptr, L.col, strong, key, state,
-                         d_ull + 3);
-      CKH(hipGetLastError());
-    }
-    for (int round = 0; n > PMIS_WG_MAX; ++round) {
-      if (round > 10000) { set_error("air_setup: PMIS did not terminate"); tmp.release(); delete h; return AH_EINVAL; }
-      unsigned long long* left_d = d_ull + (round & 1);
-      hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, L.rowptr, L.col, strong, key, state, nbmax);
-      hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d);
-      hipLaunchKernelGGL(k_pmis_fmark, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, strong, state, left_d);
-      CKH(hipGetLastError());
-      // rounds run in pairs between host checks: a round after the last
-      // undecided point is gone changes nothing and leaves its flag at 0
-      if ((round & 1) == 0) continue;
-      unsigned long long left = 0;
-      CK(read_bytes(left_d, &left, sizeof(left), st));
-      if (left == 0) break;
+      CK(pmis_split(n, L.rowptr, L.col, strong, infl, l, key, nbmax, state, d_ull, st));
     }
     }
     // coarse numbering
@@ -1295,7 +1423,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     // strength of the restriction neighbourhoods (theta_r; the same mask
     // when it equals theta)
     uint8_t* strong_r = strong;
-    if (prm.theta_r > 0.0 && prm.theta_r != prm.theta) {
+    if (!blk && prm.theta_r > 0.0 && prm.theta_r != prm.theta) {
       int32_t* infl_r = nullptr;
       CK(tmp.get(&strong_r, L.nnz));
       CK(tmp.get(&infl_r, n));
@@ -1307,6 +1435,11 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, strong_r, L.cf,
                        cidx, L.pcol, rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
+    if (blk) {
+      hipLaunchKernelGGL(k_block_pcol, g1(nbr), dim3(256), 0, st, nbr, (int)L.ob, L.optr, L.ocol, bw, sb, L.cf, cidx,
+                         L.pcol);
+      CKH(hipGetLastError());
+    }
     if (d2) {
       // distance-two neighbourhoods: R row lengths, |N_i| and the R A P bound
       int32_t *mcnt = nullptr, *c2 = nullptr;

@@ -1,0 +1,85 @@
+"""Block AIR on level 0 (``block_air=1``: the facet blocks are the unknowns of
+the coarsening, coarser levels scalar) on the HIP path against the oracle's:
+C/F splitting and one-point interpolation bit for bit on every level, lAIR
+restriction and coarse matrices to 1e-10, solutions at tol 1e-12 to 1e-10,
+iteration counts at the workload tolerance within +-1; with a separate
+restriction threshold too; and the parameter checks of the entry point."""
+import numpy as np
+import pytest
+
+from oracle import air as oair
+from oracle.drivers import setup_problem, air_fgmres_solve
+from gpu_cases import case, gpu_system, to_scipy, rel_sparse_diff
+
+pytestmark = pytest.mark.gpu
+
+SMALL_COARSE = 40
+
+
+def _compare(H, OH):
+    assert H.info["levels"] == OH.nlev
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    assert H.info["n_fallback"] == OH.n_fallback
+    for l in range(OH.nlev - 1):
+        lv = H.level(l)
+        ol = OH.levels[l]
+        assert np.array_equal(lv["cf"].cpu().numpy(), ol.cf), l
+        Pd = ol.P.tocsr()
+        assert np.all(np.diff(Pd.indptr) <= 1)
+        opc = np.full(ol.A.shape[0], -1)
+        opc[np.repeat(np.arange(Pd.shape[0]), np.diff(Pd.indptr))] = Pd.indices
+        assert np.array_equal(lv["pcol"].cpu().numpy(), opc), l
+        R = to_scipy(lv["Rptr"], lv["Rcol"], lv["Rval"], ol.R.shape[0], ol.R.shape[1])
+        assert rel_sparse_diff(R, ol.R) < 1e-10, l
+        nxt = H.level(l + 1)
+        Ac = to_scipy(nxt["rowptr"], nxt["col"], nxt["val"], nxt["n"])
+        assert rel_sparse_diff(Ac, OH.levels[l + 1].A) < 1e-10, l
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "kuhn_nu2", "c5", "layer"])
+def test_block_air_hierarchy_and_solve_parity(name):
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b)
+    # every row of a level-0 block shares its block's label
+    cf0 = H.level(0)["cf"].cpu().numpy().reshape(-1, o.b)
+    assert np.all(cf0 == cf0[:, :1])
+    _compare(H, OH)
+    x, info = H.solve(tol=1e-12)
+    xo, _ = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    tol = 1e-10 if name.startswith("c1") else 1e-8
+    _, i8 = H.solve(tol=tol)
+    _, io8 = air_fgmres_solve(o, tol=tol, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
+
+
+def test_block_air_restriction_threshold():
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("kuhn_nu4")
+    print("case kuhn_nu4 theta 0.2 theta_r 0.3", flush=True)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, theta=0.2, theta_r=0.3)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b, theta=0.2, theta_r=0.3)
+    _compare(H, OH)
+
+
+def test_block_air_rejects_unsupported_settings():
+    from paper_2010_11130_amd import Hierarchy
+    from paper_2010_11130_amd._lib import AirHdgError
+    v, c, prob, p = case("c1")
+    g = gpu_system(v, c, prob, p)
+    for kw in ({"lair_distance": 2}, {"coarsening": 1}, {"block_air": 2}):
+        kw = dict(kw)
+        kw.setdefault("block_air", 1)
+        with pytest.raises(AirHdgError):
+            Hierarchy(g, **kw)
+    gu = gpu_system(v, c, prob, p, block_scale=False)
+    with pytest.raises(AirHdgError):
+        Hierarchy(gu, block_air=1)
