@@ -61,8 +61,11 @@ const char* ah_last_error(void);
 /* ------------------------------------------------------------ memory ---
  * Device memory of library objects (ah_system, ah_hier, the solver
  * workspace a hierarchy allocates on its first solve, temporaries) comes
- * from a library-owned stream-ordered pool unless the caller registers its
- * own allocator (e.g. torch's caching allocator, so both share one pool):
+ * from the library's caching allocator (hipMalloc; freed blocks stay cached
+ * per device and stream and are reused by later requests of up to their
+ * size on that stream; on out-of-memory the device's cache is released and
+ * the allocation retried) unless the caller registers its own allocator
+ * (e.g. torch's caching allocator, so both share one pool):
  *   alloc(ctx, bytes, stream): device memory of at least bytes (256-byte
  *     aligned) usable in stream order on stream (a hipStream_t), or NULL
  *     (the library call then fails with AH_ENOMEM);
@@ -76,6 +79,12 @@ const char* ah_last_error(void);
 typedef void* (*ah_alloc_fn)(void* ctx, int64_t bytes, void* stream);
 typedef void (*ah_free_fn)(void* ctx, void* ptr, int64_t bytes, void* stream);
 ah_status ah_set_allocator(ah_alloc_fn alloc, ah_free_fn free, void* ctx);
+
+/* Gives the blocks that the library's caching allocator holds for the
+ * current device, freed by objects and not reused yet, back to the device
+ * (hipFree).  Waits for the device first.  Objects that are alive keep
+ * their memory.  AH_EHIP on a runtime error. */
+ah_status ah_pool_trim(void);
 
 /* ---------------------------------------------------------------- mesh ---
  * Space-time simplex mesh (Section 2.2: slab-by-slab slabs or one

@@ -58,6 +58,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
 SIGNATURES = {
     "ah_last_error": (C.c_char_p, []),
     "ah_set_allocator": (i32, [ALLOC_FN, FREE_FN, vp]),
+    "ah_pool_trim": (i32, []),
     "ah_mesh_create": (i32, [i32, i64, vp, i64, vp, C.POINTER(vp)]),
     "ah_mesh_destroy": (None, [vp]),
     "ah_mesh_sizes": (i32, [vp, P_i64, P_i64]),

@@ -88,6 +88,12 @@ def use_torch_allocator(on=True):
     _torch_alloc = cbs        # the callbacks must outlive every allocation made through them
 
 
+def pool_trim():
+    """Give the unused memory of the library's own pool back to the device
+    (``ah_pool_trim``; waits for the device)."""
+    check(lib().ah_pool_trim(), "ah_pool_trim")
+
+
 def sizes(dim_st, p):
     """(nq, nqf, nu, b) for space-time dimension ``dim_st`` and degree ``p``."""
     a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()

@@ -40,10 +40,10 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Stream-ordered device memory owned by a library object: requests are
 // carved (256-byte aligned) out of chunks of at least CHUNK bytes, so an
 // object makes a handful of allocation calls instead of one per buffer.
-// Stream-ordered bump allocator: chunks come from hipMallocAsync on the
-// arena's current stream and go back with hipFreeAsync on the stream each
-// chunk came from.  A chunk is only carved on the stream it was allocated
-// on; switching stream starts a new chunk.
+// Stream-ordered bump allocator: chunks come from the library's caching
+// allocator (or the caller's) for the arena's current stream and go back to
+// it with the stream each chunk came from.  A chunk is only carved on the
+// stream it was allocated on; switching stream starts a new chunk.
 struct Arena {
   static constexpr size_t CHUNK = size_t(32) << 20;
   // a chunk with the stream it was allocated on and, for memory from a
@@ -54,6 +54,7 @@ struct Arena {
     size_t bytes;
     ah_free_fn free_fn;
     void* ctx;
+    int dev;                         // device of a library-cache chunk
   };
   std::vector<Chunk> ptrs;
   char* cur = nullptr;

@@ -27,29 +27,68 @@ void set_error(const char* fmt, ...) {
   g_last_error = buf;
 }
 
-// The library's stream-ordered pool on the current device.  Freed memory
-// stays in the pool (release threshold at its maximum) instead of going back
-// to the driver at every synchronization, so the per-slab objects of a time
-// march reuse it without new mappings.
-static hipMemPool_t device_pool() {
-  static std::mutex mu;
-  static hipMemPool_t pools[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  std::lock_guard<std::mutex> lock(mu);
-  if (!pools[dev]) {
-    hipMemPoolProps props{};
-    props.allocType = hipMemAllocationTypePinned;
-    props.handleTypes = hipMemHandleTypeNone;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = dev;
-    hipMemPool_t pool = nullptr;
-    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    pools[dev] = pool;
+// The library's caching device allocator (used unless the caller registers
+// its own).  A freed block stays cached with its device and the stream it
+// was freed on; a later request on the same device and stream takes the
+// smallest cached block that holds it, if that block is at most twice the
+// request, so the per-slab objects of a march and the solver workspaces of
+// successive hierarchies reuse memory without new mappings.  Otherwise the
+// memory comes from hipMalloc; when that runs out, the device is
+// synchronized, every cached block of the device is released and the call
+// is retried once.  Sizes are rounded up to 2 MiB.  Reuse on the freeing
+// stream is safe in stream order: work enqueued after the free runs after
+// the work that used the block before.
+namespace {
+constexpr size_t CACHE_ROUND = size_t(2) << 20;
+std::mutex g_cache_mu;
+std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void*>> g_cache;
+
+// Frees every cached block of device dev (the caller has synchronized it).
+void cache_release_device(int dev) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+      if (it->first.first == dev) {
+        for (auto& b : it->second) drop.push_back(b.second);
+        it = g_cache.erase(it);
+      } else {
+        ++it;
+      }
+    }
   }
-  return pools[dev];
+  for (void* q : drop) (void)hipFree(q);
+}
+}  // namespace
+
+static hipError_t cache_alloc(void** p, size_t* bytes, hipStream_t st, int dev) {
+  *bytes = (*bytes + CACHE_ROUND - 1) / CACHE_ROUND * CACHE_ROUND;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto c = g_cache.find({dev, st});
+    if (c != g_cache.end()) {
+      auto it = c->second.lower_bound(*bytes);
+      if (it != c->second.end() && it->first <= 2 * *bytes) {
+        *p = it->second;
+        *bytes = it->first;
+        c->second.erase(it);
+        return hipSuccess;
+      }
+    }
+  }
+  hipError_t e = hipMalloc(p, *bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    cache_release_device(dev);
+    e = hipMalloc(p, *bytes);
+  }
+  return e;
+}
+
+static void cache_free(void* p, size_t bytes, hipStream_t st, int dev) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  g_cache[{dev, st}].emplace(bytes, p);
 }
 
 // The caller's device allocator (ah_set_allocator), if one is registered.
@@ -68,6 +107,7 @@ ah_status Arena::alloc(void** p, size_t bytes) {
     ah_alloc_fn afn;
     ah_free_fn ffn;
     void* ctx;
+    int dev = -1;
     {
       std::lock_guard<std::mutex> lock(g_alloc_mu);
       afn = g_alloc;
@@ -82,14 +122,15 @@ ah_status Arena::alloc(void** p, size_t bytes) {
       }
     } else {
       ffn = nullptr;
-      hipMemPool_t pool = device_pool();
-      hipError_t e = pool ? hipMallocFromPoolAsync(&q, want, pool, stream) : hipMallocAsync(&q, want, stream);
+      if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+      hipError_t e = cache_alloc(&q, &want, stream, dev);
       if (e != hipSuccess) {
+        (void)hipGetLastError();
         set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
         return AH_ENOMEM;
       }
     }
-    ptrs.push_back({q, stream, want, ffn, ctx});
+    ptrs.push_back({q, stream, want, ffn, ctx, dev});
     if (want > CHUNK) {          // dedicated chunk for a large buffer
       *p = q;
       return AH_OK;
@@ -109,7 +150,7 @@ void Arena::release() {
     if (c.free_fn)
       c.free_fn(c.ctx, c.p, (int64_t)c.bytes, (void*)c.stream);
     else
-      (void)hipFreeAsync(c.p, c.stream);
+      cache_free(c.p, c.bytes, c.stream, c.dev);
   }
   ptrs.clear();
   cur = nullptr;
@@ -716,6 +757,18 @@ extern "C" ah_status ah_quad_rule(int dim, int n, double* xi, double* w) {
 }
 
 extern "C" const char* ah_last_error(void) { return ah::g_last_error_cstr(); }
+
+extern "C" ah_status ah_pool_trim(void) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    ah::set_error("ah_pool_trim: %s", hipGetErrorString(e));
+    return AH_EHIP;
+  }
+  cache_release_device(dev);
+  return AH_OK;
+}
 
 extern "C" ah_status ah_set_allocator(ah_alloc_fn alloc, ah_free_fn free_fn, void* ctx) {
   if ((alloc == nullptr) != (free_fn == nullptr)) {

@@ -45,3 +45,33 @@ def test_torch_allocator_roundtrip():
     g2 = gpu_system(v, c, prob, p)
     x2, _ = Hierarchy(g2, max_coarse=40).solve(tol=1e-10)
     assert np.array_equal(x2.cpu().numpy(), x0)
+
+
+def test_library_cache_reuses_and_trims():
+    """The library's caching allocator: repeated hierarchies of one system
+    (setup + solve, destroyed each time) take no new device memory after the
+    first, give the same solution bit for bit, and ah_pool_trim gives the
+    cached blocks back to the device."""
+    from paper_2010_11130_amd import Hierarchy, pool_trim
+    v, c, prob, p = case("kuhn_nu4")
+    g = gpu_system(v, c, prob, p)
+    torch.cuda.synchronize()
+    pool_trim()
+    free0 = torch.cuda.mem_get_info()[0]
+    xs, frees = [], []
+    for _ in range(4):
+        H = Hierarchy(g, max_coarse=40, block_air=1)
+        x, info = H.solve(tol=1e-10)
+        assert info["converged"]
+        xs.append(x.cpu().numpy())
+        del H, x
+        gc.collect()
+        torch.cuda.synchronize()
+        frees.append(torch.cuda.mem_get_info()[0])
+    for x in xs[1:]:
+        assert np.array_equal(x, xs[0])
+    # the first pass maps the cache's blocks, the later ones reuse them
+    assert frees[1] == frees[2] == frees[3], frees
+    assert frees[1] < free0
+    pool_trim()
+    assert torch.cuda.mem_get_info()[0] > frees[3]

@@ -83,3 +83,55 @@ def test_block_air_rejects_unsupported_settings():
     gu = gpu_system(v, c, prob, p, block_scale=False)
     with pytest.raises(AirHdgError):
         Hierarchy(gu, block_air=1)
+
+
+@pytest.mark.parametrize("name", ["c1", "kuhn_nu4", "c5"])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_block_air_vcycle_parity(name, transpose, fp32):
+    """One V-cycle of the block-AIR hierarchy and its transpose, FP64 to
+    1e-10; the FP32 cycle within a small factor of the oracle's FP32
+    emulation of the same cycle."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, transpose, fp32, flush=True)
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, adjoint=1, fp32_cycle=1 if fp32 else 0)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b)
+    r = np.random.default_rng(5).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda"), precision=1 if fp32 else 0, transpose=transpose).cpu().numpy()
+    zo = oair.vcycle_T(OH, r) if transpose else oair.vcycle(OH, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    if not fp32:
+        assert err <= 1e-10
+        return
+    z32 = oair.vcycle_T(OH, r, dtype=np.float32) if transpose else oair.vcycle(OH, r, dtype=np.float32)
+    err32 = np.linalg.norm(z32.astype(np.float64) - zo) / np.linalg.norm(zo)
+    print("fp32 cycle error: hip %.3e  emulated %.3e" % (err, err32), flush=True)
+    assert err32 < 1e-5
+    assert err <= 4.0 * err32 + 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_block_air_adjoint_solve(precision):
+    """The adjoint solve S^T lam = g with the transposed block-AIR hierarchy
+    against the oracle's dense adjoint, FP64 and FP32 cycles."""
+    import torch
+    from oracle import adjoint as oadj
+    from oracle.drivers import direct_solve
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("c5")
+    print("case c5 adjoint precision", precision, flush=True)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, adjoint=1, fp32_cycle=precision)
+    target = direct_solve(o) + 0.1 * np.random.default_rng(9).standard_normal(o.n)
+    lam, info = H.solve(tol=1e-13, precision=precision)
+    assert info["converged"]
+    gvec = lam - torch.as_tensor(target, device="cuda")
+    adj, ainfo = H.solve_adjoint(gvec, tol=1e-13, precision=precision)
+    assert ainfo["converged"]
+    adj_o = oadj.adjoint_direct(o, direct_solve(o) - target)
+    assert np.linalg.norm(adj.cpu().numpy() - adj_o) <= 1e-9 * np.linalg.norm(adj_o)
