@@ -4,9 +4,11 @@ Headline workload (all at once, 2+1-D): the space-time cube [0,1]^3 split
 into 96^3 cubes -> 5,308,416 tets (x1-reflected Kuhn split), p = 1 (b = 3,
 31,795,200 free facet DOFs), a = (1, 0.5), nu = 1e-4, smooth solution plus a
 tanh front of width 1e-2 (data from the manufactured solution).  The system
-is assembled once; one step is lAIR setup + FGMRES(100) to relative
-residual 1e-8 (F, F, C Jacobi post-sweeps), the metric's "setup+solve", on
-the assembled system resident in HBM.
+is assembled once; one step is AIR setup (block AIR on level 0, the facet
+blocks as the points of the coarsening; scalar lAIR below) + FGMRES(100) to
+relative residual 1e-8 (F, F, C Jacobi post-sweeps), the metric's
+"setup+solve", on the assembled system resident in HBM.  The same step with
+scalar AIR on every level is recorded beside it.
 
 value = free DOFs / step time with the FP64 cycle; the FP32-cycle figure
 sits beside it.  The roofline entry is the tagged kernel with the largest
@@ -41,6 +43,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--c3-n", type=int, default=96, help="cubes per side of the headline space-time mesh")
     ap.add_argument("--c3-nu", type=float, default=1e-4)
+    ap.add_argument("--scalar-air", action="store_true",
+                    help="headline with scalar AIR on level 0 instead of block AIR (the scalar figures are "
+                         "recorded beside the block ones either way)")
+    ap.add_argument("--no-alt-air", action="store_true",
+                    help="skip the record of the other level-0 coarsening (scalar AIR, or block AIR with --scalar-air)")
     ap.add_argument("--no-c3-variants", action="store_true",
                     help="skip BiCGSTAB, ordered relaxations and nu = 0, 1e-2 on the headline mesh")
     ap.add_argument("--no-march", action="store_true", help="skip the slab-by-slab march record")
@@ -406,25 +413,35 @@ def setup_warm_solve(s, tol, precision=0, method=0, **air):
     return rec, x
 
 
-def c3_variants(c3, tol, x64):
-    """Setup + warm solve of other settings on the same 96^3 workload:
+def c3_variants(c3, tol, x64, air):
+    """Setup + warm solve of other settings on the same 96^3 workload, with
+    the headline's level-0 coarsening ``air``: strength threshold 0.5,
     BiCGSTAB (the paper's Krylov method), the ordered Gauss-Seidel
     relaxations of Lemma 3.1 (relax 2: all points in flow order; relax 3: F
-    points then all points, the Section 4 schedule), FP64 and FP32 cycles;
-    and the same mesh at nu = 0 and nu = 1e-2."""
+    points then all points, the Section 4 schedule), FP64 and FP32 cycles,
+    and relax 2 with the other coarsening; the same mesh at nu = 0 and
+    nu = 1e-2, both coarsenings."""
     import torch
     from paper_2010_11130_amd import System
     from workloads.problems import SmoothPlusFront
     s = c3["system"]
+    other = {} if air else {"block_air": 1}
+    oname = "scalar" if air else "block"
     out = {}
-    for key, prec, kw in (("bicgstab", 0, {"method": 1}), ("ordered_relax2", 0, {"relax": 2}),
-                          ("ordered_relax2_fp32_cycle", 1, {"relax": 2}), ("ordered_relax3", 0, {"relax": 3})):
+    for key, prec, kw in (("theta_0.5", 0, {"theta": 0.5}), ("bicgstab", 0, {"method": 1}),
+                          ("ordered_relax2", 0, {"relax": 2}), ("ordered_relax2_fp32_cycle", 1, {"relax": 2}),
+                          ("ordered_relax3", 0, {"relax": 3}),
+                          (oname + "_ordered_relax2", 0, dict(other, relax=2))):
+        kw = dict(air, **kw) if not key.startswith(oname) else kw
         r, x = setup_warm_solve(s, tol, prec, **kw)
-        r["rel_diff_vs_fp64_jacobi"] = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
+        r["rel_diff_vs_headline_fp64"] = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
         out[key] = r
         del x
-    for nu, variants in ((0.0, (("jacobi", {}), ("ordered_relax2", {"relax": 2}))),
-                         (1e-2, (("jacobi_theta_0.1", {"theta": 0.1}),))):
+    # nu = 1e-2: scalar AIR at theta 0.25 does not converge in 1000 iterations
+    v12 = ((("jacobi", air), ("scalar_jacobi_theta_0.1", {"theta": 0.1})) if air else
+           (("jacobi_theta_0.1", {"theta": 0.1}), ("block_jacobi", other)))
+    for nu, variants in ((0.0, (("jacobi", air), (oname + "_jacobi", other), ("ordered_relax2", dict(air, relax=2)))),
+                         (1e-2, v12)):
         prob = SmoothPlusFront(nu)
         f = prob.f(c3["xe"]).contiguous()
         torch.cuda.synchronize()
@@ -905,12 +922,13 @@ def roofline(prof, workload, p, D, ne):
             "launches": k["launches"]}
 
 
-def cpu_baseline(n=24, nu=1e-4, tol=1e-8):
+def cpu_baseline(n=24, nu=1e-4, tol=1e-8, block_air=True):
     """The oracle (plain FP64 numpy/scipy) on a bounded sample of the
     headline workload's mesh family: the n^3 Kuhn mesh of the same problem,
-    p = 1, with the BLAS thread pools held at one thread (the oracle's sparse
-    products and loops run on one core anyway).  value = free DOFs /
-    (lAIR setup + FGMRES) as in the headline; assembly timed apart."""
+    p = 1, the headline's level-0 coarsening, with the BLAS thread pools held
+    at one thread (the oracle's sparse products and loops run on one core
+    anyway).  value = free DOFs / (AIR setup + FGMRES) as in the headline;
+    assembly timed apart."""
     from workloads import kuhn_cube_mesh
     from workloads.problems import SmoothPlusFront
     from oracle.drivers import setup_problem
@@ -924,7 +942,7 @@ def cpu_baseline(n=24, nu=1e-4, tol=1e-8):
     t0 = time.perf_counter()
     s = setup_problem(v, c, SmoothPlusFront(nu), 1)
     t1 = time.perf_counter()
-    H = air.setup(s.Shat)
+    H = air.setup(s.Shat, block_air=block_air, block=s.b)
     t2 = time.perf_counter()
     x, info = krylov.fgmres(s.Shat, s.Hhat, lambda r: air.vcycle(H, r), tol=tol)
     t3 = time.perf_counter()
@@ -932,8 +950,9 @@ def cpu_baseline(n=24, nu=1e-4, tol=1e-8):
         limiter.unregister()
     return {"value": s.n / (t3 - t1), "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": "%d^3 Kuhn mesh of the headline problem (p=1, nu=%g, %d free DOFs, 1/%d of the headline's): "
-                      "lAIR setup %.1f s + FGMRES to %g %.1f s (%d iterations), one thread; assembly %.1f s apart"
-                      % (n, nu, s.n, round(31795200 / s.n), t2 - t1, tol, t3 - t2, info["iters"], t1 - t0)}
+                      "%s setup %.1f s + FGMRES to %g %.1f s (%d iterations), one thread; assembly %.1f s apart"
+                      % (n, nu, s.n, round(31795200 / s.n), "block AIR" if block_air else "lAIR", t2 - t1, tol,
+                         t3 - t2, info["iters"], t1 - t0)}
 
 
 def march_record(args):
@@ -1062,30 +1081,45 @@ def main():
     c3 = c3_inputs(args.c3_n, args.c3_nu)
     s = c3["system"]
     log("bench: C3 %d^3 assembled, %d free DOFs, %.1f ms" % (args.c3_n, s.n, c3["assemble_ms"]))
-    r64, prof64, x64 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 0, profile=True)
+    air = {} if args.scalar_air else {"block_air": 1}
+    r64, prof64, x64 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 0, profile=True, **air)
     log("bench: FP64 %.1f ms/step, %d iterations" % (r64["ms_per_step"], r64["iters"]))
+    level0 = ("scalar lAIR on every level" if args.scalar_air else
+              "block AIR on level 0 (facet blocks as the points of strength, PMIS and one-point P; lAIR over "
+              "all rows of the strong F blocks), scalar lAIR below")
     out = {
         "metric": METRIC, "value": r64["value"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "all-at-once 2+1D space-time cube: %d^3 Kuhn cubes -> %d tets, p=1 (b=3), "
-                               "a=(1,0.5), nu=%g, smooth solution + tanh front of width 1e-2; one step = lAIR setup "
-                               "(theta 0.25, PMIS, one-point P, distance-1 lAIR) + FGMRES(100) to %g with F,F,C "
+                               "a=(1,0.5), nu=%g, smooth solution + tanh front of width 1e-2; one step = AIR setup "
+                               "(%s; theta 0.25, PMIS, one-point P, distance-1 lAIR) + FGMRES(100) to %g with F,F,C "
                                "Jacobi post-sweeps, on the assembled system in HBM"
-                               % (args.c3_n, c3["tets"], args.c3_nu, args.tol),
-                   "free_dofs": s.n, "tol": args.tol},
+                               % (args.c3_n, c3["tets"], args.c3_nu, level0, args.tol),
+                   "free_dofs": s.n, "tol": args.tol, "block_air": not args.scalar_air},
         "fp64": r64, "assemble_ms": c3["assemble_ms"],
         "end_to_end_dofs_per_s": s.n / (1e-3 * (c3["assemble_ms"] + r64["ms_per_step"])),
         "kernels": prof64,
     }
     if not args.no_fp32:
-        r32, prof32, x32 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 1, profile=True)
+        r32, prof32, x32 = setup_solve_steps(s, args.steps, args.warmup, args.tol, 1, profile=True, **air)
         log("bench: FP32 cycle %.1f ms/step, %d iterations" % (r32["ms_per_step"], r32["iters"]))
         r32["speedup_vs_fp64"] = r64["ms_per_step"] / r32["ms_per_step"]
         r32["rel_diff_vs_fp64"] = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
         r32["kernels"] = prof32
         out["fp32_cycle"] = r32
         del x32
+    # the other level-0 coarsening on the same system, same timing
+    other = {"block_air": 1} if args.scalar_air else {}
+    rec = {}
+    for prec in (() if args.no_alt_air else (0,) if args.no_fp32 else (0, 1)):
+        r, _, x = setup_solve_steps(s, args.steps, args.warmup, args.tol, prec, **other)
+        r["rel_diff_vs_headline_fp64"] = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
+        rec["fp64" if prec == 0 else "fp32_cycle"] = r
+        del x
+    if rec:
+        out["block_air" if args.scalar_air else "scalar_air"] = rec
+        log("bench: %s done" % ("block AIR" if args.scalar_air else "scalar AIR"))
     if prof64:
         rf = roofline(prof64, "c3", 1, 3, c3["tets"])
         cb = copy_bandwidth()
@@ -1093,7 +1127,7 @@ def main():
         rf["frac_of_copy"] = rf["achieved"] / cb
         out["roofline"] = rf
     if not args.no_c3_variants:
-        out["c3_variants"] = c3_variants(c3, args.tol, x64)
+        out["c3_variants"] = c3_variants(c3, args.tol, x64, air)
         log("bench: C3 variants done")
     del x64, s, c3
     torch.cuda.empty_cache()
@@ -1105,7 +1139,7 @@ def main():
         log("bench: C5 done")
     out["c1"] = c1_record()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.c3_nu, args.tol)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.c3_nu, args.tol, not args.scalar_air)
     print(json.dumps(out))
 
 
