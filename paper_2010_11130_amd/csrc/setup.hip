@@ -538,6 +538,138 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
   }
 }
 
+// Block AIR lAIR rows (level 0): one wave per C block, rows i0 .. i0 + b - 1.
+// Every row of a block holds the same off-diagonal blocks in full, so N (the
+// rows of the strong F blocks) and its order come from each row alike; the
+// b right-hand sides -A[i0 + r, N]^T are gathered in that order, T =
+// A[N, N]^T is factored once by LU with partial pivoting, and the
+// right-hand sides are carried through the same eliminations and back
+// substitutions as in k_lair, so each row gets the values k_lair would
+// give it.  *err is set if the rows of a block disagree on |N|.
+constexpr int LB_BMAX = 10;
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_lair_blk(int64_t ncb, int b, const int64_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                 const uint8_t* __restrict__ strong, const int8_t* __restrict__ cf,
+                                                 const int32_t* __restrict__ clist, const int64_t* __restrict__ Rptr,
+                                                 int32_t* __restrict__ Rcol, double* __restrict__ Rval,
+                                                 unsigned long long* __restrict__ nfall, int* __restrict__ err) {
+  __shared__ int32_t N[MAXM];
+  __shared__ double T[MAXM * MAXM];
+  __shared__ double z[LB_BMAX * MAXM];
+  const int64_t kb = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t i0 = clist[kb * b];
+  int m = 0;
+  for (int q = 0; q < b; ++q) {
+    const int64_t i = i0 + q;
+    int base = 0;
+    for (int64_t k0 = rp[i]; k0 < rp[i + 1]; k0 += 64) {
+      const int64_t k = k0 + lane;
+      const bool f = k < rp[i + 1] && strong[k] && !cf[ci[k]];
+      const unsigned long long mask = __ballot(f);
+      const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+      if (f && pos < MAXM) {
+        if (q == 0) N[pos] = ci[k];
+        z[q * MAXM + pos] = -v[k];
+      }
+      base += __popcll(mask);
+    }
+    if (q == 0) m = base;
+    else if (base != m && lane == 0) atomicOr(err, 1);
+  }
+  __syncthreads();
+  if (m == 0 || m > MAXM) {
+    // m > MAXM cannot occur: the host picks MAXM >= max |N|
+    if (lane < b) {
+      const int64_t out = Rptr[kb * b + lane];
+      Rcol[out] = (int32_t)(i0 + lane);
+      Rval[out] = 1.0;
+    }
+    if (lane == 0) atomicAdd(nfall, (unsigned long long)b);
+    return;
+  }
+  for (int k = lane; k < m * m; k += 64) T[k] = 0.0;
+  __syncthreads();
+  // T[c][r] = A[N_r, N_c]
+  for (int r = 0; r < m; ++r) {
+    const int64_t j = N[r];
+    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
+      const int32_t col = ci[k];
+      int lo = 0, hi = m - 1, c = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        if (N[mid] == col) { c = mid; break; }
+        if (N[mid] < col) lo = mid + 1; else hi = mid - 1;
+      }
+      if (c >= 0) T[c * m + r] = v[k];
+    }
+  }
+  __syncthreads();
+  double sc = 0.0;
+  for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
+  sc = wave_max(sc);
+  bool bad = false;
+  for (int k = 0; k < m; ++k) {
+    double best = -1.0;
+    int bi = m;
+    for (int r = k + lane; r < m; r += 64) {
+      const double a = fabs(T[r * m + k]);
+      if (a > best) { best = a; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int p = bi;
+    if (fabs(T[p * m + k]) <= 1e-14 * sc) bad = true;
+    if (p != k) {
+      for (int c = lane; c < m; c += 64) {
+        const double t = T[k * m + c]; T[k * m + c] = T[p * m + c]; T[p * m + c] = t;
+      }
+      if (lane < b) {
+        const double t = z[lane * MAXM + k]; z[lane * MAXM + k] = z[lane * MAXM + p]; z[lane * MAXM + p] = t;
+      }
+    }
+    __syncthreads();
+    const double pv = bad ? 1.0 : T[k * m + k];
+    for (int r = k + 1 + lane; r < m; r += 64) {
+      const double f = T[r * m + k] / pv;
+      for (int c = k + 1; c < m; ++c) T[r * m + c] -= f * T[k * m + c];
+      for (int q = 0; q < b; ++q) z[q * MAXM + r] -= f * z[q * MAXM + k];
+    }
+    __syncthreads();
+  }
+  for (int c = m - 1; c >= 0; --c) {
+    for (int q = 0; q < b; ++q) {
+      double s = 0.0;
+      for (int j = c + 1 + lane; j < m; j += 64) s += T[c * m + j] * z[q * MAXM + j];
+      s = wave_sum(s);
+      if (lane == 0) z[q * MAXM + c] = (z[q * MAXM + c] - s) / (bad ? 1.0 : T[c * m + c]);
+    }
+    __syncthreads();
+  }
+  // rows in increasing column order: N is sorted and holds no row of the block
+  int ins = 0;
+  for (int r = lane; r < m; r += 64) ins += N[r] < i0;
+  for (int o = 32; o > 0; o >>= 1) ins += __shfl_xor(ins, o, 64);
+  for (int q = 0; q < b; ++q) {
+    const int64_t out = Rptr[kb * b + q];
+    for (int r = lane; r < m; r += 64) {
+      const int pos = r < ins ? r : r + 1;
+      Rcol[out + pos] = N[r];
+      Rval[out + pos] = bad ? 0.0 : z[q * MAXM + r];
+    }
+    if (lane == 0) {
+      Rcol[out + ins] = (int32_t)(i0 + q);
+      Rval[out + ins] = 1.0;
+    }
+  }
+  if (bad && lane == 0) atomicAdd(nfall, (unsigned long long)b);
+}
+
 // R A P per coarse row with an LDS open-addressing hash on the coarse
 // column (HS >= candidates, so it never overflows).  NUMERIC = false counts
 // the distinct columns; NUMERIC = true accumulates, sorts and writes.
@@ -625,6 +757,142 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
   for (int k = lane; k < tot; k += 64) {
     ccol[o + k] = ck[k];
     cval[o + k] = cv[k];
+  }
+}
+
+// R A P for the b coarse rows of a block AIR C block (level 0), one wave
+// per block: the rows of R of a block have the same length and hold the
+// same neighbourhood columns at the same positions, with each row's own
+// column at one common position.  A row of the neighbourhood is read once
+// for all b coarse rows (k_rap reads it once per row); the own rows are
+// read once each.  One LDS hash on the coarse column holds b sums and a
+// mask of the rows that reached the column, so every coarse row gets the
+// columns and the sums (in the same order of additions) k_rap gives it.
+// NUMERIC = false counts the columns of each row; NUMERIC = true sums,
+// sorts by column and writes the b rows.
+template <int HS, bool NUMERIC, int B>
+__global__ __launch_bounds__(64) void k_rap_blk(int64_t ncb, const int64_t* __restrict__ Rptr,
+                                                const int32_t* __restrict__ Rcol, const double* __restrict__ Rval,
+                                                const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                const double* __restrict__ v, const int32_t* __restrict__ pcol,
+                                                const int32_t* __restrict__ clist, int32_t* __restrict__ cnt,
+                                                const int64_t* __restrict__ cptr, int32_t* __restrict__ ccol,
+                                                double* __restrict__ cval) {
+  __shared__ int32_t key[HS];
+  __shared__ uint32_t tch[HS];
+  __shared__ double val[NUMERIC ? HS * B : 1];
+  __shared__ int32_t sidx[NUMERIC ? HS : 1];
+  __shared__ int s_cnt;
+  const int64_t r0 = (int64_t)blockIdx.x * B;
+  const int lane = threadIdx.x;
+  for (int k = lane; k < HS; k += 64) {
+    key[k] = -1;
+    tch[k] = 0u;
+    if (NUMERIC)
+      for (int q = 0; q < B; ++q) val[k * B + q] = 0.0;
+  }
+  if (lane == 0) s_cnt = 0;
+  __syncthreads();
+  const int64_t i0 = clist[r0];
+  const int64_t base0 = Rptr[r0];
+  const int len = (int)(Rptr[r0 + 1] - base0);
+  for (int t = 0; t < len; ++t) {
+    const int32_t j = Rcol[base0 + t];
+    const bool own = j == (int32_t)i0;
+    for (int q = 0; q < (own ? B : 1); ++q) {
+      const int64_t row = own ? i0 + q : j;
+      double rv[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) rv[u] = NUMERIC ? Rval[Rptr[r0 + u] + t] : 0.0;
+      const uint32_t bits = own ? (1u << q) : ((1u << B) - 1u);
+      for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += 64) {
+        const int32_t c = pcol[ci[k]];
+        if (c < 0) continue;
+        uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
+        while (true) {
+          const int32_t prev = atomicCAS(&key[h], -1, c);
+          if (prev == -1 || prev == c) {
+            if (prev == -1) atomicAdd(&s_cnt, 1);
+            atomicOr(&tch[h], bits);
+            if (NUMERIC) {
+              if (own) atomicAdd(&val[h * B + q], rv[q] * v[k]);
+              else
+#pragma unroll
+                for (int u = 0; u < B; ++u) atomicAdd(&val[h * B + u], rv[u] * v[k]);
+            }
+            break;
+          }
+          h = (h + 1) & (HS - 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!NUMERIC) {
+    int c[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) c[q] = 0;
+    for (int k = lane; k < HS; k += 64)
+#pragma unroll
+      for (int q = 0; q < B; ++q) c[q] += (tch[k] >> q) & 1u;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_xor(c[q], o, 64);
+      if (lane == 0) cnt[r0 + q] = c[q];
+    }
+    return;
+  }
+  // occupied slots to the front as (column, slot) pairs: one wave reads a
+  // chunk before writing it, and every write position is <= the positions
+  // still to be read
+  const int tot = s_cnt;
+  int base = 0;
+  for (int k0 = 0; k0 < HS; k0 += 64) {
+    const int k = k0 + lane;
+    const int32_t kk = key[k];
+    const bool occ = kk >= 0;
+    const unsigned long long mask = __ballot(occ);
+    const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (occ) { key[pos] = kk; sidx[pos] = k; }
+    base += __popcll(mask);
+    __syncthreads();
+  }
+  int S = 1;
+  while (S < tot) S <<= 1;
+  for (int k = tot + lane; k < S; k += 64) key[k] = 0x7fffffff;
+  __syncthreads();
+  for (int kk = 2; kk <= S; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int x = lane; x < S; x += 64) {
+        const int y = x ^ jj;
+        if (y > x) {
+          const bool up = (x & kk) == 0;
+          const int32_t a = key[x], bb = key[y];
+          if ((a > bb) == up) {
+            key[x] = bb; key[y] = a;
+            const int32_t t = sidx[x]; sidx[x] = sidx[y]; sidx[y] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = 0; q < B; ++q) {
+    const int64_t o = cptr[r0 + q];
+    int wbase = 0;
+    for (int k0 = 0; k0 < tot; k0 += 64) {
+      const int k = k0 + lane;
+      const int sl = k < tot ? sidx[k] : 0;
+      const bool has = k < tot && ((tch[sl] >> q) & 1u);
+      const unsigned long long mask = __ballot(has);
+      if (has) {
+        const int pos = wbase + __popcll(mask & ((1ull << lane) - 1ull));
+        ccol[o + pos] = key[k];
+        cval[o + pos] = val[sl * B + q];
+      }
+      wbase += __popcll(mask);
+    }
   }
 }
 
@@ -1095,6 +1363,23 @@ static ah_status lair_dispatch(int cap, bool d2, int64_t nc, const AhLevel& L, c
   return AH_OK;
 }
 
+// Block AIR lAIR rows, one wave per C block (capacity as lair_dispatch).
+static ah_status lair_blk_dispatch(int cap, int64_t ncb, int b, const AhLevel& L, const uint8_t* strong,
+                                   const int32_t* clist, unsigned long long* nfall, int* err, hipStream_t st) {
+  if (ncb == 0) return AH_OK;
+#define LB(M) hipLaunchKernelGGL((k_lair_blk<M>), dim3((unsigned)ncb), dim3(64), 0, st, ncb, b, L.rowptr, L.col, \
+                                 L.val, strong, L.cf, clist, L.Rptr, L.Rcol, L.Rval, nfall, err)
+  switch (cap) {
+    case 8: LB(8); break;
+    case 16: LB(16); break;
+    case 32: LB(32); break;
+    default: LB(64); break;
+  }
+#undef LB
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
 template <int HS>
 static ah_status rap_launch(int64_t nc, const AhLevel& L, int32_t* cnt, const int64_t* cptr, int32_t* ccol,
                             double* cval, bool numeric, hipStream_t st) {
@@ -1160,6 +1445,58 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
     AH_TRY(read_bytes(left_d, &left, sizeof(left), st));
     if (left == 0) return AH_OK;
   }
+}
+
+template <int HS, bool NUMERIC, int B>
+static void rap_blk_launch(int64_t ncb, const AhLevel& L, const int32_t* clist, int32_t* cnt, const int64_t* cptr,
+                           int32_t* ccol, double* cval, hipStream_t st) {
+  hipLaunchKernelGGL((k_rap_blk<HS, NUMERIC, B>), dim3((unsigned)ncb), dim3(64), 0, st, ncb, L.Rptr, L.Rcol, L.Rval,
+                     L.rowptr, L.col, L.val, L.pcol, clist, cnt, cptr, ccol, cval);
+}
+
+// Whether the block R A P kernels take blocks of b rows with hash size hs
+// (the numeric pass keeps b sums per slot in LDS).
+static bool rap_blk_fits(int b, int hs, bool numeric) {
+  if (b != 2 && b != 3 && b != 6) return false;
+  if (hs < 64 || hs > 4096) return false;
+  return numeric ? hs * (12 + 8 * b) <= 65536 : true;
+}
+
+template <bool NUMERIC, int B>
+static ah_status rap_blk_hs(int hs, int64_t ncb, const AhLevel& L, const int32_t* clist, int32_t* cnt,
+                            const int64_t* cptr, int32_t* ccol, double* cval, hipStream_t st) {
+  switch (hs) {
+    case 64: rap_blk_launch<64, NUMERIC, B>(ncb, L, clist, cnt, cptr, ccol, cval, st); break;
+    case 128: rap_blk_launch<128, NUMERIC, B>(ncb, L, clist, cnt, cptr, ccol, cval, st); break;
+    case 256: rap_blk_launch<256, NUMERIC, B>(ncb, L, clist, cnt, cptr, ccol, cval, st); break;
+    case 512: rap_blk_launch<512, NUMERIC, B>(ncb, L, clist, cnt, cptr, ccol, cval, st); break;
+    case 1024: rap_blk_launch<1024, NUMERIC, B>(ncb, L, clist, cnt, cptr, ccol, cval, st); break;
+    case 2048:
+      if (NUMERIC) return AH_EUNSUPPORTED;
+      rap_blk_launch<2048, false, B>(ncb, L, clist, cnt, cptr, ccol, cval, st);
+      break;
+    case 4096:
+      if (NUMERIC) return AH_EUNSUPPORTED;
+      rap_blk_launch<4096, false, B>(ncb, L, clist, cnt, cptr, ccol, cval, st);
+      break;
+    default: return AH_EUNSUPPORTED;
+  }
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+static ah_status rap_blk_dispatch(int hs, int b, bool numeric, int64_t ncb, const AhLevel& L, const int32_t* clist,
+                                  int32_t* cnt, const int64_t* cptr, int32_t* ccol, double* cval, hipStream_t st) {
+  if (ncb == 0) return AH_OK;
+  ah_status rc = AH_EUNSUPPORTED;
+  if (b == 2) rc = numeric ? rap_blk_hs<true, 2>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st)
+                           : rap_blk_hs<false, 2>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st);
+  if (b == 3) rc = numeric ? rap_blk_hs<true, 3>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st)
+                           : rap_blk_hs<false, 3>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st);
+  if (b == 6) rc = numeric ? rap_blk_hs<true, 6>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st)
+                           : rap_blk_hs<false, 6>(hs, ncb, L, clist, cnt, cptr, ccol, cval, st);
+  if (rc == AH_EUNSUPPORTED) set_error("block R A P: unsupported block size or hash size");
+  return rc;
 }
 
 }  // namespace ah
@@ -1492,7 +1829,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       tmp.release(); delete h; return AH_EUNSUPPORTED;
     }
     const int cap = maxm <= 8 ? 8 : maxm <= 16 ? 16 : maxm <= 32 ? 32 : 64;
-    CK(lair_dispatch(cap, d2, nc, L, strong_r, clist, d_ull + 2, st));
+    if (blk && nc % L.ob) {
+      set_error("air_setup: block AIR coarse grid of %lld rows is not made of whole blocks", (long long)nc);
+      tmp.release(); delete h; return AH_EUNSUPPORTED;
+    }
+    if (blk && L.ob <= LB_BMAX) {
+      CKH(hipMemsetAsync(d_int + 2, 0, sizeof(int), st));
+      CK(lair_blk_dispatch(cap, nc / L.ob, (int)L.ob, L, strong_r, clist, d_ull + 2, d_int + 2, st));
+    } else {
+      CK(lair_dispatch(cap, d2, nc, L, strong_r, clist, d_ull + 2, st));
+    }
     CKH(hipGetLastError());
     // R A P
     const int maxcand = hmax[1];
@@ -1501,7 +1847,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     C.n = nc;
     int32_t* ccnt = nullptr;
     CK(tmp.get(&ccnt, nc + 1));
-    CK(rap_dispatch(hs, nc, L, ccnt, nullptr, nullptr, nullptr, false, st));
+    // block AIR level 0: the rows of a C block together (a block's
+    // candidates are at most b times a row's)
+    int hsb = 256;
+    while (hsb <= (int64_t)L.ob * maxcand && hsb < 8192) hsb *= 2;
+    const bool rblk = blk && rap_blk_fits((int)L.ob, hsb, false) && L.ob <= LB_BMAX;
+    if (rblk) CK(rap_blk_dispatch(hsb, (int)L.ob, false, nc / L.ob, L, clist, ccnt, nullptr, nullptr, nullptr, st));
+    else CK(rap_dispatch(hs, nc, L, ccnt, nullptr, nullptr, nullptr, false, st));
     CK(ar.get(&C.rowptr, nc + 1));
     CK(scan_i32_to_i64(ccnt, C.rowptr, nc, st, tmp));
     // the numeric pass hashes a row's distinct coarse columns only: size its
@@ -1514,13 +1866,24 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       double* pin = pinned_scratch(2);
       if (!pin) { set_error("pinned host allocation failed"); tmp.release(); delete h; return AH_ENOMEM; }
       CKH(hipMemcpyAsync(pin, C.rowptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      CKH(hipMemcpyAsync(pin + 1, d_int + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(pin + 1, d_int + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       CKH(hipStreamSynchronize(st));
       std::memcpy(&C.nnz, pin, sizeof(int64_t));
-      std::memcpy(&rmax, pin + 1, sizeof(int));
+      int e2[2];
+      std::memcpy(e2, pin + 1, sizeof(e2));
+      rmax = e2[1];
+      if (blk && e2[0]) {
+        set_error("air_setup: rows of a facet block differ in their block AIR neighbourhood");
+        tmp.release(); delete h; return AH_EUNSUPPORTED;
+      }
     }
     int hsn = 64;
     while (hsn < 2 * rmax && hsn < hs) hsn *= 2;
+    // the block pass hashes the union of its rows' columns (at most a row's
+    // plus the b - 1 other own columns)
+    int hsnb = 64;
+    while (hsnb < 2 * (rmax + (int)L.ob) && hsnb < hsb) hsnb *= 2;
+    const bool nblk = rblk && rap_blk_fits((int)L.ob, hsnb, true);
     CK(ar.get(&C.col, C.nnz));
     CK(ar.get(&C.val, C.nnz));
     {
@@ -1530,7 +1893,8 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       double by = (double)L.nnzR * 12.0 + (double)(nc + 1) * 8.0 + (double)C.nnz * 12.0 + (double)(nc + 1) * 8.0 +
                   (double)L.nnz * 12.0 + (double)n * 4.0;
       prof_begin(ps, l == 0 ? "rap0" : nullptr, st, by);
-      CK(rap_dispatch(hsn, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
+      if (nblk) CK(rap_blk_dispatch(hsnb, (int)L.ob, true, nc / L.ob, L, clist, ccnt, C.rowptr, C.col, C.val, st));
+      else CK(rap_dispatch(hsn, nc, L, ccnt, C.rowptr, C.col, C.val, true, st));
       prof_end(ps);
     }
     if (prm.fp32_cycle) {
