@@ -1564,8 +1564,10 @@ static ah_status ensure_workspace(ah_hier* h, int m, int precision, hipStream_t 
       h->Z32 = nullptr;
       h->m_alloc = m;
     }
-    if (precision == 0 && !h->Z) AH_TRY(ar.get(&h->Z, (int64_t)m * n));
-    if (precision == 1 && !h->Z32) AH_TRY(ar.get(&h->Z32, (int64_t)m * n));
+    // Z and Z32 hold the full capacity m_alloc (>= m): a later call with a
+    // restart up to m_alloc reuses them without a new check
+    if (precision == 0 && !h->Z) AH_TRY(ar.get(&h->Z, (int64_t)h->m_alloc * n));
+    if (precision == 1 && !h->Z32) AH_TRY(ar.get(&h->Z32, (int64_t)h->m_alloc * n));
   }
   W->V = h->V;
   W->Z = precision == 0 ? h->Z : nullptr;

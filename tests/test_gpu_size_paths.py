@@ -140,3 +140,27 @@ def test_coarse_list_sweeps_solve(built, coarse_lists, name):
     xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
     assert info["converged"]
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("delayed", [False, True])
+def test_workspace_reuse_across_restarts_and_precisions(built, monkeypatch, delayed):
+    """One hierarchy solved with a long restart in FP64, then with shorter
+    and growing restarts in FP32 and FP64 (regression: the basis of a
+    precision first used with a short restart was sized for that restart,
+    not for the workspace's capacity, and a later longer restart wrote past
+    it).  Every solve matches a fresh hierarchy's solve of the same
+    settings bit for bit."""
+    from paper_2010_11130_amd import Hierarchy
+    if delayed:
+        monkeypatch.setenv("AH_DCGS_MIN", "0")
+    g, o = built("kuhn_nu4")
+    print("case kuhn_nu4 workspace reuse, delayed", delayed, flush=True)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1)
+    H.solve(tol=1e-10, restart=30, precision=0)
+    for prec, m in ((1, 5), (1, 8), (1, 30), (0, 5), (0, 12)):
+        x, info = H.solve(tol=1e-10, restart=m, precision=prec)
+        F = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=1)
+        xf, infof = F.solve(tol=1e-10, restart=m, precision=prec)
+        assert info["converged"] and info["iters"] == infof["iters"], (prec, m)
+        assert np.array_equal(x.cpu().numpy(), xf.cpu().numpy()), (prec, m)
+        del F
