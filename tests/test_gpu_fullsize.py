@@ -13,6 +13,10 @@ kernel).
   CPU from the exported matrix. The C5 source gradient is checked against
   central differences, which are exact for any step because J is quadratic
   in the amplitudes.
+* C3 with block AIR on level 0 (the benchmark's setting): the same
+  properties, and level 0 checked block by block on a seeded sample against
+  the oracle's strength and local-solve routines (P rows, lAIR rows, the
+  PMIS rule for F blocks).
 """
 import time
 
@@ -288,3 +292,151 @@ def test_c5_full_size_source_gradient_vs_central_differences(c5_mesh):
         an = float(grad @ d)
         print("direction", k, "adjoint", an, "central difference", fd, flush=True)
         assert abs(an - fd) <= 1e-7 * abs(fd)
+
+
+# Block AIR on level 0, the benchmark's coarsening: it converges at the
+# default threshold for every nu of the workload.
+@pytest.mark.parametrize("nu", [0.0, 1e-4, 1e-2])
+def test_c3_full_size_block_air_polynomial_reproduction(c3_mesh, nu):
+    from paper_2010_11130_amd import Hierarchy
+    from workloads.problems import PolynomialProblem
+    v, m, fv, bf, kinds = c3_mesh
+    print("case C3 full size, block AIR, linear u, nu", nu, flush=True)
+    prob = PolynomialProblem(2, 1, nu, seed=11, a_const=np.array([1.0, 0.5]), a_lin=np.zeros((2, 3)))
+    s = _system(m, v, fv, bf, kinds, prob, 1, keep=False)
+    H = Hierarchy(s, block_air=1)
+    x, info = H.solve(tol=1e-11)
+    assert info["converged"]
+    ue = _exact_free_trace(v, fv, kinds, 1, prob.u)
+    err = (torch.linalg.norm(x - ue) / torch.linalg.norm(ue)).item()
+    print("levels", H.info["levels"], "iterations", info["iters"], "trace error", err, flush=True)
+    assert err <= 1e-8
+    assert _true_residual(s, x) <= 1e-11
+
+
+def _block_air_level0_sampled(H, b, theta, nsamp=1500, seed=3):
+    """Level 0 of a block-AIR hierarchy at full size against the oracle's
+    routines, block by block on a seeded sample: block weights and strength
+    from the exported rows; the PMIS rule for F blocks (an F block without a
+    strong C block it depends on is one that no block depends on strongly,
+    i.e. F from the start); P of F blocks (strongest strong C block, row m
+    to row m); and the lAIR rows of C blocks from their local systems
+    (1e-10)."""
+    lv = H.level(0)
+    n = lv["n"]
+    nb = n // b
+    rp = lv["rowptr"].cpu().numpy()
+    cf = lv["cf"].cpu().numpy().astype(np.int64)
+    pcol = lv["pcol"].cpu().numpy()
+    Rptr = lv["Rptr"].cpu().numpy()
+    cfb = cf.reshape(nb, b)
+    assert np.all(cfb == cfb[:, :1]), "rows of a block with different labels"
+    cidx = np.cumsum(cf) - 1
+    rng = np.random.default_rng(seed)
+    blocks = np.sort(rng.choice(nb, nsamp, replace=False))
+
+    def rows(I_list):
+        """CSR pieces (host) of the rows of the given blocks."""
+        r = (np.asarray(I_list)[:, None] * b + np.arange(b)).ravel()
+        lo, hi = rp[r], rp[r + 1]
+        cnt = hi - lo
+        pos = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
+        t = torch.as_tensor(pos, device=lv["col"].device)
+        c = lv["col"][t].cpu().numpy().astype(np.int64)
+        vv = lv["val"][t].cpu().numpy()
+        ptr = np.concatenate([[0], np.cumsum(cnt)])
+        return {int(ri): (c[ptr[k]:ptr[k + 1]], vv[ptr[k]:ptr[k + 1]]) for k, ri in enumerate(r)}
+
+    def weights(I, R):
+        w = {}
+        for q in range(b):
+            c, vv = R[I * b + q]
+            for cc, a in zip(c // b, np.abs(vv)):
+                if cc != I:
+                    w[int(cc)] = max(w.get(int(cc), 0.0), a)
+        Js = np.array(sorted(w), dtype=np.int64)
+        wv = np.array([w[j] for j in Js])
+        # the oracle's strength marks on this one block row, its blocks
+        # numbered 1.. locally (row 0 stands for I, which has no entry)
+        Wi = sp.csr_matrix((wv, np.arange(1, len(Js) + 1), [0, len(Js)]), shape=(1, len(Js) + 1))
+        strong = oair.strength(Wi, theta) if len(Js) else np.zeros(0, dtype=bool)
+        return Js, wv, strong
+
+    R0 = rows(blocks)
+    checked_r = checked_p = checked_f0 = 0
+    for I in blocks:
+        J, w, st = weights(int(I), R0)
+        if cfb[I, 0] == 1:
+            NJ = J[st & (cfb[J, 0] == 0)]
+            Nrows = (NJ[:, None] * b + np.arange(b)).ravel()
+            if len(Nrows) == 0:
+                continue
+            RN = rows(NJ)
+            q_ = len(Nrows)
+            pos = {int(r): k for k, r in enumerate(Nrows)}
+            M = np.zeros((q_, q_))
+            for r in Nrows:
+                c, vv = RN[int(r)]
+                for cc, a in zip(c, vv):
+                    k = pos.get(int(cc))
+                    if k is not None:
+                        M[pos[int(r)], k] = a
+            rhs = np.zeros((b, q_))
+            for qq in range(b):
+                c, vv = R0[int(I) * b + qq]
+                for cc, a in zip(c, vv):
+                    k = pos.get(int(cc))
+                    if k is not None:
+                        rhs[qq, k] = -a
+            z, bad = oair.batched_lu_solve(np.repeat(M.T[None], b, axis=0), rhs)
+            for qq in range(b):
+                row = int(cidx[int(I) * b + qq])
+                lo, hi = Rptr[row], Rptr[row + 1]
+                rc = lv["Rcol"][lo:hi].cpu().numpy()
+                rv = lv["Rval"][lo:hi].cpu().numpy()
+                exp_c = np.sort(np.concatenate([Nrows, [int(I) * b + qq]]))
+                assert np.array_equal(rc, exp_c), I
+                got = rv[np.searchsorted(exp_c, Nrows)]
+                ref = np.zeros(q_) if bad[qq] else z[qq]
+                assert np.linalg.norm(got - ref) <= 1e-10 * max(np.linalg.norm(ref), 1e-300), I
+                assert rv[np.searchsorted(exp_c, int(I) * b + qq)] == 1.0
+            checked_r += 1
+        else:
+            el = st & (cfb[J, 0] == 1)
+            exp = -np.ones(b, dtype=np.int64)
+            if not np.any(el) and len(J):
+                RK = rows(J)
+                for K in J:
+                    JK, _, sK = weights(int(K), RK)
+                    assert not np.any(sK & (JK == I)), (I, K)
+                checked_f0 += 1
+            if np.any(el):
+                mx = w[el].max()
+                Js = J[el & (w >= mx * (1.0 - 1e-12))][0]
+                exp = cidx[Js * b + np.arange(b)]
+            assert np.array_equal(pcol[int(I) * b + np.arange(b)], exp), I
+            checked_p += 1
+    print("sampled blocks: %d C (lAIR rows), %d F (P rows, %d without a strong C block)"
+          % (checked_r, checked_p, checked_f0), flush=True)
+    assert checked_r > 100 and checked_p > 100
+
+
+def test_c3_full_size_block_air_headline(c3_mesh):
+    """The benchmark's step at full size: block AIR setup, FGMRES to 1e-8 in
+    FP64 and with the FP32 cycle, true residual, and the sampled level-0
+    check against the oracle's routines."""
+    from paper_2010_11130_amd import Hierarchy
+    from workloads.problems import SmoothPlusFront
+    v, m, fv, bf, kinds = c3_mesh
+    print("case C3 full size, block AIR, smooth + front, nu 1e-4", flush=True)
+    prob = SmoothPlusFront(1e-4)
+    s = _system(m, v, fv, bf, kinds, prob, 1, keep=False)
+    H = Hierarchy(s, block_air=1, fp32_cycle=1)
+    x, info = H.solve(tol=1e-8)
+    x32, info32 = H.solve(tol=1e-8, precision=1)
+    print("levels", H.info["levels"], "iterations", info["iters"], info32["iters"], flush=True)
+    assert info["converged"] and info32["converged"]
+    assert info["iters"] <= 60 and info32["iters"] <= 60      # 51 and 52 on this mesh
+    assert _true_residual(s, x) <= 1e-8
+    assert _true_residual(s, x32) <= 1e-8
+    _block_air_level0_sampled(H, 3, 0.25)
