@@ -1815,6 +1815,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     }
     L.nc = nc;
     L.clist = clist;
+    L.fblk = blk;
     if (L.ob) {
       hipLaunchKernelGGL(k_list_vals, grows(n - nc), dim3(256), 0, st, n - nc, L.flist, L.optr, L.ob, d_fst + 64);
       CKH(hipGetLastError());
@@ -2025,6 +2026,9 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
   // by one workgroup inside a single launch per cycle
   {
     if (const char* e = std::getenv("AH_G0")) h->g0 = std::atoi(e);
+    if (const char* e = std::getenv("AH_FBB")) h->fbb = std::atoi(e) != 0;
+    if (const char* e = std::getenv("AH_LPB")) h->lpb = std::atoi(e);
+    if (h->lpb != 2 && h->lpb != 4 && h->lpb != 8) h->lpb = 0;
     if (const char* e = std::getenv("AH_DCGS_MIN")) h->dcgs_min = std::atoll(e);
     if (const char* e = std::getenv("AH_GC")) h->gc = std::atoi(e);
     if (h->gc != 2 && h->gc != 4 && h->gc != 8 && h->gc != 16 && h->gc != 32) h->gc = 0;

@@ -160,6 +160,66 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
   }
 }
 
+// The same operator by facet block rows: LPB lanes per block row R, a lane
+// per off-diagonal block s of the row (s = g, g + LPB, ...).  A lane reads
+// the block's column index once, its B values of x once, and the B x B
+// values of the block (row m, column c at (m nb + s) B + c), accumulating
+// one sum per row of the block row; the B sums are reduced across the
+// lanes and lane m mod LPB writes row R B + m.  Each x value is gathered once for
+// the B rows that use it (k_fb gathers it once per row).  Items are block
+// rows: all of them (SP_MV, SP_RES), or the blocks of a row list made of
+// whole blocks in increasing order (SP_SWEEP_LIST: block k is list[k B] / B).
+template <class TA, class TX, class TY, int B, int LPB, int MODE>
+__global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restrict__ optr,
+                                             const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
+                                             const TX* __restrict__ x, const TY* __restrict__ b, TY omega,
+                                             TY* __restrict__ y, const int32_t* __restrict__ list,
+                                             TY* __restrict__ y2) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kk = gid / LPB;
+  const int g = (int)(gid % LPB);
+  if (kk >= nbr) return;
+  const int64_t R = MODE == SP_SWEEP_LIST ? (int64_t)list[kk * B] / B : kk;
+  const int64_t o0 = optr[R];
+  const int nb = (int)(optr[R + 1] - o0);
+  const TA* __restrict__ v = ov + o0 * (B * B);
+  TY acc[B];
+#pragma unroll
+  for (int m = 0; m < B; ++m) acc[m] = 0;
+  for (int sl = g; sl < nb; sl += LPB) {
+    const int64_t J = ocol[o0 + sl];
+    TY xv[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) xv[c] = (TY)x[J * B + c];
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      const TA* __restrict__ vr = v + ((int64_t)m * nb + sl) * B;
+#pragma unroll
+      for (int c = 0; c < B; ++c) acc[m] += (TY)vr[c] * xv[c];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < B; ++m)
+#pragma unroll
+    for (int o = LPB / 2; o > 0; o >>= 1) acc[m] += __shfl_xor(acc[m], o, LPB);
+#pragma unroll
+  for (int m = 0; m < B; ++m) {
+    if (m % LPB != g) continue;      // lane m mod LPB writes row m
+    const int64_t i = R * B + m;
+    const TY xi = (TY)x[i];
+    const TY a = acc[m] + xi;
+    if (MODE == SP_MV) {
+      y[i] = a;
+    } else if (MODE == SP_RES) {
+      y[i] = b[i] - a;
+    } else {
+      const TY xn = xi + omega * (b[i] - a);
+      y[i] = xn;
+      if (y2) y2[i] = xn;
+    }
+  }
+}
+
 // One level of the ordered forward sweep on level 0 (flow order of Lemma
 // 3.1): x_i <- b_i - sum of a_ij x_j over the off-diagonal blocks (the
 // diagonal blocks are the identity), written to xn.  Blocks of earlier
@@ -1122,6 +1182,67 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
   return AH_OK;
 }
 
+// Lanes per block row of k_fbb from the mean number of off-diagonal blocks
+// per block row (C3: 6 -> 8 lanes).
+static int fbb_lanes(int64_t nvals, int64_t n, int B) {
+  const double nb = n ? (double)nvals / ((double)n * B) : 0.0;
+  if (nb <= 2.0) return 2;
+  if (nb <= 4.0) return 4;
+  return 8;
+}
+
+template <class TA, class TX, class TY, int MODE, int B>
+static void fbb_launch(int L, int64_t nbr, hipStream_t st, const int64_t* optr, const int32_t* ocol, const TA* ov,
+                       const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2) {
+#define FBB(LP) hipLaunchKernelGGL((k_fbb<TA, TX, TY, B, LP, MODE>), dim3((unsigned)cdiv(nbr * LP, 256)), dim3(256), 0, \
+                                   st, nbr, optr, ocol, ov, x, b, omega, y, list, y2)
+  switch (L) {
+    case 2: FBB(2); break;
+    case 4: FBB(4); break;
+    default: FBB(8); break;
+  }
+#undef FBB
+}
+
+// k_fbb over n rows (the listed ones for SP_SWEEP_LIST, whole blocks in
+// increasing order), block size B, L lanes per block row.
+template <class TA, class TX, class TY, int MODE>
+static ah_status fbb_g(int B, int L, int64_t n, const int64_t* optr, const int32_t* ocol, const TA* ov, const TX* x,
+                       const TY* b, TY omega, TY* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
+                       const int32_t* list = nullptr, TY* y2 = nullptr) {
+  if (n == 0) return AH_OK;
+  if (n % B) { set_error("block-row sweep over %lld rows, not whole blocks of %d", (long long)n, B); return AH_EINVAL; }
+  const int64_t nbr = n / B;
+  ProfScope ps;
+  prof_begin(ps, tag, st, bytes);
+  switch (B) {
+    case 2: fbb_launch<TA, TX, TY, MODE, 2>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 3: fbb_launch<TA, TX, TY, MODE, 3>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 4: fbb_launch<TA, TX, TY, MODE, 4>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 6: fbb_launch<TA, TX, TY, MODE, 6>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 10: fbb_launch<TA, TX, TY, MODE, 10>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    default: set_error("unsupported facet block size %d", B); return AH_EUNSUPPORTED;
+  }
+  prof_end(ps);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
+// Level-0 kernel over n rows of the facet-block layout: by block rows
+// (k_fbb) where the rows are whole blocks (all rows, or block AIR point
+// lists), else by rows (k_fb).
+template <class T, int MODE>
+static ah_status fb_any(const ah_hier* h, const AhLevel& L, bool blocks, int64_t n, const T* ov, const T* x,
+                        const T* b, T om, T* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
+                        const int32_t* list = nullptr, T* y2 = nullptr) {
+  if (blocks && h->fbb) {
+    const int lp = h->lpb ? h->lpb : fbb_lanes(L.nov, L.n, L.ob);
+    return fbb_g<T, T, T, MODE>(L.ob, lp, n, L.optr, L.ocol, ov, x, b, om, y, st, tag, bytes, list, y2);
+  }
+  const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
+  return fb_g<T, T, T, MODE>(L.ob, Gb, n, L.optr, L.ocol, ov, x, b, om, y, st, tag, bytes, list, y2);
+}
+
 // Algorithmic bytes of a Jacobi sweep on the point set X of level L: the X
 // rows of A once, x once, b and d on X, the X updates written.
 template <class T>
@@ -1391,15 +1512,14 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   const char* tf = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
   const char* tc = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
   if (l == 0 && L.ob && Ops<T>::O(L)) {
-    const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
     const T* ov = Ops<T>::O(L);
-    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, x, b, om, y, st, tf,
-                                         fb_sweep_bytes<T>(L, 0, false), L.flist)));
+    AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF, ov, x, b, om, y, st, tf, fb_sweep_bytes<T>(L, 0, false),
+                                     L.flist)));
     if (nsw == 1) return AH_OK;
-    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF, L.optr, L.ocol, ov, y, b, om, x, st, tf,
-                                         fb_sweep_bytes<T>(L, 0, true), L.flist, out)));
-    AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, L.nc, L.optr, L.ocol, ov, x, b, om, out, st, tc,
-                                         fb_sweep_bytes<T>(L, 1, false), L.clist)));
+    AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF, ov, y, b, om, x, st, tf, fb_sweep_bytes<T>(L, 0, true),
+                                     L.flist, out)));
+    AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, L.nc, ov, x, b, om, out, st, tc, fb_sweep_bytes<T>(L, 1, false),
+                                     L.clist)));
     return AH_OK;
   }
   AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,
@@ -1466,19 +1586,18 @@ static ah_status vcycle_t(ah_hier* h, int l, const T* g, T* out, hipStream_t st)
     // A_0^T by facet blocks: the first sweep (C points, or the F points
     // with one sweep) starts from zero, y_X = omega g_X / d_X, written to
     // both buffers; the F sweeps then alternate over the F list
-    const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
     const int X = h->prm.relax == 1 ? 0 : 1;
     hipLaunchKernelGGL((k_sweep_from_zero<T>), g1(L.n), dim3(256), 0, st, L.n, L.cf, X, g, Ops<T>::d(L), om, cur,
                        alt);
     AH_LAUNCHED();
     if (h->prm.relax != 1) {
-      AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF0(L), L.optr, L.ocol, Ops<T>::OT(L), cur, g, om, alt, st,
-                                           nullptr, 0.0, L.flist)));
-      AH_TRY((fb_g<T, T, T, SP_SWEEP_LIST>(L.ob, Gb, nF0(L), L.optr, L.ocol, Ops<T>::OT(L), alt, g, om, cur, st,
-                                           nullptr, 0.0, L.flist)));
+      AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF0(L), Ops<T>::OT(L), cur, g, om, alt, st, nullptr, 0.0,
+                                       L.flist)));
+      AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF0(L), Ops<T>::OT(L), alt, g, om, cur, st, nullptr, 0.0,
+                                       L.flist)));
     }
     // residual g - A^T y, restricted by P^T
-    AH_TRY((fb_g<T, T, T, SP_RES>(L.ob, Gb, L.n, L.optr, L.ocol, Ops<T>::OT(L), cur, g, (T)0, alt, st)));
+    AH_TRY((fb_any<T, SP_RES>(h, L, true, L.n, Ops<T>::OT(L), cur, g, (T)0, alt, st)));
     AH_TRY((csr_g<T, T, T, SP_MV>(4, L.nc, L.PTptr, L.PTcol, (const T*)nullptr, alt, (const T*)nullptr,
                                   (const T*)nullptr, (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
     T* ec = (l + 1 == nlev - 1) ? Ops<T>::x(C) : Ops<T>::b(C);
@@ -1684,6 +1803,7 @@ struct Op {
   const int32_t* ocol = nullptr;
   const double* ov = nullptr;
   int64_t nov = 0;
+  int lpb = 0;                 // > 0: the facet-block layout by block rows (k_fbb), that many lanes each
 };
 
 static int op_lanes(const ah_hier* h, const Op& A, int64_t n) {
@@ -1703,6 +1823,8 @@ static double op_mv_bytes(const ah_hier* h, const Op& A, int64_t n, double wx) {
 template <class TX, int MODE>
 static ah_status op_apply(const Op& A, int G, int64_t n, const TX* x, const double* b, double* y, hipStream_t st,
                           const char* tag = nullptr, double bytes = 0.0) {
+  if (A.ob && A.lpb)
+    return fbb_g<double, TX, double, MODE>(A.ob, A.lpb, n, A.optr, A.ocol, A.ov, x, b, 0.0, y, st, tag, bytes);
   if (A.ob)
     return fb_g<double, TX, double, MODE>(A.ob, G, n, A.optr, A.ocol, A.ov, x, b, 0.0, y, st, tag, bytes);
   return csr_g<double, TX, double, MODE>(G, n, A.rp, A.ci, A.v, x, b, (const double*)nullptr,
@@ -2262,6 +2384,7 @@ static ah_status solve_forward(ah_hier* h, const KWork& W, const double* rhs, do
     A.ocol = L0.ocol;
     A.ov = L0.oval;
     A.nov = L0.nov;
+    A.lpb = h->fbb ? (h->lpb ? h->lpb : fbb_lanes(L0.nov, n, L0.ob)) : 0;
   }
   if (prm.method == 1) return bicgstab(h, A, b, x, prm, 0, st, info);
   return fgmres(h, W, A, b, x, prm, 0, st, info);
@@ -2345,6 +2468,7 @@ extern "C" ah_status air_solve_adjoint(const ah_hier* hc, const double* g, doubl
     AT.ocol = L0.ocol;
     AT.ov = L0.otval;
     AT.nov = L0.nov;
+    AT.lpb = h->fbb ? (h->lpb ? h->lpb : fbb_lanes(L0.nov, n, L0.ob)) : 0;
   }
   ah_status rc = prm->method == 1 ? bicgstab(h, AT, g, mu, *prm, 1, st, info)
                                    : fgmres(h, W, AT, g, mu, *prm, 1, st, info);

@@ -79,6 +79,7 @@ struct AhLevel {
   // level 0 of a scaled system: the operator by off-diagonal facet blocks
   // (identity diagonal blocks), ob = block size, 0 where not available
   int ob = 0;
+  bool fblk = false;           // F and C points are whole facet blocks (block AIR): block-row sweeps
   int64_t nov = 0;             // stored values (off-diagonal blocks * ob^2)
   int64_t novF = 0;            // of which in F rows
   const int64_t* optr = nullptr;
@@ -230,6 +231,8 @@ struct ah_hier {
   int64_t tail_bytes_t[2] = {0, 0};
   const char* tail_img_t[2] = {nullptr, nullptr};
   int g0 = 0;                  // lanes per row of the level-0 kernels (0: from the mean row length)
+  int fbb = 1;                 // level-0 kernels by facet block rows where the rows are whole blocks
+  int lpb = 0;                 // lanes per block row of those (0: from the mean blocks per row)
   int64_t dcgs_min = (int64_t)1 << 21;   // FGMRES uses delayed CGS2 from this many unknowns on
   int gc = 0;                  // lanes per row of the coarse-level kernels (0: from the mean row length)
   int64_t list_min = (int64_t)1 << 16;   // coarse levels from this many rows on sweep their F and C lists
