@@ -207,7 +207,8 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 // the number of R A P candidates of its coarse row (row lengths of A over
 // {i} and N_i); for F points their list and the F-row statistics (count,
 // entries).
-// imax[0] = max |N_i|, imax[1] = max candidates; fst[0..1] = F rows, entries.
+// imax[0] = max |N_i|, imax[1] = max candidates, imax[2] = max length of a
+// C row; fst[0..1] = F rows, entries.
 // PG lanes per row; the strongest C neighbour is the first in row order
 // (smallest column) within relative 1e-12 of the maximum.
 __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __restrict__ rp,
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
                                                   unsigned long long* __restrict__ fst) {
   const int g = (int)(threadIdx.x % PG);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
-  int mmax = 0, cmax = 0;
+  int mmax = 0, cmax = 0, omax = 0;
   unsigned long long fcnt = 0, fent = 0;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; i < n; i += stride) {
     const int64_t k0 = rp[i], k1 = rp[i + 1];
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
         rcnt[cidx[i]] = 1 + m;
         clist[cidx[i]] = (int32_t)i;
         mmax = m > mmax ? m : mmax;
+        omax = (int)(k1 - k0) > omax ? (int)(k1 - k0) : omax;
         const int c = cand > 0x3fffffff ? 0x3fffffff : (int)cand;
         cmax = c > cmax ? c : cmax;
       }
@@ -270,17 +272,18 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
   }
   // block totals, one atomic each
   for (int o = 32; o > 0; o >>= 1) {
-    int a = __shfl_xor(mmax, o, 64), c = __shfl_xor(cmax, o, 64);
+    int a = __shfl_xor(mmax, o, 64), c = __shfl_xor(cmax, o, 64), ow = __shfl_xor(omax, o, 64);
     mmax = a > mmax ? a : mmax;
     cmax = c > cmax ? c : cmax;
+    omax = ow > omax ? ow : omax;
     fcnt += __shfl_xor(fcnt, o, 64);
     fent += __shfl_xor(fent, o, 64);
   }
-  __shared__ int sm[2][4];
+  __shared__ int sm[3][4];
   __shared__ unsigned long long su[2][4];
   const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
-    sm[0][w] = mmax; sm[1][w] = cmax;
+    sm[0][w] = mmax; sm[1][w] = cmax; sm[2][w] = omax;
     su[0][w] = fcnt; su[1][w] = fent;
   }
   __syncthreads();
@@ -288,11 +291,13 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
     for (int k = 1; k < (int)(blockDim.x / 64); ++k) {
       mmax = sm[0][k] > mmax ? sm[0][k] : mmax;
       cmax = sm[1][k] > cmax ? sm[1][k] : cmax;
+      omax = sm[2][k] > omax ? sm[2][k] : omax;
       fcnt += su[0][k];
       fent += su[1][k];
     }
     if (mmax) atomicMax(&imax[0], mmax);
     if (cmax) atomicMax(&imax[1], cmax);
+    if (omax) atomicMax(&imax[2], omax);
     if (fcnt) atomicAdd(&fst[0], fcnt);
     if (fent) atomicAdd(&fst[1], fent);
   }
@@ -1610,7 +1615,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
 #define CKH(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error("air_setup: %s", hipGetErrorString(e_)); tmp.release(); delete h; return AH_EHIP; } } while (0)
   unsigned long long* d_ull = nullptr;   // [0..1] undecided counts (alternating rounds), [2] lAIR fallbacks,
                                          // [3] single-workgroup PMIS round overflow
-  int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] error, [3] max A_c row
+  int* d_int = nullptr;                  // [0] max |N_i|, [1] max candidates, [2] max C-row length (then error flags), [3] max A_c row
   unsigned long long* d_fst = nullptr;   // per level: F rows, F-row entries
   CK(ar.get(&d_ull, 4));
   CK(ar.get(&d_int, 4));
@@ -1843,15 +1848,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     CKH(hipGetLastError());
     // R A P
     const int maxcand = hmax[1];
-    int hs = maxcand < 256 ? 256 : maxcand < 1024 ? 1024 : maxcand < 2048 ? 2048 : maxcand < 4096 ? 4096 : -1;
+    int hs = maxcand < 256 ? 256 : maxcand < 512 ? 512 : maxcand < 1024 ? 1024 : maxcand < 2048 ? 2048
+                                                     : maxcand < 4096 ? 4096 : -1;
     AhLevel C;
     C.n = nc;
     int32_t* ccnt = nullptr;
     CK(tmp.get(&ccnt, nc + 1));
     // block AIR level 0: the rows of a C block together (a block's
-    // candidates are at most b times a row's)
+    // candidates: a row's, plus the other b - 1 own rows)
     int hsb = 256;
-    while (hsb <= (int64_t)L.ob * maxcand && hsb < 8192) hsb *= 2;
+    while (hsb <= (int64_t)maxcand + (int64_t)(L.ob - 1) * hmax[2] && hsb < 8192) hsb *= 2;
     const bool rblk = blk && rap_blk_fits((int)L.ob, hsb, false) && L.ob <= LB_BMAX;
     if (rblk) CK(rap_blk_dispatch(hsb, (int)L.ob, false, nc / L.ob, L, clist, ccnt, nullptr, nullptr, nullptr, st));
     else CK(rap_dispatch(hs, nc, L, ccnt, nullptr, nullptr, nullptr, false, st));

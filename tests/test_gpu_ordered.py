@@ -187,3 +187,28 @@ def test_ordered_cycles_repeat_bit_for_bit(built, relax, fp32):
     zo = oair.vcycle(OH, r)
     tol = 1e-5 if fp32 else 1e-10
     assert np.linalg.norm(zs[0] - zo) <= tol * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5"])
+@pytest.mark.parametrize("relax", [2, 3])
+def test_ordered_with_block_air(built, name, relax):
+    """The ordered relaxations on a block AIR hierarchy (the F points of
+    relax 3 are whole facet blocks): one cycle and its transpose to 1e-10,
+    the solve to 1e-10 and the iteration counts within +-1 of the oracle."""
+    print("case", name, relax, "block AIR", flush=True)
+    g, o = built(name)
+    H = _hier(g, relax, adjoint=1, block_air=1)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, relax=RELAX[relax], block=o.b, block_air=True)
+    r = np.random.default_rng(8).standard_normal(g.n)
+    for transpose in (False, True):
+        z = H.vcycle(torch.as_tensor(r, device="cuda"), transpose=transpose).cpu().numpy()
+        zo = oair.vcycle_T(OH, r) if transpose else oair.vcycle(OH, r)
+        assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo), transpose
+    x, info = H.solve(tol=1e-12)
+    xo, _ = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    tol = 1e-10 if name.startswith("c1") else 1e-8
+    _, i8 = H.solve(tol=tol)
+    _, io8 = air_fgmres_solve(o, tol=tol, hier=OH)
+    assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
