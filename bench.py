@@ -458,6 +458,40 @@ def c3_variants(c3, tol, x64, air):
     return out
 
 
+def c4_record(args):
+    """The precision form on the C2 slab shapes (64 slabs of 342,528 DOFs,
+    p = 2, rotating hill) at nu = 0 and 1e-4: the pipelined march with the
+    FP64 and the FP32 cycle, FGMRES iterations per slab, and the FP32-cycle
+    solution's difference from the FP64 one on the last slab (the FP64 slab
+    solve matches the FP64 oracle in the full-slab tests)."""
+    import torch
+    out = {}
+    for nu in (0.0, 1e-4):
+        march = March(args.n, args.slabs, args.p, nu)
+        march.builders = args.builders
+        rec = {}
+        last = {}
+        for prec in (0, 1):
+            march.step(prec, args.tol)
+            torch.cuda.synchronize()
+            its = []
+            t0 = time.perf_counter()
+            for _ in range(args.march_steps):
+                lam, _ = march.step(prec, args.tol, iters=its)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.march_steps
+            last[prec] = lam
+            rec["fp64" if prec == 0 else "fp32_cycle"] = {
+                "value": args.slabs * lam.numel() / dt, "ms_per_step": 1e3 * dt,
+                "fgmres_iters_per_slab": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)}}
+        rec["fp32_cycle"]["rel_diff_vs_fp64_last_slab"] = (torch.linalg.norm(last[1] - last[0]) /
+                                                           torch.linalg.norm(last[0])).item()
+        rec["fp32_cycle"]["speedup_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["fp32_cycle"]["ms_per_step"]
+        out["nu=%g" % nu] = rec
+        del march
+    return out
+
+
 def c1_record(n=16, p=1, nu=1e-4, tol=1e-10, steps=20):
     """The C1 problem (1+1D, (0,1)^2 as n x n quads -> 2 n^2 triangles, p = 1,
     a = 1, manufactured u = sin 2 pi (x - t) e^-t, 1,536 free DOFs at n = 16):
@@ -1138,6 +1172,9 @@ def main():
     if not args.no_march:
         out["slab_march"] = march_record(args)
         log("bench: march done")
+        pool_trim()
+        out["c4_precision"] = c4_record(args)
+        log("bench: C4 done")
         pool_trim()
     if not args.no_large:
         out["c5_adjoint"] = c5_adjoint(args.tol)

@@ -951,8 +951,7 @@ __global__ void k_cast32(int64_t n, const double* __restrict__ a, float* __restr
   if (i < n) b[i] = (float)a[i];
 }
 
-// Dense copy of the coarsest matrix and its inverse by Gauss-Jordan with
-// partial pivoting in one workgroup.
+// Dense copy of the coarsest matrix.
 __global__ void k_dense(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                         const double* __restrict__ v, double* __restrict__ M) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -960,68 +959,80 @@ __global__ void k_dense(int64_t n, const int64_t* __restrict__ rp, const int32_t
   for (int64_t k = rp[i]; k < rp[i + 1]; ++k) M[i * n + ci[k]] = v[k];
 }
 
-__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M, double* __restrict__ Inv,
-                                                       int* __restrict__ err) {
+// Gauss-Jordan with partial pivoting on [M | Inv] over many workgroups, one
+// column c per pair of launches (within one workgroup the n^3 updates of a
+// few hundred rows take tens of milliseconds on one compute unit).
+// k_gj_pivot (one workgroup): pivot search in column c (largest |M[r][c]|,
+// r >= c, smallest row on ties), row swap,
+// scaling of the pivot row, and the multipliers f[r] = M[r][c] (f[c] = 0).
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int c, double* __restrict__ M, double* __restrict__ Inv,
+                                                   double* __restrict__ f, int* __restrict__ err) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
   __shared__ int s_p;
   const int t = threadIdx.x;
-  for (int k = t; k < n * n; k += blockDim.x) Inv[k] = (k / n == k % n) ? 1.0 : 0.0;
+  double best = -1.0;
+  int bi = n;
+  for (int r = c + t; r < n; r += blockDim.x) {
+    const double a = fabs(M[(int64_t)r * n + c]);
+    if (a > best) { best = a; bi = r; }
+  }
+  sv[t] = best;
+  si[t] = bi;
   __syncthreads();
-  for (int c = 0; c < n; ++c) {
-    double best = -1.0;
-    int bi = n;
-    for (int r = c + t; r < n; r += blockDim.x) {
-      double a = fabs(M[(int64_t)r * n + c]);
-      if (a > best) { best = a; bi = r; }
-    }
-    sv[t] = best;
-    si[t] = bi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (t < s && (sv[t + s] > sv[t] || (sv[t + s] == sv[t] && si[t + s] < si[t]))) {
-        sv[t] = sv[t + s];
-        si[t] = si[t + s];
-      }
-      __syncthreads();
-    }
-    if (t == 0) {
-      s_p = si[0];
-      if (!(sv[0] > 0.0)) atomicOr(err, 1);
-    }
-    __syncthreads();
-    const int p = s_p;
-    if (p != c)
-      for (int j = t; j < n; j += blockDim.x) {
-        double x = M[(int64_t)c * n + j]; M[(int64_t)c * n + j] = M[(int64_t)p * n + j]; M[(int64_t)p * n + j] = x;
-        x = Inv[(int64_t)c * n + j]; Inv[(int64_t)c * n + j] = Inv[(int64_t)p * n + j]; Inv[(int64_t)p * n + j] = x;
-      }
-    __syncthreads();
-    double d = M[(int64_t)c * n + c];
-    if (d == 0.0) d = 1.0;
-    __syncthreads();
-    for (int j = t; j < n; j += blockDim.x) {
-      M[(int64_t)c * n + j] /= d;
-      Inv[(int64_t)c * n + j] /= d;
-    }
-    __syncthreads();
-    for (int64_t idx = t; idx < (int64_t)n * n; idx += blockDim.x) {
-      int r = (int)(idx / n), j = (int)(idx % n);
-      if (r == c) continue;
-      double f = M[(int64_t)r * n + c];
-      if (j == c) continue;
-      M[(int64_t)r * n + j] -= f * M[(int64_t)c * n + j];
-      Inv[(int64_t)r * n + j] -= f * Inv[(int64_t)c * n + j];
-    }
-    __syncthreads();
-    for (int r = t; r < n; r += blockDim.x) {
-      if (r == c) continue;
-      double f = M[(int64_t)r * n + c];
-      Inv[(int64_t)r * n + c] -= f * Inv[(int64_t)c * n + c];
-      M[(int64_t)r * n + c] = 0.0;
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s && (sv[t + s] > sv[t] || (sv[t + s] == sv[t] && si[t + s] < si[t]))) {
+      sv[t] = sv[t + s];
+      si[t] = si[t + s];
     }
     __syncthreads();
   }
+  if (t == 0) {
+    s_p = si[0];
+    if (!(sv[0] > 0.0)) atomicOr(err, 1);
+  }
+  __syncthreads();
+  const int p = s_p;
+  if (p != c)
+    for (int j = t; j < n; j += blockDim.x) {
+      double x = M[(int64_t)c * n + j]; M[(int64_t)c * n + j] = M[(int64_t)p * n + j]; M[(int64_t)p * n + j] = x;
+      x = Inv[(int64_t)c * n + j]; Inv[(int64_t)c * n + j] = Inv[(int64_t)p * n + j]; Inv[(int64_t)p * n + j] = x;
+    }
+  __syncthreads();
+  double d = M[(int64_t)c * n + c];
+  if (d == 0.0) d = 1.0;
+  __syncthreads();
+  for (int j = t; j < n; j += blockDim.x) {
+    M[(int64_t)c * n + j] /= d;
+    Inv[(int64_t)c * n + j] /= d;
+  }
+  for (int r = t; r < n; r += blockDim.x) f[r] = r == c ? 0.0 : M[(int64_t)r * n + c];
+}
+
+// Elimination of column c from every other row, a thread per entry of
+// [M | Inv]: M[r][j] -= f[r] M[c][j] (j > c; M[r][c] = 0; the columns left
+// of c hold zeros in the pivot row), Inv[r][j] -= f[r] Inv[c][j].
+__global__ __launch_bounds__(256) void k_gj_update(int n, int c, double* __restrict__ M, double* __restrict__ Inv,
+                                                   const double* __restrict__ f) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = 2 * (int64_t)n;
+  if (idx >= (int64_t)n * w) return;
+  const int r = (int)(idx / w), jj = (int)(idx % w);
+  if (r == c) return;
+  const double fr = f[r];
+  if (jj < n) {
+    if (jj > c) M[(int64_t)r * n + jj] -= fr * M[(int64_t)c * n + jj];
+    else if (jj == c) M[(int64_t)r * n + c] = 0.0;
+  } else {
+    const int j = jj - n;
+    Inv[(int64_t)r * n + j] -= fr * Inv[(int64_t)c * n + j];
+  }
+}
+
+// Identity of order n.
+__global__ void k_eye(int n, double* __restrict__ Inv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (int64_t)n * n) Inv[k] = (k / n == k % n) ? 1.0 : 0.0;
 }
 
 // Inverse of a dense matrix of order n <= 64 by Gauss-Jordan elimination
@@ -1980,8 +1991,17 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       hipLaunchKernelGGL(k_inv_gj, dim3(1), dim3(256), 0, st, (int)nL, M, h->cinv, d_int + 2);
     else if (nL <= INV_LDS_MAX)
       hipLaunchKernelGGL(k_inv_lds, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
-    else
-      hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, (int)nL, M, h->cinv, d_int + 2);
+    else {
+      // many workgroups per column (one workgroup took about 90 ms at
+      // n = 480, a stalled coarsening of a pure-advection slab)
+      double* fcol = nullptr;
+      CK(tmp.get(&fcol, nL));
+      hipLaunchKernelGGL(k_eye, g1(nL * nL), dim3(256), 0, st, (int)nL, h->cinv);
+      for (int c = 0; c < (int)nL; ++c) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, (int)nL, c, M, h->cinv, fcol, d_int + 2);
+        hipLaunchKernelGGL(k_gj_update, g1(2 * nL * nL), dim3(256), 0, st, (int)nL, c, M, h->cinv, fcol);
+      }
+    }
     CKH(hipGetLastError());
   }
   if (prm.adjoint && !h->lev[0].ATptr && !h->lev[0].otval) {

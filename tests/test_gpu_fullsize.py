@@ -440,3 +440,34 @@ def test_c3_full_size_block_air_headline(c3_mesh):
     assert _true_residual(s, x) <= 1e-8
     assert _true_residual(s, x32) <= 1e-8
     _block_air_level0_sampled(H, 3, 0.25)
+
+
+@pytest.mark.parametrize("nu", [0.0, 1e-4])
+def test_c4_fp32_cycle_full_slab_vs_oracle(nu):
+    """The precision form on the C2 slab shape (342,528 DOFs) at nu = 0 and
+    1e-4: the FP32-cycle solution at tol 1e-10 against the FP64 oracle's
+    solution (1e-8), the FP64 one at 1e-12 (1e-10), and the iteration
+    counts of the two cycles at 1e-8."""
+    from paper_2010_11130_amd import Hierarchy
+    from workloads import slab_prism_tet_mesh
+    from workloads.problems import slab_hill
+    print("case C4 full slab, nu", nu, flush=True)
+    v, c = slab_prism_tet_mesh(64, 1.0 / 64)
+    prob = slab_hill(nu)
+    m, fv, bf, kinds = _mesh(v, c)
+    s = _system(m, v, fv, bf, kinds, prob, 2)
+    H = Hierarchy(s, fp32_cycle=1)
+    x64, i64 = H.solve(tol=1e-12)
+    x32, i32 = H.solve(tol=1e-10, precision=1)
+    _, j64 = H.solve(tol=1e-8)
+    _, j32 = H.solve(tol=1e-8, precision=1)
+    assert i64["converged"] and i32["converged"]
+    o = setup_problem(v, c, prob, 2)
+    xo, _ = air_fgmres_solve(o, tol=1e-12, hier=oair.setup(o.Shat))
+    e64 = np.linalg.norm(x64.cpu().numpy() - xo) / np.linalg.norm(xo)
+    e32 = np.linalg.norm(x32.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print("iterations to 1e-8: FP64 %d, FP32 cycle %d; error vs oracle: FP64 %.2e, FP32 cycle %.2e"
+          % (j64["iters"], j32["iters"], e64, e32), flush=True)
+    assert e64 <= 1e-10
+    assert e32 <= 1e-8
+    assert abs(j32["iters"] - j64["iters"]) <= 2

@@ -499,3 +499,25 @@ def test_lair_distance_bad_parameter(built):
     g, _, _ = built("c1")
     with pytest.raises(AirHdgError):
         Hierarchy(g, lair_distance=3)
+
+
+def test_coarsest_large_many_workgroup_inverse():
+    """A coarsest level above the LDS sizes (the stalled coarsening of a
+    pure-advection slab, max_coarse large): the dense inverse by
+    Gauss-Jordan over many workgroups, one cycle against the oracle."""
+    from paper_2010_11130_amd import Hierarchy
+    v, c, prob, p = case("slab")
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=1500)
+    OH = oair.setup(o.Shat, max_coarse=1500)
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    print("coarsest", H.info["n"][-1], flush=True)
+    assert H.info["n"][-1] > 128
+    r = np.random.default_rng(3).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    x, info = H.solve(tol=1e-12)
+    xo, _ = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
