@@ -415,7 +415,9 @@ def setup_warm_solve(s, tol, precision=0, method=0, **air):
 
 def c3_variants(c3, tol, x64, air):
     """Setup + warm solve of other settings on the same 96^3 workload, with
-    the headline's level-0 coarsening ``air``: strength threshold 0.5,
+    the headline's level-0 coarsening ``air``: strength threshold 0.5 (also
+    with 0.25 for the restriction neighbourhoods, FP64 and FP32 cycle), the
+    Section 4 thresholds (0.2 for the coarsening, 0.3 for the restriction),
     BiCGSTAB (the paper's Krylov method), the ordered Gauss-Seidel
     relaxations of Lemma 3.1 (relax 2: all points in flow order; relax 3: F
     points then all points, the Section 4 schedule), FP64 and FP32 cycles,
@@ -428,7 +430,11 @@ def c3_variants(c3, tol, x64, air):
     other = {} if air else {"block_air": 1}
     oname = "scalar" if air else "block"
     out = {}
-    for key, prec, kw in (("theta_0.5", 0, {"theta": 0.5}), ("bicgstab", 0, {"method": 1}),
+    for key, prec, kw in (("theta_0.5", 0, {"theta": 0.5}),
+                          ("theta_0.5_theta_r_0.25", 0, {"theta": 0.5, "theta_r": 0.25}),
+                          ("theta_0.5_theta_r_0.25_fp32_cycle", 1, {"theta": 0.5, "theta_r": 0.25}),
+                          ("section4_theta_0.2_theta_r_0.3", 0, {"theta": 0.2, "theta_r": 0.3}),
+                          ("bicgstab", 0, {"method": 1}),
                           ("ordered_relax2", 0, {"relax": 2}), ("ordered_relax2_fp32_cycle", 1, {"relax": 2}),
                           ("ordered_relax3", 0, {"relax": 3}),
                           (oname + "_ordered_relax2", 0, dict(other, relax=2))):
