@@ -531,9 +531,10 @@ def c5_adjoint(tol):
     nu = 1e-3: assembly with the element data kept, lAIR setup with the
     transposed operators, the forward FGMRES solve, the adjoint solve of the
     misfit J = |Lambda|^2 / 2 and the gradients with respect to the source
-    values and nu; FP64 and FP32 cycles, and FP64 with strength threshold
-    0.5 (the facet couplings are diffusion-dominated here: tau = nu alpha /
-    h_K exceeds |a|)."""
+    values and nu; FP64 and FP32 cycles, and with strength threshold 0.5
+    for the coarsening (also with 0.25 for the restriction neighbourhoods):
+    the facet couplings are diffusion-dominated here (tau = nu alpha / h_K
+    exceeds |a|)."""
     import torch
     from paper_2010_11130_amd import System, Hierarchy, source_gauss
     from workloads import kuhn_cube_mesh, map_vertices_c5
@@ -551,10 +552,13 @@ def c5_adjoint(tol):
     torch.cuda.synchronize()
     out["assemble_ms"] = 1e3 * (time.perf_counter() - t0)
     out["free_dofs"] = s.n
-    for prec, theta, key in ((0, 0.25, "fp64"), (1, 0.25, "fp32_cycle"), (0, 0.5, "fp64_theta_0.5")):
+    for prec, theta, theta_r, key in ((0, 0.25, 0.0, "fp64"), (1, 0.25, 0.0, "fp32_cycle"),
+                                      (0, 0.5, 0.0, "fp64_theta_0.5"),
+                                      (0, 0.5, 0.25, "fp64_theta_0.5_theta_r_0.25"),
+                                      (1, 0.5, 0.25, "fp32_cycle_theta_0.5_theta_r_0.25")):
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        h = Hierarchy(s, adjoint=1, fp32_cycle=prec, theta=theta)
+        h = Hierarchy(s, adjoint=1, fp32_cycle=prec, theta=theta, theta_r=theta_r)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         # a first forward and adjoint solve allocate the FGMRES basis
