@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # kernels timed with HIP events inside the library (ah_profile_*)
-PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "rap0",
-                "arnoldi_dot", "arnoldi_update"]
+PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "relax1_f", "relax1_c",
+                "relax1_f_f32", "relax1_c_f32", "rap0", "arnoldi_dot", "arnoldi_update"]
 METRIC = "DOF/s to 1e-8 rel. residual (setup+solve), FP32 vs FP64 V-cycle; HBM GB/s"
 
 
@@ -185,6 +185,10 @@ KERNEL_SOURCES = {"element": "paper_2010_11130_amd/csrc/assemble.hip",
                   "relax0_c": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax0_f_f32": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax0_c_f32": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax1_f": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax1_c": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax1_f_f32": "paper_2010_11130_amd/csrc/solve.hip",
+                  "relax1_c_f32": "paper_2010_11130_amd/csrc/solve.hip",
                   "arnoldi_dot": "paper_2010_11130_amd/csrc/solve.hip",
                   "arnoldi_update": "paper_2010_11130_amd/csrc/solve.hip",
                   "rap0": "paper_2010_11130_amd/csrc/setup.hip"}

@@ -261,6 +261,12 @@ typedef struct {
   int64_t n_fallback;  /* lAIR rows that fell back to injection */
   double op_complexity;
   double t_setup_ms;
+  int64_t block_view_values;  /* values of level 1 read by full blocks in
+                                 its F and C sweeps (block AIR, level 1 swept
+                                 from its point lists): its CSR entries plus
+                                 the zero fill of block rows whose rows do
+                                 not share one block pattern; 0 where level 1
+                                 is swept by CSR rows */
 } ah_setup_info;
 
 /* Environment (read by air_setup; for tests and tuning): AH_TAIL_MAX (rows,

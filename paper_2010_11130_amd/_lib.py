@@ -31,7 +31,8 @@ class AirParams(C.Structure):
 
 class SetupInfo(C.Structure):
     _fields_ = [("levels", C.c_int), ("n", C.c_int64 * 32), ("nnz", C.c_int64 * 32),
-                ("n_fallback", C.c_int64), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double)]
+                ("n_fallback", C.c_int64), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
+                ("block_view_values", C.c_int64)]
 
 
 class SolveParams(C.Structure):

@@ -287,7 +287,8 @@ class Hierarchy:
         self.h = h
         self.info = {"levels": info.levels, "n": list(info.n[:info.levels]),
                      "nnz": list(info.nnz[:info.levels]), "n_fallback": info.n_fallback,
-                     "op_complexity": info.op_complexity, "t_setup_ms": info.t_setup_ms}
+                     "op_complexity": info.op_complexity, "t_setup_ms": info.t_setup_ms,
+                     "block_view_values": info.block_view_values}
 
     def __del__(self, _destroy=destroy):
         if getattr(self, "h", None):

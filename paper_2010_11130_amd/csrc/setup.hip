@@ -1576,6 +1576,192 @@ static void rs_first_pass_host(int64_t n, const std::vector<int64_t>& rp, const 
 
 ah_hier::~ah_hier() { arena.release(); }
 
+// A CSR operator whose rows come in groups of B (block rows) read by the
+// sweeps as full b x b blocks: block row I holds the distinct column blocks
+// J (column / B) of its B rows; row m stores, per block s, the B values of
+// columns J_s B + c at (m nb_I + s) B + c from the block row's value base.
+// A block row is regular when its B rows have the same length, a multiple
+// of B, and entry t of every row has column J B + t mod B with J the block
+// of entry t - t mod B of the first row: then its CSR values are already in
+// that layout, and the base is the CSR offset of its first row.  Other block
+// rows get their blocks in a side array, in the order a merge of the rows
+// meets them, zero where a row has no entry (every entry lands in exactly
+// one slot, so a row's sum is its CSR sum); their base is stored as ~offset.
+// One thread per block row.
+template <int B>
+__device__ __forceinline__ int32_t bfull_next(const int64_t* p, const int64_t* e, const int32_t* __restrict__ ci) {
+  int32_t J = 0x7fffffff;
+#pragma unroll
+  for (int q = 0; q < B; ++q)
+    if (p[q] < e[q]) J = min(J, ci[p[q]] / B);
+  return J;
+}
+
+template <int B>
+__device__ bool bfull_regular(const int64_t* p, const int64_t* e, const int32_t* __restrict__ ci) {
+  const int64_t len = e[0] - p[0];
+  if (len % B) return false;
+#pragma unroll
+  for (int q = 1; q < B; ++q)
+    if (e[q] - p[q] != len) return false;
+  for (int64_t t = 0; t < len; ++t) {
+    const int32_t J = ci[p[0] + t - t % B] / B;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (ci[p[q] + t] != J * B + (int32_t)(t % B)) return false;
+  }
+  return true;
+}
+
+// Blocks of each block row (cnt), of which in the side array (acnt: all of
+// an irregular block row's, none of a regular one's).
+template <int B>
+__global__ void k_bfull_count(int64_t nbr, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              int64_t* __restrict__ cnt, int64_t* __restrict__ acnt) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nbr) return;
+  int64_t p[B], e[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) { p[q] = rp[I * B + q]; e[q] = rp[I * B + q + 1]; }
+  if (bfull_regular<B>(p, e, ci)) {
+    cnt[I] = (e[0] - p[0]) / B;
+    acnt[I] = 0;
+    return;
+  }
+  int64_t c = 0;
+  for (int32_t J = bfull_next<B>(p, e, ci); J != 0x7fffffff; J = bfull_next<B>(p, e, ci)) {
+    ++c;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      while (p[q] < e[q] && ci[p[q]] / B == J) ++p[q];
+  }
+  cnt[I] = c;
+  acnt[I] = c;
+}
+
+// Block columns and value bases of every block row; the side-array blocks
+// of the irregular ones.
+template <int B>
+__global__ void k_bfull_fill(int64_t nbr, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const double* __restrict__ v, const int64_t* __restrict__ bptr,
+                             const int64_t* __restrict__ aptr, int32_t* __restrict__ bcol,
+                             int64_t* __restrict__ voff, double* __restrict__ aux) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nbr) return;
+  int64_t p[B], e[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) { p[q] = rp[I * B + q]; e[q] = rp[I * B + q + 1]; }
+  const int64_t o0 = bptr[I];
+  const int64_t nb = bptr[I + 1] - o0;
+  const int64_t a0 = aptr[I];
+  if (aptr[I + 1] == a0) {     // regular (or empty): values in place
+    for (int64_t s = 0; s < nb; ++s) bcol[o0 + s] = ci[p[0] + s * B] / B;
+    voff[I] = p[0];
+    return;
+  }
+  voff[I] = ~(a0 * (B * B));
+  double* __restrict__ vb = aux + a0 * (B * B);
+  int64_t s = 0;
+  for (int32_t J = bfull_next<B>(p, e, ci); J != 0x7fffffff && s < nb; J = bfull_next<B>(p, e, ci), ++s) {
+    bcol[o0 + s] = J;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      double* __restrict__ w = vb + (q * nb + s) * B;
+#pragma unroll
+      for (int c = 0; c < B; ++c) w[c] = 0.0;
+      while (p[q] < e[q] && ci[p[q]] / B == J) {
+        w[ci[p[q]] - J * B] = v[p[q]];
+        ++p[q];
+      }
+    }
+  }
+}
+
+// The full-block view of level l (block size B) for its F and C sweeps, if
+// it stores at most 1.25 times the CSR entries; otherwise the level keeps
+// the CSR sweeps.  Also the F rows' stored values (sweep byte counts) and
+// the FP32 side array for the FP32 cycle.
+static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st) {
+  AhLevel& L = h->lev[l];
+  const int64_t nbr = L.n / B;
+  if (nbr == 0 || nbr * B != L.n || !L.flist || (B != 2 && B != 3 && B != 6)) return AH_OK;
+  Arena tmp;
+  tmp.stream = st;
+  int64_t *cnt = nullptr, *acnt = nullptr, *bptr = nullptr, *aptr = nullptr, *voff = nullptr;
+  unsigned long long* d_cnt = nullptr;
+  ah_status rc = tmp.get(&cnt, nbr);
+  if (rc == AH_OK) rc = tmp.get(&acnt, nbr);
+  if (rc == AH_OK) rc = tmp.get(&aptr, nbr + 1);
+  if (rc == AH_OK) rc = tmp.get(&d_cnt, 1);
+  if (rc == AH_OK) rc = h->arena.get(&bptr, nbr + 1);
+  if (rc == AH_OK) rc = h->arena.get(&voff, nbr);
+  if (rc < 0) { tmp.release(); return rc; }
+  switch (B) {
+    case 2: hipLaunchKernelGGL(k_bfull_count<2>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+    case 3: hipLaunchKernelGGL(k_bfull_count<3>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+    default: hipLaunchKernelGGL(k_bfull_count<6>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+  }
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: block view count"); return AH_EHIP; }
+  rc = scan_i64(cnt, bptr, nbr, st, tmp);
+  if (rc == AH_OK) rc = scan_i64(acnt, aptr, nbr, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  double* pin = pinned_scratch(2);
+  if (!pin) { tmp.release(); set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  if (hipMemcpyAsync(pin, bptr + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(pin + 1, aptr + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    tmp.release();
+    set_error("air_setup: block view count readback");
+    return AH_EHIP;
+  }
+  int64_t tot[2] = {0, 0};
+  std::memcpy(tot, pin, sizeof(tot));
+  const int64_t nv = tot[0] * B * B, na = tot[1] * B * B;
+  if ((double)nv > 1.25 * (double)L.nnz) { tmp.release(); return AH_OK; }
+  int32_t* bcol = nullptr;
+  double* aux = nullptr;
+  rc = h->arena.get(&bcol, std::max<int64_t>(tot[0], 1));
+  if (rc == AH_OK) rc = h->arena.get(&aux, std::max<int64_t>(na, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  switch (B) {
+    case 2: hipLaunchKernelGGL(k_bfull_fill<2>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, L.val, bptr, aptr, bcol, voff, aux); break;
+    case 3: hipLaunchKernelGGL(k_bfull_fill<3>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, L.val, bptr, aptr, bcol, voff, aux); break;
+    default: hipLaunchKernelGGL(k_bfull_fill<6>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, L.val, bptr, aptr, bcol, voff, aux); break;
+  }
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: block view fill"); return AH_EHIP; }
+  if (h->prm.fp32_cycle) {
+    rc = h->arena.get(&L.baux32, std::max<int64_t>(na, 1));
+    if (rc < 0) { tmp.release(); return rc; }
+    if (na > 0) hipLaunchKernelGGL(k_cast32, g1(na), dim3(256), 0, st, na, aux, L.baux32);
+  }
+  const int64_t nF = L.n - L.nc;
+  if (hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), st) != hipSuccess) {
+    tmp.release();
+    set_error("air_setup: block view counts");
+    return AH_EHIP;
+  }
+  if (nF > 0) hipLaunchKernelGGL(k_list_vals, grows(nF), dim3(256), 0, st, nF, L.flist, bptr, B, d_cnt);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(pin, d_cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    tmp.release();
+    set_error("air_setup: block view readback");
+    return AH_EHIP;
+  }
+  tmp.release();
+  unsigned long long nvF = 0;
+  std::memcpy(&nvF, pin, sizeof(nvF));
+  L.bb = B;
+  L.nbv = nv;
+  L.nbvF = (int64_t)nvF;
+  L.nbaux = na;
+  L.bptr = bptr;
+  L.bcol = bcol;
+  L.bvoff = voff;
+  L.baux = aux;
+  return AH_OK;
+}
+
 extern "C" void ah_air_defaults(ah_air_params* p) {
   if (!p) return;
   p->theta = 0.25;
@@ -2061,6 +2247,17 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     if (const char* e = std::getenv("AH_LIST_MIN")) h->list_min = std::atoll(e);
     if (h->g0 != 2 && h->g0 != 4 && h->g0 != 8 && h->g0 != 16 && h->g0 != 32) h->g0 = 0;
     const int nl = (int)h->lev.size();
+    // level 1 under block AIR: R A P with P = P_b (x) I and block lAIR rows
+    // is made of ob x ob blocks; its F and C sweeps (list sweeps, not the
+    // coarsest level) read it by full blocks (one column index per block)
+    bool l1b = true;
+    if (const char* e = std::getenv("AH_L1B")) l1b = std::atoi(e) != 0;
+    if (l1b && nl > 2 && h->lev[0].fblk && h->lev[1].n >= h->list_min) {
+      ProfScope ps;
+      prof_begin(ps, "view1", st, 0.0);
+      CK(block_view_build(h, 1, h->lev[0].ob, st));
+      prof_end(ps);
+    }
     std::vector<TailLevel> tl(nl);
     for (int l = 0; l < nl; ++l) {
       const AhLevel& L = h->lev[l];
@@ -2142,6 +2339,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     }
     info->n_fallback = h->nfallback;
     info->op_complexity = h->lev[0].nnz ? tot / (double)h->lev[0].nnz : 0.0;
+    info->block_view_values = h->lev.size() > 1 ? h->lev[1].nbv : 0;
     info->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   *out = h;

@@ -160,6 +160,54 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
   }
 }
 
+// A coarse level read by full blocks (every block of block row R, the
+// diagonal one included; row m of R at (m nb + s) B + c from the block row's
+// value base: voff[R] into the CSR values av where voff[R] >= 0, else ~voff[R]
+// into the side array ax): the Jacobi sweep of SP_SWEEP_LIST on the listed
+// rows, with the row sums of k_fb and the diagonal d of k_csr.
+template <class TA, class TX, class TY, int B, int G>
+__global__ __launch_bounds__(256) void k_fbd(int64_t n, const int32_t* __restrict__ list,
+                                             const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
+                                             const int64_t* __restrict__ voff, const TA* __restrict__ av,
+                                             const TA* __restrict__ ax, const TX* __restrict__ x,
+                                             const TY* __restrict__ b, const TY* __restrict__ d, TY omega,
+                                             TY* __restrict__ y, TY* __restrict__ y2) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ii = gid / G;
+  const int g = (int)(gid % G);
+  if (ii >= n) return;
+  const int64_t i = list[ii];
+  const int64_t R = i / B;
+  const int m = (int)(i - R * B);
+  const int64_t o0 = bptr[R];
+  const int len = (int)(bptr[R + 1] - o0) * B;
+  const int64_t vo = voff[R];
+  const TA* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * len;
+  const int32_t* __restrict__ cb = bcol + o0;
+  TY acc = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  int e = g;
+  for (; e + 3 * G < len; e += 4 * G) {
+    const int e1 = e + G, e2 = e + 2 * G, e3 = e + 3 * G;
+    const int64_t c0 = (int64_t)cb[e / B] * B + e % B, c1 = (int64_t)cb[e1 / B] * B + e1 % B;
+    const int64_t c2 = (int64_t)cb[e2 / B] * B + e2 % B, c3 = (int64_t)cb[e3 / B] * B + e3 % B;
+    const TY a0 = (TY)v[e], a1 = (TY)v[e1], a2 = (TY)v[e2], a3 = (TY)v[e3];
+    acc += a0 * (TY)x[c0];
+    acc1 += a1 * (TY)x[c1];
+    acc2 += a2 * (TY)x[c2];
+    acc3 += a3 * (TY)x[c3];
+  }
+  for (; e < len; e += G) acc += (TY)v[e] * (TY)x[(int64_t)cb[e / B] * B + e % B];
+  acc += (acc1 + acc2) + acc3;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (g != 0) return;
+  TY xi = (TY)x[i];
+  const TY di = d[i];
+  if (fabs((double)di) >= 1e-30) xi += omega * (b[i] - acc) / di;
+  if (y2) y2[i] = xi;
+  y[i] = xi;
+}
+
 // The same operator by facet block rows: LPB lanes per block row R, a lane
 // per off-diagonal block s of the row (s = g, g + LPB, ...).  A lane reads
 // the block's column index once, its B values of x once, and the B x B
@@ -1182,6 +1230,34 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
   return AH_OK;
 }
 
+// Sweep of the listed rows of a level read by full blocks (k_fbd); av the
+// level's CSR values, ax its side array, in the cycle's precision.
+template <class T>
+static ah_status fbd_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
+                       const T* b, const T* d, T omega, T* y, hipStream_t st, const char* tag, double bytes,
+                       T* y2 = nullptr) {
+  if (n == 0) return AH_OK;
+  const int G = fb_lanes(L.nbv, L.n);
+  ProfScope ps;
+  prof_begin(ps, tag, st, bytes);
+  const dim3 grid((unsigned)cdiv(n * G, 256));
+#define FBD(BB, GG) hipLaunchKernelGGL((k_fbd<T, T, T, BB, GG>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, \
+                                       L.bvoff, av, ax, x, b, d, omega, y, y2)
+#define FBD_G(BB) switch (G) { case 2: FBD(BB, 2); break; case 4: FBD(BB, 4); break; case 8: FBD(BB, 8); break; \
+                               default: FBD(BB, 16); break; }
+  switch (L.bb) {
+    case 2: FBD_G(2); break;
+    case 3: FBD_G(3); break;
+    case 6: FBD_G(6); break;
+    default: prof_end(ps); set_error("unsupported block size %d", L.bb); return AH_EUNSUPPORTED;
+  }
+#undef FBD_G
+#undef FBD
+  prof_end(ps);
+  AH_LAUNCHED();
+  return AH_OK;
+}
+
 // Lanes per block row of k_fbb from the mean number of off-diagonal blocks
 // per block row (C3: 6 -> 8 lanes).
 static int fbb_lanes(int64_t nvals, int64_t n, int B) {
@@ -1265,6 +1341,18 @@ static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
          (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 3.0 : 2.0) * w;
 }
 
+// The same for a sweep of a coarse level read by full blocks: the X rows'
+// values, every block column index and block-row offset and value base, the list,
+// x once, b and d on X, the X updates written (twice with a second output).
+template <class T>
+static double fbd_sweep_bytes(const AhLevel& L, int X, bool y2) {
+  const double w = sizeof(T);
+  const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
+  const int64_t nvX = X == 0 ? L.nbvF : L.nbv - L.nbvF;
+  return (double)nvX * w + (double)(L.nbv / (L.bb * L.bb)) * 4.0 + (double)(L.n / L.bb) * 16.0 + 8.0 +
+         (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 4.0 : 3.0) * w;
+}
+
 ah_status tail_image_build(ah_hier* h, hipStream_t st) {
   if (!h->tail_lds || h->tail0 < 0) return AH_OK;
   const int nlev = (int)h->lev.size();
@@ -1311,6 +1399,7 @@ struct Ops<double> {
   static const double* d(const AhLevel& L) { return L.diag; }
   static const double* O(const AhLevel& L) { return L.oval; }
   static const double* OT(const AhLevel& L) { return L.otval; }
+  static const double* BX(const AhLevel& L) { return L.baux; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -1325,6 +1414,7 @@ struct Ops<float> {
   static const float* d(const AhLevel& L) { return L.diag32; }
   static const float* O(const AhLevel& L) { return L.oval32; }
   static const float* OT(const AhLevel& L) { return L.otval32; }
+  static const float* BX(const AhLevel& L) { return L.baux32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -1509,8 +1599,10 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
   AH_LAUNCHED();
   // level-0 timing tags, one per sweep kernel and grid (coarse levels: none)
-  const char* tf = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32";
-  const char* tc = l > 0 ? nullptr : sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32";
+  const char* tf = l == 0 ? (sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32")
+                   : l == 1 ? (sizeof(T) == 8 ? "relax1_f" : "relax1_f_f32") : nullptr;
+  const char* tc = l == 0 ? (sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32")
+                   : l == 1 ? (sizeof(T) == 8 ? "relax1_c" : "relax1_c_f32") : nullptr;
   if (l == 0 && L.ob && Ops<T>::O(L)) {
     const T* ov = Ops<T>::O(L);
     AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF, ov, x, b, om, y, st, tf, fb_sweep_bytes<T>(L, 0, false),
@@ -1520,6 +1612,17 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                                      L.flist, out)));
     AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, L.nc, ov, x, b, om, out, st, tc, fb_sweep_bytes<T>(L, 1, false),
                                      L.clist)));
+    return AH_OK;
+  }
+  if (l > 0 && L.bb && Ops<T>::A(L) && Ops<T>::BX(L)) {
+    // level 1 under block AIR: the sweeps read it by full blocks
+    const T* av = Ops<T>::A(L);
+    const T* ax = Ops<T>::BX(L);
+    const T* d = Ops<T>::d(L);
+    AH_TRY(fbd_g<T>(L, av, ax, nF, L.flist, x, b, d, om, y, st, tf, fbd_sweep_bytes<T>(L, 0, false)));
+    if (nsw == 1) return AH_OK;
+    AH_TRY(fbd_g<T>(L, av, ax, nF, L.flist, y, b, d, om, x, st, tf, fbd_sweep_bytes<T>(L, 0, true), out));
+    AH_TRY(fbd_g<T>(L, av, ax, L.nc, L.clist, x, b, d, om, out, st, tc, fbd_sweep_bytes<T>(L, 1, false)));
     return AH_OK;
   }
   AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,

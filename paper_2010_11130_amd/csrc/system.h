@@ -90,6 +90,20 @@ struct AhLevel {
   // holds the transpose of block (J, I); null where the CSR A^T is used
   double* otval = nullptr;
   float* otval32 = nullptr;
+  // a coarse level made of ob x ob blocks (level 1 under block AIR) read by
+  // full blocks: block row R has bptr[R + 1] - bptr[R] blocks with column
+  // blocks bcol[bptr[R] ..], row m's values at (m nb + s) bb + c from base
+  // bvoff[R] of the CSR values (val / val32) where bvoff[R] >= 0, else from
+  // ~bvoff[R] of baux / baux32 (zero-filled blocks); bb = 0 where not built
+  int bb = 0;
+  int64_t nbv = 0;             // stored values
+  int64_t nbvF = 0;            // of which in F rows
+  int64_t nbaux = 0;           // of which in the side array
+  const int64_t* bptr = nullptr;
+  const int32_t* bcol = nullptr;
+  const int64_t* bvoff = nullptr;
+  const double* baux = nullptr;
+  float* baux32 = nullptr;
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;

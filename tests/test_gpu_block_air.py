@@ -135,3 +135,62 @@ def test_block_air_adjoint_solve(precision):
     assert ainfo["converged"]
     adj_o = oadj.adjoint_direct(o, direct_solve(o) - target)
     assert np.linalg.norm(adj.cpu().numpy() - adj_o) <= 1e-9 * np.linalg.norm(adj_o)
+
+
+@pytest.fixture
+def level1_lists(monkeypatch):
+    """Coarse levels swept from their F and C lists at any size and no
+    single-workgroup tail, so level 1 of the small cases takes the sweeps of
+    the large ones (read by full blocks under block AIR)."""
+    monkeypatch.setenv("AH_LIST_MIN", "0")
+    monkeypatch.setenv("AH_TAIL_MAX", "0")
+
+
+@pytest.mark.parametrize("name", ["kuhn_nu4", "c5", "slab"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_block_air_level1_full_block_sweeps(level1_lists, monkeypatch, name, fp32):
+    """Level 1 under block AIR is made of b x b blocks; its sweeps read it by
+    full blocks (one column index per block; the CSR values in place where
+    the rows of a block row share one block pattern, a zero-filled side array
+    elsewhere).  One V-cycle
+    against the oracle's (FP64 1e-10; FP32 within 4x the oracle's FP32
+    emulation), the same cycle with the copy switched off (AH_L1B=0, the CSR
+    sweeps) to 1e-13 in FP64, and the solution and iteration count against
+    the oracle's solve."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, fp32, flush=True)
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    prec = 1 if fp32 else 0
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, fp32_cycle=prec)
+    assert H.info["levels"] > 2
+    nnz1 = H.info["nnz"][1]
+    assert nnz1 <= H.info["block_view_values"] <= 1.25 * nnz1, (H.info["block_view_values"], nnz1)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b)
+    r = np.random.default_rng(7).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda"), precision=prec).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    monkeypatch.setenv("AH_L1B", "0")
+    Hc = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, fp32_cycle=prec)
+    assert Hc.info["block_view_values"] == 0
+    zc = Hc.vcycle(torch.as_tensor(r, device="cuda"), precision=prec).cpu().numpy()
+    if fp32:
+        z32 = oair.vcycle(OH, r, dtype=np.float32)
+        err32 = np.linalg.norm(z32.astype(np.float64) - zo) / np.linalg.norm(zo)
+        print("fp32 cycle error: full blocks %.3e  csr %.3e  emulated %.3e"
+              % (err, np.linalg.norm(zc - zo) / np.linalg.norm(zo), err32), flush=True)
+        assert err <= 4.0 * err32 + 1e-12
+    else:
+        assert err <= 1e-10
+        assert np.linalg.norm(z - zc) <= 1e-13 * np.linalg.norm(zc)
+    x, info = H.solve(tol=1e-12 if not fp32 else 1e-10, precision=prec)
+    assert info["converged"]
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= (1e-10 if not fp32 else 1e-8) * np.linalg.norm(xo)
+    if not fp32:
+        _, i8 = H.solve(tol=1e-8)
+        _, io8 = air_fgmres_solve(o, tol=1e-8, hier=OH)
+        assert abs(i8["iters"] - io8["iters"]) <= 1, (i8["iters"], io8["iters"])
