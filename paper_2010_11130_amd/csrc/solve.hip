@@ -164,42 +164,38 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
 // diagonal one included; row m of R at (m nb + s) B + c from the block row's
 // value base: voff[R] into the CSR values av where voff[R] >= 0, else ~voff[R]
 // into the side array ax): the Jacobi sweep of SP_SWEEP_LIST on the listed
-// rows, with the row sums of k_fb and the diagonal d of k_csr.
-template <class TA, class TX, class TY, int B, int G>
-__global__ __launch_bounds__(256) void k_fbd(int64_t n, const int32_t* __restrict__ list,
+// rows with the diagonal d, as k_csr.  LP lanes per row, a lane per block
+// (s = g, g + LP, ...): a lane reads the block's column index, the row's B
+// contiguous values of the block and the B contiguous values of x (wide
+// loads: a third of the load instructions of a lane per value).
+template <class TA, class TX, class TY, int B, int LP>
+__global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                                              const int64_t* __restrict__ voff, const TA* __restrict__ av,
                                              const TA* __restrict__ ax, const TX* __restrict__ x,
                                              const TY* __restrict__ b, const TY* __restrict__ d, TY omega,
                                              TY* __restrict__ y, TY* __restrict__ y2) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ii = gid / G;
-  const int g = (int)(gid % G);
+  const int64_t ii = gid / LP;
+  const int g = (int)(gid % LP);
   if (ii >= n) return;
   const int64_t i = list[ii];
   const int64_t R = i / B;
   const int m = (int)(i - R * B);
   const int64_t o0 = bptr[R];
-  const int len = (int)(bptr[R + 1] - o0) * B;
+  const int nb = (int)(bptr[R + 1] - o0);
   const int64_t vo = voff[R];
-  const TA* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * len;
+  const TA* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * nb * B;
   const int32_t* __restrict__ cb = bcol + o0;
-  TY acc = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  int e = g;
-  for (; e + 3 * G < len; e += 4 * G) {
-    const int e1 = e + G, e2 = e + 2 * G, e3 = e + 3 * G;
-    const int64_t c0 = (int64_t)cb[e / B] * B + e % B, c1 = (int64_t)cb[e1 / B] * B + e1 % B;
-    const int64_t c2 = (int64_t)cb[e2 / B] * B + e2 % B, c3 = (int64_t)cb[e3 / B] * B + e3 % B;
-    const TY a0 = (TY)v[e], a1 = (TY)v[e1], a2 = (TY)v[e2], a3 = (TY)v[e3];
-    acc += a0 * (TY)x[c0];
-    acc1 += a1 * (TY)x[c1];
-    acc2 += a2 * (TY)x[c2];
-    acc3 += a3 * (TY)x[c3];
-  }
-  for (; e < len; e += G) acc += (TY)v[e] * (TY)x[(int64_t)cb[e / B] * B + e % B];
-  acc += (acc1 + acc2) + acc3;
+  TY acc = 0;
+  for (int sl = g; sl < nb; sl += LP) {
+    const int64_t J = cb[sl];
+    const TA* __restrict__ vr = v + sl * B;
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    for (int c = 0; c < B; ++c) acc += (TY)vr[c] * (TY)x[J * B + c];
+  }
+#pragma unroll
+  for (int o = LP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LP);
   if (g != 0) return;
   TY xi = (TY)x[i];
   const TY di = d[i];
@@ -1230,29 +1226,36 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
   return AH_OK;
 }
 
-// Sweep of the listed rows of a level read by full blocks (k_fbd); av the
-// level's CSR values, ax its side array, in the cycle's precision.
+// Sweep of the listed rows of a level read by full blocks (k_fbr); av the
+// level's CSR values, ax its side array, in the cycle's precision.  Lanes
+// per row: 4 in FP64, 2 in FP32 (C3 level 1, about six blocks per row:
+// F sweep 656 / 436 us against 859 / 716 us with 8 lanes; AH_L1LP = 2, 4
+// or 8 overrides).
 template <class T>
-static ah_status fbd_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
+static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
                        const T* b, const T* d, T omega, T* y, hipStream_t st, const char* tag, double bytes,
                        T* y2 = nullptr) {
   if (n == 0) return AH_OK;
-  const int G = fb_lanes(L.nbv, L.n);
+  static const int lp_env = [] {
+    const char* e = std::getenv("AH_L1LP");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 2 || v == 4 || v == 8) ? v : 0;
+  }();
+  const int LP = lp_env ? lp_env : sizeof(T) == 8 ? 4 : 2;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
-  const dim3 grid((unsigned)cdiv(n * G, 256));
-#define FBD(BB, GG) hipLaunchKernelGGL((k_fbd<T, T, T, BB, GG>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, \
+  const dim3 grid((unsigned)cdiv(n * LP, 256));
+#define FBR(BB, LL) hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, \
                                        L.bvoff, av, ax, x, b, d, omega, y, y2)
-#define FBD_G(BB) switch (G) { case 2: FBD(BB, 2); break; case 4: FBD(BB, 4); break; case 8: FBD(BB, 8); break; \
-                               default: FBD(BB, 16); break; }
+#define FBR_L(BB) switch (LP) { case 2: FBR(BB, 2); break; case 4: FBR(BB, 4); break; default: FBR(BB, 8); break; }
   switch (L.bb) {
-    case 2: FBD_G(2); break;
-    case 3: FBD_G(3); break;
-    case 6: FBD_G(6); break;
+    case 2: FBR_L(2); break;
+    case 3: FBR_L(3); break;
+    case 6: FBR_L(6); break;
     default: prof_end(ps); set_error("unsupported block size %d", L.bb); return AH_EUNSUPPORTED;
   }
-#undef FBD_G
-#undef FBD
+#undef FBR_L
+#undef FBR
   prof_end(ps);
   AH_LAUNCHED();
   return AH_OK;
@@ -1345,7 +1348,7 @@ static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
 // values, every block column index and block-row offset and value base, the list,
 // x once, b and d on X, the X updates written (twice with a second output).
 template <class T>
-static double fbd_sweep_bytes(const AhLevel& L, int X, bool y2) {
+static double fbr_sweep_bytes(const AhLevel& L, int X, bool y2) {
   const double w = sizeof(T);
   const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
   const int64_t nvX = X == 0 ? L.nbvF : L.nbv - L.nbvF;
@@ -1619,10 +1622,10 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     const T* av = Ops<T>::A(L);
     const T* ax = Ops<T>::BX(L);
     const T* d = Ops<T>::d(L);
-    AH_TRY(fbd_g<T>(L, av, ax, nF, L.flist, x, b, d, om, y, st, tf, fbd_sweep_bytes<T>(L, 0, false)));
+    AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, x, b, d, om, y, st, tf, fbr_sweep_bytes<T>(L, 0, false)));
     if (nsw == 1) return AH_OK;
-    AH_TRY(fbd_g<T>(L, av, ax, nF, L.flist, y, b, d, om, x, st, tf, fbd_sweep_bytes<T>(L, 0, true), out));
-    AH_TRY(fbd_g<T>(L, av, ax, L.nc, L.clist, x, b, d, om, out, st, tc, fbd_sweep_bytes<T>(L, 1, false)));
+    AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, y, b, d, om, x, st, tf, fbr_sweep_bytes<T>(L, 0, true), out));
+    AH_TRY(fbr_g<T>(L, av, ax, L.nc, L.clist, x, b, d, om, out, st, tc, fbr_sweep_bytes<T>(L, 1, false)));
     return AH_OK;
   }
   AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,

@@ -148,18 +148,21 @@ def level1_lists(monkeypatch):
 
 @pytest.mark.parametrize("name", ["kuhn_nu4", "c5", "slab"])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_block_air_level1_full_block_sweeps(level1_lists, monkeypatch, name, fp32):
+@pytest.mark.parametrize("lanes", ["auto", "8"])
+def test_block_air_level1_full_block_sweeps(level1_lists, monkeypatch, name, fp32, lanes):
     """Level 1 under block AIR is made of b x b blocks; its sweeps read it by
     full blocks (one column index per block; the CSR values in place where
     the rows of a block row share one block pattern, a zero-filled side array
-    elsewhere).  One V-cycle
+    elsewhere), a lane per block (lanes per row by precision, or 8).  One V-cycle
     against the oracle's (FP64 1e-10; FP32 within 4x the oracle's FP32
     emulation), the same cycle with the copy switched off (AH_L1B=0, the CSR
     sweeps) to 1e-13 in FP64, and the solution and iteration count against
     the oracle's solve."""
     import torch
     from paper_2010_11130_amd import Hierarchy
-    print("case", name, fp32, flush=True)
+    print("case", name, fp32, lanes, flush=True)
+    if lanes != "auto":
+        monkeypatch.setenv("AH_L1LP", lanes)
     v, c, prob, p = case(name)
     g = gpu_system(v, c, prob, p)
     o = setup_problem(v, c, prob, p)
