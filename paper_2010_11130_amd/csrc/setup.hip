@@ -1576,6 +1576,78 @@ static void rs_first_pass_host(int64_t n, const std::vector<int64_t>& rp, const 
 
 ah_hier::~ah_hier() { arena.release(); }
 
+// Level 0 under block AIR in sweep order: item k < nbF is the k-th F block
+// (list[k B] / B of the F list), the rest the C blocks; each item's blocks
+// (column indices and B x B values) copied to its range of the copy, 16
+// lanes per item reading and writing contiguous runs.
+__global__ void k_so_perm(int64_t n, const int32_t* __restrict__ list, int B, int32_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = list[k * B] / B;
+}
+
+__global__ void k_so_count(int64_t nbr, const int32_t* __restrict__ perm, const int64_t* __restrict__ optr,
+                           int64_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbr) cnt[k] = optr[perm[k] + 1] - optr[perm[k]];
+}
+
+__global__ void k_so_copy(int64_t nbr, int B, const int32_t* __restrict__ perm, const int64_t* __restrict__ optr,
+                          const int32_t* __restrict__ ocol, const double* __restrict__ ov,
+                          const int64_t* __restrict__ soptr, int32_t* __restrict__ socol, double* __restrict__ sov,
+                          float* __restrict__ sov32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid / 16;
+  const int t = (int)(gid % 16);
+  if (k >= nbr) return;
+  const int64_t R = perm[k];
+  const int64_t o = optr[R], p = soptr[k];
+  const int64_t nb = optr[R + 1] - o;
+  for (int64_t s = t; s < nb; s += 16) socol[p + s] = ocol[o + s];
+  const int64_t bb = (int64_t)B * B;
+  for (int64_t e = t; e < nb * bb; e += 16) {
+    const double a = ov[o * bb + e];
+    sov[p * bb + e] = a;
+    if (sov32) sov32[p * bb + e] = (float)a;
+  }
+}
+
+static ah_status sweep_order_build(ah_hier* h, hipStream_t st) {
+  AhLevel& L = h->lev[0];
+  const int B = L.ob;
+  if (!L.fblk || B < 2 || !L.oval || !L.flist || !L.clist) return AH_OK;
+  const int64_t nbr = L.n / B, nbF = L.nF / B, nbC = L.nc / B;
+  if (nbr * B != L.n || nbF * B != L.nF || nbC * B != L.nc || nbF + nbC != nbr) return AH_OK;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  int32_t *perm = nullptr, *socol = nullptr;
+  int64_t *cnt = nullptr, *soptr = nullptr;
+  double* sov = nullptr;
+  const int64_t nblk = L.nov / ((int64_t)B * B);
+  ah_status rc = tmp.get(&cnt, std::max<int64_t>(nbr, 1));
+  if (rc == AH_OK) rc = ar.get(&perm, std::max<int64_t>(nbr, 1));
+  if (rc == AH_OK) rc = ar.get(&soptr, nbr + 1);
+  if (rc == AH_OK) rc = ar.get(&socol, std::max<int64_t>(nblk, 1));
+  if (rc == AH_OK) rc = ar.get(&sov, std::max<int64_t>(L.nov, 1));
+  if (rc == AH_OK && h->prm.fp32_cycle) rc = ar.get(&L.soval32, std::max<int64_t>(L.nov, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nbF > 0) hipLaunchKernelGGL(k_so_perm, g1(nbF), dim3(256), 0, st, nbF, L.flist, B, perm);
+  if (nbC > 0) hipLaunchKernelGGL(k_so_perm, g1(nbC), dim3(256), 0, st, nbC, L.clist, B, perm + nbF);
+  hipLaunchKernelGGL(k_so_count, g1(nbr), dim3(256), 0, st, nbr, perm, L.optr, cnt);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: sweep order"); return AH_EHIP; }
+  rc = scan_i64(cnt, soptr, nbr, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  hipLaunchKernelGGL(k_so_copy, g1(nbr * 16), dim3(256), 0, st, nbr, B, perm, L.optr, L.ocol, L.oval, soptr, socol,
+                     sov, L.soval32);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: sweep order copy"); return AH_EHIP; }
+  tmp.release();
+  L.sperm = perm;
+  L.soptr = soptr;
+  L.socol = socol;
+  L.soval = sov;
+  return AH_OK;
+}
+
 // A CSR operator whose rows come in groups of B (block rows) read by the
 // sweeps as full b x b blocks: block row I holds the distinct column blocks
 // J (column / B) of its B rows; row m stores, per block s, the B values of
@@ -2250,8 +2322,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     // level 1 under block AIR: R A P with P = P_b (x) I and block lAIR rows
     // is made of ob x ob blocks; its F and C sweeps (list sweeps, not the
     // coarsest level) read it by full blocks (one column index per block)
-    bool l1b = true;
+    bool l1b = true, swo = true;
     if (const char* e = std::getenv("AH_L1B")) l1b = std::atoi(e) != 0;
+    if (const char* e = std::getenv("AH_SWO")) swo = std::atoi(e) != 0;
+    // level 0 under block AIR with Jacobi sweeps: the sweep-ordered copy
+    if (swo && nl > 1 && h->lev[0].fblk && prm.relax < 2 && h->fbb) {
+      ProfScope ps;
+      prof_begin(ps, "order0", st, 0.0);
+      CK(sweep_order_build(h, st));
+      prof_end(ps);
+    }
     if (l1b && nl > 2 && h->lev[0].fblk && h->lev[1].n >= h->list_min) {
       ProfScope ps;
       prof_begin(ps, "view1", st, 0.0);

@@ -24,7 +24,7 @@
 
 namespace ah {
 
-enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5 };
+enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5, SP_SWEEP_ORD = 6 };
 
 // MODE SP_MV:      y = A x
 // MODE SP_RES:     y = b - A x
@@ -212,7 +212,9 @@ __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restric
 // lanes and lane m mod LPB writes row R B + m.  Each x value is gathered once for
 // the B rows that use it (k_fb gathers it once per row).  Items are block
 // rows: all of them (SP_MV, SP_RES), or the blocks of a row list made of
-// whole blocks in increasing order (SP_SWEEP_LIST: block k is list[k B] / B).
+// whole blocks in increasing order (SP_SWEEP_LIST: block k is list[k B] / B),
+// or (SP_SWEEP_ORD) the block rows list[k] of a copy of the operator stored
+// in that order (item k's blocks at optr[k] .. optr[k + 1]); both sweep.
 template <class TA, class TX, class TY, int B, int LPB, int MODE>
 __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restrict__ optr,
                                              const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
@@ -223,9 +225,10 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   const int64_t kk = gid / LPB;
   const int g = (int)(gid % LPB);
   if (kk >= nbr) return;
-  const int64_t R = MODE == SP_SWEEP_LIST ? (int64_t)list[kk * B] / B : kk;
-  const int64_t o0 = optr[R];
-  const int nb = (int)(optr[R + 1] - o0);
+  const int64_t R = MODE == SP_SWEEP_LIST ? (int64_t)list[kk * B] / B : MODE == SP_SWEEP_ORD ? (int64_t)list[kk] : kk;
+  const int64_t ko = MODE == SP_SWEEP_ORD ? kk : R;
+  const int64_t o0 = optr[ko];
+  const int nb = (int)(optr[ko + 1] - o0);
   const TA* __restrict__ v = ov + o0 * (B * B);
   TY acc[B];
 #pragma unroll
@@ -1403,6 +1406,7 @@ struct Ops<double> {
   static const double* O(const AhLevel& L) { return L.oval; }
   static const double* OT(const AhLevel& L) { return L.otval; }
   static const double* BX(const AhLevel& L) { return L.baux; }
+  static const double* SO(const AhLevel& L) { return L.soval; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -1418,6 +1422,7 @@ struct Ops<float> {
   static const float* O(const AhLevel& L) { return L.oval32; }
   static const float* OT(const AhLevel& L) { return L.otval32; }
   static const float* BX(const AhLevel& L) { return L.baux32; }
+  static const float* SO(const AhLevel& L) { return L.soval32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -1606,6 +1611,21 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                    : l == 1 ? (sizeof(T) == 8 ? "relax1_f" : "relax1_f_f32") : nullptr;
   const char* tc = l == 0 ? (sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32")
                    : l == 1 ? (sizeof(T) == 8 ? "relax1_c" : "relax1_c_f32") : nullptr;
+  if (l == 0 && L.sperm && Ops<T>::SO(L)) {
+    // block AIR with the sweep-ordered copy: the F blocks, then the C
+    // blocks, each set one contiguous range of block rows
+    const T* so = Ops<T>::SO(L);
+    const int lp = h->lpb ? h->lpb : fbb_lanes(L.nov, L.n, L.ob);
+    const int64_t nbF = nF / L.ob;
+    AH_TRY((fbb_g<T, T, T, SP_SWEEP_ORD>(L.ob, lp, nF, L.soptr, L.socol, so, x, b, om, y, st, tf,
+                                         fb_sweep_bytes<T>(L, 0, false), L.sperm)));
+    if (nsw == 1) return AH_OK;
+    AH_TRY((fbb_g<T, T, T, SP_SWEEP_ORD>(L.ob, lp, nF, L.soptr, L.socol, so, y, b, om, x, st, tf,
+                                         fb_sweep_bytes<T>(L, 0, true), L.sperm, out)));
+    AH_TRY((fbb_g<T, T, T, SP_SWEEP_ORD>(L.ob, lp, L.nc, L.soptr + nbF, L.socol, so, x, b, om, out, st, tc,
+                                         fb_sweep_bytes<T>(L, 1, false), L.sperm + nbF)));
+    return AH_OK;
+  }
   if (l == 0 && L.ob && Ops<T>::O(L)) {
     const T* ov = Ops<T>::O(L);
     AH_TRY((fb_any<T, SP_SWEEP_LIST>(h, L, L.fblk, nF, ov, x, b, om, y, st, tf, fb_sweep_bytes<T>(L, 0, false),

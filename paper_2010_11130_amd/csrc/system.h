@@ -86,6 +86,14 @@ struct AhLevel {
   const int32_t* ocol = nullptr;
   const double* oval = nullptr;
   float* oval32 = nullptr;
+  // block AIR: a copy of that operator with its block rows in sweep order
+  // (the F blocks, then the C blocks, each increasing): item k is block row
+  // sperm[k], its blocks at soptr[k] .. soptr[k + 1] of socol / soval
+  const int32_t* sperm = nullptr;
+  const int64_t* soptr = nullptr;
+  const int32_t* socol = nullptr;
+  const double* soval = nullptr;
+  float* soval32 = nullptr;
   // the transposed operator in the same layout (adjoint cycle): block (I, J)
   // holds the transpose of block (J, I); null where the CSR A^T is used
   double* otval = nullptr;
