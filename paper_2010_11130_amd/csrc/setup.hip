@@ -1749,11 +1749,78 @@ __global__ void k_bfull_fill(int64_t nbr, const int64_t* __restrict__ rp, const 
   }
 }
 
+// The rows of a level read by full blocks, copied in sweep order: item k of
+// the concatenated F and C lists gets its row's values (nb B of them) at
+// off[k]; cnt_k first, then the copy with 16 lanes per row.
+__global__ void k_bso_count(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ bptr,
+                            int64_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t R = items[k] / B;
+  cnt[k] = (bptr[R + 1] - bptr[R]) * B;
+}
+
+__global__ void k_bso_copy(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ bptr,
+                           const int64_t* __restrict__ voff, const double* __restrict__ av,
+                           const double* __restrict__ ax, const int64_t* __restrict__ off, double* __restrict__ sov,
+                           float* __restrict__ sov32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid / 16;
+  const int t = (int)(gid % 16);
+  if (k >= n) return;
+  const int64_t i = items[k];
+  const int64_t R = i / B;
+  const int64_t len = (bptr[R + 1] - bptr[R]) * B;
+  const int64_t vo = voff[R];
+  const double* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (i - R * B) * len;
+  const int64_t p = off[k];
+  for (int64_t e = t; e < len; e += 16) {
+    const double a = v[e];
+    sov[p + e] = a;
+    if (sov32) sov32[p + e] = (float)a;
+  }
+}
+
 // The full-block view of level l (block size B) for its F and C sweeps, if
 // it stores at most 1.25 times the CSR entries; otherwise the level keeps
 // the CSR sweeps.  Also the F rows' stored values (sweep byte counts) and
 // the FP32 side array for the FP32 cycle.
-static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st) {
+// The values of the F rows, then of the C rows, of a level read by full
+// blocks, in that order (FP64 and, for the FP32 cycle, FP32).
+static ah_status block_view_order(ah_hier* h, int l, hipStream_t st) {
+  AhLevel& L = h->lev[l];
+  const int B = L.bb;
+  const int64_t nF = L.n - L.nc;
+  if (!L.flist || !L.clist) return AH_OK;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  int64_t *cnt = nullptr, *off = nullptr;
+  double* sov = nullptr;
+  ah_status rc = tmp.get(&cnt, std::max<int64_t>(L.n, 1));
+  if (rc == AH_OK) rc = ar.get(&off, L.n + 1);
+  if (rc == AH_OK) rc = ar.get(&sov, std::max<int64_t>(L.nbv, 1));
+  if (rc == AH_OK && h->prm.fp32_cycle) rc = ar.get(&L.soval32, std::max<int64_t>(L.nbv, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0) hipLaunchKernelGGL(k_bso_count, g1(nF), dim3(256), 0, st, nF, L.flist, B, L.bptr, cnt);
+  if (L.nc > 0) hipLaunchKernelGGL(k_bso_count, g1(L.nc), dim3(256), 0, st, L.nc, L.clist, B, L.bptr, cnt + nF);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: level order count"); return AH_EHIP; }
+  rc = scan_i64(cnt, off, L.n, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0)
+    hipLaunchKernelGGL(k_bso_copy, g1(nF * 16), dim3(256), 0, st, nF, L.flist, B, L.bptr, L.bvoff, L.val, L.baux, off,
+                       sov, L.soval32);
+  if (L.nc > 0)
+    hipLaunchKernelGGL(k_bso_copy, g1(L.nc * 16), dim3(256), 0, st, L.nc, L.clist, B, L.bptr, L.bvoff, L.val, L.baux,
+                       off + nF, sov, L.soval32);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: level order copy"); return AH_EHIP; }
+  tmp.release();
+  L.bsoff = off;
+  L.soval = sov;
+  return AH_OK;
+}
+
+static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st, bool so) {
   AhLevel& L = h->lev[l];
   const int64_t nbr = L.n / B;
   if (nbr == 0 || nbr * B != L.n || !L.flist || (B != 2 && B != 3 && B != 6)) return AH_OK;
@@ -1831,7 +1898,7 @@ static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st) {
   L.bcol = bcol;
   L.bvoff = voff;
   L.baux = aux;
-  return AH_OK;
+  return so ? block_view_order(h, l, st) : AH_OK;
 }
 
 extern "C" void ah_air_defaults(ah_air_params* p) {
@@ -2335,7 +2402,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     if (l1b && nl > 2 && h->lev[0].fblk && h->lev[1].n >= h->list_min) {
       ProfScope ps;
       prof_begin(ps, "view1", st, 0.0);
-      CK(block_view_build(h, 1, h->lev[0].ob, st));
+      CK(block_view_build(h, 1, h->lev[0].ob, st, swo));
       prof_end(ps);
     }
     std::vector<TailLevel> tl(nl);

@@ -167,8 +167,10 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
 // rows with the diagonal d, as k_csr.  LP lanes per row, a lane per block
 // (s = g, g + LP, ...): a lane reads the block's column index, the row's B
 // contiguous values of the block and the B contiguous values of x (wide
-// loads: a third of the load instructions of a lane per value).
-template <class TA, class TX, class TY, int B, int LP>
+// loads: a third of the load instructions of a lane per value).  ORD: the
+// values of item k are the row's values in a copy in sweep order, at
+// voff[k] of av (ax unused).
+template <class TA, class TX, class TY, int B, int LP, bool ORD>
 __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
                                              const int64_t* __restrict__ voff, const TA* __restrict__ av,
@@ -184,8 +186,8 @@ __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restric
   const int m = (int)(i - R * B);
   const int64_t o0 = bptr[R];
   const int nb = (int)(bptr[R + 1] - o0);
-  const int64_t vo = voff[R];
-  const TA* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * nb * B;
+  const int64_t vo = voff[ORD ? ii : R];
+  const TA* __restrict__ v = ORD ? av + vo : (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * nb * B;
   const int32_t* __restrict__ cb = bcol + o0;
   TY acc = 0;
   for (int sl = g; sl < nb; sl += LP) {
@@ -1237,7 +1239,7 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
 template <class T>
 static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
                        const T* b, const T* d, T omega, T* y, hipStream_t st, const char* tag, double bytes,
-                       T* y2 = nullptr) {
+                       T* y2 = nullptr, const int64_t* soff = nullptr) {
   if (n == 0) return AH_OK;
   static const int lp_env = [] {
     const char* e = std::getenv("AH_L1LP");
@@ -1248,8 +1250,15 @@ static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, co
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   const dim3 grid((unsigned)cdiv(n * LP, 256));
-#define FBR(BB, LL) hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, \
-                                       L.bvoff, av, ax, x, b, d, omega, y, y2)
+#define FBR(BB, LL)                                                                                         \
+  do {                                                                                                      \
+    if (soff)                                                                                               \
+      hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL, true>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, soff, \
+                         av, ax, x, b, d, omega, y, y2);                                                    \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL, false>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol,  \
+                         L.bvoff, av, ax, x, b, d, omega, y, y2);                                           \
+  } while (0)
 #define FBR_L(BB) switch (LP) { case 2: FBR(BB, 2); break; case 4: FBR(BB, 4); break; default: FBR(BB, 8); break; }
   switch (L.bb) {
     case 2: FBR_L(2); break;
@@ -1642,6 +1651,18 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     const T* av = Ops<T>::A(L);
     const T* ax = Ops<T>::BX(L);
     const T* d = Ops<T>::d(L);
+    if (Ops<T>::SO(L) && L.bsoff) {
+      // from the copy in sweep order: the F rows, then the C rows
+      const T* so = Ops<T>::SO(L);
+      AH_TRY(fbr_g<T>(L, so, so, nF, L.flist, x, b, d, om, y, st, tf, fbr_sweep_bytes<T>(L, 0, false), nullptr,
+                      L.bsoff));
+      if (nsw == 1) return AH_OK;
+      AH_TRY(fbr_g<T>(L, so, so, nF, L.flist, y, b, d, om, x, st, tf, fbr_sweep_bytes<T>(L, 0, true), out,
+                      L.bsoff));
+      AH_TRY(fbr_g<T>(L, so, so, L.nc, L.clist, x, b, d, om, out, st, tc, fbr_sweep_bytes<T>(L, 1, false), nullptr,
+                      L.bsoff + nF));
+      return AH_OK;
+    }
     AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, x, b, d, om, y, st, tf, fbr_sweep_bytes<T>(L, 0, false)));
     if (nsw == 1) return AH_OK;
     AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, y, b, d, om, x, st, tf, fbr_sweep_bytes<T>(L, 0, true), out));

@@ -112,6 +112,9 @@ struct AhLevel {
   const int64_t* bvoff = nullptr;
   const double* baux = nullptr;
   float* baux32 = nullptr;
+  // and its rows' values once more in sweep order (the F rows, then the C
+  // rows, each in list order): item k's row at bsoff[k] of soval / soval32
+  const int64_t* bsoff = nullptr;
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;
