@@ -71,15 +71,21 @@ __global__ void k_pmis_init(int64_t n, const int32_t* __restrict__ infl, int lev
 // 8 lanes per row for the PMIS phases and the one-point kernel.
 constexpr int PG = 8;
 
+// The round kernels visit rows 0 .. n-1, or the rows list[0 .. n-1] (the
+// points still undecided when the list was made; points only leave that
+// state, so the rows outside the list are no-ops of the round).
 __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
                                                     const uint8_t* __restrict__ strong,
                                                     const uint64_t* __restrict__ key, const int8_t* __restrict__ state,
-                                                    unsigned long long* __restrict__ nbmax) {
+                                                    unsigned long long* __restrict__ nbmax,
+                                                    const int32_t* __restrict__ list) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = gid / PG;
+  const int64_t ii = gid / PG;
   const int g = (int)(gid % PG);
-  if (i >= n || state[i] != 0) return;
+  if (ii >= n) return;
+  const int64_t i = list ? (int64_t)list[ii] : ii;
+  if (state[i] != 0) return;
   unsigned long long mx = 0, ki = key[i];
   for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG) {
     if (!strong[k]) continue;
@@ -99,10 +105,13 @@ __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __
 // nbmax is reset for the next round (only undecided points carry a value),
 // and the round's undecided flag is cleared.
 __global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsigned long long* __restrict__ nbmax,
-                              int8_t* __restrict__ state, unsigned long long* __restrict__ left) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *left = 0;
-  if (i >= n || state[i] != 0) return;
+                              int8_t* __restrict__ state, unsigned long long* __restrict__ left,
+                              const int32_t* __restrict__ list) {
+  const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii == 0) *left = 0;
+  if (ii >= n) return;
+  const int64_t i = list ? (int64_t)list[ii] : ii;
+  if (state[i] != 0) return;
   if (key[i] > nbmax[i]) state[i] = 1;
   nbmax[i] = 0;
 }
@@ -113,11 +122,13 @@ __global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsig
 __global__ __launch_bounds__(256) void k_pmis_fmark(int64_t n, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
                                                     const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
-                                                    unsigned long long* __restrict__ left) {
+                                                    unsigned long long* __restrict__ left,
+                                                    const int32_t* __restrict__ list) {
   const int g = (int)(threadIdx.x % PG);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
   int undecided = 0;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; i < n; i += stride) {
+  for (int64_t ii = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; ii < n; ii += stride) {
+    const int64_t i = list ? (int64_t)list[ii] : ii;
     if (state[i] != 0) continue;
     int hit = 0;
     for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG)
@@ -1425,6 +1436,21 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
   return AH_EUNSUPPORTED;
 }
 
+// Undecided points of the rows 0 .. n-1 (or of list[0 .. n-1]): flag, then
+// written at the flag's prefix sum.
+__global__ void k_pmis_uflag(int64_t n, const int8_t* __restrict__ state, const int32_t* __restrict__ list,
+                             int32_t* __restrict__ flag) {
+  const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii >= n) return;
+  flag[ii] = state[list ? list[ii] : ii] == 0 ? 1 : 0;
+}
+
+__global__ void k_pmis_ulist(int64_t n, const int32_t* __restrict__ list, const int32_t* __restrict__ flag,
+                             const int64_t* __restrict__ pos, int32_t* __restrict__ out) {
+  const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii < n && flag[ii]) out[pos[ii]] = list ? list[ii] : (int32_t)ii;
+}
+
 // PMIS C/F splitting of the graph (n, rp, ci) over its strong entries:
 // state[i] = 1 (C) or 2 (F).  key and nbmax hold n entries of scratch;
 // flags[0..1] are the undecided flags of alternating rounds, flags[3] the
@@ -1447,19 +1473,44 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
     AH_HIP(hipGetLastError());
     return AH_OK;
   }
+  // after each host check the rounds run over the points still undecided
+  // (two lists, alternating; the arena outlives the split)
+  Arena tmp;
+  tmp.stream = st;
+  int32_t* lists[2] = {nullptr, nullptr};
+  int32_t* flag = nullptr;
+  int64_t* pos = nullptr;
+  ah_status rc = tmp.get(&lists[0], n);
+  if (rc == AH_OK) rc = tmp.get(&lists[1], n);
+  if (rc == AH_OK) rc = tmp.get(&flag, n);
+  if (rc == AH_OK) rc = tmp.get(&pos, n + 1);
+  if (rc < 0) { tmp.release(); return rc; }
+  const int32_t* list = nullptr;
+  int64_t nl = n;
+  int which = 0;
   for (int round = 0;; ++round) {
-    if (round > 10000) { set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
+    if (round > 10000) { tmp.release(); set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
     unsigned long long* left_d = flags + (round & 1);
-    hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, rp, ci, strong, key, state, nbmax);
-    hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d);
-    hipLaunchKernelGGL(k_pmis_fmark, grows(n), dim3(256), 0, st, n, rp, ci, strong, state, left_d);
-    AH_HIP(hipGetLastError());
-    // rounds run in pairs between host checks: a round after the last
-    // undecided point is gone changes nothing and leaves its flag at 0
+    hipLaunchKernelGGL(k_pmis_nbmax, g1(nl * PG), dim3(256), 0, st, nl, rp, ci, strong, key, state, nbmax, list);
+    hipLaunchKernelGGL(k_pmis_select, g1(nl), dim3(256), 0, st, nl, key, nbmax, state, left_d, list);
+    hipLaunchKernelGGL(k_pmis_fmark, grows(nl), dim3(256), 0, st, nl, rp, ci, strong, state, left_d, list);
+    if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: PMIS round"); return AH_EHIP; }
+    // rounds run in pairs between host checks (the count of points still
+    // undecided): a round after the last undecided point is gone changes
+    // nothing
     if ((round & 1) == 0) continue;
-    unsigned long long left = 0;
-    AH_TRY(read_bytes(left_d, &left, sizeof(left), st));
-    if (left == 0) return AH_OK;
+    int32_t* out = lists[which];
+    hipLaunchKernelGGL(k_pmis_uflag, g1(nl), dim3(256), 0, st, nl, state, list, flag);
+    rc = scan_i32_to_i64(flag, pos, nl, st, tmp);
+    if (rc < 0) { tmp.release(); return rc; }
+    hipLaunchKernelGGL(k_pmis_ulist, g1(nl), dim3(256), 0, st, nl, list, flag, pos, out);
+    int64_t cnt = 0;
+    rc = read_bytes(pos + nl, &cnt, sizeof(cnt), st);
+    if (rc < 0) { tmp.release(); return rc; }
+    if (cnt == 0) { tmp.release(); return AH_OK; }
+    list = out;
+    nl = cnt;
+    which ^= 1;
   }
 }
 
