@@ -73,16 +73,18 @@ constexpr int PG = 8;
 
 // The round kernels visit rows 0 .. n-1, or the rows list[0 .. n-1] (the
 // points still undecided when the list was made; points only leave that
-// state, so the rows outside the list are no-ops of the round).
+// state, so the rows outside the list are no-ops of the round); with nd,
+// the list's length is *nd (at most n, the bound the grid was sized for).
 __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci,
                                                     const uint8_t* __restrict__ strong,
                                                     const uint64_t* __restrict__ key, const int8_t* __restrict__ state,
                                                     unsigned long long* __restrict__ nbmax,
-                                                    const int32_t* __restrict__ list) {
+                                                    const int32_t* __restrict__ list, const int64_t* __restrict__ nd) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / PG;
   const int g = (int)(gid % PG);
+  if (nd) n = *nd;
   if (ii >= n) return;
   const int64_t i = list ? (int64_t)list[ii] : ii;
   if (state[i] != 0) return;
@@ -106,9 +108,10 @@ __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __
 // and the round's undecided flag is cleared.
 __global__ void k_pmis_select(int64_t n, const uint64_t* __restrict__ key, unsigned long long* __restrict__ nbmax,
                               int8_t* __restrict__ state, unsigned long long* __restrict__ left,
-                              const int32_t* __restrict__ list) {
+                              const int32_t* __restrict__ list, const int64_t* __restrict__ nd) {
   const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ii == 0) *left = 0;
+  if (nd) n = *nd;
   if (ii >= n) return;
   const int64_t i = list ? (int64_t)list[ii] : ii;
   if (state[i] != 0) return;
@@ -123,10 +126,12 @@ __global__ __launch_bounds__(256) void k_pmis_fmark(int64_t n, const int64_t* __
                                                     const int32_t* __restrict__ ci,
                                                     const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
                                                     unsigned long long* __restrict__ left,
-                                                    const int32_t* __restrict__ list) {
+                                                    const int32_t* __restrict__ list,
+                                                    const int64_t* __restrict__ nd) {
   const int g = (int)(threadIdx.x % PG);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / PG);
   int undecided = 0;
+  if (nd) n = *nd;
   for (int64_t ii = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PG; ii < n; ii += stride) {
     const int64_t i = list ? (int64_t)list[ii] : ii;
     if (state[i] != 0) continue;
@@ -1439,10 +1444,10 @@ static ah_status rap_dispatch(int hs, int64_t nc, const AhLevel& L, int32_t* cnt
 // Undecided points of the rows 0 .. n-1 (or of list[0 .. n-1]): flag, then
 // written at the flag's prefix sum.
 __global__ void k_pmis_uflag(int64_t n, const int8_t* __restrict__ state, const int32_t* __restrict__ list,
-                             int32_t* __restrict__ flag) {
+                             const int64_t* __restrict__ nd, int32_t* __restrict__ flag) {
   const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ii >= n) return;
-  flag[ii] = state[list ? list[ii] : ii] == 0 ? 1 : 0;
+  flag[ii] = (!nd || ii < *nd) && state[list ? list[ii] : ii] == 0 ? 1 : 0;
 }
 
 __global__ void k_pmis_ulist(int64_t n, const int32_t* __restrict__ list, const int32_t* __restrict__ flag,
@@ -1473,44 +1478,46 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
     AH_HIP(hipGetLastError());
     return AH_OK;
   }
-  // after each host check the rounds run over the points still undecided
-  // (two lists, alternating; the arena outlives the split)
+  // after each round the points still undecided are listed (their count
+  // stays on the device; the grids are sized by the last count read on the
+  // host, an upper bound), and the next round runs over that list; the
+  // host reads the count every second round
   Arena tmp;
   tmp.stream = st;
   int32_t* lists[2] = {nullptr, nullptr};
   int32_t* flag = nullptr;
-  int64_t* pos = nullptr;
+  int64_t* pos[2] = {nullptr, nullptr};
   ah_status rc = tmp.get(&lists[0], n);
   if (rc == AH_OK) rc = tmp.get(&lists[1], n);
   if (rc == AH_OK) rc = tmp.get(&flag, n);
-  if (rc == AH_OK) rc = tmp.get(&pos, n + 1);
+  if (rc == AH_OK) rc = tmp.get(&pos[0], n + 1);
+  if (rc == AH_OK) rc = tmp.get(&pos[1], n + 1);
   if (rc < 0) { tmp.release(); return rc; }
   const int32_t* list = nullptr;
-  int64_t nl = n;
-  int which = 0;
+  const int64_t* nd = nullptr;
+  int64_t nl = n;   // host bound of the list length
   for (int round = 0;; ++round) {
     if (round > 10000) { tmp.release(); set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
     unsigned long long* left_d = flags + (round & 1);
-    hipLaunchKernelGGL(k_pmis_nbmax, g1(nl * PG), dim3(256), 0, st, nl, rp, ci, strong, key, state, nbmax, list);
-    hipLaunchKernelGGL(k_pmis_select, g1(nl), dim3(256), 0, st, nl, key, nbmax, state, left_d, list);
-    hipLaunchKernelGGL(k_pmis_fmark, grows(nl), dim3(256), 0, st, nl, rp, ci, strong, state, left_d, list);
+    hipLaunchKernelGGL(k_pmis_nbmax, g1(nl * PG), dim3(256), 0, st, nl, rp, ci, strong, key, state, nbmax, list, nd);
+    hipLaunchKernelGGL(k_pmis_select, g1(nl), dim3(256), 0, st, nl, key, nbmax, state, left_d, list, nd);
+    hipLaunchKernelGGL(k_pmis_fmark, grows(nl), dim3(256), 0, st, nl, rp, ci, strong, state, left_d, list, nd);
+    int32_t* out = lists[round & 1];
+    int64_t* p = pos[round & 1];
+    hipLaunchKernelGGL(k_pmis_uflag, g1(nl), dim3(256), 0, st, nl, state, list, nd, flag);
     if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: PMIS round"); return AH_EHIP; }
-    // rounds run in pairs between host checks (the count of points still
-    // undecided): a round after the last undecided point is gone changes
-    // nothing
-    if ((round & 1) == 0) continue;
-    int32_t* out = lists[which];
-    hipLaunchKernelGGL(k_pmis_uflag, g1(nl), dim3(256), 0, st, nl, state, list, flag);
-    rc = scan_i32_to_i64(flag, pos, nl, st, tmp);
+    rc = scan_i32_to_i64(flag, p, nl, st, tmp);
     if (rc < 0) { tmp.release(); return rc; }
-    hipLaunchKernelGGL(k_pmis_ulist, g1(nl), dim3(256), 0, st, nl, list, flag, pos, out);
+    hipLaunchKernelGGL(k_pmis_ulist, g1(nl), dim3(256), 0, st, nl, list, flag, p, out);
+    if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: PMIS list"); return AH_EHIP; }
+    list = out;
+    nd = p + nl;
+    if ((round & 1) == 0) continue;
     int64_t cnt = 0;
-    rc = read_bytes(pos + nl, &cnt, sizeof(cnt), st);
+    rc = read_bytes(nd, &cnt, sizeof(cnt), st);
     if (rc < 0) { tmp.release(); return rc; }
     if (cnt == 0) { tmp.release(); return AH_OK; }
-    list = out;
     nl = cnt;
-    which ^= 1;
   }
 }
 
