@@ -226,8 +226,9 @@ __global__ void k_cf_flags(int64_t n, const int8_t* __restrict__ state, int8_t* 
 // imax[0] = max |N_i|, imax[1] = max candidates, imax[2] = max length of a
 // C row; fst[0..1] = F rows, entries.
 // PG lanes per row; the strongest C neighbour is the first in row order
-// (smallest column) within relative 1e-12 of the maximum.
-__global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __restrict__ rp,
+// (smallest column) within relative 1e-12 of the maximum.  fsearch = 0
+// (block AIR, whose P comes from the block graph): F rows only listed.
+__global__ __launch_bounds__(256) void k_onepoint(int64_t n, int fsearch, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
                                                   const uint8_t* __restrict__ strong,
                                                   const uint8_t* __restrict__ strong_r, const int8_t* __restrict__ cf,
@@ -266,8 +267,9 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
       continue;
     }
     double mx = -1.0;
-    for (int64_t k = k0 + g; k < k1; k += PG)
-      if (strong[k] && cf[ci[k]]) mx = fmax(mx, fabs(v[k]));
+    if (fsearch)
+      for (int64_t k = k0 + g; k < k1; k += PG)
+        if (strong[k] && cf[ci[k]]) mx = fmax(mx, fabs(v[k]));
     for (int o = PG / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, PG));
     int64_t first = k1;
     if (mx >= 0.0) {
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, const int64_t* __re
       }
     }
     if (g == 0) {
-      pcol[i] = first < k1 ? (int32_t)cidx[ci[first]] : -1;
+      if (fsearch) pcol[i] = first < k1 ? (int32_t)cidx[ci[first]] : -1;
       flist[i - cidx[i]] = (int32_t)i;   // F points in increasing order
       fcnt += 1;
       fent += (unsigned long long)(k1 - k0);
@@ -1326,7 +1328,10 @@ __global__ void k_block_expand(int64_t n, int b, const int8_t* __restrict__ sb, 
 
 // Scalar strong mask of the level-0 CSR from the block marks: entry (i, j)
 // is strong when blocks i/b != j/b are joined by a strong block slot (the
-// slots of a block row are sorted by column).  PG lanes per row.
+// slots of a block row are sorted by column).  PG lanes per row.  Where the
+// row holds whole blocks in column order, entry t of the row is in the
+// row's block t / b, which is slot t / b (before the diagonal block) or
+// t / b - 1 (after it): that slot is tried first, then a binary search.
 __global__ __launch_bounds__(256) void k_block_mask(int64_t n, int b, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const int64_t* __restrict__ optr,
                                                     const int32_t* __restrict__ ocol,
@@ -1336,10 +1341,14 @@ __global__ __launch_bounds__(256) void k_block_mask(int64_t n, int b, const int6
   const int g = (int)(gid % PG);
   if (i >= n) return;
   const int64_t I = i / b, lo0 = optr[I], hi0 = optr[I + 1] - 1;
-  for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG) {
+  const int64_t r0 = rp[i];
+  for (int64_t k = r0 + g; k < rp[i + 1]; k += PG) {
     const int32_t J = ci[k] / b;
     uint8_t f = 0;
-    if (J != I) {
+    const int64_t q = lo0 + (k - r0) / b - (J > I ? 1 : 0);
+    if (J != I && q >= lo0 && q <= hi0 && ocol[q] == J) {
+      f = sb[q];
+    } else if (J != I) {
       int64_t lo = lo0, hi = hi0;
       while (lo <= hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -2168,7 +2177,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
                          infl_r);
       CKH(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, L.rowptr, L.col, L.val, strong, strong_r, L.cf,
+    hipLaunchKernelGGL(k_onepoint, grows(n), dim3(256), 0, st, n, blk ? 0 : 1, L.rowptr, L.col, L.val, strong, strong_r, L.cf,
                        cidx, L.pcol, rcnt, clist, L.flist, d_int, d_fst + 2 * l);
     CKH(hipGetLastError());
     if (blk) {
