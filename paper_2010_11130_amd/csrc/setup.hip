@@ -1465,6 +1465,10 @@ __global__ void k_pmis_ulist(int64_t n, const int32_t* __restrict__ list, const 
   if (ii < n && flag[ii]) out[pos[ii]] = list ? list[ii] : (int32_t)ii;
 }
 
+// Graphs from this many points on run their later PMIS rounds over a list
+// of the undecided points.
+constexpr int64_t PMIS_LIST_MIN = (int64_t)1 << 20;
+
 // PMIS C/F splitting of the graph (n, rp, ci) over its strong entries:
 // state[i] = 1 (C) or 2 (F).  key and nbmax hold n entries of scratch;
 // flags[0..1] are the undecided flags of alternating rounds, flags[3] the
@@ -1487,10 +1491,28 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
     AH_HIP(hipGetLastError());
     return AH_OK;
   }
-  // after each round the points still undecided are listed (their count
-  // stays on the device; the grids are sized by the last count read on the
-  // host, an upper bound), and the next round runs over that list; the
-  // host reads the count every second round
+  if (n < PMIS_LIST_MIN) {
+    // rounds over all points (launch-latency bound: listing costs more)
+    for (int round = 0;; ++round) {
+      if (round > 10000) { set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
+      unsigned long long* left_d = flags + (round & 1);
+      hipLaunchKernelGGL(k_pmis_nbmax, g1(n * PG), dim3(256), 0, st, n, rp, ci, strong, key, state, nbmax, nullptr,
+                         nullptr);
+      hipLaunchKernelGGL(k_pmis_select, g1(n), dim3(256), 0, st, n, key, nbmax, state, left_d, nullptr, nullptr);
+      hipLaunchKernelGGL(k_pmis_fmark, grows(n), dim3(256), 0, st, n, rp, ci, strong, state, left_d, nullptr, nullptr);
+      AH_HIP(hipGetLastError());
+      // rounds run in pairs between host checks: a round after the last
+      // undecided point is gone changes nothing and leaves its flag at 0
+      if ((round & 1) == 0) continue;
+      unsigned long long left = 0;
+      AH_TRY(read_bytes(left_d, &left, sizeof(left), st));
+      if (left == 0) return AH_OK;
+    }
+  }
+  // large graphs: after each round the points still undecided are listed
+  // (their count stays on the device; the grids are sized by the last count
+  // read on the host, an upper bound), and the next round runs over that
+  // list; the host reads the count every second round
   Arena tmp;
   tmp.stream = st;
   int32_t* lists[2] = {nullptr, nullptr};

@@ -1615,11 +1615,12 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   T* y = nsw == 1 ? out : Ops<T>::y(L);
   hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
   AH_LAUNCHED();
-  // level-0 timing tags, one per sweep kernel and grid (coarse levels: none)
+  // level-0 timing tags, and level 1's where it is read by full blocks
+  const bool t1 = l == 1 && L.bb;
   const char* tf = l == 0 ? (sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32")
-                   : l == 1 ? (sizeof(T) == 8 ? "relax1_f" : "relax1_f_f32") : nullptr;
+                   : t1 ? (sizeof(T) == 8 ? "relax1_f" : "relax1_f_f32") : nullptr;
   const char* tc = l == 0 ? (sizeof(T) == 8 ? "relax0_c" : "relax0_c_f32")
-                   : l == 1 ? (sizeof(T) == 8 ? "relax1_c" : "relax1_c_f32") : nullptr;
+                   : t1 ? (sizeof(T) == 8 ? "relax1_c" : "relax1_c_f32") : nullptr;
   if (l == 0 && L.sperm && Ops<T>::SO(L)) {
     // block AIR with the sweep-ordered copy: the F blocks, then the C
     // blocks, each set one contiguous range of block rows
