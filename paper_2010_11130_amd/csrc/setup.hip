@@ -428,6 +428,47 @@ __global__ __launch_bounds__(64) void k_lair_count2(int64_t nc, const int64_t* _
   }
 }
 
+// T[c m + r] = A[N_r, N_c] for the m rows N (sorted, m <= 64): the entries
+// of all m rows at once, a lane per entry (its row r from the prefix sums of
+// the row lengths), the column's position in N by binary search.  T must be
+// zero on entry; pre (m + 1 ints) and st0 (m offsets) are LDS scratch.
+__device__ void gather_nn(int m, const int32_t* N, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const double* __restrict__ v, double* T, int* pre, int64_t* st0, int lane) {
+  int len = 0;
+  int64_t s0 = 0;
+  if (lane < m) {
+    const int64_t j = N[lane];
+    s0 = rp[j];
+    len = (int)(rp[j + 1] - s0);
+  }
+  int inc = len;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane < m) { pre[lane + 1] = inc; st0[lane] = s0; }
+  if (lane == 0) pre[0] = 0;
+  __syncthreads();
+  const int tot = pre[m];
+  for (int e = lane; e < tot; e += 64) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {   // the last row starting at or before e
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int64_t k = st0[lo] + (e - pre[lo]);
+    const int32_t col = ci[k];
+    int a = 0, b = m - 1, c = -1;
+    while (a <= b) {
+      const int mid = (a + b) >> 1;
+      if (N[mid] == col) { c = mid; break; }
+      if (N[mid] < col) a = mid + 1; else b = mid - 1;
+    }
+    if (c >= 0) T[c * m + lo] = v[k];
+  }
+  __syncthreads();
+}
+
 template <int MAXM, bool D2>
 __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const double* __restrict__ v, const uint8_t* __restrict__ strong,
@@ -438,6 +479,8 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
   __shared__ double T[MAXM * MAXM];
   __shared__ double z[MAXM];
   __shared__ int s_m;
+  __shared__ int s_pre[MAXM + 1];
+  __shared__ int64_t s_st0[MAXM];
   int32_t* N = Nbuf;
   const int64_t ic = blockIdx.x;
   const int lane = threadIdx.x;
@@ -489,20 +532,7 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
   for (int k = lane; k < m * m; k += 64) T[k] = 0.0;
   __syncthreads();
   // T[c][r] = A[N_r, N_c]
-  for (int r = 0; r < m; ++r) {
-    int64_t j = N[r];
-    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
-      int32_t col = ci[k];
-      int lo = 0, hi = m - 1, c = -1;
-      while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        if (N[mid] == col) { c = mid; break; }
-        if (N[mid] < col) lo = mid + 1; else hi = mid - 1;
-      }
-      if (c >= 0) T[c * m + r] = v[k];
-    }
-  }
-  __syncthreads();
+  gather_nn(m, N, rp, ci, v, T, s_pre, s_st0, lane);
   double sc = 0.0;
   for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
   sc = wave_max(sc);
@@ -581,6 +611,8 @@ __global__ __launch_bounds__(64) void k_lair_blk(int64_t ncb, int b, const int64
   __shared__ int32_t N[MAXM];
   __shared__ double T[MAXM * MAXM];
   __shared__ double z[LB_BMAX * MAXM];
+  __shared__ int s_pre[MAXM + 1];
+  __shared__ int64_t s_st0[MAXM];
   const int64_t kb = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t i0 = clist[kb * b];
@@ -616,20 +648,7 @@ __global__ __launch_bounds__(64) void k_lair_blk(int64_t ncb, int b, const int64
   for (int k = lane; k < m * m; k += 64) T[k] = 0.0;
   __syncthreads();
   // T[c][r] = A[N_r, N_c]
-  for (int r = 0; r < m; ++r) {
-    const int64_t j = N[r];
-    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
-      const int32_t col = ci[k];
-      int lo = 0, hi = m - 1, c = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        if (N[mid] == col) { c = mid; break; }
-        if (N[mid] < col) lo = mid + 1; else hi = mid - 1;
-      }
-      if (c >= 0) T[c * m + r] = v[k];
-    }
-  }
-  __syncthreads();
+  gather_nn(m, N, rp, ci, v, T, s_pre, s_st0, lane);
   double sc = 0.0;
   for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
   sc = wave_max(sc);
