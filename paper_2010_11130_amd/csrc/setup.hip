@@ -1485,8 +1485,11 @@ __global__ void k_pmis_ulist(int64_t n, const int32_t* __restrict__ list, const 
 }
 
 // Graphs from this many points on run their later PMIS rounds over a list
-// of the undecided points.
-constexpr int64_t PMIS_LIST_MIN = (int64_t)1 << 20;
+// of the undecided points (AH_PMIS_LIST_MIN overrides).
+static int64_t pmis_list_min() {
+  const char* e = std::getenv("AH_PMIS_LIST_MIN");
+  return e ? (int64_t)std::atoll(e) : (int64_t)1 << 20;
+}
 
 // PMIS C/F splitting of the graph (n, rp, ci) over its strong entries:
 // state[i] = 1 (C) or 2 (F).  key and nbmax hold n entries of scratch;
@@ -1498,7 +1501,9 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
   hipLaunchKernelGGL(k_pmis_init, g1(n), dim3(256), 0, st, n, infl, level, key, state);
   AH_HIP(hipGetLastError());
   AH_HIP(hipMemsetAsync(nbmax, 0, n * sizeof(unsigned long long), st));
-  if (n <= PMIS_WG_MAX) {
+  const char* wg_env = std::getenv("AH_PMIS_WG_MAX");   // at most PMIS_WG_MAX (its LDS size)
+  const int64_t wg_max = wg_env ? std::min<int64_t>(std::atoll(wg_env), PMIS_WG_MAX) : (int64_t)PMIS_WG_MAX;
+  if (n <= wg_max) {
     // small graph: every round in one workgroup, no host checks
     static std::once_flag once;
     std::call_once(once, [] {
@@ -1510,7 +1515,7 @@ static ah_status pmis_split(int64_t n, const int64_t* rp, const int32_t* ci, con
     AH_HIP(hipGetLastError());
     return AH_OK;
   }
-  if (n < PMIS_LIST_MIN) {
+  if (n < pmis_list_min()) {
     // rounds over all points (launch-latency bound: listing costs more)
     for (int round = 0;; ++round) {
       if (round > 10000) { set_error("air_setup: PMIS did not terminate"); return AH_EINVAL; }
@@ -1999,6 +2004,10 @@ static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st, bool
   unsigned long long nvF = 0;
   std::memcpy(&nvF, pin, sizeof(nvF));
   L.bb = B;
+  if (const char* e = std::getenv("AH_L1LP")) {
+    const int v = std::atoi(e);
+    L.blp = (v == 2 || v == 4 || v == 8) ? v : 0;
+  }
   L.nbv = nv;
   L.nbvF = (int64_t)nvF;
   L.nbaux = na;

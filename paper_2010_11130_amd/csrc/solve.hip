@@ -1235,18 +1235,13 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
 // level's CSR values, ax its side array, in the cycle's precision.  Lanes
 // per row: 4 in FP64, 2 in FP32 (C3 level 1, about six blocks per row:
 // F sweep 656 / 436 us against 859 / 716 us with 8 lanes; AH_L1LP = 2, 4
-// or 8 overrides).
+// or 8 at setup overrides).
 template <class T>
 static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
                        const T* b, const T* d, T omega, T* y, hipStream_t st, const char* tag, double bytes,
                        T* y2 = nullptr, const int64_t* soff = nullptr) {
   if (n == 0) return AH_OK;
-  static const int lp_env = [] {
-    const char* e = std::getenv("AH_L1LP");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 2 || v == 4 || v == 8) ? v : 0;
-  }();
-  const int LP = lp_env ? lp_env : sizeof(T) == 8 ? 4 : 2;
+  const int LP = L.blp ? L.blp : sizeof(T) == 8 ? 4 : 2;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   const dim3 grid((unsigned)cdiv(n * LP, 256));

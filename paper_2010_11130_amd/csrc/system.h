@@ -104,6 +104,7 @@ struct AhLevel {
   // bvoff[R] of the CSR values (val / val32) where bvoff[R] >= 0, else from
   // ~bvoff[R] of baux / baux32 (zero-filled blocks); bb = 0 where not built
   int bb = 0;
+  int blp = 0;                 // lanes per row of its sweeps (0: by precision)
   int64_t nbv = 0;             // stored values
   int64_t nbvF = 0;            // of which in F rows
   int64_t nbaux = 0;           // of which in the side array

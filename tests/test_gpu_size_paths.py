@@ -5,7 +5,10 @@ small parity cases and compared with the oracle:
     Gram-Schmidt, so the two differ only in rounding;
   * coarse levels swept through their F and C point lists after an explicit
     interpolation (default from 2^16 rows; AH_LIST_MIN=0 here), with 2, 4
-    and 8 lanes per row (AH_GC).
+    and 8 lanes per row (AH_GC);
+  * PMIS by rounds of separate launches (default above 8192 points;
+    AH_PMIS_WG_MAX=0 here), over all points or over the points still
+    undecided (default from 2^20 points; AH_PMIS_LIST_MIN=0 here).
 
 Tolerances as in the other parity tests: solution at tol 1e-12 within 1e-10
 relative of the oracle's, iteration counts at the workload tolerance within
@@ -164,3 +167,31 @@ def test_workspace_reuse_across_restarts_and_precisions(built, monkeypatch, dela
         assert info["converged"] and info["iters"] == infof["iters"], (prec, m)
         assert np.array_equal(x.cpu().numpy(), xf.cpu().numpy()), (prec, m)
         del F
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5", "layer"])
+@pytest.mark.parametrize("block_air", [0, 1])
+@pytest.mark.parametrize("listed", [False, True])
+def test_pmis_rounds_paths(built, monkeypatch, name, block_air, listed):
+    """PMIS by rounds of separate launches (default above 8192 points;
+    AH_PMIS_WG_MAX=0 here), over all points in every round or (``listed``,
+    default from 2^20 points; AH_PMIS_LIST_MIN=0) over the points still
+    undecided: the same rounds, so C/F splitting and one-point P bit for bit
+    equal to the oracle's on every level, scalar and block AIR."""
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, block_air, listed, flush=True)
+    monkeypatch.setenv("AH_PMIS_WG_MAX", "0")
+    monkeypatch.setenv("AH_PMIS_LIST_MIN", "0" if listed else str(1 << 40))
+    g, o = built(name)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=block_air)
+    kw = {"block_air": True, "block": o.b} if block_air else {}
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, **kw)
+    assert H.info["n"] == [lev.A.shape[0] for lev in OH.levels]
+    for l in range(OH.nlev - 1):
+        lv = H.level(l)
+        ol = OH.levels[l]
+        assert np.array_equal(lv["cf"].cpu().numpy(), ol.cf), l
+        Pd = ol.P.tocsr()
+        opc = np.full(ol.A.shape[0], -1)
+        opc[np.repeat(np.arange(Pd.shape[0]), np.diff(Pd.indptr))] = Pd.indices
+        assert np.array_equal(lv["pcol"].cpu().numpy(), opc), l
