@@ -1894,6 +1894,69 @@ __global__ void k_bso_copy(int64_t n, const int32_t* __restrict__ items, int B, 
   }
 }
 
+// The rows of a CSR level copied in sweep order: item k of the concatenated
+// F and C lists gets its row's entries at off[k]; counts first, then the
+// copy with 16 lanes per row.
+__global__ void k_cso_count(int64_t n, const int32_t* __restrict__ items, const int64_t* __restrict__ rp,
+                            int64_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) cnt[k] = rp[items[k] + 1] - rp[items[k]];
+}
+
+__global__ void k_cso_copy(int64_t n, const int32_t* __restrict__ items, const int64_t* __restrict__ rp,
+                           const int32_t* __restrict__ ci, const double* __restrict__ v,
+                           const int64_t* __restrict__ off, int32_t* __restrict__ oc, double* __restrict__ ov,
+                           float* __restrict__ ov32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid / 16;
+  const int t = (int)(gid % 16);
+  if (k >= n) return;
+  const int64_t i = items[k];
+  const int64_t s0 = rp[i], len = rp[i + 1] - s0, p = off[k];
+  for (int64_t e = t; e < len; e += 16) {
+    oc[p + e] = ci[s0 + e];
+    const double a = v[s0 + e];
+    ov[p + e] = a;
+    if (ov32) ov32[p + e] = (float)a;
+  }
+}
+
+// The sweep-ordered copy of CSR level l (FP64 and, for the FP32 cycle, FP32).
+static ah_status csr_order_build(ah_hier* h, int l, hipStream_t st) {
+  AhLevel& L = h->lev[l];
+  const int64_t nF = L.n - L.nc;
+  if (!L.flist || !L.clist || L.n == 0) return AH_OK;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  int64_t *cnt = nullptr, *off = nullptr;
+  int32_t* oc = nullptr;
+  double* ov = nullptr;
+  ah_status rc = tmp.get(&cnt, L.n);
+  if (rc == AH_OK) rc = ar.get(&off, L.n + 1);
+  if (rc == AH_OK) rc = ar.get(&oc, std::max<int64_t>(L.nnz, 1));
+  if (rc == AH_OK) rc = ar.get(&ov, std::max<int64_t>(L.nnz, 1));
+  if (rc == AH_OK && h->prm.fp32_cycle) rc = ar.get(&L.coval32, std::max<int64_t>(L.nnz, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0) hipLaunchKernelGGL(k_cso_count, g1(nF), dim3(256), 0, st, nF, L.flist, L.rowptr, cnt);
+  if (L.nc > 0) hipLaunchKernelGGL(k_cso_count, g1(L.nc), dim3(256), 0, st, L.nc, L.clist, L.rowptr, cnt + nF);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: level order count"); return AH_EHIP; }
+  rc = scan_i64(cnt, off, L.n, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0)
+    hipLaunchKernelGGL(k_cso_copy, g1(nF * 16), dim3(256), 0, st, nF, L.flist, L.rowptr, L.col, L.val, off, oc, ov,
+                       L.coval32);
+  if (L.nc > 0)
+    hipLaunchKernelGGL(k_cso_copy, g1(L.nc * 16), dim3(256), 0, st, L.nc, L.clist, L.rowptr, L.col, L.val, off + nF,
+                       oc, ov, L.coval32);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: level order copy"); return AH_EHIP; }
+  tmp.release();
+  L.coptr = off;
+  L.cocol = oc;
+  L.coval = ov;
+  return AH_OK;
+}
+
 // The full-block view of level l (block size B) for its F and C sweeps, if
 // it stores at most 1.25 times the CSR entries; otherwise the level keeps
 // the CSR sweeps.  Also the F rows' stored values (sweep byte counts) and
@@ -2522,6 +2585,16 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       CK(block_view_build(h, 1, h->lev[0].ob, st, swo));
       prof_end(ps);
     }
+    // coarse levels swept from their lists without a full-block view: the
+    // sweep-ordered CSR copy (not the coarsest level, nor the tail's)
+    if (swo)
+      for (int l = 1; l + 1 < nl; ++l) {
+        if (h->lev[l].n < h->list_min || h->lev[l].bb || h->lev[l].n <= tail_max) continue;
+        ProfScope ps;
+        prof_begin(ps, "order_csr", st, 0.0);
+        CK(csr_order_build(h, l, st));
+        prof_end(ps);
+      }
     std::vector<TailLevel> tl(nl);
     for (int l = 0; l < nl; ++l) {
       const AhLevel& L = h->lev[l];

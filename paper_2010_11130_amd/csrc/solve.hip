@@ -35,6 +35,8 @@ enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWE
 //                  rows outside X get x_i = e[pc[i]]
 // MODE SP_SWEEP_LIST: the sweep on the rows listed in pc[0..n) only; other
 //                  rows of y are not written
+// MODE SP_SWEEP_ORD: SP_SWEEP_LIST on a copy of the listed rows stored in
+//                  list order: item ii's entries at rp[ii] .. rp[ii + 1]
 // y2 (sweeps, optional): the updated rows are also written there.
 // A values may be null (all ones).
 template <class TA, class TX, class TY, int G, int MODE>
@@ -47,13 +49,15 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   const int64_t ii = gid / G;
   const int g = (int)(gid % G);
   if (ii >= n) return;
-  const int64_t i = MODE == SP_SWEEP_LIST ? (int64_t)pc[ii] : ii;
-  constexpr bool SW = MODE == SP_SWEEP || MODE == SP_SWEEP_P || MODE == SP_SWEEP_LIST;
-  const bool active = MODE == SP_SWEEP_LIST || !SW || !cf || cf[i] == X;
+  constexpr bool LS = MODE == SP_SWEEP_LIST || MODE == SP_SWEEP_ORD;
+  const int64_t i = LS ? (int64_t)pc[ii] : ii;
+  constexpr bool SW = MODE == SP_SWEEP || MODE == SP_SWEEP_P || LS;
+  const bool active = LS || !SW || !cf || cf[i] == X;
   TY acc = 0;
   if (active) {
-    const int64_t k1 = rp[i + 1];
-    int64_t kb = rp[i] + g;
+    const int64_t kr = MODE == SP_SWEEP_ORD ? ii : i;
+    const int64_t k1 = rp[kr + 1];
+    int64_t kb = rp[kr] + g;
     if (MODE != SP_SWEEP_P && av) {
       // four independent column / value / x loads in flight per lane
       TY acc1 = 0, acc2 = 0, acc3 = 0;
@@ -1411,6 +1415,7 @@ struct Ops<double> {
   static const double* OT(const AhLevel& L) { return L.otval; }
   static const double* BX(const AhLevel& L) { return L.baux; }
   static const double* SO(const AhLevel& L) { return L.soval; }
+  static const double* CO(const AhLevel& L) { return L.coval; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -1427,6 +1432,7 @@ struct Ops<float> {
   static const float* OT(const AhLevel& L) { return L.otval32; }
   static const float* BX(const AhLevel& L) { return L.baux32; }
   static const float* SO(const AhLevel& L) { return L.soval32; }
+  static const float* CO(const AhLevel& L) { return L.coval32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -1663,6 +1669,19 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     if (nsw == 1) return AH_OK;
     AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, y, b, d, om, x, st, tf, fbr_sweep_bytes<T>(L, 0, true), out));
     AH_TRY(fbr_g<T>(L, av, ax, L.nc, L.clist, x, b, d, om, out, st, tc, fbr_sweep_bytes<T>(L, 1, false)));
+    return AH_OK;
+  }
+  if (l > 0 && L.coptr && Ops<T>::CO(L)) {
+    // the rows' entries in sweep order: the F rows, then the C rows
+    const T* co = Ops<T>::CO(L);
+    const T* d = Ops<T>::d(L);
+    AH_TRY((csr_g<T, T, T, SP_SWEEP_ORD>(G, nF, L.coptr, L.cocol, co, x, b, d, L.cf, 0, om, y, st, tf,
+                                         sweep_bytes<T>(L, 0), L.flist)));
+    if (nsw == 1) return AH_OK;
+    AH_TRY((csr_g<T, T, T, SP_SWEEP_ORD>(G, nF, L.coptr, L.cocol, co, y, b, d, L.cf, 0, om, x, st, tf,
+                                         sweep_bytes<T>(L, 0), L.flist, out)));
+    AH_TRY((csr_g<T, T, T, SP_SWEEP_ORD>(G, L.nc, L.coptr + nF, L.cocol, co, x, b, d, L.cf, 1, om, out, st, tc,
+                                         sweep_bytes<T>(L, 1), L.clist)));
     return AH_OK;
   }
   AH_TRY((csr_g<T, T, T, SP_SWEEP_LIST>(G, nF, L.rowptr, L.col, Ops<T>::A(L), x, b, Ops<T>::d(L), L.cf, 0, om, y,

@@ -116,6 +116,14 @@ struct AhLevel {
   // and its rows' values once more in sweep order (the F rows, then the C
   // rows, each in list order): item k's row at bsoff[k] of soval / soval32
   const int64_t* bsoff = nullptr;
+  // a coarse level swept from its point lists (no full-block view): its
+  // rows' entries once more in sweep order (the F rows, then the C rows,
+  // each in list order): item k's entries at coptr[k] .. coptr[k + 1] of
+  // cocol / coval / coval32
+  const int64_t* coptr = nullptr;
+  const int32_t* cocol = nullptr;
+  const double* coval = nullptr;
+  float* coval32 = nullptr;
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;

@@ -195,3 +195,35 @@ def test_pmis_rounds_paths(built, monkeypatch, name, block_air, listed):
         opc = np.full(ol.A.shape[0], -1)
         opc[np.repeat(np.arange(Pd.shape[0]), np.diff(Pd.indptr))] = Pd.indices
         assert np.array_equal(lv["pcol"].cpu().numpy(), opc), l
+
+
+@pytest.mark.parametrize("name", ["c1", "slab", "kuhn_nu4", "c5", "layer"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_coarse_list_sweeps_sweep_ordered(built, monkeypatch, name, fp32):
+    """Coarse levels swept from their lists at any size, no single-workgroup
+    tail (AH_LIST_MIN=0, AH_TAIL_MAX=0), scalar AIR: their sweeps read a copy
+    of the rows' entries in sweep order (F rows, then C rows).  The sums per
+    row are those of the list sweeps over the CSR (AH_SWO=0), so the cycle and
+    the solve agree bit for bit; the cycle also against the oracle's."""
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, fp32, flush=True)
+    monkeypatch.setenv("AH_LIST_MIN", "0")
+    monkeypatch.setenv("AH_TAIL_MAX", "0")
+    g, o = built(name)
+    prec = 1 if fp32 else 0
+    r = torch.as_tensor(np.random.default_rng(53).standard_normal(g.n), device="cuda")
+    out = {}
+    for swo in ("1", "0"):
+        monkeypatch.setenv("AH_SWO", swo)
+        H = Hierarchy(g, max_coarse=SMALL_COARSE, fp32_cycle=prec)
+        z = H.vcycle(r, precision=prec).cpu().numpy()
+        x, info = H.solve(tol=1e-10, precision=prec)
+        assert info["converged"]
+        out[swo] = (z, x.cpu().numpy(), info["iters"])
+    assert np.array_equal(out["1"][0], out["0"][0])
+    assert np.array_equal(out["1"][1], out["0"][1])
+    assert out["1"][2] == out["0"][2]
+    if not fp32:
+        OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE)
+        zo = oair.vcycle(OH, r.cpu().numpy())
+        assert np.linalg.norm(out["1"][0] - zo) <= 1e-10 * np.linalg.norm(zo)
