@@ -469,6 +469,68 @@ __device__ void gather_nn(int m, const int32_t* N, const int64_t* __restrict__ r
   __syncthreads();
 }
 
+// z <- T^-1 z for the m x m matrix T in LDS (row r at T[r m]) and nrhs
+// right-hand sides z[q zs + r]: LU with partial pivoting carried through the
+// right-hand sides, then back substitution.  Pivot: the largest |T[r][k]|,
+// r >= k, smallest row on ties; a pivot at or below 1e-14 of sc (the largest
+// |T|) marks the system bad, and later steps divide by 1 (the caller
+// discards the result).  Each elimination step runs a lane per (row,
+// column or right-hand side) pair with the row multipliers in f (LDS, m
+// entries); the back substitution goes by columns, a lane per (row,
+// right-hand side).  One wave; every lane calls it and gets the same result.
+__device__ bool lu_solve_wave(int m, double* T, double* z, int zs, int nrhs, double* f, double sc, int lane) {
+  bool bad = false;
+  for (int k = 0; k < m; ++k) {
+    double best = -1.0;
+    int bi = m;
+    for (int r = k + lane; r < m; r += 64) {
+      const double a = fabs(T[r * m + k]);
+      if (a > best) { best = a; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int p = bi;
+    if (fabs(T[p * m + k]) <= 1e-14 * sc) bad = true;
+    if (p != k) {
+      for (int c = lane; c < m; c += 64) {
+        const double t = T[k * m + c]; T[k * m + c] = T[p * m + c]; T[p * m + c] = t;
+      }
+      for (int q = lane; q < nrhs; q += 64) {
+        const double t = z[q * zs + k]; z[q * zs + k] = z[q * zs + p]; z[q * zs + p] = t;
+      }
+    }
+    __syncthreads();
+    const double pv = bad ? 1.0 : T[k * m + k];
+    for (int r = k + 1 + lane; r < m; r += 64) f[r] = T[r * m + k] / pv;
+    __syncthreads();
+    const int w = m - k - 1, nc = w + nrhs;
+    for (int t = lane; t < w * nc; t += 64) {
+      const int r = k + 1 + t / nc, cc = t % nc;
+      if (cc < w) {
+        T[r * m + k + 1 + cc] -= f[r] * T[k * m + k + 1 + cc];
+      } else {
+        const int q = cc - w;
+        z[q * zs + r] -= f[r] * z[q * zs + k];
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = m - 1; c >= 0; --c) {
+    const double dc = bad ? 1.0 : T[c * m + c];
+    for (int q = lane; q < nrhs; q += 64) z[q * zs + c] /= dc;
+    __syncthreads();
+    for (int t = lane; t < c * nrhs; t += 64) {
+      const int r = t / nrhs, q = t % nrhs;
+      z[q * zs + r] -= T[r * m + c] * z[q * zs + c];
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
 template <int MAXM, bool D2>
 __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const double* __restrict__ v, const uint8_t* __restrict__ strong,
@@ -481,6 +543,7 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
   __shared__ int s_m;
   __shared__ int s_pre[MAXM + 1];
   __shared__ int64_t s_st0[MAXM];
+  __shared__ double s_f[MAXM];
   int32_t* N = Nbuf;
   const int64_t ic = blockIdx.x;
   const int lane = threadIdx.x;
@@ -536,45 +599,7 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
   double sc = 0.0;
   for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
   sc = wave_max(sc);
-  bool bad = false;
-  for (int k = 0; k < m; ++k) {
-    // pivot: largest |T[r][k]|, r >= k, smallest row on ties
-    double best = -1.0;
-    int bi = m;
-    for (int r = k + lane; r < m; r += 64) {
-      double a = fabs(T[r * m + k]);
-      if (a > best) { best = a; bi = r; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ob = __shfl_xor(best, o, 64);
-      int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const int p = bi;
-    if (fabs(T[p * m + k]) <= 1e-14 * sc) bad = true;
-    if (p != k) {
-      for (int c = lane; c < m; c += 64) {
-        double t = T[k * m + c]; T[k * m + c] = T[p * m + c]; T[p * m + c] = t;
-      }
-      if (lane == 0) { double t = z[k]; z[k] = z[p]; z[p] = t; }
-    }
-    __syncthreads();
-    const double pv = bad ? 1.0 : T[k * m + k];
-    const double zk = z[k];
-    for (int r = k + 1 + lane; r < m; r += 64) {
-      double f = T[r * m + k] / pv;
-      for (int c = k + 1; c < m; ++c) T[r * m + c] -= f * T[k * m + c];
-      z[r] -= f * zk;
-    }
-    __syncthreads();
-  }
-  for (int c = m - 1; c >= 0; --c) {
-    double s = 0.0;
-    for (int j = c + 1 + lane; j < m; j += 64) s += T[c * m + j] * z[j];
-    s = wave_sum(s);
-    if (lane == 0) z[c] = (z[c] - s) / (bad ? 1.0 : T[c * m + c]);
-    __syncthreads();
-  }
+  const bool bad = lu_solve_wave(m, T, z, MAXM, 1, s_f, sc, lane);
   // row in increasing column order: N is sorted, the C point itself is not in N
   int ins = 0;
   for (int r = lane; r < m; r += 64) ins += N[r] < i;
@@ -597,8 +622,8 @@ __global__ __launch_bounds__(64) void k_lair(int64_t nc, const int64_t* __restri
 // b right-hand sides -A[i0 + r, N]^T are gathered in that order, T =
 // A[N, N]^T is factored once by LU with partial pivoting, and the
 // right-hand sides are carried through the same eliminations and back
-// substitutions as in k_lair, so each row gets the values k_lair would
-// give it.  *err is set if the rows of a block disagree on |N|.
+// substitutions as in k_lair (lu_solve_wave), so each row gets the values
+// k_lair would give it.  *err is set if the rows of a block disagree on |N|.
 constexpr int LB_BMAX = 10;
 
 template <int MAXM>
@@ -613,6 +638,7 @@ __global__ __launch_bounds__(64) void k_lair_blk(int64_t ncb, int b, const int64
   __shared__ double z[LB_BMAX * MAXM];
   __shared__ int s_pre[MAXM + 1];
   __shared__ int64_t s_st0[MAXM];
+  __shared__ double s_f[MAXM];
   const int64_t kb = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t i0 = clist[kb * b];
@@ -652,47 +678,7 @@ __global__ __launch_bounds__(64) void k_lair_blk(int64_t ncb, int b, const int64
   double sc = 0.0;
   for (int k = lane; k < m * m; k += 64) sc = fmax(sc, fabs(T[k]));
   sc = wave_max(sc);
-  bool bad = false;
-  for (int k = 0; k < m; ++k) {
-    double best = -1.0;
-    int bi = m;
-    for (int r = k + lane; r < m; r += 64) {
-      const double a = fabs(T[r * m + k]);
-      if (a > best) { best = a; bi = r; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const int p = bi;
-    if (fabs(T[p * m + k]) <= 1e-14 * sc) bad = true;
-    if (p != k) {
-      for (int c = lane; c < m; c += 64) {
-        const double t = T[k * m + c]; T[k * m + c] = T[p * m + c]; T[p * m + c] = t;
-      }
-      if (lane < b) {
-        const double t = z[lane * MAXM + k]; z[lane * MAXM + k] = z[lane * MAXM + p]; z[lane * MAXM + p] = t;
-      }
-    }
-    __syncthreads();
-    const double pv = bad ? 1.0 : T[k * m + k];
-    for (int r = k + 1 + lane; r < m; r += 64) {
-      const double f = T[r * m + k] / pv;
-      for (int c = k + 1; c < m; ++c) T[r * m + c] -= f * T[k * m + c];
-      for (int q = 0; q < b; ++q) z[q * MAXM + r] -= f * z[q * MAXM + k];
-    }
-    __syncthreads();
-  }
-  for (int c = m - 1; c >= 0; --c) {
-    for (int q = 0; q < b; ++q) {
-      double s = 0.0;
-      for (int j = c + 1 + lane; j < m; j += 64) s += T[c * m + j] * z[q * MAXM + j];
-      s = wave_sum(s);
-      if (lane == 0) z[q * MAXM + c] = (z[q * MAXM + c] - s) / (bad ? 1.0 : T[c * m + c]);
-    }
-    __syncthreads();
-  }
+  const bool bad = lu_solve_wave(m, T, z, MAXM, b, s_f, sc, lane);
   // rows in increasing column order: N is sorted and holds no row of the block
   int ins = 0;
   for (int r = lane; r < m; r += 64) ins += N[r] < i0;
