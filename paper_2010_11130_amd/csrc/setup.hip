@@ -711,6 +711,9 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
   __shared__ int32_t key[HS];
   __shared__ double val[NUMERIC ? HS : 1];
   __shared__ int s_cnt;
+  __shared__ int s_pre[65];
+  __shared__ int64_t s_st[64];
+  __shared__ double s_rv[64];
   const int64_t ic = blockIdx.x;
   const int lane = threadIdx.x;
   for (int k = lane; k < HS; k += 64) {
@@ -719,25 +722,52 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
   }
   if (lane == 0) s_cnt = 0;
   __syncthreads();
-  for (int64_t kr = Rptr[ic]; kr < Rptr[ic + 1]; ++kr) {
-    const int32_t j = Rcol[kr];
-    const double rv = NUMERIC ? Rval[kr] : 0.0;
-    for (int64_t k = rp[j] + lane; k < rp[j + 1]; k += 64) {
-      int32_t c = pcol[ci[k]];
+  // the rows of A named by up to 64 entries of the R row at once: a lane per
+  // (R entry, A entry) pair, the R entry from the prefix sums of the row
+  // lengths
+  const int64_t r0 = Rptr[ic], r1 = Rptr[ic + 1];
+  for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+    const int cl = (int)(r1 - c0 < 64 ? r1 - c0 : 64);
+    int len = 0;
+    int64_t s0 = 0;
+    double rv0 = 0.0;
+    if (lane < cl) {
+      const int32_t j = Rcol[c0 + lane];
+      s0 = rp[j];
+      len = (int)(rp[j + 1] - s0);
+      if (NUMERIC) rv0 = Rval[c0 + lane];
+    }
+    int inc = len;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane < cl) { s_pre[lane + 1] = inc; s_st[lane] = s0; s_rv[lane] = rv0; }
+    if (lane == 0) s_pre[0] = 0;
+    __syncthreads();
+    const int ne = s_pre[cl];
+    for (int e = lane; e < ne; e += 64) {
+      int lo = 0, hi = cl - 1;
+      while (lo < hi) {   // the last R entry whose row starts at or before e
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const int64_t k = s_st[lo] + (e - s_pre[lo]);
+      const int32_t c = pcol[ci[k]];
       if (c < 0) continue;
       uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
       while (true) {
-        int32_t prev = atomicCAS(&key[h], -1, c);
+        const int32_t prev = atomicCAS(&key[h], -1, c);
         if (prev == -1 || prev == c) {
           if (prev == -1) atomicAdd(&s_cnt, 1);
-          if (NUMERIC) atomicAdd(&val[h], rv * v[k]);
+          if (NUMERIC) atomicAdd(&val[h], s_rv[lo] * v[k]);
           break;
         }
         h = (h + 1) & (HS - 1);
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (!NUMERIC) {
     if (lane == 0) cnt[ic] = s_cnt;
     return;
@@ -795,7 +825,7 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
 // for all b coarse rows (k_rap reads it once per row); the own rows are
 // read once each.  One LDS hash on the coarse column holds b sums and a
 // mask of the rows that reached the column, so every coarse row gets the
-// columns and the sums (in the same order of additions) k_rap gives it.
+// columns k_rap gives it, and the same sums up to the order of additions.
 // NUMERIC = false counts the columns of each row; NUMERIC = true sums,
 // sorts by column and writes the b rows.
 template <int HS, bool NUMERIC, int B>
