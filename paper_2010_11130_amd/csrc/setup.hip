@@ -841,6 +841,9 @@ __global__ __launch_bounds__(64) void k_rap_blk(int64_t ncb, const int64_t* __re
   __shared__ double val[NUMERIC ? HS * B : 1];
   __shared__ int32_t sidx[NUMERIC ? HS : 1];
   __shared__ int s_cnt;
+  __shared__ int s_pre[65];
+  __shared__ int64_t s_st[64];
+  __shared__ double s_rv[NUMERIC ? 64 * B : 1];
   const int64_t r0 = (int64_t)blockIdx.x * B;
   const int lane = threadIdx.x;
   for (int k = lane; k < HS; k += 64) {
@@ -854,34 +857,95 @@ __global__ __launch_bounds__(64) void k_rap_blk(int64_t ncb, const int64_t* __re
   const int64_t i0 = clist[r0];
   const int64_t base0 = Rptr[r0];
   const int len = (int)(Rptr[r0 + 1] - base0);
-  for (int t = 0; t < len; ++t) {
-    const int32_t j = Rcol[base0 + t];
-    const bool own = j == (int32_t)i0;
-    for (int q = 0; q < (own ? B : 1); ++q) {
-      const int64_t row = own ? i0 + q : j;
-      double rv[B];
+  // the neighbourhood rows named by up to 64 R positions at once (a lane per
+  // (position, entry) pair, the position from the prefix sums of the row
+  // lengths), each with the b coefficients of the block's R rows; then the
+  // block's own rows i0 + q, row q with the coefficient of coarse row q only
+  int tpos = -1;
+  for (int t0 = 0; t0 < len; t0 += 64) {
+    const int cl = len - t0 < 64 ? len - t0 : 64;
+    int rl = 0;
+    int64_t s0 = 0;
+    if (lane < cl) {
+      const int32_t j = Rcol[base0 + t0 + lane];
+      if (j == (int32_t)i0) {
+        tpos = t0 + lane;
+      } else {
+        s0 = rp[j];
+        rl = (int)(rp[j + 1] - s0);
+      }
+      if (NUMERIC)
 #pragma unroll
-      for (int u = 0; u < B; ++u) rv[u] = NUMERIC ? Rval[Rptr[r0 + u] + t] : 0.0;
-      const uint32_t bits = own ? (1u << q) : ((1u << B) - 1u);
-      for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += 64) {
-        const int32_t c = pcol[ci[k]];
-        if (c < 0) continue;
-        uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
-        while (true) {
-          const int32_t prev = atomicCAS(&key[h], -1, c);
-          if (prev == -1 || prev == c) {
-            if (prev == -1) atomicAdd(&s_cnt, 1);
-            atomicOr(&tch[h], bits);
-            if (NUMERIC) {
-              if (own) atomicAdd(&val[h * B + q], rv[q] * v[k]);
-              else
+        for (int u = 0; u < B; ++u) s_rv[lane * B + u] = Rval[Rptr[r0 + u] + t0 + lane];
+    }
+    int inc = rl;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tt = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += tt;
+    }
+    if (lane < cl) { s_pre[lane + 1] = inc; s_st[lane] = s0; }
+    if (lane == 0) s_pre[0] = 0;
+    __syncthreads();
+    const int ne = s_pre[cl];
+    for (int e = lane; e < ne; e += 64) {
+      int lo = 0, hi = cl - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const int64_t k = s_st[lo] + (e - s_pre[lo]);
+      const int32_t c = pcol[ci[k]];
+      if (c < 0) continue;
+      uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
+      while (true) {
+        const int32_t prev = atomicCAS(&key[h], -1, c);
+        if (prev == -1 || prev == c) {
+          if (prev == -1) atomicAdd(&s_cnt, 1);
+          atomicOr(&tch[h], (1u << B) - 1u);
+          if (NUMERIC)
 #pragma unroll
-                for (int u = 0; u < B; ++u) atomicAdd(&val[h * B + u], rv[u] * v[k]);
-            }
-            break;
-          }
-          h = (h + 1) & (HS - 1);
+            for (int u = 0; u < B; ++u) atomicAdd(&val[h * B + u], s_rv[lo * B + u] * v[k]);
+          break;
         }
+        h = (h + 1) & (HS - 1);
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) tpos = max(tpos, __shfl_xor(tpos, o, 64));
+  if (tpos >= 0) {
+    int rl = 0;
+    int64_t s0 = 0;
+    if (lane < B) {
+      s0 = rp[i0 + lane];
+      rl = (int)(rp[i0 + lane + 1] - s0);
+      if (NUMERIC) s_rv[lane] = Rval[Rptr[r0 + lane] + tpos];
+    }
+    int inc = rl;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tt = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += tt;
+    }
+    if (lane < B) { s_pre[lane + 1] = inc; s_st[lane] = s0; }
+    if (lane == 0) s_pre[0] = 0;
+    __syncthreads();
+    const int ne = s_pre[B];
+    for (int e = lane; e < ne; e += 64) {
+      int q = 0;
+      while (q + 1 < B && s_pre[q + 1] <= e) ++q;
+      const int64_t k = s_st[q] + (e - s_pre[q]);
+      const int32_t c = pcol[ci[k]];
+      if (c < 0) continue;
+      uint32_t h = ((uint32_t)c * 2654435761u) & (HS - 1);
+      while (true) {
+        const int32_t prev = atomicCAS(&key[h], -1, c);
+        if (prev == -1 || prev == c) {
+          if (prev == -1) atomicAdd(&s_cnt, 1);
+          atomicOr(&tch[h], 1u << q);
+          if (NUMERIC) atomicAdd(&val[h * B + q], s_rv[q] * v[k]);
+          break;
+        }
+        h = (h + 1) & (HS - 1);
       }
     }
   }
