@@ -1427,10 +1427,11 @@ __global__ void k_block_expand(int64_t n, int b, const int8_t* __restrict__ sb, 
 
 // Scalar strong mask of the level-0 CSR from the block marks: entry (i, j)
 // is strong when blocks i/b != j/b are joined by a strong block slot (the
-// slots of a block row are sorted by column).  PG lanes per row.  Where the
-// row holds whole blocks in column order, entry t of the row is in the
-// row's block t / b, which is slot t / b (before the diagonal block) or
-// t / b - 1 (after it): that slot is tried first, then a binary search.
+// slots of a block row are sorted by column).  PG lanes per row.  The
+// scaled row holds the off-diagonal blocks in column order, b entries
+// each, and the single diagonal entry of the identity diagonal block, so
+// entry t is in slot t / b before the diagonal and (t - 1) / b after it:
+// that slot is tried first, then a binary search.
 __global__ __launch_bounds__(256) void k_block_mask(int64_t n, int b, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const int64_t* __restrict__ optr,
                                                     const int32_t* __restrict__ ocol,
@@ -1444,7 +1445,7 @@ __global__ __launch_bounds__(256) void k_block_mask(int64_t n, int b, const int6
   for (int64_t k = r0 + g; k < rp[i + 1]; k += PG) {
     const int32_t J = ci[k] / b;
     uint8_t f = 0;
-    const int64_t q = lo0 + (k - r0) / b - (J > I ? 1 : 0);
+    const int64_t q = lo0 + (J > I ? (k - r0 - 1) / b : (k - r0) / b);
     if (J != I && q >= lo0 && q <= hi0 && ocol[q] == J) {
       f = sb[q];
     } else if (J != I) {
@@ -1862,34 +1863,35 @@ __device__ __forceinline__ int32_t bfull_next(const int64_t* p, const int64_t* e
   return J;
 }
 
-template <int B>
-__device__ bool bfull_regular(const int64_t* p, const int64_t* e, const int32_t* __restrict__ ci) {
-  const int64_t len = e[0] - p[0];
-  if (len % B) return false;
-#pragma unroll
-  for (int q = 1; q < B; ++q)
-    if (e[q] - p[q] != len) return false;
-  for (int64_t t = 0; t < len; ++t) {
-    const int32_t J = ci[p[0] + t - t % B] / B;
-#pragma unroll
-    for (int q = 0; q < B; ++q)
-      if (ci[p[q] + t] != J * B + (int32_t)(t % B)) return false;
-  }
-  return true;
-}
-
 // Blocks of each block row (cnt), of which in the side array (acnt: all of
-// an irregular block row's, none of a regular one's).
+// an irregular block row's, none of a regular one's).  Eight lanes per
+// block row check the pattern; the first lane counts an irregular row's
+// blocks by the merge.
 template <int B>
 __global__ void k_bfull_count(int64_t nbr, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                               int64_t* __restrict__ cnt, int64_t* __restrict__ acnt) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = gid / 8;
+  const int g = (int)(gid % 8);
   if (I >= nbr) return;
   int64_t p[B], e[B];
 #pragma unroll
   for (int q = 0; q < B; ++q) { p[q] = rp[I * B + q]; e[q] = rp[I * B + q + 1]; }
-  if (bfull_regular<B>(p, e, ci)) {
-    cnt[I] = (e[0] - p[0]) / B;
+  const int64_t len = e[0] - p[0];
+  bool reg = len % B == 0;
+#pragma unroll
+  for (int q = 1; q < B; ++q) reg = reg && e[q] - p[q] == len;
+  if (reg)
+    for (int64_t t = g; t < len; t += 8) {
+      const int32_t J = ci[p[0] + t - t % B] / B;
+#pragma unroll
+      for (int q = 0; q < B; ++q) reg = reg && ci[p[q] + t] == J * B + (int32_t)(t % B);
+    }
+  int r = reg ? 1 : 0;
+  for (int o = 4; o > 0; o >>= 1) r &= __shfl_xor(r, o, 8);
+  if (g != 0) return;
+  if (r) {
+    cnt[I] = len / B;
     acnt[I] = 0;
     return;
   }
@@ -2092,9 +2094,9 @@ static ah_status block_view_build(ah_hier* h, int l, int B, hipStream_t st, bool
   if (rc == AH_OK) rc = h->arena.get(&voff, nbr);
   if (rc < 0) { tmp.release(); return rc; }
   switch (B) {
-    case 2: hipLaunchKernelGGL(k_bfull_count<2>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
-    case 3: hipLaunchKernelGGL(k_bfull_count<3>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
-    default: hipLaunchKernelGGL(k_bfull_count<6>, g1(nbr), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+    case 2: hipLaunchKernelGGL(k_bfull_count<2>, g1(nbr * 8), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+    case 3: hipLaunchKernelGGL(k_bfull_count<3>, g1(nbr * 8), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
+    default: hipLaunchKernelGGL(k_bfull_count<6>, g1(nbr * 8), dim3(256), 0, st, nbr, L.rowptr, L.col, cnt, acnt); break;
   }
   if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: block view count"); return AH_EHIP; }
   rc = scan_i64(cnt, bptr, nbr, st, tmp);
