@@ -790,6 +790,19 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
     base += __popcll(mask);
     __syncthreads();
   }
+  const int64_t o = cptr[ic];
+  if (tot <= 64) {
+    // at most one column per lane: its place in the row is the number of
+    // smaller columns (the columns are distinct)
+    if (lane < tot) {
+      const int32_t my = ck[lane];
+      int r = 0;
+      for (int j = 0; j < tot; ++j) r += ck[j] < my;
+      ccol[o + r] = my;
+      cval[o + r] = cv[lane];
+    }
+    return;
+  }
   int S = 1;
   while (S < tot) S <<= 1;
   for (int k = tot + lane; k < S; k += 64) ck[k] = 0x7fffffff;
@@ -811,7 +824,6 @@ __global__ __launch_bounds__(64) void k_rap(int64_t nc, const int64_t* __restric
       __syncthreads();
     }
   }
-  const int64_t o = cptr[ic];
   for (int k = lane; k < tot; k += 64) {
     ccol[o + k] = ck[k];
     cval[o + k] = cv[k];
@@ -979,6 +991,32 @@ __global__ __launch_bounds__(64) void k_rap_blk(int64_t ncb, const int64_t* __re
     if (occ) { key[pos] = kk; sidx[pos] = k; }
     base += __popcll(mask);
     __syncthreads();
+  }
+  if (tot <= 64) {
+    // at most one column per lane: its place in coarse row q is the number
+    // of smaller columns that row q reached (the columns are distinct)
+    if (lane < tot) {
+      const int32_t my = key[lane];
+      const int sl = sidx[lane];
+      const uint32_t mb = tch[sl];
+      int r[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) r[q] = 0;
+      for (int j = 0; j < tot; ++j)
+        if (key[j] < my) {
+          const uint32_t bj = tch[sidx[j]];
+#pragma unroll
+          for (int q = 0; q < B; ++q) r[q] += (bj >> q) & 1u;
+        }
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if ((mb >> q) & 1u) {
+          const int64_t o = cptr[r0 + q];
+          ccol[o + r[q]] = my;
+          cval[o + r[q]] = val[sl * B + q];
+        }
+    }
+    return;
   }
   int S = 1;
   while (S < tot) S <<= 1;
