@@ -237,3 +237,32 @@ def test_block_air_sweep_ordered_level0(monkeypatch, name, fp32, level1):
         OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b)
         zo = oair.vcycle(OH, r.cpu().numpy())
         assert np.linalg.norm(out["1"][0] - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("name", ["kuhn_nu4", "c5"])
+@pytest.mark.parametrize("level1", [False, True])
+def test_block_air_single_f_sweep(monkeypatch, name, level1):
+    """Block AIR with one F sweep per level (relax = 1, the oracle's "F"):
+    the sweep-ordered level-0 copy and (``level1``) level 1 by full blocks
+    stop after their first sweep.  One V-cycle against the oracle's to 1e-10
+    and the solve to 1e-10 of the oracle's."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, level1, flush=True)
+    if level1:
+        monkeypatch.setenv("AH_LIST_MIN", "0")
+        monkeypatch.setenv("AH_TAIL_MAX", "0")
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, relax=1)
+    assert (H.info["block_view_values"] > 0) == level1
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b, relax="F")
+    r = np.random.default_rng(13).standard_normal(g.n)
+    z = H.vcycle(torch.as_tensor(r, device="cuda")).cpu().numpy()
+    zo = oair.vcycle(OH, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    x, info = H.solve(tol=1e-12)
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
