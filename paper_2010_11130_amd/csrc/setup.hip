@@ -1843,6 +1843,68 @@ __global__ void k_so_copy(int64_t nbr, int B, const int32_t* __restrict__ perm, 
   }
 }
 
+// Level 0 under scalar AIR in sweep order: item k of the concatenated F and
+// C lists gets its row's values (nb B of them, row m of block row R at
+// (optr[R] B + m nb) B) at off[k]; counts first, then 16 lanes per row.
+__global__ void k_rso_count(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ optr,
+                            int64_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t R = items[k] / B;
+  cnt[k] = (optr[R + 1] - optr[R]) * B;
+}
+
+__global__ void k_rso_copy(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ optr,
+                           const double* __restrict__ ov, const int64_t* __restrict__ off, double* __restrict__ sov,
+                           float* __restrict__ sov32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid / 16;
+  const int t = (int)(gid % 16);
+  if (k >= n) return;
+  const int64_t i = items[k];
+  const int64_t R = i / B;
+  const int64_t len = (optr[R + 1] - optr[R]) * B;
+  const double* __restrict__ v = ov + optr[R] * B * B + (i - R * B) * len;
+  const int64_t p = off[k];
+  for (int64_t e = t; e < len; e += 16) {
+    const double a = v[e];
+    sov[p + e] = a;
+    if (sov32) sov32[p + e] = (float)a;
+  }
+}
+
+static ah_status row_order_build(ah_hier* h, hipStream_t st) {
+  AhLevel& L = h->lev[0];
+  const int B = L.ob;
+  const int64_t nF = L.n - L.nc;
+  if (L.fblk || B < 2 || !L.oval || !L.flist || !L.clist || L.n == 0) return AH_OK;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  int64_t *cnt = nullptr, *off = nullptr;
+  double* sov = nullptr;
+  ah_status rc = tmp.get(&cnt, L.n);
+  if (rc == AH_OK) rc = ar.get(&off, L.n + 1);
+  if (rc == AH_OK) rc = ar.get(&sov, std::max<int64_t>(L.nov, 1));
+  if (rc == AH_OK && h->prm.fp32_cycle) rc = ar.get(&L.soval32, std::max<int64_t>(L.nov, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0) hipLaunchKernelGGL(k_rso_count, g1(nF), dim3(256), 0, st, nF, L.flist, B, L.optr, cnt);
+  if (L.nc > 0) hipLaunchKernelGGL(k_rso_count, g1(L.nc), dim3(256), 0, st, L.nc, L.clist, B, L.optr, cnt + nF);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: row order count"); return AH_EHIP; }
+  rc = scan_i64(cnt, off, L.n, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  if (nF > 0)
+    hipLaunchKernelGGL(k_rso_copy, g1(nF * 16), dim3(256), 0, st, nF, L.flist, B, L.optr, L.oval, off, sov, L.soval32);
+  if (L.nc > 0)
+    hipLaunchKernelGGL(k_rso_copy, g1(L.nc * 16), dim3(256), 0, st, L.nc, L.clist, B, L.optr, L.oval, off + nF, sov,
+                       L.soval32);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: row order copy"); return AH_EHIP; }
+  tmp.release();
+  L.rsoff = off;
+  L.soval = sov;
+  return AH_OK;
+}
+
 static ah_status sweep_order_build(ah_hier* h, hipStream_t st) {
   AhLevel& L = h->lev[0];
   const int B = L.ob;
@@ -2697,6 +2759,13 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
       ProfScope ps;
       prof_begin(ps, "order0", st, 0.0);
       CK(sweep_order_build(h, st));
+      prof_end(ps);
+    }
+    // level 0 under scalar AIR with Jacobi sweeps: its rows in sweep order
+    if (swo && nl > 1 && !h->lev[0].fblk && h->lev[0].ob && prm.relax < 2) {
+      ProfScope ps;
+      prof_begin(ps, "order0", st, 0.0);
+      CK(row_order_build(h, st));
       prof_end(ps);
     }
     if (l1b && nl > 2 && h->lev[0].fblk && h->lev[1].n >= h->list_min) {

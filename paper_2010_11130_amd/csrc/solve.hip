@@ -116,23 +116,24 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
 // off-diagonal blocks of block row R, B contiguous values whose columns are
 // B ocol[s] + 0..B-1; one column index serves B values and all B rows of the
 // block row, so the row stream is the values alone.  Modes SP_MV, SP_RES and
-// SP_SWEEP_LIST as in k_csr, with d_i = 1.
+// SP_SWEEP_LIST as in k_csr, with d_i = 1; SP_SWEEP_ORD: SP_SWEEP_LIST with
+// item ii's values at soff[ii] of a copy of the listed rows in list order.
 template <class TA, class TX, class TY, int B, int G, int MODE>
 __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict__ optr,
                                             const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
                                             const TX* __restrict__ x, const TY* __restrict__ b, TY omega,
                                             TY* __restrict__ y, const int32_t* __restrict__ list,
-                                            TY* __restrict__ y2) {
+                                            TY* __restrict__ y2, const int64_t* __restrict__ soff) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / G;
   const int g = (int)(gid % G);
   if (ii >= n) return;
-  const int64_t i = MODE == SP_SWEEP_LIST ? (int64_t)list[ii] : ii;
+  const int64_t i = MODE == SP_SWEEP_LIST || MODE == SP_SWEEP_ORD ? (int64_t)list[ii] : ii;
   const int64_t R = i / B;
   const int m = (int)(i - R * B);
   const int64_t o0 = optr[R];
   const int len = (int)(optr[R + 1] - o0) * B;
-  const TA* __restrict__ v = ov + o0 * (B * B) + (int64_t)m * len;
+  const TA* __restrict__ v = MODE == SP_SWEEP_ORD ? ov + soff[ii] : ov + o0 * (B * B) + (int64_t)m * len;
   const int32_t* __restrict__ cb = ocol + o0;
   TY acc = 0, acc1 = 0, acc2 = 0, acc3 = 0;
   int e = g;
@@ -1202,12 +1203,13 @@ static int fb_lanes(int64_t nvals, int64_t n) {
 
 template <class TA, class TX, class TY, int MODE, int B>
 static void fb_launch(int G, dim3 grid, hipStream_t st, int64_t n, const int64_t* optr, const int32_t* ocol,
-                      const TA* ov, const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2) {
+                      const TA* ov, const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2,
+                      const int64_t* soff) {
   switch (G) {
-    case 2: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 2, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 4: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 4, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 8: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 8, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    default: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 16, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 2: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 2, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 4: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 4, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 8: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 8, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    default: hipLaunchKernelGGL((k_fb<TA, TX, TY, B, 16, MODE>), grid, dim3(256), 0, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
   }
 }
 
@@ -1216,18 +1218,18 @@ static void fb_launch(int G, dim3 grid, hipStream_t st, int64_t n, const int64_t
 template <class TA, class TX, class TY, int MODE>
 static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_t* ocol, const TA* ov, const TX* x,
                       const TY* b, TY omega, TY* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
-                      const int32_t* list = nullptr, TY* y2 = nullptr) {
+                      const int32_t* list = nullptr, TY* y2 = nullptr, const int64_t* soff = nullptr) {
   if (n == 0) return AH_OK;
   if (G != 2 && G != 4 && G != 8) G = 16;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   const dim3 grid((unsigned)cdiv(n * G, 256));
   switch (B) {
-    case 2: fb_launch<TA, TX, TY, MODE, 2>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 3: fb_launch<TA, TX, TY, MODE, 3>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 4: fb_launch<TA, TX, TY, MODE, 4>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 6: fb_launch<TA, TX, TY, MODE, 6>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 10: fb_launch<TA, TX, TY, MODE, 10>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 2: fb_launch<TA, TX, TY, MODE, 2>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 3: fb_launch<TA, TX, TY, MODE, 3>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 4: fb_launch<TA, TX, TY, MODE, 4>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 6: fb_launch<TA, TX, TY, MODE, 6>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
+    case 10: fb_launch<TA, TX, TY, MODE, 10>(G, grid, st, n, optr, ocol, ov, x, b, omega, y, list, y2, soff); break;
     default: set_error("unsupported facet block size %d", B); return AH_EUNSUPPORTED;
   }
   prof_end(ps);
@@ -1635,6 +1637,19 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
                                          fb_sweep_bytes<T>(L, 0, true), L.sperm, out)));
     AH_TRY((fbb_g<T, T, T, SP_SWEEP_ORD>(L.ob, lp, L.nc, L.soptr + nbF, L.socol, so, x, b, om, out, st, tc,
                                          fb_sweep_bytes<T>(L, 1, false), L.sperm + nbF)));
+    return AH_OK;
+  }
+  if (l == 0 && !L.fblk && L.rsoff && Ops<T>::SO(L)) {
+    // scalar AIR: the rows' values in sweep order (the F rows, then the C rows)
+    const T* so = Ops<T>::SO(L);
+    const int Gb = h->g0 ? h->g0 : fb_lanes(L.nov, L.n);
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_ORD>(L.ob, Gb, nF, L.optr, L.ocol, so, x, b, om, y, st, tf,
+                                        fb_sweep_bytes<T>(L, 0, false), L.flist, nullptr, L.rsoff)));
+    if (nsw == 1) return AH_OK;
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_ORD>(L.ob, Gb, nF, L.optr, L.ocol, so, y, b, om, x, st, tf,
+                                        fb_sweep_bytes<T>(L, 0, true), L.flist, out, L.rsoff)));
+    AH_TRY((fb_g<T, T, T, SP_SWEEP_ORD>(L.ob, Gb, L.nc, L.optr, L.ocol, so, x, b, om, out, st, tc,
+                                        fb_sweep_bytes<T>(L, 1, false), L.clist, nullptr, L.rsoff + nF)));
     return AH_OK;
   }
   if (l == 0 && L.ob && Ops<T>::O(L)) {

@@ -91,6 +91,9 @@ struct AhLevel {
   // sperm[k], its blocks at soptr[k] .. soptr[k + 1] of socol / soval
   const int32_t* sperm = nullptr;
   const int64_t* soptr = nullptr;
+  // scalar AIR: the values of the listed rows in sweep order instead (the F
+  // rows, then the C rows), item k's row at rsoff[k] of soval / soval32
+  const int64_t* rsoff = nullptr;
   const int32_t* socol = nullptr;
   const double* soval = nullptr;
   float* soval32 = nullptr;
