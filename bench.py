@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # kernels timed with HIP events inside the library (ah_profile_*)
 PROFILE_TAGS = ["element", "spmv0", "relax0_f", "relax0_c", "relax0_f_f32", "relax0_c_f32", "relax1_f", "relax1_c",
-                "relax1_f_f32", "relax1_c_f32", "rap0", "arnoldi_dot", "arnoldi_update"]
+                "relax1_f_f32", "relax1_c_f32", "restrict0", "restrict0_f32", "rap0", "arnoldi_dot",
+                "arnoldi_update"]
 METRIC = "DOF/s to 1e-8 rel. residual (setup+solve), FP32 vs FP64 V-cycle; HBM GB/s"
 
 
@@ -189,6 +190,8 @@ KERNEL_SOURCES = {"element": "paper_2010_11130_amd/csrc/assemble.hip",
                   "relax1_c": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax1_f_f32": "paper_2010_11130_amd/csrc/solve.hip",
                   "relax1_c_f32": "paper_2010_11130_amd/csrc/solve.hip",
+                  "restrict0": "paper_2010_11130_amd/csrc/solve.hip",
+                  "restrict0_f32": "paper_2010_11130_amd/csrc/solve.hip",
                   "arnoldi_dot": "paper_2010_11130_amd/csrc/solve.hip",
                   "arnoldi_update": "paper_2010_11130_amd/csrc/solve.hip",
                   "rap0": "paper_2010_11130_amd/csrc/setup.hip"}

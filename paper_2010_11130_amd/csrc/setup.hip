@@ -2076,6 +2076,124 @@ __global__ void k_bso_copy(int64_t n, const int32_t* __restrict__ items, int B, 
   }
 }
 
+// The restriction of a block AIR level, R = [Z I], by coarse blocks: the B
+// rows of coarse block k (fine block i0 / B, i0 = clist[k B]) hold the same
+// neighbourhood columns, whole F blocks in increasing order, and their own
+// column i0 + q with the value 1.  k_rz_count counts the neighbourhood
+// blocks and flags (*bad) a block row that is not of that form; k_rz_fill
+// writes Z's blocks (row q of block s at (zptr[k] B + q nb + s) B) and the
+// column blocks.  One thread per coarse block.
+__global__ void k_rz_count(int64_t ncb, int B, const int64_t* __restrict__ Rptr, int64_t* __restrict__ cnt,
+                           int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncb) return;
+  const int64_t len = Rptr[k * B + 1] - Rptr[k * B];
+  bool ok = len >= 1 && (len - 1) % B == 0;
+  for (int q = 1; q < B; ++q) ok = ok && Rptr[k * B + q + 1] - Rptr[k * B + q] == len;
+  cnt[k] = ok ? (len - 1) / B : 0;
+  if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_rz_fill(int64_t ncb, int B, const int64_t* __restrict__ Rptr, const int32_t* __restrict__ Rcol,
+                          const double* __restrict__ Rval, const int32_t* __restrict__ clist,
+                          const int64_t* __restrict__ zptr, int32_t* __restrict__ zcol, double* __restrict__ zval,
+                          int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncb) return;
+  const int64_t i0 = clist[k * B];
+  const int64_t z0 = zptr[k];
+  const int64_t nb = zptr[k + 1] - z0;
+  bool ok = i0 % B == 0;
+  for (int q = 0; q < B && ok; ++q) {
+    ok = ok && clist[k * B + q] == i0 + q;
+    const int64_t base = Rptr[k * B + q], len = Rptr[k * B + q + 1] - base;
+    int64_t pos = 0;
+    bool own = false;
+    for (int64_t t = 0; t < len && ok; ++t) {
+      const int32_t c = Rcol[base + t];
+      if (c >= i0 && c < i0 + B) {
+        ok = !own && c == i0 + q && Rval[base + t] == 1.0;
+        own = true;
+        continue;
+      }
+      const int64_t sb = pos / B;
+      const int cc = (int)(pos % B);
+      if (sb >= nb || c % B != cc) { ok = false; break; }
+      if (q == 0 && cc == 0) zcol[z0 + sb] = c / B;
+      else ok = ok && zcol[z0 + sb] == c / B;
+      zval[z0 * B * B + (q * nb + sb) * B + cc] = Rval[base + t];
+      ++pos;
+    }
+    ok = ok && own && pos == nb * B;
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+
+// Z of block AIR level 0 by coarse blocks for the restriction; left unbuilt
+// where a block row is not of the form (the CSR R is used then).
+static ah_status rz_build(ah_hier* h, hipStream_t st) {
+  AhLevel& L = h->lev[0];
+  const int B = L.ob;
+  if (!L.fblk || B < 2 || !L.clist || L.nc == 0 || L.nc % B) return AH_OK;
+  const int64_t ncb = L.nc / B;
+  Arena& ar = h->arena;
+  Arena tmp;
+  tmp.stream = st;
+  int64_t *cnt = nullptr, *zptr = nullptr;
+  int* bad = nullptr;
+  ah_status rc = tmp.get(&cnt, ncb);
+  if (rc == AH_OK) rc = tmp.get(&bad, 1);
+  if (rc == AH_OK) rc = ar.get(&zptr, ncb + 1);
+  if (rc < 0) { tmp.release(); return rc; }
+  if (hipMemsetAsync(bad, 0, sizeof(int), st) != hipSuccess) { tmp.release(); set_error("air_setup: R blocks"); return AH_EHIP; }
+  hipLaunchKernelGGL(k_rz_count, g1(ncb), dim3(256), 0, st, ncb, B, L.Rptr, cnt, bad);
+  if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: R blocks count"); return AH_EHIP; }
+  rc = scan_i64(cnt, zptr, ncb, st, tmp);
+  if (rc < 0) { tmp.release(); return rc; }
+  double* pin = pinned_scratch(2);
+  if (!pin) { tmp.release(); set_error("pinned host allocation failed"); return AH_ENOMEM; }
+  int hbad = 0;
+  int64_t nblk = 0;
+  if (hipMemcpyAsync(pin, zptr + ncb, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(reinterpret_cast<char*>(pin) + 8, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    tmp.release();
+    set_error("air_setup: R blocks readback");
+    return AH_EHIP;
+  }
+  std::memcpy(&nblk, pin, sizeof(nblk));
+  std::memcpy(&hbad, reinterpret_cast<char*>(pin) + 8, sizeof(hbad));
+  if (hbad) { tmp.release(); return AH_OK; }
+  const int64_t nv = nblk * B * B;
+  int32_t* zcol = nullptr;
+  double* zval = nullptr;
+  rc = ar.get(&zcol, std::max<int64_t>(nblk, 1));
+  if (rc == AH_OK) rc = ar.get(&zval, std::max<int64_t>(nv, 1));
+  if (rc < 0) { tmp.release(); return rc; }
+  hipLaunchKernelGGL(k_rz_fill, g1(ncb), dim3(256), 0, st, ncb, B, L.Rptr, L.Rcol, L.Rval, L.clist, zptr, zcol, zval,
+                     bad);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(reinterpret_cast<char*>(pin) + 8, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    tmp.release();
+    set_error("air_setup: R blocks fill");
+    return AH_EHIP;
+  }
+  std::memcpy(&hbad, reinterpret_cast<char*>(pin) + 8, sizeof(hbad));
+  tmp.release();
+  if (hbad) return AH_OK;
+  if (h->prm.fp32_cycle) {
+    AH_TRY(ar.get(&L.rzval32, std::max<int64_t>(nv, 1)));
+    if (nv > 0) hipLaunchKernelGGL(k_cast32, g1(nv), dim3(256), 0, st, nv, zval, L.rzval32);
+    AH_LAUNCHED();
+  }
+  L.rzptr = zptr;
+  L.rzcol = zcol;
+  L.rzval = zval;
+  L.nrz = nv;
+  return AH_OK;
+}
+
 // The rows of a CSR level copied in sweep order: item k of the concatenated
 // F and C lists gets its row's entries at off[k]; counts first, then the
 // copy with 16 lanes per row.
@@ -2751,14 +2869,22 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     // level 1 under block AIR: R A P with P = P_b (x) I and block lAIR rows
     // is made of ob x ob blocks; its F and C sweeps (list sweeps, not the
     // coarsest level) read it by full blocks (one column index per block)
-    bool l1b = true, swo = true;
+    bool l1b = true, swo = true, rzb = true;
     if (const char* e = std::getenv("AH_L1B")) l1b = std::atoi(e) != 0;
+    if (const char* e = std::getenv("AH_RZB")) rzb = std::atoi(e) != 0;
     if (const char* e = std::getenv("AH_SWO")) swo = std::atoi(e) != 0;
     // level 0 under block AIR with Jacobi sweeps: the sweep-ordered copy
     if (swo && nl > 1 && h->lev[0].fblk && prm.relax < 2 && h->fbb) {
       ProfScope ps;
       prof_begin(ps, "order0", st, 0.0);
       CK(sweep_order_build(h, st));
+      prof_end(ps);
+    }
+    // block AIR: the level-0 restriction by coarse blocks
+    if (rzb && nl > 1 && h->lev[0].fblk) {
+      ProfScope ps;
+      prof_begin(ps, "rz0", st, 0.0);
+      CK(rz_build(h, st));
       prof_end(ps);
     }
     // level 0 under scalar AIR with Jacobi sweeps: its rows in sweep order

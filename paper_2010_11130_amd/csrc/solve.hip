@@ -24,7 +24,8 @@
 
 namespace ah {
 
-enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5, SP_SWEEP_ORD = 6 };
+enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5, SP_SWEEP_ORD = 6,
+       SP_RESTRICT = 7 };
 
 // MODE SP_MV:      y = A x
 // MODE SP_RES:     y = b - A x
@@ -222,6 +223,9 @@ __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restric
 // whole blocks in increasing order (SP_SWEEP_LIST: block k is list[k B] / B),
 // or (SP_SWEEP_ORD) the block rows list[k] of a copy of the operator stored
 // in that order (item k's blocks at optr[k] .. optr[k + 1]); both sweep.
+// SP_RESTRICT: the restriction R = [Z I] of block AIR by coarse blocks k,
+// Z's blocks at optr[k] .. optr[k + 1], the identity on the fine block
+// list[k B] / B: y[k B + m] = x[R B + m] + (Z x)_m.
 template <class TA, class TX, class TY, int B, int LPB, int MODE>
 __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restrict__ optr,
                                              const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
@@ -232,8 +236,9 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   const int64_t kk = gid / LPB;
   const int g = (int)(gid % LPB);
   if (kk >= nbr) return;
-  const int64_t R = MODE == SP_SWEEP_LIST ? (int64_t)list[kk * B] / B : MODE == SP_SWEEP_ORD ? (int64_t)list[kk] : kk;
-  const int64_t ko = MODE == SP_SWEEP_ORD ? kk : R;
+  const int64_t R = MODE == SP_SWEEP_LIST || MODE == SP_RESTRICT ? (int64_t)list[kk * B] / B
+                    : MODE == SP_SWEEP_ORD ? (int64_t)list[kk] : kk;
+  const int64_t ko = MODE == SP_SWEEP_ORD || MODE == SP_RESTRICT ? kk : R;
   const int64_t o0 = optr[ko];
   const int nb = (int)(optr[ko + 1] - o0);
   const TA* __restrict__ v = ov + o0 * (B * B);
@@ -262,7 +267,9 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
     const int64_t i = R * B + m;
     const TY xi = (TY)x[i];
     const TY a = acc[m] + xi;
-    if (MODE == SP_MV) {
+    if (MODE == SP_RESTRICT) {
+      y[kk * B + m] = a;
+    } else if (MODE == SP_MV) {
       y[i] = a;
     } else if (MODE == SP_RES) {
       y[i] = b[i] - a;
@@ -1369,6 +1376,18 @@ static double fbr_sweep_bytes(const AhLevel& L, int X, bool y2) {
          (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 4.0 : 3.0) * w;
 }
 
+// Algorithmic bytes of the block restriction: Z's values, one column index
+// per block, the coarse-block offsets, the fine list, x on the neighbourhood
+// blocks and the own blocks once (at most all of x), the coarse vector
+// written.
+template <class T>
+static double rz_bytes(const AhLevel& L) {
+  const double w = sizeof(T);
+  const int64_t nblk = L.nrz / ((int64_t)L.ob * L.ob);
+  return (double)L.nrz * w + (double)nblk * 4.0 + (double)(L.nc / L.ob + 1) * 8.0 + (double)L.nc * 4.0 +
+         (double)L.n * w + (double)L.nc * w;
+}
+
 ah_status tail_image_build(ah_hier* h, hipStream_t st) {
   if (!h->tail_lds || h->tail0 < 0) return AH_OK;
   const int nlev = (int)h->lev.size();
@@ -1418,6 +1437,7 @@ struct Ops<double> {
   static const double* BX(const AhLevel& L) { return L.baux; }
   static const double* SO(const AhLevel& L) { return L.soval; }
   static const double* CO(const AhLevel& L) { return L.coval; }
+  static const double* RZ(const AhLevel& L) { return L.rzval; }
   static double* b(AhLevel& L) { return L.b; }
   static double* x(AhLevel& L) { return L.x; }
   static double* y(AhLevel& L) { return L.y; }
@@ -1435,6 +1455,7 @@ struct Ops<float> {
   static const float* BX(const AhLevel& L) { return L.baux32; }
   static const float* SO(const AhLevel& L) { return L.soval32; }
   static const float* CO(const AhLevel& L) { return L.coval32; }
+  static const float* RZ(const AhLevel& L) { return L.rzval32; }
   static float* b(AhLevel& L) { return L.b32; }
   static float* x(AhLevel& L) { return L.x32; }
   static float* y(AhLevel& L) { return L.y32; }
@@ -1570,8 +1591,16 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   AhLevel& C = h->lev[l + 1];
   const int G = (l == 0 && h->g0) ? h->g0 : (l > 0 && h->gc) ? h->gc : pick_g(L.nnz, L.n);
   const int GR = pick_g(L.nnzR, L.nc);
-  AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
-                                (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
+  if (l == 0 && L.rzptr && Ops<T>::RZ(L)) {
+    // block AIR: R = [Z I] by coarse blocks
+    const int lp = fbb_lanes(L.nrz, L.nc, L.ob);
+    AH_TRY((fbb_g<T, T, T, SP_RESTRICT>(L.ob, lp, L.nc, L.rzptr, L.rzcol, Ops<T>::RZ(L), b, (const T*)nullptr, (T)0,
+                                        Ops<T>::b(C), st, sizeof(T) == 8 ? "restrict0" : "restrict0_f32",
+                                        rz_bytes<T>(L), L.clist)));
+  } else {
+    AH_TRY((csr_g<T, T, T, SP_MV>(GR, L.nc, L.Rptr, L.Rcol, Ops<T>::R(L), b, (const T*)nullptr, (const T*)nullptr,
+                                  (const int8_t*)nullptr, 0, (T)0, Ops<T>::b(C), st)));
+  }
   T* ec = Ops<T>::e(C);
   AH_TRY(vcycle<T>(h, l + 1, Ops<T>::b(C), ec, st));
   const T om = (T)h->prm.omega;

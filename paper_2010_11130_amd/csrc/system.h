@@ -127,6 +127,14 @@ struct AhLevel {
   const int32_t* cocol = nullptr;
   const double* coval = nullptr;
   float* coval32 = nullptr;
+  // block AIR on level 0: R = [Z I] by coarse blocks, Z's b x b blocks (the
+  // neighbourhood F blocks) with row m of coarse block k at
+  // (rzptr[k] b + m nb) b, column blocks rzcol; null where not built
+  const int64_t* rzptr = nullptr;
+  const int32_t* rzcol = nullptr;
+  const double* rzval = nullptr;
+  float* rzval32 = nullptr;
+  int64_t nrz = 0;             // stored values of Z
   int64_t nnzR = 0;
   int64_t* Rptr = nullptr;
   int32_t* Rcol = nullptr;

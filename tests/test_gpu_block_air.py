@@ -266,3 +266,37 @@ def test_block_air_single_f_sweep(monkeypatch, name, level1):
     xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
     assert info["converged"]
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("name", ["kuhn_nu4", "kuhn_nu2", "c5", "slab"])
+def test_block_air_restriction_by_blocks(monkeypatch, name):
+    """Under block AIR the level-0 restriction R = [Z I] runs by coarse blocks
+    (Z's b x b blocks, one column index per block, the identity on the
+    block's own rows).  One V-cycle against the CSR restriction (AH_RZB=0)
+    to 1e-13 (the sums differ in order only) and against the oracle's to
+    1e-10, in FP64; the FP32 cycle within 4x the oracle's FP32 emulation;
+    the solve to 1e-10 of the oracle's."""
+    import torch
+    from paper_2010_11130_amd import Hierarchy
+    print("case", name, flush=True)
+    v, c, prob, p = case(name)
+    g = gpu_system(v, c, prob, p)
+    o = setup_problem(v, c, prob, p)
+    r = torch.as_tensor(np.random.default_rng(17).standard_normal(g.n), device="cuda")
+    z = {}
+    for rzb in ("1", "0"):
+        monkeypatch.setenv("AH_RZB", rzb)
+        H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, fp32_cycle=1)
+        z[rzb] = (H.vcycle(r).cpu().numpy(), H.vcycle(r, precision=1).cpu().numpy())
+        if rzb == "1":
+            x, info = H.solve(tol=1e-12)
+    OH = oair.setup(o.Shat, max_coarse=SMALL_COARSE, block_air=True, block=o.b)
+    zo = oair.vcycle(OH, r.cpu().numpy())
+    assert np.linalg.norm(z["1"][0] - z["0"][0]) <= 1e-13 * np.linalg.norm(z["0"][0])
+    assert np.linalg.norm(z["1"][0] - zo) <= 1e-10 * np.linalg.norm(zo)
+    z32 = oair.vcycle(OH, r.cpu().numpy(), dtype=np.float32).astype(np.float64)
+    err32 = np.linalg.norm(z32 - zo) / np.linalg.norm(zo)
+    assert np.linalg.norm(z["1"][1] - zo) / np.linalg.norm(zo) <= 4.0 * err32 + 1e-12
+    xo, io = air_fgmres_solve(o, tol=1e-12, hier=OH)
+    assert info["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
