@@ -442,6 +442,42 @@ def test_c3_full_size_block_air_headline(c3_mesh):
     _block_air_level0_sampled(H, 3, 0.25)
 
 
+def test_c3_full_size_block_air_paths_agree(c3_mesh, monkeypatch):
+    """The headline's hierarchy at full size, one V-cycle of a random vector
+    in FP64 and FP32 through each of the paths the library picks for it,
+    against the paths they replace: the sweeps from the copies in sweep
+    order (level 0 by block rows, level 1 by full blocks, the coarse CSR
+    levels) bit for bit equal to the list sweeps over the natural order
+    (AH_SWO=0); the level-0 restriction by coarse blocks and level 1 by
+    full blocks within 1e-13 of their CSR forms (AH_RZB=0, AH_L1B=0: the
+    same sums in another order)."""
+    from paper_2010_11130_amd import Hierarchy
+    from workloads.problems import SmoothPlusFront
+    v, m, fv, bf, kinds = c3_mesh
+    print("case C3 full size, block AIR paths", flush=True)
+    s = _system(m, v, fv, bf, kinds, SmoothPlusFront(1e-4), 1, keep=False)
+    r = torch.as_tensor(np.random.default_rng(23).standard_normal(s.n), device="cuda")
+    z = {}
+    for name, env in (("default", {}), ("lists", {"AH_SWO": "0"}), ("csr", {"AH_SWO": "0", "AH_RZB": "0", "AH_L1B": "0"})):
+        for k in ("AH_SWO", "AH_RZB", "AH_L1B"):
+            monkeypatch.delenv(k, raising=False)
+        for k, val in env.items():
+            monkeypatch.setenv(k, val)
+        H = Hierarchy(s, block_air=1, fp32_cycle=1)
+        if name == "default":
+            assert H.info["block_view_values"] > 0
+        z[name] = (H.vcycle(r).cpu().numpy(), H.vcycle(r, precision=1).cpu().numpy())
+        del H
+        torch.cuda.empty_cache()
+    for q in (0, 1):
+        assert np.array_equal(z["default"][q], z["lists"][q]), q
+    d64 = np.linalg.norm(z["lists"][0] - z["csr"][0]) / np.linalg.norm(z["csr"][0])
+    d32 = np.linalg.norm(z["lists"][1] - z["csr"][1]) / np.linalg.norm(z["csr"][1])
+    print("block forms against CSR forms: FP64 %.2e, FP32 %.2e" % (d64, d32), flush=True)
+    assert d64 <= 1e-13
+    assert d32 <= 1e-6      # 1.6e-7 on this mesh: FP32 rounding in another order
+
+
 @pytest.mark.parametrize("nu", [0.0, 1e-4])
 def test_c4_fp32_cycle_full_slab_vs_oracle(nu):
     """The precision form on the C2 slab shape (342,528 DOFs) at nu = 0 and
