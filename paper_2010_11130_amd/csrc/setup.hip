@@ -2046,7 +2046,8 @@ __global__ void k_bfull_fill(int64_t nbr, const int64_t* __restrict__ rp, const 
 
 // The rows of a level read by full blocks, copied in sweep order: item k of
 // the concatenated F and C lists gets its row's values (nb B of them) at
-// off[k]; cnt_k first, then the copy with 16 lanes per row.
+// off[k]; cnt_k first, then the copy with 16 lanes per row, which also
+// writes the item's record (value offset, first block column, blocks).
 __global__ void k_bso_count(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ bptr,
                             int64_t* __restrict__ cnt) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2058,17 +2059,25 @@ __global__ void k_bso_count(int64_t n, const int32_t* __restrict__ items, int B,
 __global__ void k_bso_copy(int64_t n, const int32_t* __restrict__ items, int B, const int64_t* __restrict__ bptr,
                            const int64_t* __restrict__ voff, const double* __restrict__ av,
                            const double* __restrict__ ax, const int64_t* __restrict__ off, double* __restrict__ sov,
-                           float* __restrict__ sov32) {
+                           float* __restrict__ sov32, AhRowRec* __restrict__ rec) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = gid / 16;
   const int t = (int)(gid % 16);
   if (k >= n) return;
   const int64_t i = items[k];
   const int64_t R = i / B;
-  const int64_t len = (bptr[R + 1] - bptr[R]) * B;
+  const int64_t nb = bptr[R + 1] - bptr[R];
+  const int64_t len = nb * B;
   const int64_t vo = voff[R];
   const double* __restrict__ v = (vo >= 0 ? av + vo : ax + ~vo) + (i - R * B) * len;
   const int64_t p = off[k];
+  if (t == 0) {
+    AhRowRec r;
+    r.voff = p;
+    r.o0 = (int32_t)bptr[R];
+    r.nb = (int32_t)nb;
+    rec[k] = r;
+  }
   for (int64_t e = t; e < len; e += 16) {
     const double a = v[e];
     sov[p + e] = a;
@@ -2271,10 +2280,14 @@ static ah_status block_view_order(ah_hier* h, int l, hipStream_t st) {
   Arena& ar = h->arena;
   Arena tmp;
   tmp.stream = st;
+  // the records hold the first block column of a row as int32
+  if (L.nbv / ((int64_t)B * B) >= (int64_t)INT32_MAX) return AH_OK;
   int64_t *cnt = nullptr, *off = nullptr;
+  AhRowRec* rec = nullptr;
   double* sov = nullptr;
   ah_status rc = tmp.get(&cnt, std::max<int64_t>(L.n, 1));
-  if (rc == AH_OK) rc = ar.get(&off, L.n + 1);
+  if (rc == AH_OK) rc = tmp.get(&off, L.n + 1);
+  if (rc == AH_OK) rc = ar.get(&rec, std::max<int64_t>(L.n, 1));
   if (rc == AH_OK) rc = ar.get(&sov, std::max<int64_t>(L.nbv, 1));
   if (rc == AH_OK && h->prm.fp32_cycle) rc = ar.get(&L.soval32, std::max<int64_t>(L.nbv, 1));
   if (rc < 0) { tmp.release(); return rc; }
@@ -2285,13 +2298,13 @@ static ah_status block_view_order(ah_hier* h, int l, hipStream_t st) {
   if (rc < 0) { tmp.release(); return rc; }
   if (nF > 0)
     hipLaunchKernelGGL(k_bso_copy, g1(nF * 16), dim3(256), 0, st, nF, L.flist, B, L.bptr, L.bvoff, L.val, L.baux, off,
-                       sov, L.soval32);
+                       sov, L.soval32, rec);
   if (L.nc > 0)
     hipLaunchKernelGGL(k_bso_copy, g1(L.nc * 16), dim3(256), 0, st, L.nc, L.clist, B, L.bptr, L.bvoff, L.val, L.baux,
-                       off + nF, sov, L.soval32);
+                       off + nF, sov, L.soval32, rec + nF);
   if (hipGetLastError() != hipSuccess) { tmp.release(); set_error("air_setup: level order copy"); return AH_EHIP; }
   tmp.release();
-  L.bsoff = off;
+  L.bsrec = rec;
   L.soval = sov;
   return AH_OK;
 }

@@ -54,6 +54,13 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
   const int64_t i = LS ? (int64_t)pc[ii] : ii;
   constexpr bool SW = MODE == SP_SWEEP || MODE == SP_SWEEP_P || LS;
   const bool active = LS || !SW || !cf || cf[i] == X;
+  // the listed sweeps load the row's own x, b and d before the gather
+  TY xpre = 0, bpre = 0, dpre = 0;
+  if (LS) {
+    xpre = (TY)x[i];
+    bpre = b[i];
+    dpre = d[i];
+  }
   TY acc = 0;
   if (active) {
     const int64_t kr = MODE == SP_SWEEP_ORD ? ii : i;
@@ -101,11 +108,12 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
       const int32_t c = pc[i];
       xi = c >= 0 ? (TY)x[c] : (TY)0;
     } else {
-      xi = (TY)x[i];
+      xi = LS ? xpre : (TY)x[i];
     }
     if (active) {
-      TY di = d[i];
-      if (fabs((double)di) >= 1e-30) xi += omega * (b[i] - acc) / di;
+      const TY di = LS ? dpre : d[i];
+      const TY bi = LS ? bpre : b[i];
+      if (fabs((double)di) >= 1e-30) xi += omega * (bi - acc) / di;
       if (y2) y2[i] = xi;
     }
     y[i] = xi;
@@ -130,6 +138,9 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
   const int g = (int)(gid % G);
   if (ii >= n) return;
   const int64_t i = MODE == SP_SWEEP_LIST || MODE == SP_SWEEP_ORD ? (int64_t)list[ii] : ii;
+  // the row's own x and b, loaded by every lane ahead of the gather
+  const TY xi = (TY)x[i];
+  const TY bi = MODE == SP_MV ? (TY)0 : b[i];
   const int64_t R = i / B;
   const int m = (int)(i - R * B);
   const int64_t o0 = optr[R];
@@ -153,14 +164,13 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
   if (g != 0) return;
-  const TY xi = (TY)x[i];
   acc += xi;
   if (MODE == SP_MV) {
     y[i] = acc;
   } else if (MODE == SP_RES) {
-    y[i] = b[i] - acc;
+    y[i] = bi - acc;
   } else {
-    const TY xn = xi + omega * (b[i] - acc);
+    const TY xn = xi + omega * (bi - acc);
     y[i] = xn;
     if (y2) y2[i] = xn;
   }
@@ -173,30 +183,71 @@ __global__ __launch_bounds__(256) void k_fb(int64_t n, const int64_t* __restrict
 // rows with the diagonal d, as k_csr.  LP lanes per row, a lane per block
 // (s = g, g + LP, ...): a lane reads the block's column index, the row's B
 // contiguous values of the block and the B contiguous values of x (wide
-// loads: a third of the load instructions of a lane per value).  ORD: the
-// values of item k are the row's values in a copy in sweep order, at
-// voff[k] of av (ax unused).
+// loads: a third of the load instructions of a lane per value).  ORD: item
+// k's row is described by rec[k] (its values at rec[k].voff of a copy in
+// sweep order in av, its blocks from bcol[rec[k].o0]), one load that does
+// not wait for the list.  The row's own x, b and d are loaded before the
+// gather and a lane takes two blocks per step, so that the loads of a wave
+// wait on three latencies rather than one per block; the sum runs in block
+// order, as one block at a time would.
 template <class TA, class TX, class TY, int B, int LP, bool ORD>
 __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ bptr, const int32_t* __restrict__ bcol,
-                                             const int64_t* __restrict__ voff, const TA* __restrict__ av,
-                                             const TA* __restrict__ ax, const TX* __restrict__ x,
-                                             const TY* __restrict__ b, const TY* __restrict__ d, TY omega,
-                                             TY* __restrict__ y, TY* __restrict__ y2) {
+                                             const int64_t* __restrict__ voff, const AhRowRec* __restrict__ rec,
+                                             const TA* __restrict__ av, const TA* __restrict__ ax,
+                                             const TX* __restrict__ x, const TY* __restrict__ b,
+                                             const TY* __restrict__ d, TY omega, TY* __restrict__ y,
+                                             TY* __restrict__ y2) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ii = gid / LP;
   const int g = (int)(gid % LP);
   if (ii >= n) return;
   const int64_t i = list[ii];
-  const int64_t R = i / B;
-  const int m = (int)(i - R * B);
-  const int64_t o0 = bptr[R];
-  const int nb = (int)(bptr[R + 1] - o0);
-  const int64_t vo = voff[ORD ? ii : R];
-  const TA* __restrict__ v = ORD ? av + vo : (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * nb * B;
+  int64_t o0;
+  int nb;
+  const TA* __restrict__ v;
+  if (ORD) {
+    const AhRowRec r = rec[ii];
+    o0 = r.o0;
+    nb = r.nb;
+    v = av + r.voff;
+  } else {
+    const int64_t R = i / B;
+    const int m = (int)(i - R * B);
+    o0 = bptr[R];
+    nb = (int)(bptr[R + 1] - o0);
+    const int64_t vo = voff[R];
+    v = (vo >= 0 ? av + vo : ax + ~vo) + (int64_t)m * nb * B;
+  }
+  // every lane loads them (one address per row): no branch for the
+  // compiler to wait behind
+  TY xi = (TY)x[i];
+  const TY bi = b[i], di = d[i];
   const int32_t* __restrict__ cb = bcol + o0;
   TY acc = 0;
-  for (int sl = g; sl < nb; sl += LP) {
+  int sl = g;
+  for (; sl + LP < nb; sl += 2 * LP) {
+    const int64_t J0 = cb[sl], J1 = cb[sl + LP];
+    const TA* __restrict__ v0 = v + sl * B;
+    const TA* __restrict__ v1 = v0 + LP * B;
+    TA a0[B], a1[B];
+    TX x0[B], x1[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      a0[c] = v0[c];
+      a1[c] = v1[c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      x0[c] = x[J0 * B + c];
+      x1[c] = x[J1 * B + c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) acc += (TY)a0[c] * (TY)x0[c];
+#pragma unroll
+    for (int c = 0; c < B; ++c) acc += (TY)a1[c] * (TY)x1[c];
+  }
+  if (sl < nb) {
     const int64_t J = cb[sl];
     const TA* __restrict__ vr = v + sl * B;
 #pragma unroll
@@ -205,9 +256,7 @@ __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restric
 #pragma unroll
   for (int o = LP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LP);
   if (g != 0) return;
-  TY xi = (TY)x[i];
-  const TY di = d[i];
-  if (fabs((double)di) >= 1e-30) xi += omega * (b[i] - acc) / di;
+  if (fabs((double)di) >= 1e-30) xi += omega * (bi - acc) / di;
   if (y2) y2[i] = xi;
   y[i] = xi;
 }
@@ -242,6 +291,26 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   const int64_t o0 = optr[ko];
   const int nb = (int)(optr[ko + 1] - o0);
   const TA* __restrict__ v = ov + o0 * (B * B);
+  // with a lane per row of the block row, its own x and b are loaded before
+  // the gather (their latency overlaps it)
+  // (fewer lanes than rows, small blocks: every lane loads all B of them)
+  constexpr bool PRE = LPB >= B;
+  constexpr bool PALL = !PRE && B <= 4;
+  constexpr bool NB = MODE != SP_MV && MODE != SP_RESTRICT;
+  TY xpre = 0, bpre = 0;
+  TY xall[PALL ? B : 1], ball[PALL ? B : 1];
+  if (PRE) {
+    const int64_t ip = R * B + (g < B ? g : B - 1);
+    xpre = (TY)x[ip];
+    if (NB) bpre = b[ip];
+  }
+  if (PALL) {
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      xall[m] = (TY)x[R * B + m];
+      ball[m] = NB ? b[R * B + m] : (TY)0;
+    }
+  }
   TY acc[B];
 #pragma unroll
   for (int m = 0; m < B; ++m) acc[m] = 0;
@@ -265,16 +334,17 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   for (int m = 0; m < B; ++m) {
     if (m % LPB != g) continue;      // lane m mod LPB writes row m
     const int64_t i = R * B + m;
-    const TY xi = (TY)x[i];
+    const TY xi = PRE ? xpre : PALL ? xall[PALL ? m : 0] : (TY)x[i];
+    const TY bi = PRE ? bpre : PALL ? ball[PALL ? m : 0] : NB ? b[i] : (TY)0;
     const TY a = acc[m] + xi;
     if (MODE == SP_RESTRICT) {
       y[kk * B + m] = a;
     } else if (MODE == SP_MV) {
       y[i] = a;
     } else if (MODE == SP_RES) {
-      y[i] = b[i] - a;
+      y[i] = bi - a;
     } else {
-      const TY xn = xi + omega * (b[i] - a);
+      const TY xn = xi + omega * (bi - a);
       y[i] = xn;
       if (y2) y2[i] = xn;
     }
@@ -1252,7 +1322,7 @@ static ah_status fb_g(int B, int G, int64_t n, const int64_t* optr, const int32_
 template <class T>
 static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, const int32_t* list, const T* x,
                        const T* b, const T* d, T omega, T* y, hipStream_t st, const char* tag, double bytes,
-                       T* y2 = nullptr, const int64_t* soff = nullptr) {
+                       T* y2 = nullptr, const AhRowRec* rec = nullptr) {
   if (n == 0) return AH_OK;
   const int LP = L.blp ? L.blp : sizeof(T) == 8 ? 4 : 2;
   ProfScope ps;
@@ -1260,12 +1330,12 @@ static ah_status fbr_g(const AhLevel& L, const T* av, const T* ax, int64_t n, co
   const dim3 grid((unsigned)cdiv(n * LP, 256));
 #define FBR(BB, LL)                                                                                         \
   do {                                                                                                      \
-    if (soff)                                                                                               \
-      hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL, true>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol, soff, \
-                         av, ax, x, b, d, omega, y, y2);                                                    \
+    if (rec)                                                                                                \
+      hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL, true>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol,   \
+                         (const int64_t*)nullptr, rec, av, ax, x, b, d, omega, y, y2);                      \
     else                                                                                                    \
       hipLaunchKernelGGL((k_fbr<T, T, T, BB, LL, false>), grid, dim3(256), 0, st, n, list, L.bptr, L.bcol,  \
-                         L.bvoff, av, ax, x, b, d, omega, y, y2);                                           \
+                         L.bvoff, (const AhRowRec*)nullptr, av, ax, x, b, d, omega, y, y2);                 \
   } while (0)
 #define FBR_L(BB) switch (LP) { case 2: FBR(BB, 2); break; case 4: FBR(BB, 4); break; default: FBR(BB, 8); break; }
   switch (L.bb) {
@@ -1365,15 +1435,17 @@ static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
 }
 
 // The same for a sweep of a coarse level read by full blocks: the X rows'
-// values, every block column index and block-row offset and value base, the list,
+// values, every block column index, the block-row offsets and value bases
+// (or, from the copy in sweep order, the X rows' 16-byte records), the list,
 // x once, b and d on X, the X updates written (twice with a second output).
 template <class T>
 static double fbr_sweep_bytes(const AhLevel& L, int X, bool y2) {
   const double w = sizeof(T);
   const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
   const int64_t nvX = X == 0 ? L.nbvF : L.nbv - L.nbvF;
-  return (double)nvX * w + (double)(L.nbv / (L.bb * L.bb)) * 4.0 + (double)(L.n / L.bb) * 16.0 + 8.0 +
-         (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 4.0 : 3.0) * w;
+  const double rows = L.bsrec ? (double)nX * 16.0 : (double)(L.n / L.bb) * 16.0 + 8.0;
+  return (double)nvX * w + (double)(L.nbv / (L.bb * L.bb)) * 4.0 + rows + (double)nX * 4.0 + (double)L.n * w +
+         (double)nX * (y2 ? 4.0 : 3.0) * w;
 }
 
 // Algorithmic bytes of the block restriction: Z's values, one column index
@@ -1697,16 +1769,16 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     const T* av = Ops<T>::A(L);
     const T* ax = Ops<T>::BX(L);
     const T* d = Ops<T>::d(L);
-    if (Ops<T>::SO(L) && L.bsoff) {
+    if (Ops<T>::SO(L) && L.bsrec) {
       // from the copy in sweep order: the F rows, then the C rows
       const T* so = Ops<T>::SO(L);
       AH_TRY(fbr_g<T>(L, so, so, nF, L.flist, x, b, d, om, y, st, tf, fbr_sweep_bytes<T>(L, 0, false), nullptr,
-                      L.bsoff));
+                      L.bsrec));
       if (nsw == 1) return AH_OK;
       AH_TRY(fbr_g<T>(L, so, so, nF, L.flist, y, b, d, om, x, st, tf, fbr_sweep_bytes<T>(L, 0, true), out,
-                      L.bsoff));
+                      L.bsrec));
       AH_TRY(fbr_g<T>(L, so, so, L.nc, L.clist, x, b, d, om, out, st, tc, fbr_sweep_bytes<T>(L, 1, false), nullptr,
-                      L.bsoff + nF));
+                      L.bsrec + nF));
       return AH_OK;
     }
     AH_TRY(fbr_g<T>(L, av, ax, nF, L.flist, x, b, d, om, y, st, tf, fbr_sweep_bytes<T>(L, 0, false)));

@@ -60,6 +60,15 @@ constexpr int WAVE = 64;
 
 }  // namespace ah
 
+// Where one row of a coarse level read by full blocks sits in the sweep-ordered
+// copy: the row's values from voff, its nb block columns from bcol[o0]; one
+// 16-byte load per row.
+struct alignas(16) AhRowRec {
+  int64_t voff;
+  int32_t o0;
+  int32_t nb;
+};
+
 // One level of the AIR hierarchy (scalar CSR, int64 row offsets).
 struct AhLevel {
   int64_t n = 0, nnz = 0;
@@ -117,8 +126,9 @@ struct AhLevel {
   const double* baux = nullptr;
   float* baux32 = nullptr;
   // and its rows' values once more in sweep order (the F rows, then the C
-  // rows, each in list order): item k's row at bsoff[k] of soval / soval32
-  const int64_t* bsoff = nullptr;
+  // rows, each in list order): item k's row at bsrec[k].voff of soval /
+  // soval32, its block columns at bcol[bsrec[k].o0 ..], bsrec[k].nb of them
+  const AhRowRec* bsrec = nullptr;
   // a coarse level swept from its point lists (no full-block view): its
   // rows' entries once more in sweep order (the F rows, then the C rows,
   // each in list order): item k's entries at coptr[k] .. coptr[k + 1] of
