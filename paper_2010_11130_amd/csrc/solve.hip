@@ -77,12 +77,20 @@ __global__ __launch_bounds__(256) void k_csr(int64_t n, const int64_t* __restric
         acc2 += a2 * (TY)x[c2];
         acc3 += a3 * (TY)x[c3];
       }
-      if (kb + G < k1) {   // two more in flight
-        const int32_t c0 = ci[kb], c1 = ci[kb + G];
-        const TY a0 = (TY)av[kb], a1 = (TY)av[kb + G];
+      if (kb < k1) {
+        // the last one to three entries of the lane in one step: the loads
+        // are clamped to the row's last entry (no branch between them) and
+        // the entries past the row weigh zero
+        const int64_t l = k1 - 1;
+        const int64_t q1 = kb + G < l ? kb + G : l, q2 = kb + 2 * G < l ? kb + 2 * G : l;
+        const int32_t c0 = ci[kb], c1 = ci[q1], c2 = ci[q2];
+        TY a0 = (TY)av[kb], a1 = (TY)av[q1], a2 = (TY)av[q2];
+        a1 = kb + G < k1 ? a1 : (TY)0;
+        a2 = kb + 2 * G < k1 ? a2 : (TY)0;
         acc += a0 * (TY)x[c0];
         acc1 += a1 * (TY)x[c1];
-        kb += 2 * G;
+        acc2 += a2 * (TY)x[c2];
+        kb = k1;
       }
       acc += (acc1 + acc2) + acc3;
     }
