@@ -26,8 +26,12 @@ hipEvent_t get_event() {
     pool.pop_back();
     return e;
   }
+  // timing only (read after the stream has been synchronized): no
+  // system-scope fence at each record, whose cache writeback would both
+  // stall the stream between the bracketed launches and start the next
+  // launch with cold caches
   hipEvent_t e;
-  (void)hipEventCreate(&e);
+  (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
   return e;
 }
 }  // namespace
