@@ -1843,6 +1843,38 @@ __global__ void k_so_copy(int64_t nbr, int B, const int32_t* __restrict__ perm, 
   }
 }
 
+// The column encodings of the sweep-ordered copy for sweeps that read P e_c
+// from e_c: with block one-point P, block J of P e_c is coarse block
+// pcol[J B] / B of e_c (rows in order), or zero where pcol[J B] < 0; a C
+// block's is its own coarse block.  An F column block is named by its F
+// item (fpos: the sweeps keep the F blocks' values compact).  16 lanes per
+// item.
+__global__ void k_so_fpos(int64_t nbF, const int32_t* __restrict__ perm, int32_t* __restrict__ fpos) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbF) fpos[perm[k]] = (int32_t)k;
+}
+
+__global__ void k_so_enc(int64_t nbr, int B, const int32_t* __restrict__ perm, const int64_t* __restrict__ soptr,
+                         const int32_t* __restrict__ socol, const int32_t* __restrict__ pcol,
+                         const int8_t* __restrict__ cf, const int32_t* __restrict__ fpos,
+                         int32_t* __restrict__ socp, int32_t* __restrict__ soce, int32_t* __restrict__ soown) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid / 16;
+  const int t = (int)(gid % 16);
+  if (k >= nbr) return;
+  for (int64_t o = soptr[k] + t; o < soptr[k + 1]; o += 16) {
+    const int64_t J = socol[o];
+    const int32_t pj = pcol[J * B];
+    const int32_t cj = pj >= 0 ? pj / B : -1;
+    socp[o] = cj;
+    soce[o] = cf[J * B] ? ~cj : fpos[J];
+  }
+  if (t == 0) {
+    const int32_t pr = pcol[(int64_t)perm[k] * B];
+    soown[k] = pr >= 0 ? pr / B : -1;
+  }
+}
+
 // Level 0 under scalar AIR in sweep order: item k of the concatenated F and
 // C lists gets its row's values (nb B of them, row m of block row R at
 // (optr[R] B + m nb) B) at off[k]; counts first, then 16 lanes per row.
@@ -1939,6 +1971,26 @@ static ah_status sweep_order_build(ah_hier* h, hipStream_t st) {
   L.soptr = soptr;
   L.socol = socol;
   L.soval = sov;
+  // the encodings for the sweeps without an interpolation pass
+  if (L.pcol && L.cf && nbC > 0) {
+    int32_t *socp = nullptr, *soce = nullptr, *soown = nullptr, *fpos = nullptr;
+    Arena tmp2;
+    tmp2.stream = st;
+    rc = ar.get(&socp, std::max<int64_t>(nblk, 1));
+    if (rc == AH_OK) rc = ar.get(&soce, std::max<int64_t>(nblk, 1));
+    if (rc == AH_OK) rc = ar.get(&soown, std::max<int64_t>(nbr, 1));
+    if (rc == AH_OK) rc = tmp2.get(&fpos, std::max<int64_t>(nbr, 1));
+    if (rc < 0) { tmp2.release(); return rc; }
+    if (nbF > 0) hipLaunchKernelGGL(k_so_fpos, g1(nbF), dim3(256), 0, st, nbF, perm, fpos);
+    hipLaunchKernelGGL(k_so_enc, g1(nbr * 16), dim3(256), 0, st, nbr, B, perm, soptr, socol, L.pcol, L.cf, fpos,
+                       socp, soce, soown);
+    const bool bad = hipGetLastError() != hipSuccess;
+    tmp2.release();
+    if (bad) { set_error("air_setup: sweep order encodings"); return AH_EHIP; }
+    L.socp = socp;
+    L.soce = soce;
+    L.soown = soown;
+  }
   return AH_OK;
 }
 

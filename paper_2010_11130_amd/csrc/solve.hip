@@ -25,7 +25,7 @@
 namespace ah {
 
 enum { SP_MV = 0, SP_RES = 1, SP_SWEEP = 2, SP_ADDMV = 3, SP_SWEEP_P = 4, SP_SWEEP_LIST = 5, SP_SWEEP_ORD = 6,
-       SP_RESTRICT = 7 };
+       SP_RESTRICT = 7, SP_SO_P = 8, SP_SO_E = 9, SP_SO_C = 10 };
 
 // MODE SP_MV:      y = A x
 // MODE SP_RES:     y = b - A x
@@ -283,22 +283,41 @@ __global__ __launch_bounds__(256) void k_fbr(int64_t n, const int32_t* __restric
 // SP_RESTRICT: the restriction R = [Z I] of block AIR by coarse blocks k,
 // Z's blocks at optr[k] .. optr[k + 1], the identity on the fine block
 // list[k B] / B: y[k B + m] = x[R B + m] + (Z x)_m.
+// SP_SO_P, SP_SO_E, SP_SO_C: SP_SWEEP_ORD where the iterate is P e_c, or
+// P e_c on the C blocks and the F blocks' values on the F blocks, with
+// e_c = xc and block one-point P (a copy of coarse blocks), read without
+// forming P e_c; the F blocks' values are kept compact, F item k's block at
+// k B.  SP_SO_P takes column blocks J >= 0 as coarse blocks of xc (J < 0:
+// zero) and the own block from xc at own[k]; SP_SO_E and SP_SO_C take
+// J >= 0 as compact F block J of x and J < 0 as coarse block ~J of xc, the
+// own block from x at k B (SP_SO_E) or, for the C blocks in coarse order,
+// from coarse block k of xc (SP_SO_C).  SP_SO_P and SP_SO_E write y compact
+// (y2 at the rows' own places), SP_SO_C writes y at the rows' places.  The
+// sums are the ones SP_SWEEP_ORD forms on the interpolated vector.
 template <class TA, class TX, class TY, int B, int LPB, int MODE>
 __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restrict__ optr,
                                              const int32_t* __restrict__ ocol, const TA* __restrict__ ov,
                                              const TX* __restrict__ x, const TY* __restrict__ b, TY omega,
                                              TY* __restrict__ y, const int32_t* __restrict__ list,
-                                             TY* __restrict__ y2) {
+                                             TY* __restrict__ y2, const TX* __restrict__ xc,
+                                             const int32_t* __restrict__ own) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t kk = gid / LPB;
   const int g = (int)(gid % LPB);
   if (kk >= nbr) return;
+  constexpr bool SO = MODE == SP_SO_P || MODE == SP_SO_E || MODE == SP_SO_C;
   const int64_t R = MODE == SP_SWEEP_LIST || MODE == SP_RESTRICT ? (int64_t)list[kk * B] / B
-                    : MODE == SP_SWEEP_ORD ? (int64_t)list[kk] : kk;
-  const int64_t ko = MODE == SP_SWEEP_ORD || MODE == SP_RESTRICT ? kk : R;
+                    : MODE == SP_SWEEP_ORD || SO ? (int64_t)list[kk] : kk;
+  const int64_t ko = MODE == SP_SWEEP_ORD || MODE == SP_RESTRICT || SO ? kk : R;
   const int64_t o0 = optr[ko];
   const int nb = (int)(optr[ko + 1] - o0);
   const TA* __restrict__ v = ov + o0 * (B * B);
+  // the own block's values: from xc (clamped to coarse block 0 and zeroed
+  // where P gives none) or from x
+  constexpr bool oc = MODE == SP_SO_P || MODE == SP_SO_C;
+  const int64_t po = MODE == SP_SO_P ? (int64_t)own[kk] : MODE == SP_SO_C ? kk : 0;
+  const TX* __restrict__ xo = oc ? xc + (int64_t)(po >= 0 ? po : 0) * B : x + (MODE == SP_SO_E ? kk : R) * B;
+  const bool oz = oc && po < 0;
   // with a lane per row of the block row, its own x and b are loaded before
   // the gather (their latency overlaps it)
   // (fewer lanes than rows, small blocks: every lane loads all B of them)
@@ -308,14 +327,16 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   TY xpre = 0, bpre = 0;
   TY xall[PALL ? B : 1], ball[PALL ? B : 1];
   if (PRE) {
-    const int64_t ip = R * B + (g < B ? g : B - 1);
-    xpre = (TY)x[ip];
-    if (NB) bpre = b[ip];
+    const int gp = g < B ? g : B - 1;
+    const TY t = (TY)xo[gp];   // loaded in every case: no branch before the wait
+    xpre = oz ? (TY)0 : t;
+    if (NB) bpre = b[R * B + gp];
   }
   if (PALL) {
 #pragma unroll
     for (int m = 0; m < B; ++m) {
-      xall[m] = (TY)x[R * B + m];
+      const TY t = (TY)xo[m];
+      xall[m] = oz ? (TY)0 : t;
       ball[m] = NB ? b[R * B + m] : (TY)0;
     }
   }
@@ -325,8 +346,21 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   for (int sl = g; sl < nb; sl += LPB) {
     const int64_t J = ocol[o0 + sl];
     TY xv[B];
+    if (MODE == SP_SO_P) {
+      const TX* __restrict__ xs = xc + (J >= 0 ? J : 0) * B;
 #pragma unroll
-    for (int c = 0; c < B; ++c) xv[c] = (TY)x[J * B + c];
+      for (int c = 0; c < B; ++c) {
+        const TY t = (TY)xs[c];   // loaded in every case: no branch before the wait
+        xv[c] = J >= 0 ? t : (TY)0;
+      }
+    } else if (MODE == SP_SO_E || MODE == SP_SO_C) {
+      const TX* __restrict__ xs = J >= 0 ? x + J * B : xc + (~J) * B;
+#pragma unroll
+      for (int c = 0; c < B; ++c) xv[c] = (TY)xs[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < B; ++c) xv[c] = (TY)x[J * B + c];
+    }
 #pragma unroll
     for (int m = 0; m < B; ++m) {
       const TA* __restrict__ vr = v + ((int64_t)m * nb + sl) * B;
@@ -342,7 +376,7 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
   for (int m = 0; m < B; ++m) {
     if (m % LPB != g) continue;      // lane m mod LPB writes row m
     const int64_t i = R * B + m;
-    const TY xi = PRE ? xpre : PALL ? xall[PALL ? m : 0] : (TY)x[i];
+    const TY xi = PRE ? xpre : PALL ? xall[PALL ? m : 0] : oz ? (TY)0 : (TY)xo[m];
     const TY bi = PRE ? bpre : PALL ? ball[PALL ? m : 0] : NB ? b[i] : (TY)0;
     const TY a = acc[m] + xi;
     if (MODE == SP_RESTRICT) {
@@ -353,7 +387,7 @@ __global__ __launch_bounds__(256) void k_fbb(int64_t nbr, const int64_t* __restr
       y[i] = bi - a;
     } else {
       const TY xn = xi + omega * (bi - a);
-      y[i] = xn;
+      y[MODE == SP_SO_P || MODE == SP_SO_E ? kk * B + m : i] = xn;
       if (y2) y2[i] = xn;
     }
   }
@@ -1370,9 +1404,10 @@ static int fbb_lanes(int64_t nvals, int64_t n, int B) {
 
 template <class TA, class TX, class TY, int MODE, int B>
 static void fbb_launch(int L, int64_t nbr, hipStream_t st, const int64_t* optr, const int32_t* ocol, const TA* ov,
-                       const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2) {
+                       const TX* x, const TY* b, TY omega, TY* y, const int32_t* list, TY* y2, const TX* xc,
+                       const int32_t* own) {
 #define FBB(LP) hipLaunchKernelGGL((k_fbb<TA, TX, TY, B, LP, MODE>), dim3((unsigned)cdiv(nbr * LP, 256)), dim3(256), 0, \
-                                   st, nbr, optr, ocol, ov, x, b, omega, y, list, y2)
+                                   st, nbr, optr, ocol, ov, x, b, omega, y, list, y2, xc, own)
   switch (L) {
     case 2: FBB(2); break;
     case 4: FBB(4); break;
@@ -1386,18 +1421,19 @@ static void fbb_launch(int L, int64_t nbr, hipStream_t st, const int64_t* optr, 
 template <class TA, class TX, class TY, int MODE>
 static ah_status fbb_g(int B, int L, int64_t n, const int64_t* optr, const int32_t* ocol, const TA* ov, const TX* x,
                        const TY* b, TY omega, TY* y, hipStream_t st, const char* tag = nullptr, double bytes = 0.0,
-                       const int32_t* list = nullptr, TY* y2 = nullptr) {
+                       const int32_t* list = nullptr, TY* y2 = nullptr, const TX* xc = nullptr,
+                       const int32_t* own = nullptr) {
   if (n == 0) return AH_OK;
   if (n % B) { set_error("block-row sweep over %lld rows, not whole blocks of %d", (long long)n, B); return AH_EINVAL; }
   const int64_t nbr = n / B;
   ProfScope ps;
   prof_begin(ps, tag, st, bytes);
   switch (B) {
-    case 2: fbb_launch<TA, TX, TY, MODE, 2>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 3: fbb_launch<TA, TX, TY, MODE, 3>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 4: fbb_launch<TA, TX, TY, MODE, 4>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 6: fbb_launch<TA, TX, TY, MODE, 6>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
-    case 10: fbb_launch<TA, TX, TY, MODE, 10>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2); break;
+    case 2: fbb_launch<TA, TX, TY, MODE, 2>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2, xc, own); break;
+    case 3: fbb_launch<TA, TX, TY, MODE, 3>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2, xc, own); break;
+    case 4: fbb_launch<TA, TX, TY, MODE, 4>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2, xc, own); break;
+    case 6: fbb_launch<TA, TX, TY, MODE, 6>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2, xc, own); break;
+    case 10: fbb_launch<TA, TX, TY, MODE, 10>(L, nbr, st, optr, ocol, ov, x, b, omega, y, list, y2, xc, own); break;
     default: set_error("unsupported facet block size %d", B); return AH_EUNSUPPORTED;
   }
   prof_end(ps);
@@ -1433,13 +1469,18 @@ static double sweep_bytes(const AhLevel& L, int X) {
 // The same for a level-0 sweep in the off-diagonal facet-block layout: the
 // X rows' values, every block column index and block-row offset, the list,
 // x once, b on X, the X updates written (twice with a second output).
+// With xc (the sweeps reading P e_c from e_c): the iterate read once is e_c
+// (first F sweep) or x on F and e_c on C, and the first F sweep reads the
+// F blocks' coarse blocks under P.
 template <class T>
-static double fb_sweep_bytes(const AhLevel& L, int X, bool y2) {
+static double fb_sweep_bytes(const AhLevel& L, int X, bool y2, int xc = 0) {
   const double w = sizeof(T);
   const int64_t nX = X == 0 ? L.nF : L.n - L.nF;
   const int64_t nvX = X == 0 ? L.novF : L.nov - L.novF;
+  const double xonce = xc == 1 ? (double)L.nc * w : (double)L.n * w;
+  const double own = xc == 1 ? (double)(nX / L.ob) * 4.0 : 0.0;
   return (double)nvX * w + (double)(L.nov / (L.ob * L.ob)) * 4.0 + (double)(L.n / L.ob + 1) * 8.0 +
-         (double)nX * 4.0 + (double)L.n * w + (double)nX * (y2 ? 3.0 : 2.0) * w;
+         (double)nX * 4.0 + xonce + own + (double)nX * (y2 ? 3.0 : 2.0) * w;
 }
 
 // The same for a sweep of a coarse level read by full blocks: the X rows'
@@ -1725,8 +1766,13 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
   }
   T* x = Ops<T>::x(L);
   T* y = nsw == 1 ? out : Ops<T>::y(L);
-  hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
-  AH_LAUNCHED();
+  // block AIR on level 0 with the encoded copy: the sweeps read P e_c from
+  // e_c, so P e_c is never formed
+  const bool pfree = l == 0 && nsw == 3 && L.sperm && L.soce && Ops<T>::SO(L);
+  if (!pfree) {
+    hipLaunchKernelGGL((k_interp2<T>), g1(L.n), dim3(256), 0, st, L.n, L.pcol, ec, x, y);
+    AH_LAUNCHED();
+  }
   // level-0 timing tags, and level 1's where it is read by full blocks
   const bool t1 = l == 1 && L.bb;
   const char* tf = l == 0 ? (sizeof(T) == 8 ? "relax0_f" : "relax0_f_f32")
@@ -1739,6 +1785,16 @@ static ah_status vcycle(ah_hier* h, int l, const T* b, T* out, hipStream_t st) {
     const T* so = Ops<T>::SO(L);
     const int lp = h->lpb ? h->lpb : fbb_lanes(L.nov, L.n, L.ob);
     const int64_t nbF = nF / L.ob;
+    if (pfree) {
+      // F1: P e_c -> y; F2: y on F, e_c on C -> x and out; C: x on F, e_c on C -> out
+      AH_TRY((fbb_g<T, T, T, SP_SO_P>(L.ob, lp, nF, L.soptr, L.socp, so, ec, b, om, y, st, tf,
+                                      fb_sweep_bytes<T>(L, 0, false, 1), L.sperm, nullptr, ec, L.soown)));
+      AH_TRY((fbb_g<T, T, T, SP_SO_E>(L.ob, lp, nF, L.soptr, L.soce, so, y, b, om, x, st, tf,
+                                      fb_sweep_bytes<T>(L, 0, true, 2), L.sperm, out, ec, nullptr)));
+      AH_TRY((fbb_g<T, T, T, SP_SO_C>(L.ob, lp, L.nc, L.soptr + nbF, L.soce, so, x, b, om, out, st, tc,
+                                      fb_sweep_bytes<T>(L, 1, false, 2), L.sperm + nbF, nullptr, ec)));
+      return AH_OK;
+    }
     AH_TRY((fbb_g<T, T, T, SP_SWEEP_ORD>(L.ob, lp, nF, L.soptr, L.socol, so, x, b, om, y, st, tf,
                                          fb_sweep_bytes<T>(L, 0, false), L.sperm)));
     if (nsw == 1) return AH_OK;

@@ -106,6 +106,17 @@ struct AhLevel {
   const int32_t* socol = nullptr;
   const double* soval = nullptr;
   float* soval32 = nullptr;
+  // block AIR, for sweeps that read the interpolated correction P e_c from
+  // e_c itself (one-point P copies coarse blocks): per block o of the copy,
+  // socp[o] the coarse block that P copies into column block socol[o] (-1:
+  // none, zero) and soce[o] = the F item of an F column block (its values
+  // kept compact), ~(its coarse block) for a C one; soown[k] the coarse
+  // block P copies into item k's
+  // own block row (-1: none; a C item k >= nbF is coarse block k - nbF, since
+  // the C list is in coarse order)
+  const int32_t* socp = nullptr;
+  const int32_t* soce = nullptr;
+  const int32_t* soown = nullptr;
   // the transposed operator in the same layout (adjoint cycle): block (I, J)
   // holds the transpose of block (J, I); null where the CSR A^T is used
   double* otval = nullptr;
