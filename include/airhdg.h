@@ -267,6 +267,11 @@ typedef struct {
                                  the zero fill of block rows whose rows do
                                  not share one block pattern; 0 where level 1
                                  is swept by CSR rows */
+  int64_t level0_no_interp_pass; /* 1 where the level-0 F and C sweeps (block
+                                 AIR, F, F, C Jacobi, copy in sweep order)
+                                 read the one-point interpolated correction
+                                 P e_c from e_c itself, with no pass forming
+                                 P e_c; 0 otherwise */
 } ah_setup_info;
 
 /* Environment (read by air_setup; for tests and tuning): AH_TAIL_MAX (rows,

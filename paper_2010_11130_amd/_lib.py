@@ -32,7 +32,7 @@ class AirParams(C.Structure):
 class SetupInfo(C.Structure):
     _fields_ = [("levels", C.c_int), ("n", C.c_int64 * 32), ("nnz", C.c_int64 * 32),
                 ("n_fallback", C.c_int64), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
-                ("block_view_values", C.c_int64)]
+                ("block_view_values", C.c_int64), ("level0_no_interp_pass", C.c_int64)]
 
 
 class SolveParams(C.Structure):

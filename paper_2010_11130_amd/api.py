@@ -288,7 +288,8 @@ class Hierarchy:
         self.info = {"levels": info.levels, "n": list(info.n[:info.levels]),
                      "nnz": list(info.nnz[:info.levels]), "n_fallback": info.n_fallback,
                      "op_complexity": info.op_complexity, "t_setup_ms": info.t_setup_ms,
-                     "block_view_values": info.block_view_values}
+                     "block_view_values": info.block_view_values,
+                     "level0_no_interp_pass": info.level0_no_interp_pass}
 
     def __del__(self, _destroy=destroy):
         if getattr(self, "h", None):

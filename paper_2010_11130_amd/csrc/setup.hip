@@ -3057,6 +3057,7 @@ extern "C" ah_status air_setup(const ah_system* s, const ah_air_params* prm_in, 
     info->n_fallback = h->nfallback;
     info->op_complexity = h->lev[0].nnz ? tot / (double)h->lev[0].nnz : 0.0;
     info->block_view_values = h->lev.size() > 1 ? h->lev[1].nbv : 0;
+    info->level0_no_interp_pass = h->lev.size() > 1 && h->lev[0].soce && h->prm.relax == 0 ? 1 : 0;
     info->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   *out = h;

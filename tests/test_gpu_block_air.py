@@ -204,11 +204,13 @@ def test_block_air_level1_full_block_sweeps(level1_lists, monkeypatch, name, fp3
 @pytest.mark.parametrize("level1", [False, True])
 def test_block_air_sweep_ordered_level0(monkeypatch, name, fp32, level1):
     """Level 0 under block AIR is swept from a copy with its block rows in
-    sweep order (F blocks, then C blocks), and level 1 (when it is read by
-    full blocks: ``level1``, coarse levels swept from their lists at any
-    size) from a copy of its F rows, then its C rows.  The sums per row are
-    the same as over the natural order with the F and C lists (AH_SWO=0), so
-    the cycle and the solve agree bit for bit; the cycle also against the
+    sweep order (F blocks, then C blocks), reading the interpolated
+    correction from the coarse vector and the F blocks' values from compact
+    vectors, and level 1 (when it is read by full blocks: ``level1``, coarse
+    levels swept from their lists at any size) from a copy of its F rows,
+    then its C rows.  The sums per row are the same as over the natural order
+    with the F and C lists after an interpolation pass (AH_SWO=0), so the
+    cycle and the solve agree bit for bit; the cycle also against the
     oracle's."""
     import torch
     from paper_2010_11130_amd import Hierarchy
@@ -226,6 +228,8 @@ def test_block_air_sweep_ordered_level0(monkeypatch, name, fp32, level1):
         monkeypatch.setenv("AH_SWO", swo)
         H = Hierarchy(g, max_coarse=SMALL_COARSE, block_air=1, fp32_cycle=prec)
         assert (H.info["block_view_values"] > 0) == level1
+        # the copy in sweep order comes with the sweeps that read P e_c from e_c
+        assert H.info["level0_no_interp_pass"] == (1 if swo == "1" else 0)
         z = H.vcycle(r, precision=prec).cpu().numpy()
         x, info = H.solve(tol=1e-10, precision=prec)
         assert info["converged"]

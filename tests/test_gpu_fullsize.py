@@ -466,6 +466,7 @@ def test_c3_full_size_block_air_paths_agree(c3_mesh, monkeypatch):
         H = Hierarchy(s, block_air=1, fp32_cycle=1)
         if name == "default":
             assert H.info["block_view_values"] > 0
+        assert H.info["level0_no_interp_pass"] == (1 if name == "default" else 0)
         z[name] = (H.vcycle(r).cpu().numpy(), H.vcycle(r, precision=1).cpu().numpy())
         del H
         torch.cuda.empty_cache()
