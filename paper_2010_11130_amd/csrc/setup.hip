@@ -90,8 +90,10 @@ __global__ __launch_bounds__(256) void k_pmis_nbmax(int64_t n, const int64_t* __
   if (state[i] != 0) return;
   unsigned long long mx = 0, ki = key[i];
   for (int64_t k = rp[i] + g; k < rp[i + 1]; k += PG) {
-    if (!strong[k]) continue;
-    int32_t j = ci[k];
+    // the flag and the column together (no branch between the two loads)
+    const bool sk = strong[k] != 0;
+    const int32_t j = ci[k];
+    if (!sk) continue;
     if (state[j] != 0) continue;
     mx = mx > key[j] ? mx : key[j];
     atomicMax(&nbmax[j], ki);      // i depends on j: i is a neighbour of j as well
@@ -245,11 +247,14 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, int fsearch, const 
     if (cf[i]) {
       int m = 0;
       int64_t cand = 0;
-      for (int64_t k = k0 + g; k < k1; k += PG)
-        if (strong_r[k] && !cf[ci[k]]) {
+      for (int64_t k = k0 + g; k < k1; k += PG) {
+        const bool sk = strong_r[k] != 0;
+        const int32_t c = ci[k];
+        if (sk && !cf[c]) {
           ++m;
-          cand += rp[ci[k] + 1] - rp[ci[k]];
+          cand += rp[c + 1] - rp[c];
         }
+      }
       for (int o = PG / 2; o > 0; o >>= 1) {
         m += __shfl_xor(m, o, PG);
         cand += __shfl_xor(cand, o, PG);
@@ -268,14 +273,22 @@ __global__ __launch_bounds__(256) void k_onepoint(int64_t n, int fsearch, const 
     }
     double mx = -1.0;
     if (fsearch)
-      for (int64_t k = k0 + g; k < k1; k += PG)
-        if (strong[k] && cf[ci[k]]) mx = fmax(mx, fabs(v[k]));
+      for (int64_t k = k0 + g; k < k1; k += PG) {
+        const bool sk = strong[k] != 0;
+        const int32_t c = ci[k];
+        const double a = fabs(v[k]);
+        if (sk && cf[c]) mx = fmax(mx, a);
+      }
     for (int o = PG / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, PG));
     int64_t first = k1;
     if (mx >= 0.0) {
       const double thr = mx * (1.0 - 1e-12);
-      for (int64_t k = k0 + g; k < k1; k += PG)
-        if (strong[k] && cf[ci[k]] && fabs(v[k]) >= thr) { first = k; break; }
+      for (int64_t k = k0 + g; k < k1; k += PG) {
+        const bool sk = strong[k] != 0;
+        const int32_t c = ci[k];
+        const double a = fabs(v[k]);
+        if (sk && cf[c] && a >= thr) { first = k; break; }
+      }
       for (int o = PG / 2; o > 0; o >>= 1) {
         int64_t other = __shfl_xor(first, o, PG);
         first = other < first ? other : first;
