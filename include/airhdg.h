@@ -279,12 +279,12 @@ typedef struct {
  * the cycle (0: every level runs with grid-wide kernels); AH_TAIL_LDS=0 runs
  * that coarse end from global memory instead of an LDS image; AH_G0 (2, 4,
  * 8, 16, 32) fixes the lanes per row of the level-0 kernels.  Alternative
- * code paths that give the same sums bit for bit (the defaults are the
- * faster forms): AH_SWO=0 sweeps over the natural order from the F and C
- * lists after an interpolation pass instead of from the copies in sweep
- * order; AH_L1B=0 sweeps level 1 of block AIR by CSR rows; AH_RZB=0 restricts
- * from level 0 by CSR rows (rounding-level differences); AH_FBB=0 runs the
- * level-0 kernels by rows.  Size thresholds: AH_DCGS_MIN (delayed CGS2),
+ * code paths (the defaults are the faster forms): AH_SWO=0 sweeps over the
+ * natural order from the F and C lists after an interpolation pass instead
+ * of from the copies in sweep order (the same sums, bit for bit); AH_L1B=0
+ * sweeps level 1 of block AIR by CSR rows, AH_RZB=0 restricts from level 0
+ * by CSR rows and AH_FBB=0 runs the level-0 kernels by rows (the same
+ * operators, summed in another order).  Size thresholds: AH_DCGS_MIN (delayed CGS2),
  * AH_LIST_MIN (list sweeps on coarse levels), AH_PMIS_WG_MAX,
  * AH_PMIS_LIST_MIN; lanes: AH_GC (coarse levels), AH_LPB (level-0 block
  * rows), AH_L1LP (level 1). */
