@@ -1870,7 +1870,8 @@ __global__ void k_so_fpos(int64_t nbF, const int32_t* __restrict__ perm, int32_t
 __global__ void k_so_enc(int64_t nbr, int B, const int32_t* __restrict__ perm, const int64_t* __restrict__ soptr,
                          const int32_t* __restrict__ socol, const int32_t* __restrict__ pcol,
                          const int8_t* __restrict__ cf, const int32_t* __restrict__ fpos,
-                         int32_t* __restrict__ socp, int32_t* __restrict__ soce, int32_t* __restrict__ soown) {
+                         int32_t* __restrict__ socp, int32_t* __restrict__ soce, int32_t* __restrict__ soown,
+                         int* __restrict__ bad) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = gid / 16;
   const int t = (int)(gid % 16);
@@ -1879,11 +1880,14 @@ __global__ void k_so_enc(int64_t nbr, int B, const int32_t* __restrict__ perm, c
     const int64_t J = socol[o];
     const int32_t pj = pcol[J * B];
     const int32_t cj = pj >= 0 ? pj / B : -1;
+    // P must copy whole coarse blocks, and a C block must have its own
+    if ((pj >= 0 && pj % B != 0) || (cf[J * B] && pj < 0)) *bad = 1;
     socp[o] = cj;
     soce[o] = cf[J * B] ? ~cj : fpos[J];
   }
   if (t == 0) {
     const int32_t pr = pcol[(int64_t)perm[k] * B];
+    if (pr >= 0 && pr % B != 0) *bad = 1;
     soown[k] = pr >= 0 ? pr / B : -1;
   }
 }
@@ -1987,19 +1991,29 @@ static ah_status sweep_order_build(ah_hier* h, hipStream_t st) {
   // the encodings for the sweeps without an interpolation pass
   if (L.pcol && L.cf && nbC > 0) {
     int32_t *socp = nullptr, *soce = nullptr, *soown = nullptr, *fpos = nullptr;
+    int* d_bad = nullptr;
     Arena tmp2;
     tmp2.stream = st;
     rc = ar.get(&socp, std::max<int64_t>(nblk, 1));
     if (rc == AH_OK) rc = ar.get(&soce, std::max<int64_t>(nblk, 1));
     if (rc == AH_OK) rc = ar.get(&soown, std::max<int64_t>(nbr, 1));
     if (rc == AH_OK) rc = tmp2.get(&fpos, std::max<int64_t>(nbr, 1));
+    if (rc == AH_OK) rc = tmp2.get(&d_bad, 1);
     if (rc < 0) { tmp2.release(); return rc; }
+    if (hipMemsetAsync(d_bad, 0, sizeof(int), st) != hipSuccess) {
+      tmp2.release();
+      set_error("air_setup: sweep order encodings");
+      return AH_EHIP;
+    }
     if (nbF > 0) hipLaunchKernelGGL(k_so_fpos, g1(nbF), dim3(256), 0, st, nbF, perm, fpos);
     hipLaunchKernelGGL(k_so_enc, g1(nbr * 16), dim3(256), 0, st, nbr, B, perm, soptr, socol, L.pcol, L.cf, fpos,
-                       socp, soce, soown);
-    const bool bad = hipGetLastError() != hipSuccess;
+                       socp, soce, soown, d_bad);
+    int hbad = 0;
+    rc = hipGetLastError() != hipSuccess ? AH_EHIP : read_bytes(d_bad, &hbad, sizeof(int), st);
     tmp2.release();
-    if (bad) { set_error("air_setup: sweep order encodings"); return AH_EHIP; }
+    if (rc != AH_OK) { set_error("air_setup: sweep order encodings"); return AH_EHIP; }
+    // a P that does not copy whole coarse blocks keeps the interpolation pass
+    if (hbad) return AH_OK;
     L.socp = socp;
     L.soce = soce;
     L.soown = soown;
